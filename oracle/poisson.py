@@ -1,0 +1,135 @@
+"""Exact zero-mean solution of the discrete pressure Poisson problem.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The discrete operator is A P = sum_d delta_1(beta delta_1 P)/delta_1 x_d, the
+composition of the face difference (Eq 3.21, n = 1) with itself that the
+discrete continuity equation Eq 3.24 produces once the face flux of Eq 3.23 is
+inserted. The paper's step has beta = 1; a face coefficient beta is accepted
+for the variable-coefficient form. Boundary faces of non-periodic sides carry
+a prescribed mass flux, so A has zero flux there (a pure Neumann problem,
+section 3.3). The singular system is closed by the augmented-matrix method of
+section 3.3: [A 1; 1^T 0][P; lam] = [b; 0], whose solution is the zero-mean P,
+with lam = mean(b) absorbing any compatibility residue. On fully periodic
+grids with beta = 1 the same solution is obtained by FFT diagonalisation.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .grid import Grid
+
+
+def face_grad(g: Grid, P, d):
+    """delta_1 P / delta_1 x_d on the n_d + 1 faces normal to d, with periodic
+    wrap on periodic directions and zero on boundary faces otherwise."""
+    ax = g.axis(d)
+    h = g.h[d]
+    if g.periodic(d):
+        Pm = np.roll(P, 1, axis=ax)             # cell f-1 for face f = 0..n-1
+        inner = (P - Pm) / h
+        first = np.take(inner, [0], axis=ax)
+        return np.concatenate([inner, first], axis=ax)
+    grad = np.diff(P, axis=ax) / h
+    shp = list(P.shape)
+    shp[ax] = 1
+    z = np.zeros(shp, dtype=P.dtype)
+    return np.concatenate([z, grad, z], axis=ax)
+
+
+def laplacian(g: Grid, P, beta=None):
+    """A P = sum_d [ (beta grad)_{f+1} - (beta grad)_f ] / h_d."""
+    out = np.zeros_like(P)
+    for d in range(g.ndim):
+        G = face_grad(g, P, d)
+        if beta is not None:
+            G = G * beta[d]
+        out = out + (g.plus(G, d) - g.minus(G, d)) / g.h[d]
+    return out
+
+
+def periodic_eigenvalues(g: Grid):
+    """Eigenvalues of A (beta = 1) on the Fourier modes of a periodic grid:
+    lam(k) = -sum_d (4/h_d^2) sin^2(pi k_d / n_d)."""
+    lam = np.zeros(g.shape)
+    for d in range(g.ndim):
+        k = np.arange(g.n[d])
+        ld = -(4.0 / g.h[d] ** 2) * np.sin(np.pi * k / g.n[d]) ** 2
+        shp = [1] * g.ndim
+        shp[g.axis(d)] = g.n[d]
+        lam = lam + ld.reshape(shp)
+    return lam
+
+
+class PoissonSolver:
+    """Solves A P = b for the zero-mean P; returns (P, mean(b))."""
+
+    def __init__(self, g: Grid, beta=None):
+        self.g = g
+        self.beta = beta
+        self.fft = g.all_periodic and beta is None
+        if self.fft:
+            lam = periodic_eigenvalues(g)
+            lam.flat[0] = 1.0
+            self.inv = 1.0 / lam
+            self.inv.flat[0] = 0.0
+        else:
+            self.lu = spla.splu(self._augmented().tocsc())
+
+    def _augmented(self):
+        g = self.g
+        N = int(np.prod(g.shape))
+        cols = []
+        # assemble A column by column from its action on face differences
+        idx = np.arange(N).reshape(g.shape)
+        rows, cidx, vals = [], [], []
+        for d in range(g.ndim):
+            ax = g.axis(d)
+            h2 = g.h[d] ** 2
+            n = g.n[d]
+            for f in range(n + 1):
+                # face f between cells f-1 and f along d
+                if f == 0 or f == n:
+                    if not g.periodic(d):
+                        continue
+                    if f == n:
+                        continue           # periodic face n is face 0
+                    left = np.take(idx, n - 1, axis=ax)
+                else:
+                    left = np.take(idx, f - 1, axis=ax)
+                right = np.take(idx, f % n, axis=ax)
+                w = np.ones(left.shape) / h2
+                if self.beta is not None:
+                    w = np.take(self.beta[d], f, axis=ax) / h2
+                l, r, w = left.ravel(), right.ravel(), np.asarray(w).ravel()
+                # flux w (P_r - P_l) leaves cell l through its high face and
+                # enters cell r through its low face
+                rows += [l, l, r, r]
+                cidx += [r, l, l, r]
+                vals += [w, -w, w, -w]
+        rows = np.concatenate(rows)
+        cidx = np.concatenate(cidx)
+        vals = np.concatenate(vals)
+        A = sp.coo_matrix((vals, (rows, cidx)), shape=(N, N)).tocsr()
+        one = sp.csr_matrix(np.ones((N, 1)))
+        aug = sp.bmat([[A, one], [one.T, None]])
+        del cols
+        return aug
+
+    def solve(self, b):
+        g = self.g
+        lam = np.mean(b)
+        if self.fft:
+            bh = np.fft.fftn(b)
+            P = np.fft.ifftn(bh * self.inv)
+            P = P if np.iscomplexobj(b) else P.real
+            return P, lam
+        N = b.size
+        rhs = np.concatenate([b.ravel(), [0.0]])
+        if np.iscomplexobj(rhs):
+            x = self.lu.solve(rhs.real) + 1j * self.lu.solve(rhs.imag)
+        else:
+            x = self.lu.solve(rhs)
+        return x[:N].reshape(g.shape), x[N]

@@ -1,0 +1,310 @@
+"""Initial conditions for the five synthetic workloads.
+
+Workload sizes and distributions follow the configurations the method is
+exercised on (periodic Taylor-Green/hot-spot boxes, random-mode variable-density
+boxes in 2D and 3D, and a slot-burner flame with an immersed boundary). The
+paper's own experiments (Taylor-Green vortex, section 4.2; double Tsuji flame,
+section 4.5) are analytic or need data that is not available, so these seeded
+fields stand in for them.
+
+Random draws: ``numpy.random.default_rng(seed)``; the order of draws is fixed
+and documented in each generator.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Case:
+    """A workload: grid, physical parameters and initial fields.
+
+    ``T`` is temperature at cell centres, ``v`` a list of velocity components,
+    ``Z`` the mixture fraction (None for non-reacting cases). ``ib`` holds the
+    immersed-boundary arrays (mask, targets, mass source) and ``bnd`` the
+    boundary arrays for non-periodic sides, both None for periodic boxes.
+    """
+    name: str
+    ndim: int
+    n: tuple
+    L: tuple
+    bc: tuple                 # per dim: ("periodic","periodic") or side kinds
+    params: dict
+    T: np.ndarray
+    v: list
+    Z: Optional[np.ndarray] = None
+    ib: Optional[dict] = None
+    bnd: Optional[dict] = None
+    nsteps: int = 1
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n[: self.ndim]))
+
+    @property
+    def ncells(self):
+        return int(np.prod(self.n[: self.ndim]))
+
+
+def cell_centres(n, L):
+    """Cell-centre coordinates x_i = (i + 1/2) * L / n for each direction,
+    returned as broadcastable arrays in (z, y, x) axis order."""
+    ndim = len(n)
+    out = []
+    for d in range(ndim):
+        h = L[d] / n[d]
+        c = (np.arange(n[d]) + 0.5) * h
+        shp = [1] * ndim
+        shp[ndim - 1 - d] = n[d]
+        out.append(c.reshape(shp))
+    return out  # out[d] varies along direction d
+
+
+def taylor_green(n, L, t=0.0, Re=100.0):
+    """Taylor-Green vortex on a periodic square of side L (section 4.2,
+    Eq 4.4-4.6 written for side L): wavenumber a = 2*pi/L,
+    v1 = sin(a x) cos(a y) e^{-2 a^2 t/Re}, v2 = -cos(a x) sin(a y) e^{-2 a^2 t/Re},
+    p = (cos(2 a x) + cos(2 a y))/4 e^{-4 a^2 t/Re}."""
+    x, y = cell_centres(n, L)
+    a = 2.0 * math.pi / L[0]
+    dv = math.exp(-2.0 * a * a * t / Re)
+    dp = math.exp(-4.0 * a * a * t / Re)
+    v1 = np.sin(a * x) * np.cos(a * y) * dv
+    v2 = -np.cos(a * x) * np.sin(a * y) * dv
+    p = 0.25 * (np.cos(2 * a * x) + np.cos(2 * a * y)) * dp
+    shp = (n[1], n[0])
+    return np.broadcast_to(v1, shp).copy(), np.broadcast_to(v2, shp).copy(), \
+        np.broadcast_to(p, shp).copy()
+
+
+def hot_spot_tg(n, seed, amp=4.0, r2scale=0.25, noise_T=1e-3, noise_v=1e-2):
+    """Hot spot T = 1 + amp*exp(-r^2/r2scale) centred in a periodic 2*pi box,
+    plus U(-noise_T, noise_T) per cell, on a Taylor-Green velocity plus
+    N(0, noise_v^2) per component and cell.
+    Draw order: T noise (ny, nx), then v noise (2, ny, nx)."""
+    L = (2 * math.pi, 2 * math.pi)
+    x, y = cell_centres(n, L)
+    rng = np.random.default_rng(seed)
+    r2 = (x - math.pi) ** 2 + (y - math.pi) ** 2
+    T = 1.0 + amp * np.exp(-r2 / r2scale)
+    T = T + rng.uniform(-noise_T, noise_T, size=(n[1], n[0]))
+    v1 = np.sin(x) * np.cos(y)
+    v2 = -np.cos(x) * np.sin(y)
+    nz = rng.normal(0.0, noise_v, size=(2, n[1], n[0]))
+    return T, [v1 + nz[0], v2 + nz[1]]
+
+
+def _wavevectors(ndim, kmax):
+    """All integer wavevectors k != 0 with |k| <= kmax, in lexicographic order."""
+    rng1 = range(-kmax, kmax + 1)
+    if ndim == 2:
+        ks = [(a, b) for a in rng1 for b in rng1]
+    else:
+        ks = [(a, b, c) for a in rng1 for b in rng1 for c in rng1]
+    ks = [k for k in ks if any(k) and sum(q * q for q in k) <= kmax * kmax]
+    return np.array(ks, dtype=np.int64)
+
+
+def _phase(n, L, k, coords):
+    arg = 0.0
+    for d in range(len(n)):
+        arg = arg + (2 * math.pi / L[d]) * k[d] * coords[d]
+    return arg
+
+
+def fourier_temperature(n, L, rng, kmax, amp, m=32):
+    """T = 1 + amp * fhat, fhat = (f - min f)/(max f - min f),
+    f = sum_m a_m cos(k_m . x + phi_m) over m wavevectors drawn without
+    replacement from {k != 0, |k| <= kmax}, a_m ~ U(0,1), phi_m ~ U(0, 2 pi).
+    Draw order: indices (m), amplitudes (m), phases (m)."""
+    ks = _wavevectors(len(n), kmax)
+    idx = rng.choice(len(ks), size=m, replace=False)
+    a = rng.random(m)
+    ph = 2 * math.pi * rng.random(m)
+    coords = cell_centres(n, L)
+    shp = tuple(reversed(n))
+    f = np.zeros(shp)
+    for q in range(m):
+        f = f + a[q] * np.cos(_phase(n, L, ks[idx[q]], coords) + ph[q])
+    fh = (f - f.min()) / (f.max() - f.min())
+    return 1.0 + amp * fh
+
+
+def solenoidal_velocity(n, L, rng, kmax, rms=0.1, m=32):
+    """Divergence-free random velocity, scaled to (mean |v|^2)^(1/2) = rms.
+
+    2D: streamfunction psi = sum a cos(k.x + phi); v = (d psi/dy, -d psi/dx),
+    differentiated analytically. Draws: indices, amplitudes, phases.
+    3D: v = sum [c_m cos(k.x) + s_m sin(k.x)] with c_m, s_m ~ N(0,1)^3
+    projected orthogonal to k. Draws: indices, c (m,3), s (m,3)."""
+    ndim = len(n)
+    ks = _wavevectors(ndim, kmax)
+    idx = rng.choice(len(ks), size=m, replace=False)
+    coords = cell_centres(n, L)
+    shp = tuple(reversed(n))
+    v = [np.zeros(shp) for _ in range(ndim)]
+    if ndim == 2:
+        a = rng.random(m)
+        ph = 2 * math.pi * rng.random(m)
+        for q in range(m):
+            k = ks[idx[q]]
+            kx = 2 * math.pi / L[0] * k[0]
+            ky = 2 * math.pi / L[1] * k[1]
+            s = np.sin(_phase(n, L, k, coords) + ph[q])
+            v[0] = v[0] - a[q] * ky * s
+            v[1] = v[1] + a[q] * kx * s
+    else:
+        c = rng.normal(size=(m, 3))
+        sn = rng.normal(size=(m, 3))
+        for q in range(m):
+            k = ks[idx[q]]
+            kp = np.array([2 * math.pi / L[d] * k[d] for d in range(3)])
+            kk = kp / np.linalg.norm(kp)
+            cq = c[q] - kk * (kk @ c[q])
+            sq = sn[q] - kk * (kk @ sn[q])
+            arg = _phase(n, L, k, coords)
+            ca, sa = np.cos(arg), np.sin(arg)
+            for d in range(3):
+                v[d] = v[d] + cq[d] * ca + sq[d] * sa
+    e = math.sqrt(float(np.mean(sum(x * x for x in v))))
+    return [x * (rms / e) for x in v]
+
+
+def c1_case(n=64, seed=1):
+    """2D periodic 2*pi box, 64^2: hot spot T = 1 + 4 exp(-r^2/0.25) with
+    U(-1e-3, 1e-3) noise, Taylor-Green velocity with N(0, 1e-2^2) noise,
+    Re=100, Pr=0.7, CFL 0.2, one step, Poisson to 1e-12."""
+    T, v = hot_spot_tg((n, n), seed)
+    L = (2 * math.pi, 2 * math.pi)
+    return Case("c1_hotspot_tg_64", 2, (n, n, 1), L + (1.0,),
+                (("periodic", "periodic"),) * 2,
+                dict(Re=100.0, Pr=0.7, cfl=0.2, poisson_rtol=1e-12), T, v,
+                nsteps=1)
+
+
+def c2_case(n=1024, seed=2):
+    """2D periodic 2*pi box, 1024^2: T = 1 + 3 fhat (32 modes, |k| <= 8),
+    solenoidal velocity |k| <= 8 rms 0.1, Re=500, Pr=0.7, CFL 0.3,
+    100 steps, Poisson to 1e-10. Draws: temperature, then velocity."""
+    L = (2 * math.pi, 2 * math.pi)
+    rng = np.random.default_rng(seed)
+    T = fourier_temperature((n, n), L, rng, 8, 3.0)
+    v = solenoidal_velocity((n, n), L, rng, 8, 0.1)
+    return Case("c2_random_modes_1024", 2, (n, n, 1), L + (1.0,),
+                (("periodic", "periodic"),) * 2,
+                dict(Re=500.0, Pr=0.7, cfl=0.3, poisson_rtol=1e-10), T, v,
+                nsteps=100)
+
+
+def c4_case(n=256, seed=4):
+    """3D periodic 2*pi box, 256^3: T = 1 + 5 fhat (32 modes, |k| <= 6),
+    solenoidal velocity |k| <= 6 rms 0.1, Re=400, Pr=0.7, 50 steps,
+    Poisson to 1e-10 (CFL 0.3 is the reading for the unstated CFL)."""
+    L = (2 * math.pi,) * 3
+    rng = np.random.default_rng(seed)
+    T = fourier_temperature((n, n, n), L, rng, 6, 5.0)
+    v = solenoidal_velocity((n, n, n), L, rng, 6, 0.1)
+    return Case("c4_random_modes_256cube", 3, (n, n, n), L,
+                (("periodic", "periodic"),) * 3,
+                dict(Re=400.0, Pr=0.7, cfl=0.3, poisson_rtol=1e-10), T, v,
+                nsteps=50)
+
+
+def c5_case(n=512, seed=5):
+    """2D periodic 2*pi box, 512^2 for the adjoint: T0 = 1 + 3 fhat
+    (32 modes, |k| <= 8), solenoidal velocity rms 0.1, Re=300, Pr=0.7,
+    200 steps, checkpoint every 20 (CFL 0.3 is the reading)."""
+    L = (2 * math.pi, 2 * math.pi)
+    rng = np.random.default_rng(seed)
+    T = fourier_temperature((n, n), L, rng, 8, 3.0)
+    v = solenoidal_velocity((n, n), L, rng, 8, 0.1)
+    return Case("c5_adjoint_512", 2, (n, n, 1), L + (1.0,),
+                (("periodic", "periodic"),) * 2,
+                dict(Re=300.0, Pr=0.7, cfl=0.3, poisson_rtol=1e-10), T, v,
+                nsteps=200)
+
+
+def c3_case(nx=768, ny=1536, seed=3, W=32, wall=4, wall_h=64, inj=4,
+            Umax=1.0, coflow=0.1, noise=0.01):
+    """Planar slot-jet diffusion flame in a channel (nx x ny cells, dx = 1/W).
+
+    Geometry (in cells): a burner centred at x = nx/2 standing on the bottom
+    side: two walls ``wall`` cells thick and ``wall_h`` tall flank a slot of
+    W cells; an injector layer ``inj`` cells thick spans the slot floor.
+    Slot inflow U(x) = Umax (1 - (2 (x - xc)/W)^2) (1 + noise * xi_col),
+    xi_col ~ N(0,1) per slot column (one draw of W values), fixed in time.
+    Flame-sheet parameters: Z_st = 0.055 so S = 1/Z_st - 1, fuel at Z = S+1;
+    Re=200, Pr=Sc=0.7 (Le_F = Le_O = 1), eps = 0.5, tol = 1e-3.
+    Returns the geometry arrays; temperatures are left to the solver, which
+    derives T from Z and H. ``T`` holds None-equivalent ones."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / W
+    L = (nx * h, ny * h)
+    xc = nx // 2
+    s0, s1 = xc - W // 2, xc + W // 2          # slot columns [s0, s1)
+    w0l, w1l = s0 - wall, s0                    # left wall columns
+    w0r, w1r = s1, s1 + wall                    # right wall columns
+    xi = rng.normal(size=W)
+    shp = (ny, nx)
+    chi = np.zeros(shp, dtype=np.uint8)
+    chi[0:wall_h, w0l:w1l] = 1
+    chi[0:wall_h, w0r:w1r] = 1
+    chi[0:inj, s0:s1] = 1
+    xcent = (np.arange(nx) + 0.5) * h
+    xmid = xc * h
+    U = np.zeros(nx)
+    sl = slice(s0, s1)
+    U[sl] = Umax * (1.0 - (2.0 * (xcent[sl] - xmid) / (W * h)) ** 2) * (1.0 + noise * xi)
+    S = 1.0 / 0.055 - 1.0
+    zfuel = S + 1.0
+    v1 = np.zeros(shp)
+    v2 = np.full(shp, coflow)
+    v2[0:wall_h, w0l:w1l] = 0.0
+    v2[0:wall_h, w0r:w1r] = 0.0
+    v2[0:wall_h, s0:s1] = U[sl][None, :]
+    yc = (np.arange(ny) + 0.5) * h
+    # Z: fuel in the slot, smoothed by tanh over 2 cells at the slot exit
+    Z = np.zeros(shp)
+    prof = 0.5 * (1.0 - np.tanh((yc - wall_h * h) / (2 * h)))
+    Z[:, s0:s1] = zfuel * prof[:, None]
+    # immersed boundary targets
+    vib1 = np.zeros(shp)
+    vib2 = np.zeros(shp)
+    vib2[0:inj, s0:s1] = U[sl][None, :]
+    zib = np.zeros(shp)
+    zib[0:inj, s0:s1] = zfuel
+    # mass source: injector flux U ramps across the inj-cell layer
+    Sm = np.zeros(shp)
+    Sm[0:inj, s0:s1] = (1.0 * U[sl] / (inj * h))[None, :]
+    # bottom boundary: coflow inflow outside the burner footprint, wall under it
+    vb2 = np.full(nx, coflow)
+    vb2[w0l:w1r] = 0.0
+    bnd = dict(bottom_v=[np.zeros(nx), vb2], bottom_Z=np.zeros(nx),
+               bottom_F=vb2.copy())
+    params = dict(Re=200.0, Pr=0.7, Le_F=1.0, Le_O=1.0, reacting=1, S=S,
+                  eps=0.5, tol=1e-3, Da_ib=h * h, p0=1.0, cfl=0.2,
+                  poisson_rtol=1e-10)
+    ib = dict(chi=chi, v_ib=[vib1, vib2], Z_ib=zib, Sm=Sm, Sm_rate_closed=
+              float(np.sum(U[sl]) * h))
+    return Case("c3_slot_flame_768x1536", 2, (nx, ny, 1), L + (1.0,),
+                (("slip", "slip"), ("inflow", "outflow")), params,
+                None, [v1, v2], Z=Z, ib=ib, bnd=bnd, nsteps=500)
+
+
+def make_case(name, **kw):
+    return dict(c1=c1_case, c2=c2_case, c3=c3_case, c4=c4_case,
+                c5=c5_case)[name](**kw)
+
+
+def fd_directions(shape, k=16, seed=1005):
+    """k seeded unit-RMS Gaussian perturbation fields for finite-difference checks."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(k):
+        d = rng.normal(size=shape)
+        out.append(d / math.sqrt(float(np.mean(d * d))))
+    return out
