@@ -1,0 +1,185 @@
+/*
+ * lowmach.h - C ABI of liblowmach.so, an MI355X (gfx950) implementation of one
+ * predictor-corrector time step of the low-Mach fractional-step method of
+ * Severino et al., "Numerical method for strongly variable-density flows at
+ * low Mach number" (section 3).
+ *
+ * Conventions
+ *  - Every entry point returns an lm_status; lm_last_error() gives the text of
+ *    the last failure on a context. Entry points never abort the process.
+ *  - All arrays crossing the ABI are float64, C order with x fastest: a cell
+ *    field has shape (nz, ny, nx) (2D: (ny, nx)); a face-flux array F_d has
+ *    n_d + 1 entries along direction d (entry f is the face between cells f-1
+ *    and f), the interior count along the others. Pointers are host or device
+ *    memory as the `mem` argument says (LM_HOST / LM_DEVICE); nothing is
+ *    retained after a call returns. Device copies are ordered on the
+ *    context's stream; host copies complete before the call returns.
+ *  - The caller owns the device workspace (lm_workspace_size bytes, 256-byte
+ *    aligned) and the HIP stream. The context carves every device array from
+ *    the workspace and never calls hipMalloc; it allocates only a small host
+ *    struct and a few bytes of pinned host memory for solver flags.
+ *  - A context is not thread safe; use one context per stream.
+ */
+#ifndef LOWMACH_H
+#define LOWMACH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lm_ctx lm_ctx;
+
+typedef enum {
+  LM_OK = 0,
+  LM_EINVAL = -1,        /* invalid argument (sizes, parameters, non-positive T) */
+  LM_ENOMEM = -2,        /* workspace smaller than lm_workspace_size */
+  LM_EHIP = -3,          /* a HIP runtime call failed */
+  LM_ENOCONV = -4,       /* Poisson solver hit poisson_maxit before poisson_rtol */
+  LM_ENONFINITE = -5,    /* a NaN/Inf appeared in the step */
+  LM_ESTATE = -6,        /* call out of order (e.g. lm_step before lm_set_fields) */
+  LM_EUNSUPPORTED = -7   /* valid request this build does not implement */
+} lm_status;
+
+/* Side kinds (section 3.6 ghost rules, section 3.3 flux boundary conditions). */
+enum {
+  LM_SIDE_PERIODIC = 0, /* Eq 3.45 for all fields                              */
+  LM_SIDE_SLIP = 1,     /* zero normal flux; normal v Dirichlet 0 (Eq 3.43),   */
+                        /* tangential v, Z, H Neumann 0 (Eq 3.44)              */
+  LM_SIDE_NOSLIP = 2,   /* zero normal flux; v Dirichlet 0; Z, H Neumann 0     */
+  LM_SIDE_INFLOW = 3,   /* given normal mass flux; v, Z, H Dirichlet (given)   */
+  LM_SIDE_OUTFLOW = 4   /* v, Z, H extrapolated (Eq 3.46); flux extrapolated   */
+                        /* and shifted uniformly to close global mass          */
+};
+
+enum { LM_FP64 = 0, LM_MIXED = 1 };   /* Poisson preconditioner precision */
+enum { LM_HOST = 0, LM_DEVICE = 1 };  /* where caller arrays live           */
+
+/* Grid: ndim in {2,3}; n[d] interior cells and L[d] length per direction
+ * (n[2] = 1, L[2] ignored in 2D); bc[d][0] / bc[d][1] the low / high side. */
+typedef struct {
+  int ndim;
+  int n[3];
+  double L[3];
+  int bc[3][2];
+} lm_grid;
+
+/* Dimensionless parameters (section 2.6, Eq 2.42-2.50; section 4.1):
+ *  Re, Pr        Pe = Re Pr; viscous factor Pr/Pe (Eq 2.43)
+ *  sigma         kappa = T^sigma (Eq 2.50)
+ *  inv_Fr2       buoyancy 1/Fr^2 (Eq 2.43, 3.8b)
+ *  reacting      0: Z not transported, T = qs (H - 1); 1: flame sheet
+ *  S, qs         generalised stoichiometric coefficient; qs = Q/(S+1)
+ *  eps, tol      regularisation width and tolerance (section 3.5, Eq 3.34)
+ *  Le_F, Le_O    fuel / oxidiser Lewis numbers (Eq 3.35)
+ *  Da_ib         immersed-boundary Darcy number (Eq 3.30-3.32)
+ *  p0            constant thermodynamic pressure (Eq 2.41)
+ *  dt            time step; 0 = fixed once from cfl and the initial state
+ *  cfl           CFL number used when dt == 0
+ *  precision     LM_FP64 or LM_MIXED (FP32 multigrid inside FP64 CG)
+ *  poisson_rtol  stop when ||b - A P||_2 <= rtol ||b||_2 (b mean-free)
+ *  poisson_maxit iteration cap (LM_ENOCONV beyond it)
+ *  mg_nu         smoothing sweeps per level and direction (0 = default 2)
+ *  with_ib       1 = reserve immersed-boundary arrays (needed by lm_set_fields
+ *                with a non-NULL lm_ib)                                    */
+typedef struct {
+  double Re, Pr, sigma, inv_Fr2;
+  int reacting;
+  double S, qs, eps, tol, Le_F, Le_O;
+  double Da_ib, p0, dt, cfl;
+  int precision;
+  double poisson_rtol;
+  int poisson_maxit;
+  int mg_nu;
+  int with_ib;
+} lm_params;
+
+/* Field set for lm_set_fields / lm_get_fields; NULL entries are skipped.
+ * rho is output only (always p0/T). P holds P = p dt (Eq 3.8c).           */
+typedef struct {
+  double *rho, *v[3], *Z, *H, *T, *P, *F[3];
+} lm_fields;
+
+/* Immersed-boundary data (section 3.4): chi mask (0/1 bytes), targets of
+ * Eq 3.30-3.32 and the mass source S_m of Eq 3.33; NULL = zero.           */
+typedef struct {
+  const unsigned char *chi;
+  const double *v_ib[3], *Z_ib, *H_ib, *S_m;
+} lm_ib;
+
+/* Boundary data of one inflow side: per-cell arrays over the side (C order,
+ * the side's own direction removed); NULL = zero.                          */
+typedef struct {
+  const double *v[3], *Z, *H, *F;
+} lm_side_data;
+
+typedef struct {
+  int steps;                 /* steps taken by the call                      */
+  double dt;                 /* time step in use                             */
+  double time;               /* simulated time since lm_set_fields           */
+  int poisson_iters[2];      /* last step: predictor, corrector iterations   */
+  double poisson_relres[2];  /* last step: final recursive relative residual */
+  double compat[2];          /* last step: mean(b) removed before each solve */
+  long long total_poisson_iters;
+} lm_step_stats;
+
+/* RHS-mode projection: solve A P = b for the zero-mean P, with
+ * A P = sum_d delta_1 (beta delta_1 P) (Eq 3.24 composed with Eq 3.23),
+ * beta = 1. b is a cell field (mem says where); P is written to `P` and
+ * also becomes the context's pressure (warm start of the next solve).     */
+typedef struct {
+  const double *b;
+  double *P;
+  int mem;
+  double rtol;               /* 0 = params.poisson_rtol                     */
+  int iters;                 /* out */
+  double relres;             /* out */
+  double mean_b;             /* out: compatibility residue removed          */
+} lm_project_args;
+
+/* Bytes of device workspace needed for (grid, params). */
+lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t *bytes);
+
+/* Create a context on the current HIP device over a caller workspace of
+ * `bytes` bytes (>= lm_workspace_size) and a caller stream (hipStream_t,
+ * NULL = default stream). Errors: LM_EINVAL (bad grid: ndim, n < 4, a
+ * periodic pair broken, non-positive L; bad params), LM_ENOMEM.            */
+lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *dev_workspace,
+                       size_t bytes, void *hip_stream, lm_ctx **out);
+
+/* Set the state at level 0 (time n) from T (or H) and v, optionally Z, P
+ * and F (section 3.1 start-up). H is obtained by inverting Eq 3.42 when T is
+ * given; T is re-evaluated from (Z, H) and rho = p0/T (Eq 2.49). Unless F is
+ * given, F_d is the face average of rho v (Eq 3.20, n = 1). Setting level 0
+ * clears the level n-1 history, so the next step is a Heun start (Euler
+ * predictor, BDF1 density derivative). `ib` may be NULL. LM_EINVAL if T <= 0
+ * anywhere. level must be 0.                                              */
+lm_status lm_set_fields(lm_ctx *ctx, int level, const lm_fields *f, const lm_ib *ib, int mem);
+
+/* Boundary data for an LM_SIDE_INFLOW side (dim d, side 0 = low, 1 = high). */
+lm_status lm_set_side(lm_ctx *ctx, int d, int side, const lm_side_data *data, int mem);
+
+/* Advance nsteps predictor-corrector steps (section 3.1, Eq 3.1-3.19).
+ * On LM_ENOCONV / LM_ENONFINITE the state stays at the last completed step.
+ * stats may be NULL.                                                        */
+lm_status lm_step(lm_ctx *ctx, int nsteps, lm_step_stats *stats);
+
+/* Poisson solve in RHS mode (see lm_project_args). */
+lm_status lm_project(lm_ctx *ctx, lm_project_args *args);
+
+/* Copy the current state (level 0 = time n) into caller arrays. */
+lm_status lm_get_fields(lm_ctx *ctx, int level, lm_fields *f, int mem);
+
+/* The fixed time step (after lm_set_fields when params.dt == 0). */
+lm_status lm_get_dt(const lm_ctx *ctx, double *dt);
+
+const char *lm_last_error(const lm_ctx *ctx);
+
+/* Release the context (the caller still owns workspace and stream). */
+void lm_destroy(lm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOWMACH_H */

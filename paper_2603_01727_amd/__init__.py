@@ -1,0 +1,224 @@
+"""MI355X (gfx950) low-Mach predictor-corrector step (Severino et al., section 3).
+
+``Solver`` wraps the C ABI of ``liblowmach.so``: PyTorch provides the device
+workspace and the stream; every step of the method runs in the HIP library.
+Arrays are float64, C order, x fastest: (ny, nx) or (nz, ny, nx); face fluxes
+F_d carry n_d + 1 entries along d.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import lib as _L
+
+__all__ = ["Solver", "LowMachError"]
+LowMachError = _L.LowMachError
+
+
+def _check(lib, ctx, status):
+    if status != _L.LM_OK:
+        msg = lib.lm_last_error(ctx).decode() if ctx else ""
+        raise _L.LowMachError(status, msg)
+
+
+class _Marshal:
+    """Keeps the arrays of one call alive and yields (pointer, mem)."""
+
+    def __init__(self, torch, device):
+        self.torch = torch
+        self.device = device
+        self.keep = []
+        self.mem = None
+
+    def ptr(self, a, dtype=np.float64):
+        if a is None:
+            return None
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            if a.device.type != "cuda":
+                a = a.detach().numpy()
+            else:
+                tt = t.float64 if dtype == np.float64 else t.uint8
+                a = a.detach().to(device=self.device, dtype=tt).contiguous()
+                self._mem(_L.LM_DEVICE)
+                self.keep.append(a)
+                return a.data_ptr()
+        arr = np.ascontiguousarray(a, dtype=dtype)
+        self._mem(_L.LM_HOST)
+        self.keep.append(arr)
+        return arr.ctypes.data
+
+    def _mem(self, m):
+        if self.mem is None:
+            self.mem = m
+        elif self.mem != m:
+            raise ValueError("mix of host and device arrays in one call")
+
+
+class Solver:
+    """One simulation context on one GPU.
+
+    Parameters follow ``lm_params`` of include/lowmach.h. ``bc`` is a list per
+    direction of (low, high) side kinds: "periodic", "slip", "noslip",
+    "inflow", "outflow".
+    """
+
+    def __init__(self, n: Sequence[int], L: Sequence[float], bc=None, *, Re: float, Pr: float = 0.7,
+                 sigma: float = 0.7, inv_Fr2: float = 0.0, reacting: bool = False, S: float = 1.0,
+                 qs: float = 1.0, eps: float = 0.5, tol: float = 1e-3, Le_F: float = 1.0, Le_O: float = 1.0,
+                 Da_ib: float = 1.0, p0: float = 1.0, dt: float = 0.0, cfl: float = 0.2,
+                 precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
+                 mg_nu: int = 2, with_ib: bool = False, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = _L.load()
+        ndim = len(n)
+        self.ndim = ndim
+        self.n = tuple(int(q) for q in n)
+        self.shape = tuple(reversed(self.n))
+        if bc is None:
+            bc = [("periodic", "periodic")] * ndim
+        g = _L.lm_grid()
+        g.ndim = ndim
+        for d in range(3):
+            g.n[d] = self.n[d] if d < ndim else 1
+            g.L[d] = float(L[d]) if d < ndim else 1.0
+            for s in range(2):
+                g.bc[d][s] = _L.SIDE[bc[d][s]] if d < ndim else 0
+        p = _L.lm_params(Re=Re, Pr=Pr, sigma=sigma, inv_Fr2=inv_Fr2, reacting=int(reacting), S=S, qs=qs,
+                         eps=eps, tol=tol, Le_F=Le_F, Le_O=Le_O, Da_ib=Da_ib, p0=p0, dt=dt, cfl=cfl,
+                         precision=_L.LM_MIXED if precision == "mixed" else _L.LM_FP64,
+                         poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
+                         with_ib=int(with_ib))
+        self.grid, self.params = g, p
+        self.device = torch.device(device)
+        size = C.c_size_t()
+        _check(self.lib, None, self.lib.lm_workspace_size(C.byref(g), C.byref(p), C.byref(size)))
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        _check(self.lib, None, self.lib.lm_init_grid(C.byref(g), C.byref(p), C.c_void_p(self.workspace.data_ptr()),
+                                                     size.value, C.c_void_p(self.stream.cuda_stream),
+                                                     C.byref(ctx)))
+        self.ctx = ctx
+        self.stats = None
+
+    # ------------------------------------------------------------------
+    def set(self, T=None, v=None, Z=None, H=None, P=None, F=None, ib: Optional[dict] = None):
+        m = _Marshal(self.torch, self.device)
+        f = _L.lm_fields()
+        f.T = m.ptr(T)
+        f.H = m.ptr(H)
+        f.Z = m.ptr(Z)
+        f.P = m.ptr(P)
+        for d in range(self.ndim):
+            f.v[d] = m.ptr(v[d])
+            if F is not None:
+                f.F[d] = m.ptr(F[d])
+        ibs = None
+        if ib is not None:
+            ibs = _L.lm_ib()
+            ibs.chi = m.ptr(ib.get("chi"), np.uint8)
+            for d in range(self.ndim):
+                vib = ib.get("v_ib")
+                ibs.v_ib[d] = m.ptr(vib[d]) if vib is not None else None
+            ibs.Z_ib = m.ptr(ib.get("Z_ib"))
+            ibs.H_ib = m.ptr(ib.get("H_ib"))
+            ibs.S_m = m.ptr(ib.get("Sm"))
+        mem = m.mem if m.mem is not None else _L.LM_HOST
+        _check(self.lib, self.ctx, self.lib.lm_set_fields(self.ctx, 0, C.byref(f),
+                                                          C.byref(ibs) if ibs is not None else None, mem))
+
+    def set_side(self, d: int, side: int, v=None, Z=None, H=None, F=None):
+        m = _Marshal(self.torch, self.device)
+        s = _L.lm_side_data()
+        if v is not None:
+            for q in range(self.ndim):
+                s.v[q] = m.ptr(v[q])
+        s.Z, s.H, s.F = m.ptr(Z), m.ptr(H), m.ptr(F)
+        mem = m.mem if m.mem is not None else _L.LM_HOST
+        _check(self.lib, self.ctx, self.lib.lm_set_side(self.ctx, d, side, C.byref(s), mem))
+
+    def step(self, nsteps: int = 1) -> dict:
+        st = _L.lm_step_stats()
+        _check(self.lib, self.ctx, self.lib.lm_step(self.ctx, nsteps, C.byref(st)))
+        self.stats = dict(steps=st.steps, dt=st.dt, time=st.time, poisson_iters=list(st.poisson_iters),
+                          poisson_relres=list(st.poisson_relres), compat=list(st.compat),
+                          total_poisson_iters=st.total_poisson_iters)
+        return self.stats
+
+    def get(self, names=("rho", "v", "H", "T", "P", "F", "Z"), device: bool = True) -> dict:
+        t = self.torch
+        out = {}
+        f = _L.lm_fields()
+        keep = []
+
+        def alloc(shape):
+            a = t.empty(shape, dtype=t.float64, device=self.device) if device else np.empty(shape)
+            keep.append(a)
+            return a, (a.data_ptr() if device else a.ctypes.data)
+
+        for name in names:
+            if name == "v":
+                vs = []
+                for d in range(self.ndim):
+                    a, p = alloc(self.shape)
+                    f.v[d] = p
+                    vs.append(a)
+                out["v"] = vs
+            elif name == "F":
+                fs = []
+                for d in range(self.ndim):
+                    shp = list(self.shape)
+                    shp[self.ndim - 1 - d] += 1
+                    a, p = alloc(tuple(shp))
+                    f.F[d] = p
+                    fs.append(a)
+                out["F"] = fs
+            elif name == "Z" and not self.params.reacting:
+                continue
+            else:
+                a, p = alloc(self.shape)
+                setattr(f, name, p)
+                out[name] = a
+        _check(self.lib, self.ctx, self.lib.lm_get_fields(self.ctx, 0, C.byref(f),
+                                                          _L.LM_DEVICE if device else _L.LM_HOST))
+        return out
+
+    @property
+    def dt(self) -> float:
+        v = C.c_double()
+        _check(self.lib, self.ctx, self.lib.lm_get_dt(self.ctx, C.byref(v)))
+        return v.value
+
+    def project(self, b, rtol: float = 0.0):
+        """Solve A P = b (zero-mean P, mean(b) removed) on this grid."""
+        m = _Marshal(self.torch, self.device)
+        a = _L.lm_project_args()
+        a.b = m.ptr(b)
+        if m.mem == _L.LM_DEVICE:
+            P = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+            a.P = P.data_ptr()
+        else:
+            P = np.empty(self.shape)
+            a.P = P.ctypes.data
+        a.mem = m.mem
+        a.rtol = rtol
+        _check(self.lib, self.ctx, self.lib.lm_project(self.ctx, C.byref(a)))
+        if m.mem == _L.LM_DEVICE:
+            self.torch.cuda.current_stream(self.device).synchronize()
+        return P, dict(iters=a.iters, relres=a.relres, mean_b=a.mean_b)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.lm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

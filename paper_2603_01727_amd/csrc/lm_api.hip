@@ -1,0 +1,590 @@
+// C ABI of liblowmach: context, workspace carving, field transfer and the
+// predictor-corrector step driver (section 3.1 of Severino et al.).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lm_internal.h"
+
+using namespace lm;
+
+struct lm_ctx {
+  lm_grid grid;
+  lm_params prm;
+  hipStream_t st;
+  Lay lay;
+  Bnd bnd;
+  Phys phys;
+  Level lev[3];          // roles rotate: cur (n), nxt (n+1), star
+  double *P[3];          // pressure of each level slot
+  int icur, inxt, istar;
+  double *rho_prev;
+  Resid R[2];
+  int rprev;             // index of R^{n-1}; R^n is rprev ^ 1
+  double *M[3], *b;
+  IB ib;
+  double *ib_store[6];
+  unsigned char *chi_store;
+  Sides sides;
+  double *side_store[3][2][6];
+  double *staging;
+  size_t staging_bytes;
+  int *dflags;           // [0] bad T, [1] non-finite
+  double *dscalar;       // [0] CFL max rate
+  PoissonWS pws;
+  int *hflags;           // pinned
+  double *hscalar;       // pinned
+  int have_state, have_prev;
+  double time;
+  long long total_iters;
+  int last_iters[2];
+  std::string err;
+};
+
+namespace {
+
+lm_status fail(lm_ctx *c, lm_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, LM_EHIP, std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_grid(const lm_grid *g, std::string *err) {
+  if (!g || (g->ndim != 2 && g->ndim != 3)) {
+    *err = "ndim must be 2 or 3";
+    return false;
+  }
+  for (int d = 0; d < g->ndim; ++d) {
+    if (g->n[d] < 4) {
+      *err = "each direction needs at least 4 cells";
+      return false;
+    }
+    if (!(g->L[d] > 0.0)) {
+      *err = "lengths must be positive";
+      return false;
+    }
+    for (int s = 0; s < 2; ++s)
+      if (g->bc[d][s] < LM_SIDE_PERIODIC || g->bc[d][s] > LM_SIDE_OUTFLOW) {
+        *err = "unknown side kind";
+        return false;
+      }
+    if ((g->bc[d][0] == LM_SIDE_PERIODIC) != (g->bc[d][1] == LM_SIDE_PERIODIC)) {
+      *err = "periodic sides come in pairs";
+      return false;
+    }
+  }
+  if (g->ndim == 2 && g->n[2] != 1) {
+    *err = "2D grids need n[2] == 1";
+    return false;
+  }
+  return true;
+}
+
+bool valid_params(const lm_params *p, std::string *err) {
+  if (!p) {
+    *err = "params is NULL";
+    return false;
+  }
+  if (!(p->Re > 0 && p->Pr > 0 && p->sigma >= 0 && p->p0 > 0)) {
+    *err = "Re, Pr, p0 must be positive and sigma >= 0";
+    return false;
+  }
+  if (!(p->dt > 0) && !(p->cfl > 0)) {
+    *err = "need dt > 0 or cfl > 0";
+    return false;
+  }
+  if (p->reacting && !(p->S > 0 && p->eps > 0 && p->tol > 0 && p->tol < 0.5)) {
+    *err = "reacting needs S > 0, eps > 0, 0 < tol < 0.5";
+    return false;
+  }
+  if (!(p->qs > 0) || !(p->Le_F > 0) || !(p->Le_O > 0)) {
+    *err = "qs, Le_F, Le_O must be positive";
+    return false;
+  }
+  if (p->with_ib && !(p->Da_ib > 0)) {
+    *err = "Da_ib must be positive with immersed boundaries";
+    return false;
+  }
+  if (!(p->poisson_rtol > 0) || p->poisson_maxit <= 0) {
+    *err = "poisson_rtol > 0 and poisson_maxit > 0 required";
+    return false;
+  }
+  if (p->precision != LM_FP64 && p->precision != LM_MIXED) {
+    *err = "precision must be LM_FP64 or LM_MIXED";
+    return false;
+  }
+  return true;
+}
+
+void setup_phys(lm_ctx *c) {
+  const lm_grid &g = c->grid;
+  const lm_params &p = c->prm;
+  Phys &P = c->phys;
+  for (int d = 0; d < 3; ++d) {
+    P.h[d] = d < g.ndim ? g.L[d] / g.n[d] : 1.0;
+    P.ih[d] = 1.0 / P.h[d];
+  }
+  P.Pe = p.Re * p.Pr;
+  P.Pr = p.Pr;
+  P.sigma = p.sigma;
+  P.inv_Fr2 = p.inv_Fr2;
+  P.Da = p.Da_ib > 0 ? p.Da_ib : 1.0;
+  P.p0 = p.p0;
+  P.dt = p.dt;
+  P.reacting = p.reacting;
+  P.qs = p.qs;
+  P.S = p.reacting ? p.S : 1.0;
+  P.k = p.reacting ? std::log((1.0 - p.tol) / p.tol) / (2.0 * p.eps) : 1.0;
+  P.Le_F = p.Le_F;
+  P.Le_O = p.Le_O;
+  P.N_F = (1.0 - p.Le_F) / (P.S * p.Le_F);
+  P.N_O = (p.Le_O - 1.0) / p.Le_O;
+  // F_eps(0) of Eq 3.41: ln cosh(-k) = k + log1p(exp(-2k)) - ln 2
+  const double k = P.k, S = P.S;
+  const double lc = k + std::log1p(std::exp(-2.0 * k)) - std::log(2.0);
+  const double f0 = (-(S + 1.0) * lc / k + (S - 1.0) * (-1.0)) / (2.0 * S);
+  P.fshift = -1.0 - f0;
+  P.has_ib = 0;
+  double nc = p.Pr;
+  if (1.0 > nc) nc = 1.0;
+  if (1.0 / p.Le_F > nc) nc = 1.0 / p.Le_F;
+  if (1.0 / p.Le_O > nc) nc = 1.0 / p.Le_O;
+  P.nu_coef = nc;
+}
+
+// Carves every device array (or only sizes them when cv.base == nullptr).
+bool carve(lm_ctx *c, Carver &cv, std::string *err) {
+  const int nd = c->grid.ndim;
+  const Lay &L = c->lay;
+  const size_t ab = (size_t)L.total * 8;
+  const bool reacting = c->prm.reacting != 0;
+  for (int s = 0; s < 3; ++s) {
+    Level &lv = c->lev[s];
+    memset(&lv, 0, sizeof(lv));
+    lv.rho = (double *)cv.take(ab);
+    for (int d = 0; d < nd; ++d) lv.v[d] = (double *)cv.take(ab);
+    lv.Z = reacting ? (double *)cv.take(ab) : nullptr;
+    lv.H = (double *)cv.take(ab);
+    lv.T = (double *)cv.take(ab);
+    lv.kap = (double *)cv.take(ab);
+    for (int d = 0; d < nd; ++d) lv.F[d] = (double *)cv.take(ab);
+    c->P[s] = (double *)cv.take(ab);
+  }
+  c->rho_prev = (double *)cv.take(ab);
+  for (int r = 0; r < 2; ++r) {
+    memset(&c->R[r], 0, sizeof(Resid));
+    c->R[r].H = (double *)cv.take(ab);
+    c->R[r].Z = reacting ? (double *)cv.take(ab) : nullptr;
+    for (int d = 0; d < nd; ++d) c->R[r].v[d] = (double *)cv.take(ab);
+  }
+  for (int d = 0; d < 3; ++d) c->M[d] = d < nd ? (double *)cv.take(ab) : nullptr;
+  c->b = (double *)cv.take(ab);
+  memset(&c->ib, 0, sizeof(c->ib));
+  for (int q = 0; q < 6; ++q) c->ib_store[q] = nullptr;
+  c->chi_store = nullptr;
+  if (c->prm.with_ib) {
+    c->chi_store = (unsigned char *)cv.take((size_t)L.total);
+    for (int q = 0; q < nd + 3; ++q) c->ib_store[q] = (double *)cv.take(ab);
+  }
+  memset(&c->sides, 0, sizeof(c->sides));
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < 2; ++s)
+      for (int q = 0; q < 6; ++q) c->side_store[d][s][q] = nullptr;
+  for (int d = 0; d < nd; ++d)
+    for (int s = 0; s < 2; ++s)
+      if (c->grid.bc[d][s] == LM_SIDE_INFLOW) {
+        const size_t nside = (size_t)(L.ncells() / L.n[d]);
+        for (int q = 0; q < 6; ++q) c->side_store[d][s][q] = (double *)cv.take(nside * 8);
+      }
+  long mx = 1;
+  for (int d = 0; d < 3; ++d) mx *= (L.n[d] + 1);
+  c->staging_bytes = (size_t)mx * 8;
+  c->staging = (double *)cv.take(c->staging_bytes);
+  c->dflags = (int *)cv.take(64);
+  c->dscalar = (double *)cv.take(64);
+  double h[3];
+  for (int d = 0; d < 3; ++d) h[d] = c->phys.h[d];
+  return poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision == LM_MIXED,
+                      c->prm.mg_nu > 0 ? c->prm.mg_nu : 2, err);
+}
+
+void setup_layout(lm_ctx *c) {
+  c->lay = make_layout(c->grid.ndim, c->grid.n, 8);
+  Bnd &B = c->bnd;
+  B.all_periodic = 1;
+  for (int d = 0; d < 3; ++d) {
+    for (int s = 0; s < 2; ++s) B.kind[d][s] = d < c->grid.ndim ? c->grid.bc[d][s] : LM_SIDE_PERIODIC;
+    B.periodic[d] = B.kind[d][0] == LM_SIDE_PERIODIC;
+    if (d < c->grid.ndim && !B.periodic[d]) B.all_periodic = 0;
+  }
+}
+
+Level &cur(lm_ctx *c) { return c->lev[c->icur]; }
+
+lm_status copy_in(lm_ctx *c, const double *src, double *dst, int face_dir, int mem) {
+  const Lay &L = c->lay;
+  long m = L.ncells();
+  if (face_dir >= 0) m = m / L.n[face_dir] * (L.n[face_dir] + 1);
+  const double *dsrc = src;
+  if (mem == LM_HOST) {
+    HIPCHK(c, hipMemcpyAsync(c->staging, src, (size_t)m * 8, hipMemcpyHostToDevice, c->st));
+    dsrc = c->staging;
+  }
+  HIPCHK(c, launch_pack(c->st, L, dsrc, dst, face_dir));
+  if (mem == LM_HOST) HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+lm_status copy_out(lm_ctx *c, const double *src, double *dst, int face_dir, int mem) {
+  const Lay &L = c->lay;
+  long m = L.ncells();
+  if (face_dir >= 0) m = m / L.n[face_dir] * (L.n[face_dir] + 1);
+  if (mem == LM_HOST) {
+    HIPCHK(c, launch_unpack(c->st, L, src, c->staging, face_dir));
+    HIPCHK(c, hipMemcpyAsync(dst, c->staging, (size_t)m * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  } else {
+    HIPCHK(c, launch_unpack(c->st, L, src, dst, face_dir));
+  }
+  return LM_OK;
+}
+
+lm_status copy_side(lm_ctx *c, const double *src, double *dst, size_t n, int mem) {
+  if (!src) {
+    HIPCHK(c, hipMemsetAsync(dst, 0, n * 8, c->st));
+    return LM_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(dst, src, n * 8, mem == LM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           c->st));
+  if (mem == LM_HOST) HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t *bytes) {
+  std::string err;
+  if (!bytes || !valid_grid(grid, &err) || !valid_params(params, &err)) return LM_EINVAL;
+  lm_ctx *c = new (std::nothrow) lm_ctx();
+  if (!c) return LM_ENOMEM;
+  c->grid = *grid;
+  c->prm = *params;
+  setup_phys(c);
+  setup_layout(c);
+  Carver cv{nullptr, 0};
+  bool ok = carve(c, cv, &err);
+  delete c;
+  if (!ok) return LM_EUNSUPPORTED;
+  *bytes = cv.off + 256;
+  return LM_OK;
+}
+
+lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, size_t bytes, void *stream,
+                       lm_ctx **out) {
+  if (!out) return LM_EINVAL;
+  *out = nullptr;
+  std::string err;
+  if (!valid_grid(grid, &err) || !valid_params(params, &err)) return LM_EINVAL;
+  if (!ws) return LM_EINVAL;
+  size_t need = 0;
+  lm_status s = lm_workspace_size(grid, params, &need);
+  if (s != LM_OK) return s;
+  if (bytes < need) return LM_ENOMEM;
+  lm_ctx *c = new (std::nothrow) lm_ctx();
+  if (!c) return LM_ENOMEM;
+  c->grid = *grid;
+  c->prm = *params;
+  c->st = (hipStream_t)stream;
+  setup_phys(c);
+  setup_layout(c);
+  char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  Carver cv{base, 0};
+  if (!carve(c, cv, &err)) {
+    delete c;
+    return LM_EUNSUPPORTED;
+  }
+  c->icur = 0;
+  c->inxt = 1;
+  c->istar = 2;
+  c->rprev = 0;
+  c->have_state = 0;
+  c->have_prev = 0;
+  c->time = 0;
+  c->total_iters = 0;
+  c->last_iters[0] = c->last_iters[1] = 0;
+  if (hipHostMalloc((void **)&c->hflags, 64) != hipSuccess ||
+      hipHostMalloc((void **)&c->hscalar, 64) != hipSuccess ||
+      hipHostMalloc((void **)&c->pws.host_sc, sizeof(SolverScalars)) != hipSuccess) {
+    lm_destroy(c);
+    return LM_EHIP;
+  }
+  // zero the whole carved region once (ghost layers, padding, scalars)
+  if (hipMemsetAsync(base, 0, cv.off, c->st) != hipSuccess) {
+    lm_destroy(c);
+    return LM_EHIP;
+  }
+  double h[3] = {c->phys.h[0], c->phys.h[1], c->phys.h[2]};
+  if (poisson_setup(c->st, c->pws, h) != hipSuccess) {
+    lm_destroy(c);
+    return LM_EHIP;
+  }
+  *out = c;
+  return LM_OK;
+}
+
+lm_status lm_set_side(lm_ctx *c, int d, int side, const lm_side_data *data, int mem) {
+  if (!c || !data || d < 0 || d >= c->grid.ndim || side < 0 || side > 1)
+    return fail(c, LM_EINVAL, "bad side arguments");
+  if (c->grid.bc[d][side] != LM_SIDE_INFLOW) return fail(c, LM_EINVAL, "side is not an inflow side");
+  const size_t n = (size_t)(c->lay.ncells() / c->lay.n[d]);
+  double **st = c->side_store[d][side];
+  lm_status s;
+  for (int q = 0; q < 3; ++q) {
+    if (q >= c->grid.ndim) break;
+    if ((s = copy_side(c, data->v[q], st[q], n, mem)) != LM_OK) return s;
+  }
+  if ((s = copy_side(c, data->Z, st[3], n, mem)) != LM_OK) return s;
+  if ((s = copy_side(c, data->H, st[4], n, mem)) != LM_OK) return s;
+  if ((s = copy_side(c, data->F, st[5], n, mem)) != LM_OK) return s;
+  SideData &sd = c->sides.s[d][side];
+  for (int q = 0; q < 3; ++q) sd.v[q] = q < c->grid.ndim ? st[q] : nullptr;
+  sd.Z = st[3];
+  sd.H = st[4];
+  sd.F = st[5];
+  return LM_OK;
+}
+
+lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *ib, int mem) {
+  if (!c || !f) return fail(c, LM_EINVAL, "NULL argument");
+  if (level != 0) return fail(c, LM_EUNSUPPORTED, "only level 0 can be set");
+  if (!f->T && !f->H) return fail(c, LM_EINVAL, "need T or H");
+  const int nd = c->grid.ndim;
+  for (int d = 0; d < nd; ++d)
+    if (!f->v[d]) return fail(c, LM_EINVAL, "need every velocity component");
+  Level &lv = cur(c);
+  lm_status s;
+  for (int d = 0; d < nd; ++d)
+    if ((s = copy_in(c, f->v[d], lv.v[d], -1, mem)) != LM_OK) return s;
+  if (c->prm.reacting) {
+    if (f->Z) {
+      if ((s = copy_in(c, f->Z, lv.Z, -1, mem)) != LM_OK) return s;
+    } else {
+      HIPCHK(c, hipMemsetAsync(lv.Z, 0, (size_t)c->lay.total * 8, c->st));
+    }
+  }
+  const int from_T = f->T != nullptr;
+  if (from_T) {
+    if ((s = copy_in(c, f->T, lv.T, -1, mem)) != LM_OK) return s;
+  } else {
+    if ((s = copy_in(c, f->H, lv.H, -1, mem)) != LM_OK) return s;
+  }
+  if (f->P) {
+    if ((s = copy_in(c, f->P, c->P[c->icur], -1, mem)) != LM_OK) return s;
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->P[c->icur], 0, (size_t)c->lay.total * 8, c->st));
+  }
+  // immersed boundary
+  c->phys.has_ib = 0;
+  memset(&c->ib, 0, sizeof(c->ib));
+  if (ib) {
+    if (!c->prm.with_ib) return fail(c, LM_EINVAL, "context created without with_ib");
+    if (ib->chi) {
+      const unsigned char *src = ib->chi;
+      if (mem == LM_HOST) {
+        HIPCHK(c, hipMemcpyAsync(c->staging, ib->chi, (size_t)c->lay.ncells(), hipMemcpyHostToDevice, c->st));
+        src = (const unsigned char *)c->staging;
+      }
+      HIPCHK(c, launch_pack_u8(c->st, c->lay, src, c->chi_store));
+      if (mem == LM_HOST) HIPCHK(c, hipStreamSynchronize(c->st));
+      c->ib.chi = c->chi_store;
+      c->phys.has_ib = 1;
+    }
+    const double *srcs[6] = {ib->v_ib[0], ib->v_ib[1], nd == 3 ? ib->v_ib[2] : nullptr, ib->Z_ib, ib->H_ib,
+                             ib->S_m};
+    const int slot[6] = {0, 1, 2, nd, nd + 1, nd + 2};
+    for (int q = 0; q < 6; ++q) {
+      if (!srcs[q]) continue;
+      double *dst = c->ib_store[slot[q]];
+      if ((s = copy_in(c, srcs[q], dst, -1, mem)) != LM_OK) return s;
+      if (q < 3) c->ib.v_ib[q] = dst;
+      if (q == 3) c->ib.Z_ib = dst;
+      if (q == 4) c->ib.H_ib = dst;
+      if (q == 5) c->ib.S_m = dst;
+    }
+  }
+  HIPCHK(c, hipMemsetAsync(c->dflags, 0, 64, c->st));
+  HIPCHK(c, launch_init_state(c->st, c->lay, c->phys, c->bnd, c->sides, from_T, lv, c->dflags));
+  if (f->F[0]) {
+    for (int d = 0; d < nd; ++d) {
+      if (!f->F[d]) return fail(c, LM_EINVAL, "give every face-flux component or none");
+      if ((s = copy_in(c, f->F[d], lv.F[d], d, mem)) != LM_OK) return s;
+    }
+  } else {
+    HIPCHK(c, launch_face_flux(c->st, c->lay, c->bnd, c->sides, lv, c->M));
+  }
+  if (!(c->prm.dt > 0)) {
+    HIPCHK(c, launch_cfl(c->st, c->lay, c->phys, lv, c->ib.chi, c->pws.partials, c->dscalar, &c->pws.sc->counter));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->hflags, c->dflags, 16, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, 8, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (c->hflags[0]) return fail(c, LM_EINVAL, "temperature must be positive everywhere");
+  if (!(c->prm.dt > 0)) {
+    const double m = c->hscalar[0];
+    if (!(m > 0) || !std::isfinite(m)) return fail(c, LM_EINVAL, "cannot fix dt from the CFL condition");
+    c->phys.dt = c->prm.cfl / m;
+  } else {
+    c->phys.dt = c->prm.dt;
+  }
+  c->have_state = 1;
+  c->have_prev = 0;
+  c->time = 0.0;
+  return LM_OK;
+}
+
+static lm_status do_stage(lm_ctx *c, int corrector, int &iters, double &relres, double &compat) {
+  const Lay &L = c->lay;
+  Level &A = c->lev[c->icur];
+  Level &out = corrector ? c->lev[c->inxt] : c->lev[c->istar];
+  Level &src = corrector ? c->lev[c->istar] : A;
+  Resid &rprev = c->R[c->rprev];
+  Resid &rn = c->R[c->rprev ^ 1];
+  HIPCHK(c, launch_ghosts(c->st, L, c->bnd, c->phys, c->sides, src.v, src.Z, src.H, src.T, src.kap));
+  const int first = !c->have_prev;
+  HIPCHK(c, launch_stage(c->st, corrector, first, L, c->phys, src, A, rprev, rn, c->ib, out, c->M));
+  HIPCHK(c, launch_rhs(c->st, L, c->bnd, c->phys, c->sides, c->M, out.rho, A.rho, c->rho_prev, !first, c->ib.S_m,
+                       c->b, c->pws.partials, c->pws.sc));
+  const double *x0 = corrector ? c->P[c->istar] : c->P[c->icur];
+  int conv = 0;
+  const int expect = c->last_iters[corrector];
+  HIPCHK(c, poisson_solve(c->st, c->pws, c->b, x0, c->prm.poisson_rtol, c->prm.poisson_maxit, expect, &iters,
+                          &relres, &conv));
+  compat = c->pws.host_sc->mean_b;
+  c->last_iters[corrector] = iters > 0 ? iters : 1;
+  c->total_iters += iters;
+  if (!conv) return fail(c, LM_ENOCONV, "Poisson solver did not reach poisson_rtol");
+  double *P_out = corrector ? c->P[c->inxt] : c->P[c->istar];
+  HIPCHK(c, launch_project(c->st, L, c->bnd, c->phys, c->sides, c->M, c->pws.x, out.rho, c->pws.sc, out.F, out.v,
+                           P_out, c->dflags + 1));
+  return LM_OK;
+}
+
+lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
+  if (!c) return LM_EINVAL;
+  if (!c->have_state) return fail(c, LM_ESTATE, "lm_set_fields must come first");
+  if (nsteps < 0) return fail(c, LM_EINVAL, "nsteps < 0");
+  int done = 0;
+  int it[2] = {0, 0};
+  double rr[2] = {0, 0}, cm[2] = {0, 0};
+  for (int n = 0; n < nsteps; ++n) {
+    HIPCHK(c, hipMemsetAsync(c->dflags + 1, 0, 4, c->st));
+    lm_status s = do_stage(c, 0, it[0], rr[0], cm[0]);
+    if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
+    if (s == LM_OK) {
+      HIPCHK(c, hipMemcpyAsync(c->hflags + 1, c->dflags + 1, 4, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      if (c->hflags[1]) s = fail(c, LM_ENONFINITE, "non-finite velocity after the step");
+    }
+    if (s != LM_OK) {
+      if (stats) {
+        stats->steps = done;
+        stats->dt = c->phys.dt;
+        stats->time = c->time;
+      }
+      return s;
+    }
+    // commit: level n+1 becomes current; rho^n becomes rho^{n-1}
+    double *old_prev = c->rho_prev;
+    c->rho_prev = c->lev[c->icur].rho;
+    c->lev[c->icur].rho = old_prev;
+    std::swap(c->icur, c->inxt);
+    c->rprev ^= 1;
+    c->have_prev = 1;
+    c->time += c->phys.dt;
+    ++done;
+  }
+  if (stats) {
+    stats->steps = done;
+    stats->dt = c->phys.dt;
+    stats->time = c->time;
+    for (int q = 0; q < 2; ++q) {
+      stats->poisson_iters[q] = it[q];
+      stats->poisson_relres[q] = rr[q];
+      stats->compat[q] = cm[q];
+    }
+    stats->total_poisson_iters = c->total_iters;
+  }
+  return LM_OK;
+}
+
+lm_status lm_project(lm_ctx *c, lm_project_args *a) {
+  if (!c || !a || !a->b) return fail(c, LM_EINVAL, "NULL argument");
+  lm_status s = copy_in(c, a->b, c->b, -1, a->mem);
+  if (s != LM_OK) return s;
+  const Lay &L = c->lay;
+  HIPCHK(c, launch_mean(c->st, L, c->b, c->pws.partials, c->pws.sc));
+  int iters = 0, conv = 0;
+  double relres = 0;
+  const double rtol = a->rtol > 0 ? a->rtol : c->prm.poisson_rtol;
+  HIPCHK(c, poisson_solve(c->st, c->pws, c->b, c->P[c->icur], rtol, c->prm.poisson_maxit, 0, &iters, &relres,
+                          &conv));
+  a->iters = iters;
+  a->relres = relres;
+  a->mean_b = c->pws.host_sc->mean_b;
+  if (!conv) return fail(c, LM_ENOCONV, "Poisson solver did not reach rtol");
+  HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, c->P[c->icur]));
+  if (a->P) return copy_out(c, c->P[c->icur], a->P, -1, a->mem);
+  return LM_OK;
+}
+
+lm_status lm_get_fields(lm_ctx *c, int level, lm_fields *f, int mem) {
+  if (!c || !f) return fail(c, LM_EINVAL, "NULL argument");
+  if (level != 0) return fail(c, LM_EUNSUPPORTED, "only level 0 can be read");
+  if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
+  Level &lv = cur(c);
+  lm_status s;
+  const int nd = c->grid.ndim;
+  if (f->rho && (s = copy_out(c, lv.rho, f->rho, -1, mem)) != LM_OK) return s;
+  for (int d = 0; d < nd; ++d)
+    if (f->v[d] && (s = copy_out(c, lv.v[d], f->v[d], -1, mem)) != LM_OK) return s;
+  if (f->Z) {
+    if (!lv.Z) return fail(c, LM_EINVAL, "Z is not transported (reacting = 0)");
+    if ((s = copy_out(c, lv.Z, f->Z, -1, mem)) != LM_OK) return s;
+  }
+  if (f->H && (s = copy_out(c, lv.H, f->H, -1, mem)) != LM_OK) return s;
+  if (f->T && (s = copy_out(c, lv.T, f->T, -1, mem)) != LM_OK) return s;
+  if (f->P && (s = copy_out(c, c->P[c->icur], f->P, -1, mem)) != LM_OK) return s;
+  for (int d = 0; d < nd; ++d)
+    if (f->F[d] && (s = copy_out(c, lv.F[d], f->F[d], d, mem)) != LM_OK) return s;
+  if (mem == LM_DEVICE) HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+lm_status lm_get_dt(const lm_ctx *c, double *dt) {
+  if (!c || !dt) return LM_EINVAL;
+  if (!c->have_state && !(c->prm.dt > 0)) return LM_ESTATE;
+  *dt = c->phys.dt;
+  return LM_OK;
+}
+
+const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+void lm_destroy(lm_ctx *c) {
+  if (!c) return;
+  if (c->hflags) (void)hipHostFree(c->hflags);
+  if (c->hscalar) (void)hipHostFree(c->hscalar);
+  if (c->pws.host_sc) (void)hipHostFree(c->pws.host_sc);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Device helpers shared by the kernels of liblowmach: cell indexing with
+// periodic wrap, block reductions over 64-wide wavefronts, the single-pass
+// "last block finishes the reduction" pattern, and the flame-sheet
+// temperature map.
+#pragma once
+
+#include "lm_internal.h"
+
+namespace lm {
+
+// Linear block id and cell coordinates of the 2D-tiled launch (64 x 4 blocks,
+// grid z = planes). Returns false for threads past the ragged edge.
+struct CellPos {
+  int i, j, k;
+  long c;
+};
+
+__device__ inline bool cell_of_thread(const Lay &L, CellPos &p) {
+  p.i = blockIdx.x * kBX + threadIdx.x;
+  p.j = blockIdx.y * kBY + threadIdx.y;
+  p.k = blockIdx.z;
+  if (p.i >= L.n[0] || p.j >= L.n[1]) return false;
+  p.c = L.at(p.i, p.j, p.k);
+  return true;
+}
+
+__device__ inline unsigned linear_block() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ inline unsigned num_blocks() { return gridDim.x * gridDim.y * gridDim.z; }
+__device__ inline int linear_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
+
+// Index of the neighbour of cell (coord q along d) at offset +-1 with
+// periodic wrap; returns -1 when the neighbour lies outside a non-periodic
+// side.
+__device__ inline long nbr(const Lay &L, const Bnd &B, long c, int q, int d, int dir) {
+  if (dir > 0) {
+    if (q + 1 < L.n[d]) return c + L.s[d];
+    return B.periodic[d] ? c - (long)(L.n[d] - 1) * L.s[d] : -1;
+  }
+  if (q > 0) return c - L.s[d];
+  return B.periodic[d] ? c + (long)(L.n[d] - 1) * L.s[d] : -1;
+}
+
+__device__ inline int coord(const CellPos &p, int d) { return d == 0 ? p.i : (d == 1 ? p.j : p.k); }
+
+// Sum over a block of kBlock threads; the result is valid in thread 0.
+// Fixed reduction tree, so results are bitwise reproducible.
+__device__ inline double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int t = linear_tid();
+  const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) / 64;
+  __syncthreads();
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0)
+    for (int w = 0; w < nw; ++w) s += sh[w];
+  return s;
+}
+
+__device__ inline double block_max(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int t = linear_tid();
+  const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) / 64;
+  __syncthreads();
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  double s = -1.0;
+  if (t == 0)
+    for (int w = 0; w < nw; ++w) s = fmax(s, sh[w]);
+  return s;
+}
+
+// Publishes this block's partials and returns true in the block that
+// arrives last (all blocks' partials are then visible to it).
+__device__ inline bool arrive_last(unsigned *counter) {
+  __shared__ int last;
+  const int t = linear_tid();
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == num_blocks() - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+// Sum of nb partials (fixed order, whole block participates); valid in thread 0.
+__device__ inline double sum_partials(const double *part, unsigned nb, double *sh) {
+  const int t = linear_tid();
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  double s = 0.0;
+  for (unsigned q = t; q < nb; q += nt) s += part[q];
+  return block_sum(s, sh);
+}
+
+// ---- flame sheet: T(Z, H), section 3.5 -------------------------------------
+
+__device__ inline double lncosh(double x) {
+  const double ax = fabs(x);
+  return ax + log1p(exp(-2.0 * ax)) - 0.69314718055994530942;
+}
+
+// Regularised F of Eq 3.41 translated by fshift (F~(0) = -1).
+__device__ inline double f_tilde(const Phys &P, double Z) {
+  const double S = P.S, k = P.k;
+  const double fe = (-(S + 1.0) * lncosh(k * (Z - 1.0)) / k + (S - 1.0) * (Z - 1.0)) / (2.0 * S);
+  return fe + P.fshift;
+}
+
+// Eq 3.42; without reaction Z = 0 and F(0) = -1 (Eq 3.37).
+__device__ inline double temperature(const Phys &P, double Z, double H) {
+  if (!P.reacting) return P.qs * (H - 1.0);
+  return P.qs * (f_tilde(P, Z) + H);
+}
+
+__device__ inline double theta_eps(const Phys &P, double Z) { return 0.5 * (1.0 + tanh(P.k * (Z - 1.0))); }
+
+}  // namespace lm

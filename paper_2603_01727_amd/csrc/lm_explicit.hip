@@ -1,0 +1,798 @@
+// Explicit part of the predictor-corrector step on the collocated grid:
+// ghost cells (section 3.6), the fused residual + Adams update + equation of
+// state kernel (sections 3.1, 3.2, 3.4, 3.5), the Poisson right-hand side
+// with the outflow mass closure (section 3.1, 3.3) and the projection of
+// face fluxes and cell velocities (Eq 3.23, 3.25).
+#include "lm_device.h"
+
+namespace lm {
+
+// ---------------------------------------------------------------------------
+// Side data and ghost rules
+// ---------------------------------------------------------------------------
+
+// Compact index of the side cell that holds position p on a side normal to d
+// (other coordinates clamped into the interior).
+__device__ inline long side_index(const Lay &L, int d, int i, int j, int k) {
+  i = min(max(i, 0), L.n[0] - 1);
+  j = min(max(j, 0), L.n[1] - 1);
+  k = min(max(k, 0), L.n[2] - 1);
+  if (d == 0) return (long)k * L.n[1] + j;
+  if (d == 1) return (long)k * L.n[0] + i;
+  return (long)j * L.n[0] + i;
+}
+
+enum { R_PER = 0, R_DIR = 1, R_NEU = 2, R_EXT = 3 };
+
+// Ghost rule of field f (0..2 velocity components, 3 Z, 4 H) on side (d, s).
+__device__ inline int ghost_rule(const Bnd &B, int d, int s, int f) {
+  const int kind = B.kind[d][s];
+  switch (kind) {
+    case LM_SIDE_PERIODIC: return R_PER;
+    case LM_SIDE_OUTFLOW: return R_EXT;
+    case LM_SIDE_INFLOW: return R_DIR;
+    case LM_SIDE_NOSLIP: return f < 3 ? R_DIR : R_NEU;
+    default: return (f == d) ? R_DIR : R_NEU;  // slip wall
+  }
+}
+
+__device__ inline double side_value(const Sides &sd, const Lay &L, int d, int s, int f, int i, int j,
+                                    int k) {
+  const SideData &q = sd.s[d][s];
+  const double *a = f < 3 ? q.v[f] : (f == 3 ? q.Z : q.H);
+  if (!a) return 0.0;
+  return a[side_index(L, d, i, j, k)];
+}
+
+// Value of field `a` (rule set f) at ghost position (i, j, k): the rules of
+// the highest out-of-range direction are applied first, which reproduces
+// filling directions in the order x, y, z with each pass covering the ghosts
+// of the directions already filled.
+template <int DIM>
+__device__ double ghost_value(const Lay &L, const Bnd &B, const Sides &sd, const double *a, int f, int i,
+                              int j, int k) {
+  double w[27];
+  int pos[27][3];
+  int nt = 1;
+  w[0] = 1.0;
+  pos[0][0] = i;
+  pos[0][1] = j;
+  pos[0][2] = k;
+  double cst = 0.0;
+  for (int d = DIM - 1; d >= 0; --d) {
+    const int n = L.n[d];
+    const int cur = nt;
+    for (int t = 0; t < cur; ++t) {
+      const int q = pos[t][d];
+      if (q >= 0 && q < n) continue;
+      const int s = q < 0 ? 0 : 1;
+      const int i1 = s == 0 ? 0 : n - 1, i2 = s == 0 ? 1 : n - 2, i3 = s == 0 ? 2 : n - 3;
+      switch (ghost_rule(B, d, s, f)) {
+        case R_PER: pos[t][d] = s == 0 ? n - 1 : 0; break;
+        case R_DIR:
+          cst += 2.0 * w[t] * side_value(sd, L, d, s, f, pos[t][0], pos[t][1], pos[t][2]);
+          w[t] = -w[t];
+          pos[t][d] = i1;
+          break;
+        case R_NEU: pos[t][d] = i1; break;
+        default: {
+          const double wt = w[t];
+          w[t] = 3.0 * wt;
+          pos[t][d] = i1;
+          w[nt] = -3.0 * wt;
+          pos[nt][0] = pos[t][0]; pos[nt][1] = pos[t][1]; pos[nt][2] = pos[t][2];
+          pos[nt][d] = i2;
+          ++nt;
+          w[nt] = wt;
+          pos[nt][0] = pos[t][0]; pos[nt][1] = pos[t][1]; pos[nt][2] = pos[t][2];
+          pos[nt][d] = i3;
+          ++nt;
+        }
+      }
+    }
+  }
+  double v = cst;
+  for (int t = 0; t < nt; ++t) v += w[t] * a[L.at(pos[t][0], pos[t][1], pos[t][2])];
+  return v;
+}
+
+// Ghost position number t of the padded box (box minus interior).
+template <int DIM>
+__device__ inline bool ghost_pos(const Lay &L, long t, int &i, int &j, int &k) {
+  const long nx2 = L.n[0] + 2, ny2 = L.n[1] + 2;
+  if (DIM == 3) {
+    const long a = 2 * nx2 * ny2;
+    if (t < a) {
+      k = (t / (nx2 * ny2)) ? L.n[2] : -1;
+      long r = t % (nx2 * ny2);
+      j = (int)(r / nx2) - 1;
+      i = (int)(r % nx2) - 1;
+      return true;
+    }
+    t -= a;
+  }
+  const int nz = L.n[2];
+  const long b = 2 * nx2 * nz;
+  if (t < b) {
+    long plane = t / (2 * nx2);
+    long r = t % (2 * nx2);
+    k = DIM == 3 ? (int)plane : 0;
+    j = (r / nx2) ? L.n[1] : -1;
+    i = (int)(r % nx2) - 1;
+    return true;
+  }
+  t -= b;
+  const long c = 2L * L.n[1] * nz;
+  if (t < c) {
+    long plane = t / (2L * L.n[1]);
+    long r = t % (2L * L.n[1]);
+    k = DIM == 3 ? (int)plane : 0;
+    j = (int)(r / 2);
+    i = (r % 2) ? L.n[0] : -1;
+    return true;
+  }
+  return false;
+}
+
+template <int DIM>
+inline long ghost_count(const Lay &L) {
+  long nx2 = L.n[0] + 2, ny2 = L.n[1] + 2;
+  long cnt = 2 * nx2 * L.n[2] + 2L * L.n[1] * L.n[2];
+  if (DIM == 3) cnt += 2 * nx2 * ny2;
+  return cnt;
+}
+
+struct GhostArgs {
+  double *v[3], *Z, *H, *T, *kap;
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_ghosts_periodic(Lay L, GhostArgs g, long count) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int i, j, k;
+  if (!ghost_pos<DIM>(L, t, i, j, k)) return;
+  const int si = i < 0 ? L.n[0] - 1 : (i >= L.n[0] ? 0 : i);
+  const int sj = j < 0 ? L.n[1] - 1 : (j >= L.n[1] ? 0 : j);
+  const int sk = DIM == 3 ? (k < 0 ? L.n[2] - 1 : (k >= L.n[2] ? 0 : k)) : k;
+  const long dst = L.at(i, j, k), src = L.at(si, sj, sk);
+  for (int c = 0; c < DIM; ++c) g.v[c][dst] = g.v[c][src];
+  g.H[dst] = g.H[src];
+  if (g.Z) g.Z[dst] = g.Z[src];
+  g.T[dst] = g.T[src];
+  g.kap[dst] = g.kap[src];
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_ghosts_general(Lay L, Bnd B, Phys P, Sides sd, GhostArgs g,
+                                                           long count) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int i, j, k;
+  if (!ghost_pos<DIM>(L, t, i, j, k)) return;
+  const long dst = L.at(i, j, k);
+  for (int c = 0; c < DIM; ++c) g.v[c][dst] = ghost_value<DIM>(L, B, sd, g.v[c], c, i, j, k);
+  const double H = ghost_value<DIM>(L, B, sd, g.H, 4, i, j, k);
+  double Z = 0.0;
+  if (P.reacting) Z = ghost_value<DIM>(L, B, sd, g.Z, 3, i, j, k);
+  g.H[dst] = H;
+  if (g.Z) g.Z[dst] = Z;
+  const double T = temperature(P, Z, H);
+  g.T[dst] = T;
+  g.kap[dst] = pow(T, P.sigma);
+}
+
+hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
+                         double *v[3], double *Z, double *H, double *T, double *kap) {
+  GhostArgs g{{v[0], v[1], v[2]}, Z, H, T, kap};
+  const long cnt = L.ndim == 3 ? ghost_count<3>(L) : ghost_count<2>(L);
+  const unsigned nb = ceil_div(cnt, kBlock);
+  if (B.all_periodic) {
+    if (L.ndim == 3)
+      hipLaunchKernelGGL(k_ghosts_periodic<3>, dim3(nb), dim3(kBlock), 0, st, L, g, cnt);
+    else
+      hipLaunchKernelGGL(k_ghosts_periodic<2>, dim3(nb), dim3(kBlock), 0, st, L, g, cnt);
+  } else {
+    if (L.ndim == 3)
+      hipLaunchKernelGGL(k_ghosts_general<3>, dim3(nb), dim3(kBlock), 0, st, L, B, P, sd, g, cnt);
+    else
+      hipLaunchKernelGGL(k_ghosts_general<2>, dim3(nb), dim3(kBlock), 0, st, L, B, P, sd, g, cnt);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Residuals at one time level and the Adams update
+// ---------------------------------------------------------------------------
+
+// tau_id on the face between cell cl and cl + s_d (Eq 2.46 on d-faces):
+// kappa_f [D_d v_i + D_i v_d - 2/3 delta_id div], D_d the difference across
+// the face, D_k (k != d) the mean of the two cells' centred differences.
+template <int DIM>
+__device__ inline double tau_face(const Lay &L, const Phys &P, const Level &lv, long cl, int d, int i) {
+  const long sd = L.s[d];
+  const double kf = 0.5 * (lv.kap[cl] + lv.kap[cl + sd]);
+  double D[3][3];  // D[k][c] = D_k v_c on this face
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double *vc = lv.v[c];
+      if (k == d) {
+        D[k][c] = (vc[cl + sd] - vc[cl]) * P.ih[d];
+      } else {
+        const long sk = L.s[k];
+        const double h2 = 2.0 * P.h[k];
+        const double a = (vc[cl + sk] - vc[cl - sk]) / h2;
+        const double b = (vc[cl + sd + sk] - vc[cl + sd - sk]) / h2;
+        D[k][c] = 0.5 * (a + b);
+      }
+    }
+  }
+  double t = D[d][i] + D[i][d];
+  if (i == d) {
+    double div = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) div += D[k][k];
+    t = t - (2.0 / 3.0) * div;
+  }
+  return kf * t;
+}
+
+// Scalar terms of Eq 3.26b and the centred diffusion of section 3.2.
+template <int DIM>
+__device__ inline void scalar_terms(const Lay &L, const Phys &P, const Level &lv, const double *phi, long c,
+                                    double &adv, double &dif) {
+  adv = 0.0;
+  dif = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const long s = L.s[d];
+    const double gp = (phi[c + s] - phi[c]) / P.h[d];
+    const double gm = (phi[c] - phi[c - s]) / P.h[d];
+    const double kp = 0.5 * (lv.kap[c] + lv.kap[c + s]);
+    const double km = 0.5 * (lv.kap[c - s] + lv.kap[c]);
+    adv = adv + 0.5 * (lv.F[d][c] * gp + lv.F[d][c - s] * gm);
+    dif = dif + (kp * gp - km * gm) / P.h[d];
+  }
+}
+
+template <int DIM>
+__device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, const IB &ib, long c, double &RH,
+                                 double &RZ, double Rv[3]) {
+  const double rho = lv.rho[c];
+  const double kap = lv.kap[c];
+  const double chi = (P.has_ib && ib.chi) ? (double)ib.chi[c] : 0.0;
+  double advH, difH;
+  scalar_terms<DIM>(L, P, lv, lv.H, c, advH, difH);
+  double rH = -advH + difH / P.Pe;
+  RZ = 0.0;
+  if (P.reacting) {
+    double advZ, difZ;
+    scalar_terms<DIM>(L, P, lv, lv.Z, c, advZ, difZ);
+    const double Z = lv.Z[c];
+    const double th = theta_eps(P, Z);
+    const double le = (P.Le_F - P.Le_O) * th + P.Le_O;
+    const double nn = (P.N_F - P.N_O) * th + P.N_O;
+    double rZ = -advZ + difZ / (le * P.Pe);
+    rH = rH + nn * difZ / P.Pe;
+    if (chi != 0.0) {
+      const double zib = ib.Z_ib ? ib.Z_ib[c] : 0.0;
+      rZ = rZ - chi * kap * (Z - zib) / (le * P.Pe * P.Da);
+    }
+    RZ = rZ / rho;
+  }
+  if (chi != 0.0) {
+    const double hib = ib.H_ib ? ib.H_ib[c] : 0.0;
+    rH = rH - chi * kap * (lv.H[c] - hib) / (P.Pe * P.Da);
+  }
+  RH = rH / rho;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    double conv = 0.0, visc = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const long s = L.s[d];
+      const double *vi = lv.v[i];
+      const double flp = lv.F[d][c] * (0.5 * (vi[c] + vi[c + s]));
+      const double flm = lv.F[d][c - s] * (0.5 * (vi[c - s] + vi[c]));
+      conv = conv + (flp - flm) / P.h[d];
+      const double tp = tau_face<DIM>(L, P, lv, c, d, i);
+      const double tm = tau_face<DIM>(L, P, lv, c - s, d, i);
+      visc = visc + (tp - tm) / P.h[d];
+    }
+    double r = -conv + (P.Pr / P.Pe) * visc;
+    if (i == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
+    if (chi != 0.0) {
+      const double vib = ib.v_ib[i] ? ib.v_ib[i][c] : 0.0;
+      r = r - chi * (P.Pr / (P.Pe * P.Da)) * kap * (lv.v[i][c] - vib);
+    }
+    Rv[i] = r;
+  }
+}
+
+struct StageArgs {
+  Level cur, n0, out;
+  Resid rprev, rn;
+  IB ib;
+  double *M[3];
+};
+
+// Predictor (corrector = 0): residuals of level n, stored for the corrector
+// and the next step; AB2 (Euler on the first step) for H, Z and rho v
+// (Eq 3.1, 3.3, 3.10); T*, rho*, kappa* from the equation of state (Eq 3.6).
+// Corrector: residuals of the predicted level; AM2 with the stored level-n
+// residuals (Eq 3.12, 3.13, 3.18); T, rho, kappa at n+1 (Eq 3.15).
+template <int DIM, int CORR>
+__global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, int first) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+  double RH, RZ, Rv[3];
+  residuals<DIM>(L, P, a.cur, a.ib, c, RH, RZ, Rv);
+  const double dt = P.dt;
+  const double rho0 = a.n0.rho[c];
+  double H, Z = 0.0;
+  if (!CORR) {
+    a.rn.H[c] = RH;
+    if (P.reacting) a.rn.Z[c] = RZ;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) a.rn.v[i][c] = Rv[i];
+    if (first) {
+      H = a.n0.H[c] + dt * RH;
+      if (P.reacting) Z = a.n0.Z[c] + dt * RZ;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) a.M[i][c] = rho0 * a.n0.v[i][c] + dt * Rv[i];
+    } else {
+      H = a.n0.H[c] + dt * (1.5 * RH - 0.5 * a.rprev.H[c]);
+      if (P.reacting) Z = a.n0.Z[c] + dt * (1.5 * RZ - 0.5 * a.rprev.Z[c]);
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+        a.M[i][c] = rho0 * a.n0.v[i][c] + dt * (1.5 * Rv[i] - 0.5 * a.rprev.v[i][c]);
+    }
+  } else {
+    H = a.n0.H[c] + 0.5 * dt * (RH + a.rn.H[c]);
+    if (P.reacting) Z = a.n0.Z[c] + 0.5 * dt * (RZ + a.rn.Z[c]);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) a.M[i][c] = rho0 * a.n0.v[i][c] + 0.5 * dt * (Rv[i] + a.rn.v[i][c]);
+  }
+  const double T = temperature(P, Z, H);
+  a.out.H[c] = H;
+  if (P.reacting) a.out.Z[c] = Z;
+  a.out.T[c] = T;
+  a.out.rho[c] = P.p0 / T;
+  a.out.kap[c] = pow(T, P.sigma);
+}
+
+hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, const Phys &P,
+                        const Level &cur, const Level &n0, const Resid &rprev, const Resid &rn,
+                        const IB &ib, Level &out, double *M[3]) {
+  StageArgs a;
+  a.cur = cur;
+  a.n0 = n0;
+  a.out = out;
+  a.rprev = rprev;
+  a.rn = rn;
+  a.ib = ib;
+  for (int i = 0; i < 3; ++i) a.M[i] = M[i];
+  dim3 g = grid_for(L), b(kBX, kBY);
+  if (L.ndim == 3) {
+    if (corrector)
+      hipLaunchKernelGGL((k_stage<3, 1>), g, b, 0, st, L, P, a, first);
+    else
+      hipLaunchKernelGGL((k_stage<3, 0>), g, b, 0, st, L, P, a, first);
+  } else {
+    if (corrector)
+      hipLaunchKernelGGL((k_stage<2, 1>), g, b, 0, st, L, P, a, first);
+    else
+      hipLaunchKernelGGL((k_stage<2, 0>), g, b, 0, st, L, P, a, first);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Poisson right-hand side and projection
+// ---------------------------------------------------------------------------
+
+// Prescribed normal mass flux on the boundary face of side (d, s) next to
+// cell p; outflow sides extrapolate the cell momentum quadratically to the
+// face (cells at 1/2, 3/2, 5/2 spacings: weights 15/8, -10/8, 3/8).
+__device__ inline double boundary_flux(const Lay &L, const Bnd &B, const Sides &sd, const double *Md,
+                                       const CellPos &p, int d, int s) {
+  const int kind = B.kind[d][s];
+  if (kind == LM_SIDE_SLIP || kind == LM_SIDE_NOSLIP) return 0.0;
+  if (kind == LM_SIDE_INFLOW) {
+    const double *F = sd.s[d][s].F;
+    return F ? F[side_index(L, d, p.i, p.j, p.k)] : 0.0;
+  }
+  const long sdd = L.s[d];
+  const int q = coord(p, d);
+  long c1 = p.c + (long)((s == 0 ? 0 : L.n[d] - 1) - q) * sdd;
+  long c2 = c1 + (s == 0 ? sdd : -sdd);
+  long c3 = c2 + (s == 0 ? sdd : -sdd);
+  return (15.0 * Md[c1] - 10.0 * Md[c2] + 3.0 * Md[c3]) / 8.0;
+}
+
+struct RhsArgs {
+  const double *M[3];
+  const double *rho_new, *rho_n, *rho_prev, *S_m;
+  double *b, *partials;
+  SolverScalars *sc;
+  int bdf2;
+  int has_outflow;
+  double outflow_area, dV;
+};
+
+// b = sum_d delta_1 G_d + d_t rho - S_m, G_d the face average of the
+// predicted momentum on interior faces and the prescribed flux on boundary
+// faces (Eq 3.9-3.11, 3.17-3.19, 3.24, 3.33). The last block forms mean(b)
+// (periodic / closed) or the uniform outflow shift that makes sum(b) = 0.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, RhsArgs a) {
+  __shared__ double sh[kBlock / 64];
+  CellPos p;
+  double part = 0.0;
+  if (cell_of_thread(L, p)) {
+    const long c = p.c;
+    double div = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double *Md = a.M[d];
+      const int q = coord(p, d);
+      const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
+      const double Gh = nh >= 0 ? 0.5 * (Md[c] + Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
+      const double Gl = nl >= 0 ? 0.5 * (Md[nl] + Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
+      div = div + (Gh - Gl) / P.h[d];
+    }
+    double drho;
+    if (a.bdf2)
+      drho = (3.0 * a.rho_new[c] - 4.0 * a.rho_n[c] + a.rho_prev[c]) / (2.0 * P.dt);
+    else
+      drho = (a.rho_new[c] - a.rho_n[c]) / P.dt;
+    const double src = a.S_m ? drho - a.S_m[c] : drho;
+    const double b = div + src;
+    a.b[c] = b;
+    part = b;
+  }
+  const double s = block_sum(part, sh);
+  if (linear_tid() == 0) a.partials[linear_block()] = s;
+  if (arrive_last(&a.sc->counter)) {
+    const double tot = sum_partials(a.partials, num_blocks(), sh);
+    if (linear_tid() == 0) {
+      a.sc->sum_b = tot;
+      if (a.has_outflow) {
+        a.sc->outflow_c = tot * a.dV / a.outflow_area;
+        a.sc->mean_b = 0.0;
+      } else {
+        a.sc->outflow_c = 0.0;
+        a.sc->mean_b = tot / (double)L.ncells();
+      }
+      a.sc->counter = 0;
+    }
+  }
+}
+
+hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
+                      double *const M[3], const double *rho_new, const double *rho_n,
+                      const double *rho_prev, int bdf2, const double *S_m, double *b,
+                      double *partials, SolverScalars *sc) {
+  RhsArgs a;
+  for (int i = 0; i < 3; ++i) a.M[i] = M[i];
+  a.rho_new = rho_new;
+  a.rho_n = rho_n;
+  a.rho_prev = rho_prev;
+  a.S_m = S_m;
+  a.b = b;
+  a.partials = partials;
+  a.sc = sc;
+  a.bdf2 = bdf2;
+  a.has_outflow = 0;
+  a.outflow_area = 0.0;
+  a.dV = 1.0;
+  for (int d = 0; d < L.ndim; ++d) a.dV *= P.h[d];
+  for (int d = 0; d < L.ndim; ++d)
+    for (int s = 0; s < 2; ++s)
+      if (B.kind[d][s] == LM_SIDE_OUTFLOW) {
+        a.has_outflow = 1;
+        a.outflow_area += a.dV / P.h[d] * (double)L.ncells() / L.n[d];
+      }
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_rhs<3>, g, bl, 0, st, L, B, P, sd, a);
+  else
+    hipLaunchKernelGGL(k_rhs<2>, g, bl, 0, st, L, B, P, sd, a);
+  return hipGetLastError();
+}
+
+struct ProjArgs {
+  const double *M[3];
+  const double *x, *rho_new;
+  const SolverScalars *sc;
+  double *F[3], *v[3], *P_out;
+  int *nonfinite;
+};
+
+// F_d = G_d - delta_1 P on interior faces and the prescribed flux on
+// boundary faces (Eq 3.23; outflow faces carry the uniform shift);
+// v = (M - delta_2 P)/rho_new (Eq 3.25) with P ghosts by quadratic
+// extrapolation at non-periodic sides (Eq 3.27-3.28); P stored zero-mean.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides sd, ProjArgs a) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+  const double *x = a.x;
+  const double oc = a.sc->outflow_c;
+  const double xc = x ? x[c] : 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double *Md = a.M[d];
+    const int q = coord(p, d);
+    const long sdd = L.s[d];
+    const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
+    double xp, xm;
+    if (nh >= 0) {
+      xp = x ? x[nh] : 0.0;
+      const double G = 0.5 * (Md[c] + Md[nh]);
+      a.F[d][c] = G - (xp - xc) / P.h[d];
+    } else {
+      double G = boundary_flux(L, B, sd, Md, p, d, 1);
+      if (B.kind[d][1] == LM_SIDE_OUTFLOW) G -= oc;
+      a.F[d][c] = G;
+      xp = x ? 3.0 * xc - 3.0 * x[c - sdd] + x[c - 2 * sdd] : 0.0;
+    }
+    if (nl >= 0) {
+      xm = x ? x[nl] : 0.0;
+      if (q == 0) {  // periodic: duplicate of the wrapped face, same arithmetic
+        const double G = 0.5 * (Md[nl] + Md[c]);
+        a.F[d][c - sdd] = G - (xc - xm) / P.h[d];
+      }
+    } else {
+      double G = boundary_flux(L, B, sd, Md, p, d, 0);
+      if (B.kind[d][0] == LM_SIDE_OUTFLOW) G += oc;
+      a.F[d][c - sdd] = G;
+      xm = x ? 3.0 * xc - 3.0 * x[c + sdd] + x[c + 2 * sdd] : 0.0;
+    }
+    const double v = (Md[c] - (xp - xm) / (2.0 * P.h[d])) / a.rho_new[c];
+    a.v[d][c] = v;
+    bad |= !isfinite(v);
+  }
+  if (a.P_out) a.P_out[c] = (x == nullptr || a.sc->zero) ? 0.0 : xc - a.sc->mean_x;
+  if (bad) atomicOr(a.nonfinite, 1);
+}
+
+hipError_t launch_project(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
+                          double *const M[3], const double *x, const double *rho_new,
+                          const SolverScalars *sc, double *F[3], double *v[3], double *P_out,
+                          int *nonfinite) {
+  ProjArgs a;
+  for (int i = 0; i < 3; ++i) {
+    a.M[i] = M[i];
+    a.F[i] = F[i];
+    a.v[i] = v[i];
+  }
+  a.x = x;
+  a.rho_new = rho_new;
+  a.sc = sc;
+  a.P_out = P_out;
+  a.nonfinite = nonfinite;
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_project<3>, g, bl, 0, st, L, B, P, sd, a);
+  else
+    hipLaunchKernelGGL(k_project<2>, g, bl, 0, st, L, B, P, sd, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels
+// ---------------------------------------------------------------------------
+
+// H from T by inverting Eq 3.42 (or T from H), then T re-evaluated from
+// (Z, H), rho = p0/T (Eq 2.49), kappa = T^sigma (Eq 2.50).
+__global__ void __launch_bounds__(kBlock) k_init_state(Lay L, Phys P, Level lv, int from_T, int *bad) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+  const double Z = P.reacting ? lv.Z[c] : 0.0;
+  double H;
+  if (from_T) {
+    const double T0 = lv.T[c];
+    H = P.reacting ? T0 / P.qs - f_tilde(P, Z) : T0 / P.qs + 1.0;
+    lv.H[c] = H;
+  } else {
+    H = lv.H[c];
+  }
+  const double T = temperature(P, Z, H);
+  if (!(T > 0.0)) atomicOr(bad, 1);
+  lv.T[c] = T;
+  lv.rho[c] = P.p0 / T;
+  lv.kap[c] = pow(T, P.sigma);
+}
+
+hipError_t launch_init_state(hipStream_t st, const Lay &L, const Phys &P, const Bnd &B,
+                             const Sides &sd, int from_T, Level &lv, int *bad_flag) {
+  (void)B;
+  (void)sd;
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  hipLaunchKernelGGL(k_init_state, g, bl, 0, st, L, P, lv, from_T, bad_flag);
+  return hipGetLastError();
+}
+
+// M = rho v at cells (scratch for the initial face flux).
+__global__ void __launch_bounds__(kBlock) k_momentum(Lay L, Level lv, double *M0, double *M1, double *M2) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+  const double r = lv.rho[c];
+  M0[c] = r * lv.v[0][c];
+  M1[c] = r * lv.v[1][c];
+  if (L.ndim == 3) M2[c] = r * lv.v[2][c];
+}
+
+// Initial face flux: face average of rho v (Eq 3.20, n = 1), prescribed
+// flux on boundary faces, extrapolated flux on outflow faces.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_face_flux(Lay L, Bnd B, Sides sd, ProjArgs a) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double *Md = a.M[d];
+    const int q = coord(p, d);
+    const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
+    a.F[d][c] = nh >= 0 ? 0.5 * (Md[c] + Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
+    if (q == 0) a.F[d][c - L.s[d]] = nl >= 0 ? 0.5 * (Md[nl] + Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
+  }
+}
+
+hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Sides &sd,
+                            const Level &lv, double *M[3]) {
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  hipLaunchKernelGGL(k_momentum, g, bl, 0, st, L, lv, M[0], M[1], M[2]);
+  ProjArgs a{};
+  for (int i = 0; i < 3; ++i) {
+    a.M[i] = M[i];
+    a.F[i] = lv.F[i];
+  }
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_face_flux<3>, g, bl, 0, st, L, B, sd, a);
+  else
+    hipLaunchKernelGGL(k_face_flux<2>, g, bl, 0, st, L, B, sd, a);
+  return hipGetLastError();
+}
+
+// dt = CFL / max over cells of sum_d |v_d|/h_d + 2 nu sum_d 1/h_d^2 + chi nu/Da,
+// nu = max(Pr, 1, 1/Le_F, 1/Le_O) kappa/(Pe rho).
+__global__ void __launch_bounds__(kBlock) k_cfl(Lay L, Phys P, Level lv, const unsigned char *chi,
+                                                double *partials, double *out, unsigned *counter) {
+  __shared__ double sh[kBlock / 64];
+  CellPos p;
+  double rate = 0.0;
+  if (cell_of_thread(L, p)) {
+    const long c = p.c;
+    const double nu = P.nu_coef * lv.kap[c] / (P.Pe * lv.rho[c]);
+    double a = 0.0, q = 0.0;
+    for (int d = 0; d < L.ndim; ++d) {
+      a = a + fabs(lv.v[d][c]) / P.h[d];
+      q = q + 1.0 / (P.h[d] * P.h[d]);
+    }
+    rate = a + 2.0 * nu * q;
+    if (chi) rate = rate + (double)chi[c] * nu / P.Da;
+  }
+  const double m = block_max(rate, sh);
+  if (linear_tid() == 0) partials[linear_block()] = m;
+  if (arrive_last(counter)) {
+    double v = -1.0;
+    for (unsigned q = linear_tid(); q < num_blocks(); q += kBlock) v = fmax(v, partials[q]);
+    v = block_max(v, sh);
+    if (linear_tid() == 0) {
+      *out = v;
+      *counter = 0;
+    }
+  }
+}
+
+hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
+                      const unsigned char *chi, double *partials, double *out_max, unsigned *counter) {
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  hipLaunchKernelGGL(k_cfl, g, bl, 0, st, L, P, lv, chi, partials, out_max, counter);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion between compact caller arrays and padded device arrays
+// ---------------------------------------------------------------------------
+
+// face_dir < 0: cell field (nz, ny, nx). face_dir = d: face array with
+// n_d + 1 entries along d, entry f stored at padded cell f - 1 (its high face).
+__global__ void __launch_bounds__(kBlock) k_pack(Lay L, const double *src, double *dst, int fd, int unpack) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long m[3] = {L.n[0], L.n[1], L.n[2]};
+  if (fd >= 0) m[fd] += 1;
+  const long tot = m[0] * m[1] * m[2];
+  if (t >= tot) return;
+  const int i = (int)(t % m[0]);
+  const int j = (int)((t / m[0]) % m[1]);
+  const int k = (int)(t / (m[0] * m[1]));
+  const int o0 = fd == 0 ? -1 : 0, o1 = fd == 1 ? -1 : 0, o2 = fd == 2 ? -1 : 0;
+  const long pidx = L.at(i + o0, j + o1, k + o2);
+  if (unpack)
+    dst[t] = src[pidx];
+  else
+    dst[pidx] = src[t];
+}
+
+hipError_t launch_pack(hipStream_t st, const Lay &L, const double *src, double *dst, int face_dir) {
+  long m = L.ncells();
+  if (face_dir >= 0) m = m / L.n[face_dir] * (L.n[face_dir] + 1);
+  hipLaunchKernelGGL(k_pack, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, L, src, dst, face_dir, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(hipStream_t st, const Lay &L, const double *src, double *dst, int face_dir) {
+  long m = L.ncells();
+  if (face_dir >= 0) m = m / L.n[face_dir] * (L.n[face_dir] + 1);
+  hipLaunchKernelGGL(k_pack, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, st, L, src, dst, face_dir, 1);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) k_pack_u8(Lay L, const unsigned char *src, unsigned char *dst) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.ncells()) return;
+  const int i = (int)(t % L.n[0]);
+  const int j = (int)((t / L.n[0]) % L.n[1]);
+  const int k = (int)(t / ((long)L.n[0] * L.n[1]));
+  dst[L.at(i, j, k)] = src[t];
+}
+
+hipError_t launch_pack_u8(hipStream_t st, const Lay &L, const unsigned char *src, unsigned char *dst) {
+  hipLaunchKernelGGL(k_pack_u8, dim3(ceil_div(L.ncells(), kBlock)), dim3(kBlock), 0, st, L, src, dst);
+  return hipGetLastError();
+}
+
+}  // namespace lm
+
+namespace lm {
+
+// mean(a) over the interior into sc->mean_b (outflow shift cleared).
+__global__ void __launch_bounds__(kBlock) k_mean(Lay L, const double *a, double *partials, SolverScalars *sc) {
+  __shared__ double sh[kBlock / 64];
+  CellPos p;
+  double v = 0.0;
+  if (cell_of_thread(L, p)) v = a[p.c];
+  const double s = block_sum(v, sh);
+  if (linear_tid() == 0) partials[linear_block()] = s;
+  if (arrive_last(&sc->counter)) {
+    const double t = sum_partials(partials, num_blocks(), sh);
+    if (linear_tid() == 0) {
+      sc->sum_b = t;
+      sc->mean_b = t / (double)L.ncells();
+      sc->outflow_c = 0.0;
+      sc->counter = 0;
+    }
+  }
+}
+
+hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc) {
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  hipLaunchKernelGGL(k_mean, g, bl, 0, st, L, a, partials, sc);
+  return hipGetLastError();
+}
+
+// out = x - mean(x) (zero-mean pressure), or 0 when the right-hand side vanished.
+__global__ void __launch_bounds__(kBlock) k_shift(Lay L, const double *x, const SolverScalars *sc, double *out) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  out[p.c] = sc->zero ? 0.0 : x[p.c] - sc->mean_x;
+}
+
+hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out) {
+  dim3 g = grid_for(L), bl(kBX, kBY);
+  hipLaunchKernelGGL(k_shift, g, bl, 0, st, L, x, sc, out);
+  return hipGetLastError();
+}
+
+}  // namespace lm

@@ -1,0 +1,176 @@
+// Internal declarations of liblowmach: data layout, kernel parameter blocks,
+// device reduction helpers and the host-side launch functions shared by the
+// translation units. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/lowmach.h"
+
+namespace lm {
+
+constexpr int kBlock = 256;          // threads per block of the cell kernels
+constexpr int kBX = 64, kBY = 4;     // 2D block shape (one wavefront per row)
+
+// Padded cell layout of one grid level. Every cell array carries one ghost
+// layer per direction (2D arrays have no z ghosts). Rows are padded so that
+// the first interior cell of every row starts on a 128-byte boundary.
+struct Lay {
+  int ndim;
+  int n[3];      // interior cells per direction (n[2] = 1 in 2D)
+  long s[3];     // element strides: 1, row pitch, plane pitch
+  long base;     // element index of interior cell (0,0,0)
+  long total;    // elements to allocate per array
+  __host__ __device__ long at(int i, int j, int k) const { return base + i + j * s[1] + k * s[2]; }
+  __host__ __device__ long ncells() const { return (long)n[0] * n[1] * n[2]; }
+};
+
+Lay make_layout(int ndim, const int n[3], int elem_bytes);
+
+// Boundary description handed to kernels.
+struct Bnd {
+  int kind[3][2];     // LM_SIDE_* per direction and side
+  int periodic[3];    // 1 if direction is periodic
+  int all_periodic;
+};
+
+// Physical and discretisation constants handed to the explicit kernels.
+struct Phys {
+  double h[3], ih[3];
+  double Pe, Pr, sigma, inv_Fr2, Da, p0, dt;
+  int reacting;
+  double qs, S, k, Le_F, Le_O, N_F, N_O, fshift;  // fshift = -1 - F_eps(0)
+  int has_ib;
+  double nu_coef;   // max(Pr, 1, 1/Le_F, 1/Le_O)
+};
+
+// One time level of the state (device pointers into the workspace).
+struct Level {
+  double *rho, *v[3], *Z, *H, *T, *kap, *F[3];
+};
+
+// Residual set of one time level.
+struct Resid {
+  double *H, *Z, *v[3];
+};
+
+// Immersed-boundary arrays (padded layout; NULL when absent).
+struct IB {
+  const unsigned char *chi;
+  const double *v_ib[3], *Z_ib, *H_ib, *S_m;
+};
+
+// Inflow side data (compact, per side cell), device pointers or NULL.
+struct SideData {
+  const double *v[3], *Z, *H, *F;
+};
+
+struct Sides {
+  SideData s[3][2];
+};
+
+// Device scalars of the Poisson solver, one block per solve.
+struct SolverScalars {
+  double rz, pq, alpha, beta, rr, cc, mean_b, sum_b, mean_x, tol2, outflow_c;
+  int done, iters, zero, first, maxit, nonconv;
+  unsigned counter;
+};
+
+// Multigrid level storage (precision chosen at run time, hence void*).
+struct MGLevel {
+  Lay lay;
+  void *x, *b;       // correction, right-hand side
+  double ih2[3];     // 1/h^2 per direction
+};
+
+// ---- helpers -------------------------------------------------------------
+
+inline unsigned ceil_div(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+inline dim3 grid_for(const Lay &L) {
+  return dim3(ceil_div(L.n[0], kBX), ceil_div(L.n[1], kBY), L.n[2]);
+}
+inline long nblocks_for(const Lay &L) {
+  dim3 g = grid_for(L);
+  return (long)g.x * g.y * g.z;
+}
+
+// ---- launchers (explicit part, lm_explicit.hip) --------------------------
+hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
+                         double *v[3], double *Z, double *H, double *T, double *kap);
+hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, const Phys &P,
+                        const Level &cur, const Level &n0, const Resid &rprev, const Resid &rn,
+                        const IB &ib, Level &out, double *M[3]);
+hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
+                      double *const M[3], const double *rho_new, const double *rho_n,
+                      const double *rho_prev, int bdf2, const double *S_m, double *b,
+                      double *partials, SolverScalars *sc);
+hipError_t launch_project(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
+                          double *const M[3], const double *x, const double *rho_new,
+                          const SolverScalars *sc, double *F[3], double *v[3], double *P_out,
+                          int *nonfinite);
+hipError_t launch_pack(hipStream_t st, const Lay &L, const double *src_compact, double *dst_padded,
+                       int face_dir);
+hipError_t launch_unpack(hipStream_t st, const Lay &L, const double *src_padded, double *dst_compact,
+                         int face_dir);
+hipError_t launch_pack_u8(hipStream_t st, const Lay &L, const unsigned char *src, unsigned char *dst);
+hipError_t launch_init_state(hipStream_t st, const Lay &L, const Phys &P, const Bnd &B,
+                             const Sides &sd, int from_T, Level &lv, int *bad_flag);
+hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Sides &sd,
+                            const Level &lv, double *M[3]);
+hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
+                      const unsigned char *chi, double *partials, double *out_max,
+                      unsigned *counter);
+hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc);
+hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);
+
+// ---- Poisson (lm_poisson.hip) ----------------------------------------------
+// Bump allocator over the caller workspace; with base == nullptr it only
+// counts bytes (sizing pass).
+struct Carver {
+  char *base;
+  size_t off;
+  void *take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void *p = base ? (void *)(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+constexpr int kMaxLev = 24;
+constexpr long kCoarseCells = 4096;   // levels at or below this size: one-block kernel
+constexpr long kMaxCoarsest = 1024;   // dense pseudo-inverse limit
+
+struct PoissonWS {
+  Lay lay;                 // fine layout (FP64 CG vectors)
+  Bnd bnd;
+  int nlev, lc;            // MG levels; first level handled by the coarse kernel
+  int mixed, nu;
+  MGLevel lev[kMaxLev];    // lev[0].b is the CG residual, lev[0].x the output z
+  double *x, *r, *p[2], *q;
+  void *z[2];              // preconditioned residuals in MG precision
+  void *pinv;              // dense pseudo-inverse of the coarsest operator
+  double *partials;
+  SolverScalars *sc;       // device scalars
+  SolverScalars *host_sc;  // pinned host copy
+  int pflip, zflip;
+};
+
+// Plans the hierarchy and carves (or sizes, base == nullptr) the solver
+// arrays. Returns false if the grid does not coarsen to <= kMaxCoarsest cells.
+bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed,
+                  int nu, std::string *err);
+// Host-side set-up of the coarsest-level pseudo-inverse (after carving).
+hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h[3]);
+// Solve A x = b for the zero-mean x (A P = sum_d delta_1 delta_1 P with
+// zero-flux non-periodic sides), warm-started from x0 (NULL = 0). b is read
+// with sc->mean_b and the outflow shift sc->outflow_c removed on the fly.
+// The solution stays in ws.x with its mean in sc->mean_x.
+hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const double *x0, double rtol,
+                         int maxit, int expect_iters, int *iters, double *relres, int *converged);
+
+}  // namespace lm

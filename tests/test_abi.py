@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every symbol that include/lowmach.h
+declares; argument checks that need no GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lowmach.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for need in ("lm_workspace_size", "lm_init_grid", "lm_set_fields", "lm_step", "lm_project",
+                 "lm_get_fields", "lm_destroy", "lm_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(lib.EXPORTS) == set(declared_functions())
+
+
+def _grid_params(n=(64, 64), bc=None):
+    from paper_2603_01727_amd import lib
+    g = lib.lm_grid()
+    g.ndim = len(n)
+    for d in range(3):
+        g.n[d] = n[d] if d < len(n) else 1
+        g.L[d] = 1.0
+        for s in range(2):
+            g.bc[d][s] = 0 if bc is None else bc[d][s]
+    p = lib.lm_params(Re=100.0, Pr=0.7, sigma=0.7, qs=1.0, S=1.0, eps=0.5, tol=1e-3, Le_F=1.0, Le_O=1.0,
+                      p0=1.0, cfl=0.2, poisson_rtol=1e-10, poisson_maxit=100, mg_nu=2)
+    return g, p
+
+
+def test_workspace_size_scales_with_grid():
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    sizes = []
+    for n in ((64, 64), (128, 128), (32, 32, 32)):
+        g, p = _grid_params(n)
+        b = C.c_size_t()
+        assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+        sizes.append(b.value)
+    assert sizes[1] > 3.5 * sizes[0]
+    # FP64 state: at least ~30 padded arrays of 8 bytes per cell
+    assert sizes[0] > 30 * 64 * 64 * 8
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b = C.c_size_t()
+    g, p = _grid_params((64, 64))
+    g.ndim = 4
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    g, p = _grid_params((64, 64), bc=[(0, 1), (0, 0), (0, 0)])   # broken periodic pair
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    g, p = _grid_params((64, 64))
+    p.poisson_rtol = 0.0
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    g, p = _grid_params((250, 250))   # coarsens to 125^2 > 1024 cells
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    ctx = C.c_void_p()
+    g, p = _grid_params((64, 64))
+    assert L.lm_init_grid(C.byref(g), C.byref(p), None, 0, None, C.byref(ctx)) == lib.LM_EINVAL
