@@ -1,0 +1,138 @@
+"""Benchmark: cell-updates/s of the full predictor-corrector step.
+
+Workload: the 2D doubly periodic 2*pi box at 1024^2, FP64, random-mode
+temperature (density ratio up to 4) and solenoidal velocity, Re = 500,
+Pr = 0.7, CFL 0.3, Poisson solved to relative residual 1e-10 in both stages
+(seeded synthetic input). A step is one predictor-corrector pass with two
+multigrid-preconditioned CG solves. The same workload is also timed with the
+mixed-precision preconditioner. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    return ap.parse_args()
+
+
+def time_solver(case, precision, steps, warmup):
+    import torch
+    from paper_2603_01727_amd import Solver
+    p = case.params
+    s = Solver(case.n[:2], case.L[:2], Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"], precision=precision,
+               poisson_rtol=p["poisson_rtol"], poisson_maxit=200, device="cuda:0")
+    s.set(T=case.T, v=case.v)
+    if warmup:
+        s.step(warmup)
+    torch.cuda.synchronize()
+    it0 = s.stats["total_poisson_iters"] if s.stats else 0
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    iters = (s.stats["total_poisson_iters"] - it0) / (2.0 * steps)
+    sec = t1 - t0
+    return dict(sec=sec, ms_per_step=1e3 * sec / steps, value=case.ncells * steps / sec,
+                poisson_iters_per_solve=iters, dt=s.dt, solver=s)
+
+
+def kernel_roofline(s, n):
+    """Times the dominant kernel class (the level-0 multigrid smoother
+    half-sweep) in isolation with HIP events on the solver's stream and
+    prices its algorithmic bytes against the HBM peak."""
+    from paper_2603_01727_amd import lib as L
+    import ctypes as C
+    ms = C.c_double()
+    reps = 200
+    st = s.lib.lm_bench_kernel(s.ctx, 0, reps, C.byref(ms))
+    if st != 0:
+        return None
+    per_launch_s = ms.value * 1e-3
+    # one half-sweep reads x at every cell (neighbours of the updated colour)
+    # and b at half the cells, and writes x at half the cells: 8 + 4 + 4 B/cell
+    bytes_per_cell = 16.0
+    achieved = bytes_per_cell * n * n / per_launch_s / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="k_mg_smooth (level 0, one colour)", avg_us=round(per_launch_s * 1e6, 3),
+                bytes_per_cell=bytes_per_cell)
+
+
+def cpu_baseline(case, nsteps=3):
+    """The FP64 oracle on the host: one warm-up step, then nsteps timed."""
+    from oracle import Grid, Oracle, Params
+    p = case.params
+    g = Grid(case.n[:2], case.L[:2])
+    o = Oracle(g, Params(Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"]))
+    st = o.initial_state(case.T, case.v)
+    st = o.step(st)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        st = o.step(st)
+    sec = time.perf_counter() - t0
+    return dict(value=case.ncells * nsteps / sec, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"{nsteps} steps of the {case.n[0]}x{case.n[1]} workload after one warm-up step "
+                       f"(NumPy FP64, FFT Poisson, single thread), {sec:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from workloads import c2_case
+    case = c2_case(n=a.n)
+    r64 = time_solver(case, "fp64", a.steps, a.warmup)
+    roof = kernel_roofline(r64["solver"], a.n)
+    mixed = None
+    if not a.no_mixed:
+        rmx = time_solver(case, "mixed", a.steps, a.warmup)
+        mixed = dict(value=rmx["value"], ms_per_step=round(rmx["ms_per_step"], 4),
+                     poisson_iters_per_solve=rmx["poisson_iters_per_solve"],
+                     speedup_vs_fp64=round(rmx["value"] / r64["value"], 3))
+    cpu = None if a.no_cpu else cpu_baseline(case)
+    out = {
+        "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",
+        "value": r64["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r64["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded random-mode temperature and solenoidal velocity)",
+        "config": {"workload": f"2D periodic 2pi box {a.n}x{a.n}, random modes |k|<=8, density ratio 4, "
+                               f"Re=500, Pr=0.7, CFL 0.3, Poisson rtol 1e-10",
+                   "cells": case.ncells, "dt": r64["dt"],
+                   "poisson_iters_per_solve": r64["poisson_iters_per_solve"]},
+        "mixed": mixed,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

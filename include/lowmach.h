@@ -174,6 +174,16 @@ lm_status lm_get_fields(lm_ctx *ctx, int level, lm_fields *f, int mem);
 /* The fixed time step (after lm_set_fields when params.dt == 0). */
 lm_status lm_get_dt(const lm_ctx *ctx, double *dt);
 
+/* Kernel timing hook: launches one kernel class `reps` times back to back on
+ * the context's stream between two HIP events and returns the mean duration
+ * of one launch in *avg_ms. Needs a state (after lm_set_fields); the kernels
+ * only touch scratch arrays, so the state is unchanged. which:
+ *   0 level-0 multigrid smoother half-sweep   1 predictor stage kernel
+ *   2 CG search-direction update + operator   3 level-0 residual + restriction
+ *   4 CG solution/residual update              5 coarse-grid V-cycle block
+ *   6 Poisson right-hand side                  7 projection                    */
+lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
+
 const char *lm_last_error(const lm_ctx *ctx);
 
 /* Release the context (the caller still owns workspace and stream). */

@@ -433,7 +433,7 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
     HIPCHK(c, launch_face_flux(c->st, c->lay, c->bnd, c->sides, lv, c->M));
   }
   if (!(c->prm.dt > 0)) {
-    HIPCHK(c, launch_cfl(c->st, c->lay, c->phys, lv, c->ib.chi, c->pws.partials, c->dscalar, &c->pws.sc->counter));
+    HIPCHK(c, launch_cfl(c->st, c->lay, c->phys, lv, c->ib.chi, c->pws.partials, c->dscalar));
   }
   HIPCHK(c, hipMemcpyAsync(c->hflags, c->dflags, 16, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, 8, hipMemcpyDeviceToHost, c->st));
@@ -588,3 +588,52 @@ void lm_destroy(lm_ctx *c) {
 }
 
 }  // extern "C"
+
+extern "C" lm_status lm_bench_kernel(lm_ctx *c, int which, int reps, double *avg_ms) {
+  if (!c || !avg_ms || reps <= 0) return fail(c, LM_EINVAL, "bad arguments");
+  if (!c->have_state) return fail(c, LM_ESTATE, "lm_set_fields must come first");
+  if (which < 0 || which > 7) return fail(c, LM_EINVAL, "unknown kernel class");
+  if (which == 3 && c->pws.lc == 0) return fail(c, LM_EUNSUPPORTED, "grid has no multi-block MG level");
+  // solver kernels run only while the device flag `done` is clear
+  SolverScalars sc{};
+  sc.done = 0;
+  sc.rzh[0] = sc.rzh[1] = 1.0;
+  sc.cc = 1.0;
+  HIPCHK(c, hipMemcpyAsync(c->pws.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  Level &A = c->lev[c->icur];
+  Level &S = c->lev[c->istar];
+  auto one = [&]() -> hipError_t {
+    switch (which) {
+      case 1:
+        return launch_stage(c->st, 0, 1, c->lay, c->phys, A, A, c->R[c->rprev], c->R[c->rprev ^ 1], c->ib, S,
+                            c->M);
+      case 6:
+        return launch_rhs(c->st, c->lay, c->bnd, c->phys, c->sides, c->M, S.rho, A.rho, c->rho_prev, 0, c->ib.S_m,
+                          c->b, c->pws.partials, c->pws.sc);
+      case 7:
+        return launch_project(c->st, c->lay, c->bnd, c->phys, c->sides, c->M, c->pws.x, S.rho, c->pws.sc, S.F,
+                              S.v, c->P[c->istar], c->dflags + 1);
+      default: return poisson_bench_launch(c->st, c->pws, which);
+    }
+  };
+  hipError_t e = one();  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, c->st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = one();
+  if (e == hipSuccess) e = hipEventRecord(e1, c->st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore the solver flag so later predicated launches stay idle
+  sc.done = 1;
+  if (e == hipSuccess) e = hipMemcpyAsync(c->pws.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return fail(c, LM_EHIP, std::string("HIP error in lm_bench_kernel: ") + hipGetErrorString(e));
+  *avg_ms = (double)ms / reps;
+  return LM_OK;
+}

@@ -72,23 +72,9 @@ __device__ inline double block_max(double v, double *sh) {
   return s;
 }
 
-// Publishes this block's partials and returns true in the block that
-// arrives last (all blocks' partials are then visible to it).
-__device__ inline bool arrive_last(unsigned *counter) {
-  __shared__ int last;
-  const int t = linear_tid();
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == num_blocks() - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-// Sum of nb partials (fixed order, whole block participates); valid in thread 0.
+// Sum of nb partials written by an earlier kernel (fixed order, whole block
+// participates); valid in thread 0. Partial sums are always consumed by a
+// later kernel: no grid-wide fence is ever needed.
 __device__ inline double sum_partials(const double *part, unsigned nb, double *sh) {
   const int t = linear_tid();
   const int nt = blockDim.x * blockDim.y * blockDim.z;

@@ -456,18 +456,22 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
   }
   const double s = block_sum(part, sh);
   if (linear_tid() == 0) a.partials[linear_block()] = s;
-  if (arrive_last(&a.sc->counter)) {
-    const double tot = sum_partials(a.partials, num_blocks(), sh);
-    if (linear_tid() == 0) {
-      a.sc->sum_b = tot;
-      if (a.has_outflow) {
-        a.sc->outflow_c = tot * a.dV / a.outflow_area;
-        a.sc->mean_b = 0.0;
-      } else {
-        a.sc->outflow_c = 0.0;
-        a.sc->mean_b = tot / (double)L.ncells();
-      }
-      a.sc->counter = 0;
+}
+
+// One block: total of the right-hand side; mean(b) for periodic / closed
+// domains, or the uniform outflow shift that makes sum(b) = 0.
+__global__ void __launch_bounds__(kBlock) k_rhs_finish(const double *partials, int np, double ncells,
+                                                       int has_outflow, double dV, double area, SolverScalars *sc) {
+  __shared__ double sh[kBlock / 64];
+  const double tot = sum_partials(partials, (unsigned)np, sh);
+  if (threadIdx.x == 0) {
+    sc->sum_b = tot;
+    if (has_outflow) {
+      sc->outflow_c = tot * dV / area;
+      sc->mean_b = 0.0;
+    } else {
+      sc->outflow_c = 0.0;
+      sc->mean_b = tot / ncells;
     }
   }
 }
@@ -501,6 +505,8 @@ hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P,
     hipLaunchKernelGGL(k_rhs<3>, g, bl, 0, st, L, B, P, sd, a);
   else
     hipLaunchKernelGGL(k_rhs<2>, g, bl, 0, st, L, B, P, sd, a);
+  hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
+                     (double)L.ncells(), a.has_outflow, a.dV, a.outflow_area, sc);
   return hipGetLastError();
 }
 
@@ -667,7 +673,7 @@ hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Si
 // dt = CFL / max over cells of sum_d |v_d|/h_d + 2 nu sum_d 1/h_d^2 + chi nu/Da,
 // nu = max(Pr, 1, 1/Le_F, 1/Le_O) kappa/(Pe rho).
 __global__ void __launch_bounds__(kBlock) k_cfl(Lay L, Phys P, Level lv, const unsigned char *chi,
-                                                double *partials, double *out, unsigned *counter) {
+                                                double *partials) {
   __shared__ double sh[kBlock / 64];
   CellPos p;
   double rate = 0.0;
@@ -684,21 +690,22 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Lay L, Phys P, Level lv, const u
   }
   const double m = block_max(rate, sh);
   if (linear_tid() == 0) partials[linear_block()] = m;
-  if (arrive_last(counter)) {
-    double v = -1.0;
-    for (unsigned q = linear_tid(); q < num_blocks(); q += kBlock) v = fmax(v, partials[q]);
-    v = block_max(v, sh);
-    if (linear_tid() == 0) {
-      *out = v;
-      *counter = 0;
-    }
-  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cfl_finish(const double *partials, int np, double *out) {
+  __shared__ double sh[kBlock / 64];
+  double v = -1.0;
+  for (int q = threadIdx.x; q < np; q += kBlock) v = fmax(v, partials[q]);
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) *out = v;
 }
 
 hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
-                      const unsigned char *chi, double *partials, double *out_max, unsigned *counter) {
+                      const unsigned char *chi, double *partials, double *out_max) {
   dim3 g = grid_for(L), bl(kBX, kBY);
-  hipLaunchKernelGGL(k_cfl, g, bl, 0, st, L, P, lv, chi, partials, out_max, counter);
+  hipLaunchKernelGGL(k_cfl, g, bl, 0, st, L, P, lv, chi, partials);
+  hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
+                     out_max);
   return hipGetLastError();
 }
 
@@ -765,20 +772,13 @@ __global__ void __launch_bounds__(kBlock) k_mean(Lay L, const double *a, double 
   if (cell_of_thread(L, p)) v = a[p.c];
   const double s = block_sum(v, sh);
   if (linear_tid() == 0) partials[linear_block()] = s;
-  if (arrive_last(&sc->counter)) {
-    const double t = sum_partials(partials, num_blocks(), sh);
-    if (linear_tid() == 0) {
-      sc->sum_b = t;
-      sc->mean_b = t / (double)L.ncells();
-      sc->outflow_c = 0.0;
-      sc->counter = 0;
-    }
-  }
 }
 
 hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc) {
   dim3 g = grid_for(L), bl(kBX, kBY);
   hipLaunchKernelGGL(k_mean, g, bl, 0, st, L, a, partials, sc);
+  hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
+                     (double)L.ncells(), 0, 1.0, 1.0, sc);
   return hipGetLastError();
 }
 

@@ -74,16 +74,17 @@ struct Sides {
 
 // Device scalars of the Poisson solver, one block per solve.
 struct SolverScalars {
-  double rz, pq, alpha, beta, rr, cc, mean_b, sum_b, mean_x, tol2, outflow_c;
-  int done, iters, zero, first, maxit, nonconv;
-  unsigned counter;
+  double rzh[2];     // r.z of the last two iterations (slot = iteration & 1)
+  double rr, cc;     // last ||r||^2 and ||c||^2 (c: mean-free right-hand side)
+  double mean_b, sum_b, outflow_c, mean_x;
+  int done, iters, zero, nonconv;  // kept contiguous (cleared together)
 };
 
 // Multigrid level storage (precision chosen at run time, hence void*).
 struct MGLevel {
   Lay lay;
-  void *x, *b;       // correction, right-hand side
-  double ih2[3];     // 1/h^2 per direction
+  void *x, *xpost, *b;  // pre- and post-smoothed correction, right-hand side
+  double ih2[3];        // 1/h^2 per direction
 };
 
 // ---- helpers -------------------------------------------------------------
@@ -122,12 +123,11 @@ hipError_t launch_init_state(hipStream_t st, const Lay &L, const Phys &P, const 
 hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Sides &sd,
                             const Level &lv, double *M[3]);
 hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
-                      const unsigned char *chi, double *partials, double *out_max,
-                      unsigned *counter);
+                      const unsigned char *chi, double *partials, double *out_max);
 hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc);
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);
 
-// ---- Poisson (lm_poisson.hip) ----------------------------------------------
+// ---- Poisson (lm_solver.hip) -----------------------------------------------
 // Bump allocator over the caller workspace; with base == nullptr it only
 // counts bytes (sizing pass).
 struct Carver {
@@ -142,7 +142,7 @@ struct Carver {
 };
 
 constexpr int kMaxLev = 24;
-constexpr long kCoarseCells = 4096;   // levels at or below this size: one-block kernel
+constexpr long kCoarseCells = 1024;   // levels at or below this size: one-block LDS kernel
 constexpr long kMaxCoarsest = 1024;   // dense pseudo-inverse limit
 
 struct PoissonWS {
@@ -150,14 +150,16 @@ struct PoissonWS {
   Bnd bnd;
   int nlev, lc;            // MG levels; first level handled by the coarse kernel
   int mixed, nu;
-  MGLevel lev[kMaxLev];    // lev[0].b is the CG residual, lev[0].x the output z
-  double *x, *r, *p[2], *q;
+  MGLevel lev[kMaxLev];    // level 0 uses r, zpre and z below
+  double *x, *r[2], *p[2], *q;
   void *z[2];              // preconditioned residuals in MG precision
+  void *zpre;              // finest-level pre-smoothed correction
   void *pinv;              // dense pseudo-inverse of the coarsest operator
-  double *partials;
+  double *part_cc, *part_pq, *part_rz;  // per-block partial sums
+  long np_max;
+  double *partials;        // scratch partials of once-per-solve reductions
   SolverScalars *sc;       // device scalars
   SolverScalars *host_sc;  // pinned host copy
-  int pflip, zflip;
 };
 
 // Plans the hierarchy and carves (or sizes, base == nullptr) the solver
@@ -172,5 +174,9 @@ hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h[3]);
 // The solution stays in ws.x with its mean in sc->mean_x.
 hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const double *x0, double rtol,
                          int maxit, int expect_iters, int *iters, double *relres, int *converged);
+// One launch of a solver kernel class for timing (see lm_bench_kernel);
+// the caller has cleared sc->done. Returns hipErrorInvalidValue for an
+// unknown class.
+hipError_t poisson_bench_launch(hipStream_t st, PoissonWS &ws, int which);
 
 }  // namespace lm

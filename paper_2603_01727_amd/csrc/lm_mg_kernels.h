@@ -1,0 +1,474 @@
+// Multigrid kernels of the Poisson preconditioner that work out of LDS:
+//  - fused 2D tile kernels with temporal blocking (one launch per level and
+//    direction of the V-cycle), and
+//  - the one-block coarse V-cycle over all levels of at most kCoarseCells
+//    cells, with the dense pseudo-inverse on the coarsest grid.
+// Included by lm_solver.hip only.
+#pragma once
+
+namespace lm {
+
+// ---------------------------------------------------------------------------
+// Fused 2D tile kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Down2DArgs {
+  Lay Lf, Lc;
+  Bnd B;
+  T ihx, ihy, idg;          // 1/h^2 per direction; 1/diag for interior cells
+  const void *b;            // right-hand side (FP64 r_{k-1} on the finest level)
+  T *xpre, *bc;             // outputs: pre-smoothed x, coarse right-hand side
+  // finest-level CG update (k >= 1)
+  double *x;
+  const double *p, *q;
+  double *rnew;
+  const double *part_pq;
+  int np_pq;
+  const SolverScalars *sc;
+  int k;                    // CG iteration (0: plain V-cycle on r_0)
+  int finest;
+  int tiles_x;
+};
+
+template <typename T>
+struct Up2DArgs {
+  Lay Lf, Lc;
+  Bnd B;
+  T ihx, ihy, idg;
+  const T *xpre, *xc;
+  const void *b;      // FP64 r_k on the finest level
+  T *xout;
+  const T *zold;      // flexible CG: z_{k-1}
+  double *part_rz;    // finest level: [rz | rr | rzo] x np
+  int np;
+  const SolverScalars *sc;
+  int finest;
+  int tiles_x;
+};
+
+__device__ inline int wrap_or_out(int g, int n, int periodic) {
+  if (g >= 0 && g < n) return g;
+  if (!periodic) return -1;
+  return g < 0 ? g + n : g - n;
+}
+
+// True when every frame position is a cell with all four neighbours, so
+// the sweeps need no boundary tests (periodic directions always qualify).
+__device__ inline bool frame_interior(const Bnd &B, int gx0, int gy0, int W, int HH, int nx, int ny) {
+  const bool okx = B.periodic[0] || (gx0 > 0 && gx0 + W < nx);
+  const bool oky = B.periodic[1] || (gy0 > 0 && gy0 + HH < ny);
+  return okx && oky;
+}
+
+// Gauss-Seidel value at frame offset o, general case: raw global position
+// (gx, gy) possibly outside a non-periodic side, in which case the cell does
+// not exist (returns false).
+template <typename T, int W>
+__device__ inline bool gs_general(const T *xs, const T *bs, int o, int gx, int gy, int nx, int ny, const Bnd &B,
+                                  T ihx, T ihy, bool zero_nb, T &out) {
+  if (!B.periodic[0] && (gx < 0 || gx >= nx)) return false;
+  if (!B.periodic[1] && (gy < 0 || gy >= ny)) return false;
+  T sx = T(0), sy = T(0);
+  int cx = 0, cy = 0;
+  if (B.periodic[0] || gx > 0) {
+    if (!zero_nb) sx += xs[o - 1];
+    ++cx;
+  }
+  if (B.periodic[0] || gx + 1 < nx) {
+    if (!zero_nb) sx += xs[o + 1];
+    ++cx;
+  }
+  if (B.periodic[1] || gy > 0) {
+    if (!zero_nb) sy += xs[o - W];
+    ++cy;
+  }
+  if (B.periodic[1] || gy + 1 < ny) {
+    if (!zero_nb) sy += xs[o + W];
+    ++cy;
+  }
+  out = (bs[o] + (ihx * sx + ihy * sy)) / (ihx * (T)cx + ihy * (T)cy);
+  return true;
+}
+
+// (L x) at frame offset o (cell known to exist).
+template <typename T, int W>
+__device__ inline T lx_general(const T *xs, int o, int gx, int gy, int nx, int ny, const Bnd &B, T ihx, T ihy) {
+  T sx = T(0), sy = T(0);
+  int cx = 0, cy = 0;
+  if (B.periodic[0] || gx > 0) {
+    sx += xs[o - 1];
+    ++cx;
+  }
+  if (B.periodic[0] || gx + 1 < nx) {
+    sx += xs[o + 1];
+    ++cx;
+  }
+  if (B.periodic[1] || gy > 0) {
+    sy += xs[o - W];
+    ++cy;
+  }
+  if (B.periodic[1] || gy + 1 < ny) {
+    sy += xs[o + W];
+    ++cy;
+  }
+  return (ihx * (T)cx + ihy * (T)cy) * xs[o] - (ihx * sx + ihy * sy);
+}
+
+// Half-sweeps s = S0 .. S1 on shrinking regions [s, W-s) x [s, HH-s) of a
+// W x HH frame; colour of half-sweep s is (s + cshift) & 1 (0 = red).
+// Cells of one colour are enumerated directly (two per row pair), so the
+// loop has compile-time bounds and no parity test.
+template <typename T, int W, int HH, int S0, int S1, int CSHIFT>
+__device__ inline void sweeps(T *xs, const T *bs, int p0, int gx0, int gy0, int nx, int ny, const Bnd &B, T ihx,
+                              T ihy, T idg, bool fast, bool zero_first) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = S0; s <= S1; ++s) {
+    const int color = (s + CSHIFT) & 1;
+    const int w = W - 2 * s, rows = HH - 2 * s;
+    const int half = w / 2;
+    const int cnt = half * rows;
+    const bool zn = zero_first && s == S0;
+    for (int o = tid; o < cnt; o += kBlock) {
+      const int ly = s + o / half;
+      const int lx = s + 2 * (o % half) + ((color + p0 + ly + s) & 1);
+      const int off = ly * W + lx;
+      if (fast) {
+        if (zn)
+          xs[off] = bs[off] * idg;
+        else
+          xs[off] = (bs[off] + (ihx * (xs[off - 1] + xs[off + 1]) + ihy * (xs[off - W] + xs[off + W]))) * idg;
+      } else {
+        T v;
+        if (gs_general<T, W>(xs, bs, off, gx0 + lx, gy0 + ly, nx, ny, B, ihx, ihy, zn, v)) xs[off] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Down: [CG update] + NU red-black sweeps from zero + residual + restriction.
+template <typename T, int NU>
+__global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
+  constexpr int H = 2 * NU + 1;
+  constexpr int W = TX + 2 * H, HH = TY + 2 * H;
+  __shared__ T xs[W * HH];
+  __shared__ T bs[W * HH];
+  __shared__ double sh[kBlock / 64];
+  if (a.sc->done) return;
+  const int nx = a.Lf.n[0], ny = a.Lf.n[1];
+  const int tile = blockIdx.x;
+  const int gx0 = (tile % a.tiles_x) * TX - H, gy0 = (tile / a.tiles_x) * TY - H;
+  const int p0 = (gx0 + gy0) & 1;
+  const int tid = threadIdx.x;
+  const bool fast = frame_interior(a.B, gx0, gy0, W, HH, nx, ny);
+  double alpha = 0.0;
+  const bool cg = a.finest && a.k >= 1;
+  if (cg) {
+    const double pq = sum_all(a.part_pq, a.np_pq, sh);
+    alpha = a.sc->rzh[(a.k - 1) & 1] / pq;
+  }
+  // right-hand side on the frame minus its outer ring
+  for (int o = tid; o < W * HH; o += kBlock) {
+    const int lx = o % W, ly = o / W;
+    T bv = T(0);
+    const bool ring = (lx == 0 || ly == 0 || lx == W - 1 || ly == HH - 1);
+    const int gx = wrap_or_out(gx0 + lx, nx, a.B.periodic[0]);
+    const int gy = wrap_or_out(gy0 + ly, ny, a.B.periodic[1]);
+    if (!ring && gx >= 0 && gy >= 0) {
+      const long c = a.Lf.at(gx, gy, 0);
+      if (a.finest) {
+        double rv = ((const double *)a.b)[c];
+        if (cg) {
+          rv = rv - alpha * a.q[c];
+          const bool own = lx >= H && lx < H + TX && ly >= H && ly < H + TY;
+          if (own) {
+            a.rnew[c] = rv;
+            a.x[c] += alpha * a.p[c];
+          }
+        }
+        bv = (T)rv;
+      } else {
+        bv = ((const T *)a.b)[c];
+      }
+    }
+    bs[o] = bv;
+  }
+  __syncthreads();
+  // zero initial guess: the first (red) half-sweep reads no neighbours, and
+  // every later half-sweep only reads cells updated before it
+  sweeps<T, W, HH, 1, 2 * NU, 1>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, true);
+  for (int o = tid; o < TX * TY; o += kBlock) {
+    const int lx = H + o % TX, ly = H + o / TX;
+    a.xpre[a.Lf.at(gx0 + lx, gy0 + ly, 0)] = xs[ly * W + lx];
+  }
+  for (int o = tid; o < (TX / 2) * (TY / 2); o += kBlock) {
+    const int cx = o % (TX / 2), cy = o / (TX / 2);
+    T acc = T(0);
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int lx = H + 2 * cx + dx, ly = H + 2 * cy + dy;
+        const int off = ly * W + lx;
+        T Lx;
+        if (fast)
+          Lx = (T(2) * (a.ihx + a.ihy)) * xs[off] - (a.ihx * (xs[off - 1] + xs[off + 1]) + a.ihy * (xs[off - W] + xs[off + W]));
+        else
+          Lx = lx_general<T, W>(xs, off, gx0 + lx, gy0 + ly, nx, ny, a.B, a.ihx, a.ihy);
+        acc += bs[off] - Lx;
+      }
+    const int Cx = (gx0 + H) / 2 + cx, Cy = (gy0 + H) / 2 + cy;
+    a.bc[a.Lc.at(Cx, Cy, 0)] = acc * T(0.25);
+  }
+}
+
+// Up: prolongation + NU black-red sweeps; finest level: r.z, r.r partials.
+template <typename T, int NU>
+__global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
+  constexpr int H = 2 * NU;
+  constexpr int W = TX + 2 * H, HH = TY + 2 * H;
+  __shared__ T xs[W * HH];
+  __shared__ T bs[W * HH];
+  __shared__ double sh[kBlock / 64];
+  if (a.sc->done) return;
+  const int nx = a.Lf.n[0], ny = a.Lf.n[1];
+  const int tile = blockIdx.x;
+  const int gx0 = (tile % a.tiles_x) * TX - H, gy0 = (tile / a.tiles_x) * TY - H;
+  const int p0 = (gx0 + gy0) & 1;
+  const int tid = threadIdx.x;
+  const bool fast = frame_interior(a.B, gx0, gy0, W, HH, nx, ny);
+  for (int o = tid; o < W * HH; o += kBlock) {
+    const int lx = o % W, ly = o / W;
+    const int gx = wrap_or_out(gx0 + lx, nx, a.B.periodic[0]);
+    const int gy = wrap_or_out(gy0 + ly, ny, a.B.periodic[1]);
+    T xv = T(0), bv = T(0);
+    if (gx >= 0 && gy >= 0) {
+      const long c = a.Lf.at(gx, gy, 0);
+      xv = a.xpre[c] + a.xc[a.Lc.at(gx >> 1, gy >> 1, 0)];
+      const bool ring = (lx == 0 || ly == 0 || lx == W - 1 || ly == HH - 1);
+      if (!ring) bv = a.finest ? (T)((const double *)a.b)[c] : ((const T *)a.b)[c];
+    }
+    xs[o] = xv;
+    bs[o] = bv;
+  }
+  __syncthreads();
+  sweeps<T, W, HH, 1, 2 * NU, 0>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, false);
+  double rz = 0.0, rr = 0.0, rzo = 0.0;
+  for (int o = tid; o < TX * TY; o += kBlock) {
+    const int lx = H + o % TX, ly = H + o / TX;
+    const long c = a.Lf.at(gx0 + lx, gy0 + ly, 0);
+    const T zv = xs[ly * W + lx];
+    a.xout[c] = zv;
+    if (a.finest) {
+      const double rv = ((const double *)a.b)[c];
+      rz += rv * (double)zv;
+      rr += rv * rv;
+      if (a.zold) rzo += rv * (double)a.zold[c];
+    }
+  }
+  if (a.finest) {
+    const double s0 = block_sum(rz, sh);
+    const double s1 = block_sum(rr, sh);
+    const double s2 = a.zold ? block_sum(rzo, sh) : 0.0;
+    if (linear_tid() == 0) {
+      a.part_rz[blockIdx.x] = s0;
+      a.part_rz[a.np + blockIdx.x] = s1;
+      a.part_rz[2 * a.np + blockIdx.x] = s2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-block coarse V-cycle in LDS
+// ---------------------------------------------------------------------------
+constexpr int kCoarseLds = 1408;  // cells of all coarse levels together
+
+template <typename T>
+struct CoarseArgs {
+  int l0, nlev, nu;
+  Bnd B;
+  int n[kMaxLev][3];
+  int off[kMaxLev];        // LDS offset of each level (compact, x fastest)
+  int lg[kMaxLev][2];      // log2(n[0]/2), log2(n[1]) or -1 when not a power of two
+  Ih2<T> ih2[kMaxLev];
+  Lay L0;                  // global layout of level l0
+  const void *b0;          // global right-hand side of level l0
+  int b0_double;
+  T *x0;                   // global output: correction of level l0
+  const T *pinv;           // dense pseudo-inverse of the coarsest level
+};
+
+template <int DIM, typename T>
+__device__ inline void c_decode(const int n[3], int t, int &i, int &j, int &k) {
+  const int n0 = n[0], n1 = n[1];
+  int row;
+  if ((n0 & (n0 - 1)) == 0) {
+    i = t & (n0 - 1);
+    row = t >> __builtin_ctz(n0);
+  } else {
+    row = t / n0;
+    i = t - row * n0;
+  }
+  if (DIM == 3) {
+    if ((n1 & (n1 - 1)) == 0) {
+      j = row & (n1 - 1);
+      k = row >> __builtin_ctz(n1);
+    } else {
+      k = row / n1;
+      j = row - k * n1;
+    }
+  } else {
+    j = row;
+    k = 0;
+  }
+}
+
+template <int DIM, typename T>
+__device__ inline void c_parts(const int n[3], const Bnd &B, const T ih2[3], const T *x, int i, int j, int k, T &nbs,
+                               T &dg) {
+  nbs = T(0);
+  dg = T(0);
+  const int q[3] = {i, j, k};
+  const int st[3] = {1, n[0], n[0] * n[1]};
+  const int c = i + n[0] * (j + n[1] * k);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    T s = T(0);
+    int cnt = 0;
+    if (q[d] > 0) {
+      s += x[c - st[d]];
+      ++cnt;
+    } else if (B.periodic[d]) {
+      s += x[c + (n[d] - 1) * st[d]];
+      ++cnt;
+    }
+    if (q[d] + 1 < n[d]) {
+      s += x[c + st[d]];
+      ++cnt;
+    } else if (B.periodic[d]) {
+      s += x[c - (n[d] - 1) * st[d]];
+      ++cnt;
+    }
+    nbs += ih2[d] * s;
+    dg += ih2[d] * (T)cnt;
+  }
+}
+
+// q = t / n, r = t % n with a shift when lg >= 0 (n = 2^lg).
+__device__ inline int c_divmod(int t, int n, int lg, int &r) {
+  if (lg >= 0) {
+    r = t & (n - 1);
+    return t >> lg;
+  }
+  const int q = t / n;
+  r = t - q * n;
+  return q;
+}
+
+// One red/black half-sweep of level l (even n[0]); the cells of one colour
+// are enumerated directly: i = 2m + ((colour + j + k) & 1).
+template <int DIM, typename T>
+__device__ inline void c_half(const CoarseArgs<T> &a, T *xs, const T *bs, int l, int color, bool zero_init) {
+  const int *n = a.n[l];
+  const int h0 = n[0] >> 1;
+  const int N = h0 * n[1] * n[2];
+  T *x = xs + a.off[l];
+  const T *b = bs + a.off[l];
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    int m, j, k = 0;
+    const int row = c_divmod(t, h0, a.lg[l][0], m);
+    if (DIM == 3)
+      k = c_divmod(row, n[1], a.lg[l][1], j);
+    else
+      j = row;
+    const int i = 2 * m + ((color + j + k) & 1);
+    const int idx = i + n[0] * (j + n[1] * k);
+    T nbs, dg;
+    c_parts<DIM, T>(n, a.B, a.ih2[l].v, x, i, j, k, nbs, dg);
+    if (zero_init) nbs = T(0);
+    x[idx] = (b[idx] + nbs) / dg;
+  }
+  __syncthreads();
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, const SolverScalars *sc) {
+  __shared__ T xs[kCoarseLds];
+  __shared__ T bs[kCoarseLds];
+  if (sc->done) return;
+  const int last = a.nlev - 1;
+  {
+    const int *n = a.n[a.l0];
+    const int N = n[0] * n[1] * n[2];
+    for (int t = threadIdx.x; t < N; t += blockDim.x) {
+      int i, j, k;
+      c_decode<DIM, T>(n, t, i, j, k);
+      const long g = a.L0.at(i, j, k);
+      bs[a.off[a.l0] + t] = a.b0_double ? (T)((const double *)a.b0)[g] : ((const T *)a.b0)[g];
+    }
+    __syncthreads();
+  }
+  for (int l = a.l0; l < last; ++l) {
+    for (int s = 0; s < a.nu; ++s) {
+      c_half<DIM, T>(a, xs, bs, l, 0, s == 0);
+      c_half<DIM, T>(a, xs, bs, l, 1, false);
+    }
+    const int *nf = a.n[l], *nc = a.n[l + 1];
+    const int Nc = nc[0] * nc[1] * nc[2];
+    const T *x = xs + a.off[l];
+    const T *b = bs + a.off[l];
+    for (int t = threadIdx.x; t < Nc; t += blockDim.x) {
+      int I, J, K;
+      c_decode<DIM, T>(nc, t, I, J, K);
+      T acc = T(0);
+      for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int i = 2 * I + dx, j = 2 * J + dy, k = DIM == 3 ? 2 * K + dz : 0;
+            const int c = i + nf[0] * (j + nf[1] * k);
+            T nbs, dg;
+            c_parts<DIM, T>(nf, a.B, a.ih2[l].v, x, i, j, k, nbs, dg);
+            acc += b[c] - (dg * x[c] - nbs);
+          }
+      bs[a.off[l + 1] + t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
+    }
+    __syncthreads();
+  }
+  {
+    const int *n = a.n[last];
+    const int N = n[0] * n[1] * n[2];
+    for (int row = threadIdx.x; row < N; row += blockDim.x) {
+      T acc = T(0);
+      for (int col = 0; col < N; ++col) acc += a.pinv[(long)row * N + col] * bs[a.off[last] + col];
+      xs[a.off[last] + row] = acc;
+    }
+    __syncthreads();
+  }
+  for (int l = last - 1; l >= a.l0; --l) {
+    const int *nf = a.n[l], *nc = a.n[l + 1];
+    const int N = nf[0] * nf[1] * nf[2];
+    for (int t = threadIdx.x; t < N; t += blockDim.x) {
+      int i, j, k;
+      c_decode<DIM, T>(nf, t, i, j, k);
+      const int pc = (i >> 1) + nc[0] * ((j >> 1) + nc[1] * (DIM == 3 ? (k >> 1) : 0));
+      xs[a.off[l] + t] += xs[a.off[l + 1] + pc];
+    }
+    __syncthreads();
+    for (int s = 0; s < a.nu; ++s) {
+      c_half<DIM, T>(a, xs, bs, l, 1, false);
+      c_half<DIM, T>(a, xs, bs, l, 0, false);
+    }
+  }
+  {
+    const int *n = a.n[a.l0];
+    const int N = n[0] * n[1] * n[2];
+    for (int t = threadIdx.x; t < N; t += blockDim.x) {
+      int i, j, k;
+      c_decode<DIM, T>(n, t, i, j, k);
+      a.x0[a.L0.at(i, j, k)] = xs[a.off[a.l0] + t];
+    }
+  }
+}
+
+}  // namespace lm

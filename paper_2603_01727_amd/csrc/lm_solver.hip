@@ -1,0 +1,881 @@
+// Pressure Poisson solver: preconditioned conjugate gradients on the
+// singular, symmetric operator L = -A, A P = sum_d delta_1 delta_1 P (the
+// discrete continuity constraint Eq 3.24 with the face flux of Eq 3.23;
+// zero flux through non-periodic sides, section 3.3). The preconditioner is
+// one symmetric geometric multigrid V-cycle: red-black Gauss-Seidel
+// (red-black down, black-red up), 2^d-cell averaging restriction,
+// piecewise-constant prolongation, rediscretised coarse operators and an
+// exact pseudo-inverse on the coarsest grid, so the zero-mean solution is
+// obtained as with the augmented-matrix method the paper uses. In mixed mode
+// the V-cycle runs in FP32 and CG (flexible, Polak-Ribiere beta) in FP64.
+//
+// Kernel structure. Iteration k is a fixed kernel sequence
+//   pq(k) -> [update(k)] -> V-cycle(k)
+// Scalars never leave the device. A reduction kernel writes one partial sum
+// per block; the next kernel that needs the total has every block sum those
+// partials in the same fixed order (no atomics, no grid-wide fences, bitwise
+// reproducible). Convergence is decided inside pq(k), which raises a device
+// flag that turns every later kernel into an immediate return; the host
+// queues iterations in batches and reads the flag once per batch.
+//
+// On 2D levels whose sizes are multiples of the 64 x 16 tile, the V-cycle
+// uses LDS tiles with temporal blocking: one kernel per level on the way down
+// (nu red-black sweeps from a zero guess, residual, restriction; on the
+// finest level also the CG update of x and r) and one on the way up
+// (prolongation, nu black-red sweeps; on the finest level also the r.z and
+// r.r partial sums). Other levels use one kernel per half-sweep.
+#include <cmath>
+#include <vector>
+
+#include "lm_device.h"
+
+namespace lm {
+
+constexpr int kCoarseThreads = 1024;
+constexpr int kRedBlocks = 1024;   // grid of the grid-stride reduction kernels
+constexpr int TX = 64, TY = 16;    // 2D tile of the fused multigrid kernels
+
+Lay make_layout(int ndim, const int n[3], int elem_bytes) {
+  Lay L;
+  L.ndim = ndim;
+  const int align = 128 / elem_bytes;  // elements per 128-byte line
+  for (int d = 0; d < 3; ++d) L.n[d] = d < ndim ? n[d] : 1;
+  const long px = ((long)(L.n[0] + 2) + align - 1) / align * align;
+  const long py = L.n[1] + 2;
+  L.s[0] = 1;
+  L.s[1] = px;
+  L.s[2] = ndim == 3 ? px * py : 0;
+  const long planes = ndim == 3 ? L.n[2] + 2 : 1;
+  long b0 = 1 + px + (ndim == 3 ? L.s[2] : 0);
+  const long shift = (align - (b0 % align)) % align;
+  L.base = b0 + shift;
+  L.total = shift + px * py * planes + align;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+
+// Block-wide sum returned to every thread (fixed tree).
+__device__ inline double block_allsum(double v, double *sh) {
+  const double s = block_sum(v, sh);
+  __shared__ double bc;
+  if (linear_tid() == 0) bc = s;
+  __syncthreads();
+  const double r = bc;
+  __syncthreads();
+  return r;
+}
+
+// Sum of np partials, identical in every block and thread.
+__device__ inline double sum_all(const double *part, int np, double *sh) {
+  const int t = linear_tid();
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  double s = 0.0;
+  for (int q = t; q < np; q += nt) s += part[q];
+  return block_allsum(s, sh);
+}
+
+template <int DIM>
+__device__ inline void decode(const Lay &L, long t, int &i, int &j, int &k);
+
+// Grid-stride loops run over 64 x 4 tiles of cells (one wavefront per row):
+// one 32-bit division per tile instead of per cell.
+__device__ inline int ntiles_of(const Lay &L) { return ((L.n[0] + 63) >> 6) * ((L.n[1] + 3) >> 2) * L.n[2]; }
+
+__device__ inline bool tile_cell(const Lay &L, int tile, int &i, int &j, int &k) {
+  const int tx = (L.n[0] + 63) >> 6, ty = (L.n[1] + 3) >> 2;
+  const int txy = tx * ty;
+  k = tile / txy;
+  const int rem = tile - k * txy;
+  const int y = rem / tx;
+  const int x = rem - y * tx;
+  i = (x << 6) + (threadIdx.x & 63);
+  j = (y << 2) + (threadIdx.x >> 6);
+  return i < L.n[0] && j < L.n[1];
+}
+
+template <int DIM>
+__device__ inline void decode(const Lay &L, long t, int &i, int &j, int &k) {
+  i = (int)(t % L.n[0]);
+  j = (int)((t / L.n[0]) % L.n[1]);
+  k = DIM == 3 ? (int)(t / ((long)L.n[0] * L.n[1])) : 0;
+}
+
+// Neighbour sum and diagonal of L = -A at one cell (periodic wrap, zero
+// flux through non-periodic sides).
+template <int DIM, typename A, typename T>
+__device__ inline void op_parts(const Lay &L, const Bnd &B, const A ih2[3], const T *x, int i, int j, int k,
+                                long c, A &nbsum, A &diag) {
+  nbsum = A(0);
+  diag = A(0);
+  const int q[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    A s = A(0);
+    int cnt = 0;
+    const long lo = (q[d] > 0) ? c - L.s[d] : (B.periodic[d] ? c + (long)(L.n[d] - 1) * L.s[d] : -1);
+    const long hi = (q[d] + 1 < L.n[d]) ? c + L.s[d] : (B.periodic[d] ? c - (long)(L.n[d] - 1) * L.s[d] : -1);
+    if (lo >= 0) {
+      s += (A)x[lo];
+      ++cnt;
+    }
+    if (hi >= 0) {
+      s += (A)x[hi];
+      ++cnt;
+    }
+    nbsum += ih2[d] * s;
+    diag += ih2[d] * (A)cnt;
+  }
+}
+
+template <typename T>
+struct Ih2 {
+  T v[3];
+};
+
+// ---------------------------------------------------------------------------
+// CG kernels (FP64 vectors on the fine layout, grid-stride over cells)
+// ---------------------------------------------------------------------------
+struct CGArgs {
+  Lay L;
+  Bnd B;
+  double ih2[3], ih[3];
+  const double *b, *x0;
+  double *x;
+  double *rold, *rnew;    // r_{k-1}, r_k
+  double *pold, *pnew;    // p_{k-1}, p_k
+  double *q;
+  const void *z, *zold;   // z_{k-1}, z_{k-2} (flexible)
+  double *part_cc, *part_pq, *part_rz;  // part_rz: [rz | rr | rzo] x np_rz
+  int np_rz, np_pq;
+  SolverScalars *sc;
+  double tol2;
+  int k;
+  int flexible;
+};
+
+// x = x0; r_0 = c - L x0 with c = -(b - mean(b) - outflow shift); ||c||^2 partials.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
+  __shared__ double sh[kBlock / 64];
+  SolverScalars *sc = a.sc;
+  const long N = a.L.ncells();
+  double cc = 0.0;
+  const double mb = sc->mean_b, oc = sc->outflow_c;
+  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
+    int i, j, k;
+    if (!tile_cell(a.L, tile, i, j, k)) continue;
+    const long c = a.L.at(i, j, k);
+    const double xv = a.x0 ? a.x0[c] : 0.0;
+    a.x[c] = xv;
+    double bb = a.b[c] - mb;
+    const int q[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (a.B.kind[d][0] == LM_SIDE_OUTFLOW && q[d] == 0) bb -= oc * a.ih[d];
+      if (a.B.kind[d][1] == LM_SIDE_OUTFLOW && q[d] == a.L.n[d] - 1) bb -= oc * a.ih[d];
+    }
+    const double cv = -bb;
+    double Lx = 0.0;
+    if (a.x0) {
+      double nbs, dg;
+      op_parts<DIM, double, double>(a.L, a.B, a.ih2, a.x0, i, j, k, c, nbs, dg);
+      Lx = dg * xv - nbs;
+    }
+    a.rnew[c] = cv - Lx;
+    cc += cv * cv;
+  }
+  const double s = block_sum(cc, sh);
+  if (linear_tid() == 0) a.part_cc[blockIdx.x] = s;
+}
+
+// Convergence test on r_{k-1}; beta_k; p_k = z_{k-1} + beta_k p_{k-1};
+// q = L p_k; partials of p_k.q.
+template <int DIM, typename TZ>
+__global__ void __launch_bounds__(kBlock) k_cg_pq(CGArgs a, int np_cc) {
+  __shared__ double sh[kBlock / 64];
+  SolverScalars *sc = a.sc;
+  if (sc->done) return;
+  const int k = a.k;
+  const double cc = sum_all(a.part_cc, np_cc, sh);
+  const double rz = sum_all(a.part_rz, a.np_rz, sh);
+  const double rr = sum_all(a.part_rz + a.np_rz, a.np_rz, sh);
+  const double rzo = a.flexible ? sum_all(a.part_rz + 2 * a.np_rz, a.np_rz, sh) : 0.0;
+  const bool converged = (cc == 0.0) || (rr <= a.tol2 * cc);
+  const bool broken = !isfinite(rr) || !isfinite(rz);
+  double beta = 0.0;
+  if (k > 1) beta = (a.flexible ? rz - rzo : rz) / sc->rzh[(k - 2) & 1];
+  if (linear_block() == 0 && linear_tid() == 0) {
+    sc->rzh[(k - 1) & 1] = rz;
+    sc->rr = rr;
+    sc->cc = cc;
+    sc->iters = k - 1;
+    if (converged || broken) {
+      sc->done = 1;
+      sc->zero = (cc == 0.0);
+      sc->nonconv = broken && !converged;
+    }
+  }
+  if (converged || broken) return;
+  const TZ *z = (const TZ *)a.z;
+  const long N = a.L.ncells();
+  double pq = 0.0;
+  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
+    int i, j, kk;
+    if (!tile_cell(a.L, tile, i, j, kk)) continue;
+    const long c = a.L.at(i, j, kk);
+    auto pv = [&](long m) -> double { return k > 1 ? (double)z[m] + beta * a.pold[m] : (double)z[m]; };
+    const double pc = pv(c);
+    double nbs = 0.0, dg = 0.0;
+    const int q[3] = {i, j, kk};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double s = 0.0;
+      int cnt = 0;
+      const long lo = (q[d] > 0) ? c - a.L.s[d] : (a.B.periodic[d] ? c + (long)(a.L.n[d] - 1) * a.L.s[d] : -1);
+      const long hi = (q[d] + 1 < a.L.n[d]) ? c + a.L.s[d]
+                                            : (a.B.periodic[d] ? c - (long)(a.L.n[d] - 1) * a.L.s[d] : -1);
+      if (lo >= 0) {
+        s += pv(lo);
+        ++cnt;
+      }
+      if (hi >= 0) {
+        s += pv(hi);
+        ++cnt;
+      }
+      nbs += a.ih2[d] * s;
+      dg += a.ih2[d] * (double)cnt;
+    }
+    const double qv = dg * pc - nbs;
+    a.pnew[c] = pc;
+    a.q[c] = qv;
+    pq += pc * qv;
+  }
+  const double s = block_sum(pq, sh);
+  if (linear_tid() == 0) a.part_pq[blockIdx.x] = s;
+}
+
+// alpha_k = rho_{k-1}/(p_k.q); x += alpha p_k; r_k = r_{k-1} - alpha q.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_cg_update(CGArgs a) {
+  __shared__ double sh[kBlock / 64];
+  SolverScalars *sc = a.sc;
+  if (sc->done) return;
+  const double pq = sum_all(a.part_pq, a.np_pq, sh);
+  const double alpha = sc->rzh[(a.k - 1) & 1] / pq;
+  const long N = a.L.ncells();
+  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
+    int i, j, k;
+    if (!tile_cell(a.L, tile, i, j, k)) continue;
+    const long c = a.L.at(i, j, k);
+    a.x[c] += alpha * a.pnew[c];
+    a.rnew[c] = a.rold[c] - alpha * a.q[c];
+  }
+}
+
+// Partials of r.z, r.r (and r.z_old) for the unfused finest level.
+template <int DIM, typename TZ>
+__global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
+  __shared__ double sh[kBlock / 64];
+  SolverScalars *sc = a.sc;
+  if (sc->done) return;
+  const TZ *z = (const TZ *)a.z;
+  const TZ *zo = (const TZ *)a.zold;
+  const long N = a.L.ncells();
+  double rz = 0.0, rr = 0.0, rzo = 0.0;
+  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
+    int i, j, k;
+    if (!tile_cell(a.L, tile, i, j, k)) continue;
+    const long c = a.L.at(i, j, k);
+    const double rv = a.rnew[c];
+    rz += rv * (double)z[c];
+    rr += rv * rv;
+    if (zo) rzo += rv * (double)zo[c];
+  }
+  const double s0 = block_sum(rz, sh);
+  const double s1 = block_sum(rr, sh);
+  const double s2 = zo ? block_sum(rzo, sh) : 0.0;
+  if (linear_tid() == 0) {
+    a.part_rz[blockIdx.x] = s0;
+    a.part_rz[a.np_rz + blockIdx.x] = s1;
+    a.part_rz[2 * a.np_rz + blockIdx.x] = s2;
+  }
+}
+
+// Sum of x into partials (mean of the final solution).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_sum_x(Lay L, const double *x, double *part) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0.0;
+  const long N = L.ncells();
+  for (int tile = blockIdx.x; tile < ntiles_of(L); tile += gridDim.x) {
+    int i, j, k;
+    if (!tile_cell(L, tile, i, j, k)) continue;
+    s += x[L.at(i, j, k)];
+  }
+  const double r = block_sum(s, sh);
+  if (linear_tid() == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_mean_x(const double *part, int np, double ncells, SolverScalars *sc) {
+  __shared__ double sh[kBlock / 64];
+  const double s = sum_all(part, np, sh);
+  if (threadIdx.x == 0) sc->mean_x = s / ncells;
+}
+
+// ---------------------------------------------------------------------------
+// Unfused multigrid kernels (any dimension, ragged sizes)
+// ---------------------------------------------------------------------------
+
+// One red (color 0) or black (color 1) half-sweep of Gauss-Seidel on
+// L x = b. With zero_init the previous iterate is zero (first half-sweep
+// of the pre-smoother): red cells take b/diag without reading x.
+template <int DIM, typename TX, typename TB>
+__global__ void __launch_bounds__(kBlock) k_mg_smooth(Lay L, Bnd B, Ih2<TX> ih2, TX *x, const TB *b, int color,
+                                                      int zero_init, const SolverScalars *sc) {
+  if (sc->done) return;
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  if (((p.i + p.j + p.k) & 1) != color) return;
+  TX nbs, dg;
+  op_parts<DIM, TX, TX>(L, B, ih2.v, x, p.i, p.j, p.k, p.c, nbs, dg);
+  if (zero_init && color == 0) nbs = TX(0);
+  x[p.c] = ((TX)b[p.c] + nbs) / dg;
+}
+
+// Coarse right-hand side: average over the 2^DIM children of b - L x.
+template <int DIM, typename TX, typename TB>
+__global__ void __launch_bounds__(kBlock) k_mg_restrict(Lay Lf, Lay Lc, Bnd B, Ih2<TX> ih2, const TX *x,
+                                                        const TB *b, TX *bc, const SolverScalars *sc) {
+  if (sc->done) return;
+  CellPos p;
+  if (!cell_of_thread(Lc, p)) return;
+  TX acc = TX(0);
+#pragma unroll
+  for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int i = 2 * p.i + dx, j = 2 * p.j + dy, k = DIM == 3 ? 2 * p.k + dz : 0;
+        const long c = Lf.at(i, j, k);
+        TX nbs, dg;
+        op_parts<DIM, TX, TX>(Lf, B, ih2.v, x, i, j, k, c, nbs, dg);
+        acc += ((TX)b[c] - (dg * x[c] - nbs));
+      }
+  bc[p.c] = acc * (DIM == 3 ? TX(0.125) : TX(0.25));
+}
+
+// x_fine += x_coarse(parent) (piecewise-constant prolongation).
+template <int DIM, typename TX>
+__global__ void __launch_bounds__(kBlock) k_mg_prolong(Lay Lf, Lay Lc, TX *xf, const TX *xc,
+                                                       const SolverScalars *sc) {
+  if (sc->done) return;
+  CellPos p;
+  if (!cell_of_thread(Lf, p)) return;
+  xf[p.c] += xc[Lc.at(p.i >> 1, p.j >> 1, DIM == 3 ? (p.k >> 1) : 0)];
+}
+
+}  // namespace lm
+
+#include "lm_mg_kernels.h"
+
+namespace lm {
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static bool fused_level(const PoissonWS &ws, int l) {
+  const Lay &L = ws.lev[l].lay;
+  return L.ndim == 2 && ws.nu >= 1 && ws.nu <= 3 && L.n[0] % TX == 0 && L.n[1] % TY == 0 && l < ws.lc;
+}
+
+bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed,
+                  int nu, std::string *err) {
+  ws.lay = fine;
+  ws.bnd = B;
+  ws.mixed = mixed;
+  ws.nu = nu;
+  const int ndim = fine.ndim;
+  const int eb = mixed ? 4 : 8;
+  int n[3] = {fine.n[0], fine.n[1], fine.n[2]};
+  double hh[3] = {h[0], h[1], h[2]};
+  int nl = 0;
+  while (true) {
+    MGLevel &m = ws.lev[nl];
+    m.lay = nl == 0 ? fine : make_layout(ndim, n, eb);
+    for (int d = 0; d < 3; ++d) m.ih2[d] = d < ndim ? 1.0 / (hh[d] * hh[d]) : 0.0;
+    ++nl;
+    long N = (long)n[0] * n[1] * n[2];
+    bool even = true;
+    for (int d = 0; d < ndim; ++d) even = even && (n[d] % 2 == 0) && (n[d] / 2 >= 2);
+    if (!even || N <= 64 || nl == kMaxLev) break;
+    for (int d = 0; d < ndim; ++d) {
+      n[d] /= 2;
+      hh[d] *= 2.0;
+    }
+  }
+  ws.nlev = nl;
+  const long ncoarsest = ws.lev[nl - 1].lay.ncells();
+  if (ncoarsest > kMaxCoarsest) {
+    if (err) *err = "grid does not coarsen to <= 1024 cells (need even sizes down to the coarse grid)";
+    return false;
+  }
+  ws.lc = 0;
+  while (ws.lc < nl - 1 && ws.lev[ws.lc].lay.ncells() > kCoarseCells) ++ws.lc;
+  long lds = 0;
+  for (int l = ws.lc; l < nl; ++l) lds += ws.lev[l].lay.ncells();
+  if (lds > kCoarseLds) {
+    if (err) *err = "coarse grid too large for the one-block coarse solver";
+    return false;
+  }
+  const size_t fbytes = (size_t)fine.total * 8;
+  ws.x = (double *)cv.take(fbytes);
+  ws.r[0] = (double *)cv.take(fbytes);
+  ws.r[1] = (double *)cv.take(fbytes);
+  ws.p[0] = (double *)cv.take(fbytes);
+  ws.p[1] = (double *)cv.take(fbytes);
+  ws.q = (double *)cv.take(fbytes);
+  ws.z[0] = cv.take((size_t)fine.total * eb);
+  ws.z[1] = mixed ? cv.take((size_t)fine.total * eb) : ws.z[0];
+  ws.zpre = cv.take((size_t)fine.total * eb);
+  ws.lev[0].x = nullptr;
+  ws.lev[0].xpost = nullptr;
+  ws.lev[0].b = nullptr;
+  for (int l = 1; l < nl; ++l) {
+    const size_t lb = (size_t)ws.lev[l].lay.total * eb;
+    ws.lev[l].x = cv.take(lb);
+    ws.lev[l].xpost = cv.take(lb);
+    ws.lev[l].b = cv.take(lb);
+  }
+  ws.pinv = cv.take((size_t)ncoarsest * ncoarsest * eb);
+  const long ntile0 = (long)(fine.n[0] / TX) * (fine.n[1] / TY) + 1;
+  long npmax = kRedBlocks;
+  if (ntile0 > npmax) npmax = ntile0;
+  ws.np_max = npmax;
+  ws.part_cc = (double *)cv.take((size_t)npmax * 8);
+  ws.part_pq = (double *)cv.take((size_t)npmax * 8);
+  ws.part_rz = (double *)cv.take((size_t)3 * npmax * 8);
+  ws.partials = (double *)cv.take((size_t)(nblocks_for(fine) + kRedBlocks) * 8 + 64);
+  ws.sc = (SolverScalars *)cv.take(sizeof(SolverScalars));
+  return true;
+}
+
+// Pseudo-inverse of the coarsest operator: (L + J/N)^{-1} - J/N, where J is
+// the all-ones matrix (L is singular with the constants as null space).
+hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h0[3]) {
+  (void)h0;
+  const MGLevel &m = ws.lev[ws.nlev - 1];
+  const Lay &L = m.lay;
+  const long N = L.ncells();
+  std::vector<double> A((size_t)N * N, 0.0), I((size_t)N * N, 0.0);
+  auto idx = [&](int i, int j, int k) { return (long)i + (long)L.n[0] * (j + (long)L.n[1] * k); };
+  for (int k = 0; k < L.n[2]; ++k)
+    for (int j = 0; j < L.n[1]; ++j)
+      for (int i = 0; i < L.n[0]; ++i) {
+        const long r = idx(i, j, k);
+        const int q[3] = {i, j, k};
+        for (int d = 0; d < L.ndim; ++d) {
+          for (int dir = -1; dir <= 1; dir += 2) {
+            int qq[3] = {q[0], q[1], q[2]};
+            qq[d] += dir;
+            if (qq[d] < 0 || qq[d] >= L.n[d]) {
+              if (!ws.bnd.periodic[d]) continue;
+              qq[d] = (qq[d] + L.n[d]) % L.n[d];
+            }
+            const long cidx = idx(qq[0], qq[1], qq[2]);
+            A[r * N + r] += m.ih2[d];
+            A[r * N + cidx] -= m.ih2[d];
+          }
+        }
+      }
+  for (long a = 0; a < N * N; ++a) A[a] += 1.0 / (double)N;
+  for (long a = 0; a < N; ++a) I[a * N + a] = 1.0;
+  for (long col = 0; col < N; ++col) {  // Gauss-Jordan, partial pivoting
+    long piv = col;
+    for (long r = col + 1; r < N; ++r)
+      if (std::fabs(A[r * N + col]) > std::fabs(A[piv * N + col])) piv = r;
+    if (piv != col)
+      for (long c = 0; c < N; ++c) {
+        std::swap(A[col * N + c], A[piv * N + c]);
+        std::swap(I[col * N + c], I[piv * N + c]);
+      }
+    const double d = A[col * N + col];
+    for (long c = 0; c < N; ++c) {
+      A[col * N + c] /= d;
+      I[col * N + c] /= d;
+    }
+    for (long r = 0; r < N; ++r) {
+      if (r == col) continue;
+      const double f = A[r * N + col];
+      if (f == 0.0) continue;
+      for (long c = 0; c < N; ++c) {
+        A[r * N + c] -= f * A[col * N + c];
+        I[r * N + c] -= f * I[col * N + c];
+      }
+    }
+  }
+  for (long a = 0; a < N * N; ++a) I[a] -= 1.0 / (double)N;
+  hipError_t e;
+  if (ws.mixed) {
+    std::vector<float> f(I.begin(), I.end());
+    e = hipMemcpyAsync(ws.pinv, f.data(), f.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  } else {
+    e = hipMemcpyAsync(ws.pinv, I.data(), I.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  return e;
+}
+
+template <typename T>
+static Ih2<T> ih2_of(const PoissonWS &ws, int l) {
+  Ih2<T> v;
+  for (int d = 0; d < 3; ++d) v.v[d] = (T)ws.lev[l].ih2[d];
+  return v;
+}
+
+// Arrays of level l: input (pre-smoothed) and output (post-smoothed)
+// corrections. Unfused levels smooth in place.
+template <typename T>
+static T *lev_xin(PoissonWS &ws, int l, void *z) {
+  if (l == 0) return fused_level(ws, 0) ? (T *)ws.zpre : (T *)z;
+  return (T *)ws.lev[l].x;
+}
+template <typename T>
+static T *lev_xout(PoissonWS &ws, int l, void *z) {
+  if (l == 0) return (T *)z;
+  if (l >= ws.lc) return (T *)ws.lev[l].x;
+  return (fused_level(ws, l) ? (T *)ws.lev[l].xpost : (T *)ws.lev[l].x);
+}
+
+template <typename T>
+static void launch_nu(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
+  if (nu == 1) hipLaunchKernelGGL((k_mg_down2d<T, 1>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_down2d<T, 2>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_down2d<T, 3>), g, dim3(kBlock), 0, st, a);
+}
+template <typename T>
+static void launch_nu(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st) {
+  if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_up2d<T, 3>), g, dim3(kBlock), 0, st, a);
+}
+
+template <typename T>
+static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xpre, double *x, const double *p,
+                               const double *q, double *rnew) {
+  Down2DArgs<T> a;
+  const Lay &L = ws.lev[l].lay;
+  a.Lf = L;
+  a.Lc = ws.lev[l + 1].lay;
+  a.B = ws.bnd;
+  a.ihx = (T)ws.lev[l].ih2[0];
+  a.ihy = (T)ws.lev[l].ih2[1];
+  a.idg = (T)(1.0 / (2.0 * ws.lev[l].ih2[0] + 2.0 * ws.lev[l].ih2[1]));
+  a.finest = (l == 0);
+  a.k = k;
+  a.b = b;
+  a.xpre = xpre;
+  a.bc = (T *)ws.lev[l + 1].b;
+  a.x = x;
+  a.p = p;
+  a.q = q;
+  a.rnew = rnew;
+  a.part_pq = ws.part_pq;
+  a.np_pq = kRedBlocks;
+  a.sc = ws.sc;
+  a.tiles_x = L.n[0] / TX;
+  return a;
+}
+
+template <typename T>
+static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, const void *b, T *xout,
+                           const T *zold) {
+  Up2DArgs<T> a;
+  const Lay &L = ws.lev[l].lay;
+  a.Lf = L;
+  a.Lc = ws.lev[l + 1].lay;
+  a.B = ws.bnd;
+  a.ihx = (T)ws.lev[l].ih2[0];
+  a.ihy = (T)ws.lev[l].ih2[1];
+  a.idg = (T)(1.0 / (2.0 * ws.lev[l].ih2[0] + 2.0 * ws.lev[l].ih2[1]));
+  a.xpre = xpre;
+  a.xc = xc;
+  a.b = b;
+  a.xout = xout;
+  a.finest = (l == 0);
+  a.zold = zold;
+  a.part_rz = ws.part_rz;
+  a.np = (L.n[0] / TX) * (L.n[1] / TY);
+  a.sc = ws.sc;
+  a.tiles_x = L.n[0] / TX;
+  return a;
+}
+
+template <typename T>
+static CoarseArgs<T> coarse_args(PoissonWS &ws, void *z, const double *r) {
+  CoarseArgs<T> ca;
+  ca.l0 = ws.lc;
+  ca.nlev = ws.nlev;
+  ca.nu = ws.nu;
+  ca.B = ws.bnd;
+  int off = 0;
+  auto lg2 = [](int v) {
+    int q = 0;
+    while ((1 << q) < v) ++q;
+    return (1 << q) == v ? q : -1;
+  };
+  for (int l = 0; l < ws.nlev; ++l) {
+    for (int d = 0; d < 3; ++d) ca.n[l][d] = ws.lev[l].lay.n[d];
+    ca.lg[l][0] = lg2(ws.lev[l].lay.n[0] / 2);
+    ca.lg[l][1] = lg2(ws.lev[l].lay.n[1]);
+    ca.ih2[l] = ih2_of<T>(ws, l);
+    ca.off[l] = l >= ws.lc ? off : 0;
+    if (l >= ws.lc) off += (int)ws.lev[l].lay.ncells();
+  }
+  ca.L0 = ws.lev[ws.lc].lay;
+  ca.b0 = ws.lc == 0 ? (const void *)r : ws.lev[ws.lc].b;
+  ca.b0_double = (ws.lc == 0);
+  ca.x0 = ws.lc == 0 ? (T *)z : (T *)ws.lev[ws.lc].x;
+  ca.pinv = (const T *)ws.pinv;
+  return ca;
+}
+
+// V-cycle of iteration k on b = r_k (finest), writing z = z_k.
+template <int DIM, typename T>
+static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
+  const Bnd &B = ws.bnd;
+  const int nu = ws.nu;
+  const SolverScalars *sc = ws.sc;
+  void *z = ws.z[k & 1];
+  const double *r = ws.r[k & 1];
+  const double *rprev = ws.r[(k + 1) & 1];
+  dim3 bb(kBX, kBY);
+  for (int l = 0; l < ws.lc; ++l) {
+    const Lay &L = ws.lev[l].lay, &Lc = ws.lev[l + 1].lay;
+    T *xin = lev_xin<T>(ws, l, z);
+    if (fused_level(ws, l)) {
+      const void *b = l == 0 ? (k >= 1 ? (const void *)rprev : (const void *)r) : ws.lev[l].b;
+      Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
+      launch_nu<T>(nu, a, dim3((L.n[0] / TX) * (L.n[1] / TY)), st);
+    } else {
+      dim3 g = grid_for(L);
+      for (int s = 0; s < nu; ++s) {
+        for (int color = 0; color < 2; ++color) {
+          if (l == 0)
+            hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin, r, color,
+                               s == 0 && color == 0, sc);
+          else
+            hipLaunchKernelGGL((k_mg_smooth<DIM, T, T>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin,
+                               (const T *)ws.lev[l].b, color, s == 0 && color == 0, sc);
+        }
+      }
+      if (l == 0)
+        hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(Lc), bb, 0, st, L, Lc, B, ih2_of<T>(ws, l),
+                           xin, r, (T *)ws.lev[l + 1].b, sc);
+      else
+        hipLaunchKernelGGL((k_mg_restrict<DIM, T, T>), grid_for(Lc), bb, 0, st, L, Lc, B, ih2_of<T>(ws, l), xin,
+                           (const T *)ws.lev[l].b, (T *)ws.lev[l + 1].b, sc);
+    }
+  }
+  hipLaunchKernelGGL((k_mg_coarse<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st, coarse_args<T>(ws, z, r), sc);
+  for (int l = ws.lc - 1; l >= 0; --l) {
+    const Lay &L = ws.lev[l].lay, &Lc = ws.lev[l + 1].lay;
+    T *xin = lev_xin<T>(ws, l, z);
+    T *xout = lev_xout<T>(ws, l, z);
+    const T *xc = lev_xout<T>(ws, l + 1, z);
+    if (fused_level(ws, l)) {
+      const T *zold = (l == 0 && ws.mixed && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
+      Up2DArgs<T> a = up_args<T>(ws, l, xin, xc, l == 0 ? (const void *)r : ws.lev[l].b, xout, zold);
+      launch_nu<T>(nu, a, dim3(a.np), st);
+    } else {
+      dim3 g = grid_for(L);
+      hipLaunchKernelGGL((k_mg_prolong<DIM, T>), g, bb, 0, st, L, Lc, xin, xc, sc);
+      for (int s = 0; s < nu; ++s) {
+        for (int cc = 0; cc < 2; ++cc) {
+          const int color = 1 - cc;
+          if (l == 0)
+            hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin, r, color, 0,
+                               sc);
+          else
+            hipLaunchKernelGGL((k_mg_smooth<DIM, T, T>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin,
+                               (const T *)ws.lev[l].b, color, 0, sc);
+        }
+      }
+    }
+  }
+  if (!fused_level(ws, 0)) {
+    CGArgs a = cg;
+    a.rnew = ws.r[k & 1];
+    a.z = z;
+    a.zold = (ws.mixed && k >= 1) ? ws.z[(k + 1) & 1] : nullptr;
+    a.np_rz = kRedBlocks;
+    hipLaunchKernelGGL((k_cg_rz<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
+  }
+}
+
+static int np_rz_of(const PoissonWS &ws) {
+  return fused_level(ws, 0) ? (ws.lay.n[0] / TX) * (ws.lay.n[1] / TY) : kRedBlocks;
+}
+
+template <int DIM, typename T>
+static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
+  // pq(k): p_k = z_{k-1} + beta p_{k-1}
+  a.k = k;
+  a.z = ws.z[(k - 1) & 1];
+  a.pold = ws.p[(k - 1) & 1];
+  a.pnew = ws.p[k & 1];
+  a.np_rz = np_rz_of(ws);
+  a.flexible = ws.mixed;
+  hipLaunchKernelGGL((k_cg_pq<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks);
+  a.np_pq = kRedBlocks;
+  if (!fused_level(ws, 0)) {
+    a.rold = ws.r[(k - 1) & 1];
+    a.rnew = ws.r[k & 1];
+    hipLaunchKernelGGL((k_cg_update<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
+  }
+  vcycle<DIM, T>(st, ws, k, a);
+}
+
+template <int DIM, typename T>
+static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, const double *x0, double rtol,
+                            int maxit, int expect, int *iters, double *relres, int *converged) {
+  CGArgs a;
+  a.L = ws.lay;
+  a.B = ws.bnd;
+  for (int d = 0; d < 3; ++d) {
+    a.ih2[d] = ws.lev[0].ih2[d];
+    a.ih[d] = std::sqrt(ws.lev[0].ih2[d]);
+  }
+  a.b = bvec;
+  a.x0 = x0;
+  a.x = ws.x;
+  a.rold = nullptr;
+  a.rnew = ws.r[0];
+  a.pold = a.pnew = nullptr;
+  a.q = ws.q;
+  a.z = a.zold = nullptr;
+  a.part_cc = ws.part_cc;
+  a.part_pq = ws.part_pq;
+  a.part_rz = ws.part_rz;
+  a.np_rz = np_rz_of(ws);
+  a.np_pq = kRedBlocks;
+  a.sc = ws.sc;
+  a.tol2 = rtol * rtol;
+  a.k = 0;
+  a.flexible = ws.mixed;
+  hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cg_init<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
+  vcycle<DIM, T>(st, ws, 0, a);
+  int k = 1;
+  int batch = expect > 0 ? expect + 1 : 4;
+  while (true) {
+    for (int q = 0; q < batch && k <= maxit + 1; ++q, ++k) iteration<DIM, T>(st, ws, a, k);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(ws.host_sc, ws.sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (ws.host_sc->done || k > maxit + 1) break;
+    batch = 2;
+  }
+  const SolverScalars &h = *ws.host_sc;
+  *iters = h.iters;
+  *relres = h.cc > 0 ? std::sqrt(h.rr / h.cc) : 0.0;
+  *converged = h.done && !h.nonconv;
+  // mean of the solution (the stored pressure is zero-mean)
+  hipLaunchKernelGGL((k_sum_x<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, ws.lay, (const double *)ws.x,
+                     ws.partials);
+  hipLaunchKernelGGL(k_fin_mean_x, dim3(1), dim3(kBlock), 0, st, (const double *)ws.partials, kRedBlocks,
+                     (double)ws.lay.ncells(), ws.sc);
+  return hipGetLastError();
+}
+
+hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const double *x0, double rtol,
+                         int maxit, int expect_iters, int *iters, double *relres, int *converged) {
+  if (ws.lay.ndim == 3)
+    return ws.mixed ? solve_dim<3, float>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged)
+                    : solve_dim<3, double>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged);
+  return ws.mixed ? solve_dim<2, float>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged)
+                  : solve_dim<2, double>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged);
+}
+
+// ---------------------------------------------------------------------------
+// Timing hook: one launch of a kernel class on scratch arrays
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
+  CGArgs a;
+  a.L = ws.lay;
+  a.B = ws.bnd;
+  for (int d = 0; d < 3; ++d) {
+    a.ih2[d] = ws.lev[0].ih2[d];
+    a.ih[d] = std::sqrt(ws.lev[0].ih2[d]);
+  }
+  a.b = ws.r[0];
+  a.x0 = nullptr;
+  a.x = ws.x;
+  a.rold = ws.r[0];
+  a.rnew = ws.r[1];
+  a.pold = ws.p[0];
+  a.pnew = ws.p[1];
+  a.q = ws.q;
+  a.z = ws.z[0];
+  a.zold = nullptr;
+  a.part_cc = ws.part_cc;
+  a.part_pq = ws.part_pq;
+  a.part_rz = ws.part_rz;
+  a.np_rz = np_rz_of(ws);
+  a.np_pq = kRedBlocks;
+  a.sc = ws.sc;
+  a.tol2 = 0.0;
+  a.k = 2;
+  a.flexible = 0;
+  switch (which) {
+    case 0: {  // finest-level down kernel (fused) or one half-sweep
+      if (fused_level(ws, 0)) {
+        Down2DArgs<T> d = down_args<T>(ws, 0, 2, ws.r[1], (T *)ws.zpre, ws.x, ws.p[0], ws.q, ws.r[0]);
+        launch_nu<T>(ws.nu, d, dim3((ws.lay.n[0] / TX) * (ws.lay.n[1] / TY)), st);
+      } else {
+        hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, ws.lay, ws.bnd,
+                           ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc);
+      }
+      break;
+    }
+    case 2: hipLaunchKernelGGL((k_cg_pq<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks); break;
+    case 3: {  // finest-level up kernel (fused) or restriction
+      if (ws.lc == 0) return hipErrorInvalidValue;
+      if (fused_level(ws, 0)) {
+        Up2DArgs<T> u = up_args<T>(ws, 0, (const T *)ws.zpre, lev_xout<T>(ws, 1, ws.z[0]), ws.r[0], (T *)ws.z[0],
+                                   nullptr);
+        launch_nu<T>(ws.nu, u, dim3(u.np), st);
+      } else {
+        hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(ws.lev[1].lay), dim3(kBX, kBY), 0, st,
+                           ws.lay, ws.lev[1].lay, ws.bnd, ih2_of<T>(ws, 0), (const T *)ws.z[0],
+                           (const double *)ws.r[0], (T *)ws.lev[1].b, ws.sc);
+      }
+      break;
+    }
+    case 4: hipLaunchKernelGGL((k_cg_update<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a); break;
+    case 5:
+      hipLaunchKernelGGL((k_mg_coarse<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st,
+                         coarse_args<T>(ws, ws.z[0], ws.r[0]), ws.sc);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t poisson_bench_launch(hipStream_t st, PoissonWS &ws, int which) {
+  if (ws.lay.ndim == 3)
+    return ws.mixed ? bench_launch_dim<3, float>(st, ws, which) : bench_launch_dim<3, double>(st, ws, which);
+  return ws.mixed ? bench_launch_dim<2, float>(st, ws, which) : bench_launch_dim<2, double>(st, ws, which);
+}
+
+}  // namespace lm

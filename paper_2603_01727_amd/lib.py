@@ -69,6 +69,7 @@ EXPORTS = {
     "lm_project": (C.c_int, [C.c_void_p, C.POINTER(lm_project_args)]),
     "lm_get_fields": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(lm_fields), C.c_int]),
     "lm_get_dt": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lm_bench_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     "lm_last_error": (C.c_char_p, [C.c_void_p]),
     "lm_destroy": (None, [C.c_void_p]),
 }
