@@ -75,6 +75,7 @@ struct Sides {
 // Device scalars of the Poisson solver, one block per solve.
 struct SolverScalars {
   double rzh[2];     // r.z of the last two iterations (slot = iteration & 1)
+  double alh[2];     // alpha of the last two iterations (single-reduction CG)
   double rr, cc;     // last ||r||^2 and ||c||^2 (c: mean-free right-hand side)
   double mean_b, sum_b, outflow_c, mean_x;
   int done, iters, zero, nonconv;  // kept contiguous (cleared together)
@@ -152,6 +153,9 @@ struct PoissonWS {
   int mixed, nu;
   MGLevel lev[kMaxLev];    // level 0 uses r, zpre and z below
   double *x, *r[2], *p[2], *q;
+  int cgcg;                // single-reduction (Chronopoulos-Gear) CG in FP64 mode
+  double tol2;             // rtol^2 of the solve in progress
+  double *w, *s[2];        // its A u and s = A p vectors
   void *z[2];              // preconditioned residuals in MG precision
   void *zpre;              // finest-level pre-smoothed correction
   void *pinv;              // dense pseudo-inverse of the coarsest operator

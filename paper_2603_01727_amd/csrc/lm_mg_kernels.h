@@ -24,10 +24,19 @@ struct Down2DArgs {
   double *rnew;
   const double *part_pq;
   int np_pq;
-  const SolverScalars *sc;
+  SolverScalars *sc;
   int k;                    // CG iteration (0: plain V-cycle on r_0)
   int finest;
   int tiles_x;
+  // single-reduction CG (Chronopoulos-Gear): p, s, x, r updated here
+  int cgcg;
+  const T *u;               // z_{k-1} = M r_{k-1}
+  const double *w;          // A u
+  const double *s_old;      // s_{k-2}
+  double *s_new, *p_io;     // s_{k-1}; p updated in place
+  const double *part_g, *part_cc;  // [gamma | delta | rr] x np_g; ||c||^2 x np_cc
+  int np_g, np_cc;
+  double tol2;
 };
 
 template <typename T>
@@ -39,11 +48,12 @@ struct Up2DArgs {
   const void *b;      // FP64 r_k on the finest level
   T *xout;
   const T *zold;      // flexible CG: z_{k-1}
-  double *part_rz;    // finest level: [rz | rr | rzo] x np
+  double *part_rz;    // finest level: [rz | rr | rzo] x np, or [r.u | w.u | rr] x np
   int np;
   const SolverScalars *sc;
   int finest;
   int tiles_x;
+  double *w;          // single-reduction CG: w = A u written on the finest level
 };
 
 __device__ inline int wrap_or_out(int g, int n, int periodic) {
@@ -162,37 +172,145 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   const int p0 = (gx0 + gy0) & 1;
   const int tid = threadIdx.x;
   const bool fast = frame_interior(a.B, gx0, gy0, W, HH, nx, ny);
-  double alpha = 0.0;
+  double alpha = 0.0, beta = 0.0;
   const bool cg = a.finest && a.k >= 1;
-  if (cg) {
+  if (cg && a.cgcg) {
+    // gamma = r.u, delta = (A u).u, rr = r.r of iteration k-1: convergence
+    // test, then alpha and beta of the single-reduction recurrence
+    const double cc = sum_all(a.part_cc, a.np_cc, sh);
+    double g, d, rr;
+    sum_all3(a.part_g, a.part_g + a.np_g, a.part_g + 2 * a.np_g, a.np_g, sh, g, d, rr);
+    const bool conv = (cc == 0.0) || (rr <= a.tol2 * cc);
+    if (a.k == 1) {
+      alpha = g / d;
+    } else {
+      beta = g / a.sc->rzh[(a.k - 2) & 1];
+      alpha = g / (d - beta * g / a.sc->alh[(a.k - 2) & 1]);
+    }
+    const bool broken = !isfinite(rr) || !isfinite(alpha) || !isfinite(beta);
+    if (blockIdx.x == 0 && tid == 0) {
+      a.sc->rzh[(a.k - 1) & 1] = g;
+      a.sc->alh[(a.k - 1) & 1] = alpha;
+      a.sc->rr = rr;
+      a.sc->cc = cc;
+      a.sc->iters = a.k - 1;
+      if (conv || broken) {
+        a.sc->done = 1;
+        a.sc->zero = (cc == 0.0);
+        a.sc->nonconv = broken && !conv;
+      }
+    }
+    if (conv || broken) return;
+  } else if (cg) {
     const double pq = sum_all(a.part_pq, a.np_pq, sh);
     alpha = a.sc->rzh[(a.k - 1) & 1] / pq;
   }
-  // right-hand side on the frame minus its outer ring
-  for (int o = tid; o < W * HH; o += kBlock) {
+  // right-hand side on the frame minus its outer ring; all loads of the
+  // phase are issued before any is used (addresses of absent cells are
+  // replaced by a valid one and the value discarded)
+  constexpr int NPOS = W * HH;
+  constexpr int NIT = (NPOS + kBlock - 1) / kBlock;
+  long gi[NIT];
+  bool ok[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int o = tid + it * kBlock;
     const int lx = o % W, ly = o / W;
-    T bv = T(0);
     const bool ring = (lx == 0 || ly == 0 || lx == W - 1 || ly == HH - 1);
     const int gx = wrap_or_out(gx0 + lx, nx, a.B.periodic[0]);
     const int gy = wrap_or_out(gy0 + ly, ny, a.B.periodic[1]);
-    if (!ring && gx >= 0 && gy >= 0) {
-      const long c = a.Lf.at(gx, gy, 0);
-      if (a.finest) {
-        double rv = ((const double *)a.b)[c];
-        if (cg) {
-          rv = rv - alpha * a.q[c];
-          const bool own = lx >= H && lx < H + TX && ly >= H && ly < H + TY;
-          if (own) {
-            a.rnew[c] = rv;
-            a.x[c] += alpha * a.p[c];
-          }
-        }
-        bv = (T)rv;
-      } else {
-        bv = ((const T *)a.b)[c];
+    ok[it] = o < NPOS && !ring && gx >= 0 && gy >= 0;
+    gi[it] = ok[it] ? a.Lf.at(gx, gy, 0) : a.Lf.base;
+  }
+  if (a.finest && cg && a.cgcg) {
+    // r_k = r_{k-1} - alpha (w + beta s_{k-2}) on the frame
+    const double *rb = (const double *)a.b;
+    const bool old = a.k >= 2;
+    double rv[NIT], wv[NIT], sv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      rv[it] = rb[gi[it]];
+      wv[it] = a.w[gi[it]];
+      sv[it] = old ? a.s_old[gi[it]] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int o = tid + it * kBlock;
+      if (o < NPOS) bs[o] = ok[it] ? (T)(rv[it] - alpha * (wv[it] + beta * sv[it])) : T(0);
+    }
+    // own cells: p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
+    constexpr int NOWN = TX * TY / kBlock;
+    long oi[NOWN];
+    double ro[NOWN], wo[NOWN], so[NOWN], xo[NOWN], po[NOWN];
+    T uo[NOWN];
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) {
+      const int o = tid + u * kBlock;
+      oi[u] = a.Lf.at(gx0 + H + o % TX, gy0 + H + o / TX, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) {
+      ro[u] = rb[oi[u]];
+      wo[u] = a.w[oi[u]];
+      so[u] = old ? a.s_old[oi[u]] : 0.0;
+      po[u] = old ? a.p_io[oi[u]] : 0.0;
+      xo[u] = a.x[oi[u]];
+      uo[u] = a.u[oi[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) {
+      const double pn = (double)uo[u] + beta * po[u];
+      const double sn = wo[u] + beta * so[u];
+      a.p_io[oi[u]] = pn;
+      a.s_new[oi[u]] = sn;
+      a.x[oi[u]] = xo[u] + alpha * pn;
+      a.rnew[oi[u]] = ro[u] - alpha * (wo[u] + beta * so[u]);
+    }
+  } else if (a.finest) {
+    const double *rb = (const double *)a.b;
+    double rv[NIT], qv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      rv[it] = rb[gi[it]];
+      qv[it] = cg ? a.q[gi[it]] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int o = tid + it * kBlock;
+      if (o < NPOS) bs[o] = ok[it] ? (T)(rv[it] - alpha * qv[it]) : T(0);
+    }
+    if (cg) {  // CG update of the tile's own cells
+      constexpr int NOWN = TX * TY / kBlock;
+      long oi[NOWN];
+      double ro[NOWN], qo[NOWN], xo[NOWN], po[NOWN];
+#pragma unroll
+      for (int u = 0; u < NOWN; ++u) {
+        const int o = tid + u * kBlock;
+        oi[u] = a.Lf.at(gx0 + H + o % TX, gy0 + H + o / TX, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < NOWN; ++u) {
+        ro[u] = rb[oi[u]];
+        qo[u] = a.q[oi[u]];
+        xo[u] = a.x[oi[u]];
+        po[u] = a.p[oi[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < NOWN; ++u) {
+        a.rnew[oi[u]] = ro[u] - alpha * qo[u];
+        a.x[oi[u]] = xo[u] + alpha * po[u];
       }
     }
-    bs[o] = bv;
+  } else {
+    const T *bb = (const T *)a.b;
+    T v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) v[it] = bb[gi[it]];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int o = tid + it * kBlock;
+      if (o < NPOS) bs[o] = ok[it] ? v[it] : T(0);
+    }
   }
   __syncthreads();
   // zero initial guess: the first (red) half-sweep reads no neighbours, and
@@ -224,9 +342,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
 }
 
 // Up: prolongation + NU black-red sweeps; finest level: r.z, r.r partials.
-template <typename T, int NU>
+// With EXTRA = 1 the frame carries one more halo ring, so the smoothed u is
+// valid one cell beyond the tile and w = A u is formed for the tile
+// (single-reduction CG: partials of r.u, w.u and r.r).
+template <typename T, int NU, int EXTRA>
 __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
-  constexpr int H = 2 * NU;
+  constexpr int H = 2 * NU + EXTRA;
   constexpr int W = TX + 2 * H, HH = TY + 2 * H;
   __shared__ T xs[W * HH];
   __shared__ T bs[W * HH];
@@ -238,33 +359,98 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
   const int p0 = (gx0 + gy0) & 1;
   const int tid = threadIdx.x;
   const bool fast = frame_interior(a.B, gx0, gy0, W, HH, nx, ny);
-  for (int o = tid; o < W * HH; o += kBlock) {
+  constexpr int NPOS = W * HH;
+  constexpr int NIT = (NPOS + kBlock - 1) / kBlock;
+  long gi[NIT], ci[NIT];
+  bool okx[NIT], okb[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int o = tid + it * kBlock;
     const int lx = o % W, ly = o / W;
     const int gx = wrap_or_out(gx0 + lx, nx, a.B.periodic[0]);
     const int gy = wrap_or_out(gy0 + ly, ny, a.B.periodic[1]);
-    T xv = T(0), bv = T(0);
-    if (gx >= 0 && gy >= 0) {
-      const long c = a.Lf.at(gx, gy, 0);
-      xv = a.xpre[c] + a.xc[a.Lc.at(gx >> 1, gy >> 1, 0)];
-      const bool ring = (lx == 0 || ly == 0 || lx == W - 1 || ly == HH - 1);
-      if (!ring) bv = a.finest ? (T)((const double *)a.b)[c] : ((const T *)a.b)[c];
+    const bool ring = (lx == 0 || ly == 0 || lx == W - 1 || ly == HH - 1);
+    okx[it] = o < NPOS && gx >= 0 && gy >= 0;
+    okb[it] = okx[it] && !ring;
+    gi[it] = okx[it] ? a.Lf.at(gx, gy, 0) : a.Lf.base;
+    ci[it] = okx[it] ? a.Lc.at(gx >> 1, gy >> 1, 0) : a.Lc.base;
+  }
+  T xv[NIT], cv[NIT], bv[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    xv[it] = a.xpre[gi[it]];
+    cv[it] = a.xc[ci[it]];
+    bv[it] = a.finest ? (T)((const double *)a.b)[gi[it]] : ((const T *)a.b)[gi[it]];
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int o = tid + it * kBlock;
+    if (o < NPOS) {
+      xs[o] = okx[it] ? xv[it] + cv[it] : T(0);
+      bs[o] = okb[it] ? bv[it] : T(0);
     }
-    xs[o] = xv;
-    bs[o] = bv;
   }
   __syncthreads();
+  // regions shrink from the frame edge, so with the extra ring the last
+  // half-sweep leaves u valid on the tile plus one cell
   sweeps<T, W, HH, 1, 2 * NU, 0>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, false);
   double rz = 0.0, rr = 0.0, rzo = 0.0;
-  for (int o = tid; o < TX * TY; o += kBlock) {
+  constexpr int NOWN = TX * TY / kBlock;
+  long oi[NOWN];
+  T zv[NOWN];
+#pragma unroll
+  for (int u = 0; u < NOWN; ++u) {
+    const int o = tid + u * kBlock;
     const int lx = H + o % TX, ly = H + o / TX;
-    const long c = a.Lf.at(gx0 + lx, gy0 + ly, 0);
-    const T zv = xs[ly * W + lx];
-    a.xout[c] = zv;
-    if (a.finest) {
-      const double rv = ((const double *)a.b)[c];
-      rz += rv * (double)zv;
-      rr += rv * rv;
-      if (a.zold) rzo += rv * (double)a.zold[c];
+    oi[u] = a.Lf.at(gx0 + lx, gy0 + ly, 0);
+    zv[u] = xs[ly * W + lx];
+    a.xout[oi[u]] = zv[u];
+  }
+  if (EXTRA && a.finest) {
+    double rv[NOWN];
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) rv[u] = ((const double *)a.b)[oi[u]];
+    double ru = 0.0, wu = 0.0;
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) {
+      const int o = tid + u * kBlock;
+      const int lx = H + o % TX, ly = H + o / TX;
+      const int off = ly * W + lx;
+      T Lu;
+      if (fast)
+        Lu = (T(2) * (a.ihx + a.ihy)) * xs[off] -
+             (a.ihx * (xs[off - 1] + xs[off + 1]) + a.ihy * (xs[off - W] + xs[off + W]));
+      else
+        Lu = lx_general<T, W>(xs, off, gx0 + lx, gy0 + ly, nx, ny, a.B, a.ihx, a.ihy);
+      const double wv = (double)Lu;
+      a.w[oi[u]] = wv;
+      ru += rv[u] * (double)zv[u];
+      wu += wv * (double)zv[u];
+      rr += rv[u] * rv[u];
+    }
+    const double s0 = block_sum(ru, sh);
+    const double s1 = block_sum(wu, sh);
+    const double s2 = block_sum(rr, sh);
+    if (linear_tid() == 0) {
+      a.part_rz[blockIdx.x] = s0;
+      a.part_rz[a.np + blockIdx.x] = s1;
+      a.part_rz[2 * a.np + blockIdx.x] = s2;
+    }
+    return;
+  }
+  if (a.finest) {
+    double rv[NOWN];
+    T zo[NOWN];
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) {
+      rv[u] = ((const double *)a.b)[oi[u]];
+      zo[u] = a.zold ? a.zold[oi[u]] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NOWN; ++u) {
+      rz += rv[u] * (double)zv[u];
+      rr += rv[u] * rv[u];
+      rzo += rv[u] * (double)zo[u];
     }
   }
   if (a.finest) {

@@ -68,13 +68,49 @@ __device__ inline double block_allsum(double v, double *sh) {
   return r;
 }
 
-// Sum of np partials, identical in every block and thread.
+// Sum of np partials, identical in every block and thread. Loads are issued
+// four at a time per thread so their latencies overlap.
 __device__ inline double sum_all(const double *part, int np, double *sh) {
   const int t = linear_tid();
   const int nt = blockDim.x * blockDim.y * blockDim.z;
   double s = 0.0;
-  for (int q = t; q < np; q += nt) s += part[q];
+  for (int q0 = 0; q0 < np; q0 += 4 * nt) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * nt + t;
+      v[u] = part[q < np ? q : 0];
+      if (q >= np) v[u] = 0.0;
+    }
+    s += (v[0] + v[1]) + (v[2] + v[3]);
+  }
   return block_allsum(s, sh);
+}
+
+// Sums of three partial arrays of np entries each (one combined pass).
+__device__ inline void sum_all3(const double *p0, const double *p1, const double *p2, int np, double *sh,
+                                double &s0, double &s1, double &s2) {
+  const int t = linear_tid();
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int q0 = 0; q0 < np; q0 += 4 * nt) {
+    double v0[4], v1[4], v2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * nt + t;
+      const int qs = q < np ? q : 0;
+      v0[u] = p0[qs];
+      v1[u] = p1[qs];
+      v2[u] = p2 ? p2[qs] : 0.0;
+      if (q >= np) v0[u] = v1[u] = v2[u] = 0.0;
+    }
+    a0 += (v0[0] + v0[1]) + (v0[2] + v0[3]);
+    a1 += (v1[0] + v1[1]) + (v1[2] + v1[3]);
+    a2 += (v2[0] + v2[1]) + (v2[2] + v2[3]);
+  }
+  s0 = block_allsum(a0, sh);
+  s1 = block_allsum(a1, sh);
+  s2 = block_allsum(a2, sh);
 }
 
 template <int DIM>
@@ -200,9 +236,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_pq(CGArgs a, int np_cc) {
   if (sc->done) return;
   const int k = a.k;
   const double cc = sum_all(a.part_cc, np_cc, sh);
-  const double rz = sum_all(a.part_rz, a.np_rz, sh);
-  const double rr = sum_all(a.part_rz + a.np_rz, a.np_rz, sh);
-  const double rzo = a.flexible ? sum_all(a.part_rz + 2 * a.np_rz, a.np_rz, sh) : 0.0;
+  double rz, rr, rzo;
+  sum_all3(a.part_rz, a.part_rz + a.np_rz, a.flexible ? a.part_rz + 2 * a.np_rz : nullptr, a.np_rz, sh, rz, rr,
+           rzo);
   const bool converged = (cc == 0.0) || (rr <= a.tol2 * cc);
   const bool broken = !isfinite(rr) || !isfinite(rz);
   double beta = 0.0;
@@ -297,6 +333,89 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
   const double s0 = block_sum(rz, sh);
   const double s1 = block_sum(rr, sh);
   const double s2 = zo ? block_sum(rzo, sh) : 0.0;
+  if (linear_tid() == 0) {
+    a.part_rz[blockIdx.x] = s0;
+    a.part_rz[a.np_rz + blockIdx.x] = s1;
+    a.part_rz[2 * a.np_rz + blockIdx.x] = s2;
+  }
+}
+
+// Single-reduction CG (Chronopoulos-Gear) for an unfused finest level.
+// Step k: convergence test on r_{k-1}; beta = g_{k-1}/g_{k-2},
+// alpha = g_{k-1} / (d_{k-1} - beta g_{k-1}/alpha_{k-2}) with g = r.u and
+// d = (A u).u; p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_cgcg_update(CGArgs a, int np_cc, const double *w, const double *s_old,
+                                                        double *s_new) {
+  __shared__ double sh[kBlock / 64];
+  SolverScalars *sc = a.sc;
+  if (sc->done) return;
+  const int k = a.k;
+  const double cc = sum_all(a.part_cc, np_cc, sh);
+  double g, d, rr;
+  sum_all3(a.part_rz, a.part_rz + a.np_rz, a.part_rz + 2 * a.np_rz, a.np_rz, sh, g, d, rr);
+  const bool conv = (cc == 0.0) || (rr <= a.tol2 * cc);
+  double alpha, beta = 0.0;
+  if (k == 1) {
+    alpha = g / d;
+  } else {
+    beta = g / sc->rzh[(k - 2) & 1];
+    alpha = g / (d - beta * g / sc->alh[(k - 2) & 1]);
+  }
+  const bool broken = !isfinite(rr) || !isfinite(alpha) || !isfinite(beta);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rzh[(k - 1) & 1] = g;
+    sc->alh[(k - 1) & 1] = alpha;
+    sc->rr = rr;
+    sc->cc = cc;
+    sc->iters = k - 1;
+    if (conv || broken) {
+      sc->done = 1;
+      sc->zero = (cc == 0.0);
+      sc->nonconv = broken && !conv;
+    }
+  }
+  if (conv || broken) return;
+  const double *u = (const double *)a.z;
+  const bool old = k >= 2;
+  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
+    int i, j, kk;
+    if (!tile_cell(a.L, tile, i, j, kk)) continue;
+    const long c = a.L.at(i, j, kk);
+    const double so = old ? s_old[c] : 0.0;
+    const double pn = u[c] + (old ? beta * a.pnew[c] : 0.0);
+    const double sn = w[c] + beta * so;
+    a.pnew[c] = pn;
+    s_new[c] = sn;
+    a.x[c] += alpha * pn;
+    a.rnew[c] = a.rold[c] - alpha * sn;
+  }
+}
+
+// w = A u (u = M r) and partials of r.u, w.u, r.r for the unfused finest level.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
+  __shared__ double sh[kBlock / 64];
+  if (a.sc->done) return;
+  const double *u = (const double *)a.z;
+  double ru = 0.0, wu = 0.0, rr = 0.0;
+  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
+    int i, j, k;
+    if (!tile_cell(a.L, tile, i, j, k)) continue;
+    const long c = a.L.at(i, j, k);
+    double nbs, dg;
+    op_parts<DIM, double, double>(a.L, a.B, a.ih2, u, i, j, k, c, nbs, dg);
+    const double uc = u[c];
+    const double wv = dg * uc - nbs;
+    const double rv = a.rnew[c];
+    w[c] = wv;
+    ru += rv * uc;
+    wu += wv * uc;
+    rr += rv * rv;
+  }
+  const double s0 = block_sum(ru, sh);
+  const double s1 = block_sum(wu, sh);
+  const double s2 = block_sum(rr, sh);
   if (linear_tid() == 0) {
     a.part_rz[blockIdx.x] = s0;
     a.part_rz[a.np_rz + blockIdx.x] = s1;
@@ -439,6 +558,10 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   ws.p[0] = (double *)cv.take(fbytes);
   ws.p[1] = (double *)cv.take(fbytes);
   ws.q = (double *)cv.take(fbytes);
+  ws.cgcg = !mixed;
+  ws.w = (double *)cv.take(fbytes);
+  ws.s[0] = (double *)cv.take(fbytes);
+  ws.s[1] = (double *)cv.take(fbytes);
   ws.z[0] = cv.take((size_t)fine.total * eb);
   ws.z[1] = mixed ? cv.take((size_t)fine.total * eb) : ws.z[0];
   ws.zpre = cv.take((size_t)fine.total * eb);
@@ -559,10 +682,16 @@ static void launch_nu(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
   else hipLaunchKernelGGL((k_mg_down2d<T, 3>), g, dim3(kBlock), 0, st, a);
 }
 template <typename T>
-static void launch_nu(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st) {
-  if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1>), g, dim3(kBlock), 0, st, a);
-  else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2>), g, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_mg_up2d<T, 3>), g, dim3(kBlock), 0, st, a);
+static void launch_nu(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool extra) {
+  if (extra) {
+    if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 1>), g, dim3(kBlock), 0, st, a);
+    else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 1>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up2d<T, 3, 1>), g, dim3(kBlock), 0, st, a);
+    return;
+  }
+  if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 0>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 0>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_up2d<T, 3, 0>), g, dim3(kBlock), 0, st, a);
 }
 
 template <typename T>
@@ -589,6 +718,18 @@ static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xp
   a.np_pq = kRedBlocks;
   a.sc = ws.sc;
   a.tiles_x = L.n[0] / TX;
+  // single-reduction CG (finest level, FP64)
+  a.cgcg = ws.cgcg && l == 0;
+  a.u = (const T *)ws.z[0];
+  a.w = ws.w;
+  a.s_old = ws.s[k & 1];
+  a.s_new = ws.s[(k + 1) & 1];
+  a.p_io = ws.p[0];
+  a.part_g = ws.part_rz;
+  a.part_cc = ws.part_cc;
+  a.np_g = (ws.lay.n[0] / TX) * (ws.lay.n[1] / TY);
+  a.np_cc = kRedBlocks;
+  a.tol2 = ws.tol2;
   return a;
 }
 
@@ -613,6 +754,7 @@ static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, con
   a.np = (L.n[0] / TX) * (L.n[1] / TY);
   a.sc = ws.sc;
   a.tiles_x = L.n[0] / TX;
+  a.w = ws.w;
   return a;
 }
 
@@ -691,7 +833,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     if (fused_level(ws, l)) {
       const T *zold = (l == 0 && ws.mixed && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
       Up2DArgs<T> a = up_args<T>(ws, l, xin, xc, l == 0 ? (const void *)r : ws.lev[l].b, xout, zold);
-      launch_nu<T>(nu, a, dim3(a.np), st);
+      launch_nu<T>(nu, a, dim3(a.np), st, ws.cgcg && l == 0);
     } else {
       dim3 g = grid_for(L);
       hipLaunchKernelGGL((k_mg_prolong<DIM, T>), g, bb, 0, st, L, Lc, xin, xc, sc);
@@ -714,7 +856,10 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     a.z = z;
     a.zold = (ws.mixed && k >= 1) ? ws.z[(k + 1) & 1] : nullptr;
     a.np_rz = kRedBlocks;
-    hipLaunchKernelGGL((k_cg_rz<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
+    if (ws.cgcg)
+      hipLaunchKernelGGL((k_cgcg_w<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, ws.w);
+    else
+      hipLaunchKernelGGL((k_cg_rz<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
   }
 }
 
@@ -724,8 +869,23 @@ static int np_rz_of(const PoissonWS &ws) {
 
 template <int DIM, typename T>
 static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
-  // pq(k): p_k = z_{k-1} + beta p_{k-1}
   a.k = k;
+  if (ws.cgcg) {
+    // single-reduction CG: the update runs in the finest down kernel, or
+    // in its own kernel when that level is not tiled
+    if (!fused_level(ws, 0)) {
+      a.z = ws.z[0];
+      a.pnew = ws.p[0];
+      a.rold = ws.r[(k - 1) & 1];
+      a.rnew = ws.r[k & 1];
+      a.np_rz = kRedBlocks;
+      hipLaunchKernelGGL((k_cgcg_update<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks,
+                         (const double *)ws.w, (const double *)ws.s[k & 1], ws.s[(k + 1) & 1]);
+    }
+    vcycle<DIM, T>(st, ws, k, a);
+    return;
+  }
+  // pq(k): p_k = z_{k-1} + beta p_{k-1}
   a.z = ws.z[(k - 1) & 1];
   a.pold = ws.p[(k - 1) & 1];
   a.pnew = ws.p[k & 1];
@@ -766,6 +926,7 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   a.np_pq = kRedBlocks;
   a.sc = ws.sc;
   a.tol2 = rtol * rtol;
+  ws.tol2 = a.tol2;
   a.k = 0;
   a.flexible = ws.mixed;
   hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
@@ -841,6 +1002,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
     case 0: {  // finest-level down kernel (fused) or one half-sweep
       if (fused_level(ws, 0)) {
         Down2DArgs<T> d = down_args<T>(ws, 0, 2, ws.r[1], (T *)ws.zpre, ws.x, ws.p[0], ws.q, ws.r[0]);
+        d.tol2 = 0.0;  // never converged: time the full kernel
         launch_nu<T>(ws.nu, d, dim3((ws.lay.n[0] / TX) * (ws.lay.n[1] / TY)), st);
       } else {
         hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, ws.lay, ws.bnd,
@@ -854,7 +1016,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       if (fused_level(ws, 0)) {
         Up2DArgs<T> u = up_args<T>(ws, 0, (const T *)ws.zpre, lev_xout<T>(ws, 1, ws.z[0]), ws.r[0], (T *)ws.z[0],
                                    nullptr);
-        launch_nu<T>(ws.nu, u, dim3(u.np), st);
+        launch_nu<T>(ws.nu, u, dim3(u.np), st, ws.cgcg);
       } else {
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(ws.lev[1].lay), dim3(kBX, kBY), 0, st,
                            ws.lay, ws.lev[1].lay, ws.bnd, ih2_of<T>(ws, 0), (const T *)ws.z[0],
