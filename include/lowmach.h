@@ -109,9 +109,13 @@ typedef struct {
 } lm_ib;
 
 /* Boundary data of one inflow side: per-cell arrays over the side (C order,
- * the side's own direction removed); NULL = zero.                          */
+ * the side's own direction removed); NULL = zero. `wall` (bytes, NULL = none)
+ * flags cells of the side covered by a solid footprint: there Z and H take
+ * zero-gradient ghosts (Eq 3.44) instead of Dirichlet ones (Eq 3.43); give
+ * F = 0 and v = 0 on those cells.                                          */
 typedef struct {
   const double *v[3], *Z, *H, *F;
+  const unsigned char *wall;
 } lm_side_data;
 
 typedef struct {

@@ -152,6 +152,10 @@ def fill_ghosts(g: Grid, Ap, rules):
                 Ap[G] = Ap[_side_index(g, d, src, d)]
             elif kind == "dirichlet":           # Eq 3.43, mirrored ghost
                 Ap[G] = 2.0 * _extend(g, d, rule[1]) - Ap[_side_index(g, d, i1, d)]
+            elif kind == "dirichlet_or_wall":   # Eq 3.43 on inflow cells, Eq 3.44 (zero) on wall cells
+                inner = Ap[_side_index(g, d, i1, d)]
+                wall = _extend(g, d, np.asarray(rule[2], dtype=bool))
+                Ap[G] = np.where(wall, inner, 2.0 * _extend(g, d, rule[1]) - inner)
             elif kind == "neumann":             # Eq 3.44, Phi = outward-normal derivative
                 Ap[G] = Ap[_side_index(g, d, i1, d)] + h * _extend(g, d, rule[1])
             elif kind == "extrap":              # Eq 3.46 / 3.28 on a uniform grid: A=3, B=-3, C=1
@@ -178,7 +182,9 @@ def field_rules(g: Grid, field, comp=None):
     slip wall: normal velocity Dirichlet 0, tangential velocity and scalars
       Neumann 0.
     no-slip wall: velocity Dirichlet 0, scalars Neumann 0.
-    inflow: velocity and scalars Dirichlet with the side's given values.
+    inflow: velocity and scalars Dirichlet with the side's given values;
+      cells flagged 'wall' in the side data (a solid footprint on the
+      side) take Neumann 0 for the scalars instead.
     outflow: velocity and scalars by quadratic extrapolation (Eq 3.46).
     P: quadratic extrapolation at every non-periodic side (Eq 3.27-3.28).
     """
@@ -194,8 +200,11 @@ def field_rules(g: Grid, field, comp=None):
             elif kind == "outflow":
                 pair.append(("extrap",))
             elif kind == "inflow":
+                wall = g.bvalue(d, side, "wall", default=None)
                 if field == "v":
                     pair.append(("dirichlet", g.bvalue(d, side, "v", comp)))
+                elif wall is not None:
+                    pair.append(("dirichlet_or_wall", g.bvalue(d, side, field), wall))
                 else:
                     pair.append(("dirichlet", g.bvalue(d, side, field)))
             elif kind == "noslip":

@@ -91,17 +91,22 @@ class Oracle:
         self.stats = {}
 
     # -- set-up ------------------------------------------------------------
-    def initial_state(self, T, v, Z=None, P=None, F=None):
-        """State at level 0 from temperature and velocity (and Z).
+    def initial_state(self, T, v, Z=None, P=None, F=None, H=None):
+        """State at level 0 from temperature (or excess enthalpy) and
+        velocity (and Z).
 
-        H is obtained by inverting Eq 3.42; T is then re-evaluated from (Z, H)
-        and rho = p0/T (Eq 2.49). Unless given, the face fluxes are the face
-        average of rho v (Eq 3.20 with n = 1), not projected, and P = 0."""
+        H is obtained by inverting Eq 3.42 when T is given; T is then
+        re-evaluated from (Z, H) and rho = p0/T (Eq 2.49). Unless given, the
+        face fluxes are the face average of rho v (Eq 3.20 with n = 1), not
+        projected, and P = 0."""
         g, fp = self.g, self.fp
         Zs = None
         if self.p.reacting:
             Zs = np.zeros(g.shape) if Z is None else np.array(Z, dtype=np.float64)
-        H = enthalpy_from_T(np.asarray(T, dtype=np.float64), Zs if Zs is not None else 0.0, fp)
+        if T is None:
+            H = np.array(H, dtype=np.float64)
+        else:
+            H = enthalpy_from_T(np.asarray(T, dtype=np.float64), Zs if Zs is not None else 0.0, fp)
         T2 = temperature(Zs if Zs is not None else 0.0, H, fp)
         rho = self.p.p0 / T2
         v = [np.array(a, dtype=np.float64) for a in v]
@@ -183,7 +188,15 @@ class Oracle:
         if self.p.reacting:
             Zp = g.pad(st.Z)
             fill_ghosts(g, Zp, field_rules(g, "Z"))
-        Tp = temperature(Zp if Zp is not None else 0.0, Hp, self.fp)
+            # Ghost temperatures (used only for the boundary-face
+            # conductivity) take Z clamped to its realizable range
+            # [0, S+1]; a mirrored ghost of a small interior Z can otherwise
+            # leave the range where the map of Eq 3.42 stays positive.
+            Zc = np.clip(Zp, 0.0, self.p.S + 1.0)
+            g.interior(Zc)[...] = st.Z
+            Tp = temperature(Zc, Hp, self.fp)
+        else:
+            Tp = temperature(0.0, Hp, self.fp)
         return vp, Zp, Hp, Tp
 
     def _scalar_terms(self, phip, kapp, F):

@@ -132,13 +132,16 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.lm_set_fields(self.ctx, 0, C.byref(f),
                                                           C.byref(ibs) if ibs is not None else None, mem))
 
-    def set_side(self, d: int, side: int, v=None, Z=None, H=None, F=None):
+    def set_side(self, d: int, side: int, v=None, Z=None, H=None, F=None, wall=None):
+        """Boundary data of an inflow side; ``wall`` flags the cells of the
+        side under a solid footprint (zero-gradient Z and H there)."""
         m = _Marshal(self.torch, self.device)
         s = _L.lm_side_data()
         if v is not None:
             for q in range(self.ndim):
                 s.v[q] = m.ptr(v[q])
         s.Z, s.H, s.F = m.ptr(Z), m.ptr(H), m.ptr(F)
+        s.wall = m.ptr(wall, np.uint8)
         mem = m.mem if m.mem is not None else _L.LM_HOST
         _check(self.lib, self.ctx, self.lib.lm_set_side(self.ctx, d, side, C.byref(s), mem))
 

@@ -28,7 +28,7 @@ struct lm_ctx {
   double *ib_store[6];
   unsigned char *chi_store;
   Sides sides;
-  double *side_store[3][2][6];
+  double *side_store[3][2][7];  // v[3], Z, H, F, wall flags (bytes)
   double *staging;
   size_t staging_bytes;
   int *dflags;           // [0] bad T, [1] non-finite
@@ -197,12 +197,12 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   memset(&c->sides, 0, sizeof(c->sides));
   for (int d = 0; d < 3; ++d)
     for (int s = 0; s < 2; ++s)
-      for (int q = 0; q < 6; ++q) c->side_store[d][s][q] = nullptr;
+      for (int q = 0; q < 7; ++q) c->side_store[d][s][q] = nullptr;
   for (int d = 0; d < nd; ++d)
     for (int s = 0; s < 2; ++s)
       if (c->grid.bc[d][s] == LM_SIDE_INFLOW) {
         const size_t nside = (size_t)(L.ncells() / L.n[d]);
-        for (int q = 0; q < 6; ++q) c->side_store[d][s][q] = (double *)cv.take(nside * 8);
+        for (int q = 0; q < 7; ++q) c->side_store[d][s][q] = (double *)cv.take(nside * 8);
       }
   long mx = 1;
   for (int d = 0; d < 3; ++d) mx *= (L.n[d] + 1);
@@ -357,6 +357,13 @@ lm_status lm_set_side(lm_ctx *c, int d, int side, const lm_side_data *data, int 
   if ((s = copy_side(c, data->H, st[4], n, mem)) != LM_OK) return s;
   if ((s = copy_side(c, data->F, st[5], n, mem)) != LM_OK) return s;
   SideData &sd = c->sides.s[d][side];
+  sd.wall = nullptr;
+  if (data->wall) {
+    HIPCHK(c, hipMemcpyAsync(st[6], data->wall, n, mem == LM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                             c->st));
+    if (mem == LM_HOST) HIPCHK(c, hipStreamSynchronize(c->st));
+    sd.wall = (const unsigned char *)st[6];
+  }
   for (int q = 0; q < 3; ++q) sd.v[q] = q < c->grid.ndim ? st[q] : nullptr;
   sd.Z = st[3];
   sd.H = st[4];

@@ -24,13 +24,19 @@ __device__ inline long side_index(const Lay &L, int d, int i, int j, int k) {
 
 enum { R_PER = 0, R_DIR = 1, R_NEU = 2, R_EXT = 3 };
 
-// Ghost rule of field f (0..2 velocity components, 3 Z, 4 H) on side (d, s).
-__device__ inline int ghost_rule(const Bnd &B, int d, int s, int f) {
+// Ghost rule of field f (0..2 velocity components, 3 Z, 4 H) on side (d, s)
+// at position (i, j, k) (used for the solid footprint of inflow sides).
+__device__ inline int ghost_rule(const Bnd &B, const Sides &sd, const Lay &L, int d, int s, int f, int i, int j,
+                                 int k) {
   const int kind = B.kind[d][s];
   switch (kind) {
     case LM_SIDE_PERIODIC: return R_PER;
     case LM_SIDE_OUTFLOW: return R_EXT;
-    case LM_SIDE_INFLOW: return R_DIR;
+    case LM_SIDE_INFLOW: {
+      const unsigned char *w = sd.s[d][s].wall;
+      if (f >= 3 && w && w[side_index(L, d, i, j, k)]) return R_NEU;
+      return R_DIR;
+    }
     case LM_SIDE_NOSLIP: return f < 3 ? R_DIR : R_NEU;
     default: return (f == d) ? R_DIR : R_NEU;  // slip wall
   }
@@ -67,7 +73,7 @@ __device__ double ghost_value(const Lay &L, const Bnd &B, const Sides &sd, const
       if (q >= 0 && q < n) continue;
       const int s = q < 0 ? 0 : 1;
       const int i1 = s == 0 ? 0 : n - 1, i2 = s == 0 ? 1 : n - 2, i3 = s == 0 ? 2 : n - 3;
-      switch (ghost_rule(B, d, s, f)) {
+      switch (ghost_rule(B, sd, L, d, s, f, pos[t][0], pos[t][1], pos[t][2])) {
         case R_PER: pos[t][d] = s == 0 ? n - 1 : 0; break;
         case R_DIR:
           cst += 2.0 * w[t] * side_value(sd, L, d, s, f, pos[t][0], pos[t][1], pos[t][2]);
@@ -177,7 +183,10 @@ __global__ void __launch_bounds__(kBlock) k_ghosts_general(Lay L, Bnd B, Phys P,
   if (P.reacting) Z = ghost_value<DIM>(L, B, sd, g.Z, 3, i, j, k);
   g.H[dst] = H;
   if (g.Z) g.Z[dst] = Z;
-  const double T = temperature(P, Z, H);
+  // ghost temperature (boundary-face conductivity only) with Z clamped to
+  // its realizable range [0, S+1]
+  const double Zc = P.reacting ? fmin(fmax(Z, 0.0), P.S + 1.0) : 0.0;
+  const double T = temperature(P, Zc, H);
   g.T[dst] = T;
   g.kap[dst] = pow(T, P.sigma);
 }

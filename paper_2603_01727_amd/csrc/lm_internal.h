@@ -66,6 +66,7 @@ struct IB {
 // Inflow side data (compact, per side cell), device pointers or NULL.
 struct SideData {
   const double *v[3], *Z, *H, *F;
+  const unsigned char *wall;  // solid footprint cells of an inflow side
 };
 
 struct Sides {

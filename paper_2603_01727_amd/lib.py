@@ -45,7 +45,8 @@ class lm_ib(C.Structure):
 
 
 class lm_side_data(C.Structure):
-    _fields_ = [("v", C.c_void_p * 3), ("Z", C.c_void_p), ("H", C.c_void_p), ("F", C.c_void_p)]
+    _fields_ = [("v", C.c_void_p * 3), ("Z", C.c_void_p), ("H", C.c_void_p), ("F", C.c_void_p),
+                ("wall", C.c_void_p)]
 
 
 class lm_step_stats(C.Structure):

@@ -9,6 +9,7 @@ from workloads import Case
 
 PARAM_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O",
               "Da_ib", "p0", "dt", "cfl")
+SIDE_INDEX = {"slip", "noslip", "inflow", "outflow"}
 
 
 def _params(case: Case, over):
@@ -21,7 +22,7 @@ def oracle_for(case: Case, **over):
     nd = case.ndim
     g = Grid(case.n[:nd], case.L[:nd], bc=case.bc, bnd=case.bnd)
     o = Oracle(g, Params(**_params(case, over)), ib=case.ib)
-    st = o.initial_state(case.T, case.v, Z=case.Z)
+    st = o.initial_state(case.T, case.v, Z=case.Z, H=case.H)
     return o, st
 
 
@@ -30,7 +31,10 @@ def gpu_for(case: Case, rtol=1e-13, precision="fp64", **over):
     nd = case.ndim
     s = Solver(case.n[:nd], case.L[:nd], bc=case.bc, precision=precision, poisson_rtol=rtol,
                poisson_maxit=400, with_ib=case.ib is not None, **_params(case, over))
-    s.set(T=case.T, v=case.v, Z=case.Z, ib=case.ib)
+    for (d, side), data in (case.bnd or {}).items():
+        s.set_side(d, side, v=data.get("v"), Z=data.get("Z"), H=data.get("H"), F=data.get("F"),
+                   wall=data.get("wall"))
+    s.set(T=case.T, H=case.H if case.T is None else None, v=case.v, Z=case.Z, ib=case.ib)
     return s
 
 

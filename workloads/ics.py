@@ -19,6 +19,11 @@ from typing import Optional
 import numpy as np
 
 
+# Q/(S+1) for S = 1/0.055 - 1, eps = 0.5, tol = 1e-3: 6 / (1 + F~(Z_max)) with
+# Z_max = 1 + ln S/(2k), so that the peak regularised temperature is 7.
+QS_C3 = 6.09951783620629
+
+
 @dataclasses.dataclass
 class Case:
     """A workload: grid, physical parameters and initial fields.
@@ -40,6 +45,7 @@ class Case:
     ib: Optional[dict] = None
     bnd: Optional[dict] = None
     nsteps: int = 1
+    H: Optional[np.ndarray] = None
 
     @property
     def shape(self):
@@ -237,10 +243,18 @@ def c3_case(nx=768, ny=1536, seed=3, W=32, wall=4, wall_h=64, inj=4,
     W cells; an injector layer ``inj`` cells thick spans the slot floor.
     Slot inflow U(x) = Umax (1 - (2 (x - xc)/W)^2) (1 + noise * xi_col),
     xi_col ~ N(0,1) per slot column (one draw of W values), fixed in time.
-    Flame-sheet parameters: Z_st = 0.055 so S = 1/Z_st - 1, fuel at Z = S+1;
-    Re=200, Pr=Sc=0.7 (Le_F = Le_O = 1), eps = 0.5, tol = 1e-3.
-    Returns the geometry arrays; temperatures are left to the solver, which
-    derives T from Z and H. ``T`` holds None-equivalent ones."""
+    Flame sheet: Z_st = 0.055 so S = 1/Z_st - 1 with fuel at Z = S + 1;
+    eps = 0.5, tol = 1e-3; Q/(S+1) = QS_C3 places the peak of the
+    regularised temperature at 7 (density ratio 7) with T = 1 in the
+    oxidiser; H = H_inf = (S+1)/Q + 1 everywhere. Re = 200, Pr = Sc = 0.7
+    (Le_F = Le_O = 1). Sides: slip walls in x, inflow at the bottom (coflow
+    outside the burner footprint, wall under it), outflow at the top.
+    Immersed boundary: mask of walls and injector, Da_ib = dx^2; targets
+    v = 0 in the walls, v = (0, U) with Z = S + 1 in the injector,
+    H = H_inf, Z held at its initial profile in the solid; mass source
+    S_m = U / (inj dx) in the injector (fuel density 1 at T = 1), so the
+    injected rate is sum(U) dx per unit depth. Below the slot the bottom
+    side carries Z = S + 1 so the injector's Dirichlet ghost is fuel."""
     rng = np.random.default_rng(seed)
     h = 1.0 / W
     L = (nx * h, ny * h)
@@ -260,6 +274,8 @@ def c3_case(nx=768, ny=1536, seed=3, W=32, wall=4, wall_h=64, inj=4,
     sl = slice(s0, s1)
     U[sl] = Umax * (1.0 - (2.0 * (xcent[sl] - xmid) / (W * h)) ** 2) * (1.0 + noise * xi)
     S = 1.0 / 0.055 - 1.0
+    qs = QS_C3
+    Hinf = 1.0 / qs + 1.0
     zfuel = S + 1.0
     v1 = np.zeros(shp)
     v2 = np.full(shp, coflow)
@@ -267,32 +283,35 @@ def c3_case(nx=768, ny=1536, seed=3, W=32, wall=4, wall_h=64, inj=4,
     v2[0:wall_h, w0r:w1r] = 0.0
     v2[0:wall_h, s0:s1] = U[sl][None, :]
     yc = (np.arange(ny) + 0.5) * h
-    # Z: fuel in the slot, smoothed by tanh over 2 cells at the slot exit
-    Z = np.zeros(shp)
-    prof = 0.5 * (1.0 - np.tanh((yc - wall_h * h) / (2 * h)))
-    Z[:, s0:s1] = zfuel * prof[:, None]
-    # immersed boundary targets
+    # resolved fuel column: smooth top-hat across the slot edges (tanh over
+    # one cell, so the burner walls are oxidiser-cold a few cells out) and
+    # at the slot exit (tanh over two cells); the solid keeps this profile
+    sx = 0.5 * (np.tanh((xcent - s0 * h) / h) - np.tanh((xcent - s1 * h) / h))
+    sy = 0.5 * (1.0 - np.tanh((yc - wall_h * h) / (2.0 * h)))
+    Z = zfuel * sy[:, None] * sx[None, :]
     vib1 = np.zeros(shp)
     vib2 = np.zeros(shp)
     vib2[0:inj, s0:s1] = U[sl][None, :]
-    zib = np.zeros(shp)
-    zib[0:inj, s0:s1] = zfuel
-    # mass source: injector flux U ramps across the inj-cell layer
+    zib = Z.copy()
+    hib = np.full(shp, Hinf)
     Sm = np.zeros(shp)
-    Sm[0:inj, s0:s1] = (1.0 * U[sl] / (inj * h))[None, :]
-    # bottom boundary: coflow inflow outside the burner footprint, wall under it
+    Sm[0:inj, s0:s1] = (U[sl] / (inj * h))[None, :]
     vb2 = np.full(nx, coflow)
     vb2[w0l:w1r] = 0.0
-    bnd = dict(bottom_v=[np.zeros(nx), vb2], bottom_Z=np.zeros(nx),
-               bottom_F=vb2.copy())
-    params = dict(Re=200.0, Pr=0.7, Le_F=1.0, Le_O=1.0, reacting=1, S=S,
+    zb = Z[0, :].copy()                         # the injector floor holds fuel
+    foot = np.zeros(nx, dtype=np.uint8)
+    foot[w0l:w1r] = 1                           # burner footprint: wall cells of the side
+    bnd = {(1, 0): dict(v=[np.zeros(nx), vb2], Z=zb, H=np.full(nx, Hinf), F=vb2.copy(), wall=foot)}
+    params = dict(Re=200.0, Pr=0.7, Le_F=1.0, Le_O=1.0, reacting=1, S=S, qs=qs,
                   eps=0.5, tol=1e-3, Da_ib=h * h, p0=1.0, cfl=0.2,
                   poisson_rtol=1e-10)
-    ib = dict(chi=chi, v_ib=[vib1, vib2], Z_ib=zib, Sm=Sm, Sm_rate_closed=
-              float(np.sum(U[sl]) * h))
-    return Case("c3_slot_flame_768x1536", 2, (nx, ny, 1), L + (1.0,),
+    ib = dict(chi=chi, v_ib=[vib1, vib2], Z_ib=zib, H_ib=hib, Sm=Sm)
+    case = Case(f"c3_slot_flame_{nx}x{ny}", 2, (nx, ny, 1), L + (1.0,),
                 (("slip", "slip"), ("inflow", "outflow")), params,
                 None, [v1, v2], Z=Z, ib=ib, bnd=bnd, nsteps=500)
+    case.H = np.full(shp, Hinf)
+    case.injected_rate = float(np.sum(U) * h)
+    return case
 
 
 def make_case(name, **kw):
