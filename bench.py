@@ -10,8 +10,8 @@ mixed-precision preconditioner. Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -20,26 +20,50 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Dominant kernel: the finest-level multigrid down kernel, which also carries
+# the single-reduction CG update. Algorithmic bytes per cell (FP64): reads
+# r, w, s, u, p, x (6 x 8 B), writes p, s, x, r and the pre-smoothed
+# correction (5 x 8 B), and the coarse right-hand side (8 B per 4 cells).
+DOMINANT = "k_mg_down2d (finest level, fused CG update + 2 red-black sweeps + restriction)"
+BYTES_PER_CELL = 6 * 8 + 5 * 8 + 8 / 4
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mg_down2d_finest_c2_1024_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_01727_amd", "csrc", f)
+                  for f in ("lm_mg_kernels.h", "lm_solver.hip")]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
 
 
-def time_solver(case, precision, steps, warmup):
-    import torch
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def make_solver(case, precision):
     from paper_2603_01727_amd import Solver
     p = case.params
     s = Solver(case.n[:2], case.L[:2], Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"], precision=precision,
                poisson_rtol=p["poisson_rtol"], poisson_maxit=200, device="cuda:0")
     s.set(T=case.T, v=case.v)
+    return s
+
+
+def time_solver(case, precision, steps, warmup):
+    import torch
+    s = make_solver(case, precision)
     if warmup:
         s.step(warmup)
     torch.cuda.synchronize()
@@ -54,30 +78,31 @@ def time_solver(case, precision, steps, warmup):
                 poisson_iters_per_solve=iters, dt=s.dt, solver=s)
 
 
-def kernel_roofline(s, n):
-    """Times the dominant kernel class (the level-0 multigrid smoother
-    half-sweep) in isolation with HIP events on the solver's stream and
-    prices its algorithmic bytes against the HBM peak."""
-    from paper_2603_01727_amd import lib as L
+def kernel_roofline(s, ncells):
+    """Average duration of the dominant kernel, timed with HIP events on the
+    solver's stream (lm_bench_kernel), priced at its algorithmic bytes."""
     import ctypes as C
     ms = C.c_double()
-    reps = 200
-    st = s.lib.lm_bench_kernel(s.ctx, 0, reps, C.byref(ms))
+    st = s.lib.lm_bench_kernel(s.ctx, 0, 200, C.byref(ms))
     if st != 0:
         return None
     per_launch_s = ms.value * 1e-3
-    # one half-sweep reads x at every cell (neighbours of the updated colour)
-    # and b at half the cells, and writes x at half the cells: 8 + 4 + 4 B/cell
-    bytes_per_cell = 16.0
-    achieved = bytes_per_cell * n * n / per_launch_s / 1e9
+    achieved = BYTES_PER_CELL * ncells / per_launch_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("kernel_source_hash") == kernel_source_hash():
+            traffic = t.get("bytes_per_launch")
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_mg_smooth (level 0, one colour)", avg_us=round(per_launch_s * 1e6, 3),
-                bytes_per_cell=bytes_per_cell)
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=DOMINANT,
+                avg_us=round(per_launch_s * 1e6, 3), bytes_per_cell=BYTES_PER_CELL,
+                algorithmic_bytes_per_launch=BYTES_PER_CELL * ncells)
 
 
-def cpu_baseline(case, nsteps=3):
-    """The FP64 oracle on the host: one warm-up step, then nsteps timed."""
+def cpu_baseline(case, budget_s=12.0):
+    """The FP64 oracle on the host: one warm-up step, then steps until about
+    budget_s seconds have passed (at least 2)."""
     from oracle import Grid, Oracle, Params
     p = case.params
     g = Grid(case.n[:2], case.L[:2])
@@ -85,24 +110,38 @@ def cpu_baseline(case, nsteps=3):
     st = o.initial_state(case.T, case.v)
     st = o.step(st)
     t0 = time.perf_counter()
-    for _ in range(nsteps):
+    n = 0
+    while n < 2 or time.perf_counter() - t0 < budget_s:
         st = o.step(st)
+        n += 1
     sec = time.perf_counter() - t0
-    return dict(value=case.ncells * nsteps / sec, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"{nsteps} steps of the {case.n[0]}x{case.n[1]} workload after one warm-up step "
+    return dict(value=case.ncells * n / sec, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"{n} steps of the {case.n[0]}x{case.n[1]} workload after one warm-up step "
                        f"(NumPy FP64, FFT Poisson, single thread), {sec:.1f} s")
+
+
+def copy_calibration():
+    """Device-to-device copy of 512 MiB, twice (reference for the HBM
+    byte counters: 512 MiB read + 512 MiB written per copy)."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import torch
     from workloads import c2_case
     case = c2_case(n=a.n)
+    if a.copy_calibration:
+        copy_calibration()
     r64 = time_solver(case, "fp64", a.steps, a.warmup)
-    roof = kernel_roofline(r64["solver"], a.n)
+    roof = kernel_roofline(r64["solver"], case.ncells)
     mixed = None
     if not a.no_mixed:
         rmx = time_solver(case, "mixed", a.steps, a.warmup)
