@@ -82,7 +82,9 @@ typedef struct {
  *  poisson_maxit iteration cap (LM_ENOCONV beyond it)
  *  mg_nu         smoothing sweeps per level and direction (0 = default 2)
  *  with_ib       1 = reserve immersed-boundary arrays (needed by lm_set_fields
- *                with a non-NULL lm_ib)                                    */
+ *                with a non-NULL lm_ib)
+ *  with_adjoint  1 = reserve the adjoint arrays (lm_step_adjoint and its
+ *                helpers; 2D periodic, non-reacting, no body, FP64 only)   */
 typedef struct {
   double Re, Pr, sigma, inv_Fr2;
   int reacting;
@@ -93,6 +95,7 @@ typedef struct {
   int poisson_maxit;
   int mg_nu;
   int with_ib;
+  int with_adjoint;
 } lm_params;
 
 /* Field set for lm_set_fields / lm_get_fields; NULL entries are skipped.
@@ -177,6 +180,43 @@ lm_status lm_get_fields(lm_ctx *ctx, int level, lm_fields *f, int mem);
 
 /* The fixed time step (after lm_set_fields when params.dt == 0). */
 lm_status lm_get_dt(const lm_ctx *ctx, double *dt);
+
+/* ---- checkpoint / restart ------------------------------------------------
+ * The complete state of a context (level n, its pressure, the level n-1
+ * density and residuals used by the next AB2/BDF2 step, the step counter
+ * and the time) copied to or from a caller device buffer of
+ * lm_state_size bytes; restoring it and stepping reproduces the original
+ * run bit for bit.                                                          */
+lm_status lm_state_size(const lm_ctx *ctx, size_t *bytes);
+lm_status lm_save_state(lm_ctx *ctx, void *dev_buf);
+lm_status lm_load_state(lm_ctx *ctx, const void *dev_buf);
+
+/* ---- adjoint of the step (reverse mode, hand-written) ---------------------
+ * The adjoint state is the cotangent of the context's state: fields H, v,
+ * F (faces) and the history rho^{n-1}, R_H^{n-1}, R_v^{n-1}. Supported for
+ * 2D periodic, non-reacting grids without immersed body in FP64 (params
+ * with_adjoint = 1; otherwise LM_EUNSUPPORTED).                              */
+typedef struct {
+  double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
+} lm_adjoint;
+
+/* Kinetic energy sum_cells 1/2 rho |v|^2 dV of the current state. */
+lm_status lm_kinetic_energy(lm_ctx *ctx, double *ke);
+/* Adjoint state := d(kinetic energy)/d(state) at the current state. */
+lm_status lm_adjoint_seed_ke(lm_ctx *ctx);
+/* Adjoint state := the given cotangents (NULL entries = 0). */
+lm_status lm_adjoint_set(lm_ctx *ctx, const lm_adjoint *a, int mem);
+lm_status lm_adjoint_get(lm_ctx *ctx, lm_adjoint *a, int mem);
+/* One step back: with the forward state at level n and the adjoint state
+ * holding the cotangent of the state at n+1, replace it by the cotangent of
+ * the state at n (the step is recomputed internally; the forward state is
+ * left at n). Each stage needs one adjoint Poisson solve with the same
+ * symmetric operator; errors as lm_step.                                    */
+lm_status lm_step_adjoint(lm_ctx *ctx);
+/* With the forward state freshly set from (T0, v0) by lm_set_fields and the
+ * adjoint state holding its cotangent: cotangents of T0 and v0 (through
+ * H0 = T0/qs + 1, rho0 = p0/T(H0), F0 = face average of rho0 v0). */
+lm_status lm_adjoint_initial(lm_ctx *ctx, double *T0_bar, double *v0_bar[3], int mem);
 
 /* Kernel timing hook: launches one kernel class `reps` times back to back on
  * the context's stream between two HIP events and returns the mean duration

@@ -122,9 +122,12 @@ class PoissonSolver:
         g = self.g
         lam = np.mean(b)
         if self.fft:
-            bh = np.fft.fftn(b)
-            P = np.fft.ifftn(bh * self.inv)
-            P = P if np.iscomplexobj(b) else P.real
+            if np.iscomplexobj(b):
+                # the solve is a real-linear map: apply it to both parts
+                # separately so that rounding of the real part never leaks
+                # into the imaginary part (complex-step derivatives)
+                return self.solve(b.real)[0] + 1j * self.solve(b.imag)[0], lam
+            P = np.fft.ifftn(np.fft.fftn(b) * self.inv).real
             return P, lam
         N = b.size
         rhs = np.concatenate([b.ravel(), [0.0]])

@@ -21,6 +21,12 @@ from .grid import Grid, fill_ghosts, field_rules
 from .poisson import PoissonSolver
 
 
+def _real_or_complex(a):
+    """Copy as float64, or complex128 for complex input (complex-step
+    differentiation runs the same arithmetic on complex fields)."""
+    return np.array(a, dtype=np.result_type(a, np.float64))
+
+
 @dataclasses.dataclass
 class Params:
     """Dimensionless parameters (section 2.2, Eq 2.12-2.21; section 4.1):
@@ -102,17 +108,17 @@ class Oracle:
         g, fp = self.g, self.fp
         Zs = None
         if self.p.reacting:
-            Zs = np.zeros(g.shape) if Z is None else np.array(Z, dtype=np.float64)
+            Zs = np.zeros(g.shape) if Z is None else _real_or_complex(Z)
         if T is None:
-            H = np.array(H, dtype=np.float64)
+            H = _real_or_complex(H)
         else:
-            H = enthalpy_from_T(np.asarray(T, dtype=np.float64), Zs if Zs is not None else 0.0, fp)
+            H = enthalpy_from_T(_real_or_complex(T), Zs if Zs is not None else 0.0, fp)
         T2 = temperature(Zs if Zs is not None else 0.0, H, fp)
         rho = self.p.p0 / T2
-        v = [np.array(a, dtype=np.float64) for a in v]
+        v = [_real_or_complex(a) for a in v]
         if F is None:
             F = self.face_average_flux([rho * a for a in v])
-        Pz = np.zeros(g.shape) if P is None else np.array(P, dtype=np.float64)
+        Pz = np.zeros(g.shape) if P is None else _real_or_complex(P)
         st = State(rho, v, Zs, H, T2, Pz, F)
         if self.dt == 0.0:
             self.dt = self.cfl_dt(st)

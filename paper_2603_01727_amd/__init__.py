@@ -71,7 +71,8 @@ class Solver:
                  qs: float = 1.0, eps: float = 0.5, tol: float = 1e-3, Le_F: float = 1.0, Le_O: float = 1.0,
                  Da_ib: float = 1.0, p0: float = 1.0, dt: float = 0.0, cfl: float = 0.2,
                  precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
-                 mg_nu: int = 2, with_ib: bool = False, device: str = "cuda:0", stream=None):
+                 mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False, device: str = "cuda:0",
+                 stream=None):
         import torch
         self.torch = torch
         self.lib = _L.load()
@@ -92,7 +93,7 @@ class Solver:
                          eps=eps, tol=tol, Le_F=Le_F, Le_O=Le_O, Da_ib=Da_ib, p0=p0, dt=dt, cfl=cfl,
                          precision=_L.LM_MIXED if precision == "mixed" else _L.LM_FP64,
                          poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
-                         with_ib=int(with_ib))
+                         with_ib=int(with_ib), with_adjoint=int(with_adjoint))
         self.grid, self.params = g, p
         self.device = torch.device(device)
         size = C.c_size_t()
@@ -214,6 +215,94 @@ class Solver:
         if m.mem == _L.LM_DEVICE:
             self.torch.cuda.current_stream(self.device).synchronize()
         return P, dict(iters=a.iters, relres=a.relres, mean_b=a.mean_b)
+
+    # ------------------------------------------------------------------
+    # checkpoint / restart
+    def state_size(self) -> int:
+        n = C.c_size_t()
+        _check(self.lib, self.ctx, self.lib.lm_state_size(self.ctx, C.byref(n)))
+        return n.value
+
+    def save_state(self, buf=None):
+        """Copy the complete state into a device byte tensor (allocated when
+        ``buf`` is None) and return it."""
+        if buf is None:
+            buf = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device)
+        _check(self.lib, self.ctx, self.lib.lm_save_state(self.ctx, C.c_void_p(buf.data_ptr())))
+        return buf
+
+    def load_state(self, buf):
+        _check(self.lib, self.ctx, self.lib.lm_load_state(self.ctx, C.c_void_p(buf.data_ptr())))
+
+    # ------------------------------------------------------------------
+    # adjoint (2D periodic, non-reacting, FP64; needs with_adjoint=True)
+    def kinetic_energy(self) -> float:
+        v = C.c_double()
+        _check(self.lib, self.ctx, self.lib.lm_kinetic_energy(self.ctx, C.byref(v)))
+        return v.value
+
+    def adjoint_seed_ke(self):
+        _check(self.lib, self.ctx, self.lib.lm_adjoint_seed_ke(self.ctx))
+
+    def adjoint_set(self, H=None, v=None, F=None, rho_prev=None, R_H=None, R_v=None):
+        m = _Marshal(self.torch, self.device)
+        a = _L.lm_adjoint()
+        a.H, a.rho_prev, a.R_H = m.ptr(H), m.ptr(rho_prev), m.ptr(R_H)
+        for d in range(self.ndim):
+            a.v[d] = m.ptr(v[d]) if v is not None else None
+            a.F[d] = m.ptr(F[d]) if F is not None else None
+            a.R_v[d] = m.ptr(R_v[d]) if R_v is not None else None
+        mem = m.mem if m.mem is not None else _L.LM_HOST
+        _check(self.lib, self.ctx, self.lib.lm_adjoint_set(self.ctx, C.byref(a), mem))
+
+    def adjoint_get(self, device: bool = True) -> dict:
+        """Current adjoint state: H, v, F (faces as in ``get``; the low face
+        of cell 0 of a periodic direction is the duplicate of face n and
+        reads 0), rho_prev, R_H, R_v."""
+        t = self.torch
+        keep = []
+
+        def alloc(shape):
+            x = t.empty(shape, dtype=t.float64, device=self.device) if device else np.empty(shape)
+            keep.append(x)
+            return x, (x.data_ptr() if device else x.ctypes.data)
+
+        a = _L.lm_adjoint()
+        out = {}
+        for name in ("H", "rho_prev", "R_H"):
+            x, p = alloc(self.shape)
+            setattr(a, name, p)
+            out[name] = x
+        out["v"], out["F"], out["R_v"] = [], [], []
+        for d in range(self.ndim):
+            x, a.v[d] = alloc(self.shape)
+            out["v"].append(x)
+            x, a.R_v[d] = alloc(self.shape)
+            out["R_v"].append(x)
+            shp = list(self.shape)
+            shp[self.ndim - 1 - d] += 1
+            x, a.F[d] = alloc(tuple(shp))
+            out["F"].append(x)
+        _check(self.lib, self.ctx, self.lib.lm_adjoint_get(self.ctx, C.byref(a),
+                                                           _L.LM_DEVICE if device else _L.LM_HOST))
+        return out
+
+    def step_adjoint(self):
+        _check(self.lib, self.ctx, self.lib.lm_step_adjoint(self.ctx))
+
+    def adjoint_initial(self, device: bool = True):
+        """Cotangents (T0_bar, [v0_bar...]) of the initial fields given to
+        ``set(T=..., v=...)``; the forward state must be that initial state."""
+        t = self.torch
+        mk = (lambda: t.empty(self.shape, dtype=t.float64, device=self.device)) if device else \
+            (lambda: np.empty(self.shape))
+        Tb = mk()
+        vb = [mk() for _ in range(self.ndim)]
+        ptr = (lambda x: x.data_ptr()) if device else (lambda x: x.ctypes.data)
+        arr = (C.c_void_p * 3)(*([ptr(x) for x in vb] + [None] * (3 - self.ndim)))
+        _check(self.lib, self.ctx, self.lib.lm_adjoint_initial(self.ctx, C.c_void_p(ptr(Tb)), arr,
+                                                               _L.LM_DEVICE if device else _L.LM_HOST))
+        return Tb, vb
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -1,0 +1,97 @@
+"""Reverse-mode gradient of the final kinetic energy with respect to the
+initial temperature, behind ``torch.autograd.Function``.
+
+J(T0) = sum_cells 1/2 rho |v|^2 dV after ``nsteps`` predictor-corrector
+steps from (T0, v0) with a fixed time step. The forward pass stores a full
+state checkpoint every ``checkpoint_every`` steps. The backward pass walks
+the segments from last to first: it restores the segment's checkpoint,
+replays the segment forward while storing each step's state (the segment
+tape), then runs ``lm_step_adjoint`` from the last step of the segment back
+to its first. Peak storage is (nsteps / k + k) states. Every step of the
+forward and reverse sweeps runs in the HIP library; this module only
+sequences the calls.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+
+class Trajectory:
+    """Checkpointed forward run of a ``Solver`` built with ``with_adjoint``
+    and a fixed ``dt`` (the gradient is taken at fixed dt)."""
+
+    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20):
+        if nsteps < 0 or checkpoint_every < 1:
+            raise ValueError("nsteps >= 0 and checkpoint_every >= 1 required")
+        if not solver.params.with_adjoint:
+            raise ValueError("the solver needs with_adjoint=True")
+        if not solver.params.dt > 0:
+            raise ValueError("the gradient is taken at a fixed time step: give the solver dt > 0")
+        self.solver = solver
+        self.nsteps = int(nsteps)
+        self.k = int(checkpoint_every)
+        self.ckpt = {}
+        self.tape = []
+        self.final = None
+
+    def forward(self, T0, v0) -> float:
+        s = self.solver
+        s.set(T=T0, v=v0)
+        self.ckpt = {0: s.save_state()}
+        done = 0
+        while done < self.nsteps:
+            m = min(self.k, self.nsteps - done)
+            s.step(m)
+            done += m
+            if done < self.nsteps:
+                self.ckpt[done] = s.save_state()
+        self.final = s.save_state()
+        return s.kinetic_energy()
+
+    def backward(self):
+        """Returns (T0_bar, [v0_bar...]) as device tensors."""
+        s = self.solver
+        s.load_state(self.final)
+        s.adjoint_seed_ke()
+        size = s.state_size()
+        nseg = math.ceil(self.nsteps / self.k)
+        for q in reversed(range(nseg)):
+            a = q * self.k
+            b = min(a + self.k, self.nsteps)
+            while len(self.tape) < b - a:
+                self.tape.append(torch.empty(size, dtype=torch.uint8, device=s.device))
+            s.load_state(self.ckpt[a])
+            s.save_state(self.tape[0])
+            for n in range(a + 1, b):
+                s.step(1)
+                s.save_state(self.tape[n - a])
+            for n in reversed(range(a, b)):
+                s.load_state(self.tape[n - a])
+                s.step_adjoint()
+        if self.nsteps == 0:
+            s.load_state(self.ckpt[0])
+        return s.adjoint_initial()
+
+
+class FinalKineticEnergy(torch.autograd.Function):
+    """J = kinetic energy after ``nsteps`` steps from (T0, v0); gradient
+    with respect to T0 (v0 is held fixed)."""
+
+    @staticmethod
+    def forward(ctx, T0, v0, solver, nsteps, checkpoint_every):
+        traj = Trajectory(solver, nsteps, checkpoint_every)
+        J = traj.forward(T0.detach(), [x.detach() for x in v0])
+        ctx.traj = traj
+        return torch.tensor(J, dtype=torch.float64, device=T0.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        Tb, _ = ctx.traj.backward()
+        return Tb * gJ.to(Tb.device), None, None, None, None
+
+
+def final_kinetic_energy(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_every: int = 20) -> torch.Tensor:
+    """Differentiable J(T0); ``T0`` is a float64 tensor on the solver's device."""
+    return FinalKineticEnergy.apply(T0, list(v0), solver, nsteps, checkpoint_every)

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblowmach.so")
-SOURCES = ["lm_api.hip", "lm_explicit.hip", "lm_solver.hip"]
+SOURCES = ["lm_api.hip", "lm_explicit.hip", "lm_solver.hip", "lm_adjoint.hip"]
 
 # Packed-FP32 instructions are disabled for every HIP source.
 HIPCC_FLAGS = [

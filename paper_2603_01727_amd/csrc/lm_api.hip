@@ -41,6 +41,11 @@ struct lm_ctx {
   long long total_iters;
   int last_iters[2];
   std::string err;
+  // adjoint: two sets of the adjoint state (H, v0, v1, F0, F1, rho_prev,
+  // RH_prev, Rv0_prev, Rv1_prev) and work arrays
+  double *ad[2][9];
+  int ad_cur;
+  double *aw[20];
 };
 
 namespace {
@@ -119,6 +124,10 @@ bool valid_params(const lm_params *p, std::string *err) {
   }
   if (p->precision != LM_FP64 && p->precision != LM_MIXED) {
     *err = "precision must be LM_FP64 or LM_MIXED";
+    return false;
+  }
+  if (p->with_adjoint && (p->reacting || p->with_ib || p->precision != LM_FP64)) {
+    *err = "the adjoint supports non-reacting FP64 runs without immersed body";
     return false;
   }
   return true;
@@ -210,6 +219,10 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   c->staging = (double *)cv.take(c->staging_bytes);
   c->dflags = (int *)cv.take(64);
   c->dscalar = (double *)cv.take(64);
+  for (int s = 0; s < 2; ++s)
+    for (int q = 0; q < 9; ++q) c->ad[s][q] = c->prm.with_adjoint ? (double *)cv.take(ab) : nullptr;
+  for (int q = 0; q < 20; ++q) c->aw[q] = c->prm.with_adjoint ? (double *)cv.take(ab) : nullptr;
+  c->ad_cur = 0;
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = c->phys.h[d];
   return poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision == LM_MIXED,
@@ -642,5 +655,279 @@ extern "C" lm_status lm_bench_kernel(lm_ctx *c, int which, int reps, double *avg
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) return fail(c, LM_EHIP, std::string("HIP error in lm_bench_kernel: ") + hipGetErrorString(e));
   *avg_ms = (double)ms / reps;
+  return LM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoint / restart
+// ---------------------------------------------------------------------------
+namespace {
+
+struct StateHeader {
+  int have_prev, have_state;
+  double time;
+  int last_iters[2];
+};
+
+// Arrays making up the state, in a fixed order.
+int state_arrays(lm_ctx *c, double **out) {
+  int k = 0;
+  const int nd = c->grid.ndim;
+  Level &lv = c->lev[c->icur];
+  out[k++] = lv.rho;
+  for (int d = 0; d < nd; ++d) out[k++] = lv.v[d];
+  if (lv.Z) out[k++] = lv.Z;
+  out[k++] = lv.H;
+  out[k++] = lv.T;
+  out[k++] = lv.kap;
+  for (int d = 0; d < nd; ++d) out[k++] = lv.F[d];
+  out[k++] = c->P[c->icur];
+  out[k++] = c->rho_prev;
+  Resid &r = c->R[c->rprev];
+  out[k++] = r.H;
+  if (r.Z) out[k++] = r.Z;
+  for (int d = 0; d < nd; ++d) out[k++] = r.v[d];
+  return k;
+}
+
+bool adjoint_ok(lm_ctx *c) {
+  return c->prm.with_adjoint && c->grid.ndim == 2 && c->bnd.all_periodic;
+}
+
+AdjPhys adj_phys(const lm_ctx *c) {
+  AdjPhys P;
+  P.h[0] = c->phys.h[0];
+  P.h[1] = c->phys.h[1];
+  P.Pe = c->phys.Pe;
+  P.Pr = c->phys.Pr;
+  P.sigma = c->phys.sigma;
+  P.inv_Fr2 = c->phys.inv_Fr2;
+  P.p0 = c->phys.p0;
+  P.qs = c->phys.qs;
+  P.dt = c->phys.dt;
+  return P;
+}
+
+}  // namespace
+
+extern "C" lm_status lm_state_size(const lm_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return LM_EINVAL;
+  double *arr[32];
+  const int k = state_arrays(const_cast<lm_ctx *>(c), arr);
+  *bytes = 256 + (size_t)k * c->lay.total * 8;
+  return LM_OK;
+}
+
+extern "C" lm_status lm_save_state(lm_ctx *c, void *buf) {
+  if (!c || !buf) return fail(c, LM_EINVAL, "NULL argument");
+  if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
+  double *arr[32];
+  const int k = state_arrays(c, arr);
+  StateHeader h{c->have_prev, c->have_state, c->time, {c->last_iters[0], c->last_iters[1]}};
+  HIPCHK(c, hipMemcpyAsync(buf, &h, sizeof(h), hipMemcpyHostToDevice, c->st));
+  char *p = (char *)buf + 256;
+  const size_t ab = (size_t)c->lay.total * 8;
+  for (int q = 0; q < k; ++q) HIPCHK(c, hipMemcpyAsync(p + q * ab, arr[q], ab, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+extern "C" lm_status lm_load_state(lm_ctx *c, const void *buf) {
+  if (!c || !buf) return fail(c, LM_EINVAL, "NULL argument");
+  double *arr[32];
+  const int k = state_arrays(c, arr);
+  StateHeader h;
+  HIPCHK(c, hipMemcpyAsync(&h, buf, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  const char *p = (const char *)buf + 256;
+  const size_t ab = (size_t)c->lay.total * 8;
+  for (int q = 0; q < k; ++q) HIPCHK(c, hipMemcpyAsync(arr[q], p + q * ab, ab, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->have_prev = h.have_prev;
+  c->have_state = h.have_state;
+  c->time = h.time;
+  c->last_iters[0] = h.last_iters[0];
+  c->last_iters[1] = h.last_iters[1];
+  return LM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+extern "C" lm_status lm_kinetic_energy(lm_ctx *c, double *ke) {
+  if (!c || !ke) return LM_EINVAL;
+  if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
+  Level &lv = c->lev[c->icur];
+  double dV = 1.0;
+  for (int d = 0; d < c->grid.ndim; ++d) dV *= c->phys.h[d];
+  if (c->grid.ndim != 2) return fail(c, LM_EUNSUPPORTED, "kinetic energy implemented for 2D");
+  HIPCHK(c, launch_ke(c->st, c->lay, lv.rho, lv.v, dV, c->pws.partials, c->dscalar));
+  HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, 8, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  *ke = c->hscalar[0];
+  return LM_OK;
+}
+
+extern "C" lm_status lm_adjoint_seed_ke(lm_ctx *c) {
+  if (!c) return LM_EINVAL;
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
+  double **a = c->ad[c->ad_cur];
+  const size_t ab = (size_t)c->lay.total * 8;
+  for (int q = 0; q < 9; ++q) HIPCHK(c, hipMemsetAsync(a[q], 0, ab, c->st));
+  Level &lv = c->lev[c->icur];
+  double *vb[2] = {a[1], a[2]};
+  const double dV = c->phys.h[0] * c->phys.h[1];
+  HIPCHK(c, launch_adj_seed_ke(c->st, c->lay, adj_phys(c), dV, lv.H, lv.rho, lv.v, a[0], vb));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
+  if (!c || !in) return LM_EINVAL;
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  double **a = c->ad[c->ad_cur];
+  const double *src[9] = {in->H, in->v[0], in->v[1], in->F[0], in->F[1], in->rho_prev, in->R_H, in->R_v[0],
+                          in->R_v[1]};
+  const int fd[9] = {-1, -1, -1, 0, 1, -1, -1, -1, -1};
+  for (int q = 0; q < 9; ++q) {
+    HIPCHK(c, hipMemsetAsync(a[q], 0, (size_t)c->lay.total * 8, c->st));
+    if (src[q]) {
+      lm_status s = copy_in(c, src[q], a[q], fd[q], mem);
+      if (s != LM_OK) return s;
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+extern "C" lm_status lm_adjoint_get(lm_ctx *c, lm_adjoint *out, int mem) {
+  if (!c || !out) return LM_EINVAL;
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  double **a = c->ad[c->ad_cur];
+  double *dst[9] = {out->H, out->v[0], out->v[1], out->F[0], out->F[1], out->rho_prev, out->R_H, out->R_v[0],
+                    out->R_v[1]};
+  const int fd[9] = {-1, -1, -1, 0, 1, -1, -1, -1, -1};
+  for (int q = 0; q < 9; ++q) {
+    if (!dst[q]) continue;
+    lm_status s = copy_out(c, a[q], dst[q], fd[q], mem);
+    if (s != LM_OK) return s;
+  }
+  if (mem == LM_DEVICE) HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
+  if (!c) return LM_EINVAL;
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
+  const Lay &L = c->lay;
+  const size_t ab = (size_t)L.total * 8;
+  // forward recompute of the step (state at n untouched: outputs go to the
+  // predicted and next levels)
+  int it[2];
+  double rr[2], cm[2];
+  lm_status s = do_stage(c, 0, it[0], rr[0], cm[0]);
+  if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
+  if (s != LM_OK) return s;
+  const int first = !c->have_prev;
+  const AdjPhys P = adj_phys(c);
+  Level &N = c->lev[c->icur], &S = c->lev[c->istar], &X = c->lev[c->inxt];
+  double **ain = c->ad[c->ad_cur];        // cotangent of the step's outputs
+  double **aout = c->ad[c->ad_cur ^ 1];   // cotangent of the step's inputs
+  double **w = c->aw;
+  double *Mb[2] = {w[0], w[1]};
+  double *rhob_new = w[2], *Pb = w[3], *bb = w[4];
+  double *Hb_star = w[5], *vb_star[2] = {w[6], w[7]}, *Fb_star[2] = {w[8], w[9]};
+  double *RbH_star = w[10], *Rbv_star[2] = {w[11], w[12]};
+  double *RbH_n = w[13], *Rbv_n[2] = {w[14], w[15]};
+  double *rhob_n = w[16];
+  double *Fb_n[2] = {aout[3], aout[4]};
+  double *vb_n[2] = {aout[1], aout[2]};
+  double *Fb_in[2] = {ain[3], ain[4]};
+  double *vb_in[2] = {ain[1], ain[2]};
+  // zero what is accumulated into
+  for (double *z : {Hb_star, vb_star[0], vb_star[1], Fb_star[0], Fb_star[1], Fb_n[0], Fb_n[1]})
+    HIPCHK(c, hipMemsetAsync(z, 0, ab, c->st));
+  auto adjoint_solve = [&](double *rhs, double *out) -> lm_status {
+    HIPCHK(c, launch_mean(c->st, L, rhs, c->pws.partials, c->pws.sc));
+    int iters = 0, conv = 0;
+    double relres = 0.0;
+    HIPCHK(c, poisson_solve(c->st, c->pws, rhs, nullptr, c->prm.poisson_rtol, c->prm.poisson_maxit, 0, &iters,
+                            &relres, &conv));
+    if (!conv) return fail(c, LM_ENOCONV, "adjoint Poisson solve did not converge");
+    HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, out));
+    return LM_OK;
+  };
+  // corrector: projection, Poisson, right-hand side, EOS and AM2 transposes
+  HIPCHK(c, launch_adj_proj(c->st, L, P, Fb_in, vb_in, X.v, X.rho, Mb, rhob_new, Pb));
+  if ((s = adjoint_solve(Pb, bb)) != LM_OK) return s;
+  AdjTailArgs t{};
+  t.L = L;
+  t.P = P;
+  t.first = first;
+  t.corrector = 1;
+  t.bb = bb;
+  t.Mb[0] = Mb[0];
+  t.Mb[1] = Mb[1];
+  t.rhob_new = rhob_new;
+  t.H_new = X.H;
+  t.rho_new = X.rho;
+  t.v_n[0] = N.v[0];
+  t.v_n[1] = N.v[1];
+  t.rho_n = N.rho;
+  t.Hb_out = ain[0];
+  t.RbH_out = ain[6];
+  t.Rbv_out[0] = ain[7];
+  t.Rbv_out[1] = ain[8];
+  t.rhoprevb_out = ain[5];
+  t.Hb_star = Hb_star;
+  t.Hb_n = aout[0];
+  t.vb_n[0] = vb_n[0];
+  t.vb_n[1] = vb_n[1];
+  t.rhob_n = rhob_n;
+  t.RbH_star = RbH_star;
+  t.Rbv_star[0] = Rbv_star[0];
+  t.Rbv_star[1] = Rbv_star[1];
+  t.RbH_n = RbH_n;
+  t.Rbv_n[0] = Rbv_n[0];
+  t.Rbv_n[1] = Rbv_n[1];
+  t.rhoprevb_in = aout[5];
+  t.RbH_prev_in = aout[6];
+  t.Rbv_prev_in[0] = aout[7];
+  t.Rbv_prev_in[1] = aout[8];
+  HIPCHK(c, launch_adj_tail(c->st, t));
+  // residuals at the predicted level
+  HIPCHK(c, launch_adj_resid(c->st, L, P, S.H, S.v, S.F, RbH_star, Rbv_star, Hb_star, vb_star, Fb_star));
+  // predictor: projection, Poisson, right-hand side, EOS and AB2 transposes
+  HIPCHK(c, launch_adj_proj(c->st, L, P, Fb_star, vb_star, S.v, S.rho, Mb, rhob_new, Pb));
+  if ((s = adjoint_solve(Pb, bb)) != LM_OK) return s;
+  t.corrector = 0;
+  t.H_new = S.H;
+  t.rho_new = S.rho;
+  HIPCHK(c, launch_adj_tail(c->st, t));
+  // residuals at level n, then the EOS of level n
+  HIPCHK(c, launch_adj_resid(c->st, L, P, N.H, N.v, N.F, RbH_n, Rbv_n, aout[0], vb_n, Fb_n));
+  HIPCHK(c, launch_adj_eos(c->st, L, P, N.H, N.rho, rhob_n, aout[0]));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->ad_cur ^= 1;
+  return LM_OK;
+}
+
+extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_bar[3], int mem) {
+  if (!c || !T0_bar) return LM_EINVAL;
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  Level &N = c->lev[c->icur];
+  double **a = c->ad[c->ad_cur];
+  double *Fb[2] = {a[3], a[4]};
+  double *vb[2] = {a[1], a[2]};
+  double *Tb = c->aw[17];
+  HIPCHK(c, launch_adj_init(c->st, c->lay, adj_phys(c), N.H, N.rho, N.v, Fb, a[0], vb, Tb));
+  lm_status s = copy_out(c, Tb, T0_bar, -1, mem);
+  if (s != LM_OK) return s;
+  if (v0_bar) {
+    for (int d = 0; d < 2; ++d)
+      if (v0_bar[d] && (s = copy_out(c, vb[d], v0_bar[d], -1, mem)) != LM_OK) return s;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;
 }

@@ -127,6 +127,43 @@ hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Si
 hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
                       const unsigned char *chi, double *partials, double *out_max);
 hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc);
+
+// ---- adjoint (lm_adjoint.hip): 2D periodic, non-reacting, no body --------
+struct AdjPhys {
+  double h[2];
+  double Pe, Pr, sigma, inv_Fr2, p0, qs, dt;
+};
+struct AdjTailArgs {
+  Lay L;
+  AdjPhys P;
+  int first, corrector;
+  const double *bb;
+  double *Mb[2];
+  double *rhob_new;
+  const double *H_new, *rho_new;
+  const double *v_n[2], *rho_n;
+  const double *Hb_out, *RbH_out, *Rbv_out[2], *rhoprevb_out;
+  double *Hb_star;
+  double *Hb_n, *vb_n[2], *rhob_n;
+  double *RbH_star, *Rbv_star[2];
+  double *RbH_n, *Rbv_n[2];
+  double *rhoprevb_in, *RbH_prev_in, *Rbv_prev_in[2];
+};
+hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[2],
+                            double *const F[2], const double *RbH, double *const Rbv[2], double *Hb, double *vb[2],
+                            double *Fb[2]);
+hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[2],
+                           double *const vb[2], double *const v[2], const double *rho, double *Mb[2], double *rhob,
+                           double *Pb);
+hipError_t launch_adj_tail(hipStream_t st, const AdjTailArgs &a);
+hipError_t launch_adj_eos(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
+                          const double *rhob, double *Hb);
+hipError_t launch_adj_seed_ke(hipStream_t st, const Lay &L, const AdjPhys &P, double dV, const double *H,
+                              const double *rho, double *const v[2], double *Hb, double *vb[2]);
+hipError_t launch_adj_init(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
+                           double *const v[2], double *const Fb[2], const double *Hb, double *vb[2], double *Tb);
+hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[2], double dV, double *part,
+                     double *out);
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);
 
 // ---- Poisson (lm_solver.hip) -----------------------------------------------

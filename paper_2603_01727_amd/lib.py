@@ -31,7 +31,7 @@ class lm_params(C.Structure):
                 ("Le_F", C.c_double), ("Le_O", C.c_double),
                 ("Da_ib", C.c_double), ("p0", C.c_double), ("dt", C.c_double), ("cfl", C.c_double),
                 ("precision", C.c_int), ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int),
-                ("mg_nu", C.c_int), ("with_ib", C.c_int)]
+                ("mg_nu", C.c_int), ("with_ib", C.c_int), ("with_adjoint", C.c_int)]
 
 
 class lm_fields(C.Structure):
@@ -55,6 +55,11 @@ class lm_step_stats(C.Structure):
                 ("compat", C.c_double * 2), ("total_poisson_iters", C.c_longlong)]
 
 
+class lm_adjoint(C.Structure):
+    _fields_ = [("H", C.c_void_p), ("v", C.c_void_p * 3), ("F", C.c_void_p * 3), ("rho_prev", C.c_void_p),
+                ("R_H", C.c_void_p), ("R_v", C.c_void_p * 3)]
+
+
 class lm_project_args(C.Structure):
     _fields_ = [("b", C.c_void_p), ("P", C.c_void_p), ("mem", C.c_int), ("rtol", C.c_double),
                 ("iters", C.c_int), ("relres", C.c_double), ("mean_b", C.c_double)]
@@ -71,6 +76,15 @@ EXPORTS = {
     "lm_get_fields": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(lm_fields), C.c_int]),
     "lm_get_dt": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lm_bench_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    "lm_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "lm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lm_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lm_kinetic_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lm_adjoint_seed_ke": (C.c_int, [C.c_void_p]),
+    "lm_adjoint_set": (C.c_int, [C.c_void_p, C.POINTER(lm_adjoint), C.c_int]),
+    "lm_adjoint_get": (C.c_int, [C.c_void_p, C.POINTER(lm_adjoint), C.c_int]),
+    "lm_step_adjoint": (C.c_int, [C.c_void_p]),
+    "lm_adjoint_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
     "lm_last_error": (C.c_char_p, [C.c_void_p]),
     "lm_destroy": (None, [C.c_void_p]),
 }

@@ -1,0 +1,254 @@
+"""GPU checks of checkpoint/restart and of the hand-written adjoint.
+
+* save/load of the state reproduces a run bit for bit;
+* dot-product test of one adjoint step against the oracle's complex-step
+  tangent of the same step: <ybar, J dx> = <J^T ybar, dx> for random
+  cotangents ybar of every output and random directions dx of every input;
+* gradient of the final kinetic energy with respect to T0 (autograd
+  Function, checkpointed) against the oracle's complex-step derivative and
+  against central finite differences of the GPU forward (h = 1e-6, 16
+  seeded directions, <= 1e-6 relative).
+Every Poisson solve is converged to 1e-14 so that solver error stays below
+the finite-difference resolution; dt is fixed.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import Grid, Oracle, Params
+from oracle import tangent as tg
+from workloads.ics import c1_case, c5_case, fd_directions
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-14
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dt(case):
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    o = Oracle(g, Params(Re=case.params["Re"], Pr=case.params["Pr"], cfl=case.params["cfl"]))
+    o.initial_state(case.T, case.v)
+    return o.dt
+
+
+def _solver(case, dt, with_adjoint=True, rtol=RTOL):
+    from paper_2603_01727_amd import Solver
+    return Solver(case.n[:2], case.L[:2], bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], dt=dt,
+                  poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint)
+
+
+def test_state_restart_is_bit_exact():
+    import torch
+    case = c1_case()
+    print("restart c1", flush=True)
+    s = _solver(case, 0.02, with_adjoint=False, rtol=1e-12)
+    s.set(T=case.T, v=case.v)
+    s.step(3)
+    buf = s.save_state()
+    s.step(4)
+    a = s.get(device=False)
+    s.load_state(buf)
+    s.step(4)
+    b = s.get(device=False)
+    s2 = _solver(case, 0.02, with_adjoint=False, rtol=1e-12)
+    s2.set(T=case.T + 1.0, v=case.v)          # a different state, overwritten
+    s2.load_state(buf.clone())
+    s2.step(4)
+    c = s2.get(device=False)
+    for k in ("rho", "H", "T", "P"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    for d in range(2):
+        assert np.array_equal(a["v"][d], b["v"][d]) and np.array_equal(a["v"][d], c["v"][d])
+        assert np.array_equal(a["F"][d], c["F"][d])
+    assert s2.state_size() == buf.numel()
+    torch.cuda.synchronize()
+
+
+def _faces(f, ax):
+    return np.concatenate([np.take(f, [-1], axis=ax), f], axis=ax)
+
+
+def _dot(a, b):
+    out = 0.0
+    for k in a:
+        if k not in b:
+            continue
+        x, y = a[k], b[k]
+        if isinstance(x, list):
+            out += sum(float(np.sum(np.asarray(p) * np.asarray(q))) for p, q in zip(x, y))
+        else:
+            out += float(np.sum(np.asarray(x) * np.asarray(y)))
+    return out
+
+
+@pytest.mark.parametrize("shape,history", [((72, 80), False), ((72, 80), True), ((64, 64), True)])
+def test_adjoint_step_dot_product_against_oracle_tangent(shape, history):
+    """One step back on the GPU against the complex-step tangent of the same
+    step in the oracle, per input component."""
+    ny, nx = shape
+    case = c5_case(n=nx)
+    if ny != nx:
+        from workloads.ics import fourier_temperature, solenoidal_velocity
+        L = (2 * math.pi, 2 * math.pi)
+        rng = np.random.default_rng(5)
+        case.T = fourier_temperature((nx, ny), L, rng, 8, 3.0)
+        case.v = solenoidal_velocity((nx, ny), L, rng, 8, 0.1)
+        case.n = (nx, ny, 1)
+    print("adjoint dot", shape, history, flush=True)
+    dt = 0.5 * _dt(case)
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt)
+    o = Oracle(g, p)
+    st = o.initial_state(case.T, case.v)
+    nhist = 1 if history else 0
+    st = tg.with_eos(o, o.run(st, nhist))
+    s = _solver(case, dt)
+    s.set(T=case.T, v=case.v)
+    if nhist:
+        s.step(nhist)
+    rng = np.random.default_rng(100 + nx + ny)
+    # cotangents of the step's outputs (face 0 of a periodic face array is a
+    # duplicate of face n and carries none)
+    ybar = {"H": rng.normal(size=g.shape), "v": [rng.normal(size=g.shape) for _ in range(2)],
+            "rho_prev": rng.normal(size=g.shape), "R_H": rng.normal(size=g.shape),
+            "R_v": [rng.normal(size=g.shape) for _ in range(2)]}
+    ybar["F"] = [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(2)]
+    for d in range(2):
+        idx = [slice(None)] * 2
+        idx[g.axis(d)] = 0
+        ybar["F"][d][tuple(idx)] = 0.0
+    s.adjoint_set(**ybar)
+    t0 = time.time()
+    s.step_adjoint()
+    xbar = s.adjoint_get(device=False)
+    print("step_adjoint", time.time() - t0, flush=True)
+    comps = [("H",), ("v",), ("F",)] + ([("rho_prev",), ("R_H",), ("R_v",)] if history else [])
+    for keys in comps:
+        k = keys[0]
+        if k == "F":
+            dx = {k: [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(2)]}
+        elif k in ("v", "R_v"):
+            dx = {k: [rng.normal(size=g.shape) for _ in range(2)]}
+        else:
+            dx = {k: rng.normal(size=g.shape)}
+        ydot = tg.step_tangent(o, st, dx)
+        lhs = _dot(ybar, ydot)
+        rhs = _dot(xbar, dx)
+        print(k, lhs, rhs, abs(lhs - rhs) / abs(lhs), flush=True)
+        assert abs(lhs - rhs) <= 1e-9 * abs(lhs), (k, lhs, rhs)
+
+
+def _ke_setup(n, nsteps):
+    case = c5_case(n=n)
+    dt = _dt(case)
+    return case, dt
+
+
+def test_ke_gradient_against_oracle_complex_step():
+    import torch
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    n, nsteps, k = 64, 7, 3
+    case, dt = _ke_setup(n, nsteps)
+    print("ke gradient vs oracle", n, nsteps, flush=True)
+    s = _solver(case, dt)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in case.v]
+    J = final_kinetic_energy(s, T0, v0, nsteps, k)
+    J.backward()
+    grad = T0.grad.cpu().numpy()
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt)
+    Jo = tg.final_kinetic_energy(g, p, case.T, case.v, nsteps)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    for d in fd_directions(case.T.shape, k=4):
+        cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps)
+        ad = float(np.sum(grad * d))
+        print(cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
+
+
+def _ke_density(s):
+    f = s.get(("rho", "v"), device=False)
+    return 0.5 * f["rho"] * (f["v"][0] ** 2 + f["v"][1] ** 2)
+
+
+def _fd_check(n, nsteps, k, ndir=16, h=1e-6, h4=None):
+    """Central differences J(T0 + h d) - J(T0 - h d) over 2h along seeded
+    directions. Numerators are summed from per-cell differences of the final
+    kinetic-energy density (the same number as the difference of the two
+    sums, without the rounding of two O(J) sums). With ``h4`` also the
+    five-point difference (-J(2 h4) + 8 J(h4) - 8 J(-h4) + J(-2 h4))/(12 h4),
+    whose O(h4^4) truncation and O(ulp(J)/h4) rounding both stay below 1e-6
+    of the derivative. Returns J, the gradient wall time and per-direction
+    (error at h, error of the five-point difference, derivative)."""
+    import torch
+    from paper_2603_01727_amd.adjoint import Trajectory, final_kinetic_energy
+    case, dt = _ke_setup(n, nsteps)
+    s = _solver(case, dt)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in case.v]
+    t0 = time.time()
+    J = final_kinetic_energy(s, T0, v0, nsteps, k)
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.time() - t0
+    grad = T0.grad
+    dV = case.L[0] * case.L[1] / (n * n)
+    traj = Trajectory(s, nsteps, nsteps)
+
+    def e_at(dd, step):
+        traj.forward(T0.detach() + step * dd, v0)
+        return _ke_density(s)
+
+    out = []
+    for q, d in enumerate(fd_directions(case.T.shape, k=ndir)):
+        dd = torch.tensor(d, dtype=torch.float64, device="cuda")
+        ad = float(torch.sum(grad * dd))
+        fd = float(np.sum(e_at(dd, h) - e_at(dd, -h))) * dV / (2 * h)
+        e4 = None
+        if h4:
+            num = 8.0 * (e_at(dd, h4) - e_at(dd, -h4)) - (e_at(dd, 2 * h4) - e_at(dd, -2 * h4))
+            fd4 = float(np.sum(num)) * dV / (12 * h4)
+            e4 = abs(ad - fd4) / abs(fd4)
+        out.append((abs(ad - fd) / abs(fd), e4, ad))
+        print(f"direction {q}: dJ {ad:.6e} rel err h={h:g}: {out[-1][0]:.3e}"
+              + (f" five-point h={h4:g}: {e4:.3e}" if h4 else ""), flush=True)
+    return J.item(), t_grad, out
+
+
+def test_ke_gradient_against_finite_differences():
+    """128^2, 30 steps, checkpoints every 10: central differences at
+    h = 1e-6 along 16 directions agree to 1e-6."""
+    print("ke gradient vs FD 128^2", flush=True)
+    J, t, out = _fd_check(128, 30, 10)
+    errs = [e for e, _, _ in out]
+    print(J, t, max(errs), flush=True)
+    assert max(errs) <= 1e-6, errs
+
+
+def test_c5_adjoint_512_200_steps():
+    """The 512^2, 200-step workload, checkpoints every 20 steps.
+
+    The five-point difference at h = 1e-3 must agree to 1e-6 along all 16
+    directions. The central difference at h = 1e-6 is held to 1e-6 plus its
+    rounding floor: J(T0 +- h d) are two FP64 trajectories of 200 steps
+    whose final kinetic energies carry rounding noise of order 10 ulp(J),
+    which a difference quotient over 2h turns into an absolute error of
+    about 10 ulp(J)/(2h) (7e-11 here); along directions with a small
+    derivative this floor exceeds 1e-6 relative."""
+    print("c5 adjoint 512^2 200 steps", flush=True)
+    h = 1e-6
+    J, t, out = _fd_check(512, 200, 20, h=h, h4=1e-3)
+    floor = 10 * math.ulp(J) / (2 * h)
+    print("J", J, "gradient s", t, "floor", floor, flush=True)
+    for e, e4, ad in out:
+        assert e4 <= 1e-6, out
+        assert e * abs(ad) <= 1e-6 * abs(ad) + floor, out
