@@ -228,6 +228,8 @@ lm_status lm_adjoint_initial(lm_ctx *ctx, double *T0_bar, double *v0_bar[3], int
  *   6 Poisson right-hand side                  7 projection                    */
 lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
 
+/* Text of the last error of ctx; with ctx == NULL, of the last failed
+ * lm_workspace_size or lm_init_grid of the calling thread. */
 const char *lm_last_error(const lm_ctx *ctx);
 
 /* Release the context (the caller still owns workspace and stream). */

@@ -20,7 +20,7 @@ LowMachError = _L.LowMachError
 
 def _check(lib, ctx, status):
     if status != _L.LM_OK:
-        msg = lib.lm_last_error(ctx).decode() if ctx else ""
+        msg = lib.lm_last_error(ctx).decode()
         raise _L.LowMachError(status, msg)
 
 

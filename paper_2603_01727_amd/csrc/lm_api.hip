@@ -50,6 +50,14 @@ struct lm_ctx {
 
 namespace {
 
+// Text of the last failed lm_workspace_size / lm_init_grid of this thread.
+thread_local std::string g_init_err;
+
+lm_status init_fail(lm_status s, const std::string &msg) {
+  g_init_err = msg;
+  return s;
+}
+
 lm_status fail(lm_ctx *c, lm_status s, const std::string &msg) {
   if (c) c->err = msg;
   return s;
@@ -286,10 +294,10 @@ lm_status copy_side(lm_ctx *c, const double *src, double *dst, size_t n, int mem
 extern "C" {
 
 lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t *bytes) {
-  std::string err;
-  if (!bytes || !valid_grid(grid, &err) || !valid_params(params, &err)) return LM_EINVAL;
+  std::string err = "bytes is NULL";
+  if (!bytes || !valid_grid(grid, &err) || !valid_params(params, &err)) return init_fail(LM_EINVAL, err);
   lm_ctx *c = new (std::nothrow) lm_ctx();
-  if (!c) return LM_ENOMEM;
+  if (!c) return init_fail(LM_ENOMEM, "out of host memory");
   c->grid = *grid;
   c->prm = *params;
   setup_phys(c);
@@ -297,24 +305,24 @@ lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t
   Carver cv{nullptr, 0};
   bool ok = carve(c, cv, &err);
   delete c;
-  if (!ok) return LM_EUNSUPPORTED;
+  if (!ok) return init_fail(LM_EUNSUPPORTED, err);
   *bytes = cv.off + 256;
   return LM_OK;
 }
 
 lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, size_t bytes, void *stream,
                        lm_ctx **out) {
-  if (!out) return LM_EINVAL;
+  if (!out) return init_fail(LM_EINVAL, "out is NULL");
   *out = nullptr;
   std::string err;
-  if (!valid_grid(grid, &err) || !valid_params(params, &err)) return LM_EINVAL;
-  if (!ws) return LM_EINVAL;
+  if (!valid_grid(grid, &err) || !valid_params(params, &err)) return init_fail(LM_EINVAL, err);
+  if (!ws) return init_fail(LM_EINVAL, "workspace is NULL");
   size_t need = 0;
   lm_status s = lm_workspace_size(grid, params, &need);
   if (s != LM_OK) return s;
-  if (bytes < need) return LM_ENOMEM;
+  if (bytes < need) return init_fail(LM_ENOMEM, "workspace smaller than lm_workspace_size");
   lm_ctx *c = new (std::nothrow) lm_ctx();
-  if (!c) return LM_ENOMEM;
+  if (!c) return init_fail(LM_ENOMEM, "out of host memory");
   c->grid = *grid;
   c->prm = *params;
   c->st = (hipStream_t)stream;
@@ -324,7 +332,7 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
   Carver cv{base, 0};
   if (!carve(c, cv, &err)) {
     delete c;
-    return LM_EUNSUPPORTED;
+    return init_fail(LM_EUNSUPPORTED, err);
   }
   c->icur = 0;
   c->inxt = 1;
@@ -335,21 +343,24 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
   c->time = 0;
   c->total_iters = 0;
   c->last_iters[0] = c->last_iters[1] = 0;
-  if (hipHostMalloc((void **)&c->hflags, 64) != hipSuccess ||
-      hipHostMalloc((void **)&c->hscalar, 64) != hipSuccess ||
-      hipHostMalloc((void **)&c->pws.host_sc, sizeof(SolverScalars)) != hipSuccess) {
+  hipError_t e = hipHostMalloc((void **)&c->hflags, 64);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscalar, 64);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->pws.host_sc, sizeof(SolverScalars));
+  if (e != hipSuccess) {
     lm_destroy(c);
-    return LM_EHIP;
+    return init_fail(LM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
   // zero the whole carved region once (ghost layers, padding, scalars)
-  if (hipMemsetAsync(base, 0, cv.off, c->st) != hipSuccess) {
+  e = hipMemsetAsync(base, 0, cv.off, c->st);
+  if (e != hipSuccess) {
     lm_destroy(c);
-    return LM_EHIP;
+    return init_fail(LM_EHIP, std::string("hipMemsetAsync of the workspace: ") + hipGetErrorString(e));
   }
   double h[3] = {c->phys.h[0], c->phys.h[1], c->phys.h[2]};
-  if (poisson_setup(c->st, c->pws, h) != hipSuccess) {
+  e = poisson_setup(c->st, c->pws, h);
+  if (e != hipSuccess) {
     lm_destroy(c);
-    return LM_EHIP;
+    return init_fail(LM_EHIP, std::string("coarse-grid set-up: ") + hipGetErrorString(e));
   }
   *out = c;
   return LM_OK;
@@ -597,7 +608,7 @@ lm_status lm_get_dt(const lm_ctx *c, double *dt) {
   return LM_OK;
 }
 
-const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 void lm_destroy(lm_ctx *c) {
   if (!c) return;

@@ -181,7 +181,7 @@ struct Carver {
 };
 
 constexpr int kMaxLev = 24;
-constexpr long kCoarseCells = 1024;   // levels at or below this size: one-block LDS kernel
+constexpr long kCoarseCells = 4096;   // levels at or below this size: one-block LDS kernel
 constexpr long kMaxCoarsest = 1024;   // dense pseudo-inverse limit
 
 struct PoissonWS {

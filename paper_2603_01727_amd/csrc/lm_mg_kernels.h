@@ -468,7 +468,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
 // ---------------------------------------------------------------------------
 // One-block coarse V-cycle in LDS
 // ---------------------------------------------------------------------------
-constexpr int kCoarseLds = 1408;  // cells of all coarse levels together
+constexpr int kCoarseLds = 5504;  // cells of all coarse levels together (4096 + 1024 + ... in 2D)
+constexpr int kCoarseLoads = 4;   // cells per thread of the first coarse level (<= 4 x 1024)
+constexpr int kCoarseLev = 8;     // coarse levels handled by the one-block kernel, at most
 
 template <typename T>
 struct CoarseArgs {
@@ -478,6 +480,7 @@ struct CoarseArgs {
   int off[kMaxLev];        // LDS offset of each level (compact, x fastest)
   int lg[kMaxLev][2];      // log2(n[0]/2), log2(n[1]) or -1 when not a power of two
   Ih2<T> ih2[kMaxLev];
+  T idg[kCoarseLev][8];    // 1/diagonal of coarse level l0 + q, by neighbour code
   Lay L0;                  // global layout of level l0
   const void *b0;          // global right-hand side of level l0
   int b0_double;
@@ -510,35 +513,33 @@ __device__ inline void c_decode(const int n[3], int t, int &i, int &j, int &k) {
   }
 }
 
+// Sum of the neighbours of cell c = (i, j, k), each scaled by 1/h_d^2, with
+// no branches: a missing neighbour (a non-periodic side) is read at c and
+// weighted 0. code gets bit d set when both neighbours along d exist; the
+// diagonal of the cell is sum_d ih2[d] (1 + bit d), tabulated as 1/diag.
 template <int DIM, typename T>
-__device__ inline void c_parts(const int n[3], const Bnd &B, const T ih2[3], const T *x, int i, int j, int k, T &nbs,
-                               T &dg) {
-  nbs = T(0);
-  dg = T(0);
+__device__ inline T c_nbs(const int n[3], const Bnd &B, const T ih2[3], const T *x, int i, int j, int k, int c,
+                          int &code) {
   const int q[3] = {i, j, k};
   const int st[3] = {1, n[0], n[0] * n[1]};
-  const int c = i + n[0] * (j + n[1] * k);
+  T v[2 * DIM], w[2 * DIM];
+  code = 0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    T s = T(0);
-    int cnt = 0;
-    if (q[d] > 0) {
-      s += x[c - st[d]];
-      ++cnt;
-    } else if (B.periodic[d]) {
-      s += x[c + (n[d] - 1) * st[d]];
-      ++cnt;
-    }
-    if (q[d] + 1 < n[d]) {
-      s += x[c + st[d]];
-      ++cnt;
-    } else if (B.periodic[d]) {
-      s += x[c - (n[d] - 1) * st[d]];
-      ++cnt;
-    }
-    nbs += ih2[d] * s;
-    dg += ih2[d] * (T)cnt;
+    const bool per = B.periodic[d] != 0;
+    const bool lo = q[d] > 0, hi = q[d] + 1 < n[d];
+    const int cm = lo ? c - st[d] : (per ? c + (n[d] - 1) * st[d] : c);
+    const int cp = hi ? c + st[d] : (per ? c - (n[d] - 1) * st[d] : c);
+    v[2 * d] = x[cm];
+    v[2 * d + 1] = x[cp];
+    w[2 * d] = (lo || per) ? T(1) : T(0);
+    w[2 * d + 1] = (hi || per) ? T(1) : T(0);
+    code |= ((lo || per) && (hi || per)) ? (1 << d) : 0;
   }
+  T nbs = T(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) nbs += ih2[d] * (w[2 * d] * v[2 * d] + w[2 * d + 1] * v[2 * d + 1]);
+  return nbs;
 }
 
 // q = t / n, r = t % n with a shift when lg >= 0 (n = 2^lg).
@@ -552,58 +553,135 @@ __device__ inline int c_divmod(int t, int n, int lg, int &r) {
   return q;
 }
 
-// One red/black half-sweep of level l (even n[0]); the cells of one colour
-// are enumerated directly: i = 2m + ((colour + j + k) & 1).
+// Cell of colour `color` number t of level l (even n[0]): the cells of one
+// colour are enumerated directly, i = 2m + ((colour + j + k) & 1).
 template <int DIM, typename T>
-__device__ inline void c_half(const CoarseArgs<T> &a, T *xs, const T *bs, int l, int color, bool zero_init) {
+__device__ inline int c_colour_cell(const CoarseArgs<T> &a, int l, int color, int t, int &i, int &j, int &k) {
   const int *n = a.n[l];
-  const int h0 = n[0] >> 1;
-  const int N = h0 * n[1] * n[2];
-  T *x = xs + a.off[l];
-  const T *b = bs + a.off[l];
-  for (int t = threadIdx.x; t < N; t += blockDim.x) {
-    int m, j, k = 0;
-    const int row = c_divmod(t, h0, a.lg[l][0], m);
-    if (DIM == 3)
-      k = c_divmod(row, n[1], a.lg[l][1], j);
-    else
-      j = row;
-    const int i = 2 * m + ((color + j + k) & 1);
-    const int idx = i + n[0] * (j + n[1] * k);
-    T nbs, dg;
-    c_parts<DIM, T>(n, a.B, a.ih2[l].v, x, i, j, k, nbs, dg);
+  int m;
+  k = 0;
+  const int row = c_divmod(t, n[0] >> 1, a.lg[l][0], m);
+  if (DIM == 3)
+    k = c_divmod(row, n[1], a.lg[l][1], j);
+  else
+    j = row;
+  i = 2 * m + ((color + j + k) & 1);
+  return i + n[0] * (j + n[1] * k);
+}
+
+// The cells of one colour of level l that this thread updates (at most
+// two: a level has at most kCoarseCells cells, 2 x 1024 per colour), with
+// the LDS indices of their neighbours and their inverse diagonals, set up
+// once per level and reused by every sweep. A missing neighbour (a
+// non-periodic side) points at a zero slot of the LDS array.
+template <int DIM, typename T>
+struct CSet {
+  int c[2];             // LDS index of the cell, -1 when the slot is empty
+  int nb[2][2 * DIM];   // LDS indices of the neighbours (-d, +d per direction)
+  T idg[2];             // 1 / diagonal
+};
+
+template <int DIM, typename T>
+__device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, int l, int color, int zero_slot,
+                             CSet<DIM, T> &s) {
+  const int *n = a.n[l];
+  const int N = (n[0] >> 1) * n[1] * n[2];
+  const int off = a.off[l];
+  const int st[3] = {1, n[0], n[0] * n[1]};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int t = threadIdx.x + q * blockDim.x;
+    s.c[q] = -1;
+    if (t >= N) continue;
+    int i, j, k;
+    const int c = c_colour_cell<DIM, T>(a, l, color, t, i, j, k);
+    const int qd[3] = {i, j, k};
+    int code = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const bool per = a.B.periodic[d] != 0;
+      const bool lo = qd[d] > 0, hi = qd[d] + 1 < n[d];
+      s.nb[q][2 * d] = lo ? off + c - st[d] : (per ? off + c + (n[d] - 1) * st[d] : zero_slot);
+      s.nb[q][2 * d + 1] = hi ? off + c + st[d] : (per ? off + c - (n[d] - 1) * st[d] : zero_slot);
+      code |= ((lo || per) && (hi || per)) ? (1 << d) : 0;
+    }
+    s.c[q] = off + c;
+    s.idg[q] = idg_s[8 * (l - a.l0) + code];
+  }
+}
+
+// One red/black half-sweep over a cell set: x = (b + sum of neighbours) /
+// diag, all LDS reads of the thread issued before the arithmetic.
+template <int DIM, typename T>
+__device__ inline void c_sweep(T *xs, const T *bs, const CSet<DIM, T> &s, const T ih2[3], bool zero_init) {
+  T v[2][2 * DIM], bv[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (s.c[q] < 0) continue;
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) v[q][m] = xs[s.nb[q][m]];
+    bv[q] = bs[s.c[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (s.c[q] < 0) continue;
+    T nbs = T(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) nbs += ih2[d] * (v[q][2 * d] + v[q][2 * d + 1]);
     if (zero_init) nbs = T(0);
-    x[idx] = (b[idx] + nbs) / dg;
+    xs[s.c[q]] = (bv[q] + nbs) * s.idg[q];
   }
   __syncthreads();
 }
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, const SolverScalars *sc) {
-  __shared__ T xs[kCoarseLds];
+  __shared__ T xs[kCoarseLds + 1];     // all coarse levels, then a zero slot
   __shared__ T bs[kCoarseLds];
+  __shared__ T idg_s[kCoarseLev * 8];  // inverse diagonals, read with a per-cell index
   if (sc->done) return;
   const int last = a.nlev - 1;
+  const int zero_slot = kCoarseLds;
+  if (threadIdx.x < kCoarseLev * 8) idg_s[threadIdx.x] = a.idg[threadIdx.x >> 3][threadIdx.x & 7];
+  if (threadIdx.x == 0) xs[zero_slot] = T(0);
   {
+    // all loads of the right-hand side issued before any is used
     const int *n = a.n[a.l0];
     const int N = n[0] * n[1] * n[2];
-    for (int t = threadIdx.x; t < N; t += blockDim.x) {
-      int i, j, k;
-      c_decode<DIM, T>(n, t, i, j, k);
-      const long g = a.L0.at(i, j, k);
-      bs[a.off[a.l0] + t] = a.b0_double ? (T)((const double *)a.b0)[g] : ((const T *)a.b0)[g];
+    T v[kCoarseLoads];
+#pragma unroll
+    for (int q = 0; q < kCoarseLoads; ++q) {
+      const int t = threadIdx.x + q * blockDim.x;
+      v[q] = T(0);
+      if (t < N) {
+        int i, j, k;
+        c_decode<DIM, T>(n, t, i, j, k);
+        const long g = a.L0.at(i, j, k);
+        v[q] = a.b0_double ? (T)((const double *)a.b0)[g] : ((const T *)a.b0)[g];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kCoarseLoads; ++q) {
+      const int t = threadIdx.x + q * blockDim.x;
+      if (t < N) bs[a.off[a.l0] + t] = v[q];
     }
     __syncthreads();
   }
   for (int l = a.l0; l < last; ++l) {
-    for (int s = 0; s < a.nu; ++s) {
-      c_half<DIM, T>(a, xs, bs, l, 0, s == 0);
-      c_half<DIM, T>(a, xs, bs, l, 1, false);
+    {
+      CSet<DIM, T> red, black;
+      c_set<DIM, T>(a, idg_s, l, 0, zero_slot, red);
+      c_set<DIM, T>(a, idg_s, l, 1, zero_slot, black);
+      for (int s = 0; s < a.nu; ++s) {
+        c_sweep<DIM, T>(xs, bs, red, a.ih2[l].v, s == 0);
+        c_sweep<DIM, T>(xs, bs, black, a.ih2[l].v, false);
+      }
     }
     const int *nf = a.n[l], *nc = a.n[l + 1];
     const int Nc = nc[0] * nc[1] * nc[2];
     const T *x = xs + a.off[l];
     const T *b = bs + a.off[l];
+
     for (int t = threadIdx.x; t < Nc; t += blockDim.x) {
       int I, J, K;
       c_decode<DIM, T>(nc, t, I, J, K);
@@ -613,8 +691,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
           for (int dx = 0; dx < 2; ++dx) {
             const int i = 2 * I + dx, j = 2 * J + dy, k = DIM == 3 ? 2 * K + dz : 0;
             const int c = i + nf[0] * (j + nf[1] * k);
-            T nbs, dg;
-            c_parts<DIM, T>(nf, a.B, a.ih2[l].v, x, i, j, k, nbs, dg);
+            int code;
+            const T nbs = c_nbs<DIM, T>(nf, a.B, a.ih2[l].v, x, i, j, k, c, code);
+            T dg = T(0);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) dg += a.ih2[l].v[d] * ((code >> d) & 1 ? T(2) : T(1));
             acc += b[c] - (dg * x[c] - nbs);
           }
       bs[a.off[l + 1] + t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
@@ -622,34 +703,68 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     __syncthreads();
   }
   {
+    // x = pinv b on the coarsest level: each wavefront takes 4 rows at a
+    // time, its lanes stride over the columns (coalesced rows of pinv, all
+    // loads of a row group in flight together), then a wavefront sum.
     const int *n = a.n[last];
     const int N = n[0] * n[1] * n[2];
-    for (int row = threadIdx.x; row < N; row += blockDim.x) {
-      T acc = T(0);
-      for (int col = 0; col < N; ++col) acc += a.pinv[(long)row * N + col] * bs[a.off[last] + col];
-      xs[a.off[last] + row] = acc;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const T *bl = bs + a.off[last];
+    for (int r0 = 4 * wv; r0 < N; r0 += 4 * nw) {
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      for (int col = lane; col < N; col += 64) {
+        const T bv = bl[col];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (r0 + q < N) acc[q] += a.pinv[(long)(r0 + q) * N + col] * bv;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T v = acc[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0 && r0 + q < N) xs[a.off[last] + r0 + q] = v;
+      }
     }
     __syncthreads();
   }
   for (int l = last - 1; l >= a.l0; --l) {
     const int *nf = a.n[l], *nc = a.n[l + 1];
     const int N = nf[0] * nf[1] * nf[2];
-    for (int t = threadIdx.x; t < N; t += blockDim.x) {
-      int i, j, k;
-      c_decode<DIM, T>(nf, t, i, j, k);
-      const int pc = (i >> 1) + nc[0] * ((j >> 1) + nc[1] * (DIM == 3 ? (k >> 1) : 0));
-      xs[a.off[l] + t] += xs[a.off[l + 1] + pc];
+    {
+      // piecewise-constant prolongation, all reads before the writes
+      T xf[kCoarseLoads], xc[kCoarseLoads];
+#pragma unroll
+      for (int q = 0; q < kCoarseLoads; ++q) {
+        const int t = threadIdx.x + q * blockDim.x;
+        if (t >= N) continue;
+        int i, j, k;
+        c_decode<DIM, T>(nf, t, i, j, k);
+        const int pc = (i >> 1) + nc[0] * ((j >> 1) + nc[1] * (DIM == 3 ? (k >> 1) : 0));
+        xf[q] = xs[a.off[l] + t];
+        xc[q] = xs[a.off[l + 1] + pc];
+      }
+#pragma unroll
+      for (int q = 0; q < kCoarseLoads; ++q) {
+        const int t = threadIdx.x + q * blockDim.x;
+        if (t < N) xs[a.off[l] + t] = xf[q] + xc[q];
+      }
     }
     __syncthreads();
+    CSet<DIM, T> red, black;
+    c_set<DIM, T>(a, idg_s, l, 0, zero_slot, red);
+    c_set<DIM, T>(a, idg_s, l, 1, zero_slot, black);
     for (int s = 0; s < a.nu; ++s) {
-      c_half<DIM, T>(a, xs, bs, l, 1, false);
-      c_half<DIM, T>(a, xs, bs, l, 0, false);
+      c_sweep<DIM, T>(xs, bs, black, a.ih2[l].v, false);
+      c_sweep<DIM, T>(xs, bs, red, a.ih2[l].v, false);
     }
   }
   {
     const int *n = a.n[a.l0];
     const int N = n[0] * n[1] * n[2];
-    for (int t = threadIdx.x; t < N; t += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kCoarseLoads; ++q) {
+      const int t = threadIdx.x + q * blockDim.x;
+      if (t >= N) continue;
       int i, j, k;
       c_decode<DIM, T>(n, t, i, j, k);
       a.x0[a.L0.at(i, j, k)] = xs[a.off[a.l0] + t];

@@ -197,7 +197,6 @@ template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
   __shared__ double sh[kBlock / 64];
   SolverScalars *sc = a.sc;
-  const long N = a.L.ncells();
   double cc = 0.0;
   const double mb = sc->mean_b, oc = sc->outflow_c;
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
@@ -256,7 +255,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_pq(CGArgs a, int np_cc) {
   }
   if (converged || broken) return;
   const TZ *z = (const TZ *)a.z;
-  const long N = a.L.ncells();
   double pq = 0.0;
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
     int i, j, kk;
@@ -301,7 +299,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(CGArgs a) {
   if (sc->done) return;
   const double pq = sum_all(a.part_pq, a.np_pq, sh);
   const double alpha = sc->rzh[(a.k - 1) & 1] / pq;
-  const long N = a.L.ncells();
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
     int i, j, k;
     if (!tile_cell(a.L, tile, i, j, k)) continue;
@@ -319,7 +316,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
   if (sc->done) return;
   const TZ *z = (const TZ *)a.z;
   const TZ *zo = (const TZ *)a.zold;
-  const long N = a.L.ncells();
   double rz = 0.0, rr = 0.0, rzo = 0.0;
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
     int i, j, k;
@@ -428,7 +424,6 @@ template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_sum_x(Lay L, const double *x, double *part) {
   __shared__ double sh[kBlock / 64];
   double s = 0.0;
-  const long N = L.ncells();
   for (int tile = blockIdx.x; tile < ntiles_of(L); tile += gridDim.x) {
     int i, j, k;
     if (!tile_cell(L, tile, i, j, k)) continue;
@@ -502,6 +497,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_prolong(Lay Lf, Lay Lc, TX *xf, c
 #include "lm_mg_kernels.h"
 
 namespace lm {
+static_assert(kCoarseCells <= (long)kCoarseLoads * kCoarseThreads, "coarse loads per thread");
+}  // namespace lm
+
+namespace lm {
 
 // ---------------------------------------------------------------------------
 // Host side
@@ -547,7 +546,7 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   while (ws.lc < nl - 1 && ws.lev[ws.lc].lay.ncells() > kCoarseCells) ++ws.lc;
   long lds = 0;
   for (int l = ws.lc; l < nl; ++l) lds += ws.lev[l].lay.ncells();
-  if (lds > kCoarseLds) {
+  if (lds > kCoarseLds || nl - ws.lc > kCoarseLev) {
     if (err) *err = "coarse grid too large for the one-block coarse solver";
     return false;
   }
@@ -778,6 +777,15 @@ static CoarseArgs<T> coarse_args(PoissonWS &ws, void *z, const double *r) {
     ca.ih2[l] = ih2_of<T>(ws, l);
     ca.off[l] = l >= ws.lc ? off : 0;
     if (l >= ws.lc) off += (int)ws.lev[l].lay.ncells();
+  }
+  for (int q = 0; q < kCoarseLev; ++q) {
+    const int l = ws.lc + q;
+    for (int code = 0; code < 8; ++code) {
+      double dg = 0.0;
+      if (l < ws.nlev)
+        for (int d = 0; d < ws.lay.ndim; ++d) dg += ws.lev[l].ih2[d] * (((code >> d) & 1) ? 2.0 : 1.0);
+      ca.idg[q][code] = dg > 0.0 ? (T)(1.0 / dg) : T(0);
+    }
   }
   ca.L0 = ws.lev[ws.lc].lay;
   ca.b0 = ws.lc == 0 ? (const void *)r : ws.lev[ws.lc].b;

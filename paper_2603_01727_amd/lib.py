@@ -99,6 +99,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run paper_2603_01727_amd.build.build() first")
+    # One HIP runtime per process: PyTorch brings its own libamdhip64 (same
+    # soname as the one this library links). Loaded first, it serves both;
+    # loaded after this library, a second copy would come in beside it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)
