@@ -158,17 +158,18 @@ __device__ inline void sweeps(T *xs, const T *bs, int p0, int gx0, int gy0, int 
 }
 
 // Down: [CG update] + NU red-black sweeps from zero + residual + restriction.
-template <typename T, int NU>
+template <typename T, int NU, int TXT, int TYT>
 __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
+  static_assert((TXT * TYT) % kBlock == 0 && TXT % 2 == 0 && TYT % 2 == 0, "tile shape");
   constexpr int H = 2 * NU + 1;
-  constexpr int W = TX + 2 * H, HH = TY + 2 * H;
+  constexpr int W = TXT + 2 * H, HH = TYT + 2 * H;
   __shared__ T xs[W * HH];
   __shared__ T bs[W * HH];
   __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
   const int tile = blockIdx.x;
-  const int gx0 = (tile % a.tiles_x) * TX - H, gy0 = (tile / a.tiles_x) * TY - H;
+  const int gx0 = (tile % a.tiles_x) * TXT - H, gy0 = (tile / a.tiles_x) * TYT - H;
   const int p0 = (gx0 + gy0) & 1;
   const int tid = threadIdx.x;
   const bool fast = frame_interior(a.B, gx0, gy0, W, HH, nx, ny);
@@ -239,14 +240,14 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
       if (o < NPOS) bs[o] = ok[it] ? (T)(rv[it] - alpha * (wv[it] + beta * sv[it])) : T(0);
     }
     // own cells: p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
-    constexpr int NOWN = TX * TY / kBlock;
+    constexpr int NOWN = TXT * TYT / kBlock;
     long oi[NOWN];
     double ro[NOWN], wo[NOWN], so[NOWN], xo[NOWN], po[NOWN];
     T uo[NOWN];
 #pragma unroll
     for (int u = 0; u < NOWN; ++u) {
       const int o = tid + u * kBlock;
-      oi[u] = a.Lf.at(gx0 + H + o % TX, gy0 + H + o / TX, 0);
+      oi[u] = a.Lf.at(gx0 + H + o % TXT, gy0 + H + o / TXT, 0);
     }
 #pragma unroll
     for (int u = 0; u < NOWN; ++u) {
@@ -280,13 +281,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
       if (o < NPOS) bs[o] = ok[it] ? (T)(rv[it] - alpha * qv[it]) : T(0);
     }
     if (cg) {  // CG update of the tile's own cells
-      constexpr int NOWN = TX * TY / kBlock;
+      constexpr int NOWN = TXT * TYT / kBlock;
       long oi[NOWN];
       double ro[NOWN], qo[NOWN], xo[NOWN], po[NOWN];
 #pragma unroll
       for (int u = 0; u < NOWN; ++u) {
         const int o = tid + u * kBlock;
-        oi[u] = a.Lf.at(gx0 + H + o % TX, gy0 + H + o / TX, 0);
+        oi[u] = a.Lf.at(gx0 + H + o % TXT, gy0 + H + o / TXT, 0);
       }
 #pragma unroll
       for (int u = 0; u < NOWN; ++u) {
@@ -316,12 +317,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   // zero initial guess: the first (red) half-sweep reads no neighbours, and
   // every later half-sweep only reads cells updated before it
   sweeps<T, W, HH, 1, 2 * NU, 1>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, true);
-  for (int o = tid; o < TX * TY; o += kBlock) {
-    const int lx = H + o % TX, ly = H + o / TX;
+  for (int o = tid; o < TXT * TYT; o += kBlock) {
+    const int lx = H + o % TXT, ly = H + o / TXT;
     a.xpre[a.Lf.at(gx0 + lx, gy0 + ly, 0)] = xs[ly * W + lx];
   }
-  for (int o = tid; o < (TX / 2) * (TY / 2); o += kBlock) {
-    const int cx = o % (TX / 2), cy = o / (TX / 2);
+  for (int o = tid; o < (TXT / 2) * (TYT / 2); o += kBlock) {
+    const int cx = o % (TXT / 2), cy = o / (TXT / 2);
     T acc = T(0);
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy)
@@ -345,17 +346,18 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
 // With EXTRA = 1 the frame carries one more halo ring, so the smoothed u is
 // valid one cell beyond the tile and w = A u is formed for the tile
 // (single-reduction CG: partials of r.u, w.u and r.r).
-template <typename T, int NU, int EXTRA>
+template <typename T, int NU, int EXTRA, int TXT, int TYT>
 __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
+  static_assert((TXT * TYT) % kBlock == 0 && TXT % 2 == 0 && TYT % 2 == 0, "tile shape");
   constexpr int H = 2 * NU + EXTRA;
-  constexpr int W = TX + 2 * H, HH = TY + 2 * H;
+  constexpr int W = TXT + 2 * H, HH = TYT + 2 * H;
   __shared__ T xs[W * HH];
   __shared__ T bs[W * HH];
   __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
   const int tile = blockIdx.x;
-  const int gx0 = (tile % a.tiles_x) * TX - H, gy0 = (tile / a.tiles_x) * TY - H;
+  const int gx0 = (tile % a.tiles_x) * TXT - H, gy0 = (tile / a.tiles_x) * TYT - H;
   const int p0 = (gx0 + gy0) & 1;
   const int tid = threadIdx.x;
   const bool fast = frame_interior(a.B, gx0, gy0, W, HH, nx, ny);
@@ -395,13 +397,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
   // half-sweep leaves u valid on the tile plus one cell
   sweeps<T, W, HH, 1, 2 * NU, 0>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, false);
   double rz = 0.0, rr = 0.0, rzo = 0.0;
-  constexpr int NOWN = TX * TY / kBlock;
+  constexpr int NOWN = TXT * TYT / kBlock;
   long oi[NOWN];
   T zv[NOWN];
 #pragma unroll
   for (int u = 0; u < NOWN; ++u) {
     const int o = tid + u * kBlock;
-    const int lx = H + o % TX, ly = H + o / TX;
+    const int lx = H + o % TXT, ly = H + o / TXT;
     oi[u] = a.Lf.at(gx0 + lx, gy0 + ly, 0);
     zv[u] = xs[ly * W + lx];
     a.xout[oi[u]] = zv[u];
@@ -414,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
 #pragma unroll
     for (int u = 0; u < NOWN; ++u) {
       const int o = tid + u * kBlock;
-      const int lx = H + o % TX, ly = H + o / TX;
+      const int lx = H + o % TXT, ly = H + o / TXT;
       const int off = ly * W + lx;
       T Lu;
       if (fast)

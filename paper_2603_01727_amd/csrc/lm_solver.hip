@@ -33,7 +33,8 @@ namespace lm {
 
 constexpr int kCoarseThreads = 1024;
 constexpr int kRedBlocks = 1024;   // grid of the grid-stride reduction kernels
-constexpr int TX = 64, TY = 16;    // 2D tile of the fused multigrid kernels
+constexpr int TX = 64, TY = 16;    // 2D tile of the fused multigrid kernels, finest level
+constexpr int TXS = 32, TYS = 8;   // 2D tile of the coarser fused levels (latency bound: short phases)
 
 Lay make_layout(int ndim, const int n[3], int elem_bytes) {
   Lay L;
@@ -506,9 +507,13 @@ namespace lm {
 // Host side
 // ---------------------------------------------------------------------------
 
+static int tile_x(int l) { return l == 0 ? TX : TXS; }
+static int tile_y(int l) { return l == 0 ? TY : TYS; }
+
 static bool fused_level(const PoissonWS &ws, int l) {
   const Lay &L = ws.lev[l].lay;
-  return L.ndim == 2 && ws.nu >= 1 && ws.nu <= 3 && L.n[0] % TX == 0 && L.n[1] % TY == 0 && l < ws.lc;
+  return L.ndim == 2 && ws.nu >= 1 && ws.nu <= 3 && L.n[0] % tile_x(l) == 0 && L.n[1] % tile_y(l) == 0 &&
+         l < ws.lc;
 }
 
 bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed,
@@ -674,23 +679,40 @@ static T *lev_xout(PoissonWS &ws, int l, void *z) {
   return (fused_level(ws, l) ? (T *)ws.lev[l].xpost : (T *)ws.lev[l].x);
 }
 
-template <typename T>
-static void launch_nu(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
-  if (nu == 1) hipLaunchKernelGGL((k_mg_down2d<T, 1>), g, dim3(kBlock), 0, st, a);
-  else if (nu == 2) hipLaunchKernelGGL((k_mg_down2d<T, 2>), g, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_mg_down2d<T, 3>), g, dim3(kBlock), 0, st, a);
+template <typename T, int TXT, int TYT>
+static void launch_nu_t(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
+  if (nu == 1) hipLaunchKernelGGL((k_mg_down2d<T, 1, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_down2d<T, 2, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_down2d<T, 3, TXT, TYT>), g, dim3(kBlock), 0, st, a);
 }
-template <typename T>
-static void launch_nu(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool extra) {
+template <typename T, int TXT, int TYT>
+static void launch_nu_t(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool extra) {
   if (extra) {
-    if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 1>), g, dim3(kBlock), 0, st, a);
-    else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 1>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_mg_up2d<T, 3, 1>), g, dim3(kBlock), 0, st, a);
+    if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 1, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+    else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 1, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up2d<T, 3, 1, TXT, TYT>), g, dim3(kBlock), 0, st, a);
     return;
   }
-  if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 0>), g, dim3(kBlock), 0, st, a);
-  else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 0>), g, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_mg_up2d<T, 3, 0>), g, dim3(kBlock), 0, st, a);
+  if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 0, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 0, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_up2d<T, 3, 0, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+}
+// Level 0 runs the large tile, coarser levels the small one.
+template <typename T>
+static void launch_nu(int l, int nu, Down2DArgs<T> &a, hipStream_t st) {
+  const dim3 g((a.Lf.n[0] / tile_x(l)) * (a.Lf.n[1] / tile_y(l)));
+  if (l == 0)
+    launch_nu_t<T, TX, TY>(nu, a, g, st);
+  else
+    launch_nu_t<T, TXS, TYS>(nu, a, g, st);
+}
+template <typename T>
+static void launch_nu(int l, int nu, Up2DArgs<T> &a, hipStream_t st, bool extra) {
+  const dim3 g((a.Lf.n[0] / tile_x(l)) * (a.Lf.n[1] / tile_y(l)));
+  if (l == 0)
+    launch_nu_t<T, TX, TY>(nu, a, g, st, extra);
+  else
+    launch_nu_t<T, TXS, TYS>(nu, a, g, st, extra);
 }
 
 template <typename T>
@@ -716,7 +738,7 @@ static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xp
   a.part_pq = ws.part_pq;
   a.np_pq = kRedBlocks;
   a.sc = ws.sc;
-  a.tiles_x = L.n[0] / TX;
+  a.tiles_x = L.n[0] / tile_x(l);
   // single-reduction CG (finest level, FP64)
   a.cgcg = ws.cgcg && l == 0;
   a.u = (const T *)ws.z[0];
@@ -750,9 +772,9 @@ static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, con
   a.finest = (l == 0);
   a.zold = zold;
   a.part_rz = ws.part_rz;
-  a.np = (L.n[0] / TX) * (L.n[1] / TY);
+  a.np = (L.n[0] / tile_x(l)) * (L.n[1] / tile_y(l));
   a.sc = ws.sc;
-  a.tiles_x = L.n[0] / TX;
+  a.tiles_x = L.n[0] / tile_x(l);
   a.w = ws.w;
   return a;
 }
@@ -811,7 +833,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     if (fused_level(ws, l)) {
       const void *b = l == 0 ? (k >= 1 ? (const void *)rprev : (const void *)r) : ws.lev[l].b;
       Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
-      launch_nu<T>(nu, a, dim3((L.n[0] / TX) * (L.n[1] / TY)), st);
+      launch_nu<T>(l, nu, a, st);
     } else {
       dim3 g = grid_for(L);
       for (int s = 0; s < nu; ++s) {
@@ -841,7 +863,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     if (fused_level(ws, l)) {
       const T *zold = (l == 0 && ws.mixed && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
       Up2DArgs<T> a = up_args<T>(ws, l, xin, xc, l == 0 ? (const void *)r : ws.lev[l].b, xout, zold);
-      launch_nu<T>(nu, a, dim3(a.np), st, ws.cgcg && l == 0);
+      launch_nu<T>(l, nu, a, st, ws.cgcg && l == 0);
     } else {
       dim3 g = grid_for(L);
       hipLaunchKernelGGL((k_mg_prolong<DIM, T>), g, bb, 0, st, L, Lc, xin, xc, sc);
@@ -1011,7 +1033,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       if (fused_level(ws, 0)) {
         Down2DArgs<T> d = down_args<T>(ws, 0, 2, ws.r[1], (T *)ws.zpre, ws.x, ws.p[0], ws.q, ws.r[0]);
         d.tol2 = 0.0;  // never converged: time the full kernel
-        launch_nu<T>(ws.nu, d, dim3((ws.lay.n[0] / TX) * (ws.lay.n[1] / TY)), st);
+        launch_nu<T>(0, ws.nu, d, st);
       } else {
         hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, ws.lay, ws.bnd,
                            ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc);
@@ -1024,7 +1046,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       if (fused_level(ws, 0)) {
         Up2DArgs<T> u = up_args<T>(ws, 0, (const T *)ws.zpre, lev_xout<T>(ws, 1, ws.z[0]), ws.r[0], (T *)ws.z[0],
                                    nullptr);
-        launch_nu<T>(ws.nu, u, dim3(u.np), st, ws.cgcg);
+        launch_nu<T>(0, ws.nu, u, st, ws.cgcg);
       } else {
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(ws.lev[1].lay), dim3(kBX, kBY), 0, st,
                            ws.lay, ws.lev[1].lay, ws.bnd, ih2_of<T>(ws, 0), (const T *)ws.z[0],
