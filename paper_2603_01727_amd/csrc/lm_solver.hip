@@ -35,6 +35,8 @@ constexpr int kCoarseThreads = 1024;
 constexpr int kRedBlocks = 1024;   // grid of the grid-stride reduction kernels
 constexpr int TX = 64, TY = 16;    // 2D tile of the fused multigrid kernels, finest level
 constexpr int TXS = 32, TYS = 8;   // 2D tile of the coarser fused levels (latency bound: short phases)
+constexpr int TX3 = 32, TY3 = 8;   // x-y tile of the fused 3D level kernels
+constexpr long kFused3DMinCells = 1L << 21;  // smaller 3D levels run the per-half-sweep kernels
 
 Lay make_layout(int ndim, const int n[3], int elem_bytes) {
   Lay L;
@@ -496,6 +498,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_prolong(Lay Lf, Lay Lc, TX *xf, c
 }  // namespace lm
 
 #include "lm_mg_kernels.h"
+#include "lm_mg3d.h"
 
 namespace lm {
 static_assert(kCoarseCells <= (long)kCoarseLoads * kCoarseThreads, "coarse loads per thread");
@@ -509,6 +512,25 @@ namespace lm {
 
 static int tile_x(int l) { return l == 0 ? TX : TXS; }
 static int tile_y(int l) { return l == 0 ? TY : TYS; }
+
+// Depth of the z chunk of a fused 3D level kernel: 32 planes, halved (down
+// to 8) while the level would have fewer than 1024 blocks; 0 if none fits.
+static int tz3_of(const Lay &L) {
+  const long cols = (long)(L.n[0] / TX3) * (L.n[1] / TY3);
+  int tz = 32;
+  while (tz > 8 && cols * (L.n[2] / tz) < 1024) tz /= 2;
+  return (L.n[2] % tz == 0) ? tz : 0;
+}
+
+// Blocks of the fused 3D kernels of a level.
+static long blocks3d(const Lay &L) { return (long)(L.n[0] / TX3) * (L.n[1] / TY3) * (L.n[2] / tz3_of(L)); }
+
+// Level l runs the fused 3D kernels (fully periodic grids).
+static bool fused3d(const PoissonWS &ws, int l) {
+  const Lay &L = ws.lev[l].lay;
+  return L.ndim == 3 && ws.bnd.all_periodic && ws.nu >= 1 && ws.nu <= 3 && l < ws.lc &&
+         L.ncells() >= kFused3DMinCells && L.n[0] % TX3 == 0 && L.n[1] % TY3 == 0 && tz3_of(L) > 0;
+}
 
 static bool fused_level(const PoissonWS &ws, int l) {
   const Lay &L = ws.lev[l].lay;
@@ -582,6 +604,7 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   const long ntile0 = (long)(fine.n[0] / TX) * (fine.n[1] / TY) + 1;
   long npmax = kRedBlocks;
   if (ntile0 > npmax) npmax = ntile0;
+  if (fused3d(ws, 0) && blocks3d(fine) > npmax) npmax = blocks3d(fine);
   ws.np_max = npmax;
   ws.part_cc = (double *)cv.take((size_t)npmax * 8);
   ws.part_pq = (double *)cv.take((size_t)npmax * 8);
@@ -669,15 +692,60 @@ static Ih2<T> ih2_of(const PoissonWS &ws, int l) {
 // corrections. Unfused levels smooth in place.
 template <typename T>
 static T *lev_xin(PoissonWS &ws, int l, void *z) {
-  if (l == 0) return fused_level(ws, 0) ? (T *)ws.zpre : (T *)z;
+  if (l == 0) return (fused_level(ws, 0) || fused3d(ws, 0)) ? (T *)ws.zpre : (T *)z;
   return (T *)ws.lev[l].x;
 }
 template <typename T>
 static T *lev_xout(PoissonWS &ws, int l, void *z) {
   if (l == 0) return (T *)z;
   if (l >= ws.lc) return (T *)ws.lev[l].x;
-  return (fused_level(ws, l) ? (T *)ws.lev[l].xpost : (T *)ws.lev[l].x);
+  return ((fused_level(ws, l) || fused3d(ws, l)) ? (T *)ws.lev[l].xpost : (T *)ws.lev[l].x);
 }
+
+template <typename T>
+static Fused3DArgs<T> f3_args(PoissonWS &ws, int l, const void *b, int b_double) {
+  Fused3DArgs<T> a;
+  const Lay &L = ws.lev[l].lay;
+  a.Lf = L;
+  a.Lc = ws.lev[l + 1].lay;
+  a.ihx = (T)ws.lev[l].ih2[0];
+  a.ihy = (T)ws.lev[l].ih2[1];
+  a.ihz = (T)ws.lev[l].ih2[2];
+  a.idg = (T)(1.0 / (2.0 * (ws.lev[l].ih2[0] + ws.lev[l].ih2[1] + ws.lev[l].ih2[2])));
+  a.tiles_x = L.n[0] / TX3;
+  a.tiles_y = L.n[1] / TY3;
+  a.tz = tz3_of(L);
+  a.b = b;
+  a.b_double = b_double;
+  a.xpre = nullptr;
+  a.xc = nullptr;
+  a.xout = nullptr;
+  a.bc = (T *)ws.lev[l + 1].b;
+  a.sc = ws.sc;
+  return a;
+}
+
+template <typename T>
+static void launch_3d(int nu, bool down, Fused3DArgs<T> &a, hipStream_t st, bool extra = false) {
+  const dim3 g(a.tiles_x * a.tiles_y * (a.Lf.n[2] / a.tz));
+  if (down) {
+    if (nu == 1) hipLaunchKernelGGL((k_mg_down3d<T, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    else if (nu == 2) hipLaunchKernelGGL((k_mg_down3d<T, 2, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_mg_down3d<T, 3, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+  } else if (extra) {
+    if (nu == 1) hipLaunchKernelGGL((k_mg_up3d<T, 1, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    else if (nu == 2) hipLaunchKernelGGL((k_mg_up3d<T, 2, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up3d<T, 3, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+  } else {
+    if (nu == 1) hipLaunchKernelGGL((k_mg_up3d<T, 1, 0, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    else if (nu == 2) hipLaunchKernelGGL((k_mg_up3d<T, 2, 0, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up3d<T, 3, 0, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+  }
+}
+
+
+// The finest 3D up kernel forms w = A u and the single-reduction CG partials.
+static bool w_in_up3d(const PoissonWS &ws) { return ws.cgcg && fused3d(ws, 0); }
 
 template <typename T, int TXT, int TYT>
 static void launch_nu_t(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
@@ -834,6 +902,10 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       const void *b = l == 0 ? (k >= 1 ? (const void *)rprev : (const void *)r) : ws.lev[l].b;
       Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
       launch_nu<T>(l, nu, a, st);
+    } else if (fused3d(ws, l)) {
+      Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
+      a.xout = xin;
+      launch_3d<T>(nu, true, a, st);
     } else {
       dim3 g = grid_for(L);
       for (int s = 0; s < nu; ++s) {
@@ -864,6 +936,16 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       const T *zold = (l == 0 && ws.mixed && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
       Up2DArgs<T> a = up_args<T>(ws, l, xin, xc, l == 0 ? (const void *)r : ws.lev[l].b, xout, zold);
       launch_nu<T>(l, nu, a, st, ws.cgcg && l == 0);
+    } else if (fused3d(ws, l)) {
+      Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
+      a.xpre = xin;
+      a.xc = xc;
+      a.xout = xout;
+      const bool extra = l == 0 && w_in_up3d(ws);
+      a.w = ws.w;
+      a.part_rz = ws.part_rz;
+      a.np = (int)blocks3d(L);
+      launch_3d<T>(nu, false, a, st, extra);
     } else {
       dim3 g = grid_for(L);
       hipLaunchKernelGGL((k_mg_prolong<DIM, T>), g, bb, 0, st, L, Lc, xin, xc, sc);
@@ -886,15 +968,17 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     a.z = z;
     a.zold = (ws.mixed && k >= 1) ? ws.z[(k + 1) & 1] : nullptr;
     a.np_rz = kRedBlocks;
-    if (ws.cgcg)
-      hipLaunchKernelGGL((k_cgcg_w<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, ws.w);
-    else
+    if (ws.cgcg) {
+      if (!w_in_up3d(ws)) hipLaunchKernelGGL((k_cgcg_w<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, ws.w);
+    } else
       hipLaunchKernelGGL((k_cg_rz<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
   }
 }
 
 static int np_rz_of(const PoissonWS &ws) {
-  return fused_level(ws, 0) ? (ws.lay.n[0] / TX) * (ws.lay.n[1] / TY) : kRedBlocks;
+  if (fused_level(ws, 0)) return (ws.lay.n[0] / TX) * (ws.lay.n[1] / TY);
+  if (w_in_up3d(ws)) return (int)blocks3d(ws.lay);
+  return kRedBlocks;
 }
 
 template <int DIM, typename T>
@@ -908,7 +992,7 @@ static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
       a.pnew = ws.p[0];
       a.rold = ws.r[(k - 1) & 1];
       a.rnew = ws.r[k & 1];
-      a.np_rz = kRedBlocks;
+      a.np_rz = np_rz_of(ws);
       hipLaunchKernelGGL((k_cgcg_update<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks,
                          (const double *)ws.w, (const double *)ws.s[k & 1], ws.s[(k + 1) & 1]);
     }

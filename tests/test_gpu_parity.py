@@ -140,3 +140,32 @@ def test_c2_full_size_one_step():
     errs = compare(st1, s.get(device=False))
     print(errs, s.stats, flush=True)
     _check(errs)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_3d_fused_multigrid_128(precision):
+    """128^3: the finest multigrid level runs the fused z-marching 3D
+    kernels (FP64, or FP32 inside the flexible FP64 CG)."""
+    case = c4_case(n=128)
+    print("3d 128^3", precision, flush=True)
+    o, st = oracle_for(case)
+    st = o.run(st, 2)
+    s = gpu_for(case, precision=precision)
+    s.step(2)
+    errs = compare(st, s.get(device=False))
+    print(errs, s.stats, flush=True)
+    _check(errs)
+
+
+def test_c4_full_size_one_step():
+    """The 256^3 workload at full size, one step, all fields against the
+    oracle (two fused 3D levels, 256^3 and 128^3)."""
+    case = c4_case()
+    print("c4 full size", flush=True)
+    o, st = oracle_for(case)
+    st1 = o.step(st)
+    s = gpu_for(case)
+    s.step(1)
+    errs = compare(st1, s.get(device=False))
+    print(errs, s.stats, flush=True)
+    _check(errs)
