@@ -178,9 +178,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   if (cg && a.cgcg) {
     // gamma = r.u, delta = (A u).u, rr = r.r of iteration k-1: convergence
     // test, then alpha and beta of the single-reduction recurrence
-    const double cc = sum_all(a.part_cc, a.np_cc, sh);
-    double g, d, rr;
-    sum_all3(a.part_g, a.part_g + a.np_g, a.part_g + 2 * a.np_g, a.np_g, sh, g, d, rr);
+    double cc, g, d, rr;
+    sum_cc3(a.k, a.part_cc, a.np_cc, a.sc, a.part_g, a.part_g + a.np_g, a.part_g + 2 * a.np_g, a.np_g, cc, g, d, rr);
     const bool conv = (cc == 0.0) || (rr <= a.tol2 * cc);
     if (a.k == 1) {
       alpha = g / d;

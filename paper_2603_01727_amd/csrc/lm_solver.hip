@@ -60,20 +60,35 @@ Lay make_layout(int ndim, const int n[3], int elem_bytes) {
 // Small device helpers
 // ---------------------------------------------------------------------------
 
-// Block-wide sum returned to every thread (fixed tree).
-__device__ inline double block_allsum(double v, double *sh) {
-  const double s = block_sum(v, sh);
-  __shared__ double bc;
-  if (linear_tid() == 0) bc = s;
+// Block-wide sums of NV values, identical in every thread: wavefront
+// shuffles, one exchange through LDS, then every thread adds the
+// per-wavefront sums in wavefront order (the tree of block_sum, so the
+// values are bitwise those of block_sum).
+template <int NV>
+__device__ inline void block_allsum_n(double (&v)[NV]) {
+  __shared__ double shn[NV][16];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+  const int t = linear_tid();
+  const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) / 64;
+  __syncthreads();  // an earlier call may still be reading shn
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) shn[q][t >> 6] = v[q];
+  }
   __syncthreads();
-  const double r = bc;
-  __syncthreads();
-  return r;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += shn[q][w];
+    v[q] = s;
+  }
 }
 
-// Sum of np partials, identical in every block and thread. Loads are issued
-// four at a time per thread so their latencies overlap.
-__device__ inline double sum_all(const double *part, int np, double *sh) {
+// This thread's share of the sum of np partials: loads issued four at a
+// time so their latencies overlap.
+__device__ inline double partial_share(const double *part, int np) {
   const int t = linear_tid();
   const int nt = blockDim.x * blockDim.y * blockDim.z;
   double s = 0.0;
@@ -87,33 +102,48 @@ __device__ inline double sum_all(const double *part, int np, double *sh) {
     }
     s += (v[0] + v[1]) + (v[2] + v[3]);
   }
-  return block_allsum(s, sh);
+  return s;
+}
+
+// Sum of np partials, identical in every block and thread.
+__device__ inline double sum_all(const double *part, int np, double *) {
+  double v[1] = {partial_share(part, np)};
+  block_allsum_n<1>(v);
+  return v[0];
 }
 
 // Sums of three partial arrays of np entries each (one combined pass).
-__device__ inline void sum_all3(const double *p0, const double *p1, const double *p2, int np, double *sh,
+__device__ inline void sum_all3(const double *p0, const double *p1, const double *p2, int np, double *,
                                 double &s0, double &s1, double &s2) {
-  const int t = linear_tid();
-  const int nt = blockDim.x * blockDim.y * blockDim.z;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int q0 = 0; q0 < np; q0 += 4 * nt) {
-    double v0[4], v1[4], v2[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = q0 + u * nt + t;
-      const int qs = q < np ? q : 0;
-      v0[u] = p0[qs];
-      v1[u] = p1[qs];
-      v2[u] = p2 ? p2[qs] : 0.0;
-      if (q >= np) v0[u] = v1[u] = v2[u] = 0.0;
-    }
-    a0 += (v0[0] + v0[1]) + (v0[2] + v0[3]);
-    a1 += (v1[0] + v1[1]) + (v1[2] + v1[3]);
-    a2 += (v2[0] + v2[1]) + (v2[2] + v2[3]);
+  double v[3] = {partial_share(p0, np), partial_share(p1, np), p2 ? partial_share(p2, np) : 0.0};
+  block_allsum_n<3>(v);
+  s0 = v[0];
+  s1 = v[1];
+  s2 = v[2];
+}
+
+// ||c||^2 (the partials of the solve's right-hand side on the first
+// iteration, the value stored by block 0 afterwards) together with the
+// three sums of sum_all3, in one pass.
+__device__ inline void sum_cc3(int k, const double *part_cc, int np_cc, const SolverScalars *sc, const double *p0,
+                               const double *p1, const double *p2, int np, double &cc, double &s0, double &s1,
+                               double &s2) {
+  if (k == 1) {
+    double v[4] = {partial_share(part_cc, np_cc), partial_share(p0, np), partial_share(p1, np),
+                   p2 ? partial_share(p2, np) : 0.0};
+    block_allsum_n<4>(v);
+    cc = v[0];
+    s0 = v[1];
+    s1 = v[2];
+    s2 = v[3];
+  } else {
+    cc = sc->cc;
+    double v[3] = {partial_share(p0, np), partial_share(p1, np), p2 ? partial_share(p2, np) : 0.0};
+    block_allsum_n<3>(v);
+    s0 = v[0];
+    s1 = v[1];
+    s2 = v[2];
   }
-  s0 = block_allsum(a0, sh);
-  s1 = block_allsum(a1, sh);
-  s2 = block_allsum(a2, sh);
 }
 
 template <int DIM>
@@ -237,10 +267,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_pq(CGArgs a, int np_cc) {
   SolverScalars *sc = a.sc;
   if (sc->done) return;
   const int k = a.k;
-  const double cc = sum_all(a.part_cc, np_cc, sh);
-  double rz, rr, rzo;
-  sum_all3(a.part_rz, a.part_rz + a.np_rz, a.flexible ? a.part_rz + 2 * a.np_rz : nullptr, a.np_rz, sh, rz, rr,
-           rzo);
+  double cc, rz, rr, rzo;
+  sum_cc3(k, a.part_cc, np_cc, sc, a.part_rz, a.part_rz + a.np_rz, a.flexible ? a.part_rz + 2 * a.np_rz : nullptr,
+          a.np_rz, cc, rz, rr, rzo);
   const bool converged = (cc == 0.0) || (rr <= a.tol2 * cc);
   const bool broken = !isfinite(rr) || !isfinite(rz);
   double beta = 0.0;
@@ -346,13 +375,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_cgcg_update(CGArgs a, int np_cc, const double *w, const double *s_old,
                                                         double *s_new) {
-  __shared__ double sh[kBlock / 64];
   SolverScalars *sc = a.sc;
   if (sc->done) return;
   const int k = a.k;
-  const double cc = sum_all(a.part_cc, np_cc, sh);
-  double g, d, rr;
-  sum_all3(a.part_rz, a.part_rz + a.np_rz, a.part_rz + 2 * a.np_rz, a.np_rz, sh, g, d, rr);
+  double cc, g, d, rr;
+  sum_cc3(k, a.part_cc, np_cc, sc, a.part_rz, a.part_rz + a.np_rz, a.part_rz + 2 * a.np_rz, a.np_rz, cc, g, d, rr);
   const bool conv = (cc == 0.0) || (rr <= a.tol2 * cc);
   double alpha, beta = 0.0;
   if (k == 1) {
