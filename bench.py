@@ -78,14 +78,26 @@ def time_solver(case, precision, steps, warmup):
                 poisson_iters_per_solve=iters, dt=s.dt, solver=s)
 
 
-def kernel_roofline(s, ncells):
-    """Average duration of the dominant kernel, timed with HIP events on the
-    solver's stream (lm_bench_kernel), priced at its algorithmic bytes."""
+def kernel_roofline(s, ncells, steps=20):
+    """Average duration of the dominant kernel as launched inside the step:
+    each of its launches in `steps` further steps of the same run is
+    bracketed by HIP events on the solver's stream (lm_kernel_timing);
+    priced at its algorithmic bytes. The same kernel timed back to back in
+    isolation (lm_bench_kernel) is reported beside it."""
     import ctypes as C
     ms = C.c_double()
-    st = s.lib.lm_bench_kernel(s.ctx, 0, 200, C.byref(ms))
-    if st != 0:
+    cnt = C.c_int()
+    if s.lib.lm_kernel_timing(s.ctx, 64 * steps) != 0:
         return None
+    s.step(steps)
+    st = s.lib.lm_kernel_timing_read(s.ctx, C.byref(ms), C.byref(cnt))
+    s.lib.lm_kernel_timing(s.ctx, 0)
+    if st != 0 or cnt.value == 0:
+        return None
+    iso = C.c_double()
+    iso_us = None
+    if s.lib.lm_bench_kernel(s.ctx, 0, 200, C.byref(iso)) == 0:
+        iso_us = round(iso.value * 1e3, 3)
     per_launch_s = ms.value * 1e-3
     achieved = BYTES_PER_CELL * ncells / per_launch_s / 1e9
     traffic = None
@@ -96,8 +108,21 @@ def kernel_roofline(s, ncells):
             traffic = t.get("bytes_per_launch")
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=DOMINANT,
-                avg_us=round(per_launch_s * 1e6, 3), bytes_per_cell=BYTES_PER_CELL,
+                avg_us=round(per_launch_s * 1e6, 3), launches_timed=cnt.value, timed_steps=steps,
+                isolated_avg_us=iso_us, bytes_per_cell=BYTES_PER_CELL,
                 algorithmic_bytes_per_launch=BYTES_PER_CELL * ncells)
+
+
+def field_differences(s_a, s_b):
+    import numpy as np
+    fa = s_a.get(("rho", "v", "H", "T", "P"), device=False)
+    fb = s_b.get(("rho", "v", "H", "T", "P"), device=False)
+    out = {}
+    for k in ("rho", "H", "T", "P"):
+        out[k] = float(np.linalg.norm(fa[k] - fb[k]) / np.linalg.norm(fb[k]))
+    for d in range(len(fb["v"])):
+        out[f"v{d}"] = float(np.linalg.norm(fa["v"][d] - fb["v"][d]) / np.linalg.norm(fb["v"][d]))
+    return out
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -148,6 +173,12 @@ def main():
         mixed = dict(value=rmx["value"], ms_per_step=round(rmx["ms_per_step"], 4),
                      poisson_iters_per_solve=rmx["poisson_iters_per_solve"],
                      speedup_vs_fp64=round(rmx["value"] / r64["value"], 3))
+        if roof is not None:
+            # both runs at the same step count: per-field relative L2
+            # difference of the mixed-precision state from the FP64 one
+            rmx["solver"].step(roof["timed_steps"])
+            mixed["rel_l2_vs_fp64"] = field_differences(rmx["solver"], r64["solver"])
+            mixed["compared_after_steps"] = a.warmup + a.steps + roof["timed_steps"]
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
         "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",

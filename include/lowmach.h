@@ -221,12 +221,24 @@ lm_status lm_adjoint_initial(lm_ctx *ctx, double *T0_bar, double *v0_bar[3], int
 /* Kernel timing hook: launches one kernel class `reps` times back to back on
  * the context's stream between two HIP events and returns the mean duration
  * of one launch in *avg_ms. Needs a state (after lm_set_fields); the kernels
- * only touch scratch arrays, so the state is unchanged. which:
- *   0 level-0 multigrid smoother half-sweep   1 predictor stage kernel
- *   2 CG search-direction update + operator   3 level-0 residual + restriction
+ * write solver scratch arrays and the predicted level only, and the next
+ * lm_step recomputes those. which:
+ *   0 finest multigrid down kernel (fused) or one half-sweep
+ *   1 predictor stage kernel                   2 CG direction update + operator
+ *   3 finest multigrid up kernel (fused) or the restriction
  *   4 CG solution/residual update              5 coarse-grid V-cycle block
  *   6 Poisson right-hand side                  7 projection                    */
 lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
+
+/* In-step timing of the finest multigrid down kernel (the fused 2D or 3D
+ * level kernel): with capacity > 0, the next launches of that kernel made
+ * by lm_step (up to capacity of them) are each bracketed by two HIP events
+ * on the context's stream; capacity = 0 stops and releases the events.
+ * lm_kernel_timing_read waits for the stream, then returns the mean
+ * event-measured duration of the recorded launches (ms) and their number
+ * (0 when the grid has no fused finest level).                             */
+lm_status lm_kernel_timing(lm_ctx *ctx, int capacity);
+lm_status lm_kernel_timing_read(lm_ctx *ctx, double *avg_ms, int *count);
 
 /* Text of the last error of ctx; with ctx == NULL, of the last failed
  * lm_workspace_size or lm_init_grid of the calling thread. */

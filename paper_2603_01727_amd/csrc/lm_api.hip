@@ -612,6 +612,7 @@ const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : g_init_
 
 void lm_destroy(lm_ctx *c) {
   if (!c) return;
+  (void)lm_kernel_timing(c, 0);
   if (c->hflags) (void)hipHostFree(c->hflags);
   if (c->hscalar) (void)hipHostFree(c->hscalar);
   if (c->pws.host_sc) (void)hipHostFree(c->pws.host_sc);
@@ -940,5 +941,49 @@ extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_ba
       if (v0_bar[d] && (s = copy_out(c, vb[d], v0_bar[d], -1, mem)) != LM_OK) return s;
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// In-step kernel timing
+// ---------------------------------------------------------------------------
+extern "C" lm_status lm_kernel_timing(lm_ctx *c, int capacity) {
+  if (!c || capacity < 0) return fail(c, LM_EINVAL, "bad arguments");
+  PoissonWS &ws = c->pws;
+  if (ws.tev) {
+    (void)hipStreamSynchronize(c->st);
+    for (int q = 0; q < 2 * ws.tcap; ++q) (void)hipEventDestroy(ws.tev[q]);
+    delete[] ws.tev;
+    ws.tev = nullptr;
+  }
+  ws.tcap = ws.tcount = 0;
+  if (capacity == 0) return LM_OK;
+  ws.tev = new (std::nothrow) hipEvent_t[2 * (size_t)capacity];
+  if (!ws.tev) return fail(c, LM_ENOMEM, "out of host memory");
+  for (int q = 0; q < 2 * capacity; ++q) {
+    const hipError_t e = hipEventCreate(&ws.tev[q]);
+    if (e != hipSuccess) {
+      for (int r = 0; r < q; ++r) (void)hipEventDestroy(ws.tev[r]);
+      delete[] ws.tev;
+      ws.tev = nullptr;
+      return fail(c, LM_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+  }
+  ws.tcap = capacity;
+  return LM_OK;
+}
+
+extern "C" lm_status lm_kernel_timing_read(lm_ctx *c, double *avg_ms, int *count) {
+  if (!c || !avg_ms || !count) return fail(c, LM_EINVAL, "NULL argument");
+  PoissonWS &ws = c->pws;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  double tot = 0.0;
+  for (int q = 0; q < ws.tcount; ++q) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, ws.tev[2 * q], ws.tev[2 * q + 1]));
+    tot += ms;
+  }
+  *count = ws.tcount;
+  *avg_ms = ws.tcount ? tot / ws.tcount : 0.0;
   return LM_OK;
 }

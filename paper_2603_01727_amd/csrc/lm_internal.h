@@ -202,6 +202,8 @@ struct PoissonWS {
   double *partials;        // scratch partials of once-per-solve reductions
   SolverScalars *sc;       // device scalars
   SolverScalars *host_sc;  // pinned host copy
+  hipEvent_t *tev;         // in-step timing of the finest down kernel: event pairs
+  int tcap, tcount;
 };
 
 // Plans the hierarchy and carves (or sizes, base == nullptr) the solver

@@ -928,11 +928,17 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     if (fused_level(ws, l)) {
       const void *b = l == 0 ? (k >= 1 ? (const void *)rprev : (const void *)r) : ws.lev[l].b;
       Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
+      const bool timed = l == 0 && ws.tcount < ws.tcap;
+      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
       launch_nu<T>(l, nu, a, st);
+      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
     } else if (fused3d(ws, l)) {
       Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
       a.xout = xin;
+      const bool timed = l == 0 && ws.tcount < ws.tcap;
+      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
       launch_3d<T>(nu, true, a, st);
+      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
     } else {
       dim3 g = grid_for(L);
       for (int s = 0; s < nu; ++s) {
