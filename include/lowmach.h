@@ -53,7 +53,7 @@ enum {
                         /* and shifted uniformly to close global mass          */
 };
 
-enum { LM_FP64 = 0, LM_MIXED = 1 };   /* Poisson preconditioner precision */
+enum { LM_FP64 = 0, LM_MIXED = 1, LM_MIXED_FLEXIBLE = 2 };   /* Poisson preconditioner precision */
 enum { LM_HOST = 0, LM_DEVICE = 1 };  /* where caller arrays live           */
 
 /* Grid: ndim in {2,3}; n[d] interior cells and L[d] length per direction
@@ -77,7 +77,11 @@ typedef struct {
  *  p0            constant thermodynamic pressure (Eq 2.41)
  *  dt            time step; 0 = fixed once from cfl and the initial state
  *  cfl           CFL number used when dt == 0
- *  precision     LM_FP64 or LM_MIXED (FP32 multigrid inside FP64 CG)
+ *  precision     LM_FP64: FP64 V-cycle in FP64 single-reduction CG;
+ *                LM_MIXED: FP32 V-cycle in the same FP64 single-reduction
+ *                CG (residual, operator, dot products and updates FP64);
+ *                LM_MIXED_FLEXIBLE: FP32 V-cycle in FP64 flexible
+ *                (Polak-Ribiere) CG
  *  poisson_rtol  stop when ||b - A P||_2 <= rtol ||b||_2 (b mean-free)
  *  poisson_maxit iteration cap (LM_ENOCONV beyond it)
  *  mg_nu         smoothing sweeps per level and direction (0 = default 2)

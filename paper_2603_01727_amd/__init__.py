@@ -91,7 +91,7 @@ class Solver:
                 g.bc[d][s] = _L.SIDE[bc[d][s]] if d < ndim else 0
         p = _L.lm_params(Re=Re, Pr=Pr, sigma=sigma, inv_Fr2=inv_Fr2, reacting=int(reacting), S=S, qs=qs,
                          eps=eps, tol=tol, Le_F=Le_F, Le_O=Le_O, Da_ib=Da_ib, p0=p0, dt=dt, cfl=cfl,
-                         precision=_L.LM_MIXED if precision == "mixed" else _L.LM_FP64,
+                         precision=_L.PRECISION[precision],
                          poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
                          with_ib=int(with_ib), with_adjoint=int(with_adjoint))
         self.grid, self.params = g, p

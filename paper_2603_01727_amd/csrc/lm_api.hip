@@ -130,8 +130,8 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "poisson_rtol > 0 and poisson_maxit > 0 required";
     return false;
   }
-  if (p->precision != LM_FP64 && p->precision != LM_MIXED) {
-    *err = "precision must be LM_FP64 or LM_MIXED";
+  if (p->precision != LM_FP64 && p->precision != LM_MIXED && p->precision != LM_MIXED_FLEXIBLE) {
+    *err = "precision must be LM_FP64, LM_MIXED or LM_MIXED_FLEXIBLE";
     return false;
   }
   if (p->with_adjoint && (p->reacting || p->with_ib || p->precision != LM_FP64)) {
@@ -233,7 +233,7 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   c->ad_cur = 0;
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = c->phys.h[d];
-  return poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision == LM_MIXED,
+  return poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision != LM_FP64, c->prm.precision == LM_MIXED_FLEXIBLE,
                       c->prm.mg_nu > 0 ? c->prm.mg_nu : 2, err);
 }
 

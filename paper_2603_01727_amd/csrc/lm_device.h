@@ -15,19 +15,34 @@ struct CellPos {
   long c;
 };
 
-__device__ inline bool cell_of_thread(const Lay &L, CellPos &p) {
-  p.i = blockIdx.x * kBX + threadIdx.x;
-  p.j = blockIdx.y * kBY + threadIdx.y;
-  p.k = blockIdx.z;
-  if (p.i >= L.n[0] || p.j >= L.n[1]) return false;
-  p.c = L.at(p.i, p.j, p.k);
-  return true;
-}
-
 __device__ inline unsigned linear_block() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 __device__ inline unsigned num_blocks() { return gridDim.x * gridDim.y * gridDim.z; }
+
+// Workgroups are dealt to the 8 XCDs round robin (linear block b runs on
+// XCD b mod 8), and each XCD has its own L2. Remapping block b to logical
+// block (b mod 8) q + b / 8 (q = blocks per XCD) gives XCD j the j-th
+// contiguous eighth of the domain, so tiles whose stencils overlap share an
+// L2. Blocks of an incomplete last round keep their index.
+constexpr unsigned kXCD = 8;
+__device__ inline unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned q = nb / kXCD;
+  if (b >= q * kXCD) return b;
+  return (b % kXCD) * q + b / kXCD;
+}
+
+__device__ inline bool cell_of_thread(const Lay &L, CellPos &p) {
+  const unsigned b = xcd_remap(linear_block(), num_blocks());
+  const unsigned bx = b % gridDim.x, byz = b / gridDim.x;
+  const unsigned by = byz % gridDim.y, bz = byz / gridDim.y;
+  p.i = bx * kBX + threadIdx.x;
+  p.j = by * kBY + threadIdx.y;
+  p.k = bz;
+  if (p.i >= L.n[0] || p.j >= L.n[1]) return false;
+  p.c = L.at(p.i, p.j, p.k);
+  return true;
+}
 __device__ inline int linear_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
 
 // Index of the neighbour of cell (coord q along d) at offset +-1 with

@@ -214,38 +214,38 @@ hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys 
 // Residuals at one time level and the Adams update
 // ---------------------------------------------------------------------------
 
-// tau_id on the face between cell cl and cl + s_d (Eq 2.46 on d-faces):
-// kappa_f [D_d v_i + D_i v_d - 2/3 delta_id div], D_d the difference across
-// the face, D_k (k != d) the mean of the two cells' centred differences.
+// tau_id on the face between cell cl and cl + s_d (Eq 2.46 on d-faces), all
+// components i at once: kappa_f [D_d v_i + D_i v_d - 2/3 delta_id div], D_d
+// the difference across the face, D_k (k != d) the mean of the two cells'
+// centred differences. Only the derivatives the face needs are formed: the
+// normal ones of every component, and along each k != d those of v_d and
+// v_k.
 template <int DIM>
-__device__ inline double tau_face(const Lay &L, const Phys &P, const Level &lv, long cl, int d, int i) {
+__device__ inline void face_stress(const Lay &L, const Phys &P, const Level &lv, long cl, int d, double tau[3]) {
   const long sd = L.s[d];
   const double kf = 0.5 * (lv.kap[cl] + lv.kap[cl + sd]);
-  double D[3][3];  // D[k][c] = D_k v_c on this face
+  double Dn[3];       // D_d v_c
+  double Dkd[3];      // D_k v_d (k != d)
+  double Dkk[3];      // D_k v_k (k != d)
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
+  for (int c = 0; c < DIM; ++c) Dn[c] = (lv.v[c][cl + sd] - lv.v[c][cl]) * P.ih[d];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const double *vc = lv.v[c];
-      if (k == d) {
-        D[k][c] = (vc[cl + sd] - vc[cl]) * P.ih[d];
-      } else {
-        const long sk = L.s[k];
-        const double h2 = 2.0 * P.h[k];
-        const double a = (vc[cl + sk] - vc[cl - sk]) / h2;
-        const double b = (vc[cl + sd + sk] - vc[cl + sd - sk]) / h2;
-        D[k][c] = 0.5 * (a + b);
-      }
-    }
+  for (int k = 0; k < DIM; ++k) {
+    if (k == d) continue;
+    const long sk = L.s[k];
+    const double h2 = 2.0 * P.h[k];
+    const double *vd = lv.v[d], *vk = lv.v[k];
+    Dkd[k] = 0.5 * ((vd[cl + sk] - vd[cl - sk]) / h2 + (vd[cl + sd + sk] - vd[cl + sd - sk]) / h2);
+    Dkk[k] = 0.5 * ((vk[cl + sk] - vk[cl - sk]) / h2 + (vk[cl + sd + sk] - vk[cl + sd - sk]) / h2);
   }
-  double t = D[d][i] + D[i][d];
-  if (i == d) {
-    double div = 0.0;
+  double div = 0.0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) div += D[k][k];
-    t = t - (2.0 / 3.0) * div;
+  for (int k = 0; k < DIM; ++k) div += (k == d) ? Dn[d] : Dkk[k];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    const double t = (i == d) ? (Dn[d] + Dn[d]) - (2.0 / 3.0) * div : Dn[i] + Dkd[i];
+    tau[i] = kf * t;
   }
-  return kf * t;
 }
 
 // Scalar terms of Eq 3.26b and the centred diffusion of section 3.2.
@@ -296,9 +296,19 @@ __device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, c
     rH = rH - chi * kap * (lv.H[c] - hib) / (P.Pe * P.Da);
   }
   RH = rH / rho;
+  double visc_all[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    double tp[3], tm[3];
+    face_stress<DIM>(L, P, lv, c, d, tp);
+    face_stress<DIM>(L, P, lv, c - L.s[d], d, tm);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) visc_all[i] = visc_all[i] + (tp[i] - tm[i]) / P.h[d];
+  }
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
-    double conv = 0.0, visc = 0.0;
+    double conv = 0.0;
+    const double visc = visc_all[i];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const long s = L.s[d];
@@ -306,9 +316,6 @@ __device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, c
       const double flp = lv.F[d][c] * (0.5 * (vi[c] + vi[c + s]));
       const double flm = lv.F[d][c - s] * (0.5 * (vi[c - s] + vi[c]));
       conv = conv + (flp - flm) / P.h[d];
-      const double tp = tau_face<DIM>(L, P, lv, c, d, i);
-      const double tm = tau_face<DIM>(L, P, lv, c - s, d, i);
-      visc = visc + (tp - tm) / P.h[d];
     }
     double r = -conv + (P.Pr / P.Pe) * visc;
     if (i == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);

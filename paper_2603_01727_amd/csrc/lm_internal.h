@@ -208,7 +208,7 @@ struct PoissonWS {
 
 // Plans the hierarchy and carves (or sizes, base == nullptr) the solver
 // arrays. Returns false if the grid does not coarsen to <= kMaxCoarsest cells.
-bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed,
+bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed, int flexible,
                   int nu, std::string *err);
 // Host-side set-up of the coarsest-level pseudo-inverse (after carving).
 hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h[3]);

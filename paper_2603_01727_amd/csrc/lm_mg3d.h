@@ -14,6 +14,7 @@ template <typename T>
 struct Fused3DArgs {
   Lay Lf, Lc;
   T ihx, ihy, ihz, idg;   // 1/h^2 per direction, 1/diag
+  double dihx, dihy, dihz;  // FP64 1/h^2: w = A u is formed in FP64 whatever T is
   int tiles_x, tiles_y, tz;
   const void *b;          // right-hand side of the level (FP64 on the finest level)
   int b_double;
@@ -28,6 +29,23 @@ struct Fused3DArgs {
 };
 
 __device__ inline int wrap_p(int g, int n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
+
+// Gauss-Seidel value (b + sum of the six neighbours scaled by 1/h^2) / diag
+// from v = {b, x-, x+, y-, y+, z-, z+}. A cell is updated by its owner and
+// by the halos of its neighbours' blocks, and all of them must get the same
+// bits (the single-reduction CG needs w = A u consistent with the stored u):
+// in FP32 the expression is evaluated exactly as written, with no
+// contraction into fused multiply-adds that could differ between the
+// unrolled copies. (FP64 differences would sit at the 1e-16 level.)
+template <typename T>
+__device__ inline T gs7(const T (&v)[7], T ihx, T ihy, T ihz, T idg) {
+  return (v[0] + (ihx * (v[1] + v[2]) + ihy * (v[3] + v[4]) + ihz * (v[5] + v[6]))) * idg;
+}
+template <>
+__device__ inline float gs7<float>(const float (&v)[7], float ihx, float ihy, float ihz, float idg) {
+#pragma clang fp contract(off)
+  return (v[0] + (ihx * (v[1] + v[2]) + ihy * (v[3] + v[4]) + ihz * (v[5] + v[6]))) * idg;
+}
 
 // One red/black half-sweep on plane slot xcur of a W x HH frame over the
 // region [s, W-s) x [s, HH-s); xm / xp are the planes below and above.
@@ -71,9 +89,7 @@ __device__ inline void hs_plane(T *xcur, const T *xm, const T *xp, const T *b, i
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u)
-    if (on[u])
-      xcur[off[u]] = (v[u][0] + (ihx * (v[u][1] + v[u][2]) + ihy * (v[u][3] + v[u][4]) + ihz * (v[u][5] + v[u][6]))) *
-                     idg;
+    if (on[u]) xcur[off[u]] = gs7<T>(v[u], ihx, ihy, ihz, idg);
 }
 
 // Down leg: NU red-black sweeps from zero, then residual and restriction.
@@ -89,7 +105,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_down3d(Fused3DArgs<T> a) {
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1], nz = a.Lf.n[2];
   const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = blockIdx.x % ntile, chunk = blockIdx.x / ntile;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = lb % ntile, chunk = lb / ntile;
   const int gx0 = (tile % a.tiles_x) * TXT - H, gy0 = (tile / a.tiles_x) * TYT - H;
   const int z0 = chunk * a.tz;
   const int zf0 = z0 - H, zf1 = z0 + a.tz + H;  // frame planes [zf0, zf1)
@@ -202,7 +219,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_up3d(Fused3DArgs<T> a) {
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1], nz = a.Lf.n[2];
   const int ntile = a.tiles_x * a.tiles_y;
-  const int tile = blockIdx.x % ntile, chunk = blockIdx.x / ntile;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = lb % ntile, chunk = lb / ntile;
   const int gx0 = (tile % a.tiles_x) * TXT - H, gy0 = (tile / a.tiles_x) * TYT - H;
   const int z0 = chunk * a.tz;
   const int zf0 = z0 - H, zf1 = z0 + a.tz + H;
@@ -275,10 +293,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_up3d(Fused3DArgs<T> a) {
       if (EXTRA) {
         const T *xm = xr[(q - 1 - zf0) % NX];
         const T *xp = xr[(q + 1 - zf0) % NX];
-        const double Lu = (double)((T(2) * (a.ihx + a.ihy + a.ihz)) * u -
-                                   (a.ihx * (xs[off - 1] + xs[off + 1]) + a.ihy * (xs[off - W] + xs[off + W]) +
-                                    a.ihz * (xm[off] + xp[off])));
-        const double rv = (double)br[(q - zf0) % NB][off];
+        const double Lu = (2.0 * (a.dihx + a.dihy + a.dihz)) * (double)u -
+                          (a.dihx * ((double)xs[off - 1] + (double)xs[off + 1]) +
+                           a.dihy * ((double)xs[off - W] + (double)xs[off + W]) +
+                           a.dihz * ((double)xm[off] + (double)xp[off]));
+        // r in FP64 from the level's right-hand side (the LDS copy is in T)
+        const double rv = a.b_double ? ((const double *)a.b)[g] : (double)br[(q - zf0) % NB][off];
         a.w[g] = Lu;
         ru += rv * (double)u;
         wu += Lu * (double)u;

@@ -44,6 +44,7 @@ struct Up2DArgs {
   Lay Lf, Lc;
   Bnd B;
   T ihx, ihy, idg;
+  double dihx, dihy;  // FP64 1/h^2: w = A u is formed in FP64 whatever T is
   const T *xpre, *xc;
   const void *b;      // FP64 r_k on the finest level
   T *xout;
@@ -70,14 +71,37 @@ __device__ inline bool frame_interior(const Bnd &B, int gx0, int gy0, int W, int
   return okx && oky;
 }
 
+// Gauss-Seidel value of an interior cell. A cell is updated by its owner and
+// by the halos of its neighbours' tiles, and all must get the same bits (the
+// single-reduction CG needs w = A u consistent with the stored u): in FP32
+// the expression is evaluated exactly as written, without contraction into
+// fused multiply-adds.
+template <typename T>
+__device__ inline T gs5(T b, T xw, T xe, T xs_, T xn, T ihx, T ihy, T idg) {
+  return (b + (ihx * (xw + xe) + ihy * (xs_ + xn))) * idg;
+}
+template <>
+__device__ inline float gs5<float>(float b, float xw, float xe, float xs_, float xn, float ihx, float ihy, float idg) {
+#pragma clang fp contract(off)
+  return (b + (ihx * (xw + xe) + ihy * (xs_ + xn))) * idg;
+}
+
 // Gauss-Seidel value at frame offset o, general case: raw global position
 // (gx, gy) possibly outside a non-periodic side, in which case the cell does
-// not exist (returns false).
+// not exist (returns false). A cell with all four neighbours takes exactly
+// the arithmetic of the interior path (gs5), so that a tile computing it in
+// its halo gets the owner's bits whichever path either tile runs.
 template <typename T, int W>
 __device__ inline bool gs_general(const T *xs, const T *bs, int o, int gx, int gy, int nx, int ny, const Bnd &B,
-                                  T ihx, T ihy, bool zero_nb, T &out) {
+                                  T ihx, T ihy, T idg, bool zero_nb, T &out) {
   if (!B.periodic[0] && (gx < 0 || gx >= nx)) return false;
   if (!B.periodic[1] && (gy < 0 || gy >= ny)) return false;
+  const bool inx = B.periodic[0] || (gx > 0 && gx + 1 < nx);
+  const bool iny = B.periodic[1] || (gy > 0 && gy + 1 < ny);
+  if (inx && iny) {
+    out = zero_nb ? bs[o] * idg : gs5<T>(bs[o], xs[o - 1], xs[o + 1], xs[o - W], xs[o + W], ihx, ihy, idg);
+    return true;
+  }
   T sx = T(0), sy = T(0);
   int cx = 0, cy = 0;
   if (B.periodic[0] || gx > 0) {
@@ -101,27 +125,27 @@ __device__ inline bool gs_general(const T *xs, const T *bs, int o, int gx, int g
 }
 
 // (L x) at frame offset o (cell known to exist).
-template <typename T, int W>
-__device__ inline T lx_general(const T *xs, int o, int gx, int gy, int nx, int ny, const Bnd &B, T ihx, T ihy) {
-  T sx = T(0), sy = T(0);
+template <typename T, int W, typename A = T>
+__device__ inline A lx_general(const T *xs, int o, int gx, int gy, int nx, int ny, const Bnd &B, A ihx, A ihy) {
+  A sx = A(0), sy = A(0);
   int cx = 0, cy = 0;
   if (B.periodic[0] || gx > 0) {
-    sx += xs[o - 1];
+    sx += (A)xs[o - 1];
     ++cx;
   }
   if (B.periodic[0] || gx + 1 < nx) {
-    sx += xs[o + 1];
+    sx += (A)xs[o + 1];
     ++cx;
   }
   if (B.periodic[1] || gy > 0) {
-    sy += xs[o - W];
+    sy += (A)xs[o - W];
     ++cy;
   }
   if (B.periodic[1] || gy + 1 < ny) {
-    sy += xs[o + W];
+    sy += (A)xs[o + W];
     ++cy;
   }
-  return (ihx * (T)cx + ihy * (T)cy) * xs[o] - (ihx * sx + ihy * sy);
+  return (ihx * (A)cx + ihy * (A)cy) * (A)xs[o] - (ihx * sx + ihy * sy);
 }
 
 // Half-sweeps s = S0 .. S1 on shrinking regions [s, W-s) x [s, HH-s) of a
@@ -147,10 +171,10 @@ __device__ inline void sweeps(T *xs, const T *bs, int p0, int gx0, int gy0, int 
         if (zn)
           xs[off] = bs[off] * idg;
         else
-          xs[off] = (bs[off] + (ihx * (xs[off - 1] + xs[off + 1]) + ihy * (xs[off - W] + xs[off + W]))) * idg;
+          xs[off] = gs5<T>(bs[off], xs[off - 1], xs[off + 1], xs[off - W], xs[off + W], ihx, ihy, idg);
       } else {
         T v;
-        if (gs_general<T, W>(xs, bs, off, gx0 + lx, gy0 + ly, nx, ny, B, ihx, ihy, zn, v)) xs[off] = v;
+        if (gs_general<T, W>(xs, bs, off, gx0 + lx, gy0 + ly, nx, ny, B, ihx, ihy, idg, zn, v)) xs[off] = v;
       }
     }
     __syncthreads();
@@ -168,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
-  const int tile = blockIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int gx0 = (tile % a.tiles_x) * TXT - H, gy0 = (tile / a.tiles_x) * TYT - H;
   const int p0 = (gx0 + gy0) & 1;
   const int tid = threadIdx.x;
@@ -355,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
   __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
-  const int tile = blockIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int gx0 = (tile % a.tiles_x) * TXT - H, gy0 = (tile / a.tiles_x) * TYT - H;
   const int p0 = (gx0 + gy0) & 1;
   const int tid = threadIdx.x;
@@ -417,13 +441,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
       const int o = tid + u * kBlock;
       const int lx = H + o % TXT, ly = H + o / TXT;
       const int off = ly * W + lx;
-      T Lu;
+      double Lu;
       if (fast)
-        Lu = (T(2) * (a.ihx + a.ihy)) * xs[off] -
-             (a.ihx * (xs[off - 1] + xs[off + 1]) + a.ihy * (xs[off - W] + xs[off + W]));
+        Lu = (2.0 * (a.dihx + a.dihy)) * (double)xs[off] -
+             (a.dihx * ((double)xs[off - 1] + (double)xs[off + 1]) + a.dihy * ((double)xs[off - W] + (double)xs[off + W]));
       else
-        Lu = lx_general<T, W>(xs, off, gx0 + lx, gy0 + ly, nx, ny, a.B, a.ihx, a.ihy);
-      const double wv = (double)Lu;
+        Lu = lx_general<T, W, double>(xs, off, gx0 + lx, gy0 + ly, nx, ny, a.B, a.dihx, a.dihy);
+      const double wv = Lu;
       a.w[oi[u]] = wv;
       ru += rv[u] * (double)zv[u];
       wu += wv * (double)zv[u];

@@ -6,24 +6,29 @@
 // (red-black down, black-red up), 2^d-cell averaging restriction,
 // piecewise-constant prolongation, rediscretised coarse operators and an
 // exact pseudo-inverse on the coarsest grid, so the zero-mean solution is
-// obtained as with the augmented-matrix method the paper uses. In mixed mode
-// the V-cycle runs in FP32 and CG (flexible, Polak-Ribiere beta) in FP64.
+// obtained as with the augmented-matrix method the paper uses. The V-cycle
+// runs in FP64, or in FP32 (mixed modes) with FP64 residuals, operator,
+// updates and dot products.
 //
-// Kernel structure. Iteration k is a fixed kernel sequence
-//   pq(k) -> [update(k)] -> V-cycle(k)
-// Scalars never leave the device. A reduction kernel writes one partial sum
-// per block; the next kernel that needs the total has every block sum those
-// partials in the same fixed order (no atomics, no grid-wide fences, bitwise
-// reproducible). Convergence is decided inside pq(k), which raises a device
-// flag that turns every later kernel into an immediate return; the host
-// queues iterations in batches and reads the flag once per batch.
+// CG. Single-reduction CG (Chronopoulos-Gear: one global reduction per
+// iteration, s = A p carried by recurrence and w = A u formed on the finest
+// level of the V-cycle) in FP64 and in the default mixed mode; flexible CG
+// (Polak-Ribiere beta, q = A p formed explicitly) in the flexible mixed
+// mode. Scalars never leave the device. A reduction kernel writes one
+// partial sum per block; the next kernel that needs the total has every
+// block sum those partials in the same fixed order (no atomics, no grid-wide
+// fences, bitwise reproducible). The convergence test runs on the device and
+// raises a flag that turns every later kernel into an immediate return; the
+// host queues iterations in batches and reads the flag once per batch.
 //
-// On 2D levels whose sizes are multiples of the 64 x 16 tile, the V-cycle
-// uses LDS tiles with temporal blocking: one kernel per level on the way down
-// (nu red-black sweeps from a zero guess, residual, restriction; on the
-// finest level also the CG update of x and r) and one on the way up
-// (prolongation, nu black-red sweeps; on the finest level also the r.z and
-// r.r partial sums). Other levels use one kernel per half-sweep.
+// Levels. 2D levels whose sizes are multiples of the tile run one LDS tile
+// kernel per level and direction with temporal blocking (nu red-black sweeps
+// from a zero guess, residual and restriction on the way down; prolongation
+// and nu black-red sweeps on the way up; on the finest level also the CG
+// update, w = A u and the CG partial sums). Large fully periodic 3D levels
+// run the z-marching equivalent (lm_mg3d.h). Levels of at most kCoarseCells
+// cells are solved by one block in LDS; the remaining levels run one kernel
+// per half-sweep.
 #include <cmath>
 #include <vector>
 
@@ -372,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
 // Step k: convergence test on r_{k-1}; beta = g_{k-1}/g_{k-2},
 // alpha = g_{k-1} / (d_{k-1} - beta g_{k-1}/alpha_{k-2}) with g = r.u and
 // d = (A u).u; p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s.
-template <int DIM>
+template <int DIM, typename TZ>
 __global__ void __launch_bounds__(kBlock) k_cgcg_update(CGArgs a, int np_cc, const double *w, const double *s_old,
                                                         double *s_new) {
   SolverScalars *sc = a.sc;
@@ -402,14 +407,14 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_update(CGArgs a, int np_cc, con
     }
   }
   if (conv || broken) return;
-  const double *u = (const double *)a.z;
+  const TZ *u = (const TZ *)a.z;
   const bool old = k >= 2;
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
     int i, j, kk;
     if (!tile_cell(a.L, tile, i, j, kk)) continue;
     const long c = a.L.at(i, j, kk);
     const double so = old ? s_old[c] : 0.0;
-    const double pn = u[c] + (old ? beta * a.pnew[c] : 0.0);
+    const double pn = (double)u[c] + (old ? beta * a.pnew[c] : 0.0);
     const double sn = w[c] + beta * so;
     a.pnew[c] = pn;
     s_new[c] = sn;
@@ -419,19 +424,19 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_update(CGArgs a, int np_cc, con
 }
 
 // w = A u (u = M r) and partials of r.u, w.u, r.r for the unfused finest level.
-template <int DIM>
+template <int DIM, typename TZ>
 __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
   __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
-  const double *u = (const double *)a.z;
+  const TZ *u = (const TZ *)a.z;
   double ru = 0.0, wu = 0.0, rr = 0.0;
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
     int i, j, k;
     if (!tile_cell(a.L, tile, i, j, k)) continue;
     const long c = a.L.at(i, j, k);
     double nbs, dg;
-    op_parts<DIM, double, double>(a.L, a.B, a.ih2, u, i, j, k, c, nbs, dg);
-    const double uc = u[c];
+    op_parts<DIM, double, TZ>(a.L, a.B, a.ih2, u, i, j, k, c, nbs, dg);
+    const double uc = (double)u[c];
     const double wv = dg * uc - nbs;
     const double rv = a.rnew[c];
     w[c] = wv;
@@ -565,7 +570,7 @@ static bool fused_level(const PoissonWS &ws, int l) {
          l < ws.lc;
 }
 
-bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed,
+bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed, int flexible,
                   int nu, std::string *err) {
   ws.lay = fine;
   ws.bnd = B;
@@ -611,12 +616,12 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   ws.p[0] = (double *)cv.take(fbytes);
   ws.p[1] = (double *)cv.take(fbytes);
   ws.q = (double *)cv.take(fbytes);
-  ws.cgcg = !mixed;
+  ws.cgcg = !flexible;
   ws.w = (double *)cv.take(fbytes);
   ws.s[0] = (double *)cv.take(fbytes);
   ws.s[1] = (double *)cv.take(fbytes);
   ws.z[0] = cv.take((size_t)fine.total * eb);
-  ws.z[1] = mixed ? cv.take((size_t)fine.total * eb) : ws.z[0];
+  ws.z[1] = (mixed && !ws.cgcg) ? cv.take((size_t)fine.total * eb) : ws.z[0];  // z_old: flexible CG only
   ws.zpre = cv.take((size_t)fine.total * eb);
   ws.lev[0].x = nullptr;
   ws.lev[0].xpost = nullptr;
@@ -738,6 +743,9 @@ static Fused3DArgs<T> f3_args(PoissonWS &ws, int l, const void *b, int b_double)
   a.ihx = (T)ws.lev[l].ih2[0];
   a.ihy = (T)ws.lev[l].ih2[1];
   a.ihz = (T)ws.lev[l].ih2[2];
+  a.dihx = ws.lev[l].ih2[0];
+  a.dihy = ws.lev[l].ih2[1];
+  a.dihz = ws.lev[l].ih2[2];
   a.idg = (T)(1.0 / (2.0 * (ws.lev[l].ih2[0] + ws.lev[l].ih2[1] + ws.lev[l].ih2[2])));
   a.tiles_x = L.n[0] / TX3;
   a.tiles_y = L.n[1] / TY3;
@@ -859,6 +867,8 @@ static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, con
   a.B = ws.bnd;
   a.ihx = (T)ws.lev[l].ih2[0];
   a.ihy = (T)ws.lev[l].ih2[1];
+  a.dihx = ws.lev[l].ih2[0];
+  a.dihy = ws.lev[l].ih2[1];
   a.idg = (T)(1.0 / (2.0 * ws.lev[l].ih2[0] + 2.0 * ws.lev[l].ih2[1]));
   a.xpre = xpre;
   a.xc = xc;
@@ -966,7 +976,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     T *xout = lev_xout<T>(ws, l, z);
     const T *xc = lev_xout<T>(ws, l + 1, z);
     if (fused_level(ws, l)) {
-      const T *zold = (l == 0 && ws.mixed && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
+      const T *zold = (l == 0 && !ws.cgcg && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
       Up2DArgs<T> a = up_args<T>(ws, l, xin, xc, l == 0 ? (const void *)r : ws.lev[l].b, xout, zold);
       launch_nu<T>(l, nu, a, st, ws.cgcg && l == 0);
     } else if (fused3d(ws, l)) {
@@ -999,10 +1009,10 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     CGArgs a = cg;
     a.rnew = ws.r[k & 1];
     a.z = z;
-    a.zold = (ws.mixed && k >= 1) ? ws.z[(k + 1) & 1] : nullptr;
+    a.zold = (!ws.cgcg && k >= 1) ? ws.z[(k + 1) & 1] : nullptr;
     a.np_rz = kRedBlocks;
     if (ws.cgcg) {
-      if (!w_in_up3d(ws)) hipLaunchKernelGGL((k_cgcg_w<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, ws.w);
+      if (!w_in_up3d(ws)) hipLaunchKernelGGL((k_cgcg_w<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, ws.w);
     } else
       hipLaunchKernelGGL((k_cg_rz<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
   }
@@ -1026,7 +1036,7 @@ static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
       a.rold = ws.r[(k - 1) & 1];
       a.rnew = ws.r[k & 1];
       a.np_rz = np_rz_of(ws);
-      hipLaunchKernelGGL((k_cgcg_update<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks,
+      hipLaunchKernelGGL((k_cgcg_update<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks,
                          (const double *)ws.w, (const double *)ws.s[k & 1], ws.s[(k + 1) & 1]);
     }
     vcycle<DIM, T>(st, ws, k, a);
@@ -1037,7 +1047,7 @@ static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
   a.pold = ws.p[(k - 1) & 1];
   a.pnew = ws.p[k & 1];
   a.np_rz = np_rz_of(ws);
-  a.flexible = ws.mixed;
+  a.flexible = !ws.cgcg;
   hipLaunchKernelGGL((k_cg_pq<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks);
   a.np_pq = kRedBlocks;
   if (!fused_level(ws, 0)) {
@@ -1075,7 +1085,7 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   a.tol2 = rtol * rtol;
   ws.tol2 = a.tol2;
   a.k = 0;
-  a.flexible = ws.mixed;
+  a.flexible = !ws.cgcg;
   hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_cg_init<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);

@@ -16,7 +16,8 @@ LM_OK, LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_ENOCONV, LM_ENONFINITE, LM_ESTATE, LM_E
 STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EHIP", -4: "LM_ENOCONV",
                 -5: "LM_ENONFINITE", -6: "LM_ESTATE", -7: "LM_EUNSUPPORTED"}
 SIDE = {"periodic": 0, "slip": 1, "noslip": 2, "inflow": 3, "outflow": 4}
-LM_FP64, LM_MIXED = 0, 1
+LM_FP64, LM_MIXED, LM_MIXED_FLEXIBLE = 0, 1, 2
+PRECISION = {"fp64": LM_FP64, "mixed": LM_MIXED, "mixed-flexible": LM_MIXED_FLEXIBLE}
 LM_HOST, LM_DEVICE = 0, 1
 
 

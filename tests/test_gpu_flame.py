@@ -53,12 +53,13 @@ def test_slot_flame_ragged_unfused():
     _check(errs)
 
 
-def test_slot_flame_mixed_precision():
+@pytest.mark.parametrize("precision", ["mixed", "mixed-flexible"])
+def test_slot_flame_mixed_precision(precision):
     case = c3_case(nx=128, ny=256, W=32, wall=4, wall_h=32, inj=4)
     o, st = oracle_for(case)
     st = o.run(st, 2)
-    s = gpu_for(case, precision="mixed")
+    s = gpu_for(case, precision=precision)
     s.step(2)
     errs = compare(st, s.get(device=False))
-    print("mixed:", errs, s.stats, flush=True)
+    print(precision, errs, s.stats, flush=True)
     _check(errs)

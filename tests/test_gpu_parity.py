@@ -103,14 +103,16 @@ def test_ragged_sizes():
         _check(errs)
 
 
-def test_mixed_precision_matches_fp64_oracle():
-    """FP32 multigrid inside FP64 flexible CG converges to the same FP64
-    solution: the per-field error against the FP64 oracle is stated here."""
+@pytest.mark.parametrize("precision", ["mixed", "mixed-flexible"])
+def test_mixed_precision_matches_fp64_oracle(precision):
+    """FP32 multigrid inside the FP64 single-reduction CG (mixed) or the FP64
+    flexible CG (mixed-flexible) converges to the same FP64 solution: the
+    per-field error against the FP64 oracle is stated here."""
     case = c2_case(n=128)
-    print("mixed 128", flush=True)
+    print(precision, "128", flush=True)
     o, st = oracle_for(case)
     st = o.run(st, 2)
-    s = gpu_for(case, precision="mixed")
+    s = gpu_for(case, precision=precision)
     s.step(2)
     errs = compare(st, s.get(device=False))
     print("mixed-precision errors vs FP64 oracle:", errs, s.stats, flush=True)
@@ -142,7 +144,7 @@ def test_c2_full_size_one_step():
     _check(errs)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed-flexible"])
 def test_3d_fused_multigrid_128(precision):
     """128^3: the finest multigrid level runs the fused z-marching 3D
     kernels (FP64, or FP32 inside the flexible FP64 CG)."""
