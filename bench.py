@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for HBM counter calibration)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 FP64-vs-mixed comparison")
     return ap.parse_args()
 
 
@@ -55,7 +56,8 @@ def kernel_source_hash():
 def make_solver(case, precision):
     from paper_2603_01727_amd import Solver
     p = case.params
-    s = Solver(case.n[:2], case.L[:2], Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"], precision=precision,
+    nd = case.ndim
+    s = Solver(case.n[:nd], case.L[:nd], Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"], precision=precision,
                poisson_rtol=p["poisson_rtol"], poisson_maxit=200, device="cuda:0")
     s.set(T=case.T, v=case.v)
     return s
@@ -111,6 +113,27 @@ def kernel_roofline(s, ncells, steps=20):
                 avg_us=round(per_launch_s * 1e6, 3), launches_timed=cnt.value, timed_steps=steps,
                 isolated_avg_us=iso_us, bytes_per_cell=BYTES_PER_CELL,
                 algorithmic_bytes_per_launch=BYTES_PER_CELL * ncells)
+
+
+def bench_3d(steps=10, warmup=3):
+    """The 3D triply periodic 256^3 workload (random modes |k| <= 6,
+    density ratio 6, Re 400), FP64 against mixed precision on the same
+    device, same steps; not the headline metric."""
+    from workloads import c4_case
+    case = c4_case()
+    out = {"workload": "3D periodic 2pi box 256^3, random modes |k|<=6, density ratio 6, Re=400, Pr=0.7, "
+                       "CFL 0.3, Poisson rtol 1e-10", "steps": steps, "warmup": warmup}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        r = time_solver(case, prec, steps, warmup)
+        res[prec] = r
+        out[prec] = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 3),
+                         poisson_iters_per_solve=r["poisson_iters_per_solve"])
+    out["mixed_speedup_vs_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    out["mixed_rel_l2_vs_fp64"] = field_differences(res["mixed"]["solver"], res["fp64"]["solver"])
+    for r in res.values():
+        r["solver"].close()
+    return out
 
 
 def field_differences(s_a, s_b):
@@ -179,6 +202,12 @@ def main():
             rmx["solver"].step(roof["timed_steps"])
             mixed["rel_l2_vs_fp64"] = field_differences(rmx["solver"], r64["solver"])
             mixed["compared_after_steps"] = a.warmup + a.steps + roof["timed_steps"]
+        rfl = time_solver(case, "mixed-flexible", a.steps, a.warmup)
+        mixed["flexible_cg"] = dict(value=rfl["value"], ms_per_step=round(rfl["ms_per_step"], 4),
+                                    poisson_iters_per_solve=rfl["poisson_iters_per_solve"],
+                                    speedup_vs_fp64=round(rfl["value"] / r64["value"], 3))
+        del rfl
+    three_d = None if a.no_3d else bench_3d()
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
         "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",
@@ -198,6 +227,7 @@ def main():
                    "cells": case.ncells, "dt": r64["dt"],
                    "poisson_iters_per_solve": r64["poisson_iters_per_solve"]},
         "mixed": mixed,
+        "c4_3d": three_d,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -115,11 +115,21 @@ def _wavevectors(ndim, kmax):
     return np.array(ks, dtype=np.int64)
 
 
-def _phase(n, L, k, coords):
-    arg = 0.0
-    for d in range(len(n)):
-        arg = arg + (2 * math.pi / L[d]) * k[d] * coords[d]
-    return arg
+def _mode_sum(n, ks, coef):
+    """Re sum_m coef_m exp(i theta_m(x)) at the cell centres, theta_m(x) =
+    sum_d 2 pi k_md x_d / L_d with x_d = (i_d + 1/2) L_d / n_d, by one
+    inverse FFT: exp(i theta) = prod_d exp(i pi k_d / n_d) exp(2 pi i k_d i_d / n_d)."""
+    ndim = len(n)
+    shp = tuple(reversed(n))
+    C = np.zeros(shp, dtype=np.complex128)
+    for q in range(len(ks)):
+        k = ks[q]
+        c = complex(coef[q])
+        for d in range(ndim):
+            c *= np.exp(1j * math.pi * k[d] / n[d])
+        idx = tuple(int(k[ndim - 1 - a]) % n[ndim - 1 - a] for a in range(ndim))
+        C[idx] += c
+    return np.fft.ifftn(C).real * float(np.prod(shp))
 
 
 def fourier_temperature(n, L, rng, kmax, amp, m=32):
@@ -131,11 +141,7 @@ def fourier_temperature(n, L, rng, kmax, amp, m=32):
     idx = rng.choice(len(ks), size=m, replace=False)
     a = rng.random(m)
     ph = 2 * math.pi * rng.random(m)
-    coords = cell_centres(n, L)
-    shp = tuple(reversed(n))
-    f = np.zeros(shp)
-    for q in range(m):
-        f = f + a[q] * np.cos(_phase(n, L, ks[idx[q]], coords) + ph[q])
+    f = _mode_sum(n, ks[idx], a * np.exp(1j * ph))
     fh = (f - f.min()) / (f.max() - f.min())
     return 1.0 + amp * fh
 
@@ -150,32 +156,27 @@ def solenoidal_velocity(n, L, rng, kmax, rms=0.1, m=32):
     ndim = len(n)
     ks = _wavevectors(ndim, kmax)
     idx = rng.choice(len(ks), size=m, replace=False)
-    coords = cell_centres(n, L)
-    shp = tuple(reversed(n))
-    v = [np.zeros(shp) for _ in range(ndim)]
+    km = ks[idx]
     if ndim == 2:
         a = rng.random(m)
         ph = 2 * math.pi * rng.random(m)
-        for q in range(m):
-            k = ks[idx[q]]
-            kx = 2 * math.pi / L[0] * k[0]
-            ky = 2 * math.pi / L[1] * k[1]
-            s = np.sin(_phase(n, L, k, coords) + ph[q])
-            v[0] = v[0] - a[q] * ky * s
-            v[1] = v[1] + a[q] * kx * s
+        kx = 2 * math.pi / L[0] * km[:, 0]
+        ky = 2 * math.pi / L[1] * km[:, 1]
+        e = a * np.exp(1j * ph)
+        # -a ky sin(theta + phi) and a kx sin(theta + phi), sin(u) = Re(-i e^{iu})
+        v = [_mode_sum(n, km, 1j * ky * e), _mode_sum(n, km, -1j * kx * e)]
     else:
         c = rng.normal(size=(m, 3))
         sn = rng.normal(size=(m, 3))
+        coef = np.zeros((3, m), dtype=np.complex128)
         for q in range(m):
-            k = ks[idx[q]]
-            kp = np.array([2 * math.pi / L[d] * k[d] for d in range(3)])
+            kp = np.array([2 * math.pi / L[d] * km[q][d] for d in range(3)])
             kk = kp / np.linalg.norm(kp)
             cq = c[q] - kk * (kk @ c[q])
             sq = sn[q] - kk * (kk @ sn[q])
-            arg = _phase(n, L, k, coords)
-            ca, sa = np.cos(arg), np.sin(arg)
-            for d in range(3):
-                v[d] = v[d] + cq[d] * ca + sq[d] * sa
+            # cq cos(theta) + sq sin(theta) = Re((cq - i sq) e^{i theta})
+            coef[:, q] = cq - 1j * sq
+        v = [_mode_sum(n, km, coef[d]) for d in range(3)]
     e = math.sqrt(float(np.mean(sum(x * x for x in v))))
     return [x * (rms / e) for x in v]
 
