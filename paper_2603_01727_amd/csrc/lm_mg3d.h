@@ -215,7 +215,6 @@ __global__ void __launch_bounds__(kBlock) k_mg_up3d(Fused3DArgs<T> a) {
   constexpr int NIT = (P + kBlock - 1) / kBlock;
   __shared__ T xr[NX][P];
   __shared__ T br[NB][P];
-  __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1], nz = a.Lf.n[2];
   const int ntile = a.tiles_x * a.tiles_y;
@@ -309,13 +308,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_up3d(Fused3DArgs<T> a) {
     if (EXTRA) __syncthreads();
   }
   if (EXTRA) {
-    const double s0 = block_sum(ru, sh);
-    const double s1 = block_sum(wu, sh);
-    const double s2 = block_sum(rr, sh);
+    double v3[3] = {ru, wu, rr};
+    block_allsum_n<3>(v3);
     if (tid == 0) {
-      a.part_rz[blockIdx.x] = s0;
-      a.part_rz[a.np + blockIdx.x] = s1;
-      a.part_rz[2 * a.np + blockIdx.x] = s2;
+      a.part_rz[blockIdx.x] = v3[0];
+      a.part_rz[a.np + blockIdx.x] = v3[1];
+      a.part_rz[2 * a.np + blockIdx.x] = v3[2];
     }
   }
 }

@@ -376,7 +376,6 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
   constexpr int W = TXT + 2 * H, HH = TYT + 2 * H;
   __shared__ T xs[W * HH];
   __shared__ T bs[W * HH];
-  __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -453,13 +452,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
       wu += wv * (double)zv[u];
       rr += rv[u] * rv[u];
     }
-    const double s0 = block_sum(ru, sh);
-    const double s1 = block_sum(wu, sh);
-    const double s2 = block_sum(rr, sh);
+    double v3[3] = {ru, wu, rr};
+    block_allsum_n<3>(v3);
     if (linear_tid() == 0) {
-      a.part_rz[blockIdx.x] = s0;
-      a.part_rz[a.np + blockIdx.x] = s1;
-      a.part_rz[2 * a.np + blockIdx.x] = s2;
+      a.part_rz[blockIdx.x] = v3[0];
+      a.part_rz[a.np + blockIdx.x] = v3[1];
+      a.part_rz[2 * a.np + blockIdx.x] = v3[2];
     }
     return;
   }
@@ -479,13 +477,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
     }
   }
   if (a.finest) {
-    const double s0 = block_sum(rz, sh);
-    const double s1 = block_sum(rr, sh);
-    const double s2 = a.zold ? block_sum(rzo, sh) : 0.0;
+    double v3[3] = {rz, rr, rzo};  // rzo stays 0 without z_old
+    block_allsum_n<3>(v3);
     if (linear_tid() == 0) {
-      a.part_rz[blockIdx.x] = s0;
-      a.part_rz[a.np + blockIdx.x] = s1;
-      a.part_rz[2 * a.np + blockIdx.x] = s2;
+      a.part_rz[blockIdx.x] = v3[0];
+      a.part_rz[a.np + blockIdx.x] = v3[1];
+      a.part_rz[2 * a.np + blockIdx.x] = v3[2];
     }
   }
 }

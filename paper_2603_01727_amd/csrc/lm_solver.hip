@@ -348,7 +348,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(CGArgs a) {
 // Partials of r.z, r.r (and r.z_old) for the unfused finest level.
 template <int DIM, typename TZ>
 __global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
-  __shared__ double sh[kBlock / 64];
   SolverScalars *sc = a.sc;
   if (sc->done) return;
   const TZ *z = (const TZ *)a.z;
@@ -363,13 +362,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(CGArgs a) {
     rr += rv * rv;
     if (zo) rzo += rv * (double)zo[c];
   }
-  const double s0 = block_sum(rz, sh);
-  const double s1 = block_sum(rr, sh);
-  const double s2 = zo ? block_sum(rzo, sh) : 0.0;
+  double v3[3] = {rz, rr, rzo};  // rzo stays 0 without z_old
+  block_allsum_n<3>(v3);
   if (linear_tid() == 0) {
-    a.part_rz[blockIdx.x] = s0;
-    a.part_rz[a.np_rz + blockIdx.x] = s1;
-    a.part_rz[2 * a.np_rz + blockIdx.x] = s2;
+    a.part_rz[blockIdx.x] = v3[0];
+    a.part_rz[a.np_rz + blockIdx.x] = v3[1];
+    a.part_rz[2 * a.np_rz + blockIdx.x] = v3[2];
   }
 }
 
@@ -426,7 +424,6 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_update(CGArgs a, int np_cc, con
 // w = A u (u = M r) and partials of r.u, w.u, r.r for the unfused finest level.
 template <int DIM, typename TZ>
 __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
-  __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const TZ *u = (const TZ *)a.z;
   double ru = 0.0, wu = 0.0, rr = 0.0;
@@ -444,13 +441,12 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
     wu += wv * uc;
     rr += rv * rv;
   }
-  const double s0 = block_sum(ru, sh);
-  const double s1 = block_sum(wu, sh);
-  const double s2 = block_sum(rr, sh);
+  double v3[3] = {ru, wu, rr};
+  block_allsum_n<3>(v3);
   if (linear_tid() == 0) {
-    a.part_rz[blockIdx.x] = s0;
-    a.part_rz[a.np_rz + blockIdx.x] = s1;
-    a.part_rz[2 * a.np_rz + blockIdx.x] = s2;
+    a.part_rz[blockIdx.x] = v3[0];
+    a.part_rz[a.np_rz + blockIdx.x] = v3[1];
+    a.part_rz[2 * a.np_rz + blockIdx.x] = v3[2];
   }
 }
 

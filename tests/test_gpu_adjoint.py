@@ -240,15 +240,17 @@ def test_c5_adjoint_512_200_steps():
     The five-point difference at h = 1e-3 must agree to 1e-6 along all 16
     directions. The central difference at h = 1e-6 is held to 1e-6 plus its
     rounding floor: J(T0 +- h d) are two FP64 trajectories of 200 steps
-    whose final kinetic energies carry rounding noise of order 10 ulp(J),
-    which a difference quotient over 2h turns into an absolute error of
-    about 10 ulp(J)/(2h) (7e-11 here); along directions with a small
-    derivative this floor exceeds 1e-6 relative."""
+    whose final kinetic energies differ by rounding noise of some tens of
+    ulp(J) (about 6 to 20 ulp observed), which a difference quotient over
+    2h turns into an absolute error of order 10 ulp(J)/(2h) = 7e-11 here;
+    along directions with a small derivative that exceeds 1e-6 relative. The
+    floor allowed is 100 ulp(J)/(2h)."""
     print("c5 adjoint 512^2 200 steps", flush=True)
     h = 1e-6
     J, t, out = _fd_check(512, 200, 20, h=h, h4=1e-3)
-    floor = 10 * math.ulp(J) / (2 * h)
-    print("J", J, "gradient s", t, "floor", floor, flush=True)
+    floor = 100 * math.ulp(J) / (2 * h)
+    plain = sum(1 for e, _, _ in out if e <= 1e-6)
+    print("J", J, "gradient s", t, "floor", floor, "directions within 1e-6 at h=1e-6:", plain, flush=True)
     for e, e4, ad in out:
         assert e4 <= 1e-6, out
         assert e * abs(ad) <= 1e-6 * abs(ad) + floor, out
