@@ -239,8 +239,10 @@ lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
  * by lm_step (up to capacity of them) are each bracketed by two HIP events
  * on the context's stream; capacity = 0 stops and releases the events.
  * lm_kernel_timing_read waits for the stream, then returns the mean
- * event-measured duration of the recorded launches (ms) and their number
- * (0 when the grid has no fused finest level).                             */
+ * event-measured duration (ms) and the number of the recorded launches
+ * that did the full work of a CG iteration (iterations 1 .. the solve's
+ * iteration count: iteration 0 has no CG update and launches queued after
+ * convergence return at once); 0 when the grid has no fused finest level. */
 lm_status lm_kernel_timing(lm_ctx *ctx, int capacity);
 lm_status lm_kernel_timing_read(lm_ctx *ctx, double *avg_ms, int *count);
 

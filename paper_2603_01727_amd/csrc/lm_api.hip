@@ -954,18 +954,29 @@ extern "C" lm_status lm_kernel_timing(lm_ctx *c, int capacity) {
     (void)hipStreamSynchronize(c->st);
     for (int q = 0; q < 2 * ws.tcap; ++q) (void)hipEventDestroy(ws.tev[q]);
     delete[] ws.tev;
+    delete[] ws.tk;
     ws.tev = nullptr;
+    ws.tk = nullptr;
   }
-  ws.tcap = ws.tcount = 0;
+  ws.tcap = ws.tcount = ws.tsolve0 = 0;
   if (capacity == 0) return LM_OK;
   ws.tev = new (std::nothrow) hipEvent_t[2 * (size_t)capacity];
-  if (!ws.tev) return fail(c, LM_ENOMEM, "out of host memory");
+  ws.tk = new (std::nothrow) int[(size_t)capacity];
+  if (!ws.tev || !ws.tk) {
+    delete[] ws.tev;
+    delete[] ws.tk;
+    ws.tev = nullptr;
+    ws.tk = nullptr;
+    return fail(c, LM_ENOMEM, "out of host memory");
+  }
   for (int q = 0; q < 2 * capacity; ++q) {
     const hipError_t e = hipEventCreate(&ws.tev[q]);
     if (e != hipSuccess) {
       for (int r = 0; r < q; ++r) (void)hipEventDestroy(ws.tev[r]);
       delete[] ws.tev;
+      delete[] ws.tk;
       ws.tev = nullptr;
+      ws.tk = nullptr;
       return fail(c, LM_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
     }
   }
@@ -978,12 +989,15 @@ extern "C" lm_status lm_kernel_timing_read(lm_ctx *c, double *avg_ms, int *count
   PoissonWS &ws = c->pws;
   HIPCHK(c, hipStreamSynchronize(c->st));
   double tot = 0.0;
+  int n = 0;
   for (int q = 0; q < ws.tcount; ++q) {
+    if (ws.tk[q] < 0) continue;
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, ws.tev[2 * q], ws.tev[2 * q + 1]));
     tot += ms;
+    ++n;
   }
-  *count = ws.tcount;
-  *avg_ms = ws.tcount ? tot / ws.tcount : 0.0;
+  *count = n;
+  *avg_ms = n ? tot / n : 0.0;
   return LM_OK;
 }

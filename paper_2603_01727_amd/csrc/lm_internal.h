@@ -203,7 +203,8 @@ struct PoissonWS {
   SolverScalars *sc;       // device scalars
   SolverScalars *host_sc;  // pinned host copy
   hipEvent_t *tev;         // in-step timing of the finest down kernel: event pairs
-  int tcap, tcount;
+  int *tk;                 // CG iteration of each timed launch; -1: not a full-work launch
+  int tcap, tcount, tsolve0;
 };
 
 // Plans the hierarchy and carves (or sizes, base == nullptr) the solver

@@ -937,14 +937,20 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       const bool timed = l == 0 && ws.tcount < ws.tcap;
       if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
       launch_nu<T>(l, nu, a, st);
-      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
+      if (timed) {
+        ws.tk[ws.tcount] = k;
+        (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
+      }
     } else if (fused3d(ws, l)) {
       Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
       a.xout = xin;
       const bool timed = l == 0 && ws.tcount < ws.tcap;
       if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
       launch_3d<T>(nu, true, a, st);
-      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
+      if (timed) {
+        ws.tk[ws.tcount] = k;
+        (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
+      }
     } else {
       dim3 g = grid_for(L);
       for (int s = 0; s < nu; ++s) {
@@ -1082,6 +1088,7 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   ws.tol2 = a.tol2;
   a.k = 0;
   a.flexible = !ws.cgcg;
+  ws.tsolve0 = ws.tcount;
   hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_cg_init<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
@@ -1101,6 +1108,10 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   }
   const SolverScalars &h = *ws.host_sc;
   *iters = h.iters;
+  // timed launches of this solve that did the full work: iterations 1 ..
+  // iters (iteration 0 has no CG update; later ones found the solve done)
+  for (int q = ws.tsolve0; q < ws.tcount; ++q)
+    if (ws.tk[q] < 1 || ws.tk[q] > h.iters) ws.tk[q] = -1;
   *relres = h.cc > 0 ? std::sqrt(h.rr / h.cc) : 0.0;
   *converged = h.done && !h.nonconv;
   // mean of the solution (the stored pressure is zero-mean)
