@@ -76,3 +76,22 @@ def test_invalid_arguments_rejected_without_gpu():
     ctx = C.c_void_p()
     g, p = _grid_params((64, 64))
     assert L.lm_init_grid(C.byref(g), C.byref(p), None, 0, None, C.byref(ctx)) == lib.LM_EINVAL
+
+
+def test_degenerate_grids_and_params_rejected():
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b = C.c_size_t()
+    for n in ((2, 8), (0, 16), (8, 3)):
+        g, p = _grid_params(n)
+        assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL, n
+        assert L.lm_last_error(None).decode()  # the reason is reported without a context
+    g, p = _grid_params((64, 64))
+    p.precision = 3
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    g, p = _grid_params((64, 64))
+    p.with_adjoint = 1
+    p.reacting = 1
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    g, p = _grid_params((4, 4))       # smallest grid: one level, solved by the dense pseudo-inverse
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
