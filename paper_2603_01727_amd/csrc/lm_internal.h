@@ -190,6 +190,7 @@ struct PoissonWS {
   int nlev, lc;            // MG levels; first level handled by the coarse kernel
   int mixed, nu;
   MGLevel lev[kMaxLev];    // level 0 uses r, zpre and z below
+  int tx[kMaxLev], ty[kMaxLev];  // 2D tile of the fused level kernels (0: level not tiled)
   double *x, *r[2], *p[2], *q;
   int cgcg;                // single-reduction (Chronopoulos-Gear) CG in FP64 mode
   double tol2;             // rtol^2 of the solve in progress

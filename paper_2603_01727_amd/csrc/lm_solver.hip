@@ -38,8 +38,11 @@ namespace lm {
 
 constexpr int kCoarseThreads = 1024;
 constexpr int kRedBlocks = 1024;   // grid of the grid-stride reduction kernels
-constexpr int TX = 64, TY = 16;    // 2D tile of the fused multigrid kernels, finest level
-constexpr int TXS = 32, TYS = 8;   // 2D tile of the coarser fused levels (latency bound: short phases)
+// 2D tiles of the fused multigrid kernels: 64 x 16 preferred on the finest
+// level (bandwidth), 32 x 8 below it (latency bound: shorter phases), 16 x 16
+// for sizes that neither divides.
+constexpr int TX = 64, TY = 16;
+constexpr int TXS = 32, TYS = 8;
 constexpr int TX3 = 32, TY3 = 8;   // x-y tile of the fused 3D level kernels
 constexpr long kFused3DMinCells = 1L << 21;  // smaller 3D levels run the per-half-sweep kernels
 
@@ -538,8 +541,22 @@ namespace lm {
 // Host side
 // ---------------------------------------------------------------------------
 
-static int tile_x(int l) { return l == 0 ? TX : TXS; }
-static int tile_y(int l) { return l == 0 ? TY : TYS; }
+static int tile_x(const PoissonWS &ws, int l) { return ws.tx[l]; }
+static int tile_y(const PoissonWS &ws, int l) { return ws.ty[l]; }
+
+// Tile of 2D level l (< lc), or 0 x 0 when no tile divides it.
+static void choose_tile(PoissonWS &ws, int l) {
+  const Lay &L = ws.lev[l].lay;
+  ws.tx[l] = ws.ty[l] = 0;
+  if (L.ndim != 2 || ws.nu < 1 || ws.nu > 3 || l >= ws.lc) return;
+  const int cand[3][2] = {{TX, TY}, {TXS, TYS}, {16, 16}};
+  for (int q = (l == 0 ? 0 : 1); q < 3; ++q)
+    if (L.n[0] % cand[q][0] == 0 && L.n[1] % cand[q][1] == 0) {
+      ws.tx[l] = cand[q][0];
+      ws.ty[l] = cand[q][1];
+      return;
+    }
+}
 
 // Depth of the z chunk of a fused 3D level kernel: 32 planes, halved (down
 // to 8) while the level would have fewer than 1024 blocks; 0 if none fits.
@@ -560,11 +577,7 @@ static bool fused3d(const PoissonWS &ws, int l) {
          L.ncells() >= kFused3DMinCells && L.n[0] % TX3 == 0 && L.n[1] % TY3 == 0 && tz3_of(L) > 0;
 }
 
-static bool fused_level(const PoissonWS &ws, int l) {
-  const Lay &L = ws.lev[l].lay;
-  return L.ndim == 2 && ws.nu >= 1 && ws.nu <= 3 && L.n[0] % tile_x(l) == 0 && L.n[1] % tile_y(l) == 0 &&
-         l < ws.lc;
-}
+static bool fused_level(const PoissonWS &ws, int l) { return ws.tx[l] > 0; }
 
 bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed, int flexible,
                   int nu, std::string *err) {
@@ -629,7 +642,11 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
     ws.lev[l].b = cv.take(lb);
   }
   ws.pinv = cv.take((size_t)ncoarsest * ncoarsest * eb);
-  const long ntile0 = (long)(fine.n[0] / TX) * (fine.n[1] / TY) + 1;
+  for (int l = 0; l < kMaxLev; ++l) {
+    ws.tx[l] = ws.ty[l] = 0;
+    if (l < nl) choose_tile(ws, l);
+  }
+  const long ntile0 = fused_level(ws, 0) ? (long)(fine.n[0] / ws.tx[0]) * (fine.n[1] / ws.ty[0]) + 1 : 0;
   long npmax = kRedBlocks;
   if (ntile0 > npmax) npmax = ntile0;
   if (fused3d(ws, 0) && blocks3d(fine) > npmax) npmax = blocks3d(fine);
@@ -798,20 +815,26 @@ static void launch_nu_t(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool ext
 }
 // Level 0 runs the large tile, coarser levels the small one.
 template <typename T>
-static void launch_nu(int l, int nu, Down2DArgs<T> &a, hipStream_t st) {
-  const dim3 g((a.Lf.n[0] / tile_x(l)) * (a.Lf.n[1] / tile_y(l)));
-  if (l == 0)
+static void launch_nu(const PoissonWS &ws, int l, int nu, Down2DArgs<T> &a, hipStream_t st) {
+  const int tx = tile_x(ws, l), ty = tile_y(ws, l);
+  const dim3 g((a.Lf.n[0] / tx) * (a.Lf.n[1] / ty));
+  if (tx == TX && ty == TY)
     launch_nu_t<T, TX, TY>(nu, a, g, st);
-  else
+  else if (tx == TXS && ty == TYS)
     launch_nu_t<T, TXS, TYS>(nu, a, g, st);
+  else
+    launch_nu_t<T, 16, 16>(nu, a, g, st);
 }
 template <typename T>
-static void launch_nu(int l, int nu, Up2DArgs<T> &a, hipStream_t st, bool extra) {
-  const dim3 g((a.Lf.n[0] / tile_x(l)) * (a.Lf.n[1] / tile_y(l)));
-  if (l == 0)
+static void launch_nu(const PoissonWS &ws, int l, int nu, Up2DArgs<T> &a, hipStream_t st, bool extra) {
+  const int tx = tile_x(ws, l), ty = tile_y(ws, l);
+  const dim3 g((a.Lf.n[0] / tx) * (a.Lf.n[1] / ty));
+  if (tx == TX && ty == TY)
     launch_nu_t<T, TX, TY>(nu, a, g, st, extra);
-  else
+  else if (tx == TXS && ty == TYS)
     launch_nu_t<T, TXS, TYS>(nu, a, g, st, extra);
+  else
+    launch_nu_t<T, 16, 16>(nu, a, g, st, extra);
 }
 
 template <typename T>
@@ -837,7 +860,7 @@ static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xp
   a.part_pq = ws.part_pq;
   a.np_pq = kRedBlocks;
   a.sc = ws.sc;
-  a.tiles_x = L.n[0] / tile_x(l);
+  a.tiles_x = L.n[0] / tile_x(ws, l);
   // single-reduction CG (finest level, FP64)
   a.cgcg = ws.cgcg && l == 0;
   a.u = (const T *)ws.z[0];
@@ -847,7 +870,7 @@ static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xp
   a.p_io = ws.p[0];
   a.part_g = ws.part_rz;
   a.part_cc = ws.part_cc;
-  a.np_g = (ws.lay.n[0] / TX) * (ws.lay.n[1] / TY);
+  a.np_g = fused_level(ws, 0) ? (ws.lay.n[0] / ws.tx[0]) * (ws.lay.n[1] / ws.ty[0]) : 0;
   a.np_cc = kRedBlocks;
   a.tol2 = ws.tol2;
   return a;
@@ -873,9 +896,9 @@ static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, con
   a.finest = (l == 0);
   a.zold = zold;
   a.part_rz = ws.part_rz;
-  a.np = (L.n[0] / tile_x(l)) * (L.n[1] / tile_y(l));
+  a.np = (L.n[0] / tile_x(ws, l)) * (L.n[1] / tile_y(ws, l));
   a.sc = ws.sc;
-  a.tiles_x = L.n[0] / tile_x(l);
+  a.tiles_x = L.n[0] / tile_x(ws, l);
   a.w = ws.w;
   return a;
 }
@@ -936,7 +959,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
       const bool timed = l == 0 && ws.tcount < ws.tcap;
       if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
-      launch_nu<T>(l, nu, a, st);
+      launch_nu<T>(ws, l, nu, a, st);
       if (timed) {
         ws.tk[ws.tcount] = k;
         (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
@@ -980,7 +1003,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     if (fused_level(ws, l)) {
       const T *zold = (l == 0 && !ws.cgcg && k >= 1) ? (const T *)ws.z[(k + 1) & 1] : nullptr;
       Up2DArgs<T> a = up_args<T>(ws, l, xin, xc, l == 0 ? (const void *)r : ws.lev[l].b, xout, zold);
-      launch_nu<T>(l, nu, a, st, ws.cgcg && l == 0);
+      launch_nu<T>(ws, l, nu, a, st, ws.cgcg && l == 0);
     } else if (fused3d(ws, l)) {
       Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
       a.xpre = xin;
@@ -1021,7 +1044,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
 }
 
 static int np_rz_of(const PoissonWS &ws) {
-  if (fused_level(ws, 0)) return (ws.lay.n[0] / TX) * (ws.lay.n[1] / TY);
+  if (fused_level(ws, 0)) return (ws.lay.n[0] / ws.tx[0]) * (ws.lay.n[1] / ws.ty[0]);
   if (w_in_up3d(ws)) return (int)blocks3d(ws.lay);
   return kRedBlocks;
 }
@@ -1167,7 +1190,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       if (fused_level(ws, 0)) {
         Down2DArgs<T> d = down_args<T>(ws, 0, 2, ws.r[1], (T *)ws.zpre, ws.x, ws.p[0], ws.q, ws.r[0]);
         d.tol2 = 0.0;  // never converged: time the full kernel
-        launch_nu<T>(0, ws.nu, d, st);
+        launch_nu<T>(ws, 0, ws.nu, d, st);
       } else {
         hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, ws.lay, ws.bnd,
                            ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc);
@@ -1180,7 +1203,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       if (fused_level(ws, 0)) {
         Up2DArgs<T> u = up_args<T>(ws, 0, (const T *)ws.zpre, lev_xout<T>(ws, 1, ws.z[0]), ws.r[0], (T *)ws.z[0],
                                    nullptr);
-        launch_nu<T>(0, ws.nu, u, st, ws.cgcg);
+        launch_nu<T>(ws, 0, ws.nu, u, st, ws.cgcg);
       } else {
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(ws.lev[1].lay), dim3(kBX, kBY), 0, st,
                            ws.lay, ws.lev[1].lay, ws.bnd, ih2_of<T>(ws, 0), (const T *)ws.z[0],
