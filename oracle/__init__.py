@@ -22,5 +22,5 @@ the face between cells f-1 and f.
 """
 from .flame import FlameParams, theta_eps, le_eps, n_eps, f_eps, f_tilde, temperature, enthalpy_from_T  # noqa: F401
 from .grid import Grid, fill_ghosts  # noqa: F401
-from .poisson import PoissonSolver, laplacian  # noqa: F401
+from .poisson import PoissonSolver, beta_inv_rho, laplacian  # noqa: F401
 from .step import Params, State, Oracle  # noqa: F401

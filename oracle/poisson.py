@@ -6,7 +6,8 @@ The discrete operator is A P = sum_d delta_1(beta delta_1 P)/delta_1 x_d, the
 composition of the face difference (Eq 3.21, n = 1) with itself that the
 discrete continuity equation Eq 3.24 produces once the face flux of Eq 3.23 is
 inserted. The paper's step has beta = 1; a face coefficient beta is accepted
-for the variable-coefficient form. Boundary faces of non-periodic sides carry
+for the variable-coefficient form, beta = 1/rho_f for div(grad P / rho)
+(beta_inv_rho). Boundary faces of non-periodic sides carry
 a prescribed mass flux, so A has zero flux there (a pure Neumann problem,
 section 3.3). The singular system is closed by the augmented-matrix method of
 section 3.3: [A 1; 1^T 0][P; lam] = [b; 0], whose solution is the zero-mean P,
@@ -47,6 +48,31 @@ def laplacian(g: Grid, P, beta=None):
         if beta is not None:
             G = G * beta[d]
         out = out + (g.plus(G, d) - g.minus(G, d)) / g.h[d]
+    return out
+
+
+def beta_inv_rho(g: Grid, rho):
+    """Face coefficient beta = 1/rho_f of the variable-coefficient form
+    div(grad P / rho), with rho_f the face value of the cell density by the
+    two-point average of Eq 3.20 (n = 1), on the n_d + 1 faces normal to d
+    (face f between cells f-1 and f, periodic wrap on periodic directions).
+    Boundary faces of non-periodic sides carry no flux; their entry is 0."""
+    out = []
+    for d in range(g.ndim):
+        ax = g.axis(d)
+        if g.periodic(d):
+            rm = np.roll(rho, 1, axis=ax)             # cell f-1 for face f = 0..n-1
+            inner = 1.0 / (0.5 * (rho + rm))
+            first = np.take(inner, [0], axis=ax)
+            out.append(np.concatenate([inner, first], axis=ax))
+            continue
+        lo = np.take(rho, np.arange(0, g.n[d] - 1), axis=ax)
+        hi = np.take(rho, np.arange(1, g.n[d]), axis=ax)
+        inner = 1.0 / (0.5 * (lo + hi))
+        shp = list(rho.shape)
+        shp[ax] = 1
+        z = np.zeros(shp)
+        out.append(np.concatenate([z, inner, z], axis=ax))
     return out
 
 

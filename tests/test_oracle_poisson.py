@@ -3,7 +3,7 @@ import math
 
 import numpy as np
 
-from oracle import Grid, PoissonSolver, laplacian
+from oracle import Grid, PoissonSolver, beta_inv_rho, laplacian
 from workloads import cell_centres
 
 
@@ -84,6 +84,99 @@ def test_variable_coefficient_manufactured_second_order():
         b = bx * Px + beta * Pxx + bx * Py + beta * Pyy
         bf = _beta_faces(g, lambda X, Y: 1 / rho(X, Y))
         P, _ = PoissonSolver(g, bf).solve(b)
+        errs.append(math.sqrt(np.mean((P - (Pex - Pex.mean())) ** 2)))
+    for a, c in zip(errs, errs[1:]):
+        assert abs(math.log(a / c, 2) - 2) < 0.15, errs
+
+
+# ---------------------------------------------------------------------------
+# Variable-coefficient form div(grad P / rho): beta = 1 / (face mean of rho)
+# ---------------------------------------------------------------------------
+
+def test_beta_inv_rho_constant_density_scales_the_fft_solution():
+    """rho = c everywhere: A_beta = A / c, so P = c P_1 with P_1 the FFT
+    solution of the constant-coefficient problem (independent solve)."""
+    rng = np.random.default_rng(3)
+    g = Grid((24, 16), (2 * math.pi, 1.5))
+    b = rng.standard_normal(g.shape)
+    P1, _ = PoissonSolver(g).solve(b)
+    c = 2.75
+    Pc, _ = PoissonSolver(g, beta_inv_rho(g, np.full(g.shape, c))).solve(b)
+    assert np.max(np.abs(Pc - c * P1)) < 1e-11 * np.max(np.abs(c * P1))
+
+
+def _separable_case(g, rho_axis_d, mode_d, k, periodic):
+    """rho varies only along rho_axis_d, P only along mode_d != rho_axis_d:
+    then no flux crosses faces normal to rho_axis_d, the faces normal to
+    mode_d carry beta = 1/rho of their column, and A_beta P = lam_k P / rho
+    with lam_k the 1D eigenvalue of the mode (Fourier or cosine)."""
+    rng = np.random.default_rng(11 + rho_axis_d)
+    shp = [1] * g.ndim
+    shp[g.axis(rho_axis_d)] = g.n[rho_axis_d]
+    rho = np.broadcast_to(rng.uniform(0.25, 1.0, g.n[rho_axis_d]).reshape(shp), g.shape).copy()
+    n, h = g.n[mode_d], g.h[mode_d]
+    i = np.arange(n)
+    if periodic:
+        m = np.cos(2 * math.pi * k * i / n)
+        lam = -(4 / h ** 2) * math.sin(math.pi * k / n) ** 2
+    else:
+        m = np.cos(math.pi * k * (i + 0.5) / n)
+        lam = -(4 / h ** 2) * math.sin(math.pi * k / (2 * n)) ** 2
+    shp = [1] * g.ndim
+    shp[g.axis(mode_d)] = n
+    P = np.broadcast_to(m.reshape(shp), g.shape).copy()
+    return rho, P, lam * P / rho
+
+
+def test_beta_inv_rho_separable_closed_form():
+    """Exact solutions of the discrete variable-coefficient problem: a mode
+    along one direction with the density varying (arbitrarily) along
+    another, periodic and zero-flux sides, 2D both ways round and 3D."""
+    cases = [
+        (Grid((20, 16), (2 * math.pi, 2.0)), 0, 1, 3, True),
+        (Grid((20, 16), (2 * math.pi, 2.0)), 1, 0, 4, True),
+        (Grid((12, 18), (1.0, 1.5), bc=(("slip", "slip"), ("noslip", "outflow"))), 0, 1, 5, False),
+        (Grid((12, 18), (1.0, 1.5), bc=(("slip", "slip"), ("noslip", "outflow"))), 1, 0, 2, False),
+        (Grid((8, 10, 12), (1.0, 2.0, 3.0)), 1, 2, 2, True),
+    ]
+    for g, da, dm, k, per in cases:
+        rho, P, b = _separable_case(g, da, dm, k, per)
+        beta = beta_inv_rho(g, rho)
+        assert np.max(np.abs(laplacian(g, P, beta) - b)) < 1e-10 * np.max(np.abs(b))
+        Ps, _ = PoissonSolver(g, beta).solve(b)
+        assert np.max(np.abs(Ps - (P - P.mean()))) < 1e-9, (g.n, da, dm)
+
+
+def test_beta_inv_rho_conserves_and_is_symmetric():
+    """sum over cells of A_beta P is zero (fluxes telescope, zero-flux
+    sides), and <A_beta u, w> = <u, A_beta w>."""
+    rng = np.random.default_rng(5)
+    for g in (Grid((16, 12), (1.0, 1.0)),
+              Grid((10, 14), (1.0, 2.0), bc=(("slip", "slip"), ("inflow", "outflow"))),
+              Grid((6, 8, 10), (1.0, 1.0, 1.0), bc=(("periodic", "periodic"), ("slip", "slip"),
+                                                    ("noslip", "noslip")))):
+        rho = rng.uniform(0.2, 1.5, g.shape)
+        beta = beta_inv_rho(g, rho)
+        u, w = rng.standard_normal(g.shape), rng.standard_normal(g.shape)
+        Au, Aw = laplacian(g, u, beta), laplacian(g, w, beta)
+        assert abs(Au.sum()) < 1e-11 * np.abs(Au).sum()
+        assert abs((Au * w).sum() - (u * Aw).sum()) < 1e-11 * np.abs(Au * w).sum()
+
+
+def test_beta_inv_rho_manufactured_second_order():
+    """The same manufactured problem as above with beta from the cell
+    density by face averaging (what a solver given only rho uses):
+    still O(h^2)."""
+    errs = []
+    for n in (16, 32, 64):
+        g = Grid((n, n), (2 * math.pi, 2 * math.pi))
+        x, y = cell_centres(g.n, g.L)
+        rho = 2 + np.sin(x + y)
+        Pex = np.cos(x) * np.sin(2 * y)
+        bx = -np.cos(x + y) / rho ** 2
+        b = (bx * (-np.sin(x) * np.sin(2 * y)) + (-np.cos(x) * np.sin(2 * y)) / rho
+             + bx * (2 * np.cos(x) * np.cos(2 * y)) + (-4 * np.cos(x) * np.sin(2 * y)) / rho)
+        P, _ = PoissonSolver(g, beta_inv_rho(g, rho)).solve(b)
         errs.append(math.sqrt(np.mean((P - (Pex - Pex.mean())) ** 2)))
     for a, c in zip(errs, errs[1:]):
         assert abs(math.log(a / c, 2) - 2) < 0.15, errs
