@@ -54,6 +54,7 @@ enum {
 };
 
 enum { LM_FP64 = 0, LM_MIXED = 1, LM_MIXED_FLEXIBLE = 2 };   /* Poisson preconditioner precision */
+enum { LM_BETA_ONE = 0, LM_BETA_INV_RHO = 1 };  /* Poisson face coefficient forms (lm_params)   */
 enum { LM_HOST = 0, LM_DEVICE = 1 };  /* where caller arrays live           */
 
 /* Grid: ndim in {2,3}; n[d] interior cells and L[d] length per direction
@@ -88,7 +89,13 @@ typedef struct {
  *  with_ib       1 = reserve immersed-boundary arrays (needed by lm_set_fields
  *                with a non-NULL lm_ib)
  *  with_adjoint  1 = reserve the adjoint arrays (lm_step_adjoint and its
- *                helpers; 2D periodic, non-reacting, no body, FP64 only)   */
+ *                helpers; 2D periodic, non-reacting, no body, FP64 only)
+ *  poisson_beta  LM_BETA_ONE (0): the step's operator only; LM_BETA_INV_RHO:
+ *                also reserve the arrays of the variable-coefficient form
+ *                beta = 1/rho_f for lm_project with a density (needs a grid
+ *                that coarsens to <= 128 cells). The step itself always
+ *                uses beta = 1: its constraint is on the mass flux
+ *                (Eq 3.9, 3.24), for which the density never enters A.    */
 typedef struct {
   double Re, Pr, sigma, inv_Fr2;
   int reacting;
@@ -100,6 +107,7 @@ typedef struct {
   int mg_nu;
   int with_ib;
   int with_adjoint;
+  int poisson_beta;
 } lm_params;
 
 /* Field set for lm_set_fields / lm_get_fields; NULL entries are skipped.
@@ -136,11 +144,19 @@ typedef struct {
 } lm_step_stats;
 
 /* RHS-mode projection: solve A P = b for the zero-mean P, with
- * A P = sum_d delta_1 (beta delta_1 P) (Eq 3.24 composed with Eq 3.23),
- * beta = 1. b is a cell field (mem says where); P is written to `P` and
- * also becomes the context's pressure (warm start of the next solve).     */
+ * A P = sum_d delta_1 (beta delta_1 P) (Eq 3.24 composed with Eq 3.23).
+ * rho NULL: beta = 1 (the step's operator). rho given (a cell field, same
+ * layout and `mem` as b; needs params.poisson_beta = LM_BETA_INV_RHO, else
+ * LM_EUNSUPPORTED): beta = 1/rho_f on every face, rho_f = (rho_a + rho_b)/2
+ * the two-point face average of the adjacent cells (Eq 3.20, n = 1), i.e.
+ * the variable-coefficient form div(grad P / rho) = b; zero flux through
+ * non-periodic sides either way; LM_EINVAL if rho is not positive and
+ * finite everywhere. b is a cell field (mem says where); P is written to
+ * `P` and also becomes the context's pressure (warm start of the next
+ * solve). rho is copied; no pointer is kept.                              */
 typedef struct {
   const double *b;
+  const double *rho;
   double *P;
   int mem;
   double rtol;               /* 0 = params.poisson_rtol                     */

@@ -71,8 +71,8 @@ class Solver:
                  qs: float = 1.0, eps: float = 0.5, tol: float = 1e-3, Le_F: float = 1.0, Le_O: float = 1.0,
                  Da_ib: float = 1.0, p0: float = 1.0, dt: float = 0.0, cfl: float = 0.2,
                  precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
-                 mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False, device: str = "cuda:0",
-                 stream=None):
+                 mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False,
+                 variable_coefficient: bool = False, device: str = "cuda:0", stream=None):
         import torch
         self.torch = torch
         self.lib = _L.load()
@@ -93,7 +93,8 @@ class Solver:
                          eps=eps, tol=tol, Le_F=Le_F, Le_O=Le_O, Da_ib=Da_ib, p0=p0, dt=dt, cfl=cfl,
                          precision=_L.PRECISION[precision],
                          poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
-                         with_ib=int(with_ib), with_adjoint=int(with_adjoint))
+                         with_ib=int(with_ib), with_adjoint=int(with_adjoint),
+                         poisson_beta=_L.LM_BETA_INV_RHO if variable_coefficient else _L.LM_BETA_ONE)
         self.grid, self.params = g, p
         self.device = torch.device(device)
         size = C.c_size_t()
@@ -198,11 +199,15 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.lm_get_dt(self.ctx, C.byref(v)))
         return v.value
 
-    def project(self, b, rtol: float = 0.0):
-        """Solve A P = b (zero-mean P, mean(b) removed) on this grid."""
+    def project(self, b, rtol: float = 0.0, rho=None):
+        """Solve A P = b (zero-mean P, mean(b) removed) on this grid; with
+        ``rho`` the variable-coefficient form div(grad P / rho) = b (needs
+        ``variable_coefficient=True``). ``rho`` lives where ``b`` does."""
         m = _Marshal(self.torch, self.device)
         a = _L.lm_project_args()
         a.b = m.ptr(b)
+        if rho is not None:
+            a.rho = m.ptr(rho)
         if m.mem == _L.LM_DEVICE:
             P = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
             a.P = P.data_ptr()

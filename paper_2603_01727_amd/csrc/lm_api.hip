@@ -134,6 +134,10 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "precision must be LM_FP64, LM_MIXED or LM_MIXED_FLEXIBLE";
     return false;
   }
+  if (p->poisson_beta != LM_BETA_ONE && p->poisson_beta != LM_BETA_INV_RHO) {
+    *err = "poisson_beta must be LM_BETA_ONE or LM_BETA_INV_RHO";
+    return false;
+  }
   if (p->with_adjoint && (p->reacting || p->with_ib || p->precision != LM_FP64)) {
     *err = "the adjoint supports non-reacting FP64 runs without immersed body";
     return false;
@@ -234,7 +238,7 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = c->phys.h[d];
   return poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision != LM_FP64, c->prm.precision == LM_MIXED_FLEXIBLE,
-                      c->prm.mg_nu > 0 ? c->prm.mg_nu : 2, err);
+                      c->prm.mg_nu > 0 ? c->prm.mg_nu : 2, c->prm.poisson_beta == LM_BETA_INV_RHO, err);
 }
 
 void setup_layout(lm_ctx *c) {
@@ -560,15 +564,28 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
 
 lm_status lm_project(lm_ctx *c, lm_project_args *a) {
   if (!c || !a || !a->b) return fail(c, LM_EINVAL, "NULL argument");
+  if (a->rho && !c->pws.vc_cap)
+    return fail(c, LM_EUNSUPPORTED, "a density needs params.poisson_beta = LM_BETA_INV_RHO");
   lm_status s = copy_in(c, a->b, c->b, -1, a->mem);
   if (s != LM_OK) return s;
   const Lay &L = c->lay;
+  if (a->rho) {
+    if ((s = copy_in(c, a->rho, c->pws.rho64, -1, a->mem)) != LM_OK) return s;
+    HIPCHK(c, poisson_set_beta(c->st, c->pws));
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, &c->pws.sc->rho_bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (bad) return fail(c, LM_EINVAL, "rho must be positive and finite");
+  }
   HIPCHK(c, launch_mean(c->st, L, c->b, c->pws.partials, c->pws.sc));
   int iters = 0, conv = 0;
   double relres = 0;
   const double rtol = a->rtol > 0 ? a->rtol : c->prm.poisson_rtol;
-  HIPCHK(c, poisson_solve(c->st, c->pws, c->b, c->P[c->icur], rtol, c->prm.poisson_maxit, 0, &iters, &relres,
-                          &conv));
+  c->pws.vc = a->rho != nullptr;
+  const hipError_t e = poisson_solve(c->st, c->pws, c->b, c->P[c->icur], rtol, c->prm.poisson_maxit, 0, &iters,
+                                     &relres, &conv);
+  c->pws.vc = 0;
+  HIPCHK(c, e);
   a->iters = iters;
   a->relres = relres;
   a->mean_b = c->pws.host_sc->mean_b;

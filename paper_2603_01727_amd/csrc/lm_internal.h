@@ -80,6 +80,7 @@ struct SolverScalars {
   double rr, cc;     // last ||r||^2 and ||c||^2 (c: mean-free right-hand side)
   double mean_b, sum_b, outflow_c, mean_x;
   int done, iters, zero, nonconv;  // kept contiguous (cleared together)
+  int rho_bad;                     // a density given for beta = 1/rho_f is not positive and finite
 };
 
 // Multigrid level storage (precision chosen at run time, hence void*).
@@ -183,6 +184,7 @@ struct Carver {
 constexpr int kMaxLev = 24;
 constexpr long kCoarseCells = 4096;   // levels at or below this size: one-block LDS kernel
 constexpr long kMaxCoarsest = 1024;   // dense pseudo-inverse limit
+constexpr int kVcCoarsest = 128;      // coarsest cells of a variable-coefficient solve (inverse built on the device)
 
 struct PoissonWS {
   Lay lay;                 // fine layout (FP64 CG vectors)
@@ -203,6 +205,14 @@ struct PoissonWS {
   double *partials;        // scratch partials of once-per-solve reductions
   SolverScalars *sc;       // device scalars
   SolverScalars *host_sc;  // pinned host copy
+  // variable-coefficient form A P = sum_d delta_1 (beta delta_1 P), beta = 1/rho_f
+  int vc_cap;              // arrays below reserved
+  int vc;                  // the solve in progress uses beta = 1/rho_f
+  int vtx[kMaxLev], vty[kMaxLev];  // 2D tile of the variable-coefficient level kernels
+  double *rho64;           // finest-level density (FP64, fine layout)
+  void *rho[kMaxLev];      // density per level in MG precision (level 0 aliases rho64 in FP64)
+  void *rho_c;             // densities of the coarse-kernel levels, packed as its LDS
+  void *pinv_vc;           // pseudo-inverse of the coarsest variable-coefficient operator
   hipEvent_t *tev;         // in-step timing of the finest down kernel: event pairs
   int *tk;                 // CG iteration of each timed launch; -1: not a full-work launch
   int tcap, tcount, tsolve0;
@@ -211,7 +221,7 @@ struct PoissonWS {
 // Plans the hierarchy and carves (or sizes, base == nullptr) the solver
 // arrays. Returns false if the grid does not coarsen to <= kMaxCoarsest cells.
 bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed, int flexible,
-                  int nu, std::string *err);
+                  int nu, int vc_cap, std::string *err);
 // Host-side set-up of the coarsest-level pseudo-inverse (after carving).
 hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h[3]);
 // Solve A x = b for the zero-mean x (A P = sum_d delta_1 delta_1 P with
@@ -220,6 +230,12 @@ hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h[3]);
 // The solution stays in ws.x with its mean in sc->mean_x.
 hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const double *x0, double rtol,
                          int maxit, int expect_iters, int *iters, double *relres, int *converged);
+// Prepares a variable-coefficient solve from the density in ws.rho64 (fine
+// layout): the density on every level (2^d-cell averages), the packed
+// coarse-level densities and the coarsest pseudo-inverse. Sets
+// sc->rho_bad when a density is not positive and finite. The caller then
+// sets ws.vc for the solve.
+hipError_t poisson_set_beta(hipStream_t st, PoissonWS &ws);
 // One launch of a solver kernel class for timing (see lm_bench_kernel);
 // the caller has cleared sc->done. Returns hipErrorInvalidValue for an
 // unknown class.

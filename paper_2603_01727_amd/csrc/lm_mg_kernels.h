@@ -3,6 +3,9 @@
 //    direction of the V-cycle), and
 //  - the one-block coarse V-cycle over all levels of at most kCoarseCells
 //    cells, with the dense pseudo-inverse on the coarsest grid.
+// Each comes in the constant-coefficient form (beta = 1) and, with VC, in
+// the variable-coefficient form beta = 1/rho_f (face_beta), whose level
+// operators are rediscretised from the level's density (2^d-cell averages).
 // Included by lm_solver.hip only.
 #pragma once
 
@@ -37,6 +40,7 @@ struct Down2DArgs {
   const double *part_g, *part_cc;  // [gamma | delta | rr] x np_g; ||c||^2 x np_cc
   int np_g, np_cc;
   double tol2;
+  const T *rho;             // variable-coefficient kernels: density of the level
 };
 
 template <typename T>
@@ -55,6 +59,8 @@ struct Up2DArgs {
   int finest;
   int tiles_x;
   double *w;          // single-reduction CG: w = A u written on the finest level
+  const T *rho;       // variable-coefficient kernels: density of the level
+  const double *rho64;  // and the finest level's FP64 density (w = A u in FP64)
 };
 
 __device__ inline int wrap_or_out(int g, int n, int periodic) {
@@ -181,14 +187,122 @@ __device__ inline void sweeps(T *xs, const T *bs, int p0, int gx0, int gy0, int 
   }
 }
 
+// ---- variable-coefficient frame (beta = 1/rho_f) ---------------------------
+// On entry ig holds the frame's densities, 0 where the cell does not exist
+// (outside a non-periodic side). On exit fx[o] (fy[o]) is beta of the face
+// between frame positions o-1 and o (o-W and o), 0 when either cell is
+// missing or o is on the first column (row); ig[o] is 1/diagonal of L at
+// interior frame positions of existing cells and 0 elsewhere, so a sweep
+// leaves missing cells at 0 with no boundary tests. With zero_x the frame's
+// x is cleared as well. Every tile computes a shared cell's coefficients
+// from the same densities with the same operations (same bits).
+template <typename T, int W, int HH>
+__device__ inline void vc_frame(T *fx, T *fy, T *ig, T *xs, T ihx, T ihy, bool zero_x) {
+#pragma clang fp contract(off)
+  const int tid = threadIdx.x;
+  for (int o = tid; o < W * HH; o += kBlock) {
+    const int lx = o % W, ly = o / W;
+    const T r = ig[o];
+    T bx = T(0), by = T(0);
+    if (lx >= 1) {
+      const T rw = ig[o - 1];
+      if (r > T(0) && rw > T(0)) bx = face_beta<T>(rw, r);
+    }
+    if (ly >= 1) {
+      const T rs = ig[o - W];
+      if (r > T(0) && rs > T(0)) by = face_beta<T>(rs, r);
+    }
+    fx[o] = bx;
+    fy[o] = by;
+    if (zero_x) xs[o] = T(0);
+  }
+  __syncthreads();
+  for (int o = tid; o < W * HH; o += kBlock) {
+    const int lx = o % W, ly = o / W;
+    T v = T(0);
+    if (lx >= 1 && lx <= W - 2 && ly >= 1 && ly <= HH - 2) {
+      const T dg = ihx * (fx[o] + fx[o + 1]) + ihy * (fy[o] + fy[o + W]);
+      if (dg > T(0)) v = T(1) / dg;
+    }
+    ig[o] = v;
+  }
+  __syncthreads();
+}
+
+// Gauss-Seidel value with face coefficients (evaluated as written, no
+// contraction: halo copies of a cell get the owner's bits).
+template <typename T>
+__device__ inline T gs_vc(T b, T xw, T xe, T xs_, T xn, T bw, T be, T bs_, T bn, T ihx, T ihy, T ig) {
+#pragma clang fp contract(off)
+  return (b + (ihx * (bw * xw + be * xe) + ihy * (bs_ * xs_ + bn * xn))) * ig;
+}
+
+// (L x) at frame offset o with the frame's face coefficients.
+template <typename T, int W, typename A = T>
+__device__ inline A lx_vc(const T *xs, const T *fx, const T *fy, int o, A ihx, A ihy) {
+#pragma clang fp contract(off)
+  const A bw = fx[o], be = fx[o + 1], bs_ = fy[o], bn = fy[o + W];
+  const A dg = ihx * (bw + be) + ihy * (bs_ + bn);
+  return dg * (A)xs[o] -
+         (ihx * (bw * (A)xs[o - 1] + be * (A)xs[o + 1]) + ihy * (bs_ * (A)xs[o - W] + bn * (A)xs[o + W]));
+}
+
+// FP64 (L u) at an own cell (gx, gy) of the finest level, the face
+// coefficients from the FP64 density in global memory, u from the frame.
+template <typename T, int W>
+__device__ inline double lx_vc64(const T *xs, int o, const double *rho64, const Lay &L, const Bnd &B, int gx, int gy,
+                                 double ihx, double ihy) {
+#pragma clang fp contract(off)
+  const long c = L.at(gx, gy, 0);
+  const int nx = L.n[0], ny = L.n[1];
+  const long sy = L.s[1];
+  const double rc = rho64[c];
+  double bw = 0.0, be = 0.0, bs_ = 0.0, bn = 0.0;
+  if (B.periodic[0] || gx > 0) bw = face_beta<double>(rc, rho64[gx > 0 ? c - 1 : c + (nx - 1)]);
+  if (B.periodic[0] || gx + 1 < nx) be = face_beta<double>(rc, rho64[gx + 1 < nx ? c + 1 : c - (nx - 1)]);
+  if (B.periodic[1] || gy > 0) bs_ = face_beta<double>(rc, rho64[gy > 0 ? c - sy : c + (long)(ny - 1) * sy]);
+  if (B.periodic[1] || gy + 1 < ny) bn = face_beta<double>(rc, rho64[gy + 1 < ny ? c + sy : c - (long)(ny - 1) * sy]);
+  const double dg = ihx * (bw + be) + ihy * (bs_ + bn);
+  return dg * (double)xs[o] - (ihx * (bw * (double)xs[o - 1] + be * (double)xs[o + 1]) +
+                               ihy * (bs_ * (double)xs[o - W] + bn * (double)xs[o + W]));
+}
+
+// Variable-coefficient half-sweeps, same regions and colours as sweeps().
+template <typename T, int W, int HH, int S0, int S1, int CSHIFT>
+__device__ inline void sweeps_vc(T *xs, const T *bs, const T *fx, const T *fy, const T *ig, int p0, T ihx, T ihy,
+                                 bool zero_first) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = S0; s <= S1; ++s) {
+    const int color = (s + CSHIFT) & 1;
+    const int w = W - 2 * s, rows = HH - 2 * s;
+    const int half = w / 2;
+    const int cnt = half * rows;
+    const bool zn = zero_first && s == S0;
+    for (int o = tid; o < cnt; o += kBlock) {
+      const int ly = s + o / half;
+      const int lx = s + 2 * (o % half) + ((color + p0 + ly + s) & 1);
+      const int off = ly * W + lx;
+      if (zn)
+        xs[off] = bs[off] * ig[off];
+      else
+        xs[off] = gs_vc<T>(bs[off], xs[off - 1], xs[off + 1], xs[off - W], xs[off + W], fx[off], fx[off + 1], fy[off],
+                           fy[off + W], ihx, ihy, ig[off]);
+    }
+    __syncthreads();
+  }
+}
+
 // Down: [CG update] + NU red-black sweeps from zero + residual + restriction.
-template <typename T, int NU, int TXT, int TYT>
+template <typename T, int NU, int TXT, int TYT, bool VC = false>
 __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   static_assert((TXT * TYT) % kBlock == 0 && TXT % 2 == 0 && TYT % 2 == 0, "tile shape");
   constexpr int H = 2 * NU + 1;
   constexpr int W = TXT + 2 * H, HH = TYT + 2 * H;
+  constexpr int WV = VC ? W * HH : 1;
   __shared__ T xs[W * HH];
   __shared__ T bs[W * HH];
+  __shared__ T fx[WV], fy[WV], ig[WV];
   __shared__ double sh[kBlock / 64];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
@@ -245,6 +359,24 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
     const int gy = wrap_or_out(gy0 + ly, ny, a.B.periodic[1]);
     ok[it] = o < NPOS && !ring && gx >= 0 && gy >= 0;
     gi[it] = ok[it] ? a.Lf.at(gx, gy, 0) : a.Lf.base;
+  }
+  if constexpr (VC) {
+    // densities on the whole frame (ring included), 0 for missing cells
+    T rv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int o = tid + it * kBlock;
+      const int gx = wrap_or_out(gx0 + o % W, nx, a.B.periodic[0]);
+      const int gy = wrap_or_out(gy0 + o / W, ny, a.B.periodic[1]);
+      const bool okr = o < NPOS && gx >= 0 && gy >= 0;
+      rv[it] = a.rho[okr ? a.Lf.at(gx, gy, 0) : a.Lf.base];
+      if (!okr) rv[it] = T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int o = tid + it * kBlock;
+      if (o < NPOS) ig[o] = rv[it];
+    }
   }
   if (a.finest && cg && a.cgcg) {
     // r_k = r_{k-1} - alpha (w + beta s_{k-2}) on the frame
@@ -339,7 +471,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   __syncthreads();
   // zero initial guess: the first (red) half-sweep reads no neighbours, and
   // every later half-sweep only reads cells updated before it
-  sweeps<T, W, HH, 1, 2 * NU, 1>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, true);
+  if constexpr (VC) {
+    vc_frame<T, W, HH>(fx, fy, ig, xs, a.ihx, a.ihy, true);
+    sweeps_vc<T, W, HH, 1, 2 * NU, 1>(xs, bs, fx, fy, ig, p0, a.ihx, a.ihy, true);
+  } else {
+    sweeps<T, W, HH, 1, 2 * NU, 1>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, true);
+  }
   for (int o = tid; o < TXT * TYT; o += kBlock) {
     const int lx = H + o % TXT, ly = H + o / TXT;
     a.xpre[a.Lf.at(gx0 + lx, gy0 + ly, 0)] = xs[ly * W + lx];
@@ -354,7 +491,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
         const int lx = H + 2 * cx + dx, ly = H + 2 * cy + dy;
         const int off = ly * W + lx;
         T Lx;
-        if (fast)
+        if constexpr (VC)
+          Lx = lx_vc<T, W>(xs, fx, fy, off, a.ihx, a.ihy);
+        else if (fast)
           Lx = (T(2) * (a.ihx + a.ihy)) * xs[off] - (a.ihx * (xs[off - 1] + xs[off + 1]) + a.ihy * (xs[off - W] + xs[off + W]));
         else
           Lx = lx_general<T, W>(xs, off, gx0 + lx, gy0 + ly, nx, ny, a.B, a.ihx, a.ihy);
@@ -369,13 +508,15 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
 // With EXTRA = 1 the frame carries one more halo ring, so the smoothed u is
 // valid one cell beyond the tile and w = A u is formed for the tile
 // (single-reduction CG: partials of r.u, w.u and r.r).
-template <typename T, int NU, int EXTRA, int TXT, int TYT>
+template <typename T, int NU, int EXTRA, int TXT, int TYT, bool VC = false>
 __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
   static_assert((TXT * TYT) % kBlock == 0 && TXT % 2 == 0 && TYT % 2 == 0, "tile shape");
   constexpr int H = 2 * NU + EXTRA;
   constexpr int W = TXT + 2 * H, HH = TYT + 2 * H;
+  constexpr int WV = VC ? W * HH : 1;
   __shared__ T xs[W * HH];
   __shared__ T bs[W * HH];
+  __shared__ T fx[WV], fy[WV], ig[WV];
   if (a.sc->done) return;
   const int nx = a.Lf.n[0], ny = a.Lf.n[1];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -399,12 +540,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
     gi[it] = okx[it] ? a.Lf.at(gx, gy, 0) : a.Lf.base;
     ci[it] = okx[it] ? a.Lc.at(gx >> 1, gy >> 1, 0) : a.Lc.base;
   }
-  T xv[NIT], cv[NIT], bv[NIT];
+  T xv[NIT], cv[NIT], bv[NIT], rv[VC ? NIT : 1];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     xv[it] = a.xpre[gi[it]];
     cv[it] = a.xc[ci[it]];
     bv[it] = a.finest ? (T)((const double *)a.b)[gi[it]] : ((const T *)a.b)[gi[it]];
+    if constexpr (VC) rv[it] = a.rho[gi[it]];
   }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -412,12 +554,18 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
     if (o < NPOS) {
       xs[o] = okx[it] ? xv[it] + cv[it] : T(0);
       bs[o] = okb[it] ? bv[it] : T(0);
+      if constexpr (VC) ig[o] = okx[it] ? rv[it] : T(0);
     }
   }
   __syncthreads();
   // regions shrink from the frame edge, so with the extra ring the last
   // half-sweep leaves u valid on the tile plus one cell
-  sweeps<T, W, HH, 1, 2 * NU, 0>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, false);
+  if constexpr (VC) {
+    vc_frame<T, W, HH>(fx, fy, ig, xs, a.ihx, a.ihy, false);
+    sweeps_vc<T, W, HH, 1, 2 * NU, 0>(xs, bs, fx, fy, ig, p0, a.ihx, a.ihy, false);
+  } else {
+    sweeps<T, W, HH, 1, 2 * NU, 0>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, false);
+  }
   double rz = 0.0, rr = 0.0, rzo = 0.0;
   constexpr int NOWN = TXT * TYT / kBlock;
   long oi[NOWN];
@@ -441,11 +589,17 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
       const int lx = H + o % TXT, ly = H + o / TXT;
       const int off = ly * W + lx;
       double Lu;
-      if (fast)
+      if constexpr (VC) {
+        if constexpr (sizeof(T) == 8)
+          Lu = lx_vc<T, W, double>(xs, fx, fy, off, a.dihx, a.dihy);
+        else
+          Lu = lx_vc64<T, W>(xs, off, a.rho64, a.Lf, a.B, gx0 + lx, gy0 + ly, a.dihx, a.dihy);
+      } else if (fast) {
         Lu = (2.0 * (a.dihx + a.dihy)) * (double)xs[off] -
              (a.dihx * ((double)xs[off - 1] + (double)xs[off + 1]) + a.dihy * ((double)xs[off - W] + (double)xs[off + W]));
-      else
+      } else {
         Lu = lx_general<T, W, double>(xs, off, gx0 + lx, gy0 + ly, nx, ny, a.B, a.dihx, a.dihy);
+      }
       const double wv = Lu;
       a.w[oi[u]] = wv;
       ru += rv[u] * (double)zv[u];
@@ -508,6 +662,7 @@ struct CoarseArgs {
   int b0_double;
   T *x0;                   // global output: correction of level l0
   const T *pinv;           // dense pseudo-inverse of the coarsest level
+  const T *rho_c;          // variable coefficients: densities of levels l0.., packed at off[]
 };
 
 template <int DIM, typename T>
@@ -601,9 +756,17 @@ struct CSet {
   int c[2];             // LDS index of the cell, -1 when the slot is empty
   int nb[2][2 * DIM];   // LDS indices of the neighbours (-d, +d per direction)
   T idg[2];             // 1 / diagonal
+  T bt[2][2 * DIM];     // variable coefficients: beta / h_d^2 per neighbour (0 if missing)
 };
 
-template <int DIM, typename T>
+// beta / h_d^2 of the face between packed cells ia and ib of the coarse
+// levels (ib == zero_slot: no face).
+template <typename T>
+__device__ inline T c_face(const CoarseArgs<T> &a, int ia, int ib, int zero_slot, T ih2) {
+  return ib == zero_slot ? T(0) : ih2 * face_beta<T>(a.rho_c[ia], a.rho_c[ib]);
+}
+
+template <int DIM, typename T, bool VC = false>
 __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, int l, int color, int zero_slot,
                              CSet<DIM, T> &s) {
   const int *n = a.n[l];
@@ -628,13 +791,23 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, int l, int 
       code |= ((lo || per) && (hi || per)) ? (1 << d) : 0;
     }
     s.c[q] = off + c;
-    s.idg[q] = idg_s[8 * (l - a.l0) + code];
+    if constexpr (VC) {
+      T dg = T(0);
+#pragma unroll
+      for (int m = 0; m < 2 * DIM; ++m) {
+        s.bt[q][m] = c_face<T>(a, off + c, s.nb[q][m], zero_slot, a.ih2[l].v[m >> 1]);
+        dg += s.bt[q][m];
+      }
+      s.idg[q] = T(1) / dg;
+    } else {
+      s.idg[q] = idg_s[8 * (l - a.l0) + code];
+    }
   }
 }
 
 // One red/black half-sweep over a cell set: x = (b + sum of neighbours) /
 // diag, all LDS reads of the thread issued before the arithmetic.
-template <int DIM, typename T>
+template <int DIM, typename T, bool VC = false>
 __device__ inline void c_sweep(T *xs, const T *bs, const CSet<DIM, T> &s, const T ih2[3], bool zero_init) {
   T v[2][2 * DIM], bv[2];
 #pragma unroll
@@ -648,15 +821,20 @@ __device__ inline void c_sweep(T *xs, const T *bs, const CSet<DIM, T> &s, const 
   for (int q = 0; q < 2; ++q) {
     if (s.c[q] < 0) continue;
     T nbs = T(0);
+    if constexpr (VC) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) nbs += ih2[d] * (v[q][2 * d] + v[q][2 * d + 1]);
+      for (int m = 0; m < 2 * DIM; ++m) nbs += s.bt[q][m] * v[q][m];
+    } else {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) nbs += ih2[d] * (v[q][2 * d] + v[q][2 * d + 1]);
+    }
     if (zero_init) nbs = T(0);
     xs[s.c[q]] = (bv[q] + nbs) * s.idg[q];
   }
   __syncthreads();
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool VC = false>
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, const SolverScalars *sc) {
   __shared__ T xs[kCoarseLds + 1];     // all coarse levels, then a zero slot
   __shared__ T bs[kCoarseLds];
@@ -692,11 +870,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
   for (int l = a.l0; l < last; ++l) {
     {
       CSet<DIM, T> red, black;
-      c_set<DIM, T>(a, idg_s, l, 0, zero_slot, red);
-      c_set<DIM, T>(a, idg_s, l, 1, zero_slot, black);
+      c_set<DIM, T, VC>(a, idg_s, l, 0, zero_slot, red);
+      c_set<DIM, T, VC>(a, idg_s, l, 1, zero_slot, black);
       for (int s = 0; s < a.nu; ++s) {
-        c_sweep<DIM, T>(xs, bs, red, a.ih2[l].v, s == 0);
-        c_sweep<DIM, T>(xs, bs, black, a.ih2[l].v, false);
+        c_sweep<DIM, T, VC>(xs, bs, red, a.ih2[l].v, s == 0);
+        c_sweep<DIM, T, VC>(xs, bs, black, a.ih2[l].v, false);
       }
     }
     const int *nf = a.n[l], *nc = a.n[l + 1];
@@ -713,12 +891,32 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
           for (int dx = 0; dx < 2; ++dx) {
             const int i = 2 * I + dx, j = 2 * J + dy, k = DIM == 3 ? 2 * K + dz : 0;
             const int c = i + nf[0] * (j + nf[1] * k);
-            int code;
-            const T nbs = c_nbs<DIM, T>(nf, a.B, a.ih2[l].v, x, i, j, k, c, code);
-            T dg = T(0);
+            if constexpr (VC) {
+              // same neighbour rules and coefficients as c_set
+              const int q[3] = {i, j, k};
+              const int st[3] = {1, nf[0], nf[0] * nf[1]};
+              const int off = a.off[l];
+              T nbs = T(0), dg = T(0);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) dg += a.ih2[l].v[d] * ((code >> d) & 1 ? T(2) : T(1));
-            acc += b[c] - (dg * x[c] - nbs);
+              for (int d = 0; d < DIM; ++d) {
+                const bool per = a.B.periodic[d] != 0;
+                const bool lo = q[d] > 0, hi = q[d] + 1 < nf[d];
+                const int im = lo ? off + c - st[d] : (per ? off + c + (nf[d] - 1) * st[d] : zero_slot);
+                const int ip = hi ? off + c + st[d] : (per ? off + c - (nf[d] - 1) * st[d] : zero_slot);
+                const T bm = c_face<T>(a, off + c, im, zero_slot, a.ih2[l].v[d]);
+                const T bp = c_face<T>(a, off + c, ip, zero_slot, a.ih2[l].v[d]);
+                nbs += bm * xs[im] + bp * xs[ip];
+                dg += bm + bp;
+              }
+              acc += b[c] - (dg * x[c] - nbs);
+            } else {
+              int code;
+              const T nbs = c_nbs<DIM, T>(nf, a.B, a.ih2[l].v, x, i, j, k, c, code);
+              T dg = T(0);
+#pragma unroll
+              for (int d = 0; d < DIM; ++d) dg += a.ih2[l].v[d] * ((code >> d) & 1 ? T(2) : T(1));
+              acc += b[c] - (dg * x[c] - nbs);
+            }
           }
       bs[a.off[l + 1] + t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
     }
@@ -773,11 +971,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     }
     __syncthreads();
     CSet<DIM, T> red, black;
-    c_set<DIM, T>(a, idg_s, l, 0, zero_slot, red);
-    c_set<DIM, T>(a, idg_s, l, 1, zero_slot, black);
+    c_set<DIM, T, VC>(a, idg_s, l, 0, zero_slot, red);
+    c_set<DIM, T, VC>(a, idg_s, l, 1, zero_slot, black);
     for (int s = 0; s < a.nu; ++s) {
-      c_sweep<DIM, T>(xs, bs, black, a.ih2[l].v, false);
-      c_sweep<DIM, T>(xs, bs, red, a.ih2[l].v, false);
+      c_sweep<DIM, T, VC>(xs, bs, black, a.ih2[l].v, false);
+      c_sweep<DIM, T, VC>(xs, bs, red, a.ih2[l].v, false);
     }
   }
   {

@@ -29,6 +29,7 @@
 // run the z-marching equivalent (lm_mg3d.h). Levels of at most kCoarseCells
 // cells are solved by one block in LDS; the remaining levels run one kernel
 // per half-sweep.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -212,6 +213,45 @@ struct Ih2 {
   T v[3];
 };
 
+// Face coefficient of the variable-coefficient operator: beta = 1/rho_f
+// with rho_f = (rho_a + rho_b)/2 the two-point face average (Eq 3.20,
+// n = 1). Symmetric in its arguments bit for bit.
+template <typename T>
+__device__ inline T face_beta(T ra, T rb) {
+  return T(2) / (ra + rb);
+}
+
+// Neighbour sum and diagonal of L = -A_beta at one cell, beta = 1/rho_f
+// (same neighbour rules as op_parts).
+template <int DIM, typename A, typename T, typename R>
+__device__ inline void op_parts_vc(const Lay &L, const Bnd &B, const A ih2[3], const R *rho, const T *x, int i, int j,
+                                   int k, long c, A &nbsum, A &diag) {
+#pragma clang fp contract(off)
+  nbsum = A(0);
+  diag = A(0);
+  const int q[3] = {i, j, k};
+  const A rc = (A)rho[c];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    A s = A(0), sb = A(0);
+    const long lo = (q[d] > 0) ? c - L.s[d] : (B.periodic[d] ? c + (long)(L.n[d] - 1) * L.s[d] : -1);
+    const long hi = (q[d] + 1 < L.n[d]) ? c + L.s[d] : (B.periodic[d] ? c - (long)(L.n[d] - 1) * L.s[d] : -1);
+    if (lo >= 0) {
+      const A bt = face_beta<A>(rc, (A)rho[lo]);
+      s += bt * (A)x[lo];
+      sb += bt;
+    }
+    if (hi >= 0) {
+      const A bt = face_beta<A>(rc, (A)rho[hi]);
+      s += bt * (A)x[hi];
+      sb += bt;
+    }
+    nbsum += ih2[d] * s;
+    diag += ih2[d] * sb;
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // CG kernels (FP64 vectors on the fine layout, grid-stride over cells)
 // ---------------------------------------------------------------------------
@@ -231,6 +271,7 @@ struct CGArgs {
   double tol2;
   int k;
   int flexible;
+  const double *rho;      // density of beta = 1/rho_f; NULL: beta = 1
 };
 
 // x = x0; r_0 = c - L x0 with c = -(b - mean(b) - outflow shift); ||c||^2 partials.
@@ -257,7 +298,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
     double Lx = 0.0;
     if (a.x0) {
       double nbs, dg;
-      op_parts<DIM, double, double>(a.L, a.B, a.ih2, a.x0, i, j, k, c, nbs, dg);
+      if (a.rho)
+        op_parts_vc<DIM, double, double, double>(a.L, a.B, a.ih2, a.rho, a.x0, i, j, k, c, nbs, dg);
+      else
+        op_parts<DIM, double, double>(a.L, a.B, a.ih2, a.x0, i, j, k, c, nbs, dg);
       Lx = dg * xv - nbs;
     }
     a.rnew[c] = cv - Lx;
@@ -306,21 +350,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_pq(CGArgs a, int np_cc) {
     const int q[3] = {i, j, kk};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      double s = 0.0;
-      int cnt = 0;
+      double s = 0.0, sb = 0.0;
       const long lo = (q[d] > 0) ? c - a.L.s[d] : (a.B.periodic[d] ? c + (long)(a.L.n[d] - 1) * a.L.s[d] : -1);
       const long hi = (q[d] + 1 < a.L.n[d]) ? c + a.L.s[d]
                                             : (a.B.periodic[d] ? c - (long)(a.L.n[d] - 1) * a.L.s[d] : -1);
       if (lo >= 0) {
-        s += pv(lo);
-        ++cnt;
+        const double bt = a.rho ? face_beta<double>(a.rho[c], a.rho[lo]) : 1.0;
+        s += bt * pv(lo);
+        sb += bt;
       }
       if (hi >= 0) {
-        s += pv(hi);
-        ++cnt;
+        const double bt = a.rho ? face_beta<double>(a.rho[c], a.rho[hi]) : 1.0;
+        s += bt * pv(hi);
+        sb += bt;
       }
       nbs += a.ih2[d] * s;
-      dg += a.ih2[d] * (double)cnt;
+      dg += a.ih2[d] * sb;
     }
     const double qv = dg * pc - nbs;
     a.pnew[c] = pc;
@@ -435,7 +480,10 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
     if (!tile_cell(a.L, tile, i, j, k)) continue;
     const long c = a.L.at(i, j, k);
     double nbs, dg;
-    op_parts<DIM, double, TZ>(a.L, a.B, a.ih2, u, i, j, k, c, nbs, dg);
+    if (a.rho)
+      op_parts_vc<DIM, double, TZ, double>(a.L, a.B, a.ih2, a.rho, u, i, j, k, c, nbs, dg);
+    else
+      op_parts<DIM, double, TZ>(a.L, a.B, a.ih2, u, i, j, k, c, nbs, dg);
     const double uc = (double)u[c];
     const double wv = dg * uc - nbs;
     const double rv = a.rnew[c];
@@ -482,13 +530,16 @@ __global__ void __launch_bounds__(kBlock) k_fin_mean_x(const double *part, int n
 // of the pre-smoother): red cells take b/diag without reading x.
 template <int DIM, typename TX, typename TB>
 __global__ void __launch_bounds__(kBlock) k_mg_smooth(Lay L, Bnd B, Ih2<TX> ih2, TX *x, const TB *b, int color,
-                                                      int zero_init, const SolverScalars *sc) {
+                                                      int zero_init, const SolverScalars *sc, const TX *rho) {
   if (sc->done) return;
   CellPos p;
   if (!cell_of_thread(L, p)) return;
   if (((p.i + p.j + p.k) & 1) != color) return;
   TX nbs, dg;
-  op_parts<DIM, TX, TX>(L, B, ih2.v, x, p.i, p.j, p.k, p.c, nbs, dg);
+  if (rho)
+    op_parts_vc<DIM, TX, TX, TX>(L, B, ih2.v, rho, x, p.i, p.j, p.k, p.c, nbs, dg);
+  else
+    op_parts<DIM, TX, TX>(L, B, ih2.v, x, p.i, p.j, p.k, p.c, nbs, dg);
   if (zero_init && color == 0) nbs = TX(0);
   x[p.c] = ((TX)b[p.c] + nbs) / dg;
 }
@@ -496,7 +547,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth(Lay L, Bnd B, Ih2<TX> ih2,
 // Coarse right-hand side: average over the 2^DIM children of b - L x.
 template <int DIM, typename TX, typename TB>
 __global__ void __launch_bounds__(kBlock) k_mg_restrict(Lay Lf, Lay Lc, Bnd B, Ih2<TX> ih2, const TX *x,
-                                                        const TB *b, TX *bc, const SolverScalars *sc) {
+                                                        const TB *b, TX *bc, const SolverScalars *sc, const TX *rho) {
   if (sc->done) return;
   CellPos p;
   if (!cell_of_thread(Lc, p)) return;
@@ -510,7 +561,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_restrict(Lay Lf, Lay Lc, Bnd B, I
         const int i = 2 * p.i + dx, j = 2 * p.j + dy, k = DIM == 3 ? 2 * p.k + dz : 0;
         const long c = Lf.at(i, j, k);
         TX nbs, dg;
-        op_parts<DIM, TX, TX>(Lf, B, ih2.v, x, i, j, k, c, nbs, dg);
+        if (rho)
+          op_parts_vc<DIM, TX, TX, TX>(Lf, B, ih2.v, rho, x, i, j, k, c, nbs, dg);
+        else
+          op_parts<DIM, TX, TX>(Lf, B, ih2.v, x, i, j, k, c, nbs, dg);
         acc += ((TX)b[c] - (dg * x[c] - nbs));
       }
   bc[p.c] = acc * (DIM == 3 ? TX(0.125) : TX(0.25));
@@ -526,13 +580,113 @@ __global__ void __launch_bounds__(kBlock) k_mg_prolong(Lay Lf, Lay Lc, TX *xf, c
   xf[p.c] += xc[Lc.at(p.i >> 1, p.j >> 1, DIM == 3 ? (p.k >> 1) : 0)];
 }
 
+// ---------------------------------------------------------------------------
+// Variable-coefficient set-up (once per solve with beta = 1/rho_f)
+// ---------------------------------------------------------------------------
+
+// Flags a density that is not positive and finite; converts the finest
+// density to the multigrid precision (rt NULL: used as is).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_vc_rho0(Lay L, const double *r64, T *rt, SolverScalars *sc) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const double r = r64[p.c];
+  if (!(r > 0.0) || !isfinite(r)) sc->rho_bad = 1;
+  if (rt) rt[p.c] = (T)r;
+}
+
+// Density of the next coarser level: mean of the 2^DIM children.
+template <int DIM, typename TS, typename TD>
+__global__ void __launch_bounds__(kBlock) k_vc_rho_down(Lay Lf, Lay Lc, const TS *rf, TD *rc) {
+  CellPos p;
+  if (!cell_of_thread(Lc, p)) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx)
+        acc += (double)rf[Lf.at(2 * p.i + dx, 2 * p.j + dy, DIM == 3 ? 2 * p.k + dz : 0)];
+  rc[p.c] = (TD)(acc * (DIM == 3 ? 0.125 : 0.25));
+}
+
+// Density of a coarse-kernel level packed x fastest (the kernel's LDS order).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_vc_pack(Lay L, const T *r, T *out) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  out[p.i + (long)L.n[0] * (p.j + (long)L.n[1] * p.k)] = r[p.c];
+}
+
 }  // namespace lm
 
 #include "lm_mg_kernels.h"
 #include "lm_mg3d.h"
 
 namespace lm {
+
+// Pseudo-inverse of the coarsest variable-coefficient operator,
+// (L + J/N)^{-1} - J/N with J the all-ones matrix: L + J/N is symmetric
+// positive definite (L is singular with the constants as null space), so
+// Gauss-Jordan elimination without pivoting inverts it in place in LDS.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kCoarseThreads) k_vc_pinv(CoarseArgs<T> a, T *pinv) {
+  __shared__ double M[kVcCoarsest * kVcCoarsest];
+  __shared__ double rk[kVcCoarsest], ck[kVcCoarsest];
+  const int last = a.nlev - 1;
+  const int *n = a.n[last];
+  const int N = n[0] * n[1] * n[2];
+  const T *rho = a.rho_c + a.off[last];
+  const int t = threadIdx.x;
+  const double jn = 1.0 / (double)N;
+  for (int e = t; e < N * N; e += blockDim.x) M[e] = jn;
+  __syncthreads();
+  if (t < N) {
+    int i, j, k;
+    c_decode<DIM, T>(n, t, i, j, k);
+    const int q[3] = {i, j, k};
+    const int st[3] = {1, n[0], n[0] * n[1]};
+    const double rc = (double)rho[t];
+    for (int d = 0; d < DIM; ++d) {
+      const bool per = a.B.periodic[d] != 0;
+      const double ih2 = (double)a.ih2[last].v[d];
+      for (int side = 0; side < 2; ++side) {
+        const bool in = side == 0 ? q[d] > 0 : q[d] + 1 < n[d];
+        if (!in && !per) continue;
+        const int m = side == 0 ? (in ? t - st[d] : t + (n[d] - 1) * st[d]) : (in ? t + st[d] : t - (n[d] - 1) * st[d]);
+        const double w = ih2 * face_beta<double>(rc, (double)rho[m]);
+        M[t * N + t] += w;
+        M[t * N + m] -= w;
+      }
+    }
+  }
+  __syncthreads();
+  for (int kk = 0; kk < N; ++kk) {
+    if (t < N) {
+      rk[t] = M[kk * N + t];
+      ck[t] = M[t * N + kk];
+    }
+    __syncthreads();
+    const double ip = 1.0 / rk[kk];
+    for (int e = t; e < N * N; e += blockDim.x) {
+      const int i = e / N, j = e - (e / N) * N;
+      double v;
+      if (i == kk)
+        v = (j == kk) ? ip : rk[j] * ip;
+      else if (j == kk)
+        v = -ck[i] * ip;
+      else
+        v = M[e] - ck[i] * rk[j] * ip;
+      M[e] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < N * N; e += blockDim.x) pinv[e] = (T)(M[e] - jn);
+}
+
 static_assert(kCoarseCells <= (long)kCoarseLoads * kCoarseThreads, "coarse loads per thread");
+static_assert(kVcCoarsest <= kCoarseThreads, "one thread per coarsest cell");
 }  // namespace lm
 
 namespace lm {
@@ -541,8 +695,8 @@ namespace lm {
 // Host side
 // ---------------------------------------------------------------------------
 
-static int tile_x(const PoissonWS &ws, int l) { return ws.tx[l]; }
-static int tile_y(const PoissonWS &ws, int l) { return ws.ty[l]; }
+static int tile_x(const PoissonWS &ws, int l) { return ws.vc ? ws.vtx[l] : ws.tx[l]; }
+static int tile_y(const PoissonWS &ws, int l) { return ws.vc ? ws.vty[l] : ws.ty[l]; }
 
 // Tile of 2D level l (< lc), or 0 x 0 when no tile divides it.
 static void choose_tile(PoissonWS &ws, int l) {
@@ -554,6 +708,22 @@ static void choose_tile(PoissonWS &ws, int l) {
     if (L.n[0] % cand[q][0] == 0 && L.n[1] % cand[q][1] == 0) {
       ws.tx[l] = cand[q][0];
       ws.ty[l] = cand[q][1];
+      return;
+    }
+}
+
+// Tile of 2D level l (< lc) for the variable-coefficient kernels, whose
+// frames carry three more LDS arrays (face coefficients, 1/diagonal): the
+// small tiles only.
+static void choose_tile_vc(PoissonWS &ws, int l) {
+  const Lay &L = ws.lev[l].lay;
+  ws.vtx[l] = ws.vty[l] = 0;
+  if (!ws.vc_cap || L.ndim != 2 || ws.nu < 1 || ws.nu > 3 || l >= ws.lc) return;
+  const int cand[2][2] = {{TXS, TYS}, {16, 16}};
+  for (int q = 0; q < 2; ++q)
+    if (L.n[0] % cand[q][0] == 0 && L.n[1] % cand[q][1] == 0) {
+      ws.vtx[l] = cand[q][0];
+      ws.vty[l] = cand[q][1];
       return;
     }
 }
@@ -573,18 +743,20 @@ static long blocks3d(const Lay &L) { return (long)(L.n[0] / TX3) * (L.n[1] / TY3
 // Level l runs the fused 3D kernels (fully periodic grids).
 static bool fused3d(const PoissonWS &ws, int l) {
   const Lay &L = ws.lev[l].lay;
-  return L.ndim == 3 && ws.bnd.all_periodic && ws.nu >= 1 && ws.nu <= 3 && l < ws.lc &&
+  return !ws.vc && L.ndim == 3 && ws.bnd.all_periodic && ws.nu >= 1 && ws.nu <= 3 && l < ws.lc &&
          L.ncells() >= kFused3DMinCells && L.n[0] % TX3 == 0 && L.n[1] % TY3 == 0 && tz3_of(L) > 0;
 }
 
-static bool fused_level(const PoissonWS &ws, int l) { return ws.tx[l] > 0; }
+static bool fused_level(const PoissonWS &ws, int l) { return tile_x(ws, l) > 0; }
 
 bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, const double h[3], int mixed, int flexible,
-                  int nu, std::string *err) {
+                  int nu, int vc_cap, std::string *err) {
   ws.lay = fine;
   ws.bnd = B;
   ws.mixed = mixed;
   ws.nu = nu;
+  ws.vc_cap = vc_cap;
+  ws.vc = 0;
   const int ndim = fine.ndim;
   const int eb = mixed ? 4 : 8;
   int n[3] = {fine.n[0], fine.n[1], fine.n[2]};
@@ -618,6 +790,10 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
     if (err) *err = "coarse grid too large for the one-block coarse solver";
     return false;
   }
+  if (vc_cap && ncoarsest > kVcCoarsest) {
+    if (err) *err = "the variable-coefficient solve needs a grid that coarsens to <= 128 cells";
+    return false;
+  }
   const size_t fbytes = (size_t)fine.total * 8;
   ws.x = (double *)cv.take(fbytes);
   ws.r[0] = (double *)cv.take(fbytes);
@@ -642,13 +818,27 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
     ws.lev[l].b = cv.take(lb);
   }
   ws.pinv = cv.take((size_t)ncoarsest * ncoarsest * eb);
+  ws.rho64 = nullptr;
+  ws.rho_c = ws.pinv_vc = nullptr;
+  for (int l = 0; l < kMaxLev; ++l) ws.rho[l] = nullptr;
+  if (vc_cap) {
+    ws.rho64 = (double *)cv.take(fbytes);
+    ws.rho[0] = mixed ? cv.take((size_t)fine.total * eb) : (void *)ws.rho64;
+    for (int l = 1; l < nl; ++l) ws.rho[l] = cv.take((size_t)ws.lev[l].lay.total * eb);
+    ws.rho_c = cv.take((size_t)(kCoarseLds + 1) * eb);
+    ws.pinv_vc = cv.take((size_t)ncoarsest * ncoarsest * eb);
+  }
   for (int l = 0; l < kMaxLev; ++l) {
     ws.tx[l] = ws.ty[l] = 0;
-    if (l < nl) choose_tile(ws, l);
+    ws.vtx[l] = ws.vty[l] = 0;
+    if (l < nl) {
+      choose_tile(ws, l);
+      choose_tile_vc(ws, l);
+    }
   }
-  const long ntile0 = fused_level(ws, 0) ? (long)(fine.n[0] / ws.tx[0]) * (fine.n[1] / ws.ty[0]) + 1 : 0;
   long npmax = kRedBlocks;
-  if (ntile0 > npmax) npmax = ntile0;
+  if (ws.tx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.tx[0]) * (fine.n[1] / ws.ty[0]) + 1);
+  if (ws.vtx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.vtx[0]) * (fine.n[1] / ws.vty[0]) + 1);
   if (fused3d(ws, 0) && blocks3d(fine) > npmax) npmax = blocks3d(fine);
   ws.np_max = npmax;
   ws.part_cc = (double *)cv.take((size_t)npmax * 8);
@@ -813,11 +1003,37 @@ static void launch_nu_t(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool ext
   else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 0, TXT, TYT>), g, dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_mg_up2d<T, 3, 0, TXT, TYT>), g, dim3(kBlock), 0, st, a);
 }
-// Level 0 runs the large tile, coarser levels the small one.
+template <typename T, int TXT, int TYT>
+static void launch_nu_vc(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
+  if (nu == 1) hipLaunchKernelGGL((k_mg_down2d<T, 1, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_down2d<T, 2, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_down2d<T, 3, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+}
+template <typename T, int TXT, int TYT>
+static void launch_nu_vc(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool extra) {
+  if (extra) {
+    if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 1, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+    else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 1, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up2d<T, 3, 1, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+    return;
+  }
+  if (nu == 1) hipLaunchKernelGGL((k_mg_up2d<T, 1, 0, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+  else if (nu == 2) hipLaunchKernelGGL((k_mg_up2d<T, 2, 0, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_mg_up2d<T, 3, 0, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+}
+// Level 0 runs the large tile, coarser levels the small one; the
+// variable-coefficient kernels run the small tiles only.
 template <typename T>
 static void launch_nu(const PoissonWS &ws, int l, int nu, Down2DArgs<T> &a, hipStream_t st) {
   const int tx = tile_x(ws, l), ty = tile_y(ws, l);
   const dim3 g((a.Lf.n[0] / tx) * (a.Lf.n[1] / ty));
+  if (ws.vc) {
+    if (tx == TXS && ty == TYS)
+      launch_nu_vc<T, TXS, TYS>(nu, a, g, st);
+    else
+      launch_nu_vc<T, 16, 16>(nu, a, g, st);
+    return;
+  }
   if (tx == TX && ty == TY)
     launch_nu_t<T, TX, TY>(nu, a, g, st);
   else if (tx == TXS && ty == TYS)
@@ -829,6 +1045,13 @@ template <typename T>
 static void launch_nu(const PoissonWS &ws, int l, int nu, Up2DArgs<T> &a, hipStream_t st, bool extra) {
   const int tx = tile_x(ws, l), ty = tile_y(ws, l);
   const dim3 g((a.Lf.n[0] / tx) * (a.Lf.n[1] / ty));
+  if (ws.vc) {
+    if (tx == TXS && ty == TYS)
+      launch_nu_vc<T, TXS, TYS>(nu, a, g, st, extra);
+    else
+      launch_nu_vc<T, 16, 16>(nu, a, g, st, extra);
+    return;
+  }
   if (tx == TX && ty == TY)
     launch_nu_t<T, TX, TY>(nu, a, g, st, extra);
   else if (tx == TXS && ty == TYS)
@@ -870,9 +1093,10 @@ static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xp
   a.p_io = ws.p[0];
   a.part_g = ws.part_rz;
   a.part_cc = ws.part_cc;
-  a.np_g = fused_level(ws, 0) ? (ws.lay.n[0] / ws.tx[0]) * (ws.lay.n[1] / ws.ty[0]) : 0;
+  a.np_g = fused_level(ws, 0) ? (ws.lay.n[0] / tile_x(ws, 0)) * (ws.lay.n[1] / tile_y(ws, 0)) : 0;
   a.np_cc = kRedBlocks;
   a.tol2 = ws.tol2;
+  a.rho = ws.vc ? (const T *)ws.rho[l] : nullptr;
   return a;
 }
 
@@ -900,6 +1124,8 @@ static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, con
   a.sc = ws.sc;
   a.tiles_x = L.n[0] / tile_x(ws, l);
   a.w = ws.w;
+  a.rho = ws.vc ? (const T *)ws.rho[l] : nullptr;
+  a.rho64 = ws.vc ? ws.rho64 : nullptr;
   return a;
 }
 
@@ -937,7 +1163,8 @@ static CoarseArgs<T> coarse_args(PoissonWS &ws, void *z, const double *r) {
   ca.b0 = ws.lc == 0 ? (const void *)r : ws.lev[ws.lc].b;
   ca.b0_double = (ws.lc == 0);
   ca.x0 = ws.lc == 0 ? (T *)z : (T *)ws.lev[ws.lc].x;
-  ca.pinv = (const T *)ws.pinv;
+  ca.pinv = (const T *)(ws.vc ? ws.pinv_vc : ws.pinv);
+  ca.rho_c = ws.vc ? (const T *)ws.rho_c : nullptr;
   return ca;
 }
 
@@ -976,25 +1203,29 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       }
     } else {
       dim3 g = grid_for(L);
+      const T *rl = ws.vc ? (const T *)ws.rho[l] : nullptr;
       for (int s = 0; s < nu; ++s) {
         for (int color = 0; color < 2; ++color) {
           if (l == 0)
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin, r, color,
-                               s == 0 && color == 0, sc);
+                               s == 0 && color == 0, sc, rl);
           else
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, T>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin,
-                               (const T *)ws.lev[l].b, color, s == 0 && color == 0, sc);
+                               (const T *)ws.lev[l].b, color, s == 0 && color == 0, sc, rl);
         }
       }
       if (l == 0)
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(Lc), bb, 0, st, L, Lc, B, ih2_of<T>(ws, l),
-                           xin, r, (T *)ws.lev[l + 1].b, sc);
+                           xin, r, (T *)ws.lev[l + 1].b, sc, rl);
       else
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, T>), grid_for(Lc), bb, 0, st, L, Lc, B, ih2_of<T>(ws, l), xin,
-                           (const T *)ws.lev[l].b, (T *)ws.lev[l + 1].b, sc);
+                           (const T *)ws.lev[l].b, (T *)ws.lev[l + 1].b, sc, rl);
     }
   }
-  hipLaunchKernelGGL((k_mg_coarse<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st, coarse_args<T>(ws, z, r), sc);
+  if (ws.vc)
+    hipLaunchKernelGGL((k_mg_coarse<DIM, T, true>), dim3(1), dim3(kCoarseThreads), 0, st, coarse_args<T>(ws, z, r), sc);
+  else
+    hipLaunchKernelGGL((k_mg_coarse<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st, coarse_args<T>(ws, z, r), sc);
   for (int l = ws.lc - 1; l >= 0; --l) {
     const Lay &L = ws.lev[l].lay, &Lc = ws.lev[l + 1].lay;
     T *xin = lev_xin<T>(ws, l, z);
@@ -1016,16 +1247,17 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       launch_3d<T>(nu, false, a, st, extra);
     } else {
       dim3 g = grid_for(L);
+      const T *rl = ws.vc ? (const T *)ws.rho[l] : nullptr;
       hipLaunchKernelGGL((k_mg_prolong<DIM, T>), g, bb, 0, st, L, Lc, xin, xc, sc);
       for (int s = 0; s < nu; ++s) {
         for (int cc = 0; cc < 2; ++cc) {
           const int color = 1 - cc;
           if (l == 0)
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin, r, color, 0,
-                               sc);
+                               sc, rl);
           else
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, T>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin,
-                               (const T *)ws.lev[l].b, color, 0, sc);
+                               (const T *)ws.lev[l].b, color, 0, sc, rl);
         }
       }
     }
@@ -1044,7 +1276,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
 }
 
 static int np_rz_of(const PoissonWS &ws) {
-  if (fused_level(ws, 0)) return (ws.lay.n[0] / ws.tx[0]) * (ws.lay.n[1] / ws.ty[0]);
+  if (fused_level(ws, 0)) return (ws.lay.n[0] / tile_x(ws, 0)) * (ws.lay.n[1] / tile_y(ws, 0));
   if (w_in_up3d(ws)) return (int)blocks3d(ws.lay);
   return kRedBlocks;
 }
@@ -1111,6 +1343,7 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   ws.tol2 = a.tol2;
   a.k = 0;
   a.flexible = !ws.cgcg;
+  a.rho = ws.vc ? ws.rho64 : nullptr;
   ws.tsolve0 = ws.tcount;
   hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
   if (e != hipSuccess) return e;
@@ -1155,6 +1388,43 @@ hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const d
 }
 
 // ---------------------------------------------------------------------------
+// Variable-coefficient set-up
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+static hipError_t set_beta_dim(hipStream_t st, PoissonWS &ws) {
+  const dim3 bb(kBX, kBY);
+  const bool cast = sizeof(T) != 8;
+  hipLaunchKernelGGL((k_vc_rho0<DIM, T>), grid_for(ws.lay), bb, 0, st, ws.lay, (const double *)ws.rho64,
+                     cast ? (T *)ws.rho[0] : (T *)nullptr, ws.sc);
+  for (int l = 0; l + 1 < ws.nlev; ++l) {
+    const Lay &Lf = ws.lev[l].lay, &Lc = ws.lev[l + 1].lay;
+    if (l == 0)
+      hipLaunchKernelGGL((k_vc_rho_down<DIM, double, T>), grid_for(Lc), bb, 0, st, Lf, Lc,
+                         (const double *)ws.rho64, (T *)ws.rho[1]);
+    else
+      hipLaunchKernelGGL((k_vc_rho_down<DIM, T, T>), grid_for(Lc), bb, 0, st, Lf, Lc, (const T *)ws.rho[l],
+                         (T *)ws.rho[l + 1]);
+  }
+  const int vc = ws.vc;
+  ws.vc = 1;
+  CoarseArgs<T> ca = coarse_args<T>(ws, ws.z[0], ws.r[0]);
+  ws.vc = vc;
+  for (int l = ws.lc; l < ws.nlev; ++l)
+    hipLaunchKernelGGL((k_vc_pack<DIM, T>), grid_for(ws.lev[l].lay), bb, 0, st, ws.lev[l].lay,
+                       (const T *)ws.rho[l], (T *)ws.rho_c + ca.off[l]);
+  hipLaunchKernelGGL((k_vc_pinv<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st, ca, (T *)ws.pinv_vc);
+  return hipGetLastError();
+}
+
+hipError_t poisson_set_beta(hipStream_t st, PoissonWS &ws) {
+  if (!ws.vc_cap) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(&ws.sc->rho_bad, 0, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  if (ws.lay.ndim == 3) return ws.mixed ? set_beta_dim<3, float>(st, ws) : set_beta_dim<3, double>(st, ws);
+  return ws.mixed ? set_beta_dim<2, float>(st, ws) : set_beta_dim<2, double>(st, ws);
+}
+
+// ---------------------------------------------------------------------------
 // Timing hook: one launch of a kernel class on scratch arrays
 // ---------------------------------------------------------------------------
 template <int DIM, typename T>
@@ -1185,6 +1455,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
   a.tol2 = 0.0;
   a.k = 2;
   a.flexible = 0;
+  a.rho = nullptr;
   switch (which) {
     case 0: {  // finest-level down kernel (fused) or one half-sweep
       if (fused_level(ws, 0)) {
@@ -1193,7 +1464,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
         launch_nu<T>(ws, 0, ws.nu, d, st);
       } else {
         hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, ws.lay, ws.bnd,
-                           ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc);
+                           ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc, (const T *)nullptr);
       }
       break;
     }
@@ -1207,7 +1478,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       } else {
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(ws.lev[1].lay), dim3(kBX, kBY), 0, st,
                            ws.lay, ws.lev[1].lay, ws.bnd, ih2_of<T>(ws, 0), (const T *)ws.z[0],
-                           (const double *)ws.r[0], (T *)ws.lev[1].b, ws.sc);
+                           (const double *)ws.r[0], (T *)ws.lev[1].b, ws.sc, (const T *)nullptr);
       }
       break;
     }

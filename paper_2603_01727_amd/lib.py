@@ -19,6 +19,7 @@ SIDE = {"periodic": 0, "slip": 1, "noslip": 2, "inflow": 3, "outflow": 4}
 LM_FP64, LM_MIXED, LM_MIXED_FLEXIBLE = 0, 1, 2
 PRECISION = {"fp64": LM_FP64, "mixed": LM_MIXED, "mixed-flexible": LM_MIXED_FLEXIBLE}
 LM_HOST, LM_DEVICE = 0, 1
+LM_BETA_ONE, LM_BETA_INV_RHO = 0, 1
 
 
 class lm_grid(C.Structure):
@@ -32,7 +33,7 @@ class lm_params(C.Structure):
                 ("Le_F", C.c_double), ("Le_O", C.c_double),
                 ("Da_ib", C.c_double), ("p0", C.c_double), ("dt", C.c_double), ("cfl", C.c_double),
                 ("precision", C.c_int), ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int),
-                ("mg_nu", C.c_int), ("with_ib", C.c_int), ("with_adjoint", C.c_int)]
+                ("mg_nu", C.c_int), ("with_ib", C.c_int), ("with_adjoint", C.c_int), ("poisson_beta", C.c_int)]
 
 
 class lm_fields(C.Structure):
@@ -62,7 +63,7 @@ class lm_adjoint(C.Structure):
 
 
 class lm_project_args(C.Structure):
-    _fields_ = [("b", C.c_void_p), ("P", C.c_void_p), ("mem", C.c_int), ("rtol", C.c_double),
+    _fields_ = [("b", C.c_void_p), ("rho", C.c_void_p), ("P", C.c_void_p), ("mem", C.c_int), ("rtol", C.c_double),
                 ("iters", C.c_int), ("relres", C.c_double), ("mean_b", C.c_double)]
 
 

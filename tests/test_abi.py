@@ -95,3 +95,25 @@ def test_degenerate_grids_and_params_rejected():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     g, p = _grid_params((4, 4))       # smallest grid: one level, solved by the dense pseudo-inverse
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+
+
+def test_variable_coefficient_reservation():
+    """poisson_beta = LM_BETA_INV_RHO reserves the per-level densities and
+    the coarsest inverse (more workspace), and needs a grid that coarsens
+    to <= 128 cells; other values are rejected."""
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b0, b1 = C.c_size_t(), C.c_size_t()
+    g, p = _grid_params((128, 96))
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b0)) == lib.LM_OK
+    p.poisson_beta = lib.LM_BETA_INV_RHO
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b1)) == lib.LM_OK
+    assert b1.value > b0.value + 128 * 96 * 8
+    g, p = _grid_params((100, 60))    # coarsens to 25 x 15 = 375 cells
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b0)) == lib.LM_OK
+    p.poisson_beta = lib.LM_BETA_INV_RHO
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b0)) == lib.LM_EUNSUPPORTED
+    assert "128" in L.lm_last_error(None).decode()
+    g, p = _grid_params((64, 64))
+    p.poisson_beta = 2
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b0)) == lib.LM_EINVAL

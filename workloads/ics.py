@@ -146,6 +146,19 @@ def fourier_temperature(n, L, rng, kmax, amp, m=32):
     return 1.0 + amp * fh
 
 
+def variable_coefficient_problem(n, L, seed, kmax=8, ratio=4.0, m=32):
+    """Inputs of a variable-coefficient Poisson solve div(grad P / rho) = b
+    shaped like the step's: a density field of random modes with
+    max/min = ratio (rho = 1/ratio + (1 - 1/ratio)(1 - fhat), fhat as in
+    fourier_temperature) and a right-hand side of random modes (values in
+    [0, 1], mean not removed). Draws: the density's modes, then b's."""
+    rng = np.random.default_rng(seed)
+    fh = fourier_temperature(n, L, rng, kmax, 1.0, m=m) - 1.0
+    rho = 1.0 / ratio + (1.0 - 1.0 / ratio) * (1.0 - fh)
+    b = fourier_temperature(n, L, rng, kmax, 1.0, m=m) - 1.0
+    return rho, b
+
+
 def solenoidal_velocity(n, L, rng, kmax, rms=0.1, m=32):
     """Divergence-free random velocity, scaled to (mean |v|^2)^(1/2) = rms.
 
