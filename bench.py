@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for HBM counter calibration)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 FP64-vs-mixed comparison")
+    ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
     return ap.parse_args()
 
 
@@ -136,6 +137,48 @@ def bench_3d(steps=10, warmup=3):
     return out
 
 
+def poisson_forms(n=1024, reps=10):
+    """The pressure solve alone at n^2 in its two forms: beta = 1 (the
+    step's operator) and beta = 1/rho_f (div(grad P / rho) = b), FP64 and
+    mixed, on a seeded random-mode density (ratio 4, |k| <= 8) and
+    right-hand side, Poisson rtol 1e-10, from a zero start. Device arrays;
+    per solve: wall time between device synchronisations, including the
+    variable-coefficient set-up (density copy, coarse densities, coarsest
+    inverse)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2603_01727_amd import Solver
+    from workloads import variable_coefficient_problem
+    L = (2 * math.pi, 2 * math.pi)
+    rho, b = variable_coefficient_problem((n, n), L, seed=2)
+    out = {"workload": f"pressure solve {n}x{n} periodic, random-mode density ratio 4 and right-hand side, "
+                       f"rtol 1e-10, zero start", "solves": reps}
+    for prec in ("fp64", "mixed"):
+        s = Solver((n, n), L, Re=100.0, dt=1e-3, precision=prec, poisson_rtol=1e-10, variable_coefficient=True)
+        bt = torch.tensor(b, device="cuda:0")
+        rt = torch.tensor(rho, device="cuda:0")
+        z = torch.zeros_like(bt)
+        res = {}
+        for form, kw in (("beta_one", {}), ("beta_inv_rho", {"rho": rt})):
+            for _ in range(3):
+                s.project(bt, **kw)
+            ts = []
+            for _ in range(reps):
+                s.project(z)    # zero right-hand side: P = 0, the next solve starts cold
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = s.project(bt, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[form] = dict(ms_per_solve=round(1e3 * float(np.median(ts)), 4), iters=info["iters"],
+                             relres=info["relres"])
+        res["inv_rho_over_one"] = round(res["beta_inv_rho"]["ms_per_solve"] / res["beta_one"]["ms_per_solve"], 3)
+        out[prec] = res
+        s.close()
+    return out
+
+
 def field_differences(s_a, s_b):
     import numpy as np
     fa = s_a.get(("rho", "v", "H", "T", "P"), device=False)
@@ -208,6 +251,7 @@ def main():
                                     speedup_vs_fp64=round(rfl["value"] / r64["value"], 3))
         del rfl
     three_d = None if a.no_3d else bench_3d()
+    forms = None if a.no_vc else poisson_forms(a.n)
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
         "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",
@@ -228,6 +272,7 @@ def main():
                    "poisson_iters_per_solve": r64["poisson_iters_per_solve"]},
         "mixed": mixed,
         "c4_3d": three_d,
+        "poisson_forms": forms,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

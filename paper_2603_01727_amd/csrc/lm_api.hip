@@ -571,11 +571,7 @@ lm_status lm_project(lm_ctx *c, lm_project_args *a) {
   const Lay &L = c->lay;
   if (a->rho) {
     if ((s = copy_in(c, a->rho, c->pws.rho64, -1, a->mem)) != LM_OK) return s;
-    HIPCHK(c, poisson_set_beta(c->st, c->pws));
-    int bad = 0;
-    HIPCHK(c, hipMemcpyAsync(&bad, &c->pws.sc->rho_bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    if (bad) return fail(c, LM_EINVAL, "rho must be positive and finite");
+    HIPCHK(c, poisson_set_beta(c->st, c->pws));  // an invalid density ends the solve at once
   }
   HIPCHK(c, launch_mean(c->st, L, c->b, c->pws.partials, c->pws.sc));
   int iters = 0, conv = 0;
@@ -586,6 +582,7 @@ lm_status lm_project(lm_ctx *c, lm_project_args *a) {
                                      &relres, &conv);
   c->pws.vc = 0;
   HIPCHK(c, e);
+  if (a->rho && c->pws.host_sc->rho_bad) return fail(c, LM_EINVAL, "rho must be positive and finite");
   a->iters = iters;
   a->relres = relres;
   a->mean_b = c->pws.host_sc->mean_b;

@@ -213,6 +213,7 @@ struct PoissonWS {
   void *rho[kMaxLev];      // density per level in MG precision (level 0 aliases rho64 in FP64)
   void *rho_c;             // densities of the coarse-kernel levels, packed as its LDS
   void *pinv_vc;           // pseudo-inverse of the coarsest variable-coefficient operator
+  void *cf[kMaxLev][3];    // tiled 2D levels: west-face and south-face beta, 1/diagonal of L
   hipEvent_t *tev;         // in-step timing of the finest down kernel: event pairs
   int *tk;                 // CG iteration of each timed launch; -1: not a full-work launch
   int tcap, tcount, tsolve0;

@@ -40,7 +40,7 @@ struct Down2DArgs {
   const double *part_g, *part_cc;  // [gamma | delta | rr] x np_g; ||c||^2 x np_cc
   int np_g, np_cc;
   double tol2;
-  const T *rho;             // variable-coefficient kernels: density of the level
+  const T *cfx, *cfy, *cig;  // variable-coefficient kernels: west/south face beta, 1/diagonal
 };
 
 template <typename T>
@@ -59,8 +59,8 @@ struct Up2DArgs {
   int finest;
   int tiles_x;
   double *w;          // single-reduction CG: w = A u written on the finest level
-  const T *rho;       // variable-coefficient kernels: density of the level
-  const double *rho64;  // and the finest level's FP64 density (w = A u in FP64)
+  const T *cfx, *cfy, *cig;  // variable-coefficient kernels: west/south face beta, 1/diagonal
+  const double *rho64;  // the finest level's FP64 density (FP32 kernels: w = A u in FP64)
 };
 
 __device__ inline int wrap_or_out(int g, int n, int periodic) {
@@ -187,47 +187,12 @@ __device__ inline void sweeps(T *xs, const T *bs, int p0, int gx0, int gy0, int 
   }
 }
 
-// ---- variable-coefficient frame (beta = 1/rho_f) ---------------------------
-// On entry ig holds the frame's densities, 0 where the cell does not exist
-// (outside a non-periodic side). On exit fx[o] (fy[o]) is beta of the face
-// between frame positions o-1 and o (o-W and o), 0 when either cell is
-// missing or o is on the first column (row); ig[o] is 1/diagonal of L at
-// interior frame positions of existing cells and 0 elsewhere, so a sweep
-// leaves missing cells at 0 with no boundary tests. With zero_x the frame's
-// x is cleared as well. Every tile computes a shared cell's coefficients
-// from the same densities with the same operations (same bits).
-template <typename T, int W, int HH>
-__device__ inline void vc_frame(T *fx, T *fy, T *ig, T *xs, T ihx, T ihy, bool zero_x) {
-#pragma clang fp contract(off)
-  const int tid = threadIdx.x;
-  for (int o = tid; o < W * HH; o += kBlock) {
-    const int lx = o % W, ly = o / W;
-    const T r = ig[o];
-    T bx = T(0), by = T(0);
-    if (lx >= 1) {
-      const T rw = ig[o - 1];
-      if (r > T(0) && rw > T(0)) bx = face_beta<T>(rw, r);
-    }
-    if (ly >= 1) {
-      const T rs = ig[o - W];
-      if (r > T(0) && rs > T(0)) by = face_beta<T>(rs, r);
-    }
-    fx[o] = bx;
-    fy[o] = by;
-    if (zero_x) xs[o] = T(0);
-  }
-  __syncthreads();
-  for (int o = tid; o < W * HH; o += kBlock) {
-    const int lx = o % W, ly = o / W;
-    T v = T(0);
-    if (lx >= 1 && lx <= W - 2 && ly >= 1 && ly <= HH - 2) {
-      const T dg = ihx * (fx[o] + fx[o + 1]) + ihy * (fy[o] + fy[o + W]);
-      if (dg > T(0)) v = T(1) / dg;
-    }
-    ig[o] = v;
-  }
-  __syncthreads();
-}
+// ---- variable-coefficient frames (beta = 1/rho_f) --------------------------
+// The frame holds, per position, beta of the cell's west face (fx) and
+// south face (fy) and 1/diagonal of L (ig), precomputed once per solve for
+// the level (k_vc_coef2d), 0 for faces through non-periodic sides and for
+// positions outside the grid: one branch-free update then serves interior
+// and boundary cells, and leaves missing cells at 0.
 
 // Gauss-Seidel value with face coefficients (evaluated as written, no
 // contraction: halo copies of a cell get the owner's bits).
@@ -362,20 +327,30 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   }
   if constexpr (VC) {
     // densities on the whole frame (ring included), 0 for missing cells
-    T rv[NIT];
+    // coefficients on the whole frame (ring included), 0 for missing cells;
+    // x starts at 0 everywhere (missing cells stay 0)
+    T gv[NIT], fv[NIT], hv[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int o = tid + it * kBlock;
       const int gx = wrap_or_out(gx0 + o % W, nx, a.B.periodic[0]);
       const int gy = wrap_or_out(gy0 + o / W, ny, a.B.periodic[1]);
       const bool okr = o < NPOS && gx >= 0 && gy >= 0;
-      rv[it] = a.rho[okr ? a.Lf.at(gx, gy, 0) : a.Lf.base];
-      if (!okr) rv[it] = T(0);
+      const long id = okr ? a.Lf.at(gx, gy, 0) : a.Lf.base;
+      gv[it] = a.cig[id];
+      fv[it] = a.cfx[id];
+      hv[it] = a.cfy[id];
+      if (!okr) gv[it] = fv[it] = hv[it] = T(0);
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int o = tid + it * kBlock;
-      if (o < NPOS) ig[o] = rv[it];
+      if (o < NPOS) {
+        ig[o] = gv[it];
+        fx[o] = fv[it];
+        fy[o] = hv[it];
+        xs[o] = T(0);
+      }
     }
   }
   if (a.finest && cg && a.cgcg) {
@@ -472,7 +447,6 @@ __global__ void __launch_bounds__(kBlock) k_mg_down2d(Down2DArgs<T> a) {
   // zero initial guess: the first (red) half-sweep reads no neighbours, and
   // every later half-sweep only reads cells updated before it
   if constexpr (VC) {
-    vc_frame<T, W, HH>(fx, fy, ig, xs, a.ihx, a.ihy, true);
     sweeps_vc<T, W, HH, 1, 2 * NU, 1>(xs, bs, fx, fy, ig, p0, a.ihx, a.ihy, true);
   } else {
     sweeps<T, W, HH, 1, 2 * NU, 1>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, true);
@@ -540,13 +514,18 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
     gi[it] = okx[it] ? a.Lf.at(gx, gy, 0) : a.Lf.base;
     ci[it] = okx[it] ? a.Lc.at(gx >> 1, gy >> 1, 0) : a.Lc.base;
   }
-  T xv[NIT], cv[NIT], bv[NIT], rv[VC ? NIT : 1];
+  constexpr int NV = VC ? NIT : 1;
+  T xv[NIT], cv[NIT], bv[NIT], gv[NV], fv[NV], hv[NV];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     xv[it] = a.xpre[gi[it]];
     cv[it] = a.xc[ci[it]];
     bv[it] = a.finest ? (T)((const double *)a.b)[gi[it]] : ((const T *)a.b)[gi[it]];
-    if constexpr (VC) rv[it] = a.rho[gi[it]];
+    if constexpr (VC) {
+      gv[it] = a.cig[gi[it]];
+      fv[it] = a.cfx[gi[it]];
+      hv[it] = a.cfy[gi[it]];
+    }
   }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -554,14 +533,17 @@ __global__ void __launch_bounds__(kBlock) k_mg_up2d(Up2DArgs<T> a) {
     if (o < NPOS) {
       xs[o] = okx[it] ? xv[it] + cv[it] : T(0);
       bs[o] = okb[it] ? bv[it] : T(0);
-      if constexpr (VC) ig[o] = okx[it] ? rv[it] : T(0);
+      if constexpr (VC) {
+        ig[o] = okx[it] ? gv[it] : T(0);
+        fx[o] = okx[it] ? fv[it] : T(0);
+        fy[o] = okx[it] ? hv[it] : T(0);
+      }
     }
   }
   __syncthreads();
   // regions shrink from the frame edge, so with the extra ring the last
   // half-sweep leaves u valid on the tile plus one cell
   if constexpr (VC) {
-    vc_frame<T, W, HH>(fx, fy, ig, xs, a.ihx, a.ihy, false);
     sweeps_vc<T, W, HH, 1, 2 * NU, 0>(xs, bs, fx, fy, ig, p0, a.ihx, a.ihy, false);
   } else {
     sweeps<T, W, HH, 1, 2 * NU, 0>(xs, bs, p0, gx0, gy0, nx, ny, a.B, a.ihx, a.ihy, a.idg, fast, false);
@@ -756,18 +738,19 @@ struct CSet {
   int c[2];             // LDS index of the cell, -1 when the slot is empty
   int nb[2][2 * DIM];   // LDS indices of the neighbours (-d, +d per direction)
   T idg[2];             // 1 / diagonal
-  T bt[2][2 * DIM];     // variable coefficients: beta / h_d^2 per neighbour (0 if missing)
 };
 
-// beta / h_d^2 of the face between packed cells ia and ib of the coarse
-// levels (ib == zero_slot: no face).
+// beta / h_d^2 of the face between LDS cells ia and ib, from the densities
+// rs in LDS (ib == zero_slot: no face). Evaluated where it is used (the
+// coarse levels are small and their sweeps latency bound), so the cell sets
+// hold no coefficients and stay in registers.
 template <typename T>
-__device__ inline T c_face(const CoarseArgs<T> &a, int ia, int ib, int zero_slot, T ih2) {
-  return ib == zero_slot ? T(0) : ih2 * face_beta<T>(a.rho_c[ia], a.rho_c[ib]);
+__device__ inline T c_face(const T *rs, int ia, int ib, int zero_slot, T ih2) {
+  return ib == zero_slot ? T(0) : ih2 * face_beta<T>(rs[ia], rs[ib]);
 }
 
 template <int DIM, typename T, bool VC = false>
-__device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, int l, int color, int zero_slot,
+__device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs, int l, int color, int zero_slot,
                              CSet<DIM, T> &s) {
   const int *n = a.n[l];
   const int N = (n[0] >> 1) * n[1] * n[2];
@@ -794,10 +777,7 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, int l, int 
     if constexpr (VC) {
       T dg = T(0);
 #pragma unroll
-      for (int m = 0; m < 2 * DIM; ++m) {
-        s.bt[q][m] = c_face<T>(a, off + c, s.nb[q][m], zero_slot, a.ih2[l].v[m >> 1]);
-        dg += s.bt[q][m];
-      }
+      for (int m = 0; m < 2 * DIM; ++m) dg += c_face<T>(rs, off + c, s.nb[q][m], zero_slot, a.ih2[l].v[m >> 1]);
       s.idg[q] = T(1) / dg;
     } else {
       s.idg[q] = idg_s[8 * (l - a.l0) + code];
@@ -807,15 +787,42 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, int l, int 
 
 // One red/black half-sweep over a cell set: x = (b + sum of neighbours) /
 // diag, all LDS reads of the thread issued before the arithmetic.
+// (A missing neighbour is the zero slot: x = 0 there, so its term vanishes
+// whatever the coefficient.)
 template <int DIM, typename T, bool VC = false>
-__device__ inline void c_sweep(T *xs, const T *bs, const CSet<DIM, T> &s, const T ih2[3], bool zero_init) {
-  T v[2][2 * DIM], bv[2];
+__device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, T> &s, const T ih2[3],
+                               bool zero_init) {
+  if constexpr (VC && DIM == 3) {
+    // one cell at a time (fewer live registers); cells of one colour read
+    // only the other colour, so each result is stored at once
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (s.c[q] < 0) continue;
+      const T rc = rs[s.c[q]];
+      T nbs = T(0);
+#pragma unroll
+      for (int m = 0; m < 2 * DIM; ++m) {
+        const int nb = s.nb[q][m];
+        nbs += (ih2[m >> 1] * face_beta<T>(rc, rs[nb])) * xs[nb];
+      }
+      if (zero_init) nbs = T(0);
+      xs[s.c[q]] = (bs[s.c[q]] + nbs) * s.idg[q];
+    }
+    __syncthreads();
+    return;
+  }
+  T v[2][2 * DIM], bv[2], rv[2][VC ? 2 * DIM + 1 : 1];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     if (s.c[q] < 0) continue;
 #pragma unroll
     for (int m = 0; m < 2 * DIM; ++m) v[q][m] = xs[s.nb[q][m]];
     bv[q] = bs[s.c[q]];
+    if constexpr (VC) {
+#pragma unroll
+      for (int m = 0; m < 2 * DIM; ++m) rv[q][m] = rs[s.nb[q][m]];
+      rv[q][2 * DIM] = rs[s.c[q]];
+    }
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -823,7 +830,7 @@ __device__ inline void c_sweep(T *xs, const T *bs, const CSet<DIM, T> &s, const 
     T nbs = T(0);
     if constexpr (VC) {
 #pragma unroll
-      for (int m = 0; m < 2 * DIM; ++m) nbs += s.bt[q][m] * v[q][m];
+      for (int m = 0; m < 2 * DIM; ++m) nbs += (ih2[m >> 1] * face_beta<T>(rv[q][2 * DIM], rv[q][m])) * v[q][m];
     } else {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) nbs += ih2[d] * (v[q][2 * d] + v[q][2 * d + 1]);
@@ -839,11 +846,17 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
   __shared__ T xs[kCoarseLds + 1];     // all coarse levels, then a zero slot
   __shared__ T bs[kCoarseLds];
   __shared__ T idg_s[kCoarseLev * 8];  // inverse diagonals, read with a per-cell index
+  __shared__ T rs[VC ? kCoarseLds + 1 : 1];  // densities of all coarse levels (variable coefficients)
   if (sc->done) return;
   const int last = a.nlev - 1;
   const int zero_slot = kCoarseLds;
   if (threadIdx.x < kCoarseLev * 8) idg_s[threadIdx.x] = a.idg[threadIdx.x >> 3][threadIdx.x & 7];
   if (threadIdx.x == 0) xs[zero_slot] = T(0);
+  if constexpr (VC) {
+    const int ntot = a.off[last] + a.n[last][0] * a.n[last][1] * a.n[last][2];
+    for (int t = threadIdx.x; t < ntot; t += blockDim.x) rs[t] = a.rho_c[t];
+    if (threadIdx.x == 0) rs[zero_slot] = T(1);
+  }
   {
     // all loads of the right-hand side issued before any is used
     const int *n = a.n[a.l0];
@@ -870,11 +883,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
   for (int l = a.l0; l < last; ++l) {
     {
       CSet<DIM, T> red, black;
-      c_set<DIM, T, VC>(a, idg_s, l, 0, zero_slot, red);
-      c_set<DIM, T, VC>(a, idg_s, l, 1, zero_slot, black);
+      c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red);
+      c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black);
       for (int s = 0; s < a.nu; ++s) {
-        c_sweep<DIM, T, VC>(xs, bs, red, a.ih2[l].v, s == 0);
-        c_sweep<DIM, T, VC>(xs, bs, black, a.ih2[l].v, false);
+        c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, s == 0);
+        c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false);
       }
     }
     const int *nf = a.n[l], *nc = a.n[l + 1];
@@ -886,7 +899,10 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
       int I, J, K;
       c_decode<DIM, T>(nc, t, I, J, K);
       T acc = T(0);
+      constexpr int kUnroll = VC ? 1 : 2;
+#pragma unroll kUnroll
       for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll kUnroll
         for (int dy = 0; dy < 2; ++dy)
           for (int dx = 0; dx < 2; ++dx) {
             const int i = 2 * I + dx, j = 2 * J + dy, k = DIM == 3 ? 2 * K + dz : 0;
@@ -903,8 +919,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
                 const bool lo = q[d] > 0, hi = q[d] + 1 < nf[d];
                 const int im = lo ? off + c - st[d] : (per ? off + c + (nf[d] - 1) * st[d] : zero_slot);
                 const int ip = hi ? off + c + st[d] : (per ? off + c - (nf[d] - 1) * st[d] : zero_slot);
-                const T bm = c_face<T>(a, off + c, im, zero_slot, a.ih2[l].v[d]);
-                const T bp = c_face<T>(a, off + c, ip, zero_slot, a.ih2[l].v[d]);
+                const T bm = c_face<T>(rs, off + c, im, zero_slot, a.ih2[l].v[d]);
+                const T bp = c_face<T>(rs, off + c, ip, zero_slot, a.ih2[l].v[d]);
                 nbs += bm * xs[im] + bp * xs[ip];
                 dg += bm + bp;
               }
@@ -971,11 +987,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     }
     __syncthreads();
     CSet<DIM, T> red, black;
-    c_set<DIM, T, VC>(a, idg_s, l, 0, zero_slot, red);
-    c_set<DIM, T, VC>(a, idg_s, l, 1, zero_slot, black);
+    c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red);
+    c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black);
     for (int s = 0; s < a.nu; ++s) {
-      c_sweep<DIM, T, VC>(xs, bs, black, a.ih2[l].v, false);
-      c_sweep<DIM, T, VC>(xs, bs, red, a.ih2[l].v, false);
+      c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false);
+      c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, false);
     }
   }
   {

@@ -279,6 +279,13 @@ template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
   __shared__ double sh[kBlock / 64];
   SolverScalars *sc = a.sc;
+  if (a.rho && sc->rho_bad) {  // invalid density: the solve ends at once
+    if (linear_block() == 0 && linear_tid() == 0) {
+      sc->done = 1;
+      sc->nonconv = 1;
+    }
+    return;
+  }
   double cc = 0.0;
   const double mb = sc->mean_b, oc = sc->outflow_c;
   for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
@@ -611,6 +618,28 @@ __global__ void __launch_bounds__(kBlock) k_vc_rho_down(Lay Lf, Lay Lc, const TS
   rc[p.c] = (TD)(acc * (DIM == 3 ? 0.125 : 0.25));
 }
 
+// Face coefficients of a tiled 2D level: beta of each cell's west and south
+// faces (0 through a non-periodic side) and 1/diagonal of L (the same
+// operations as op_parts_vc, so the same bits).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_vc_coef2d(Lay L, Bnd B, T ihx, T ihy, const T *rho, T *fx, T *fy,
+                                                      T *ig) {
+#pragma clang fp contract(off)
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const int nx = L.n[0], ny = L.n[1];
+  const long c = p.c, sy = L.s[1];
+  const T rc = rho[c];
+  T bw = T(0), be = T(0), bs = T(0), bn = T(0);
+  if (B.periodic[0] || p.i > 0) bw = face_beta<T>(rc, rho[p.i > 0 ? c - 1 : c + (nx - 1)]);
+  if (B.periodic[0] || p.i + 1 < nx) be = face_beta<T>(rc, rho[p.i + 1 < nx ? c + 1 : c - (nx - 1)]);
+  if (B.periodic[1] || p.j > 0) bs = face_beta<T>(rc, rho[p.j > 0 ? c - sy : c + (long)(ny - 1) * sy]);
+  if (B.periodic[1] || p.j + 1 < ny) bn = face_beta<T>(rc, rho[p.j + 1 < ny ? c + sy : c - (long)(ny - 1) * sy]);
+  fx[c] = bw;
+  fy[c] = bs;
+  ig[c] = T(1) / (ihx * (bw + be) + ihy * (bs + bn));
+}
+
 // Density of a coarse-kernel level packed x fastest (the kernel's LDS order).
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_vc_pack(Lay L, const T *r, T *out) {
@@ -630,8 +659,9 @@ namespace lm {
 // (L + J/N)^{-1} - J/N with J the all-ones matrix: L + J/N is symmetric
 // positive definite (L is singular with the constants as null space), so
 // Gauss-Jordan elimination without pivoting inverts it in place in LDS.
+constexpr int kPinvThreads = 256;
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kCoarseThreads) k_vc_pinv(CoarseArgs<T> a, T *pinv) {
+__global__ void __launch_bounds__(kPinvThreads) k_vc_pinv(CoarseArgs<T> a, T *pinv) {
   __shared__ double M[kVcCoarsest * kVcCoarsest];
   __shared__ double rk[kVcCoarsest], ck[kVcCoarsest];
   const int last = a.nlev - 1;
@@ -662,6 +692,11 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vc_pinv(CoarseArgs<T> a, T *
     }
   }
   __syncthreads();
+  // thread t owns column j = t % N of rows t / N + R p (R = rows per pass)
+  const int R = blockDim.x / N;
+  const int j = t % N, i0 = t / N;
+  const bool active = i0 < R;
+  constexpr int kPass = (kVcCoarsest + kPinvThreads / kVcCoarsest - 1) / (kPinvThreads / kVcCoarsest);
   for (int kk = 0; kk < N; ++kk) {
     if (t < N) {
       rk[t] = M[kk * N + t];
@@ -669,16 +704,21 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vc_pinv(CoarseArgs<T> a, T *
     }
     __syncthreads();
     const double ip = 1.0 / rk[kk];
-    for (int e = t; e < N * N; e += blockDim.x) {
-      const int i = e / N, j = e - (e / N) * N;
-      double v;
-      if (i == kk)
-        v = (j == kk) ? ip : rk[j] * ip;
-      else if (j == kk)
-        v = -ck[i] * ip;
-      else
-        v = M[e] - ck[i] * rk[j] * ip;
-      M[e] = v;
+    const double rj = rk[j] * ip;
+    if (active) {
+#pragma unroll
+      for (int p = 0; p < kPass; ++p) {
+        const int i = i0 + R * p;
+        if (i >= N) break;
+        double v;
+        if (i == kk)
+          v = (j == kk) ? ip : rj;
+        else if (j == kk)
+          v = -ck[i] * ip;
+        else
+          v = M[i * N + j] - ck[i] * rj;
+        M[i * N + j] = v;
+      }
     }
     __syncthreads();
   }
@@ -686,7 +726,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_vc_pinv(CoarseArgs<T> a, T *
 }
 
 static_assert(kCoarseCells <= (long)kCoarseLoads * kCoarseThreads, "coarse loads per thread");
-static_assert(kVcCoarsest <= kCoarseThreads, "one thread per coarsest cell");
+static_assert(kVcCoarsest <= kPinvThreads, "one thread per coarsest cell");
 }  // namespace lm
 
 namespace lm {
@@ -828,6 +868,8 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
     ws.rho_c = cv.take((size_t)(kCoarseLds + 1) * eb);
     ws.pinv_vc = cv.take((size_t)ncoarsest * ncoarsest * eb);
   }
+  for (int l = 0; l < kMaxLev; ++l)
+    for (int q = 0; q < 3; ++q) ws.cf[l][q] = nullptr;
   for (int l = 0; l < kMaxLev; ++l) {
     ws.tx[l] = ws.ty[l] = 0;
     ws.vtx[l] = ws.vty[l] = 0;
@@ -835,6 +877,8 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
       choose_tile(ws, l);
       choose_tile_vc(ws, l);
     }
+    if (ws.vtx[l] > 0)
+      for (int q = 0; q < 3; ++q) ws.cf[l][q] = cv.take((size_t)ws.lev[l].lay.total * eb);
   }
   long npmax = kRedBlocks;
   if (ws.tx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.tx[0]) * (fine.n[1] / ws.ty[0]) + 1);
@@ -1096,7 +1140,9 @@ static Down2DArgs<T> down_args(PoissonWS &ws, int l, int k, const void *b, T *xp
   a.np_g = fused_level(ws, 0) ? (ws.lay.n[0] / tile_x(ws, 0)) * (ws.lay.n[1] / tile_y(ws, 0)) : 0;
   a.np_cc = kRedBlocks;
   a.tol2 = ws.tol2;
-  a.rho = ws.vc ? (const T *)ws.rho[l] : nullptr;
+  a.cfx = ws.vc ? (const T *)ws.cf[l][0] : nullptr;
+  a.cfy = ws.vc ? (const T *)ws.cf[l][1] : nullptr;
+  a.cig = ws.vc ? (const T *)ws.cf[l][2] : nullptr;
   return a;
 }
 
@@ -1124,7 +1170,9 @@ static Up2DArgs<T> up_args(PoissonWS &ws, int l, const T *xpre, const T *xc, con
   a.sc = ws.sc;
   a.tiles_x = L.n[0] / tile_x(ws, l);
   a.w = ws.w;
-  a.rho = ws.vc ? (const T *)ws.rho[l] : nullptr;
+  a.cfx = ws.vc ? (const T *)ws.cf[l][0] : nullptr;
+  a.cfy = ws.vc ? (const T *)ws.cf[l][1] : nullptr;
+  a.cig = ws.vc ? (const T *)ws.cf[l][2] : nullptr;
   a.rho64 = ws.vc ? ws.rho64 : nullptr;
   return a;
 }
@@ -1405,6 +1453,12 @@ static hipError_t set_beta_dim(hipStream_t st, PoissonWS &ws) {
       hipLaunchKernelGGL((k_vc_rho_down<DIM, T, T>), grid_for(Lc), bb, 0, st, Lf, Lc, (const T *)ws.rho[l],
                          (T *)ws.rho[l + 1]);
   }
+  if (DIM == 2)
+    for (int l = 0; l < ws.lc; ++l)
+      if (ws.vtx[l] > 0)
+        hipLaunchKernelGGL((k_vc_coef2d<T>), grid_for(ws.lev[l].lay), bb, 0, st, ws.lev[l].lay, ws.bnd,
+                           (T)ws.lev[l].ih2[0], (T)ws.lev[l].ih2[1], (const T *)ws.rho[l], (T *)ws.cf[l][0],
+                           (T *)ws.cf[l][1], (T *)ws.cf[l][2]);
   const int vc = ws.vc;
   ws.vc = 1;
   CoarseArgs<T> ca = coarse_args<T>(ws, ws.z[0], ws.r[0]);
@@ -1412,7 +1466,7 @@ static hipError_t set_beta_dim(hipStream_t st, PoissonWS &ws) {
   for (int l = ws.lc; l < ws.nlev; ++l)
     hipLaunchKernelGGL((k_vc_pack<DIM, T>), grid_for(ws.lev[l].lay), bb, 0, st, ws.lev[l].lay,
                        (const T *)ws.rho[l], (T *)ws.rho_c + ca.off[l]);
-  hipLaunchKernelGGL((k_vc_pinv<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st, ca, (T *)ws.pinv_vc);
+  hipLaunchKernelGGL((k_vc_pinv<DIM, T>), dim3(1), dim3(kPinvThreads), 0, st, ca, (T *)ws.pinv_vc);
   return hipGetLastError();
 }
 
