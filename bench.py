@@ -83,10 +83,10 @@ def time_solver(case, precision, steps, warmup):
 
 def kernel_roofline(s, ncells, steps=20):
     """Average duration of the dominant kernel as launched inside the step:
-    each of its launches in `steps` further steps of the same run is
-    bracketed by HIP events on the solver's stream (lm_kernel_timing);
-    priced at its algorithmic bytes. The same kernel timed back to back in
-    isolation (lm_bench_kernel) is reported beside it."""
+    each of its launches in `steps` further steps of the same run carries a
+    start and a stop HIP event bound to the dispatch on the solver's stream
+    (lm_kernel_timing); priced at its algorithmic bytes. The same kernel
+    timed back to back in isolation (lm_bench_kernel) is reported beside it."""
     import ctypes as C
     ms = C.c_double()
     cnt = C.c_int()

@@ -252,8 +252,10 @@ lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
 
 /* In-step timing of the finest multigrid down kernel (the fused 2D or 3D
  * level kernel): with capacity > 0, the next launches of that kernel made
- * by lm_step (up to capacity of them) are each bracketed by two HIP events
- * on the context's stream; capacity = 0 stops and releases the events.
+ * by lm_step (up to capacity of them) each carry a start and a stop HIP
+ * event bound to the dispatch on the context's stream (recorded when the
+ * kernel starts and ends, so the queueing gap before it is not counted);
+ * capacity = 0 stops and releases the events.
  * lm_kernel_timing_read waits for the stream, then returns the mean
  * event-measured duration (ms) and the number of the recorded launches
  * that did the full work of a CG iteration (iterations 1 .. the solve's

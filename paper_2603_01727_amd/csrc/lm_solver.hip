@@ -29,6 +29,8 @@
 // run the z-marching equivalent (lm_mg3d.h). Levels of at most kCoarseCells
 // cells are solved by one block in LDS; the remaining levels run one kernel
 // per half-sweep.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -1007,13 +1009,24 @@ static Fused3DArgs<T> f3_args(PoissonWS &ws, int l, const void *b, int b_double)
   return a;
 }
 
+// Launch with optional start/stop events bound to the dispatch itself: they
+// bracket the kernel's execution, not the queueing gap before it.
+template <typename K, typename A>
+static void launch_ev(K kern, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const A &a) {
+  if (e0)
+    hipExtLaunchKernelGGL(kern, g, dim3(kBlock), 0, st, e0, e1, 0, a);
+  else
+    hipLaunchKernelGGL(kern, g, dim3(kBlock), 0, st, a);
+}
+
 template <typename T>
-static void launch_3d(int nu, bool down, Fused3DArgs<T> &a, hipStream_t st, bool extra = false) {
+static void launch_3d(int nu, bool down, Fused3DArgs<T> &a, hipStream_t st, bool extra = false,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const dim3 g(a.tiles_x * a.tiles_y * (a.Lf.n[2] / a.tz));
   if (down) {
-    if (nu == 1) hipLaunchKernelGGL((k_mg_down3d<T, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
-    else if (nu == 2) hipLaunchKernelGGL((k_mg_down3d<T, 2, TX3, TY3>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_mg_down3d<T, 3, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    if (nu == 1) launch_ev(&k_mg_down3d<T, 1, TX3, TY3>, g, st, e0, e1, a);
+    else if (nu == 2) launch_ev(&k_mg_down3d<T, 2, TX3, TY3>, g, st, e0, e1, a);
+    else launch_ev(&k_mg_down3d<T, 3, TX3, TY3>, g, st, e0, e1, a);
   } else if (extra) {
     if (nu == 1) hipLaunchKernelGGL((k_mg_up3d<T, 1, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
     else if (nu == 2) hipLaunchKernelGGL((k_mg_up3d<T, 2, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
@@ -1030,10 +1043,10 @@ static void launch_3d(int nu, bool down, Fused3DArgs<T> &a, hipStream_t st, bool
 static bool w_in_up3d(const PoissonWS &ws) { return ws.cgcg && fused3d(ws, 0); }
 
 template <typename T, int TXT, int TYT>
-static void launch_nu_t(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
-  if (nu == 1) hipLaunchKernelGGL((k_mg_down2d<T, 1, TXT, TYT>), g, dim3(kBlock), 0, st, a);
-  else if (nu == 2) hipLaunchKernelGGL((k_mg_down2d<T, 2, TXT, TYT>), g, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_mg_down2d<T, 3, TXT, TYT>), g, dim3(kBlock), 0, st, a);
+static void launch_nu_t(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (nu == 1) launch_ev(&k_mg_down2d<T, 1, TXT, TYT>, g, st, e0, e1, a);
+  else if (nu == 2) launch_ev(&k_mg_down2d<T, 2, TXT, TYT>, g, st, e0, e1, a);
+  else launch_ev(&k_mg_down2d<T, 3, TXT, TYT>, g, st, e0, e1, a);
 }
 template <typename T, int TXT, int TYT>
 static void launch_nu_t(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool extra) {
@@ -1048,10 +1061,10 @@ static void launch_nu_t(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool ext
   else hipLaunchKernelGGL((k_mg_up2d<T, 3, 0, TXT, TYT>), g, dim3(kBlock), 0, st, a);
 }
 template <typename T, int TXT, int TYT>
-static void launch_nu_vc(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st) {
-  if (nu == 1) hipLaunchKernelGGL((k_mg_down2d<T, 1, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
-  else if (nu == 2) hipLaunchKernelGGL((k_mg_down2d<T, 2, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_mg_down2d<T, 3, TXT, TYT, true>), g, dim3(kBlock), 0, st, a);
+static void launch_nu_vc(int nu, Down2DArgs<T> &a, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (nu == 1) launch_ev(&k_mg_down2d<T, 1, TXT, TYT, true>, g, st, e0, e1, a);
+  else if (nu == 2) launch_ev(&k_mg_down2d<T, 2, TXT, TYT, true>, g, st, e0, e1, a);
+  else launch_ev(&k_mg_down2d<T, 3, TXT, TYT, true>, g, st, e0, e1, a);
 }
 template <typename T, int TXT, int TYT>
 static void launch_nu_vc(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool extra) {
@@ -1068,22 +1081,23 @@ static void launch_nu_vc(int nu, Up2DArgs<T> &a, dim3 g, hipStream_t st, bool ex
 // Level 0 runs the large tile, coarser levels the small one; the
 // variable-coefficient kernels run the small tiles only.
 template <typename T>
-static void launch_nu(const PoissonWS &ws, int l, int nu, Down2DArgs<T> &a, hipStream_t st) {
+static void launch_nu(const PoissonWS &ws, int l, int nu, Down2DArgs<T> &a, hipStream_t st, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr) {
   const int tx = tile_x(ws, l), ty = tile_y(ws, l);
   const dim3 g((a.Lf.n[0] / tx) * (a.Lf.n[1] / ty));
   if (ws.vc) {
     if (tx == TXS && ty == TYS)
-      launch_nu_vc<T, TXS, TYS>(nu, a, g, st);
+      launch_nu_vc<T, TXS, TYS>(nu, a, g, st, e0, e1);
     else
-      launch_nu_vc<T, 16, 16>(nu, a, g, st);
+      launch_nu_vc<T, 16, 16>(nu, a, g, st, e0, e1);
     return;
   }
   if (tx == TX && ty == TY)
-    launch_nu_t<T, TX, TY>(nu, a, g, st);
+    launch_nu_t<T, TX, TY>(nu, a, g, st, e0, e1);
   else if (tx == TXS && ty == TYS)
-    launch_nu_t<T, TXS, TYS>(nu, a, g, st);
+    launch_nu_t<T, TXS, TYS>(nu, a, g, st, e0, e1);
   else
-    launch_nu_t<T, 16, 16>(nu, a, g, st);
+    launch_nu_t<T, 16, 16>(nu, a, g, st, e0, e1);
 }
 template <typename T>
 static void launch_nu(const PoissonWS &ws, int l, int nu, Up2DArgs<T> &a, hipStream_t st, bool extra) {
@@ -1233,21 +1247,21 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       const void *b = l == 0 ? (k >= 1 ? (const void *)rprev : (const void *)r) : ws.lev[l].b;
       Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
       const bool timed = l == 0 && ws.tcount < ws.tcap;
-      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
-      launch_nu<T>(ws, l, nu, a, st);
       if (timed) {
-        ws.tk[ws.tcount] = k;
-        (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
+        launch_nu<T>(ws, l, nu, a, st, ws.tev[2 * ws.tcount], ws.tev[2 * ws.tcount + 1]);
+        ws.tk[ws.tcount++] = k;
+      } else {
+        launch_nu<T>(ws, l, nu, a, st);
       }
     } else if (fused3d(ws, l)) {
       Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
       a.xout = xin;
       const bool timed = l == 0 && ws.tcount < ws.tcap;
-      if (timed) (void)hipEventRecord(ws.tev[2 * ws.tcount], st);
-      launch_3d<T>(nu, true, a, st);
       if (timed) {
-        ws.tk[ws.tcount] = k;
-        (void)hipEventRecord(ws.tev[2 * ws.tcount++ + 1], st);
+        launch_3d<T>(nu, true, a, st, false, ws.tev[2 * ws.tcount], ws.tev[2 * ws.tcount + 1]);
+        ws.tk[ws.tcount++] = k;
+      } else {
+        launch_3d<T>(nu, true, a, st);
       }
     } else {
       dim3 g = grid_for(L);
