@@ -43,6 +43,7 @@ def parse():
                     help="also run a device copy of known size (for HBM counter calibration)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 FP64-vs-mixed comparison")
     ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 64^2, slot-flame and 512^2 workloads")
     return ap.parse_args()
 
 
@@ -54,13 +55,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+PARAM_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O", "Da_ib",
+              "p0", "dt", "cfl", "poisson_rtol")
+
+
 def make_solver(case, precision):
+    """Solver for a seeded workload (any sides, immersed body, inflow data)."""
     from paper_2603_01727_amd import Solver
-    p = case.params
     nd = case.ndim
-    s = Solver(case.n[:nd], case.L[:nd], Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"], precision=precision,
-               poisson_rtol=p["poisson_rtol"], poisson_maxit=200, device="cuda:0")
-    s.set(T=case.T, v=case.v)
+    kw = {k: case.params[k] for k in PARAM_KEYS if k in case.params}
+    s = Solver(case.n[:nd], case.L[:nd], bc=case.bc, precision=precision, poisson_maxit=200,
+               with_ib=case.ib is not None, device="cuda:0", **kw)
+    for (d, side), data in (case.bnd or {}).items():
+        s.set_side(d, side, v=data.get("v"), Z=data.get("Z"), H=data.get("H"), F=data.get("F"),
+                   wall=data.get("wall"))
+    s.set(T=case.T, H=case.H if case.T is None else None, v=case.v, Z=case.Z, ib=case.ib)
     return s
 
 
@@ -179,6 +188,26 @@ def poisson_forms(n=1024, reps=10):
     return out
 
 
+def bench_configs(steps=20, warmup=3):
+    """The other workloads at their full sizes, FP64 and mixed: 64^2 hot
+    spot (Poisson 1e-12), 768x1536 slot flame, 512^2 random modes (the
+    adjoint workload's forward step); same steps for both precisions."""
+    from workloads import c1_case, c3_case, c5_case
+    out = {}
+    for name, mk in (("c1_64", c1_case), ("c3_slot_flame_768x1536", c3_case), ("c5_512", c5_case)):
+        case = mk()
+        res = {}
+        for prec in ("fp64", "mixed"):
+            r = time_solver(case, prec, steps, warmup)
+            res[prec] = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
+                             poisson_iters_per_solve=r["poisson_iters_per_solve"])
+            r["solver"].close()
+        res["mixed_speedup_vs_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+        res["steps"], res["warmup"] = steps, warmup
+        out[name] = res
+    return out
+
+
 def field_differences(s_a, s_b):
     import numpy as np
     fa = s_a.get(("rho", "v", "H", "T", "P"), device=False)
@@ -208,7 +237,8 @@ def cpu_baseline(case, budget_s=12.0):
     sec = time.perf_counter() - t0
     return dict(value=case.ncells * n / sec, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=f"{n} steps of the {case.n[0]}x{case.n[1]} workload after one warm-up step "
-                       f"(NumPy FP64, FFT Poisson, single thread), {sec:.1f} s")
+                       f"(NumPy FP64, FFT Poisson, single thread), {sec:.1f} s",
+                host_cpus=os.cpu_count(), host_cpus_usable=len(os.sched_getaffinity(0)))
 
 
 def copy_calibration():
@@ -252,6 +282,7 @@ def main():
         del rfl
     three_d = None if a.no_3d else bench_3d()
     forms = None if a.no_vc else poisson_forms(a.n)
+    configs = None if a.no_configs else bench_configs()
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
         "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",
@@ -273,6 +304,7 @@ def main():
         "mixed": mixed,
         "c4_3d": three_d,
         "poisson_forms": forms,
+        "other_workloads": configs,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
