@@ -770,23 +770,34 @@ static void choose_tile_vc(PoissonWS &ws, int l) {
     }
 }
 
-// Depth of the z chunk of a fused 3D level kernel: 32 planes, halved (down
-// to 8) while the level would have fewer than 1024 blocks; 0 if none fits.
-static int tz3_of(const Lay &L) {
+// Depth of the z chunk of a fused 3D level kernel. Every chunk re-reads and
+// re-smooths 2H halo planes and fills a pipeline of 2 nu planes, so chunks
+// are as deep as possible while the level still has about one block per
+// block slot of the chip (256 CUs times the blocks whose LDS rings fit in
+// one CU's 160 KB): 128 planes, halved (down to 8) while there are fewer
+// blocks than that; 0 if none divides the level.
+static int tz3_of(const Lay &L, int elem_bytes, int nu) {
   const long cols = (long)(L.n[0] / TX3) * (L.n[1] / TY3);
-  int tz = 32;
-  while (tz > 8 && cols * (L.n[2] / tz) < 1024) tz /= 2;
+  const long h = 2 * nu + 1;
+  const long ring = (4 * nu + 3) * (TX3 + 2 * h) * (TY3 + 2 * h) * elem_bytes;  // down leg's LDS
+  const long per_cu = std::max(1L, 163840L / ring);
+  const long target = 256 * per_cu;
+  int tz = 128;
+  while (tz > 8 && cols * (L.n[2] / tz) < target) tz /= 2;
   return (L.n[2] % tz == 0) ? tz : 0;
 }
+static int tz3_of(const PoissonWS &ws, const Lay &L) { return tz3_of(L, ws.mixed ? 4 : 8, ws.nu); }
 
 // Blocks of the fused 3D kernels of a level.
-static long blocks3d(const Lay &L) { return (long)(L.n[0] / TX3) * (L.n[1] / TY3) * (L.n[2] / tz3_of(L)); }
+static long blocks3d(const PoissonWS &ws, const Lay &L) {
+  return (long)(L.n[0] / TX3) * (L.n[1] / TY3) * (L.n[2] / tz3_of(ws, L));
+}
 
 // Level l runs the fused 3D kernels (fully periodic grids).
 static bool fused3d(const PoissonWS &ws, int l) {
   const Lay &L = ws.lev[l].lay;
   return !ws.vc && L.ndim == 3 && ws.bnd.all_periodic && ws.nu >= 1 && ws.nu <= 3 && l < ws.lc &&
-         L.ncells() >= kFused3DMinCells && L.n[0] % TX3 == 0 && L.n[1] % TY3 == 0 && tz3_of(L) > 0;
+         L.ncells() >= kFused3DMinCells && L.n[0] % TX3 == 0 && L.n[1] % TY3 == 0 && tz3_of(ws, L) > 0;
 }
 
 static bool fused_level(const PoissonWS &ws, int l) { return tile_x(ws, l) > 0; }
@@ -885,7 +896,7 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   long npmax = kRedBlocks;
   if (ws.tx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.tx[0]) * (fine.n[1] / ws.ty[0]) + 1);
   if (ws.vtx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.vtx[0]) * (fine.n[1] / ws.vty[0]) + 1);
-  if (fused3d(ws, 0) && blocks3d(fine) > npmax) npmax = blocks3d(fine);
+  if (fused3d(ws, 0) && blocks3d(ws, fine) > npmax) npmax = blocks3d(ws, fine);
   ws.np_max = npmax;
   ws.part_cc = (double *)cv.take((size_t)npmax * 8);
   ws.part_pq = (double *)cv.take((size_t)npmax * 8);
@@ -998,7 +1009,7 @@ static Fused3DArgs<T> f3_args(PoissonWS &ws, int l, const void *b, int b_double)
   a.idg = (T)(1.0 / (2.0 * (ws.lev[l].ih2[0] + ws.lev[l].ih2[1] + ws.lev[l].ih2[2])));
   a.tiles_x = L.n[0] / TX3;
   a.tiles_y = L.n[1] / TY3;
-  a.tz = tz3_of(L);
+  a.tz = tz3_of(ws, L);
   a.b = b;
   a.b_double = b_double;
   a.xpre = nullptr;
@@ -1305,7 +1316,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       const bool extra = l == 0 && w_in_up3d(ws);
       a.w = ws.w;
       a.part_rz = ws.part_rz;
-      a.np = (int)blocks3d(L);
+      a.np = (int)blocks3d(ws, L);
       launch_3d<T>(nu, false, a, st, extra);
     } else {
       dim3 g = grid_for(L);
@@ -1339,7 +1350,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
 
 static int np_rz_of(const PoissonWS &ws) {
   if (fused_level(ws, 0)) return (ws.lay.n[0] / tile_x(ws, 0)) * (ws.lay.n[1] / tile_y(ws, 0));
-  if (w_in_up3d(ws)) return (int)blocks3d(ws.lay);
+  if (w_in_up3d(ws)) return (int)blocks3d(ws, ws.lay);
   return kRedBlocks;
 }
 
