@@ -233,10 +233,10 @@ __device__ inline void face_stress(const Lay &L, const Phys &P, const Level &lv,
   for (int k = 0; k < DIM; ++k) {
     if (k == d) continue;
     const long sk = L.s[k];
-    const double h2 = 2.0 * P.h[k];
+    const double i2h = 0.5 * P.ih[k];  // 1/(2h): centred differences
     const double *vd = lv.v[d], *vk = lv.v[k];
-    Dkd[k] = 0.5 * ((vd[cl + sk] - vd[cl - sk]) / h2 + (vd[cl + sd + sk] - vd[cl + sd - sk]) / h2);
-    Dkk[k] = 0.5 * ((vk[cl + sk] - vk[cl - sk]) / h2 + (vk[cl + sd + sk] - vk[cl + sd - sk]) / h2);
+    Dkd[k] = 0.5 * ((vd[cl + sk] - vd[cl - sk]) * i2h + (vd[cl + sd + sk] - vd[cl + sd - sk]) * i2h);
+    Dkk[k] = 0.5 * ((vk[cl + sk] - vk[cl - sk]) * i2h + (vk[cl + sd + sk] - vk[cl + sd - sk]) * i2h);
   }
   double div = 0.0;
 #pragma unroll
@@ -257,12 +257,12 @@ __device__ inline void scalar_terms(const Lay &L, const Phys &P, const Level &lv
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const long s = L.s[d];
-    const double gp = (phi[c + s] - phi[c]) / P.h[d];
-    const double gm = (phi[c] - phi[c - s]) / P.h[d];
+    const double gp = (phi[c + s] - phi[c]) * P.ih[d];
+    const double gm = (phi[c] - phi[c - s]) * P.ih[d];
     const double kp = 0.5 * (lv.kap[c] + lv.kap[c + s]);
     const double km = 0.5 * (lv.kap[c - s] + lv.kap[c]);
     adv = adv + 0.5 * (lv.F[d][c] * gp + lv.F[d][c - s] * gm);
-    dif = dif + (kp * gp - km * gm) / P.h[d];
+    dif = dif + (kp * gp - km * gm) * P.ih[d];
   }
 }
 
@@ -303,7 +303,7 @@ __device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, c
     face_stress<DIM>(L, P, lv, c, d, tp);
     face_stress<DIM>(L, P, lv, c - L.s[d], d, tm);
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) visc_all[i] = visc_all[i] + (tp[i] - tm[i]) / P.h[d];
+    for (int i = 0; i < DIM; ++i) visc_all[i] = visc_all[i] + (tp[i] - tm[i]) * P.ih[d];
   }
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
@@ -315,7 +315,7 @@ __device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, c
       const double *vi = lv.v[i];
       const double flp = lv.F[d][c] * (0.5 * (vi[c] + vi[c + s]));
       const double flm = lv.F[d][c - s] * (0.5 * (vi[c - s] + vi[c]));
-      conv = conv + (flp - flm) / P.h[d];
+      conv = conv + (flp - flm) * P.ih[d];
     }
     double r = -conv + (P.Pr / P.Pe) * visc;
     if (i == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
       const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
       const double Gh = nh >= 0 ? 0.5 * (Md[c] + Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
       const double Gl = nl >= 0 ? 0.5 * (Md[nl] + Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
-      div = div + (Gh - Gl) / P.h[d];
+      div = div + (Gh - Gl) * P.ih[d];
     }
     double drho;
     if (a.bdf2)
@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides 
     if (nh >= 0) {
       xp = x ? x[nh] : 0.0;
       const double G = 0.5 * (Md[c] + Md[nh]);
-      a.F[d][c] = G - (xp - xc) / P.h[d];
+      a.F[d][c] = G - (xp - xc) * P.ih[d];
     } else {
       double G = boundary_flux(L, B, sd, Md, p, d, 1);
       if (B.kind[d][1] == LM_SIDE_OUTFLOW) G -= oc;
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides 
       xm = x ? x[nl] : 0.0;
       if (q == 0) {  // periodic: duplicate of the wrapped face, same arithmetic
         const double G = 0.5 * (Md[nl] + Md[c]);
-        a.F[d][c - sdd] = G - (xc - xm) / P.h[d];
+        a.F[d][c - sdd] = G - (xc - xm) * P.ih[d];
       }
     } else {
       double G = boundary_flux(L, B, sd, Md, p, d, 0);

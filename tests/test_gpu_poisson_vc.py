@@ -3,9 +3,9 @@
 against the FP64 oracle's exact solve, FP64 and mixed preconditioners.
 
 Small and medium grids: element-wise relative L2 <= 1e-10 (GPU solved to
-relative residual 1e-13). The 1024^2 grid: the separable closed form (exact
-discrete solution) and the residual of the GPU answer evaluated by the
-oracle's operator."""
+relative residual 1e-13). The 1024^2 grid, beyond the oracle's sparse solve:
+the separable closed form and a manufactured problem, both exact discrete
+solutions."""
 import math
 
 import numpy as np
