@@ -32,8 +32,12 @@ class Params:
     """Dimensionless parameters (section 2.2, Eq 2.12-2.21; section 4.1):
     Pe = Re Pr; kappa = T^sigma (Eq 2.50); inv_Fr2 = 1/Fr^2 (Eq 2.43);
     Da_ib: immersed-boundary Darcy number (Eq 3.30); p0: thermodynamic
-    pressure, constant for open and periodic systems (Eq 2.41); dt = 0 asks
-    for a step fixed once from the CFL number of the initial state."""
+    pressure, constant for open and periodic systems (Eq 2.41), or its
+    initial value when p0_closed is set: an enclosed system whose p0 follows
+    from the conserved mass, p0 = m / integral(1/T) (Eq 2.40), with the
+    zeta d_t p0 source of the excess-enthalpy equation (Eq 2.45, 3.4b),
+    zeta = (S+1)(gamma-1)/(gamma Q) = (gamma-1)/(gamma qs); dt = 0 asks for a
+    step fixed once from the CFL number of the initial state."""
     Re: float = 100.0
     Pr: float = 0.7
     sigma: float = 0.7
@@ -49,6 +53,12 @@ class Params:
     p0: float = 1.0
     dt: float = 0.0
     cfl: float = 0.2
+    p0_closed: bool = False
+    gamma: float = 1.4
+
+    @property
+    def zeta(self):
+        return (self.gamma - 1.0) / (self.gamma * self.qs)
 
     @property
     def Pe(self):
@@ -71,6 +81,8 @@ class State:
     rho_prev: Optional[np.ndarray] = None     # rho^{n-1}
     R_prev: Optional[dict] = None             # residuals at level n-1
     nstep: int = 0
+    p0: float = 1.0                           # thermodynamic pressure at level n
+    p0_hist: tuple = ()                       # p0 at levels n-1, n-2 (closed systems)
 
     def copy(self):
         c = lambda a: None if a is None else a.copy()
@@ -78,7 +90,7 @@ class State:
                      c(self.P), [a.copy() for a in self.F], c(self.rho_prev),
                      None if self.R_prev is None else {k: ([a.copy() for a in v] if isinstance(v, list) else v.copy())
                                                        for k, v in self.R_prev.items()},
-                     self.nstep)
+                     self.nstep, self.p0, tuple(self.p0_hist))
 
 
 class Oracle:
@@ -106,6 +118,12 @@ class Oracle:
         face fluxes are the face average of rho v (Eq 3.20 with n = 1), not
         projected, and P = 0."""
         g, fp = self.g, self.fp
+        if self.p.p0_closed:
+            # an enclosed system: no mass crosses the sides or enters through
+            # a source; the first-step balance takes the non-reacting map
+            open_side = any(g.bc[d][s] in ("inflow", "outflow") for d in range(g.ndim) for s in (0, 1))
+            if open_side or self.ib.get("Sm") is not None or self.p.reacting:
+                raise ValueError("p0_closed needs walls or periodic sides, no mass source, non-reacting flow")
         Zs = None
         if self.p.reacting:
             Zs = np.zeros(g.shape) if Z is None else _real_or_complex(Z)
@@ -115,11 +133,13 @@ class Oracle:
             H = enthalpy_from_T(_real_or_complex(T), Zs if Zs is not None else 0.0, fp)
         T2 = temperature(Zs if Zs is not None else 0.0, H, fp)
         rho = self.p.p0 / T2
+        # enclosed system: the mass of the initial state is conserved (Eq 2.40)
+        self.mass = np.sum(rho) * g.dV
         v = [_real_or_complex(a) for a in v]
         if F is None:
             F = self.face_average_flux([rho * a for a in v])
         Pz = np.zeros(g.shape) if P is None else _real_or_complex(P)
-        st = State(rho, v, Zs, H, T2, Pz, F)
+        st = State(rho, v, Zs, H, T2, Pz, F, p0=self.p.p0)
         if self.dt == 0.0:
             self.dt = self.cfl_dt(st)
         return st
@@ -265,7 +285,37 @@ class Oracle:
                 visc[i] = visc[i] + (g.plus(tau, d) - g.minus(tau, d)) / h
         return conv, visc
 
-    def residuals(self, st: State):
+    def closed_p0(self, T):
+        """Thermodynamic pressure of an enclosed system from the equation of
+        state integrated over the domain, p0 = m / sum(dV / T) (Eq 2.40)."""
+        return self.mass / (np.sum(1.0 / T) * self.g.dV)
+
+    def ddt_p0(self, p_new, hist):
+        """d_t p0 at the level whose pressure is p_new, from the levels before
+        it (newest first): BDF2 (Eq 3.5, 3.14); with one earlier level BDF1,
+        with none 0 (start-up readings, as for d_t rho)."""
+        dt = self.dt
+        if len(hist) >= 2:
+            return (3.0 * p_new - 4.0 * hist[0] + hist[1]) / (2.0 * dt)
+        if len(hist) == 1:
+            return (p_new - hist[0]) / dt
+        return 0.0
+
+    def balance_ddt_p0(self, st: State):
+        """d_t p0 at a level with no earlier one (the first step; a start-up
+        reading, the paper is silent): the time derivative of Eq 2.40,
+        d_t p0 = (p0^2/m) sum(dV d_t T / T^2), with d_t T = qs R_H of the
+        non-reacting map T = qs (H - 1) and R_H = R_H|0 + zeta d_t p0 / rho
+        (Eq 3.4), solved for d_t p0. (A first-order start, d_t p0 = 0 or a
+        one-sided difference, leaves a first-order error in p0.)"""
+        p, dV = self.p, self.g.dV
+        RH = self.residuals(st, 0.0)["H"]
+        w = (st.p0 ** 2 / self.mass) * dV * p.qs / st.T ** 2
+        A = np.sum(w * RH)
+        B = np.sum(w * p.zeta / st.rho)
+        return A / (1.0 - B)
+
+    def residuals(self, st: State, dtp0=0.0):
         """Right-hand sides at one time level.
 
         R_Z = (1/rho)[-adv Z + div(kappa grad Z)/(Le Pe) + F_Z]      (Eq 3.2, 3.31)
@@ -273,7 +323,8 @@ class Oracle:
                       + (N/Pe) div(kappa grad Z)]                     (Eq 3.4, 3.32)
         R_v = -conv + (Pr/Pe) div tau + (1/Fr^2)(1 - rho) e_y + F_v    (Eq 3.8, 3.30)
         Le and N are the regularised coefficients of Eq 3.35 at the cell.
-        The zeta dp0/dt source of Eq 3.4b vanishes since p0 is constant."""
+        The zeta d_t p0 source of Eq 3.4b (inside the 1/rho bracket) is
+        taken with the given d_t p0: zero when p0 is constant."""
         g, p, fp = self.g, self.p, self.fp
         vp, Zp, Hp, Tp = self.padded_fields(st)
         kapp = Tp ** p.sigma
@@ -293,6 +344,8 @@ class Oracle:
             R["Z"] = rZ / st.rho
         if chi is not None:
             rH = rH - chi * kap * (st.H - self.ib.get("H_ib", 0.0)) / (Pe * p.Da_ib)
+        if p.p0_closed:
+            rH = rH + p.zeta * dtp0
         R["H"] = rH / st.rho
         conv, visc = self._momentum_terms(vp, kapp, st.F)
         Rv = []
@@ -374,10 +427,17 @@ class Oracle:
         and level-n residuals, EOS (Eq 3.15), BDF2 d_t rho (Eq 3.19),
         Poisson and projection. The level-(n-1) residuals are the ones cached
         from the previous step's level n (Eq 3.3 prints v^n inside the
-        level-(n-1) residual; v^{n-1} is read, consistent with Eq 3.1, 3.7)."""
+        level-(n-1) residual; v^{n-1} is read, consistent with Eq 3.1, 3.7).
+        Enclosed systems (p0_closed): p0* and p0^{n+1} from the conserved
+        mass (Eq 2.40) before rho* and rho^{n+1} (Eq 3.6, 3.15), and the
+        residuals carry zeta d_t p0 at their level (Eq 3.4b, 3.5, 3.14)."""
         g, p, fp = self.g, self.p, self.fp
         dt = self.dt
-        Rn = self.residuals(st)
+        closed = p.p0_closed
+        if closed and not st.p0_hist:
+            Rn = self.residuals(st, self.balance_ddt_p0(st))
+        else:
+            Rn = self.residuals(st, self.ddt_p0(st.p0, st.p0_hist) if closed else 0.0)
         first = st.R_prev is None
         M0 = [st.rho * st.v[i] for i in range(g.ndim)]
 
@@ -400,19 +460,22 @@ class Oracle:
         Zs = ab2(st.Z, Rn["Z"], Rp.get("Z")) if p.reacting else None
         Ms = [ab2(M0[i], Rn["v"][i], None if first else Rp["v"][i]) for i in range(g.ndim)]
         Ts = temperature(Zs if Zs is not None else 0.0, Hs, fp)
-        rhos = p.p0 / Ts
+        p0s = self.closed_p0(Ts) if closed else p.p0
+        rhos = p0s / Ts
         Ps, Fs, vs, bs = self.project(Ms, rhos, ddt(rhos), "pred")
-        sts = State(rhos, vs, Zs, Hs, Ts, Ps, Fs)
+        sts = State(rhos, vs, Zs, Hs, Ts, Ps, Fs, p0=p0s)
         # ---- corrector
-        Rs = self.residuals(sts)
+        hist_s = (st.p0,) + tuple(st.p0_hist[:1])
+        Rs = self.residuals(sts, self.ddt_p0(p0s, hist_s) if closed else 0.0)
         H1 = am2(st.H, Rs["H"], Rn["H"])
         Z1 = am2(st.Z, Rs["Z"], Rn["Z"]) if p.reacting else None
         M1 = [am2(M0[i], Rs["v"][i], Rn["v"][i]) for i in range(g.ndim)]
         T1 = temperature(Z1 if Z1 is not None else 0.0, H1, fp)
-        rho1 = p.p0 / T1
+        p01 = self.closed_p0(T1) if closed else p.p0
+        rho1 = p01 / T1
         P1, F1, v1, b1 = self.project(M1, rho1, ddt(rho1), "corr")
         out = State(rho1, v1, Z1, H1, T1, P1, F1, rho_prev=st.rho, R_prev=Rn,
-                    nstep=st.nstep + 1)
+                    nstep=st.nstep + 1, p0=p01, p0_hist=(st.p0,) + tuple(st.p0_hist[:1]))
         rms = lambda a: float(np.sqrt(np.mean(np.abs(a) ** 2)))
         self.stats["pc_diff_v"] = [rms(vs[i] - v1[i]) for i in range(g.ndim)]
         self.stats["pc_diff_P"] = rms(Ps - P1)
