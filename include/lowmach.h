@@ -95,7 +95,21 @@ typedef struct {
  *                beta = 1/rho_f for lm_project with a density (needs a grid
  *                that coarsens to <= 128 cells). The step itself always
  *                uses beta = 1: its constraint is on the mass flux
- *                (Eq 3.9, 3.24), for which the density never enters A.    */
+ *                (Eq 3.9, 3.24), for which the density never enters A.
+ *  p0_closed     0: p0 constant (open or periodic systems, Eq 2.41);
+ *                1: enclosed system: p0 = m / integral(1/T) dV with the mass
+ *                m of the initial state (Eq 2.40), the predicted and new
+ *                levels' p0 from their temperatures before rho = p0/T
+ *                (Eq 3.6, 3.15), and the source zeta d_t p0 inside the
+ *                (1/rho)[...] of the excess-enthalpy residual (Eq 3.4b),
+ *                zeta = (S+1)(gamma-1)/(gamma Q) = (gamma-1)/(gamma qs),
+ *                d_t p0 by BDF2 over the levels before (Eq 3.5, 3.14; BDF1
+ *                with one earlier level; on the first step from the time
+ *                derivative of Eq 2.40 with the step's residuals). Needs
+ *                non-reacting flow, periodic or wall sides and no mass
+ *                source S_m (LM_EUNSUPPORTED / LM_EINVAL otherwise); p0 is
+ *                then the initial thermodynamic pressure
+ *  gamma         ratio of specific heats (p0_closed only; > 1)             */
 typedef struct {
   double Re, Pr, sigma, inv_Fr2;
   int reacting;
@@ -108,6 +122,8 @@ typedef struct {
   int with_ib;
   int with_adjoint;
   int poisson_beta;
+  int p0_closed;
+  double gamma;
 } lm_params;
 
 /* Field set for lm_set_fields / lm_get_fields; NULL entries are skipped.
@@ -141,6 +157,7 @@ typedef struct {
   double poisson_relres[2];  /* last step: final recursive relative residual */
   double compat[2];          /* last step: mean(b) removed before each solve */
   long long total_poisson_iters;
+  double p0;                 /* thermodynamic pressure at the end of the call */
 } lm_step_stats;
 
 /* RHS-mode projection: solve A P = b for the zero-mean P, with
@@ -203,8 +220,8 @@ lm_status lm_get_dt(const lm_ctx *ctx, double *dt);
 
 /* ---- checkpoint / restart ------------------------------------------------
  * The complete state of a context (level n, its pressure, the level n-1
- * density and residuals used by the next AB2/BDF2 step, the step counter
- * and the time) copied to or from a caller device buffer of
+ * density and residuals used by the next AB2/BDF2 step, the step counter,
+ * the time and, for an enclosed system, the p0 history and mass) copied to or from a caller device buffer of
  * lm_state_size bytes; restoring it and stepping reproduces the original
  * run bit for bit.                                                          */
 lm_status lm_state_size(const lm_ctx *ctx, size_t *bytes);

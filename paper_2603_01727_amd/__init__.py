@@ -72,7 +72,8 @@ class Solver:
                  Da_ib: float = 1.0, p0: float = 1.0, dt: float = 0.0, cfl: float = 0.2,
                  precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
                  mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False,
-                 variable_coefficient: bool = False, device: str = "cuda:0", stream=None):
+                 variable_coefficient: bool = False, p0_closed: bool = False, gamma: float = 1.4,
+                 device: str = "cuda:0", stream=None):
         import torch
         self.torch = torch
         self.lib = _L.load()
@@ -94,7 +95,8 @@ class Solver:
                          precision=_L.PRECISION[precision],
                          poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
                          with_ib=int(with_ib), with_adjoint=int(with_adjoint),
-                         poisson_beta=_L.LM_BETA_INV_RHO if variable_coefficient else _L.LM_BETA_ONE)
+                         poisson_beta=_L.LM_BETA_INV_RHO if variable_coefficient else _L.LM_BETA_ONE,
+                         p0_closed=int(p0_closed), gamma=gamma)
         self.grid, self.params = g, p
         self.device = torch.device(device)
         size = C.c_size_t()
@@ -152,7 +154,7 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.lm_step(self.ctx, nsteps, C.byref(st)))
         self.stats = dict(steps=st.steps, dt=st.dt, time=st.time, poisson_iters=list(st.poisson_iters),
                           poisson_relres=list(st.poisson_relres), compat=list(st.compat),
-                          total_poisson_iters=st.total_poisson_iters)
+                          total_poisson_iters=st.total_poisson_iters, p0=st.p0)
         return self.stats
 
     def get(self, names=("rho", "v", "H", "T", "P", "F", "Z"), device: bool = True) -> dict:

@@ -46,6 +46,7 @@ struct lm_ctx {
   double *ad[2][9];
   int ad_cur;
   double *aw[20];
+  P0Dev *p0d;            // enclosed-system thermodynamic pressure (device)
 };
 
 namespace {
@@ -138,6 +139,18 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "poisson_beta must be LM_BETA_ONE or LM_BETA_INV_RHO";
     return false;
   }
+  if (p->p0_closed != 0 && p->p0_closed != 1) {
+    *err = "p0_closed must be 0 or 1";
+    return false;
+  }
+  if (p->p0_closed && !(p->gamma > 1.0)) {
+    *err = "gamma must exceed 1 for an enclosed system";
+    return false;
+  }
+  if (p->with_adjoint && p->p0_closed) {
+    *err = "the adjoint needs a constant thermodynamic pressure";
+    return false;
+  }
   if (p->with_adjoint && (p->reacting || p->with_ib || p->precision != LM_FP64)) {
     *err = "the adjoint supports non-reacting FP64 runs without immersed body";
     return false;
@@ -179,11 +192,24 @@ void setup_phys(lm_ctx *c) {
   if (1.0 / p.Le_F > nc) nc = 1.0 / p.Le_F;
   if (1.0 / p.Le_O > nc) nc = 1.0 / p.Le_O;
   P.nu_coef = nc;
+  P.closed = p.p0_closed;
+  P.zeta = p.p0_closed ? (p.gamma - 1.0) / (p.gamma * p.qs) : 0.0;
 }
 
 // Carves every device array (or only sizes them when cv.base == nullptr).
 bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   const int nd = c->grid.ndim;
+  if (c->prm.p0_closed) {
+    bool open = false;
+    for (int d = 0; d < nd; ++d)
+      for (int s = 0; s < 2; ++s)
+        open = open || c->grid.bc[d][s] == LM_SIDE_INFLOW || c->grid.bc[d][s] == LM_SIDE_OUTFLOW;
+    if (open || c->prm.reacting) {
+      if (err) *err = "an enclosed system needs periodic or wall sides and non-reacting flow";
+      return false;
+    }
+  }
+  c->p0d = (P0Dev *)cv.take(sizeof(P0Dev));
   const Lay &L = c->lay;
   const size_t ab = (size_t)L.total * 8;
   const bool reacting = c->prm.reacting != 0;
@@ -457,8 +483,11 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
       if (q == 5) c->ib.S_m = dst;
     }
   }
+  if (c->prm.p0_closed && c->ib.S_m) return fail(c, LM_EINVAL, "an enclosed system takes no mass source S_m");
   HIPCHK(c, hipMemsetAsync(c->dflags, 0, 64, c->st));
   HIPCHK(c, launch_init_state(c->st, c->lay, c->phys, c->bnd, c->sides, from_T, lv, c->dflags));
+  if (c->prm.p0_closed)  // conserved mass of this state, p0 history cleared
+    HIPCHK(c, launch_p0(c->st, 0, c->lay, c->phys, c->p0d, &lv, nullptr, nullptr, c->pws.partials));
   if (f->F[0]) {
     for (int d = 0; d < nd; ++d) {
       if (!f->F[d]) return fail(c, LM_EINVAL, "give every face-flux component or none");
@@ -496,7 +525,14 @@ static lm_status do_stage(lm_ctx *c, int corrector, int &iters, double &relres, 
   Resid &rn = c->R[c->rprev ^ 1];
   HIPCHK(c, launch_ghosts(c->st, L, c->bnd, c->phys, c->sides, src.v, src.Z, src.H, src.T, src.kap));
   const int first = !c->have_prev;
-  HIPCHK(c, launch_stage(c->st, corrector, first, L, c->phys, src, A, rprev, rn, c->ib, out, c->M));
+  const double *dtp0 = corrector ? &c->p0d->dtp0_star : &c->p0d->dtp0_n;
+  HIPCHK(c, launch_stage(c->st, corrector, first, L, c->phys, src, A, rprev, rn, c->ib, out, c->M, dtp0));
+  if (c->prm.p0_closed) {
+    // first step: d_t p0 at level n from the balance, into R_H^n and H*
+    if (!corrector && first) HIPCHK(c, launch_p0(c->st, 3, L, c->phys, c->p0d, &out, &A, rn.H, c->pws.partials));
+    // p0 of the predicted / new level from the mass, then rho = p0 / T
+    HIPCHK(c, launch_p0(c->st, corrector ? 2 : 1, L, c->phys, c->p0d, &out, &A, nullptr, c->pws.partials));
+  }
   HIPCHK(c, launch_rhs(c->st, L, c->bnd, c->phys, c->sides, c->M, out.rho, A.rho, c->rho_prev, !first, c->ib.S_m,
                        c->b, c->pws.partials, c->pws.sc));
   const double *x0 = corrector ? c->P[c->istar] : c->P[c->icur];
@@ -539,6 +575,8 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
       return s;
     }
     // commit: level n+1 becomes current; rho^n becomes rho^{n-1}
+    if (c->prm.p0_closed)
+      HIPCHK(c, launch_p0(c->st, 4, c->lay, c->phys, c->p0d, nullptr, nullptr, nullptr, nullptr));
     double *old_prev = c->rho_prev;
     c->rho_prev = c->lev[c->icur].rho;
     c->lev[c->icur].rho = old_prev;
@@ -558,6 +596,12 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
       stats->compat[q] = cm[q];
     }
     stats->total_poisson_iters = c->total_iters;
+    stats->p0 = c->prm.p0;
+    if (c->prm.p0_closed) {
+      HIPCHK(c, hipMemcpyAsync(c->hscalar + 1, &c->p0d->p0[0], 8, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      stats->p0 = c->hscalar[1];
+    }
   }
   return LM_OK;
 }
@@ -656,7 +700,7 @@ extern "C" lm_status lm_bench_kernel(lm_ctx *c, int which, int reps, double *avg
     switch (which) {
       case 1:
         return launch_stage(c->st, 0, 1, c->lay, c->phys, A, A, c->R[c->rprev], c->R[c->rprev ^ 1], c->ib, S,
-                            c->M);
+                            c->M, &c->p0d->dtp0_n);
       case 6:
         return launch_rhs(c->st, c->lay, c->bnd, c->phys, c->sides, c->M, S.rho, A.rho, c->rho_prev, 0, c->ib.S_m,
                           c->b, c->pws.partials, c->pws.sc);
@@ -694,6 +738,8 @@ struct StateHeader {
   double time;
   int last_iters[2];
 };
+// Header bytes [0, 128): StateHeader; [128, 256): the device p0 state.
+static_assert(sizeof(StateHeader) <= 128 && sizeof(P0Dev) <= 128, "state header layout");
 
 // Arrays making up the state, in a fixed order.
 int state_arrays(lm_ctx *c, double **out) {
@@ -751,6 +797,7 @@ extern "C" lm_status lm_save_state(lm_ctx *c, void *buf) {
   const int k = state_arrays(c, arr);
   StateHeader h{c->have_prev, c->have_state, c->time, {c->last_iters[0], c->last_iters[1]}};
   HIPCHK(c, hipMemcpyAsync(buf, &h, sizeof(h), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync((char *)buf + 128, c->p0d, sizeof(P0Dev), hipMemcpyDeviceToDevice, c->st));
   char *p = (char *)buf + 256;
   const size_t ab = (size_t)c->lay.total * 8;
   for (int q = 0; q < k; ++q) HIPCHK(c, hipMemcpyAsync(p + q * ab, arr[q], ab, hipMemcpyDeviceToDevice, c->st));
@@ -764,6 +811,7 @@ extern "C" lm_status lm_load_state(lm_ctx *c, const void *buf) {
   const int k = state_arrays(c, arr);
   StateHeader h;
   HIPCHK(c, hipMemcpyAsync(&h, buf, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->p0d, (const char *)buf + 128, sizeof(P0Dev), hipMemcpyDeviceToDevice, c->st));
   const char *p = (const char *)buf + 256;
   const size_t ab = (size_t)c->lay.total * 8;
   for (int q = 0; q < k; ++q) HIPCHK(c, hipMemcpyAsync(arr[q], p + q * ab, ab, hipMemcpyDeviceToDevice, c->st));

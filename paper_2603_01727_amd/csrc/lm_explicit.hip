@@ -267,8 +267,8 @@ __device__ inline void scalar_terms(const Lay &L, const Phys &P, const Level &lv
 }
 
 template <int DIM>
-__device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, const IB &ib, long c, double &RH,
-                                 double &RZ, double Rv[3]) {
+__device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, const IB &ib, long c, double dtp0,
+                                 double &RH, double &RZ, double Rv[3]) {
   const double rho = lv.rho[c];
   const double kap = lv.kap[c];
   const double chi = (P.has_ib && ib.chi) ? (double)ib.chi[c] : 0.0;
@@ -295,6 +295,7 @@ __device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, c
     const double hib = ib.H_ib ? ib.H_ib[c] : 0.0;
     rH = rH - chi * kap * (lv.H[c] - hib) / (P.Pe * P.Da);
   }
+  if (P.closed) rH = rH + P.zeta * dtp0;  // zeta d_t p0 (Eq 3.4b), enclosed systems
   RH = rH / rho;
   double visc_all[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -332,6 +333,7 @@ struct StageArgs {
   Resid rprev, rn;
   IB ib;
   double *M[3];
+  const double *dtp0;  // d_t p0 of the level the residuals are taken at (enclosed systems)
 };
 
 // Predictor (corrector = 0): residuals of level n, stored for the corrector
@@ -345,7 +347,8 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
   if (!cell_of_thread(L, p)) return;
   const long c = p.c;
   double RH, RZ, Rv[3];
-  residuals<DIM>(L, P, a.cur, a.ib, c, RH, RZ, Rv);
+  const double dtp0 = P.closed ? *a.dtp0 : 0.0;
+  residuals<DIM>(L, P, a.cur, a.ib, c, dtp0, RH, RZ, Rv);
   const double dt = P.dt;
   const double rho0 = a.n0.rho[c];
   double H, Z = 0.0;
@@ -382,8 +385,9 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
 
 hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, const Phys &P,
                         const Level &cur, const Level &n0, const Resid &rprev, const Resid &rn,
-                        const IB &ib, Level &out, double *M[3]) {
+                        const IB &ib, Level &out, double *M[3], const double *dtp0) {
   StageArgs a;
+  a.dtp0 = dtp0;
   a.cur = cur;
   a.n0 = n0;
   a.out = out;
@@ -808,6 +812,135 @@ __global__ void __launch_bounds__(kBlock) k_shift(Lay L, const double *x, const 
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out) {
   dim3 g = grid_for(L), bl(kBX, kBY);
   hipLaunchKernelGGL(k_shift, g, bl, 0, st, L, x, sc, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Thermodynamic pressure of an enclosed system (Eq 2.40)
+// ---------------------------------------------------------------------------
+
+// Per-block partial sums over the cells: 0 rho, 1 1/T, 2 R_H/T^2, 3 1/(rho T^2).
+template <int WHAT>
+__global__ void __launch_bounds__(kBlock) k_p0_sum(Lay L, const double *T, const double *rho, const double *RH,
+                                                   double *part) {
+  __shared__ double sh[kBlock / 64];
+  CellPos p;
+  double v = 0.0;
+  if (cell_of_thread(L, p)) {
+    const long c = p.c;
+    if (WHAT == 0) v = rho[c];
+    if (WHAT == 1) v = 1.0 / T[c];
+    if (WHAT == 2) v = RH[c] / (T[c] * T[c]);
+    if (WHAT == 3) v = 1.0 / (rho[c] * (T[c] * T[c]));
+  }
+  const double s = block_sum(v, sh);
+  if (linear_tid() == 0) part[linear_block()] = s;
+}
+
+// One block: the sum of the partials (fixed order) and the update of the
+// device p0 state. what: 0 mass and set-up, 1 predicted level, 2 new level,
+// 3 first half of the start-up balance (stores the sum), 4 second half.
+__global__ void __launch_bounds__(kBlock) k_p0_finish(int what, const double *part, int np, P0Dev *q, double dV,
+                                                      double p_init, double qs, double zeta, double dt) {
+  __shared__ double sh[kBlock / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x != 0) return;
+  if (what == 0) {
+    q->mass = s * dV;
+    q->p0[0] = q->p0[1] = q->p0[2] = p_init;
+    q->p0_star = q->p0_new = p_init;
+    q->dtp0_n = q->dtp0_star = q->dtp0_start = 0.0;
+    q->nhist = 0;
+  } else if (what == 1) {
+    const double ps = q->mass / (s * dV);
+    q->p0_star = ps;
+    // d_t p0 at the predicted level: BDF2 over levels n, n-1 (Eq 3.14), BDF1 with level n only
+    q->dtp0_star = q->nhist >= 1 ? (3.0 * ps - 4.0 * q->p0[0] + q->p0[1]) / (2.0 * dt) : (ps - q->p0[0]) / dt;
+  } else if (what == 2) {
+    q->p0_new = q->mass / (s * dV);
+  } else if (what == 3) {
+    q->dtp0_start = s;  // sum of R_H / T^2, finished below
+  } else {
+    // d_t p0 = (p0^2/m) sum(dV qs R_H / T^2) with R_H = R_H|0 + zeta d_t p0 / rho: solved for d_t p0
+    const double w = q->p0[0] * q->p0[0] / q->mass * dV * qs;
+    const double A = w * q->dtp0_start, B = w * zeta * s;
+    q->dtp0_start = A / (1.0 - B);
+  }
+}
+
+// rho = p0 / T with p0 of the predicted (which = 0) or new (1) level.
+__global__ void __launch_bounds__(kBlock) k_p0_eos(Lay L, const double *T, double *rho, const P0Dev *q, int which) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  rho[p.c] = (which ? q->p0_new : q->p0_star) / T[p.c];
+}
+
+// First step: the balance's d_t p0 at level n enters the stored level-n
+// residual R_H and the Euler-predicted H*, whose T* and kappa* follow.
+__global__ void __launch_bounds__(kBlock) k_p0_startup(Lay L, Phys P, const P0Dev *q, const double *rho_n,
+                                                       double *RH, Level out) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+  const double add = P.zeta * q->dtp0_start / rho_n[c];
+  RH[c] += add;
+  const double H = out.H[c] + P.dt * add;
+  const double T = temperature(P, 0.0, H);
+  out.H[c] = H;
+  out.T[c] = T;
+  out.kap[c] = pow(T, P.sigma);
+}
+
+// Commit of a completed step: history shift and d_t p0 at the new level n
+// for the next predictor (BDF2, Eq 3.5; BDF1 with one earlier level).
+__global__ void k_p0_commit(P0Dev *q, double dt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  q->p0[2] = q->p0[1];
+  q->p0[1] = q->p0[0];
+  q->p0[0] = q->p0_new;
+  q->nhist = q->nhist < 2 ? q->nhist + 1 : 2;
+  q->dtp0_n = q->nhist >= 2 ? (3.0 * q->p0[0] - 4.0 * q->p0[1] + q->p0[2]) / (2.0 * dt) : (q->p0[0] - q->p0[1]) / dt;
+}
+
+hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0Dev *p0, Level *lv, const Level *n0,
+                     double *RH, double *partials) {
+  const dim3 g = grid_for(L), bl(kBX, kBY);
+  const int np = (int)nblocks_for(L);
+  const double dV = P.h[0] * P.h[1] * (L.ndim == 3 ? P.h[2] : 1.0);
+  auto finish = [&](int w) {
+    hipLaunchKernelGGL(k_p0_finish, dim3(1), dim3(kBlock), 0, st, w, (const double *)partials, np, p0, dV, P.p0, P.qs,
+                       P.zeta, P.dt);
+  };
+  switch (what) {
+    case 0:
+      hipLaunchKernelGGL(k_p0_sum<0>, g, bl, 0, st, L, (const double *)lv->T, (const double *)lv->rho,
+                         (const double *)nullptr, partials);
+      finish(0);
+      break;
+    case 1:
+    case 2:
+      hipLaunchKernelGGL(k_p0_sum<1>, g, bl, 0, st, L, (const double *)lv->T, (const double *)nullptr,
+                         (const double *)nullptr, partials);
+      finish(what);
+      hipLaunchKernelGGL(k_p0_eos, g, bl, 0, st, L, (const double *)lv->T, lv->rho, (const P0Dev *)p0, what - 1);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_p0_sum<2>, g, bl, 0, st, L, (const double *)n0->T, (const double *)nullptr,
+                         (const double *)RH, partials);
+      finish(3);
+      hipLaunchKernelGGL(k_p0_sum<3>, g, bl, 0, st, L, (const double *)n0->T, (const double *)n0->rho,
+                         (const double *)nullptr, partials);
+      finish(4);
+      hipLaunchKernelGGL(k_p0_startup, g, bl, 0, st, L, P, (const P0Dev *)p0, (const double *)n0->rho, RH, *lv);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_p0_commit, dim3(1), dim3(64), 0, st, p0, P.dt);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

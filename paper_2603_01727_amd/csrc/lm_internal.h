@@ -45,6 +45,21 @@ struct Phys {
   double qs, S, k, Le_F, Le_O, N_F, N_O, fshift;  // fshift = -1 - F_eps(0)
   int has_ib;
   double nu_coef;   // max(Pr, 1, 1/Le_F, 1/Le_O)
+  int closed;       // enclosed system: p0 from the conserved mass (Eq 2.40)
+  double zeta;      // (gamma - 1)/(gamma qs): factor of the d_t p0 source (Eq 3.4b)
+};
+
+// Thermodynamic pressure of an enclosed system, on the device (the step
+// never reads it back): committed p0 at levels n, n-1, n-2, the pending
+// predicted and new levels and the d_t p0 each stage's residual uses.
+struct P0Dev {
+  double p0[3];        // levels n, n-1, n-2
+  double mass;         // conserved mass m = sum(rho dV)
+  double p0_star, p0_new;
+  double dtp0_n;       // d_t p0 at level n (predictor residual); 0 on the first step
+  double dtp0_star;    // d_t p0 at the predicted level (corrector residual)
+  double dtp0_start;   // first step: d_t p0 at level n from the balance of Eq 2.40
+  int nhist;           // committed levels before n (0, 1, 2)
 };
 
 // One time level of the state (device pointers into the workspace).
@@ -107,7 +122,17 @@ hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys 
                          double *v[3], double *Z, double *H, double *T, double *kap);
 hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, const Phys &P,
                         const Level &cur, const Level &n0, const Resid &rprev, const Resid &rn,
-                        const IB &ib, Level &out, double *M[3]);
+                        const IB &ib, Level &out, double *M[3], const double *dtp0);
+// Enclosed-system thermodynamic pressure (lm_explicit.hip). what:
+//   0 set-up: mass of the level, p0 = params.p0, no history
+//   1 predicted level: p0* = m / sum(dV/T*), rho* = p0*/T*, d_t p0 at it
+//   2 new level: p0^{n+1} = m / sum(dV/T^{n+1}), rho^{n+1} = p0^{n+1}/T^{n+1}
+//   3 first step, after the predictor stage kernel: d_t p0 at level n from
+//     the balance of Eq 2.40, added to the stored level-n residual R_H and
+//     to the Euler-predicted H* (then T*, kappa*)
+//   4 commit of a completed step (history shift, d_t p0 for the next step)
+hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0Dev *p0, Level *lv, const Level *n0,
+                     double *RH, double *partials);
 hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
                       double *const M[3], const double *rho_new, const double *rho_n,
                       const double *rho_prev, int bdf2, const double *S_m, double *b,

@@ -8,7 +8,7 @@ from oracle import Grid, Oracle, Params
 from workloads import Case
 
 PARAM_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O",
-              "Da_ib", "p0", "dt", "cfl")
+              "Da_ib", "p0", "dt", "cfl", "p0_closed", "gamma")
 SIDE_INDEX = {"slip", "noslip", "inflow", "outflow"}
 
 

@@ -117,3 +117,26 @@ def test_variable_coefficient_reservation():
     g, p = _grid_params((64, 64))
     p.poisson_beta = 2
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b0)) == lib.LM_EINVAL
+
+
+def test_enclosed_system_checks_without_gpu():
+    """p0_closed: gamma must exceed 1; reacting flow, inflow or outflow
+    sides are not an enclosed system; the adjoint needs constant p0."""
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b = C.c_size_t()
+    g, p = _grid_params((64, 64))
+    p.p0_closed, p.gamma = 1, 1.4
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+    p.gamma = 1.0
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.gamma, p.reacting = 1.4, 1
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    g, p = _grid_params((64, 64), bc=[(2, 2), (3, 4), (0, 0)])   # noslip x, inflow / outflow y
+    p.p0_closed, p.gamma = 1, 1.4
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    g, p = _grid_params((64, 64))
+    p.p0_closed, p.gamma, p.with_adjoint = 1, 1.4, 1
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.p0_closed = 2
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
