@@ -328,6 +328,38 @@ def c3_case(nx=768, ny=1536, seed=3, W=32, wall=4, wall_h=64, inj=4,
     return case
 
 
+def taylor_couette_case(n=64, Re=1.0, Da=1e-2, shifted=True, half=2.5):
+    """Flow between concentric cylinders of radii 1 and 2 (inner one turning
+    with unit surface speed, outer one at rest) in a periodic box
+    [-half, half]^2 of n^2 cells, the cylinders immersed by penalisation:
+    chi = 1 for r < 1 + s and r > 2 - s, s = sqrt(Da) for the shifted mask
+    (the body grown by the Brinkman length), 0 for the cell-exact one. Body
+    targets: rigid rotation inside, rest outside. Initial velocity: the exact
+    annular profile v_theta = (4 - r^2)/(3 r) in 1 <= r <= 2 and the body
+    velocities elsewhere; uniform T = 1 (constant density; the bodies hold
+    the excess enthalpy H = 2 of T = 1 at qs = 1)."""
+    L = (2.0 * half, 2.0 * half)
+    x, y = cell_centres((n, n), L)
+    x = x - half
+    y = y - half
+    X, Y = np.broadcast_arrays(x, y)
+    r2 = X * X + Y * Y
+    r = np.sqrt(r2)
+    s = math.sqrt(Da) if shifted else 0.0
+    chi = ((r < 1.0 + s) | (r > 2.0 - s)).astype(np.uint8)
+    inner = r < 1.5
+    vib = [np.where(inner, -Y, 0.0), np.where(inner, X, 0.0)]
+    ann = (r >= 1.0) & (r <= 2.0)
+    f = np.where(ann, (4.0 / np.where(ann, r2, 1.0) - 1.0) / 3.0, 0.0)
+    v = [np.where(ann, -f * Y, vib[0]), np.where(ann, f * X, vib[1])]
+    params = dict(Re=Re, Pr=0.7, Da_ib=Da, cfl=0.2, poisson_rtol=1e-10)
+    case = Case(f"taylor_couette_{n}", 2, (n, n, 1), L + (1.0,), (("periodic", "periodic"),) * 2, params,
+                np.ones((n, n)), v, ib=dict(chi=chi, v_ib=vib, H_ib=np.full((n, n), 2.0)))
+    case.exact_v = [-f * Y, f * X]
+    case.annulus = (r >= 1.0 + s) & (r <= 2.0 - s)
+    return case
+
+
 def make_case(name, **kw):
     return dict(c1=c1_case, c2=c2_case, c3=c3_case, c4=c4_case,
                 c5=c5_case)[name](**kw)
