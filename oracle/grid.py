@@ -18,9 +18,12 @@ SIDE_KINDS = ("periodic", "slip", "noslip", "inflow", "outflow")
 class Grid:
     """Uniform grid: ``n`` cells and length ``L`` per direction, and per
     direction a pair (lo, hi) of side kinds from SIDE_KINDS. ``bnd`` maps
-    (d, side) to boundary data for inflow sides: dict with optional keys
+    (d, side) to boundary data: for inflow sides a dict with optional keys
     'v' (list per component), 'Z', 'H', 'F' (normal mass flux), each an array
-    over the side's cells (interior shape without axis d) or a scalar."""
+    over the side's cells (interior shape without axis d) or a scalar; for
+    wall sides (slip, no-slip) optional 'Z', 'H': wall values that make the
+    scalar Dirichlet on that wall (an isothermal wall, Eq 4.16a-b) instead
+    of Neumann 0 (adiabatic, Eq 4.16c)."""
 
     def __init__(self, n, L, bc=None, bnd=None):
         self.ndim = len(n)
@@ -182,6 +185,8 @@ def field_rules(g: Grid, field, comp=None):
     slip wall: normal velocity Dirichlet 0, tangential velocity and scalars
       Neumann 0.
     no-slip wall: velocity Dirichlet 0, scalars Neumann 0.
+    on either wall a scalar with a value in the side data is Dirichlet
+      with that value (Eq 3.43) instead.
     inflow: velocity and scalars Dirichlet with the side's given values;
       cells flagged 'wall' in the side data (a solid footprint on the
       side) take Neumann 0 for the scalars instead.
@@ -207,6 +212,8 @@ def field_rules(g: Grid, field, comp=None):
                     pair.append(("dirichlet_or_wall", g.bvalue(d, side, field), wall))
                 else:
                     pair.append(("dirichlet", g.bvalue(d, side, field)))
+            elif field in ("Z", "H") and g.bvalue(d, side, field, default=None) is not None:
+                pair.append(("dirichlet", g.bvalue(d, side, field)))
             elif kind == "noslip":
                 pair.append(("dirichlet", 0.0) if field == "v" else ("neumann", 0.0))
             elif kind == "slip":

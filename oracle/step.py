@@ -30,7 +30,9 @@ def _real_or_complex(a):
 @dataclasses.dataclass
 class Params:
     """Dimensionless parameters (section 2.2, Eq 2.12-2.21; section 4.1):
-    Pe = Re Pr; kappa = T^sigma (Eq 2.50); inv_Fr2 = 1/Fr^2 (Eq 2.43);
+    Pe = Re Pr; kappa = T^sigma (Eq 2.50), or Sutherland's law
+    kappa = T^{3/2} (1 + C)/(T + C) (Eq 4.12) when sutherland_C = C > 0;
+    inv_Fr2 = 1/Fr^2 (Eq 2.43);
     Da_ib: immersed-boundary Darcy number (Eq 3.30); p0: thermodynamic
     pressure, constant for open and periodic systems (Eq 2.41), or its
     initial value when p0_closed is set: an enclosed system whose p0 follows
@@ -55,6 +57,15 @@ class Params:
     cfl: float = 0.2
     p0_closed: bool = False
     gamma: float = 1.4
+    sutherland_C: float = 0.0
+
+    def kappa(self, T):
+        """Conductivity (= viscosity) of temperature: T^sigma (Eq 2.50) or
+        Sutherland's law (Eq 4.12)."""
+        if self.sutherland_C > 0.0:
+            C = self.sutherland_C
+            return T * np.sqrt(T) * (1.0 + C) / (T + C)
+        return T ** self.sigma
 
     @property
     def zeta(self):
@@ -150,7 +161,7 @@ class Oracle:
         dt = CFL / max_cells[ sum_d |v_d|/h_d + 2 nu sum_d 1/h_d^2 + chi nu / Da ]
         with nu = max(Pr, 1, 1/Le_F, 1/Le_O) kappa / (Pe rho)."""
         g, p = self.g, self.p
-        kap = st.T ** p.sigma
+        kap = p.kappa(st.T)
         nu = max(p.Pr, 1.0, 1.0 / p.Le_F, 1.0 / p.Le_O) * kap / (p.Pe * st.rho)
         rate = sum(np.abs(st.v[d]) / g.h[d] for d in range(g.ndim))
         rate = rate + 2.0 * nu * sum(1.0 / g.h[d] ** 2 for d in range(g.ndim))
@@ -224,6 +235,37 @@ class Oracle:
         else:
             Tp = temperature(0.0, Hp, self.fp)
         return vp, Zp, Hp, Tp
+
+    def conductivity(self, Tp):
+        """Padded conductivity of the padded temperature. Ghosts take
+        kappa of the ghost temperature, except at an isothermal wall (a slip
+        or no-slip side with a wall H, Eq 4.16a-b), where the ghost is
+        2 kappa(T_w) - kappa(T) of the adjacent cell, so that the wall
+        face's two-cell mean is the conductivity of the wall temperature.
+        (A reading: the mirrored ghost temperature 2 T_w - T is negative
+        whenever T > 2 T_w, as at the cold wall of a cavity started from
+        the mean temperature, and kappa is undefined there.)"""
+        g, p = self.g, self.p
+        iso = [(d, s) for d in range(g.ndim) for s in (0, 1)
+               if g.bc[d][s] in ("slip", "noslip") and g.bvalue(d, s, "H", default=None) is not None]
+        if not iso:
+            return p.kappa(Tp)
+        assert not p.reacting, "isothermal walls: non-reacting flow only"
+        T = Tp.copy()
+
+        def plane(d, pos, full):
+            idx = [slice(None) if full else slice(1, -1)] * g.ndim
+            idx[g.axis(d)] = pos
+            return tuple(idx)
+
+        for d, s in iso:
+            T[plane(d, 0 if s == 0 else g.n[d] + 1, True)] = 1.0     # placeholder
+        kapp = p.kappa(T)
+        for d, s in iso:
+            Tw = temperature(0.0, np.asarray(g.bvalue(d, s, "H"), dtype=float), self.fp)
+            inner = Tp[plane(d, 1 if s == 0 else g.n[d], False)]
+            kapp[plane(d, 0 if s == 0 else g.n[d] + 1, False)] = 2.0 * p.kappa(Tw) - p.kappa(inner)
+        return kapp
 
     def _scalar_terms(self, phip, kapp, F):
         """Advective term of Eq 3.26b, sum_d avg_d(F_d delta_1 phi) (face to
@@ -327,7 +369,7 @@ class Oracle:
         taken with the given d_t p0: zero when p0 is constant."""
         g, p, fp = self.g, self.p, self.fp
         vp, Zp, Hp, Tp = self.padded_fields(st)
-        kapp = Tp ** p.sigma
+        kapp = self.conductivity(Tp)
         kap = g.interior(kapp)
         Pe = p.Pe
         chi = self.ib.get("chi")

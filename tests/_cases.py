@@ -8,7 +8,8 @@ from oracle import Grid, Oracle, Params
 from workloads import Case
 
 PARAM_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O",
-              "Da_ib", "p0", "dt", "cfl", "p0_closed", "gamma")
+              "Da_ib", "p0", "dt", "cfl", "p0_closed", "gamma",
+              "sutherland_C")
 SIDE_INDEX = {"slip", "noslip", "inflow", "outflow"}
 
 

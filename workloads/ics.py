@@ -360,6 +360,27 @@ def taylor_couette_case(n=64, Re=1.0, Da=1e-2, shifted=True, half=2.5):
     return case
 
 
+def heated_cavity_case(n=64, Ra=1e2, eps=0.6, Pr=0.71, gamma=1.4, That=600.0, Chat=110.5, cfl=0.15):
+    """Differentially heated square cavity of unit side (section 4.4): left
+    wall at T_H = 1 + eps, right wall at T_C = 1 - eps (isothermal, Eq
+    4.16a-b), adiabatic top and bottom (Eq 4.16c), every wall no-slip;
+    non-reacting with Q = S + 1 (qs = 1, T = H - 1). Scales: Pe = Pr Ra^{1/2}
+    (Eq 4.10), so Re = Ra^{1/2}; Fr = (2 Pr eps)^{1/2} (Eq 4.11); Sutherland
+    conductivity with C = Chat/That (Eq 4.12); enclosed system with gamma.
+    Initial state at rest at the mean temperature, T = 1, H = 2 (Eq 4.17),
+    p0 = 1 (so the conserved mass is 1). No random draws."""
+    nn = (n, n)
+    bc = (("noslip", "noslip"), ("noslip", "noslip"))
+    params = dict(Re=math.sqrt(Ra), Pr=Pr, inv_Fr2=1.0 / (2.0 * Pr * eps), sutherland_C=Chat / That,
+                  p0_closed=True, gamma=gamma, cfl=cfl, poisson_rtol=1e-10)
+    side = lambda Tw: dict(H=np.full(n, Tw + 1.0))
+    bnd = {(0, 0): side(1.0 + eps), (0, 1): side(1.0 - eps)}
+    case = Case(f"heated_cavity_{n}", 2, (n, n, 1), (1.0, 1.0, 1.0), bc, params,
+                np.ones(nn), [np.zeros(nn), np.zeros(nn)], bnd=bnd)
+    case.eps = eps
+    return case
+
+
 def make_case(name, **kw):
     return dict(c1=c1_case, c2=c2_case, c3=c3_case, c4=c4_case,
                 c5=c5_case)[name](**kw)
