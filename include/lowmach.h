@@ -68,7 +68,7 @@ typedef struct {
 
 /* Dimensionless parameters (section 2.6, Eq 2.42-2.50; section 4.1):
  *  Re, Pr        Pe = Re Pr; viscous factor Pr/Pe (Eq 2.43)
- *  sigma         kappa = T^sigma (Eq 2.50)
+ *  sigma         kappa = T^sigma (Eq 2.50) unless sutherland_C > 0
  *  inv_Fr2       buoyancy 1/Fr^2 (Eq 2.43, 3.8b)
  *  reacting      0: Z not transported, T = qs (H - 1); 1: flame sheet
  *  S, qs         generalised stoichiometric coefficient; qs = Q/(S+1)
@@ -109,7 +109,11 @@ typedef struct {
  *                non-reacting flow, periodic or wall sides and no mass
  *                source S_m (LM_EUNSUPPORTED / LM_EINVAL otherwise); p0 is
  *                then the initial thermodynamic pressure
- *  gamma         ratio of specific heats (p0_closed only; > 1)             */
+ *  gamma         ratio of specific heats (p0_closed only; > 1)
+ *  sutherland_C  0: kappa = T^sigma; C > 0: Sutherland's law
+ *                kappa = T^{3/2} (1 + C) / (T + C) (Eq 4.12), C the
+ *                Sutherland temperature over the reference temperature
+ *                (not with with_adjoint)                                   */
 typedef struct {
   double Re, Pr, sigma, inv_Fr2;
   int reacting;
@@ -124,6 +128,7 @@ typedef struct {
   int poisson_beta;
   int p0_closed;
   double gamma;
+  double sutherland_C;
 } lm_params;
 
 /* Field set for lm_set_fields / lm_get_fields; NULL entries are skipped.
@@ -139,11 +144,19 @@ typedef struct {
   const double *v_ib[3], *Z_ib, *H_ib, *S_m;
 } lm_ib;
 
-/* Boundary data of one inflow side: per-cell arrays over the side (C order,
- * the side's own direction removed); NULL = zero. `wall` (bytes, NULL = none)
- * flags cells of the side covered by a solid footprint: there Z and H take
- * zero-gradient ghosts (Eq 3.44) instead of Dirichlet ones (Eq 3.43); give
- * F = 0 and v = 0 on those cells.                                          */
+/* Boundary data of one side: per-cell arrays over the side (C order, the
+ * side's own direction removed).
+ * Inflow side: NULL = zero. `wall` (bytes, NULL = none) flags cells of the
+ * side covered by a solid footprint: there Z and H take zero-gradient
+ * ghosts (Eq 3.44) instead of Dirichlet ones (Eq 3.43); give F = 0 and
+ * v = 0 on those cells.
+ * Slip or no-slip wall: only H may be given (the other entries must be
+ * NULL): the wall is then isothermal, H Dirichlet with the given wall
+ * values (Eq 3.43, Eq 4.16a-b) instead of zero-gradient (adiabatic,
+ * Eq 4.16c); H = NULL makes it adiabatic again. Non-reacting flow only.
+ * The conductivity of an isothermal wall's faces is that of the wall
+ * temperature T_w = qs (H_w - 1): the mirrored ghost temperature
+ * 2 T_w - T can leave the range where kappa(T) is defined.               */
 typedef struct {
   const double *v[3], *Z, *H, *F;
   const unsigned char *wall;
@@ -201,7 +214,10 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *dev_w
  * anywhere. level must be 0.                                              */
 lm_status lm_set_fields(lm_ctx *ctx, int level, const lm_fields *f, const lm_ib *ib, int mem);
 
-/* Boundary data for an LM_SIDE_INFLOW side (dim d, side 0 = low, 1 = high). */
+/* Boundary data of side (d, side), side 0 = low, 1 = high: an inflow side,
+ * or the wall temperature of a slip / no-slip wall (see lm_side_data).
+ * LM_EINVAL for periodic or outflow sides, entries a wall cannot take;
+ * LM_EUNSUPPORTED for an isothermal wall in reacting flow.                */
 lm_status lm_set_side(lm_ctx *ctx, int d, int side, const lm_side_data *data, int mem);
 
 /* Advance nsteps predictor-corrector steps (section 3.1, Eq 3.1-3.19).

@@ -73,7 +73,7 @@ class Solver:
                  precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
                  mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False,
                  variable_coefficient: bool = False, p0_closed: bool = False, gamma: float = 1.4,
-                 device: str = "cuda:0", stream=None):
+                 sutherland_C: float = 0.0, device: str = "cuda:0", stream=None):
         import torch
         self.torch = torch
         self.lib = _L.load()
@@ -96,7 +96,7 @@ class Solver:
                          poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
                          with_ib=int(with_ib), with_adjoint=int(with_adjoint),
                          poisson_beta=_L.LM_BETA_INV_RHO if variable_coefficient else _L.LM_BETA_ONE,
-                         p0_closed=int(p0_closed), gamma=gamma)
+                         p0_closed=int(p0_closed), gamma=gamma, sutherland_C=sutherland_C)
         self.grid, self.params = g, p
         self.device = torch.device(device)
         size = C.c_size_t()
@@ -137,8 +137,9 @@ class Solver:
                                                           C.byref(ibs) if ibs is not None else None, mem))
 
     def set_side(self, d: int, side: int, v=None, Z=None, H=None, F=None, wall=None):
-        """Boundary data of an inflow side; ``wall`` flags the cells of the
-        side under a solid footprint (zero-gradient Z and H there)."""
+        """Boundary data of an inflow side (``wall`` flags the cells of the
+        side under a solid footprint: zero-gradient Z and H there), or the
+        wall value H of an isothermal slip / no-slip wall."""
         m = _Marshal(self.torch, self.device)
         s = _L.lm_side_data()
         if v is not None:

@@ -147,6 +147,14 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "gamma must exceed 1 for an enclosed system";
     return false;
   }
+  if (!(p->sutherland_C >= 0.0 && p->sutherland_C < 1e300)) {
+    *err = "sutherland_C must be >= 0 and finite";
+    return false;
+  }
+  if (p->with_adjoint && p->sutherland_C > 0.0) {
+    *err = "the adjoint supports kappa = T^sigma only";
+    return false;
+  }
   if (p->with_adjoint && p->p0_closed) {
     *err = "the adjoint needs a constant thermodynamic pressure";
     return false;
@@ -194,6 +202,7 @@ void setup_phys(lm_ctx *c) {
   P.nu_coef = nc;
   P.closed = p.p0_closed;
   P.zeta = p.p0_closed ? (p.gamma - 1.0) / (p.gamma * p.qs) : 0.0;
+  P.suth_C = p.sutherland_C;
 }
 
 // Carves every device array (or only sizes them when cv.base == nullptr).
@@ -247,7 +256,8 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
       for (int q = 0; q < 7; ++q) c->side_store[d][s][q] = nullptr;
   for (int d = 0; d < nd; ++d)
     for (int s = 0; s < 2; ++s)
-      if (c->grid.bc[d][s] == LM_SIDE_INFLOW) {
+      if (c->grid.bc[d][s] == LM_SIDE_INFLOW || c->grid.bc[d][s] == LM_SIDE_SLIP ||
+          c->grid.bc[d][s] == LM_SIDE_NOSLIP) {
         const size_t nside = (size_t)(L.ncells() / L.n[d]);
         for (int q = 0; q < 7; ++q) c->side_store[d][s][q] = (double *)cv.take(nside * 8);
       }
@@ -399,10 +409,25 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
 lm_status lm_set_side(lm_ctx *c, int d, int side, const lm_side_data *data, int mem) {
   if (!c || !data || d < 0 || d >= c->grid.ndim || side < 0 || side > 1)
     return fail(c, LM_EINVAL, "bad side arguments");
-  if (c->grid.bc[d][side] != LM_SIDE_INFLOW) return fail(c, LM_EINVAL, "side is not an inflow side");
+  const int kind = c->grid.bc[d][side];
   const size_t n = (size_t)(c->lay.ncells() / c->lay.n[d]);
   double **st = c->side_store[d][side];
   lm_status s;
+  if (kind == LM_SIDE_SLIP || kind == LM_SIDE_NOSLIP) {
+    // isothermal (H given) or adiabatic (H NULL) wall
+    if (data->v[0] || data->v[1] || data->v[2] || data->Z || data->F || data->wall)
+      return fail(c, LM_EINVAL, "a wall side takes only H (its wall temperature)");
+    if (data->H && c->prm.reacting)
+      return fail(c, LM_EUNSUPPORTED, "isothermal walls need non-reacting flow");
+    SideData &sd = c->sides.s[d][side];
+    sd.H = nullptr;
+    if (data->H) {
+      if ((s = copy_side(c, data->H, st[4], n, mem)) != LM_OK) return s;
+      sd.H = st[4];
+    }
+    return LM_OK;
+  }
+  if (kind != LM_SIDE_INFLOW) return fail(c, LM_EINVAL, "side is not an inflow or wall side");
   for (int q = 0; q < 3; ++q) {
     if (q >= c->grid.ndim) break;
     if ((s = copy_side(c, data->v[q], st[q], n, mem)) != LM_OK) return s;

@@ -120,4 +120,14 @@ __device__ inline double temperature(const Phys &P, double Z, double H) {
 
 __device__ inline double theta_eps(const Phys &P, double Z) { return 0.5 * (1.0 + tanh(P.k * (Z - 1.0))); }
 
+// Conductivity (= viscosity, Eq 2.49-2.50) of temperature: T^sigma, or
+// Sutherland's law T^{3/2} (1 + C)/(T + C) (Eq 4.12).
+__device__ inline double kappa_of(const Phys &P, double T) {
+  if (P.suth_C > 0.0) {
+    const double C = P.suth_C;
+    return T * sqrt(T) * (1.0 + C) / (T + C);
+  }
+  return pow(T, P.sigma);
+}
+
 }  // namespace lm

@@ -24,6 +24,10 @@ __device__ inline long side_index(const Lay &L, int d, int i, int j, int k) {
 
 enum { R_PER = 0, R_DIR = 1, R_NEU = 2, R_EXT = 3 };
 
+// A wall side with a given scalar (only H: an isothermal wall) takes it as
+// a Dirichlet value (Eq 3.43); otherwise wall scalars are zero-gradient.
+__device__ inline bool wall_scalar(const SideData &q, int f) { return (f == 4 && q.H) || (f == 3 && q.Z); }
+
 // Ghost rule of field f (0..2 velocity components, 3 Z, 4 H) on side (d, s)
 // at position (i, j, k) (used for the solid footprint of inflow sides).
 __device__ inline int ghost_rule(const Bnd &B, const Sides &sd, const Lay &L, int d, int s, int f, int i, int j,
@@ -37,9 +41,28 @@ __device__ inline int ghost_rule(const Bnd &B, const Sides &sd, const Lay &L, in
       if (f >= 3 && w && w[side_index(L, d, i, j, k)]) return R_NEU;
       return R_DIR;
     }
-    case LM_SIDE_NOSLIP: return f < 3 ? R_DIR : R_NEU;
-    default: return (f == d) ? R_DIR : R_NEU;  // slip wall
+    case LM_SIDE_NOSLIP: return (f < 3 || wall_scalar(sd.s[d][s], f)) ? R_DIR : R_NEU;
+    default: return (f == d || wall_scalar(sd.s[d][s], f)) ? R_DIR : R_NEU;  // slip wall
   }
+}
+
+// Isothermal wall: the highest direction in which (i, j, k) lies outside
+// the box on a slip / no-slip side with a wall H (false if none).
+template <int DIM>
+__device__ inline bool isothermal_ghost(const Lay &L, const Bnd &B, const Sides &sd, int i, int j, int k, int &dw,
+                                        int &sw) {
+  const int q[3] = {i, j, k};
+  for (int d = DIM - 1; d >= 0; --d) {
+    if (q[d] >= 0 && q[d] < L.n[d]) continue;
+    const int s = q[d] < 0 ? 0 : 1;
+    const int kind = B.kind[d][s];
+    if ((kind == LM_SIDE_SLIP || kind == LM_SIDE_NOSLIP) && sd.s[d][s].H) {
+      dw = d;
+      sw = s;
+      return true;
+    }
+  }
+  return false;
 }
 
 __device__ inline double side_value(const Sides &sd, const Lay &L, int d, int s, int f, int i, int j,
@@ -188,7 +211,18 @@ __global__ void __launch_bounds__(kBlock) k_ghosts_general(Lay L, Bnd B, Phys P,
   const double Zc = P.reacting ? fmin(fmax(Z, 0.0), P.S + 1.0) : 0.0;
   const double T = temperature(P, Zc, H);
   g.T[dst] = T;
-  g.kap[dst] = pow(T, P.sigma);
+  int dw, sw;
+  if (isothermal_ghost<DIM>(L, B, sd, i, j, k, dw, sw)) {
+    // the wall face takes the conductivity of the wall temperature: the
+    // ghost is its mirror through the face (the mirrored temperature
+    // 2 T_w - T can be out of the range of kappa in a start-up transient)
+    const double Tw = temperature(P, 0.0, side_value(sd, L, dw, sw, 4, i, j, k));
+    const long src = L.at(min(max(i, 0), L.n[0] - 1), min(max(j, 0), L.n[1] - 1),
+                          DIM == 3 ? min(max(k, 0), L.n[2] - 1) : k);
+    g.kap[dst] = 2.0 * kappa_of(P, Tw) - kappa_of(P, g.T[src]);
+  } else {
+    g.kap[dst] = kappa_of(P, T);
+  }
 }
 
 hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,
@@ -380,7 +414,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
   if (P.reacting) a.out.Z[c] = Z;
   a.out.T[c] = T;
   a.out.rho[c] = P.p0 / T;
-  a.out.kap[c] = pow(T, P.sigma);
+  a.out.kap[c] = kappa_of(P, T);
 }
 
 hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, const Phys &P,
@@ -634,7 +668,7 @@ __global__ void __launch_bounds__(kBlock) k_init_state(Lay L, Phys P, Level lv, 
   if (!(T > 0.0)) atomicOr(bad, 1);
   lv.T[c] = T;
   lv.rho[c] = P.p0 / T;
-  lv.kap[c] = pow(T, P.sigma);
+  lv.kap[c] = kappa_of(P, T);
 }
 
 hipError_t launch_init_state(hipStream_t st, const Lay &L, const Phys &P, const Bnd &B,
@@ -890,7 +924,7 @@ __global__ void __launch_bounds__(kBlock) k_p0_startup(Lay L, Phys P, const P0De
   const double T = temperature(P, 0.0, H);
   out.H[c] = H;
   out.T[c] = T;
-  out.kap[c] = pow(T, P.sigma);
+  out.kap[c] = kappa_of(P, T);
 }
 
 // Commit of a completed step: history shift and d_t p0 at the new level n

@@ -47,6 +47,7 @@ struct Phys {
   double nu_coef;   // max(Pr, 1, 1/Le_F, 1/Le_O)
   int closed;       // enclosed system: p0 from the conserved mass (Eq 2.40)
   double zeta;      // (gamma - 1)/(gamma qs): factor of the d_t p0 source (Eq 3.4b)
+  double suth_C;    // > 0: Sutherland's law for kappa (Eq 4.12); 0: kappa = T^sigma
 };
 
 // Thermodynamic pressure of an enclosed system, on the device (the step
@@ -78,7 +79,8 @@ struct IB {
   const double *v_ib[3], *Z_ib, *H_ib, *S_m;
 };
 
-// Inflow side data (compact, per side cell), device pointers or NULL.
+// Side data (compact, per side cell), device pointers or NULL: the values
+// of an inflow side, or the wall H of an isothermal slip / no-slip wall.
 struct SideData {
   const double *v[3], *Z, *H, *F;
   const unsigned char *wall;  // solid footprint cells of an inflow side

@@ -34,7 +34,7 @@ class lm_params(C.Structure):
                 ("Da_ib", C.c_double), ("p0", C.c_double), ("dt", C.c_double), ("cfl", C.c_double),
                 ("precision", C.c_int), ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int),
                 ("mg_nu", C.c_int), ("with_ib", C.c_int), ("with_adjoint", C.c_int), ("poisson_beta", C.c_int),
-                ("p0_closed", C.c_int), ("gamma", C.c_double)]
+                ("p0_closed", C.c_int), ("gamma", C.c_double), ("sutherland_C", C.c_double)]
 
 
 class lm_fields(C.Structure):

@@ -140,3 +140,21 @@ def test_enclosed_system_checks_without_gpu():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     p.p0_closed = 2
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+
+
+def test_sutherland_checks_without_gpu():
+    """sutherland_C must be >= 0 and finite; the adjoint keeps
+    kappa = T^sigma."""
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b = C.c_size_t()
+    g, p = _grid_params((64, 64))
+    p.sutherland_C = 110.5 / 600.0
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+    p.sutherland_C = -1.0
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.sutherland_C = float("nan")
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.sutherland_C, p.with_adjoint = 0.2, 1
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    assert "sigma" in L.lm_last_error(None).decode()
