@@ -79,3 +79,25 @@ def test_slot_flame_differential_diffusion():
     errs = compare(st, s.get(device=False))
     print(errs, s.stats, flush=True)
     _check(errs)
+
+
+@pytest.mark.parametrize("n,steps,precision", [(96, 3, "fp64"), (96, 2, "mixed"), (80, 2, "fp64")],
+                         ids=["96-fp64", "96-mixed", "80-ragged"])
+def test_double_tsuji_quadrant(n, steps, precision):
+    """One quadrant of the double Tsuji burner (section 4.5): a penalised
+    cylinder with the radial mass source S_m = chi rho_b U_b / r (Eq 4.19)
+    and radial ejection velocity (Eq 4.20), fuel targets (Eq 4.21),
+    symmetry sides, a stagnation-flow inflow and an outflow (Eq 4.22),
+    started from the potential flow and flame profiles of Eq 4.23-4.24;
+    reacting with Le_F = 0.97, Le_O = 1.11."""
+    from workloads import double_tsuji_case
+    case = double_tsuji_case(n=n)
+    print("double tsuji", n, steps, precision, flush=True)
+    o, st = oracle_for(case)
+    st = o.run(st, steps)
+    s = gpu_for(case, precision=precision)
+    assert abs(s.dt / o.dt - 1) < 1e-13
+    s.step(steps)
+    errs = compare(st, s.get(device=False))
+    print(errs, s.stats, flush=True)
+    _check(errs)

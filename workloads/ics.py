@@ -381,6 +381,58 @@ def heated_cavity_case(n=64, Ra=1e2, eps=0.6, Pr=0.71, gamma=1.4, That=600.0, Ch
     return case
 
 
+def double_tsuji_case(n=96, half=6.0, Ub=0.1, Da=1e-4, wF=2.0, TF=1.3, shifted=True):
+    """One quadrant [0, half]^2 (n^2 cells) of the double Tsuji burner
+    (section 4.5): a cylinder of radius 1 at the origin ejecting fuel
+    radially into planar counterflowing oxidiser jets. Symmetry (slip)
+    sides on x = 0 and y = 0 (Eq 4.22a-b), inflow v = (x, -y) with Z = 0,
+    H = H_inf at the top and outflow on the right (Eq 4.22c). Burner as a
+    penalised body: chi = 1 for r < 1 + s, s = sqrt(Da) (shifted) or 0;
+    mass source S_m = chi rho_b U_b / r (Eq 4.19) with rho_b = 1 (the fuel
+    leaves at T = 1), targets v_ib = U_b x / r (Eq 4.20), Z_ib = S + 1 and
+    H_ib = (S+1)/Q + 1 (Eq 4.21). Parameters of section 4.5: Pr = 0.71,
+    Re = 100, U_b = 0.1, S = 14.89, Q = 4.17, Le_F = 0.97, Le_O = 1.11,
+    Da_ib = 1e-4, eps = 0.5 (tol = 1e-3). Initial state: the potential flow
+    of Eq 4.23 and the Z, H profiles of Eq 4.24 outside the body, with the
+    flame width w_F and temperature T_F (taken from a reference the paper
+    cites, not given: w_F = 2, T_F = 1.3 by default); the body targets
+    inside it. No random draws."""
+    S, Q = 14.89, 4.17
+    qs = Q / (S + 1.0)
+    Hinf = (S + 1.0) / Q + 1.0
+    h = half / n
+    L = (half, half)
+    x, y = cell_centres((n, n), L)
+    X, Y = np.broadcast_arrays(x, y)
+    r2 = X * X + Y * Y
+    r = np.sqrt(r2)
+    sft = math.sqrt(Da) if shifted else 0.0
+    chi = (r < 1.0 + sft).astype(np.uint8)
+    body = chi.astype(bool)
+    vib = [Ub * X / r, Ub * Y / r]
+    # potential flow of Eq 4.23, evaluated outside the body only
+    rr2 = np.where(body, 1.0, r2)
+    v1 = X * (1.0 - (X * X - 3.0 * Y * Y) / rr2 ** 3 + Ub / rr2)
+    v2 = -Y * (1.0 + (3.0 * X * X - Y * Y) / rr2 ** 3 - Ub / rr2)
+    v = [np.where(body, vib[0], v1), np.where(body, vib[1], v2)]
+    a = Ub / wF ** 2
+    Z = np.sqrt((1.0 + a) / ((X / wF) ** 2 + a)) * np.exp(-Y * Y / 2.0)
+    H = ((S + 1.0) / Q * (TF - 1.0) - 1.0) * Z + (S + 1.0) / Q + 1.0
+    Z = np.where(body, S + 1.0, Z)
+    H = np.where(body, Hinf, H)
+    Sm = np.where(body, Ub / r, 0.0)
+    xc = (np.arange(n) + 0.5) * h
+    bnd = {(1, 1): dict(v=[xc.copy(), np.full(n, -half)], Z=np.zeros(n), H=np.full(n, Hinf),
+                        F=np.full(n, -half))}
+    params = dict(Re=100.0, Pr=0.71, reacting=1, S=S, qs=qs, eps=0.5, tol=1e-3, Le_F=0.97, Le_O=1.11,
+                  Da_ib=Da, p0=1.0, cfl=0.2, poisson_rtol=1e-10)
+    ib = dict(chi=chi, v_ib=vib, Z_ib=np.full((n, n), S + 1.0), H_ib=np.full((n, n), Hinf), Sm=Sm)
+    case = Case(f"double_tsuji_{n}", 2, (n, n, 1), L + (1.0,), (("slip", "outflow"), ("slip", "inflow")),
+                params, None, v, Z=Z, ib=ib, bnd=bnd, H=H)
+    case.injected_rate = float(np.sum(Sm) * h * h)
+    return case
+
+
 def make_case(name, **kw):
     return dict(c1=c1_case, c2=c2_case, c3=c3_case, c4=c4_case,
                 c5=c5_case)[name](**kw)
