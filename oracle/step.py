@@ -39,7 +39,8 @@ class Params:
     from the conserved mass, p0 = m / integral(1/T) (Eq 2.40), with the
     zeta d_t p0 source of the excess-enthalpy equation (Eq 2.45, 3.4b),
     zeta = (S+1)(gamma-1)/(gamma Q) = (gamma-1)/(gamma qs); dt = 0 asks for a
-    step fixed once from the CFL number of the initial state."""
+    step fixed once from the CFL number of the initial state; dt_tol > 0
+    makes the step adaptive (see Oracle.next_dt)."""
     Re: float = 100.0
     Pr: float = 0.7
     sigma: float = 0.7
@@ -58,6 +59,7 @@ class Params:
     p0_closed: bool = False
     gamma: float = 1.4
     sutherland_C: float = 0.0
+    dt_tol: float = 0.0
 
     def kappa(self, T):
         """Conductivity (= viscosity) of temperature: T^sigma (Eq 2.50) or
@@ -94,6 +96,8 @@ class State:
     nstep: int = 0
     p0: float = 1.0                           # thermodynamic pressure at level n
     p0_hist: tuple = ()                       # p0 at levels n-1, n-2 (closed systems)
+    dt_prev: float = 0.0                      # step from level n-1 to n (adaptive steps)
+    nsame: int = 0                            # steps of that size in a row (adaptive steps)
 
     def copy(self):
         c = lambda a: None if a is None else a.copy()
@@ -101,7 +105,7 @@ class State:
                      c(self.P), [a.copy() for a in self.F], c(self.rho_prev),
                      None if self.R_prev is None else {k: ([a.copy() for a in v] if isinstance(v, list) else v.copy())
                                                        for k, v in self.R_prev.items()},
-                     self.nstep, self.p0, tuple(self.p0_hist))
+                     self.nstep, self.p0, tuple(self.p0_hist), self.dt_prev, self.nsame)
 
 
 class Oracle:
@@ -135,6 +139,8 @@ class Oracle:
             open_side = any(g.bc[d][s] in ("inflow", "outflow") for d in range(g.ndim) for s in (0, 1))
             if open_side or self.ib.get("Sm") is not None or self.p.reacting:
                 raise ValueError("p0_closed needs walls or periodic sides, no mass source, non-reacting flow")
+            if self.p.dt_tol > 0.0:
+                raise ValueError("adaptive steps need a constant p0")
         Zs = None
         if self.p.reacting:
             Zs = np.zeros(g.shape) if Z is None else _real_or_complex(Z)
@@ -482,10 +488,18 @@ class Oracle:
             Rn = self.residuals(st, self.ddt_p0(st.p0, st.p0_hist) if closed else 0.0)
         first = st.R_prev is None
         M0 = [st.rho * st.v[i] for i in range(g.ndim)]
+        adaptive = p.dt_tol > 0.0
+        # ratio of this step to the previous one (adaptive steps)
+        w = dt / st.dt_prev if (adaptive and st.dt_prev > 0.0) else 1.0
 
         def ab2(x, rn, rp):
             if first:
                 return x + dt * rn
+            if adaptive:
+                # Adams-Bashforth 2 for unequal steps: the residual
+                # extrapolated linearly through t_{n-1}, t_n and integrated
+                # over [t_n, t_n + dt]
+                return x + dt * ((1.0 + 0.5 * w) * rn - 0.5 * w * rp)
             return x + dt * (1.5 * rn - 0.5 * rp)
 
         def am2(x, rs, rn):
@@ -494,6 +508,11 @@ class Oracle:
         def ddt(rnew):
             if st.rho_prev is None:
                 return (rnew - st.rho) / dt
+            if adaptive:
+                # BDF2 for unequal steps: derivative at t_{n+1} of the
+                # quadratic through (t_{n-1}, t_n, t_{n+1})
+                return ((1.0 + 2.0 * w) / (1.0 + w) * rnew - (1.0 + w) * st.rho
+                        + w * w / (1.0 + w) * st.rho_prev) / dt
             return (3.0 * rnew - 4.0 * st.rho + st.rho_prev) / (2.0 * dt)
 
         # ---- predictor
@@ -517,13 +536,60 @@ class Oracle:
         rho1 = p01 / T1
         P1, F1, v1, b1 = self.project(M1, rho1, ddt(rho1), "corr")
         out = State(rho1, v1, Z1, H1, T1, P1, F1, rho_prev=st.rho, R_prev=Rn,
-                    nstep=st.nstep + 1, p0=p01, p0_hist=(st.p0,) + tuple(st.p0_hist[:1]))
+                    nstep=st.nstep + 1, p0=p01, p0_hist=(st.p0,) + tuple(st.p0_hist[:1]), dt_prev=dt)
         rms = lambda a: float(np.sqrt(np.mean(np.abs(a) ** 2)))
         self.stats["pc_diff_v"] = [rms(vs[i] - v1[i]) for i in range(g.ndim)]
         self.stats["pc_diff_P"] = rms(Ps - P1)
         self.stats["pc_diff_H"] = rms(Hs - H1)
         self.last_predicted = sts
+        if adaptive:
+            err = self.pc_error(sts, out)
+            self.stats["pc_err"] = err
+            self.stats["dt"] = dt
+            out.nsame = st.nsame + 1 if (not first and dt == st.dt_prev) else 1
+            clean = out.nsame >= 4
+            self.stats["pc_err_clean"] = clean
+            self.dt = self.next_dt(dt, err, out, clean)
         return out
+
+    def pc_error(self, sts: State, out: State):
+        """Local error estimate of a step: the difference between the
+        predicted and corrected levels (the estimate behind Tab 2, which
+        the paper proposes for adaptive steps): the largest of the RMS of
+        |v* - v^{n+1}| (vector norm), the RMS of H* - H^{n+1} and, with
+        reaction, the RMS of Z* - Z^{n+1} over S + 1."""
+        dv2 = sum((a - b) ** 2 for a, b in zip(sts.v, out.v))
+        err = max(math.sqrt(float(np.mean(dv2))), math.sqrt(float(np.mean((sts.H - out.H) ** 2))))
+        if self.p.reacting:
+            err = max(err, math.sqrt(float(np.mean((sts.Z - out.Z) ** 2))) / (self.p.S + 1.0))
+        return err
+
+    def next_dt(self, dt, err, st: State, clean=True):
+        """Adaptive step (a reading; the paper only names the estimate).
+        The local error of the AB2/AM2 pair is O(dt^3): a decision takes
+        the factor 0.9 (dt_tol / err)^{1/3} kept in [0.5, 1.5] (1.5 when
+        err = 0) and applies it only outside [0.9, 1.1], so that the step
+        stays put while the estimate lies between about 0.55 and 1.0 times
+        dt_tol. Only the estimate of the fourth or a later step of exactly
+        one size decides: on the collocated grid the cell velocity keeps an
+        O(h^2) part proportional to the step (the projection subtracts
+        delta_2 P, P = p dt), so levels made by steps of different sizes
+        differ by O(h^2 |dt - dt_prev|), which the AB2 extrapolation of the
+        next two steps turns into an O(h^2 dt |dt - dt_prev|) term of the
+        estimate (decaying by about two orders per step after that); the
+        Euler-predicted start behaves alike. The step never exceeds the CFL
+        step of the new state: growth stops at it, and when it falls below
+        the current step the step drops to 0.9 of it. No step is
+        rejected."""
+        cap = self.cfl_dt(st)
+        new = dt
+        if clean:
+            fac = 1.5 if err <= 0.0 else min(1.5, max(0.5, 0.9 * (self.p.dt_tol / err) ** (1.0 / 3.0)))
+            if fac <= 0.9 or fac >= 1.1:
+                new = min(dt * fac, cap)
+        if new > cap:
+            new = 0.9 * cap
+        return new
 
     def run(self, st: State, nsteps: int) -> State:
         for _ in range(nsteps):
