@@ -113,7 +113,20 @@ typedef struct {
  *  sutherland_C  0: kappa = T^sigma; C > 0: Sutherland's law
  *                kappa = T^{3/2} (1 + C) / (T + C) (Eq 4.12), C the
  *                Sutherland temperature over the reference temperature
- *                (not with with_adjoint)                                   */
+ *                (not with with_adjoint)
+ *  dt_tol        0: fixed time step. > 0: adaptive step driven by the
+ *                predictor-corrector difference (the local-error estimate
+ *                of the step, O(dt^3)): err = the largest of the RMS of
+ *                |v* - v^{n+1}|, of H* - H^{n+1} and (reacting) of
+ *                (Z* - Z^{n+1})/(S+1). After the fourth or a later step of
+ *                exactly one size, the factor 0.9 (dt_tol/err)^{1/3}
+ *                (in [0.5, 1.5]) is applied when it lies outside
+ *                [0.9, 1.1]; growth stops at the CFL step of the new state
+ *                (cfl > 0 required) and the step drops to 0.9 of it when
+ *                that falls below the current step. Unequal steps use
+ *                Adams-Bashforth 2 and BDF2 for unequal spacing. Steps are
+ *                never rejected. Not with p0_closed (LM_EUNSUPPORTED) or
+ *                with_adjoint.                                            */
 typedef struct {
   double Re, Pr, sigma, inv_Fr2;
   int reacting;
@@ -129,6 +142,7 @@ typedef struct {
   int p0_closed;
   double gamma;
   double sutherland_C;
+  double dt_tol;
 } lm_params;
 
 /* Field set for lm_set_fields / lm_get_fields; NULL entries are skipped.
@@ -164,13 +178,15 @@ typedef struct {
 
 typedef struct {
   int steps;                 /* steps taken by the call                      */
-  double dt;                 /* time step in use                             */
+  double dt;                 /* size of the last step taken (lm_get_dt: next) */
   double time;               /* simulated time since lm_set_fields           */
   int poisson_iters[2];      /* last step: predictor, corrector iterations   */
   double poisson_relres[2];  /* last step: final recursive relative residual */
   double compat[2];          /* last step: mean(b) removed before each solve */
   long long total_poisson_iters;
   double p0;                 /* thermodynamic pressure at the end of the call */
+  double pc_err;             /* adaptive steps: last step's error estimate    */
+  int pc_err_used;           /* adaptive steps: 1 if it decided the next step */
 } lm_step_stats;
 
 /* RHS-mode projection: solve A P = b for the zero-mean P, with
@@ -231,7 +247,8 @@ lm_status lm_project(lm_ctx *ctx, lm_project_args *args);
 /* Copy the current state (level 0 = time n) into caller arrays. */
 lm_status lm_get_fields(lm_ctx *ctx, int level, lm_fields *f, int mem);
 
-/* The fixed time step (after lm_set_fields when params.dt == 0). */
+/* The time step of the next lm_step (fixed once after lm_set_fields when
+ * params.dt == 0; updated after every step when params.dt_tol > 0). */
 lm_status lm_get_dt(const lm_ctx *ctx, double *dt);
 
 /* ---- checkpoint / restart ------------------------------------------------

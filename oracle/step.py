@@ -510,9 +510,11 @@ class Oracle:
                 return (rnew - st.rho) / dt
             if adaptive:
                 # BDF2 for unequal steps: derivative at t_{n+1} of the
-                # quadratic through (t_{n-1}, t_n, t_{n+1})
-                return ((1.0 + 2.0 * w) / (1.0 + w) * rnew - (1.0 + w) * st.rho
-                        + w * w / (1.0 + w) * st.rho_prev) / dt
+                # quadratic through (t_{n-1}, t_n, t_{n+1}), written with
+                # the level differences (the weights of rho^{n+1}, rho^n,
+                # rho^{n-1} are (1+2w)/(1+w), -(1+w), w^2/(1+w), over dt)
+                return ((1.0 + 2.0 * w) / (1.0 + w) * (rnew - st.rho)
+                        - w * w / (1.0 + w) * (st.rho - st.rho_prev)) / dt
             return (3.0 * rnew - 4.0 * st.rho + st.rho_prev) / (2.0 * dt)
 
         # ---- predictor

@@ -73,7 +73,7 @@ class Solver:
                  precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
                  mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False,
                  variable_coefficient: bool = False, p0_closed: bool = False, gamma: float = 1.4,
-                 sutherland_C: float = 0.0, device: str = "cuda:0", stream=None):
+                 sutherland_C: float = 0.0, dt_tol: float = 0.0, device: str = "cuda:0", stream=None):
         import torch
         self.torch = torch
         self.lib = _L.load()
@@ -96,7 +96,8 @@ class Solver:
                          poisson_rtol=poisson_rtol, poisson_maxit=poisson_maxit, mg_nu=mg_nu,
                          with_ib=int(with_ib), with_adjoint=int(with_adjoint),
                          poisson_beta=_L.LM_BETA_INV_RHO if variable_coefficient else _L.LM_BETA_ONE,
-                         p0_closed=int(p0_closed), gamma=gamma, sutherland_C=sutherland_C)
+                         p0_closed=int(p0_closed), gamma=gamma, sutherland_C=sutherland_C,
+                         dt_tol=dt_tol)
         self.grid, self.params = g, p
         self.device = torch.device(device)
         size = C.c_size_t()
@@ -155,7 +156,8 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.lm_step(self.ctx, nsteps, C.byref(st)))
         self.stats = dict(steps=st.steps, dt=st.dt, time=st.time, poisson_iters=list(st.poisson_iters),
                           poisson_relres=list(st.poisson_relres), compat=list(st.compat),
-                          total_poisson_iters=st.total_poisson_iters, p0=st.p0)
+                          total_poisson_iters=st.total_poisson_iters, p0=st.p0, pc_err=st.pc_err,
+                          pc_err_used=bool(st.pc_err_used))
         return self.stats
 
     def get(self, names=("rho", "v", "H", "T", "P", "F", "Z"), device: bool = True) -> dict:

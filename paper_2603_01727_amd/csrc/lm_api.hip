@@ -47,6 +47,12 @@ struct lm_ctx {
   int ad_cur;
   double *aw[20];
   P0Dev *p0d;            // enclosed-system thermodynamic pressure (device)
+  // adaptive time step
+  double dt_prev;        // size of the step that made level n (0 before the first)
+  int nsame;             // steps of that size in a row
+  double dt_last;        // size of the last step taken
+  double pc_err;         // its predictor-corrector estimate
+  int pc_used;           // 1 if that estimate decided the next step
 };
 
 namespace {
@@ -151,6 +157,18 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "sutherland_C must be >= 0 and finite";
     return false;
   }
+  if (!(p->dt_tol >= 0.0 && p->dt_tol < 1e300)) {
+    *err = "dt_tol must be >= 0 and finite";
+    return false;
+  }
+  if (p->dt_tol > 0.0 && !(p->cfl > 0.0)) {
+    *err = "an adaptive step (dt_tol > 0) needs cfl > 0";
+    return false;
+  }
+  if (p->with_adjoint && p->dt_tol > 0.0) {
+    *err = "the adjoint needs a fixed time step";
+    return false;
+  }
   if (p->with_adjoint && p->sutherland_C > 0.0) {
     *err = "the adjoint supports kappa = T^sigma only";
     return false;
@@ -215,6 +233,10 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
         open = open || c->grid.bc[d][s] == LM_SIDE_INFLOW || c->grid.bc[d][s] == LM_SIDE_OUTFLOW;
     if (open || c->prm.reacting) {
       if (err) *err = "an enclosed system needs periodic or wall sides and non-reacting flow";
+      return false;
+    }
+    if (c->prm.dt_tol > 0.0) {
+      if (err) *err = "adaptive steps are not available for an enclosed system";
       return false;
     }
   }
@@ -538,6 +560,68 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
   c->have_state = 1;
   c->have_prev = 0;
   c->time = 0.0;
+  c->dt_prev = 0.0;
+  c->nsame = 0;
+  c->dt_last = c->phys.dt;
+  c->pc_err = 0.0;
+  c->pc_used = 0;
+  c->phys.var_step = 0;
+  return LM_OK;
+}
+
+// Weights of the predictor's AB2 and of the BDF2 density derivative for a
+// step after one of another size (adaptive steps), w = dt / dt_prev:
+// AB2 integrates the line through R^{n-1}, R^n over the step,
+// R^n (1 + w/2) - R^{n-1} w/2; BDF2 differentiates the parabola through
+// rho^{n-1}, rho^n, rho^{n+1} at t_{n+1}, taken in the differences of the
+// levels (weights (1+2w)/(1+w) and w^2/(1+w)) so that rounding scales with
+// the change of rho, not with rho / dt.
+static void set_step_weights(lm_ctx *c) {
+  Phys &P = c->phys;
+  P.var_step = 0;
+  if (!(c->prm.dt_tol > 0.0) || !c->have_prev) return;
+  const double dt = P.dt, w = dt / c->dt_prev;
+  P.var_step = 1;
+  P.ab0 = 1.0 + 0.5 * w;
+  P.ab1 = -0.5 * w;
+  P.bd0 = (1.0 + 2.0 * w) / (1.0 + w);
+  P.bd2 = w * w / (1.0 + w);
+}
+
+// After a committed step (adaptive steps): the step's error estimate from
+// the predicted and new levels, then the next step. Only the fourth or a
+// later step of exactly one size decides: levels made by steps of different
+// sizes differ by O(h^2 |dt - dt_prev|) in the cell velocity (the
+// projection subtracts delta_2 P with P = p dt), which the AB2
+// extrapolation of the next two steps carries into the estimate; the
+// Euler-predicted first step behaves alike.
+static lm_status adapt_dt(lm_ctx *c, int first) {
+  const Lay &L = c->lay;
+  Level &nw = c->lev[c->icur];
+  HIPCHK(c, launch_pc_err(c->st, L, c->prm.reacting, c->lev[c->istar], nw, c->pws.partials, c->dscalar + 1));
+  HIPCHK(c, launch_cfl(c->st, L, c->phys, nw, c->ib.chi, c->pws.partials + 3 * kErrBlocks, c->dscalar));
+  HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, 32, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const double N = (double)L.ncells();
+  double err = std::max(std::sqrt(c->hscalar[1] / N), std::sqrt(c->hscalar[2] / N));
+  if (c->prm.reacting) err = std::max(err, std::sqrt(c->hscalar[3] / N) / (c->prm.S + 1.0));
+  const double dt = c->phys.dt;
+  const double cap = c->prm.cfl / c->hscalar[0];
+  if (!(cap > 0) || !std::isfinite(cap) || !std::isfinite(err))
+    return fail(c, LM_ENONFINITE, "adaptive step: non-finite error estimate or CFL step");
+  c->nsame = (!first && dt == c->dt_prev) ? c->nsame + 1 : 1;
+  c->pc_err = err;
+  c->pc_used = c->nsame >= 4;
+  double nd = dt;
+  if (c->pc_used) {
+    const double fac =
+        err <= 0.0 ? 1.5 : std::min(1.5, std::max(0.5, 0.9 * std::cbrt(c->prm.dt_tol / err)));
+    if (fac <= 0.9 || fac >= 1.1) nd = std::min(dt * fac, cap);
+  }
+  if (nd > cap) nd = 0.9 * cap;
+  c->dt_last = dt;
+  c->dt_prev = dt;
+  c->phys.dt = nd;
   return LM_OK;
 }
 
@@ -561,6 +645,13 @@ static lm_status do_stage(lm_ctx *c, int corrector, int &iters, double &relres, 
   HIPCHK(c, launch_rhs(c->st, L, c->bnd, c->phys, c->sides, c->M, out.rho, A.rho, c->rho_prev, !first, c->ib.S_m,
                        c->b, c->pws.partials, c->pws.sc));
   const double *x0 = corrector ? c->P[c->istar] : c->P[c->icur];
+  if (!corrector && c->phys.var_step && c->phys.dt != c->dt_prev) {
+    // P = p dt: after a change of step the previous pressure, scaled by
+    // dt / dt_prev, is the warm start (in the predicted level's slot,
+    // which the predictor overwrites anyway)
+    HIPCHK(c, launch_scale_copy(c->st, L.total, c->phys.dt / c->dt_prev, c->P[c->icur], c->P[c->istar]));
+    x0 = c->P[c->istar];
+  }
   int conv = 0;
   const int expect = c->last_iters[corrector];
   HIPCHK(c, poisson_solve(c->st, c->pws, c->b, x0, c->prm.poisson_rtol, c->prm.poisson_maxit, expect, &iters,
@@ -583,6 +674,7 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
   int it[2] = {0, 0};
   double rr[2] = {0, 0}, cm[2] = {0, 0};
   for (int n = 0; n < nsteps; ++n) {
+    set_step_weights(c);
     HIPCHK(c, hipMemsetAsync(c->dflags + 1, 0, 4, c->st));
     lm_status s = do_stage(c, 0, it[0], rr[0], cm[0]);
     if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
@@ -594,7 +686,7 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
     if (s != LM_OK) {
       if (stats) {
         stats->steps = done;
-        stats->dt = c->phys.dt;
+        stats->dt = c->dt_last;
         stats->time = c->time;
       }
       return s;
@@ -607,14 +699,22 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
     c->lev[c->icur].rho = old_prev;
     std::swap(c->icur, c->inxt);
     c->rprev ^= 1;
+    const int first = !c->have_prev;
     c->have_prev = 1;
     c->time += c->phys.dt;
     ++done;
+    if (c->prm.dt_tol > 0.0) {
+      if ((s = adapt_dt(c, first)) != LM_OK) return s;
+    } else {
+      c->dt_last = c->phys.dt;
+    }
   }
   if (stats) {
     stats->steps = done;
-    stats->dt = c->phys.dt;
+    stats->dt = c->dt_last;
     stats->time = c->time;
+    stats->pc_err = c->pc_err;
+    stats->pc_err_used = c->pc_used;
     for (int q = 0; q < 2; ++q) {
       stats->poisson_iters[q] = it[q];
       stats->poisson_relres[q] = rr[q];
@@ -762,6 +862,8 @@ struct StateHeader {
   int have_prev, have_state;
   double time;
   int last_iters[2];
+  double dt, dt_prev, dt_last, pc_err;  // time step and the adaptive-step history
+  int nsame, pc_used;
 };
 // Header bytes [0, 128): StateHeader; [128, 256): the device p0 state.
 static_assert(sizeof(StateHeader) <= 128 && sizeof(P0Dev) <= 128, "state header layout");
@@ -820,7 +922,9 @@ extern "C" lm_status lm_save_state(lm_ctx *c, void *buf) {
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
   double *arr[32];
   const int k = state_arrays(c, arr);
-  StateHeader h{c->have_prev, c->have_state, c->time, {c->last_iters[0], c->last_iters[1]}};
+  StateHeader h{c->have_prev, c->have_state, c->time, {c->last_iters[0], c->last_iters[1]},
+                c->phys.dt,  c->dt_prev,     c->dt_last, c->pc_err,
+                c->nsame,    c->pc_used};
   HIPCHK(c, hipMemcpyAsync(buf, &h, sizeof(h), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync((char *)buf + 128, c->p0d, sizeof(P0Dev), hipMemcpyDeviceToDevice, c->st));
   char *p = (char *)buf + 256;
@@ -846,6 +950,12 @@ extern "C" lm_status lm_load_state(lm_ctx *c, const void *buf) {
   c->time = h.time;
   c->last_iters[0] = h.last_iters[0];
   c->last_iters[1] = h.last_iters[1];
+  c->phys.dt = h.dt;
+  c->dt_prev = h.dt_prev;
+  c->dt_last = h.dt_last;
+  c->pc_err = h.pc_err;
+  c->nsame = h.nsame;
+  c->pc_used = h.pc_used;
   return LM_OK;
 }
 

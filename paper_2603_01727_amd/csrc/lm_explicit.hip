@@ -396,6 +396,13 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
       if (P.reacting) Z = a.n0.Z[c] + dt * RZ;
 #pragma unroll
       for (int i = 0; i < DIM; ++i) a.M[i][c] = rho0 * a.n0.v[i][c] + dt * Rv[i];
+    } else if (P.var_step) {
+      // AB2 for unequal steps: weights 1 + w/2 and -w/2, w = dt / dt_prev
+      H = a.n0.H[c] + dt * (P.ab0 * RH + P.ab1 * a.rprev.H[c]);
+      if (P.reacting) Z = a.n0.Z[c] + dt * (P.ab0 * RZ + P.ab1 * a.rprev.Z[c]);
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+        a.M[i][c] = rho0 * a.n0.v[i][c] + dt * (P.ab0 * Rv[i] + P.ab1 * a.rprev.v[i][c]);
     } else {
       H = a.n0.H[c] + dt * (1.5 * RH - 0.5 * a.rprev.H[c]);
       if (P.reacting) Z = a.n0.Z[c] + dt * (1.5 * RZ - 0.5 * a.rprev.Z[c]);
@@ -500,7 +507,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
     }
     double drho;
     if (a.bdf2)
-      drho = (3.0 * a.rho_new[c] - 4.0 * a.rho_n[c] + a.rho_prev[c]) / (2.0 * P.dt);
+      drho = P.var_step ? (P.bd0 * (a.rho_new[c] - a.rho_n[c]) - P.bd2 * (a.rho_n[c] - a.rho_prev[c])) / P.dt
+                        : (3.0 * a.rho_new[c] - 4.0 * a.rho_n[c] + a.rho_prev[c]) / (2.0 * P.dt);
     else
       drho = (a.rho_new[c] - a.rho_n[c]) / P.dt;
     const double src = a.S_m ? drho - a.S_m[c] : drho;
@@ -760,6 +768,68 @@ hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &
   hipLaunchKernelGGL(k_cfl, g, bl, 0, st, L, P, lv, chi, partials);
   hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
                      out_max);
+  return hipGetLastError();
+}
+
+// Predictor-corrector differences of a step (the local-error estimate of an
+// adaptive step): per block sums of |v* - v^{n+1}|^2, (H* - H^{n+1})^2 and
+// (Z* - Z^{n+1})^2 over the cells of a grid-stride loop (fixed grid, so
+// the summation order does not depend on the launch).
+__global__ void __launch_bounds__(kBlock) k_pc_err(Lay L, int reacting, Level s, Level q, double *partials) {
+  __shared__ double sh[kBlock / 64];
+  const long N = L.ncells();
+  const int nx = L.n[0], ny = L.n[1];
+  double ev = 0.0, eh = 0.0, ez = 0.0;
+  for (long t = (long)blockIdx.x * kBlock + threadIdx.x; t < N; t += (long)kErrBlocks * kBlock) {
+    const int i = (int)(t % nx);
+    const int j = (int)((t / nx) % ny);
+    const int k = (int)(t / ((long)nx * ny));
+    const long c = L.at(i, j, k);
+    for (int d = 0; d < L.ndim; ++d) {
+      const double dv = s.v[d][c] - q.v[d][c];
+      ev = ev + dv * dv;
+    }
+    const double dh = s.H[c] - q.H[c];
+    eh = eh + dh * dh;
+    if (reacting) {
+      const double dz = s.Z[c] - q.Z[c];
+      ez = ez + dz * dz;
+    }
+  }
+  ev = block_sum(ev, sh);
+  eh = block_sum(eh, sh);
+  ez = block_sum(ez, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = ev;
+    partials[kErrBlocks + blockIdx.x] = eh;
+    partials[2 * kErrBlocks + blockIdx.x] = ez;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pc_err_finish(const double *partials, double *out) {
+  __shared__ double sh[kBlock / 64];
+  for (int q = 0; q < 3; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < kErrBlocks; b += kBlock) v = v + partials[q * kErrBlocks + b];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[q] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale_copy(long n, double a, const double *x, double *y) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) y[t] = a * x[t];
+}
+
+hipError_t launch_scale_copy(hipStream_t st, long n, double a, const double *x, double *y) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, st, n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level &star, const Level &nw,
+                         double *partials, double *out) {
+  hipLaunchKernelGGL(k_pc_err, dim3(kErrBlocks), dim3(kBlock), 0, st, L, reacting, star, nw, partials);
+  hipLaunchKernelGGL(k_pc_err_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, out);
   return hipGetLastError();
 }
 

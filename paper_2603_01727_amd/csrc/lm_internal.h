@@ -48,6 +48,10 @@ struct Phys {
   int closed;       // enclosed system: p0 from the conserved mass (Eq 2.40)
   double zeta;      // (gamma - 1)/(gamma qs): factor of the d_t p0 source (Eq 3.4b)
   double suth_C;    // > 0: Sutherland's law for kappa (Eq 4.12); 0: kappa = T^sigma
+  // unequal steps (adaptive time step): AB2 weights of R^n, R^{n-1}; BDF2
+  // d_t rho = (bd0 (rho^{new} - rho^n) - bd2 (rho^n - rho^{n-1})) / dt
+  int var_step;
+  double ab0, ab1, bd0, bd2;
 };
 
 // Thermodynamic pressure of an enclosed system, on the device (the step
@@ -155,6 +159,13 @@ hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Si
 hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
                       const unsigned char *chi, double *partials, double *out_max);
 hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc);
+// Sums over cells of |v* - v^{n+1}|^2, (H* - H^{n+1})^2, (Z* - Z^{n+1})^2
+// into out[0..2] (partials: at least 3 * kErrBlocks doubles).
+constexpr int kErrBlocks = 256;
+// y[0..n) = a x[0..n)
+hipError_t launch_scale_copy(hipStream_t st, long n, double a, const double *x, double *y);
+hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level &star, const Level &nw,
+                         double *partials, double *out);
 
 // ---- adjoint (lm_adjoint.hip): 2D periodic, non-reacting, no body --------
 struct AdjPhys {

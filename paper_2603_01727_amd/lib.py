@@ -34,7 +34,8 @@ class lm_params(C.Structure):
                 ("Da_ib", C.c_double), ("p0", C.c_double), ("dt", C.c_double), ("cfl", C.c_double),
                 ("precision", C.c_int), ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int),
                 ("mg_nu", C.c_int), ("with_ib", C.c_int), ("with_adjoint", C.c_int), ("poisson_beta", C.c_int),
-                ("p0_closed", C.c_int), ("gamma", C.c_double), ("sutherland_C", C.c_double)]
+                ("p0_closed", C.c_int), ("gamma", C.c_double), ("sutherland_C", C.c_double),
+                ("dt_tol", C.c_double)]
 
 
 class lm_fields(C.Structure):
@@ -55,7 +56,8 @@ class lm_side_data(C.Structure):
 class lm_step_stats(C.Structure):
     _fields_ = [("steps", C.c_int), ("dt", C.c_double), ("time", C.c_double),
                 ("poisson_iters", C.c_int * 2), ("poisson_relres", C.c_double * 2),
-                ("compat", C.c_double * 2), ("total_poisson_iters", C.c_longlong), ("p0", C.c_double)]
+                ("compat", C.c_double * 2), ("total_poisson_iters", C.c_longlong), ("p0", C.c_double),
+                ("pc_err", C.c_double), ("pc_err_used", C.c_int)]
 
 
 class lm_adjoint(C.Structure):

@@ -9,7 +9,7 @@ from workloads import Case
 
 PARAM_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O",
               "Da_ib", "p0", "dt", "cfl", "p0_closed", "gamma",
-              "sutherland_C")
+              "sutherland_C", "dt_tol")
 SIDE_INDEX = {"slip", "noslip", "inflow", "outflow"}
 
 

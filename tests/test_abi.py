@@ -158,3 +158,22 @@ def test_sutherland_checks_without_gpu():
     p.sutherland_C, p.with_adjoint = 0.2, 1
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     assert "sigma" in L.lm_last_error(None).decode()
+
+
+def test_adaptive_step_checks_without_gpu():
+    """dt_tol must be >= 0 and finite and needs cfl > 0; not with the
+    adjoint (EINVAL) nor with an enclosed system (EUNSUPPORTED)."""
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b = C.c_size_t()
+    g, p = _grid_params((64, 64))
+    p.dt_tol, p.cfl = 1e-6, 0.3
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+    p.dt_tol = -1.0
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.dt_tol, p.cfl, p.dt = 1e-6, 0.0, 1e-3
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.cfl, p.with_adjoint = 0.3, 1
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    p.with_adjoint, p.p0_closed, p.gamma = 0, 1, 1.4
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
