@@ -35,8 +35,11 @@ class Params:
     inv_Fr2 = 1/Fr^2 (Eq 2.43);
     Da_ib: immersed-boundary Darcy number (Eq 3.30); p0: thermodynamic
     pressure, constant for open and periodic systems (Eq 2.41), or its
-    initial value when p0_closed is set: an enclosed system whose p0 follows
-    from the conserved mass, p0 = m / integral(1/T) (Eq 2.40), with the
+    initial value when p0_closed is set: p0_closed = 1 (True), an enclosed
+    system whose p0 follows from the conserved mass, p0 = m / integral(1/T)
+    (Eq 2.40); p0_closed = 2, a semi-enclosed system whose p0 follows the
+    ordinary differential equation of Eq 2.38 (see Oracle.p0_rate); both
+    with the
     zeta d_t p0 source of the excess-enthalpy equation (Eq 2.45, 3.4b),
     zeta = (S+1)(gamma-1)/(gamma Q) = (gamma-1)/(gamma qs); dt = 0 asks for a
     step fixed once from the CFL number of the initial state; dt_tol > 0
@@ -56,7 +59,7 @@ class Params:
     p0: float = 1.0
     dt: float = 0.0
     cfl: float = 0.2
-    p0_closed: bool = False
+    p0_closed: int = 0
     gamma: float = 1.4
     sutherland_C: float = 0.0
     dt_tol: float = 0.0
@@ -97,6 +100,7 @@ class State:
     p0: float = 1.0                           # thermodynamic pressure at level n
     p0_hist: tuple = ()                       # p0 at levels n-1, n-2 (closed systems)
     dt_prev: float = 0.0                      # step from level n-1 to n (adaptive steps)
+    p0_rate_prev: Optional[float] = None      # d_t p0 at level n-1 (Eq 2.38 systems)
     nsame: int = 0                            # steps of that size in a row (adaptive steps)
 
     def copy(self):
@@ -105,7 +109,8 @@ class State:
                      c(self.P), [a.copy() for a in self.F], c(self.rho_prev),
                      None if self.R_prev is None else {k: ([a.copy() for a in v] if isinstance(v, list) else v.copy())
                                                        for k, v in self.R_prev.items()},
-                     self.nstep, self.p0, tuple(self.p0_hist), self.dt_prev, self.nsame)
+                     self.nstep, self.p0, tuple(self.p0_hist), dt_prev=self.dt_prev,
+                     p0_rate_prev=self.p0_rate_prev, nsame=self.nsame)
 
 
 class Oracle:
@@ -135,10 +140,13 @@ class Oracle:
         g, fp = self.g, self.fp
         if self.p.p0_closed:
             # an enclosed system: no mass crosses the sides or enters through
-            # a source; the first-step balance takes the non-reacting map
-            open_side = any(g.bc[d][s] in ("inflow", "outflow") for d in range(g.ndim) for s in (0, 1))
+            # a source; the first-step balance takes the non-reacting map. A
+            # semi-enclosed one (Eq 2.38) may also have inflow sides.
+            banned = ("outflow",) if self.p.p0_closed == 2 else ("inflow", "outflow")
+            open_side = any(g.bc[d][s] in banned for d in range(g.ndim) for s in (0, 1))
             if open_side or self.ib.get("Sm") is not None or self.p.reacting:
-                raise ValueError("p0_closed needs walls or periodic sides, no mass source, non-reacting flow")
+                raise ValueError("p0_closed needs walls or periodic sides (or inflow sides for Eq 2.38), "
+                                 "no mass source, non-reacting flow")
             if self.p.dt_tol > 0.0:
                 raise ValueError("adaptive steps need a constant p0")
         Zs = None
@@ -349,6 +357,30 @@ class Oracle:
             return (p_new - hist[0]) / dt
         return 0.0
 
+    def p0_rate(self, st: State):
+        """d_t p0 of a semi-enclosed system at one level, Eq 2.38 without
+        reaction: (gamma / V) [qs / Pe integral div(kappa grad H) dV - p0
+        integral div v dV]. The first integral is the sum over cells of the
+        discrete diffusion term of the H residual (it telescopes to the
+        conductive fluxes through the boundary faces); the second is the
+        volume flux out through the sides, the given normal velocity of
+        each inflow side times its face area (walls and periodic sides
+        carry none)."""
+        g, p = self.g, self.p
+        _, _, Hp, Tp = self.padded_fields(st)
+        _, dif = self._scalar_terms(Hp, self.conductivity(Tp), st.F)
+        heat = float(np.sum(dif)) * g.dV
+        flux = 0.0
+        for d in range(g.ndim):
+            area = g.dV / g.h[d]
+            for s in (0, 1):
+                if g.bc[d][s] != "inflow":
+                    continue
+                vn = np.broadcast_to(np.asarray(g.bvalue(d, s, "v", d), dtype=float),
+                                     tuple(g.shape[a] for a in range(g.ndim) if a != g.axis(d)))
+                flux += (1.0 if s == 1 else -1.0) * float(np.sum(vn)) * area
+        return p.gamma / g.volume * (p.qs / p.Pe * heat - st.p0 * flux)
+
     def balance_ddt_p0(self, st: State):
         """d_t p0 at a level with no earlier one (the first step; a start-up
         reading, the paper is silent): the time derivative of Eq 2.40,
@@ -481,12 +513,19 @@ class Oracle:
         residuals carry zeta d_t p0 at their level (Eq 3.4b, 3.5, 3.14)."""
         g, p, fp = self.g, self.p, self.fp
         dt = self.dt
-        closed = p.p0_closed
-        if closed and not st.p0_hist:
+        closed = p.p0_closed == 1
+        ode = p.p0_closed == 2
+        first = st.R_prev is None
+        if ode:
+            # semi-enclosed: p0 integrated from Eq 2.38 like the other
+            # unknowns (AB2 predictor, Euler on the first step; trapezoid
+            # corrector); its rate is the d_t p0 of each level's residual
+            f_n = self.p0_rate(st)
+            Rn = self.residuals(st, f_n)
+        elif closed and not st.p0_hist:
             Rn = self.residuals(st, self.balance_ddt_p0(st))
         else:
             Rn = self.residuals(st, self.ddt_p0(st.p0, st.p0_hist) if closed else 0.0)
-        first = st.R_prev is None
         M0 = [st.rho * st.v[i] for i in range(g.ndim)]
         adaptive = p.dt_tol > 0.0
         # ratio of this step to the previous one (adaptive steps)
@@ -523,22 +562,33 @@ class Oracle:
         Zs = ab2(st.Z, Rn["Z"], Rp.get("Z")) if p.reacting else None
         Ms = [ab2(M0[i], Rn["v"][i], None if first else Rp["v"][i]) for i in range(g.ndim)]
         Ts = temperature(Zs if Zs is not None else 0.0, Hs, fp)
-        p0s = self.closed_p0(Ts) if closed else p.p0
+        if ode:
+            p0s = st.p0 + dt * (f_n if first else 1.5 * f_n - 0.5 * st.p0_rate_prev)
+        else:
+            p0s = self.closed_p0(Ts) if closed else p.p0
         rhos = p0s / Ts
         Ps, Fs, vs, bs = self.project(Ms, rhos, ddt(rhos), "pred")
         sts = State(rhos, vs, Zs, Hs, Ts, Ps, Fs, p0=p0s)
         # ---- corrector
         hist_s = (st.p0,) + tuple(st.p0_hist[:1])
-        Rs = self.residuals(sts, self.ddt_p0(p0s, hist_s) if closed else 0.0)
+        if ode:
+            f_s = self.p0_rate(sts)
+            Rs = self.residuals(sts, f_s)
+        else:
+            Rs = self.residuals(sts, self.ddt_p0(p0s, hist_s) if closed else 0.0)
         H1 = am2(st.H, Rs["H"], Rn["H"])
         Z1 = am2(st.Z, Rs["Z"], Rn["Z"]) if p.reacting else None
         M1 = [am2(M0[i], Rs["v"][i], Rn["v"][i]) for i in range(g.ndim)]
         T1 = temperature(Z1 if Z1 is not None else 0.0, H1, fp)
-        p01 = self.closed_p0(T1) if closed else p.p0
+        if ode:
+            p01 = st.p0 + 0.5 * dt * (f_s + f_n)
+        else:
+            p01 = self.closed_p0(T1) if closed else p.p0
         rho1 = p01 / T1
         P1, F1, v1, b1 = self.project(M1, rho1, ddt(rho1), "corr")
         out = State(rho1, v1, Z1, H1, T1, P1, F1, rho_prev=st.rho, R_prev=Rn,
-                    nstep=st.nstep + 1, p0=p01, p0_hist=(st.p0,) + tuple(st.p0_hist[:1]), dt_prev=dt)
+                    nstep=st.nstep + 1, p0=p01, p0_hist=(st.p0,) + tuple(st.p0_hist[:1]), dt_prev=dt,
+                    p0_rate_prev=f_n if ode else None)
         rms = lambda a: float(np.sqrt(np.mean(np.abs(a) ** 2)))
         self.stats["pc_diff_v"] = [rms(vs[i] - v1[i]) for i in range(g.ndim)]
         self.stats["pc_diff_P"] = rms(Ps - P1)
