@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lm_internal.h"
 
@@ -145,8 +146,8 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "poisson_beta must be LM_BETA_ONE or LM_BETA_INV_RHO";
     return false;
   }
-  if (p->p0_closed != 0 && p->p0_closed != 1) {
-    *err = "p0_closed must be 0 or 1";
+  if (p->p0_closed < 0 || p->p0_closed > 2) {
+    *err = "p0_closed must be 0, 1 or 2";
     return false;
   }
   if (p->p0_closed && !(p->gamma > 1.0)) {
@@ -220,6 +221,10 @@ void setup_phys(lm_ctx *c) {
   P.nu_coef = nc;
   P.closed = p.p0_closed;
   P.zeta = p.p0_closed ? (p.gamma - 1.0) / (p.gamma * p.qs) : 0.0;
+  P.gamma = p.gamma;
+  P.volume = 1.0;
+  for (int d = 0; d < g.ndim; ++d) P.volume *= g.L[d];
+  P.vol_out = 0.0;
   P.suth_C = p.sutherland_C;
 }
 
@@ -227,12 +232,16 @@ void setup_phys(lm_ctx *c) {
 bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   const int nd = c->grid.ndim;
   if (c->prm.p0_closed) {
+    // enclosed (1): periodic or wall sides; semi-enclosed (2, Eq 2.38):
+    // inflow sides too; never an outflow side (its flux closes the mass)
     bool open = false;
     for (int d = 0; d < nd; ++d)
       for (int s = 0; s < 2; ++s)
-        open = open || c->grid.bc[d][s] == LM_SIDE_INFLOW || c->grid.bc[d][s] == LM_SIDE_OUTFLOW;
+        open = open || (c->grid.bc[d][s] == LM_SIDE_INFLOW && c->prm.p0_closed == 1) ||
+               c->grid.bc[d][s] == LM_SIDE_OUTFLOW;
     if (open || c->prm.reacting) {
-      if (err) *err = "an enclosed system needs periodic or wall sides and non-reacting flow";
+      if (err)
+        *err = "p0_closed needs periodic or wall sides (inflow sides too with 2) and non-reacting flow";
       return false;
     }
     if (c->prm.dt_tol > 0.0) {
@@ -428,6 +437,30 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
   return LM_OK;
 }
 
+// Eq 2.38 systems: the volume flux out through the inflow sides, the given
+// normal velocities times the face areas (outward: minus on low sides).
+static lm_status update_vol_out(lm_ctx *c) {
+  c->phys.vol_out = 0.0;
+  if (c->prm.p0_closed != 2) return LM_OK;
+  const Lay &L = c->lay;
+  std::vector<double> buf;
+  for (int d = 0; d < c->grid.ndim; ++d)
+    for (int s = 0; s < 2; ++s) {
+      if (c->grid.bc[d][s] != LM_SIDE_INFLOW || !c->sides.s[d][s].v[d]) continue;
+      const size_t n = (size_t)(L.ncells() / L.n[d]);
+      buf.resize(n);
+      HIPCHK(c, hipMemcpyAsync(buf.data(), c->sides.s[d][s].v[d], n * 8, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      double sum = 0.0;
+      for (size_t q = 0; q < n; ++q) sum += buf[q];
+      double area = 1.0;
+      for (int e = 0; e < c->grid.ndim; ++e)
+        if (e != d) area *= c->phys.h[e];
+      c->phys.vol_out += (s == 1 ? 1.0 : -1.0) * sum * area;
+    }
+  return LM_OK;
+}
+
 lm_status lm_set_side(lm_ctx *c, int d, int side, const lm_side_data *data, int mem) {
   if (!c || !data || d < 0 || d >= c->grid.ndim || side < 0 || side > 1)
     return fail(c, LM_EINVAL, "bad side arguments");
@@ -469,7 +502,7 @@ lm_status lm_set_side(lm_ctx *c, int d, int side, const lm_side_data *data, int 
   sd.Z = st[3];
   sd.H = st[4];
   sd.F = st[5];
-  return LM_OK;
+  return update_vol_out(c);
 }
 
 lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *ib, int mem) {
@@ -533,8 +566,10 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
   if (c->prm.p0_closed && c->ib.S_m) return fail(c, LM_EINVAL, "an enclosed system takes no mass source S_m");
   HIPCHK(c, hipMemsetAsync(c->dflags, 0, 64, c->st));
   HIPCHK(c, launch_init_state(c->st, c->lay, c->phys, c->bnd, c->sides, from_T, lv, c->dflags));
-  if (c->prm.p0_closed)  // conserved mass of this state, p0 history cleared
+  if (c->prm.p0_closed) {  // conserved mass of this state, p0 history cleared
     HIPCHK(c, launch_p0(c->st, 0, c->lay, c->phys, c->p0d, &lv, nullptr, nullptr, c->pws.partials));
+    if ((s = update_vol_out(c)) != LM_OK) return s;
+  }
   if (f->F[0]) {
     for (int d = 0; d < nd; ++d) {
       if (!f->F[d]) return fail(c, LM_EINVAL, "give every face-flux component or none");
@@ -635,8 +670,14 @@ static lm_status do_stage(lm_ctx *c, int corrector, int &iters, double &relres, 
   HIPCHK(c, launch_ghosts(c->st, L, c->bnd, c->phys, c->sides, src.v, src.Z, src.H, src.T, src.kap));
   const int first = !c->have_prev;
   const double *dtp0 = corrector ? &c->p0d->dtp0_star : &c->p0d->dtp0_n;
+  const bool ode = c->prm.p0_closed == 2;
+  // Eq 2.38: d_t p0 of the residual's level from its heat integral
+  if (ode) HIPCHK(c, launch_p0(c->st, corrector ? 7 : 5, L, c->phys, c->p0d, &src, nullptr, nullptr, c->pws.partials));
   HIPCHK(c, launch_stage(c->st, corrector, first, L, c->phys, src, A, rprev, rn, c->ib, out, c->M, dtp0));
-  if (c->prm.p0_closed) {
+  if (ode) {
+    // p0 of the predicted (AB2) / new (trapezoid) level, then rho = p0 / T
+    HIPCHK(c, launch_p0(c->st, corrector ? 8 : 6, L, c->phys, c->p0d, &out, nullptr, nullptr, c->pws.partials));
+  } else if (c->prm.p0_closed) {
     // first step: d_t p0 at level n from the balance, into R_H^n and H*
     if (!corrector && first) HIPCHK(c, launch_p0(c->st, 3, L, c->phys, c->p0d, &out, &A, rn.H, c->pws.partials));
     // p0 of the predicted / new level from the mass, then rho = p0 / T

@@ -941,12 +941,31 @@ __global__ void __launch_bounds__(kBlock) k_p0_sum(Lay L, const double *T, const
   if (linear_tid() == 0) part[linear_block()] = s;
 }
 
+// Per-block partial sums over the cells of the H residual's diffusion term
+// sum_d delta_1(kappa_f delta_1 H) (ghost-filled level): times dV it is the
+// integral of div(kappa grad H) of Eq 2.38, the boundary faces' fluxes.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_p0_heat(Lay L, Phys P, Level lv, double *part) {
+  __shared__ double sh[kBlock / 64];
+  CellPos p;
+  double v = 0.0;
+  if (cell_of_thread(L, p)) {
+    double adv;
+    scalar_terms<DIM>(L, P, lv, lv.H, p.c, adv, v);
+  }
+  const double s = block_sum(v, sh);
+  if (linear_tid() == 0) part[linear_block()] = s;
+}
+
 // One block: the sum of the partials (fixed order) and the update of the
 // device p0 state. what: 0 mass and set-up, 1 predicted level, 2 new level,
-// 3 first half of the start-up balance (stores the sum), 4 second half.
+// 3 first half of the start-up balance (stores the sum), 4 second half;
+// Eq 2.38: 5 / 7 d_t p0 at level n / the predicted level from the heat
+// integral, 6 / 8 p0 of the predicted / new level (no sum).
 __global__ void __launch_bounds__(kBlock) k_p0_finish(int what, const double *part, int np, P0Dev *q, double dV,
-                                                      double p_init, double qs, double zeta, double dt) {
+                                                      Phys P) {
   __shared__ double sh[kBlock / 64];
+  const double p_init = P.p0, qs = P.qs, zeta = P.zeta, dt = P.dt;
   double v = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
   const double s = block_sum(v, sh);
@@ -955,8 +974,20 @@ __global__ void __launch_bounds__(kBlock) k_p0_finish(int what, const double *pa
     q->mass = s * dV;
     q->p0[0] = q->p0[1] = q->p0[2] = p_init;
     q->p0_star = q->p0_new = p_init;
-    q->dtp0_n = q->dtp0_star = q->dtp0_start = 0.0;
+    q->dtp0_n = q->dtp0_star = q->dtp0_start = q->rate_prev = 0.0;
     q->nhist = 0;
+  } else if (what == 5 || what == 7) {
+    // Eq 2.38: (gamma/V) [qs/Pe int div(kappa grad H) - p0 int div v]
+    const double p0 = what == 5 ? q->p0[0] : q->p0_star;
+    const double r = P.gamma / P.volume * (qs / P.Pe * (s * dV) - p0 * P.vol_out);
+    if (what == 5)
+      q->dtp0_n = r;
+    else
+      q->dtp0_star = r;
+  } else if (what == 6) {
+    q->p0_star = q->p0[0] + dt * (q->nhist == 0 ? q->dtp0_n : 1.5 * q->dtp0_n - 0.5 * q->rate_prev);
+  } else if (what == 8) {
+    q->p0_new = q->p0[0] + 0.5 * dt * (q->dtp0_star + q->dtp0_n);
   } else if (what == 1) {
     const double ps = q->mass / (s * dV);
     q->p0_star = ps;
@@ -1001,6 +1032,7 @@ __global__ void __launch_bounds__(kBlock) k_p0_startup(Lay L, Phys P, const P0De
 // for the next predictor (BDF2, Eq 3.5; BDF1 with one earlier level).
 __global__ void k_p0_commit(P0Dev *q, double dt) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  q->rate_prev = q->dtp0_n;  // Eq 2.38 systems: the level-n rate for the next AB2
   q->p0[2] = q->p0[1];
   q->p0[1] = q->p0[0];
   q->p0[0] = q->p0_new;
@@ -1014,8 +1046,7 @@ hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0De
   const int np = (int)nblocks_for(L);
   const double dV = P.h[0] * P.h[1] * (L.ndim == 3 ? P.h[2] : 1.0);
   auto finish = [&](int w) {
-    hipLaunchKernelGGL(k_p0_finish, dim3(1), dim3(kBlock), 0, st, w, (const double *)partials, np, p0, dV, P.p0, P.qs,
-                       P.zeta, P.dt);
+    hipLaunchKernelGGL(k_p0_finish, dim3(1), dim3(kBlock), 0, st, w, (const double *)partials, np, p0, dV, P);
   };
   switch (what) {
     case 0:
@@ -1041,6 +1072,20 @@ hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0De
       break;
     case 4:
       hipLaunchKernelGGL(k_p0_commit, dim3(1), dim3(64), 0, st, p0, P.dt);
+      break;
+    case 5:
+    case 7:
+      if (L.ndim == 3)
+        hipLaunchKernelGGL(k_p0_heat<3>, g, bl, 0, st, L, P, *lv, partials);
+      else
+        hipLaunchKernelGGL(k_p0_heat<2>, g, bl, 0, st, L, P, *lv, partials);
+      finish(what);
+      break;
+    case 6:
+    case 8:
+      hipLaunchKernelGGL(k_p0_finish, dim3(1), dim3(kBlock), 0, st, what, (const double *)partials, 0, p0, dV, P);
+      hipLaunchKernelGGL(k_p0_eos, g, bl, 0, st, L, (const double *)lv->T, lv->rho, (const P0Dev *)p0,
+                         what == 6 ? 0 : 1);
       break;
     default:
       return hipErrorInvalidValue;

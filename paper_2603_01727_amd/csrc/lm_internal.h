@@ -45,7 +45,10 @@ struct Phys {
   double qs, S, k, Le_F, Le_O, N_F, N_O, fshift;  // fshift = -1 - F_eps(0)
   int has_ib;
   double nu_coef;   // max(Pr, 1, 1/Le_F, 1/Le_O)
-  int closed;       // enclosed system: p0 from the conserved mass (Eq 2.40)
+  int closed;       // 1: p0 from the conserved mass (Eq 2.40); 2: from the ODE of Eq 2.38
+  double vol_out;   // Eq 2.38: volume flux out through the inflow sides (given normal velocities)
+  double volume;    // domain volume
+  double gamma;     // ratio of specific heats (p0_closed)
   double zeta;      // (gamma - 1)/(gamma qs): factor of the d_t p0 source (Eq 3.4b)
   double suth_C;    // > 0: Sutherland's law for kappa (Eq 4.12); 0: kappa = T^sigma
   // unequal steps (adaptive time step): AB2 weights of R^n, R^{n-1}; BDF2
@@ -64,6 +67,7 @@ struct P0Dev {
   double dtp0_n;       // d_t p0 at level n (predictor residual); 0 on the first step
   double dtp0_star;    // d_t p0 at the predicted level (corrector residual)
   double dtp0_start;   // first step: d_t p0 at level n from the balance of Eq 2.40
+  double rate_prev;    // Eq 2.38 systems: d_t p0 at level n-1 (AB2 of the predictor)
   int nhist;           // committed levels before n (0, 1, 2)
 };
 
@@ -137,6 +141,11 @@ hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, 
 //     the balance of Eq 2.40, added to the stored level-n residual R_H and
 //     to the Euler-predicted H* (then T*, kappa*)
 //   4 commit of a completed step (history shift, d_t p0 for the next step)
+// Semi-enclosed systems (Eq 2.38), on ghost-filled levels:
+//   5 before the predictor stage kernel: d_t p0 at level n (lv)
+//   6 after it: p0* by AB2 (Euler on the first step), rho* = p0*/T*
+//   7 before the corrector stage kernel: d_t p0 at the predicted level (lv)
+//   8 after it: p0^{n+1} by the trapezoid rule, rho^{n+1} = p0^{n+1}/T^{n+1}
 hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0Dev *p0, Level *lv, const Level *n0,
                      double *RH, double *partials);
 hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P, const Sides &sd,

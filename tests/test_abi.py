@@ -177,3 +177,21 @@ def test_adaptive_step_checks_without_gpu():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     p.with_adjoint, p.p0_closed, p.gamma = 0, 1, 1.4
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+
+
+def test_semi_enclosed_checks_without_gpu():
+    """p0_closed = 2 (Eq 2.38) takes inflow sides but no outflow side;
+    values beyond 2 are rejected."""
+    from paper_2603_01727_amd import lib
+    L = lib.load()
+    b = C.c_size_t()
+    g, p = _grid_params((64, 64), bc=[(3, 2), (0, 0), (0, 0)])   # inflow / no-slip x, periodic y
+    p.p0_closed, p.gamma = 2, 1.4
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+    p.p0_closed = 1
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    g, p = _grid_params((64, 64), bc=[(3, 4), (0, 0), (0, 0)])   # inflow / outflow
+    p.p0_closed, p.gamma = 2, 1.4
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    p.p0_closed = 3
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
