@@ -124,7 +124,6 @@ typedef struct {
  *  sutherland_C  0: kappa = T^sigma; C > 0: Sutherland's law
  *                kappa = T^{3/2} (1 + C) / (T + C) (Eq 4.12), C the
  *                Sutherland temperature over the reference temperature
- *                (not with with_adjoint)
  *  dt_tol        0: fixed time step. > 0: adaptive step driven by the
  *                predictor-corrector difference (the local-error estimate
  *                of the step, O(dt^3)): err = the largest of the RMS of

@@ -147,8 +147,23 @@ struct Loader {
 
 __device__ inline D5 temp_of(const AdjPhys &P, const D5 &H) { return P.qs * (H - 1.0); }
 
+// kappa(T) with its derivative: T^sigma (Eq 2.50), or Sutherland's law
+// T^{3/2} (1 + C)/(T + C) (Eq 4.12), d kappa/dT = kappa (3/(2T) - 1/(T + C)).
+__device__ inline D5 kappa_dual(const AdjPhys &P, const D5 &T) {
+  if (P.suth_C > 0.0) {
+    const double C = P.suth_C, t = T.v;
+    D5 r;
+    r.v = t * sqrt(t) * (1.0 + C) / (t + C);
+    const double dv = r.v * (1.5 / t - 1.0 / (t + C));
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r.d[q] = dv * T.d[q];
+    return r;
+  }
+  return dpow(T, P.sigma);
+}
+
 __device__ inline D5 kap_at(const AdjPhys &P, const Loader &ld, int i, int j) {
-  return dpow(temp_of(P, ld.hh(i, j)), P.sigma);
+  return kappa_dual(P, temp_of(P, ld.hh(i, j)));
 }
 
 // tau_id on the face between (i, j) and its +d neighbour (Eq 2.46 on d-faces).
@@ -182,7 +197,7 @@ __device__ inline void resid_cell(const AdjPhys &P, const Loader &ld, int i, int
   const D5 Hc = ld.hh(i, j);
   const D5 Tc = temp_of(P, Hc);
   const D5 rho = D5(P.p0) / Tc;
-  const D5 kc = dpow(Tc, P.sigma);
+  const D5 kc = kappa_dual(P, Tc);
   D5 adv(0.0), dif(0.0);
 #pragma unroll
   for (int d = 0; d < 2; ++d) {

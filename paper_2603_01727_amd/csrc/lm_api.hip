@@ -170,10 +170,6 @@ bool valid_params(const lm_params *p, std::string *err) {
     *err = "the adjoint needs a fixed time step";
     return false;
   }
-  if (p->with_adjoint && p->sutherland_C > 0.0) {
-    *err = "the adjoint supports kappa = T^sigma only";
-    return false;
-  }
   if (p->with_adjoint && p->p0_closed) {
     *err = "the adjoint needs a constant thermodynamic pressure";
     return false;
@@ -945,6 +941,7 @@ AdjPhys adj_phys(const lm_ctx *c) {
   P.p0 = c->phys.p0;
   P.qs = c->phys.qs;
   P.dt = c->phys.dt;
+  P.suth_C = c->phys.suth_C;
   return P;
 }
 

@@ -180,6 +180,7 @@ hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level
 struct AdjPhys {
   double h[2];
   double Pe, Pr, sigma, inv_Fr2, p0, qs, dt;
+  double suth_C;  // > 0: Sutherland's law for kappa (Eq 4.12)
 };
 struct AdjTailArgs {
   Lay L;

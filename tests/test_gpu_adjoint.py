@@ -39,10 +39,10 @@ def _dt(case):
     return o.dt
 
 
-def _solver(case, dt, with_adjoint=True, rtol=RTOL):
+def _solver(case, dt, with_adjoint=True, rtol=RTOL, sutherland_C=0.0):
     from paper_2603_01727_amd import Solver
     return Solver(case.n[:2], case.L[:2], bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], dt=dt,
-                  poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint)
+                  poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint, sutherland_C=sutherland_C)
 
 
 def test_state_restart_is_bit_exact():
@@ -89,10 +89,13 @@ def _dot(a, b):
     return out
 
 
-@pytest.mark.parametrize("shape,history", [((72, 80), False), ((72, 80), True), ((64, 64), True)])
-def test_adjoint_step_dot_product_against_oracle_tangent(shape, history):
+@pytest.mark.parametrize("shape,history,suth", [((72, 80), False, 0.0), ((72, 80), True, 0.0), ((64, 64), True, 0.0),
+                                                ((64, 64), True, 110.5 / 600.0)],
+                         ids=["72x80", "72x80-hist", "64-hist", "64-hist-sutherland"])
+def test_adjoint_step_dot_product_against_oracle_tangent(shape, history, suth):
     """One step back on the GPU against the complex-step tangent of the same
-    step in the oracle, per input component."""
+    step in the oracle, per input component (also with Sutherland's
+    conductivity, Eq 4.12)."""
     ny, nx = shape
     case = c5_case(n=nx)
     if ny != nx:
@@ -105,12 +108,12 @@ def test_adjoint_step_dot_product_against_oracle_tangent(shape, history):
     print("adjoint dot", shape, history, flush=True)
     dt = 0.5 * _dt(case)
     g = Grid(case.n[:2], case.L[:2], bc=case.bc)
-    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth)
     o = Oracle(g, p)
     st = o.initial_state(case.T, case.v)
     nhist = 1 if history else 0
     st = tg.with_eos(o, o.run(st, nhist))
-    s = _solver(case, dt)
+    s = _solver(case, dt, sutherland_C=suth)
     s.set(T=case.T, v=case.v)
     if nhist:
         s.step(nhist)
