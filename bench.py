@@ -255,7 +255,7 @@ def copy_calibration():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1"}))
         sys.exit(2)
     from workloads import c2_case
     case = c2_case(n=a.n)

@@ -39,7 +39,7 @@ typedef enum {
   LM_ENOCONV = -4,       /* Poisson solver hit poisson_maxit before poisson_rtol */
   LM_ENONFINITE = -5,    /* a NaN/Inf appeared in the step */
   LM_ESTATE = -6,        /* call out of order (e.g. lm_step before lm_set_fields) */
-  LM_EUNSUPPORTED = -7   /* valid request this build does not implement */
+  LM_EUNSUPPORTED = -7   /* valid request that is not implemented    */
 } lm_status;
 
 /* Side kinds (section 3.6 ghost rules, section 3.3 flux boundary conditions). */
