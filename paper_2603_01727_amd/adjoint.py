@@ -1,5 +1,7 @@
-"""Reverse-mode gradient of the final kinetic energy with respect to the
-initial temperature, behind ``torch.autograd.Function``.
+"""Reverse-mode gradients of the step behind ``torch.autograd.Function``:
+of the final kinetic energy with respect to the initial temperature
+(``FinalKineticEnergy``), and of the whole final state (T, v) with respect
+to the initial (T, v) (``StepFn``).
 
 J(T0) = sum_cells 1/2 rho |v|^2 dV after ``nsteps`` predictor-corrector
 steps from (T0, v0) with a fixed time step. The forward pass stores a full
@@ -50,11 +52,17 @@ class Trajectory:
         self.final = s.save_state()
         return s.kinetic_energy()
 
-    def backward(self):
-        """Returns (T0_bar, [v0_bar...]) as device tensors."""
+    def backward(self, seed=None):
+        """Returns (T0_bar, [v0_bar...]) as device tensors. ``seed``: the
+        cotangents of the final state as keyword arguments of
+        ``Solver.adjoint_set`` (None: the gradient of the final kinetic
+        energy)."""
         s = self.solver
         s.load_state(self.final)
-        s.adjoint_seed_ke()
+        if seed is None:
+            s.adjoint_seed_ke()
+        else:
+            s.adjoint_set(**seed)
         size = s.state_size()
         nseg = math.ceil(self.nsteps / self.k)
         for q in reversed(range(nseg)):
@@ -95,3 +103,37 @@ class FinalKineticEnergy(torch.autograd.Function):
 def final_kinetic_energy(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_every: int = 20) -> torch.Tensor:
     """Differentiable J(T0); ``T0`` is a float64 tensor on the solver's device."""
     return FinalKineticEnergy.apply(T0, list(v0), solver, nsteps, checkpoint_every)
+
+
+class StepFn(torch.autograd.Function):
+    """(T_n, v_n) after ``nsteps`` steps from (T0, v0), differentiable in
+    T0 and v0: the backward pass seeds the adjoint state with the
+    cotangents of T_n (as H_bar = qs T_bar, the non-reacting map
+    T = qs (H - 1)) and of v_n, and walks the checkpointed trajectory back
+    (``Trajectory``). Outputs are float64 tensors on the solver's device."""
+
+    @staticmethod
+    def forward(ctx, T0, *args):
+        v0, (solver, nsteps, checkpoint_every) = list(args[:-3]), args[-3:]
+        traj = Trajectory(solver, nsteps, checkpoint_every)
+        traj.forward(T0.detach(), [x.detach() for x in v0])
+        g = solver.get(("T", "v"))
+        ctx.traj = traj
+        ctx.nv = len(v0)
+        return (g["T"],) + tuple(g["v"])
+
+    @staticmethod
+    def backward(ctx, gT, *gv):
+        s = ctx.traj.solver
+        zero = lambda g: torch.zeros(s.shape, dtype=torch.float64, device=s.device) if g is None else \
+            g.to(torch.float64).contiguous()
+        seed = {"H": zero(gT) * s.params.qs, "v": [zero(g) for g in gv]}
+        Tb, vb = ctx.traj.backward(seed)
+        return (Tb,) + tuple(vb) + (None, None, None)
+
+
+def step_fn(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_every: int = 20):
+    """Differentiable (T_n, [v_n...]) from (T0, v0): float64 tensors on the
+    solver's device (a Solver built with with_adjoint=True and dt > 0)."""
+    out = StepFn.apply(T0, *list(v0), solver, nsteps, checkpoint_every)
+    return out[0], list(out[1:])

@@ -257,3 +257,58 @@ def test_c5_adjoint_512_200_steps():
     for e, e4, ad in out:
         assert e4 <= 1e-6, out
         assert e * abs(ad) <= 1e-6 * abs(ad) + floor, out
+
+
+def test_step_fn_gradients():
+    """StepFn: (T_n, v_n) differentiable in (T0, v0). (1) The kinetic
+    energy formed in torch from its outputs, J = sum 1/2 (p0/T) |v|^2 dV,
+    has the same T0-gradient as FinalKineticEnergy (two seedings of one
+    adjoint). (2) A random linear functional of (T_n, v_n) against the
+    oracle's complex-step directional derivative along seeded directions
+    in T0 and in v0 (the T0 direction through the same complex step)."""
+    import torch
+    from paper_2603_01727_amd.adjoint import step_fn, final_kinetic_energy
+    n, nsteps, k = 64, 5, 2
+    case, dt = _ke_setup(n, nsteps)
+    print("step_fn gradients", n, nsteps, flush=True)
+    s = _solver(case, dt)
+    dV = case.L[0] * case.L[1] / (n * n)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in case.v]
+    Tn, vn = step_fn(s, T0, v0, nsteps, k)
+    J = (0.5 / Tn * (vn[0] ** 2 + vn[1] ** 2)).sum() * dV
+    J.backward()
+    gT = T0.grad.clone()
+    T1 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    J2 = final_kinetic_energy(s, T1, [x.detach() for x in v0], nsteps, k)
+    J2.backward()
+    assert abs(J.item() / J2.item() - 1) < 1e-13
+    rel = float(torch.linalg.norm(gT - T1.grad) / torch.linalg.norm(T1.grad))
+    print("ke via step_fn", rel, flush=True)
+    assert rel < 1e-12
+    # (2) linear functional against the oracle's tangent
+    rng = np.random.default_rng(77)
+    wT = rng.normal(size=case.T.shape)
+    wv = [rng.normal(size=case.T.shape) for _ in range(2)]
+    for x in [T0] + v0:
+        x.grad = None
+    Tn, vn = step_fn(s, T0, v0, nsteps, k)
+    L = (torch.tensor(wT, device="cuda") * Tn).sum() + sum((torch.tensor(w, device="cuda") * v).sum()
+                                                             for w, v in zip(wv, vn))
+    L.backward()
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt)
+    o = Oracle(g, p)
+    for which in ("T", "v"):
+        d = rng.normal(size=case.T.shape)
+        dT = d if which == "T" else np.zeros_like(d)
+        dv = [np.zeros_like(d), d] if which == "v" else [np.zeros_like(d)] * 2
+        hstep = 1e-20
+        st = o.initial_state(case.T + 1j * hstep * dT, [case.v[q] + 1j * hstep * dv[q] for q in range(2)])
+        st = o.run(st, nsteps)
+        cs = (np.sum(wT * st.T.imag) + sum(np.sum(w * a.imag) for w, a in zip(wv, st.v))) / hstep
+        ad = float(torch.sum(T0.grad.cpu() * torch.tensor(dT)))
+        if which == "v":
+            ad += float(torch.sum(v0[1].grad.cpu() * torch.tensor(d)))
+        print(which, cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
