@@ -14,7 +14,7 @@ import numpy as np
 
 from . import lib as _L
 
-__all__ = ["Solver", "LowMachError"]
+__all__ = ["Solver", "LowMachError", "project"]
 LowMachError = _L.LowMachError
 
 
@@ -324,3 +324,20 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def project(b, L, bc=None, rho=None, rtol: float = 1e-12, precision: str = "fp64", maxit: int = 400,
+            device: str = "cuda:0"):
+    """One-off pressure solve: the zero-mean P with A P = b on a grid of
+    b's shape (C order, x fastest) and lengths L, sides ``bc`` as for
+    ``Solver``; with ``rho`` the variable-coefficient form
+    div(grad P / rho) = b. Builds a context for the call (use
+    ``Solver.project`` for repeated solves). Returns (P, info)."""
+    shape = tuple(np.shape(b))
+    n = tuple(reversed(shape))
+    s = Solver(n, L, bc=bc, Re=1.0, dt=1.0, precision=precision, poisson_rtol=rtol, poisson_maxit=maxit,
+               variable_coefficient=rho is not None, device=device)
+    try:
+        return s.project(b, rho=rho)
+    finally:
+        s.close()

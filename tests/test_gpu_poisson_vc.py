@@ -142,3 +142,16 @@ def test_errors():
     assert e.value.status == lib.LM_EINVAL
     P, info = s.project(b, rho=rho)             # the context still works
     assert info["relres"] <= 1e-13
+
+
+def test_module_level_project():
+    """paper_2603_01727_amd.project: one-off solves, both forms."""
+    from paper_2603_01727_amd import project
+    n, L = (96, 64), (1.5, 1.0)
+    bc = [("slip", "noslip"), ("periodic", "periodic")]
+    rho, b = variable_coefficient_problem(n, L, seed=9, kmax=4)
+    g = Grid(n, L, bc=tuple(tuple(x) for x in bc))
+    for r in (None, rho):
+        Pex, _ = PoissonSolver(g, None if r is None else beta_inv_rho(g, r)).solve(b)
+        P, info = project(b, L, bc=bc, rho=r, rtol=1e-13)
+        assert rel_l2(P, Pex) <= TOL, (r is None, rel_l2(P, Pex), info)
