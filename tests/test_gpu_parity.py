@@ -171,3 +171,42 @@ def test_c4_full_size_one_step():
     errs = compare(st1, s.get(device=False))
     print(errs, s.stats, flush=True)
     _check(errs)
+
+
+def test_taylor_green_spatial_orders_table1():
+    """The GPU step on the Taylor-Green vortex (section 4.2, Re = 100, unit
+    square) against the closed form: the observed L2 orders of v1 and of
+    the interval-averaged pressure (Eq 4.7) between 20, 40, 80, 160 cells
+    match Table 1's order rows (tests/golden/tab1_orders.txt); v1 and v2
+    errors coincide (the table's notes)."""
+    import os
+    from paper_2603_01727_amd import Solver
+    from workloads import taylor_green
+    gold = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "tab1_orders.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            r = [float(x) for x in line.split()]
+            gold[(int(r[0]), int(r[1]))] = r
+    Re, dt, tend = 100.0, 5e-4, 0.1
+    k = int(round(tend / dt))
+    a = 16 * math.pi ** 2 / Re
+    errs = {}
+    for n in (20, 40, 80, 160):
+        print("taylor-green", n, flush=True)
+        v1, v2, _ = taylor_green((n, n), (1.0, 1.0), 0.0, Re)
+        s = Solver((n, n), (1.0, 1.0), Re=Re, Pr=0.7, dt=dt, poisson_rtol=1e-13, poisson_maxit=400)
+        s.set(T=np.ones((n, n)), v=[v1, v2])
+        s.step(k)
+        g = s.get(("v", "P"), device=False)
+        e1, e2, pe = taylor_green((n, n), (1.0, 1.0), k * dt, Re)
+        pbar = (math.exp(a * dt) - 1) / (a * dt) * pe
+        rms = lambda x: math.sqrt(float(np.mean(x ** 2)))
+        errs[n] = (rms(g["v"][0] - e1), rms(g["v"][1] - e2), rms(g["P"] / dt - pbar))
+    for (c, f) in ((20, 40), (40, 80), (80, 160)):
+        ov = math.log(errs[c][0] / errs[f][0]) / math.log(2)
+        op = math.log(errs[c][2] / errs[f][2]) / math.log(2)
+        print(c, f, ov, op, flush=True)
+        assert abs(ov - gold[(c, f)][2]) < 0.05, ov
+        assert abs(op - gold[(c, f)][3]) < 0.08, op
+        assert abs(errs[f][0] / errs[f][1] - 1) < 1e-6
