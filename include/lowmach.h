@@ -254,7 +254,13 @@ lm_status lm_step(lm_ctx *ctx, int nsteps, lm_step_stats *stats);
 /* Poisson solve in RHS mode (see lm_project_args). */
 lm_status lm_project(lm_ctx *ctx, lm_project_args *args);
 
-/* Copy the current state (level 0 = time n) into caller arrays. */
+/* Copy a level into caller arrays: level 0, the current state (time n);
+ * LM_LEVEL_PREDICTED, the predicted level of the last step taken (the
+ * starred fields of Eq 3.1-3.11 and P*; the difference to level 0 is the
+ * step's predictor-corrector difference, Tab 2). LM_ESTATE if no step was
+ * taken since lm_set_fields / lm_load_state; LM_EUNSUPPORTED for other
+ * levels.                                                                */
+enum { LM_LEVEL_PREDICTED = 2 };
 lm_status lm_get_fields(lm_ctx *ctx, int level, lm_fields *f, int mem);
 
 /* The time step of the next lm_step (fixed once after lm_set_fields when

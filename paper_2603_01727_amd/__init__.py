@@ -160,7 +160,9 @@ class Solver:
                           pc_err_used=bool(st.pc_err_used))
         return self.stats
 
-    def get(self, names=("rho", "v", "H", "T", "P", "F", "Z"), device: bool = True) -> dict:
+    def get(self, names=("rho", "v", "H", "T", "P", "F", "Z"), device: bool = True, predicted: bool = False) -> dict:
+        """Fields of the current level, or with ``predicted`` those of the
+        last step's predicted level (its starred fields and P*)."""
         t = self.torch
         out = {}
         f = _L.lm_fields()
@@ -194,7 +196,8 @@ class Solver:
                 a, p = alloc(self.shape)
                 setattr(f, name, p)
                 out[name] = a
-        _check(self.lib, self.ctx, self.lib.lm_get_fields(self.ctx, 0, C.byref(f),
+        level = _L.LM_LEVEL_PREDICTED if predicted else 0
+        _check(self.lib, self.ctx, self.lib.lm_get_fields(self.ctx, level, C.byref(f),
                                                           _L.LM_DEVICE if device else _L.LM_HOST))
         return out
 

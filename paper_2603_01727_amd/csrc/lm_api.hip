@@ -54,6 +54,7 @@ struct lm_ctx {
   double dt_last;        // size of the last step taken
   double pc_err;         // its predictor-corrector estimate
   int pc_used;           // 1 if that estimate decided the next step
+  int have_star;         // the predicted level of the last step is readable
 };
 
 namespace {
@@ -590,6 +591,7 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
   }
   c->have_state = 1;
   c->have_prev = 0;
+  c->have_star = 0;
   c->time = 0.0;
   c->dt_prev = 0.0;
   c->nsame = 0;
@@ -738,6 +740,7 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
     c->rprev ^= 1;
     const int first = !c->have_prev;
     c->have_prev = 1;
+    c->have_star = 1;
     c->time += c->phys.dt;
     ++done;
     if (c->prm.dt_tol > 0.0) {
@@ -800,9 +803,13 @@ lm_status lm_project(lm_ctx *c, lm_project_args *a) {
 
 lm_status lm_get_fields(lm_ctx *c, int level, lm_fields *f, int mem) {
   if (!c || !f) return fail(c, LM_EINVAL, "NULL argument");
-  if (level != 0) return fail(c, LM_EUNSUPPORTED, "only level 0 can be read");
+  if (level != 0 && level != LM_LEVEL_PREDICTED)
+    return fail(c, LM_EUNSUPPORTED, "level must be 0 or LM_LEVEL_PREDICTED");
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
-  Level &lv = cur(c);
+  if (level == LM_LEVEL_PREDICTED && !c->have_star)
+    return fail(c, LM_ESTATE, "no step taken since the state was set or loaded");
+  Level &lv = level == 0 ? cur(c) : c->lev[c->istar];
+  double *Pl = level == 0 ? c->P[c->icur] : c->P[c->istar];
   lm_status s;
   const int nd = c->grid.ndim;
   if (f->rho && (s = copy_out(c, lv.rho, f->rho, -1, mem)) != LM_OK) return s;
@@ -814,7 +821,7 @@ lm_status lm_get_fields(lm_ctx *c, int level, lm_fields *f, int mem) {
   }
   if (f->H && (s = copy_out(c, lv.H, f->H, -1, mem)) != LM_OK) return s;
   if (f->T && (s = copy_out(c, lv.T, f->T, -1, mem)) != LM_OK) return s;
-  if (f->P && (s = copy_out(c, c->P[c->icur], f->P, -1, mem)) != LM_OK) return s;
+  if (f->P && (s = copy_out(c, Pl, f->P, -1, mem)) != LM_OK) return s;
   for (int d = 0; d < nd; ++d)
     if (f->F[d] && (s = copy_out(c, lv.F[d], f->F[d], d, mem)) != LM_OK) return s;
   if (mem == LM_DEVICE) HIPCHK(c, hipStreamSynchronize(c->st));
@@ -985,6 +992,7 @@ extern "C" lm_status lm_load_state(lm_ctx *c, const void *buf) {
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->have_prev = h.have_prev;
   c->have_state = h.have_state;
+  c->have_star = 0;
   c->time = h.time;
   c->last_iters[0] = h.last_iters[0];
   c->last_iters[1] = h.last_iters[1];

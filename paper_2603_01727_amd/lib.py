@@ -20,6 +20,7 @@ LM_FP64, LM_MIXED, LM_MIXED_FLEXIBLE = 0, 1, 2
 PRECISION = {"fp64": LM_FP64, "mixed": LM_MIXED, "mixed-flexible": LM_MIXED_FLEXIBLE}
 LM_HOST, LM_DEVICE = 0, 1
 LM_BETA_ONE, LM_BETA_INV_RHO = 0, 1
+LM_LEVEL_PREDICTED = 2
 
 
 class lm_grid(C.Structure):
