@@ -76,6 +76,16 @@ def test_adaptive_slot_flame_matches_oracle():
     _run(case, 9, tol_P=1e-8)
 
 
+def test_adaptive_3d_matches_oracle():
+    """24^3 random-mode box (density ratio 6): the controller halves the
+    step twice in 12 steps."""
+    from workloads import c4_case
+    case = c4_case(n=24)
+    case.params = dict(case.params, dt_tol=1e-6)
+    print("adaptive 3D", flush=True)
+    assert _run(case, 12) >= 2
+
+
 def test_adaptive_restart_is_exact():
     import torch
     case = c1_case(n=64)
