@@ -101,6 +101,7 @@ class State:
     p0_hist: tuple = ()                       # p0 at levels n-1, n-2 (closed systems)
     dt_prev: float = 0.0                      # step from level n-1 to n (adaptive steps)
     p0_rate_prev: Optional[float] = None      # d_t p0 at level n-1 (Eq 2.38 systems)
+    dt_prev2: float = 0.0                     # step from level n-2 to n-1 (adaptive steps)
     nsame: int = 0                            # steps of that size in a row (adaptive steps)
 
     def copy(self):
@@ -110,7 +111,7 @@ class State:
                      None if self.R_prev is None else {k: ([a.copy() for a in v] if isinstance(v, list) else v.copy())
                                                        for k, v in self.R_prev.items()},
                      self.nstep, self.p0, tuple(self.p0_hist), dt_prev=self.dt_prev,
-                     p0_rate_prev=self.p0_rate_prev, nsame=self.nsame)
+                     p0_rate_prev=self.p0_rate_prev, dt_prev2=self.dt_prev2, nsame=self.nsame)
 
 
 class Oracle:
@@ -147,8 +148,6 @@ class Oracle:
             if open_side or self.ib.get("Sm") is not None or self.p.reacting:
                 raise ValueError("p0_closed needs walls or periodic sides (or inflow sides for Eq 2.38), "
                                  "no mass source, non-reacting flow")
-            if self.p.dt_tol > 0.0:
-                raise ValueError("adaptive steps need a constant p0")
         Zs = None
         if self.p.reacting:
             Zs = np.zeros(g.shape) if Z is None else _real_or_complex(Z)
@@ -346,12 +345,19 @@ class Oracle:
         state integrated over the domain, p0 = m / sum(dV / T) (Eq 2.40)."""
         return self.mass / (np.sum(1.0 / T) * self.g.dV)
 
-    def ddt_p0(self, p_new, hist):
+    def ddt_p0(self, p_new, hist, dt_new=None, dt_old=None):
         """d_t p0 at the level whose pressure is p_new, from the levels before
         it (newest first): BDF2 (Eq 3.5, 3.14); with one earlier level BDF1,
-        with none 0 (start-up readings, as for d_t rho)."""
-        dt = self.dt
+        with none 0 (start-up readings, as for d_t rho). Adaptive steps: the
+        spacings dt_new (to the newest earlier level) and dt_old (the one
+        before) give BDF2 for unequal steps in level differences, as for
+        d_t rho."""
+        dt = self.dt if dt_new is None else dt_new
         if len(hist) >= 2:
+            if self.p.dt_tol > 0.0:
+                w = dt / dt_old
+                return ((1.0 + 2.0 * w) / (1.0 + w) * (p_new - hist[0])
+                        - w * w / (1.0 + w) * (hist[0] - hist[1])) / dt
             return (3.0 * p_new - 4.0 * hist[0] + hist[1]) / (2.0 * dt)
         if len(hist) == 1:
             return (p_new - hist[0]) / dt
@@ -525,7 +531,7 @@ class Oracle:
         elif closed and not st.p0_hist:
             Rn = self.residuals(st, self.balance_ddt_p0(st))
         else:
-            Rn = self.residuals(st, self.ddt_p0(st.p0, st.p0_hist) if closed else 0.0)
+            Rn = self.residuals(st, self.ddt_p0(st.p0, st.p0_hist, st.dt_prev, st.dt_prev2) if closed else 0.0)
         M0 = [st.rho * st.v[i] for i in range(g.ndim)]
         adaptive = p.dt_tol > 0.0
         # ratio of this step to the previous one (adaptive steps)
@@ -563,7 +569,12 @@ class Oracle:
         Ms = [ab2(M0[i], Rn["v"][i], None if first else Rp["v"][i]) for i in range(g.ndim)]
         Ts = temperature(Zs if Zs is not None else 0.0, Hs, fp)
         if ode:
-            p0s = st.p0 + dt * (f_n if first else 1.5 * f_n - 0.5 * st.p0_rate_prev)
+            if first:
+                p0s = st.p0 + dt * f_n
+            elif adaptive:
+                p0s = st.p0 + dt * ((1.0 + 0.5 * w) * f_n - 0.5 * w * st.p0_rate_prev)
+            else:
+                p0s = st.p0 + dt * (1.5 * f_n - 0.5 * st.p0_rate_prev)
         else:
             p0s = self.closed_p0(Ts) if closed else p.p0
         rhos = p0s / Ts
@@ -575,7 +586,7 @@ class Oracle:
             f_s = self.p0_rate(sts)
             Rs = self.residuals(sts, f_s)
         else:
-            Rs = self.residuals(sts, self.ddt_p0(p0s, hist_s) if closed else 0.0)
+            Rs = self.residuals(sts, self.ddt_p0(p0s, hist_s, dt, st.dt_prev) if closed else 0.0)
         H1 = am2(st.H, Rs["H"], Rn["H"])
         Z1 = am2(st.Z, Rs["Z"], Rn["Z"]) if p.reacting else None
         M1 = [am2(M0[i], Rs["v"][i], Rn["v"][i]) for i in range(g.ndim)]
@@ -588,7 +599,7 @@ class Oracle:
         P1, F1, v1, b1 = self.project(M1, rho1, ddt(rho1), "corr")
         out = State(rho1, v1, Z1, H1, T1, P1, F1, rho_prev=st.rho, R_prev=Rn,
                     nstep=st.nstep + 1, p0=p01, p0_hist=(st.p0,) + tuple(st.p0_hist[:1]), dt_prev=dt,
-                    p0_rate_prev=f_n if ode else None)
+                    p0_rate_prev=f_n if ode else None, dt_prev2=st.dt_prev)
         rms = lambda a: float(np.sqrt(np.mean(np.abs(a) ** 2)))
         self.stats["pc_diff_v"] = [rms(vs[i] - v1[i]) for i in range(g.ndim)]
         self.stats["pc_diff_P"] = rms(Ps - P1)

@@ -119,3 +119,53 @@ def test_controller_tracks_tolerance_and_cfl():
             # a loose tolerance: the step climbs to the CFL step
             assert dts[-1] > 0.85 * o.cfl_dt(st)
             assert all(e < tol for e in clean)
+
+
+def _alternating(o, st, tau, m):
+    for q in range(2 * m):
+        o.dt = tau if q % 2 == 0 else 1.6 * tau
+        st = o.step(st)
+    return st
+
+
+def test_enclosed_system_unequal_steps_second_order():
+    """Enclosed system (Eq 2.40) on steps alternating tau, 1.6 tau: the
+    uniformly penalised closed box heats at constant volume, T = T_ib +
+    (T0 - T_ib) exp(-gamma t / (rho Pe Da)) in closed form; with the
+    unequal-step BDF2 of d_t p0 (and of d_t rho, AB2) the error falls at
+    second order; with the equal-step formulas on the same steps it does
+    not fall at all (the derivatives of rho and p0 are then inconsistent)."""
+    import math as _m
+    g = Grid((8, 6), (1.0, 1.0))
+    T0, T_ib, Da, Re, Pr, gam = 1.0, 2.0, 0.5, 10.0, 0.7, 1.4
+    lam = gam / ((1.0 / T0) * Re * Pr * Da)
+    for adaptive, lo, hi in ((True, 3.5, 4.5), (False, 0.0, 1.5)):
+        errs = []
+        for m in (4, 8, 16):
+            tau = 0.4 / (2.6 * m)
+            p = Params(Re=Re, Pr=Pr, sigma=0.0, Da_ib=Da, dt=tau, p0_closed=1, gamma=gam,
+                       dt_tol=1e30 if adaptive else 0.0, cfl=1e30)
+            o = Oracle(g, p, ib={"chi": np.ones(g.shape), "H_ib": np.full(g.shape, T_ib + 1.0)})
+            st = o.initial_state(np.full(g.shape, T0), [np.zeros(g.shape)] * 2)
+            st = _alternating(o, st, tau, m)
+            errs.append(abs(float(st.T.mean()) - (T_ib + (T0 - T_ib) * _m.exp(-lam * 0.4))))
+        ratios = [a / b for a, b in zip(errs, errs[1:])]
+        assert all(lo < r < hi for r in ratios), (adaptive, errs, ratios)
+
+
+def test_semi_enclosed_unequal_steps_second_order():
+    """Semi-enclosed system (Eq 2.38): compression through an inflow side
+    on alternating steps; p0 self-converges at second order with the
+    unequal-step AB2 of the ODE."""
+    n, ny, U = 16, 2, 0.5
+    x = (np.arange(n) + 0.5) / n
+    res = []
+    for m in (8, 16, 32):
+        tau = 0.2 / (2.6 * m)
+        g = Grid((n, ny), (1.0, 0.125), bc=(("inflow", "noslip"), ("periodic", "periodic")),
+                 bnd={(0, 0): dict(v=[U, 0.0], H=2.0, F=U)})
+        o = Oracle(g, Params(Re=1e6, Pr=0.71, p0_closed=2, gamma=1.4, dt=tau, dt_tol=1e30, cfl=1e30))
+        st = o.initial_state(np.ones((ny, n)), [np.broadcast_to(U * (1 - x), (ny, n)).copy(), np.zeros((ny, n))])
+        res.append(_alternating(o, st, tau, m).p0)
+    r = (res[0] - res[1]) / (res[1] - res[2])
+    assert 3.5 < r < 4.5, (res, r)
