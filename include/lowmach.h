@@ -134,9 +134,9 @@ typedef struct {
  *                [0.9, 1.1]; growth stops at the CFL step of the new state
  *                (cfl > 0 required) and the step drops to 0.9 of it when
  *                that falls below the current step. Unequal steps use
- *                Adams-Bashforth 2 and BDF2 for unequal spacing. Steps are
- *                never rejected. Not with p0_closed (LM_EUNSUPPORTED) or
- *                with_adjoint.                                            */
+ *                Adams-Bashforth 2 and BDF2 for unequal spacing (also for
+ *                the d_t p0 of p0_closed systems). Steps are never
+ *                rejected. Not with with_adjoint.                         */
 typedef struct {
   double Re, Pr, sigma, inv_Fr2;
   int reacting;

@@ -241,10 +241,6 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
         *err = "p0_closed needs periodic or wall sides (inflow sides too with 2) and non-reacting flow";
       return false;
     }
-    if (c->prm.dt_tol > 0.0) {
-      if (err) *err = "adaptive steps are not available for an enclosed system";
-      return false;
-    }
   }
   c->p0d = (P0Dev *)cv.take(sizeof(P0Dev));
   const Lay &L = c->lay;

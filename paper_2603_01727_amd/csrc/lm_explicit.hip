@@ -941,6 +941,13 @@ __global__ void __launch_bounds__(kBlock) k_p0_sum(Lay L, const double *T, const
   if (linear_tid() == 0) part[linear_block()] = s;
 }
 
+// Derivative at the newest of three levels spaced dt_new (newest pair) and
+// dt_old: BDF2 for unequal steps in level differences, w = dt_new / dt_old.
+__device__ inline double bdf2_unequal(double p_new, double p_mid, double p_old, double dt_new, double dt_old) {
+  const double w = dt_new / dt_old;
+  return ((1.0 + 2.0 * w) / (1.0 + w) * (p_new - p_mid) - w * w / (1.0 + w) * (p_mid - p_old)) / dt_new;
+}
+
 // Per-block partial sums over the cells of the H residual's diffusion term
 // sum_d delta_1(kappa_f delta_1 H) (ghost-filled level): times dV it is the
 // integral of div(kappa grad H) of Eq 2.38, the boundary faces' fluxes.
@@ -975,6 +982,7 @@ __global__ void __launch_bounds__(kBlock) k_p0_finish(int what, const double *pa
     q->p0[0] = q->p0[1] = q->p0[2] = p_init;
     q->p0_star = q->p0_new = p_init;
     q->dtp0_n = q->dtp0_star = q->dtp0_start = q->rate_prev = 0.0;
+    q->dt_hist[0] = q->dt_hist[1] = 0.0;
     q->nhist = 0;
   } else if (what == 5 || what == 7) {
     // Eq 2.38: (gamma/V) [qs/Pe int div(kappa grad H) - p0 int div v]
@@ -985,14 +993,23 @@ __global__ void __launch_bounds__(kBlock) k_p0_finish(int what, const double *pa
     else
       q->dtp0_star = r;
   } else if (what == 6) {
-    q->p0_star = q->p0[0] + dt * (q->nhist == 0 ? q->dtp0_n : 1.5 * q->dtp0_n - 0.5 * q->rate_prev);
+    if (q->nhist == 0)
+      q->p0_star = q->p0[0] + dt * q->dtp0_n;
+    else if (P.var_step)
+      q->p0_star = q->p0[0] + dt * (P.ab0 * q->dtp0_n + P.ab1 * q->rate_prev);
+    else
+      q->p0_star = q->p0[0] + dt * (1.5 * q->dtp0_n - 0.5 * q->rate_prev);
   } else if (what == 8) {
     q->p0_new = q->p0[0] + 0.5 * dt * (q->dtp0_star + q->dtp0_n);
   } else if (what == 1) {
     const double ps = q->mass / (s * dV);
     q->p0_star = ps;
-    // d_t p0 at the predicted level: BDF2 over levels n, n-1 (Eq 3.14), BDF1 with level n only
-    q->dtp0_star = q->nhist >= 1 ? (3.0 * ps - 4.0 * q->p0[0] + q->p0[1]) / (2.0 * dt) : (ps - q->p0[0]) / dt;
+    // d_t p0 at the predicted level: BDF2 over levels n, n-1 (Eq 3.14), BDF1 with level n only;
+    // after a step of another size BDF2 for unequal steps (level differences)
+    if (q->nhist >= 1 && P.var_step)
+      q->dtp0_star = bdf2_unequal(ps, q->p0[0], q->p0[1], dt, q->dt_hist[0]);
+    else
+      q->dtp0_star = q->nhist >= 1 ? (3.0 * ps - 4.0 * q->p0[0] + q->p0[1]) / (2.0 * dt) : (ps - q->p0[0]) / dt;
   } else if (what == 2) {
     q->p0_new = q->mass / (s * dV);
   } else if (what == 3) {
@@ -1030,14 +1047,19 @@ __global__ void __launch_bounds__(kBlock) k_p0_startup(Lay L, Phys P, const P0De
 
 // Commit of a completed step: history shift and d_t p0 at the new level n
 // for the next predictor (BDF2, Eq 3.5; BDF1 with one earlier level).
-__global__ void k_p0_commit(P0Dev *q, double dt) {
+__global__ void k_p0_commit(P0Dev *q, double dt, int unequal) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   q->rate_prev = q->dtp0_n;  // Eq 2.38 systems: the level-n rate for the next AB2
   q->p0[2] = q->p0[1];
   q->p0[1] = q->p0[0];
   q->p0[0] = q->p0_new;
+  q->dt_hist[1] = q->dt_hist[0];
+  q->dt_hist[0] = dt;
   q->nhist = q->nhist < 2 ? q->nhist + 1 : 2;
-  q->dtp0_n = q->nhist >= 2 ? (3.0 * q->p0[0] - 4.0 * q->p0[1] + q->p0[2]) / (2.0 * dt) : (q->p0[0] - q->p0[1]) / dt;
+  if (q->nhist >= 2 && unequal)
+    q->dtp0_n = bdf2_unequal(q->p0[0], q->p0[1], q->p0[2], q->dt_hist[0], q->dt_hist[1]);
+  else
+    q->dtp0_n = q->nhist >= 2 ? (3.0 * q->p0[0] - 4.0 * q->p0[1] + q->p0[2]) / (2.0 * dt) : (q->p0[0] - q->p0[1]) / dt;
 }
 
 hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0Dev *p0, Level *lv, const Level *n0,
@@ -1071,7 +1093,7 @@ hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0De
       hipLaunchKernelGGL(k_p0_startup, g, bl, 0, st, L, P, (const P0Dev *)p0, (const double *)n0->rho, RH, *lv);
       break;
     case 4:
-      hipLaunchKernelGGL(k_p0_commit, dim3(1), dim3(64), 0, st, p0, P.dt);
+      hipLaunchKernelGGL(k_p0_commit, dim3(1), dim3(64), 0, st, p0, P.dt, P.var_step);
       break;
     case 5:
     case 7:

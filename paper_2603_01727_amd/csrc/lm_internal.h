@@ -68,6 +68,7 @@ struct P0Dev {
   double dtp0_star;    // d_t p0 at the predicted level (corrector residual)
   double dtp0_start;   // first step: d_t p0 at level n from the balance of Eq 2.40
   double rate_prev;    // Eq 2.38 systems: d_t p0 at level n-1 (AB2 of the predictor)
+  double dt_hist[2];   // sizes of the last two committed steps (newest first; adaptive steps)
   int nhist;           // committed levels before n (0, 1, 2)
 };
 

@@ -160,7 +160,7 @@ def test_sutherland_checks_without_gpu():
 
 def test_adaptive_step_checks_without_gpu():
     """dt_tol must be >= 0 and finite and needs cfl > 0; not with the
-    adjoint (EINVAL) nor with an enclosed system (EUNSUPPORTED)."""
+    adjoint (EINVAL); enclosed systems take it."""
     from paper_2603_01727_amd import lib
     L = lib.load()
     b = C.c_size_t()
@@ -174,7 +174,7 @@ def test_adaptive_step_checks_without_gpu():
     p.cfl, p.with_adjoint = 0.3, 1
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     p.with_adjoint, p.p0_closed, p.gamma = 0, 1, 1.4
-    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
 
 
 def test_semi_enclosed_checks_without_gpu():

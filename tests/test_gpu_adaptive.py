@@ -86,6 +86,35 @@ def test_adaptive_3d_matches_oracle():
     assert _run(case, 12) >= 2
 
 
+@pytest.mark.parametrize("mode", [1, 2], ids=["enclosed", "semi-enclosed"])
+def test_adaptive_closed_systems_match_oracle(mode):
+    """Adaptive steps with p0 from the conserved mass (a closed heated box,
+    BDF2 of d_t p0 for unequal steps) and from the ODE of Eq 2.38 (gas
+    pushed in through an inflow side, AB2 with the step ratio)."""
+    if mode == 1:
+        from test_gpu_p0 import _heated_box
+        case = _heated_box((64, 48), (("periodic", "periodic"), ("noslip", "noslip")))
+        case.params = dict(case.params, dt_tol=1e-7)
+    else:
+        from test_gpu_p0 import _compression_case
+        case = _compression_case(profile=True)
+        case.params = dict(case.params, dt_tol=1e-8)
+    print("adaptive p0 mode", mode, flush=True)
+    o, st = oracle_for(case)
+    s = gpu_for(case, rtol=1e-14)
+    changes = 0
+    for k in range(12):
+        st = o.step(st)
+        stats = s.step(1)
+        assert abs(stats["p0"] / st.p0 - 1) < 1e-12, (k, stats["p0"], st.p0)
+        assert abs(s.dt / o.dt - 1) < 1e-8, (k, s.dt, o.dt)
+        changes += s.dt != stats["dt"]
+        errs = compare(st, s.get(device=False))
+        print(k, stats["dt"], stats["pc_err"], st.p0, errs, flush=True)
+        _check(errs)
+    assert changes >= 1
+
+
 def test_adaptive_restart_is_exact():
     import torch
     case = c1_case(n=64)
