@@ -111,15 +111,17 @@ typedef struct {
  *                then the initial thermodynamic pressure;
  *                2: semi-enclosed system: p0 from the ordinary differential
  *                equation of Eq 2.38, d_t p0 = (gamma/V) [qs/Pe
- *                int div(kappa grad H) dV - p0 int div v dV], the first
- *                integral the sum of the H residual's diffusion term (the
- *                boundary faces' conductive fluxes), the second the volume
- *                flux out through the inflow sides (their given normal
- *                velocities); p0 advanced by the step's AB2 predictor
- *                (Euler on the first step) and trapezoid corrector, each
- *                level's rate entering its residual as d_t p0 (Eq 3.4b).
- *                Inflow sides are allowed, outflow sides, reacting flow and
- *                S_m are not
+ *                int (div(kappa grad H) + N'(Z) div(kappa grad Z)) dV
+ *                - p0 int div v dV], the first integral the sum over cells
+ *                of the H residual's diffusion term (the boundary faces'
+ *                conductive fluxes) plus, with reaction, N' of Eq 2.39
+ *                (Heaviside regularised as in Eq 3.35) times the Z
+ *                diffusion term; the second the volume flux out through
+ *                the inflow sides (their given normal velocities); p0
+ *                advanced by the step's AB2 predictor (Euler on the first
+ *                step) and trapezoid corrector, each level's rate entering
+ *                its residual as d_t p0 (Eq 3.4b). Inflow sides and
+ *                reacting flow are allowed, outflow sides and S_m are not
  *  gamma         ratio of specific heats (p0_closed only; > 1)
  *  sutherland_C  0: kappa = T^sigma; C > 0: Sutherland's law
  *                kappa = T^{3/2} (1 + C) / (T + C) (Eq 4.12), C the

@@ -45,6 +45,12 @@ def n_eps(Z, fp: FlameParams):
     return (nf - no) * theta_eps(Z - 1.0, fp) + no
 
 
+def n_prime_eps(Z, fp: FlameParams):
+    """N' of Eq 2.39 (N'_F = -1/S, N'_O = 1), regularised like Eq 3.35:
+    (N'_F - N'_O) theta_eps(Z - 1) + N'_O."""
+    return (-1.0 / fp.S - 1.0) * theta_eps(Z - 1.0, fp) + 1.0
+
+
 def _lncosh(x):
     """ln cosh x written as |x| + log1p(exp(-2|x|)) - ln 2 (no overflow)."""
     ax = np.abs(x)

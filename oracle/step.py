@@ -16,7 +16,7 @@ from typing import Optional
 
 import numpy as np
 
-from .flame import FlameParams, le_eps, n_eps, temperature, enthalpy_from_T
+from .flame import FlameParams, le_eps, n_eps, n_prime_eps, temperature, enthalpy_from_T
 from .grid import Grid, fill_ghosts, field_rules
 from .poisson import PoissonSolver
 
@@ -145,7 +145,8 @@ class Oracle:
             # semi-enclosed one (Eq 2.38) may also have inflow sides.
             banned = ("outflow",) if self.p.p0_closed == 2 else ("inflow", "outflow")
             open_side = any(g.bc[d][s] in banned for d in range(g.ndim) for s in (0, 1))
-            if open_side or self.ib.get("Sm") is not None or self.p.reacting:
+            reacting_closed = self.p.reacting and self.p.p0_closed == 1
+            if open_side or self.ib.get("Sm") is not None or reacting_closed:
                 raise ValueError("p0_closed needs walls or periodic sides (or inflow sides for Eq 2.38), "
                                  "no mass source, non-reacting flow")
         Zs = None
@@ -364,17 +365,22 @@ class Oracle:
         return 0.0
 
     def p0_rate(self, st: State):
-        """d_t p0 of a semi-enclosed system at one level, Eq 2.38 without
-        reaction: (gamma / V) [qs / Pe integral div(kappa grad H) dV - p0
-        integral div v dV]. The first integral is the sum over cells of the
-        discrete diffusion term of the H residual (it telescopes to the
-        conductive fluxes through the boundary faces); the second is the
-        volume flux out through the sides, the given normal velocity of
-        each inflow side times its face area (walls and periodic sides
-        carry none)."""
+        """d_t p0 of a semi-enclosed system at one level, Eq 2.38:
+        (gamma / V) [qs / Pe integral (div(kappa grad H) + N' div(kappa grad
+        Z)) dV - p0 integral div v dV], N' of Eq 2.39 regularised like
+        Eq 3.35 (reacting flow only). The first integral is the sum over
+        cells of the discrete diffusion terms of the residuals (the H part
+        telescopes to the conductive fluxes through the boundary faces);
+        the second is the volume flux out through the sides, the given
+        normal velocity of each inflow side times its face area (walls and
+        periodic sides carry none)."""
         g, p = self.g, self.p
-        _, _, Hp, Tp = self.padded_fields(st)
-        _, dif = self._scalar_terms(Hp, self.conductivity(Tp), st.F)
+        _, Zp, Hp, Tp = self.padded_fields(st)
+        kapp = self.conductivity(Tp)
+        _, dif = self._scalar_terms(Hp, kapp, st.F)
+        if p.reacting:
+            _, difZ = self._scalar_terms(Zp, kapp, st.F)
+            dif = dif + n_prime_eps(st.Z, self.fp) * difZ
         heat = float(np.sum(dif)) * g.dV
         flux = 0.0
         for d in range(g.ndim):

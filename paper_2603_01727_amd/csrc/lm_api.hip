@@ -236,9 +236,11 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
       for (int s = 0; s < 2; ++s)
         open = open || (c->grid.bc[d][s] == LM_SIDE_INFLOW && c->prm.p0_closed == 1) ||
                c->grid.bc[d][s] == LM_SIDE_OUTFLOW;
-    if (open || c->prm.reacting) {
+    // the mass form of Eq 2.40 maps T with the non-reacting T(H) only;
+    // Eq 2.38 carries the flame's heat through its N' term
+    if (open || (c->prm.reacting && c->prm.p0_closed == 1)) {
       if (err)
-        *err = "p0_closed needs periodic or wall sides (inflow sides too with 2) and non-reacting flow";
+        *err = "p0_closed needs periodic or wall sides (inflow sides too with 2); 1 needs non-reacting flow";
       return false;
     }
   }

@@ -950,7 +950,10 @@ __device__ inline double bdf2_unequal(double p_new, double p_mid, double p_old, 
 
 // Per-block partial sums over the cells of the H residual's diffusion term
 // sum_d delta_1(kappa_f delta_1 H) (ghost-filled level): times dV it is the
-// integral of div(kappa grad H) of Eq 2.38, the boundary faces' fluxes.
+// integral of div(kappa grad H) of Eq 2.38, the boundary faces' fluxes. With
+// reaction each cell adds N'(Z) sum_d delta_1(kappa_f delta_1 Z), N' of
+// Eq 2.39 (-1/S on the fuel side, 1 on the oxidiser side) with the Heaviside
+// regularised as in Eq 3.35: the heat the flame releases.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_p0_heat(Lay L, Phys P, Level lv, double *part) {
   __shared__ double sh[kBlock / 64];
@@ -959,6 +962,11 @@ __global__ void __launch_bounds__(kBlock) k_p0_heat(Lay L, Phys P, Level lv, dou
   if (cell_of_thread(L, p)) {
     double adv;
     scalar_terms<DIM>(L, P, lv, lv.H, p.c, adv, v);
+    if (P.reacting) {
+      double difZ;
+      scalar_terms<DIM>(L, P, lv, lv.Z, p.c, adv, difZ);
+      v += ((-1.0 / P.S - 1.0) * theta_eps(P, lv.Z[p.c]) + 1.0) * difZ;
+    }
   }
   const double s = block_sum(v, sh);
   if (linear_tid() == 0) part[linear_block()] = s;

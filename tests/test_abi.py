@@ -121,7 +121,8 @@ def test_variable_coefficient_reservation():
 
 def test_enclosed_system_checks_without_gpu():
     """p0_closed: gamma must exceed 1; reacting flow, inflow or outflow
-    sides are not an enclosed system; the adjoint needs constant p0."""
+    sides are not an enclosed system (reacting flow is a semi-enclosed
+    one); the adjoint needs constant p0."""
     from paper_2603_01727_amd import lib
     L = lib.load()
     b = C.c_size_t()
@@ -132,6 +133,9 @@ def test_enclosed_system_checks_without_gpu():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     p.gamma, p.reacting = 1.4, 1
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    p.p0_closed = 2                          # Eq 2.38 carries the flame's heat
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+    p.p0_closed, p.reacting = 1, 0
     g, p = _grid_params((64, 64), bc=[(2, 2), (3, 4), (0, 0)])   # noslip x, inflow / outflow y
     p.p0_closed, p.gamma = 1, 1.4
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED

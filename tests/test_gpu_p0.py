@@ -152,7 +152,27 @@ def _compression_case(n=(32, 8), U=0.1, profile=False):
                 np.ones(shape), v, bnd=bnd)
 
 
-@pytest.mark.parametrize("name", ["profile", "3d", "heated-box"])
+def _reacting_box_case(n=(32, 32)):
+    """A flame in a closed box (Eq 2.38 with the N' term of Eq 2.39): a
+    fuel blob (Z up to S + 1, crossing the flame level Z = 1) in oxidiser
+    at uniform excess enthalpy, no-slip walls across x, slip walls across
+    the other directions, gravity along y, unequal Lewis numbers."""
+    from workloads import Case
+    nd = len(n)
+    shape = tuple(reversed(n))
+    S = 3.0
+    axes = [(np.arange(m) + 0.5) / m for m in n]
+    X = np.meshgrid(*reversed(axes), indexing="ij")[::-1]          # X[d] varies along axis d
+    r2 = sum((X[d] - c) ** 2 for d, c in zip(range(nd), (0.45, 0.55, 0.5)))
+    Z = (S + 1.0) * np.exp(-r2 / 0.04)
+    bc = (("noslip", "noslip"),) + (("slip", "slip"),) * (nd - 1)
+    params = dict(Re=20.0, Pr=0.71, inv_Fr2=1.0, reacting=True, S=S, qs=0.5, eps=0.5, tol=1e-3,
+                  Le_F=0.7, Le_O=1.2, p0_closed=2, gamma=1.4, cfl=0.2)
+    return Case("reacting-box", nd, tuple(n) + (1,) * (3 - nd), (1.0,) * 3, bc, params, None,
+                [np.zeros(shape) for _ in range(nd)], Z=Z, H=np.full(shape, 3.0))
+
+
+@pytest.mark.parametrize("name", ["profile", "3d", "heated-box", "reacting", "reacting-3d"])
 def test_semi_enclosed_matches_oracle(name):
     """(A uniform inflow leaves the transverse velocity zero up to rounding
     on both sides, which a relative comparison cannot use: the inflow
@@ -161,10 +181,14 @@ def test_semi_enclosed_matches_oracle(name):
         case = _compression_case(profile=True)
     elif name == "3d":
         case = _compression_case(n=(24, 8, 8), profile=True)
-    else:
+    elif name == "heated-box":
         from workloads import heated_cavity_case
         case = heated_cavity_case(n=32)           # walls only: Eq 2.38 against the heat flux
         case.params = dict(case.params, p0_closed=2)
+    elif name == "reacting":
+        case = _reacting_box_case()
+    else:
+        case = _reacting_box_case(n=(16, 16, 16))
     print("semi-enclosed", name, flush=True)
     o, st = oracle_for(case)
     s = gpu_for(case)
@@ -176,5 +200,7 @@ def test_semi_enclosed_matches_oracle(name):
         errs = compare(st, s.get(device=False))
         print(k, st.p0, errs, flush=True)
         _check(errs)
-    if name != "heated-box":
+    if name in ("profile", "3d"):
         assert st.p0 > 1.0 + 1e-4                 # compressed
+    if name.startswith("reacting"):
+        assert st.p0 > 1.0 + 1e-7                 # the flame heats the box

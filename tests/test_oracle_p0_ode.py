@@ -71,3 +71,43 @@ def test_ode_and_mass_forms_converge_together():
         assert c > 1.01                                             # the wall heated the box
         lim[mode] = c + (c - b) / 3.0
     assert abs(lim[1] - lim[2]) < 1e-7, lim
+
+
+def _reacting_box_p0(n, eps):
+    """Closed box with adiabatic walls and a mixture-fraction profile that
+    crosses the flame level: the H integral of Eq 2.38 vanishes, so the whole
+    rise of p0 comes from the N' term (the heat the flame releases)."""
+    g = Grid((n, 2), (1.0, 2.0 / n), bc=(("noslip", "noslip"), ("periodic", "periodic")))
+    x = (np.arange(n) + 0.5) / n
+    Z = np.broadcast_to(0.2 + 2.0 * (1 - x) ** 2 * (1 + 2 * x), (2, n)).copy()   # zero slope at both walls
+    dt = 0.4 / n ** 2
+    o = Oracle(g, Params(Re=5.0, Pr=0.71, reacting=True, S=3.0, qs=0.5, eps=eps, tol=1e-3,
+                         Le_F=0.7, Le_O=1.2, p0_closed=2, gamma=1.4, dt=dt))
+    st = o.initial_state(None, [np.zeros((2, n)), np.zeros((2, n))], Z=Z, H=np.full((2, n), 3.0))
+    m = o.mass
+    st = o.run(st, int(round(0.05 / dt)))
+    return st.p0, m / (float(np.sum(1.0 / st.T)) * g.dV)
+
+
+def test_reacting_ode_matches_mass_form_up_to_regularisation():
+    """Eq 2.38 with N' of Eq 2.39 against the mass form of Eq 2.40 taken from
+    the same run (the box conserves mass). With the sharp Heaviside the two
+    are one identity (N + N'/Le = N' on both sides of the flame, and N' is
+    the slope of the T(Z, H) map); the regularisation of section 3.5 breaks
+    it inside the flame layer only, so the gap between the two grid-converged
+    limits is first order in eps and small against the rise of p0. A dropped
+    or mis-signed N' term, or N in its place, leaves a gap of the order of
+    the rise itself."""
+    gap = {}
+    for eps in (0.5, 0.25):
+        r = [_reacting_box_p0(n, eps) for n in (32, 64, 128)]
+        lim = []
+        for k in (0, 1):
+            a, b, c = (x[k] for x in r)
+            assert 3.5 < (a - b) / (b - c) < 4.5, (eps, k, a, b, c)   # second order
+            lim.append(c + (c - b) / 3.0)
+        rise = lim[1] - 1.0
+        assert rise > 0.04                                           # the flame heats the box
+        gap[eps] = lim[0] - lim[1]
+        assert abs(gap[eps]) < 0.01 * rise, (eps, lim)
+    assert 0.4 < gap[0.25] / gap[0.5] < 0.6, gap                     # first order in eps
