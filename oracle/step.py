@@ -147,8 +147,8 @@ class Oracle:
             open_side = any(g.bc[d][s] in banned for d in range(g.ndim) for s in (0, 1))
             reacting_closed = self.p.reacting and self.p.p0_closed == 1
             if open_side or self.ib.get("Sm") is not None or reacting_closed:
-                raise ValueError("p0_closed needs walls or periodic sides (or inflow sides for Eq 2.38), "
-                                 "no mass source, non-reacting flow")
+                raise ValueError("p0_closed needs walls or periodic sides (or inflow sides for Eq 2.38) and "
+                                 "no mass source; the enclosed form (1) also needs non-reacting flow")
         Zs = None
         if self.p.reacting:
             Zs = np.zeros(g.shape) if Z is None else _real_or_complex(Z)
