@@ -121,7 +121,9 @@ typedef struct {
  *                advanced by the step's AB2 predictor (Euler on the first
  *                step) and trapezoid corrector, each level's rate entering
  *                its residual as d_t p0 (Eq 3.4b). Inflow sides and
- *                reacting flow are allowed, outflow sides and S_m are not
+ *                reacting flow are allowed; outflow sides, S_m and
+ *                immersed bodies (Eq 2.38 has no term for the heat of the
+ *                penalisation) are not
  *  gamma         ratio of specific heats (p0_closed only; > 1)
  *  sutherland_C  0: kappa = T^sigma; C > 0: Sutherland's law
  *                kappa = T^{3/2} (1 + C) / (T + C) (Eq 4.12), C the

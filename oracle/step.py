@@ -146,9 +146,11 @@ class Oracle:
             banned = ("outflow",) if self.p.p0_closed == 2 else ("inflow", "outflow")
             open_side = any(g.bc[d][s] in banned for d in range(g.ndim) for s in (0, 1))
             reacting_closed = self.p.reacting and self.p.p0_closed == 1
-            if open_side or self.ib.get("Sm") is not None or reacting_closed:
+            # Eq 2.38 has no term for the penalisation's heat (Eq 3.31-3.32)
+            body_ode = self.p.p0_closed == 2 and self.ib.get("chi") is not None
+            if open_side or self.ib.get("Sm") is not None or reacting_closed or body_ode:
                 raise ValueError("p0_closed needs walls or periodic sides (or inflow sides for Eq 2.38) and "
-                                 "no mass source; the enclosed form (1) also needs non-reacting flow")
+                                 "no mass source; the enclosed form (1) also needs non-reacting flow, the ODE (2) no immersed body")
         Zs = None
         if self.p.reacting:
             Zs = np.zeros(g.shape) if Z is None else _real_or_complex(Z)

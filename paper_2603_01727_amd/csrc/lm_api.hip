@@ -243,6 +243,12 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
         *err = "p0_closed needs periodic or wall sides (inflow sides too with 2); 1 needs non-reacting flow";
       return false;
     }
+    // Eq 2.38 has no term for the heat and species the penalisation of
+    // Eq 3.31-3.32 puts in or takes out (the mass form needs none)
+    if (c->prm.p0_closed == 2 && c->prm.with_ib) {
+      if (err) *err = "p0_closed = 2 (Eq 2.38) takes no immersed body";
+      return false;
+    }
   }
   c->p0d = (P0Dev *)cv.take(sizeof(P0Dev));
   const Lay &L = c->lay;

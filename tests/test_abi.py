@@ -135,6 +135,9 @@ def test_enclosed_system_checks_without_gpu():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
     p.p0_closed = 2                          # Eq 2.38 carries the flame's heat
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
+    p.with_ib, p.Da_ib = 1, 1e-3             # but not the penalisation's
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
+    p.with_ib = 0
     p.p0_closed, p.reacting = 1, 0
     g, p = _grid_params((64, 64), bc=[(2, 2), (3, 4), (0, 0)])   # noslip x, inflow / outflow y
     p.p0_closed, p.gamma = 1, 1.4
