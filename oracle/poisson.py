@@ -11,16 +11,28 @@ for the variable-coefficient form, beta = 1/rho_f for div(grad P / rho)
 a prescribed mass flux, so A has zero flux there (a pure Neumann problem,
 section 3.3). The singular system is closed by the augmented-matrix method of
 section 3.3: [A 1; 1^T 0][P; lam] = [b; 0], whose solution is the zero-mean P,
-with lam = mean(b) absorbing any compatibility residue. On fully periodic
-grids with beta = 1 the same solution is obtained by FFT diagonalisation.
+with lam = mean(b) absorbing any compatibility residue. With beta = 1 the
+operator is separable on every uniform grid: the Fourier modes diagonalise
+it along periodic directions and the cosine modes of the DCT-II along the
+zero-flux ones, so the same zero-mean solution is obtained by transforming
+b, dividing by the eigenvalues (the constant mode, eigenvalue 0, is
+dropped: that removes mean(b) and fixes the mean of P at 0) and
+transforming back. With a face coefficient beta the augmented matrix is
+factored by sparse LU.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft as sfft
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .grid import Grid
+
+# threads of the scipy.fft transforms (the elementwise NumPy work runs on one)
+FFT_WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
 
 
 def face_grad(g: Grid, P, d):
@@ -76,6 +88,23 @@ def beta_inv_rho(g: Grid, rho):
     return out
 
 
+def transform_eigenvalues(g: Grid):
+    """Eigenvalues of A (beta = 1) on the separable modes of any uniform
+    grid: along a periodic direction the Fourier mode k has
+    -(4/h_d^2) sin^2(pi k / n_d); along a zero-flux direction the cosine
+    mode cos(pi m (i + 1/2) / n_d) of the DCT-II has
+    -(4/h_d^2) sin^2(pi m / (2 n_d))."""
+    lam = np.zeros(g.shape)
+    for d in range(g.ndim):
+        k = np.arange(g.n[d])
+        den = g.n[d] if g.periodic(d) else 2 * g.n[d]
+        ld = -(4.0 / g.h[d] ** 2) * np.sin(np.pi * k / den) ** 2
+        shp = [1] * g.ndim
+        shp[g.axis(d)] = g.n[d]
+        lam = lam + ld.reshape(shp)
+    return lam
+
+
 def periodic_eigenvalues(g: Grid):
     """Eigenvalues of A (beta = 1) on the Fourier modes of a periodic grid:
     lam(k) = -sum_d (4/h_d^2) sin^2(pi k_d / n_d)."""
@@ -90,17 +119,28 @@ def periodic_eigenvalues(g: Grid):
 
 
 class PoissonSolver:
-    """Solves A P = b for the zero-mean P; returns (P, mean(b))."""
+    """Solves A P = b for the zero-mean P; returns (P, mean(b)).
 
-    def __init__(self, g: Grid, beta=None):
+    beta None: transform solve (FFT along periodic directions, DCT-II along
+    the others); ``method="lu"`` forces the sparse LU of the augmented
+    matrix instead. A face coefficient beta always takes the LU."""
+
+    def __init__(self, g: Grid, beta=None, method=None):
         self.g = g
         self.beta = beta
-        self.fft = g.all_periodic and beta is None
-        if self.fft:
-            lam = periodic_eigenvalues(g)
+        self.transform = beta is None and method != "lu"
+        self.fft = self.transform and g.all_periodic
+        if self.transform:
+            self.per_axes = [g.axis(d) for d in range(g.ndim) if g.periodic(d)]
+            self.neu_axes = [g.axis(d) for d in range(g.ndim) if not g.periodic(d)]
+            lam = transform_eigenvalues(g)
+            if self.per_axes:
+                # the real FFT keeps n//2 + 1 modes along its last axis
+                last = self.per_axes[-1]
+                lam = np.take(lam, np.arange(lam.shape[last] // 2 + 1), axis=last)
             lam.flat[0] = 1.0
             self.inv = 1.0 / lam
-            self.inv.flat[0] = 0.0
+            self.inv.flat[0] = 0.0       # constant mode: zero mean
         else:
             self.lu = spla.splu(self._augmented().tocsc())
 
@@ -144,17 +184,31 @@ class PoissonSolver:
         del cols
         return aug
 
+    def _transform_solve(self, b):
+        c = b
+        if self.neu_axes:
+            c = sfft.dctn(c, type=2, axes=self.neu_axes, norm="ortho", workers=FFT_WORKERS)
+        if self.per_axes:
+            c = sfft.rfftn(c, axes=self.per_axes, workers=FFT_WORKERS)
+            c = c * self.inv
+            s = [b.shape[a] for a in self.per_axes]
+            c = sfft.irfftn(c, s=s, axes=self.per_axes, workers=FFT_WORKERS)
+        else:
+            c = c * self.inv
+        if self.neu_axes:
+            c = sfft.idctn(c, type=2, axes=self.neu_axes, norm="ortho", workers=FFT_WORKERS)
+        return c
+
     def solve(self, b):
         g = self.g
         lam = np.mean(b)
-        if self.fft:
+        if self.transform:
             if np.iscomplexobj(b):
                 # the solve is a real-linear map: apply it to both parts
                 # separately so that rounding of the real part never leaks
                 # into the imaginary part (complex-step derivatives)
                 return self.solve(b.real)[0] + 1j * self.solve(b.imag)[0], lam
-            P = np.fft.ifftn(np.fft.fftn(b) * self.inv).real
-            return P, lam
+            return self._transform_solve(np.asarray(b, dtype=np.float64)), lam
         N = b.size
         rhs = np.concatenate([b.ravel(), [0.0]])
         if np.iscomplexobj(rhs):

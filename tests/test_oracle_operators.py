@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import Grid, Oracle, Params, fill_ghosts
-from oracle.grid import extrap_coeffs
+from oracle.grid import extrap_coeffs, field_rules
 from workloads import cell_centres
 
 TWO_PI = 2 * math.pi
@@ -122,3 +122,58 @@ def test_ghost_rules_reproduce_boundary_conditions():
     # zero Neumann: ghost equals first interior value, corners included
     assert np.array_equal(p[0, :], p[1, :])
     assert np.array_equal(p[-1, :], p[-2, :])
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_outflow_face_flux_is_exact_for_quadratic_momentum(side):
+    """The outflow face carries the cell momentum extrapolated to the face
+    by the quadratic through the three nearest cells (the outflow closure
+    of section 4.5 with the quadratic rule of Eq 3.28): for a momentum
+    field quadratic in the outflow direction the face value is exact.
+    The mirrored ghost averaged with the first cell (the interior face
+    rule at a boundary) or a linear rule misses by c h^2 / 4 or more."""
+    bc = (("periodic", "periodic"), ("outflow", "slip") if side == 0 else ("inflow", "outflow"))
+    g = Grid((3, 10), (1.0, 2.0), bc=bc)
+    x, y = cell_centres(g.n, g.L)
+    a, b, c = 0.7, -1.3, 2.9
+    m = lambda s: a + b * s + c * s * s
+    M = [np.zeros(g.shape), np.broadcast_to(m(y) + 0 * x, g.shape).copy()]
+    o = Oracle(g, Params())
+    F = o.face_average_flux(M)
+    yf = 0.0 if side == 0 else g.L[1]
+    face = F[1][0, :] if side == 0 else F[1][-1, :]
+    assert np.max(np.abs(face - m(yf))) < 1e-13
+    # the interior faces stay two-point averages (Eq 3.20, n = 1)
+    inner = 0.5 * (M[1][:-1, :] + M[1][1:, :])
+    assert np.max(np.abs(F[1][1:-1, :] - inner)) < 1e-15
+    # a plausible wrong rule: the average of the first cell and its
+    # quadratically extrapolated ghost
+    h = g.h[1]
+    m1 = m(yf + (h / 2 if side == 0 else -h / 2))
+    ghost = m(yf + (-h / 2 if side == 0 else h / 2))
+    assert abs(0.5 * (m1 + ghost) - m(yf)) > 0.2 * c * h * h
+
+
+def test_inflow_footprint_ghosts_mix_dirichlet_and_zero_gradient():
+    """An inflow side partly covered by a solid footprint: on footprint
+    cells the scalars take the zero-gradient ghost (Eq 3.44 with zero
+    flux), elsewhere the mirrored Dirichlet ghost of the given value
+    (Eq 3.43); the velocity is Dirichlet on every cell of the side."""
+    g = Grid((8, 6), (1.0, 1.0), bc=(("periodic", "periodic"), ("inflow", "outflow")))
+    wall = np.zeros(8, dtype=bool)
+    wall[2:5] = True
+    Zb = np.linspace(0.5, 1.2, 8)
+    vb = [np.zeros(8), np.where(wall, 0.0, 0.3)]
+    g.bnd[(1, 0)] = {"Z": Zb, "H": 2.5, "v": vb, "F": np.where(wall, 0.0, 0.3), "wall": wall}
+    rng = np.random.default_rng(3)
+    q = rng.standard_normal(g.shape)
+    for field, val in (("Z", Zb), ("H", np.full(8, 2.5))):
+        p = g.pad(q)
+        fill_ghosts(g, p, field_rules(g, field))
+        ghost, inner = p[0, 1:-1], p[1, 1:-1]
+        assert np.array_equal(ghost[wall], inner[wall])                         # zero gradient
+        assert np.max(np.abs(0.5 * (ghost[~wall] + inner[~wall]) - val[~wall])) < 1e-15   # face value
+    for comp in (0, 1):
+        p = g.pad(q)
+        fill_ghosts(g, p, field_rules(g, "v", comp))
+        assert np.max(np.abs(0.5 * (p[0, 1:-1] + p[1, 1:-1]) - vb[comp])) < 1e-15

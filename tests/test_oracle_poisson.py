@@ -180,3 +180,45 @@ def test_beta_inv_rho_manufactured_second_order():
         errs.append(math.sqrt(np.mean((P - (Pex - Pex.mean())) ** 2)))
     for a, c in zip(errs, errs[1:]):
         assert abs(math.log(a / c, 2) - 2) < 0.15, errs
+
+
+def test_transform_solve_matches_augmented_matrix():
+    """With beta = 1 the oracle solves by transforms (Fourier along
+    periodic directions, DCT-II along zero-flux ones, section 3.3's
+    zero-mean solution); the sparse LU of the augmented matrix
+    [A 1; 1^T 0] gives the same P and lam = mean(b), on every mix of
+    periodic and zero-flux sides, odd sizes included."""
+    cases = [((16, 20), (("slip", "slip"), ("inflow", "outflow"))),
+             ((12, 10), (("periodic", "periodic"), ("noslip", "noslip"))),
+             ((9, 12), (("slip", "noslip"), ("periodic", "periodic"))),
+             ((8, 6, 10), (("periodic", "periodic"), ("slip", "slip"), ("periodic", "periodic"))),
+             ((7, 6, 5), (("slip", "slip"), ("outflow", "inflow"), ("noslip", "noslip"))),
+             ((9, 7), None)]
+    for n, bc in cases:
+        g = Grid(n, (1.0, 1.3, 0.7)[:len(n)], bc=bc)
+        b = np.random.default_rng(len(n) + n[0]).standard_normal(g.shape) + 0.3
+        P, lam = PoissonSolver(g).solve(b)
+        assert PoissonSolver(g).transform
+        Pl, laml = PoissonSolver(g, method="lu").solve(b)
+        assert abs(lam - laml) < 1e-13
+        assert np.max(np.abs(P - Pl)) < 1e-13 * np.max(np.abs(Pl)), (n, bc)
+        r = laplacian(g, P) - (b - b.mean())
+        assert np.max(np.abs(r)) < 1e-12 * np.max(np.abs(b))
+
+
+def test_transform_solve_on_zero_flux_cosine_mode():
+    """A single cosine mode of the DCT-II on a box with zero-flux sides
+    in x and periodic y is returned divided by its eigenvalue (the
+    closed form of the Neumann eigenpair pinned above); a wrong
+    eigenvalue (the periodic sin^2(pi m / n) along x) misses by O(1)."""
+    g = Grid((24, 16), (1.0, 2.0), bc=(("slip", "outflow"), ("periodic", "periodic")))
+    i = np.arange(24)
+    j = np.arange(16)
+    m, k = 5, 3
+    u = np.cos(math.pi * m * (i[None, :] + 0.5) / 24) * np.cos(2 * math.pi * k * (j[:, None] + 0.5) / 16)
+    lam = -(4 / g.h[0] ** 2) * math.sin(math.pi * m / 48) ** 2 - (4 / g.h[1] ** 2) * math.sin(math.pi * k / 16) ** 2
+    P, mb = PoissonSolver(g).solve(u)
+    assert abs(mb) < 1e-15
+    assert np.max(np.abs(P - u / lam)) < 1e-13 * np.max(np.abs(u / lam))
+    lam_wrong = -(4 / g.h[0] ** 2) * math.sin(math.pi * m / 24) ** 2 - (4 / g.h[1] ** 2) * math.sin(math.pi * k / 16) ** 2
+    assert np.max(np.abs(P - u / lam_wrong)) > 0.1 * np.max(np.abs(u / lam))

@@ -145,3 +145,50 @@ def test_slot_flame_mass_closure_and_injection_rate():
     assert np.max(np.abs(r)) < 1e-8
     # temperature stays within the flame-sheet bounds [1, 7]
     assert st2.T.min() > 0.99 and st2.T.max() < 7.0 + 1e-9
+
+
+def _stratified_column(ny, inv_Fr2=4.0, dt=1e-3):
+    """Gas at rest between isothermal slip walls (bottom T = 1, top
+    T = 2.5), periodic in x, with the linear conduction profile
+    T = 1 + 1.5 y and kappa = 1 (sigma = 0): the discrete diffusion of
+    the linear H vanishes, so rho stays put and the only force is the
+    buoyancy (1/Fr^2)(1 - rho) e_y of Eq 3.8b. Returns the oracle, the
+    initial state and the predicted level of one step."""
+    H0, s = 2.0, 1.5
+    g = Grid((4, ny), (1.0, 1.0), bc=(("periodic", "periodic"), ("slip", "slip")),
+             bnd={(1, 0): {"H": np.full(4, H0)}, (1, 1): {"H": np.full(4, H0 + s)}})
+    x, y = cell_centres(g.n, g.L)
+    H = np.broadcast_to(H0 + s * y + 0 * x, g.shape).copy()
+    o = Oracle(g, Params(Re=50.0, Pr=0.7, sigma=0.0, inv_Fr2=inv_Fr2, dt=dt))
+    st = o.initial_state(None, [np.zeros(g.shape)] * 2, H=H)
+    o.step(st)
+    return o, st, o.last_predicted, y[:, 0]
+
+
+def test_buoyancy_gives_hydrostatic_pressure():
+    """At rest, the projection balances buoyancy: the predicted face flux
+    vanishes and P = p dt is the hydrostatic pressure,
+    P(y) = dt (1/Fr^2) integral (1 - rho) dy (Eq 3.8b with Eq 3.23-3.24),
+    exactly in its discrete form (the face difference of P equals the
+    face average of the buoyancy momentum: the trapezoid rule over cell
+    centres) and at second order against the integral of
+    1 - 1/T(y) = 1 - 1/(1 + 1.5 y). A sign error, a misplaced 1/Fr^2, the
+    force on the wrong component or a missing dt fails."""
+    inv_Fr2, dt = 4.0, 1e-3
+    errs = []
+    for ny in (16, 32, 64):
+        o, st, pr, yc = _stratified_column(ny, inv_Fr2, dt)
+        g = o.g
+        assert np.max(np.abs(pr.F[1])) < 1e-15 and np.max(np.abs(pr.F[0])) < 1e-15
+        assert np.max(np.ptp(pr.P, axis=1)) == 0.0
+        rho = st.rho[:, 0]
+        dP = g.h[1] * dt * inv_Fr2 * (1.0 - 0.5 * (rho[1:] + rho[:-1]))
+        Pd = np.concatenate([[0.0], np.cumsum(dP)])
+        Pd -= Pd.mean()
+        assert np.max(np.abs(pr.P[:, 0] - Pd)) < 1e-13 * np.max(np.abs(Pd))
+        Pc = dt * inv_Fr2 * (yc - np.log(1.0 + 1.5 * yc) / 1.5)
+        Pc -= Pc.mean()
+        errs.append(np.max(np.abs(pr.P[:, 0] - Pc)) / np.max(np.abs(Pc)))
+    assert errs[-1] < 1e-4
+    for a, b in zip(errs, errs[1:]):
+        assert abs(math.log(a / b, 2) - 2.0) < 0.1, errs
