@@ -211,9 +211,10 @@ typedef struct {
  * the two-point face average of the adjacent cells (Eq 3.20, n = 1), i.e.
  * the variable-coefficient form div(grad P / rho) = b; zero flux through
  * non-periodic sides either way; LM_EINVAL if rho is not positive and
- * finite everywhere. b is a cell field (mem says where); P is written to
- * `P` and also becomes the context's pressure (warm start of the next
- * solve). rho is copied; no pointer is kept.                              */
+ * finite everywhere. b is a cell field (mem says where); the solve starts
+ * from zero in solver scratch and P (NULL: not returned) receives the
+ * zero-mean solution; the context's state, its pressure included, is left
+ * as it was. rho is copied; no pointer is kept.                           */
 typedef struct {
   const double *b;
   const double *rho;
@@ -235,13 +236,22 @@ lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t
 lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *dev_workspace,
                        size_t bytes, void *hip_stream, lm_ctx **out);
 
-/* Set the state at level 0 (time n) from T (or H) and v, optionally Z, P
+/* level 0: set the state at time n from T (or H) and v, optionally Z, P
  * and F (section 3.1 start-up). H is obtained by inverting Eq 3.42 when T is
  * given; T is re-evaluated from (Z, H) and rho = p0/T (Eq 2.49). Unless F is
  * given, F_d is the face average of rho v (Eq 3.20, n = 1). Setting level 0
  * clears the level n-1 history, so the next step is a Heun start (Euler
- * predictor, BDF1 density derivative). `ib` may be NULL. LM_EINVAL if T <= 0
- * anywhere. level must be 0.                                              */
+ * predictor, BDF1 density derivative). `ib` may be NULL.
+ * level 1 (after level 0): the fields at time n-1 (T or H, v, optionally Z
+ * and F as for level 0; P is not used; `ib` must be NULL, the body is that
+ * of level 0). The library forms from them the history the next step reads:
+ * rho^{n-1} = p0/T^{n-1} and the residuals R_Z, R_H, R_v at level n-1
+ * (Eq 3.2, 3.4, 3.8), so the next step takes the AB2 predictor (Eq 3.1, 3.3,
+ * 3.10) and the BDF2 density derivative (Eq 3.11, 3.19) instead of the Heun
+ * start; the step from n-1 to n is taken to have the current step size.
+ * Needs a constant p0 (p0_closed = 0, else LM_EUNSUPPORTED); LM_ESTATE
+ * before level 0. LM_EINVAL if T <= 0 anywhere; other levels
+ * LM_EUNSUPPORTED.                                                        */
 lm_status lm_set_fields(lm_ctx *ctx, int level, const lm_fields *f, const lm_ib *ib, int mem);
 
 /* Boundary data of side (d, side), side 0 = low, 1 = high: an inflow side,
@@ -251,8 +261,11 @@ lm_status lm_set_fields(lm_ctx *ctx, int level, const lm_fields *f, const lm_ib 
 lm_status lm_set_side(lm_ctx *ctx, int d, int side, const lm_side_data *data, int mem);
 
 /* Advance nsteps predictor-corrector steps (section 3.1, Eq 3.1-3.19).
- * On LM_ENOCONV / LM_ENONFINITE the state stays at the last completed step.
- * stats may be NULL.                                                        */
+ * On LM_ENOCONV / LM_ENONFINITE from a stage the state stays at the last
+ * completed step. With an adaptive step (dt_tol > 0), a non-finite error
+ * estimate or CFL step after a step returns LM_ENONFINITE with that step
+ * committed. Either way stats (if not NULL) gives the steps completed,
+ * the step size and the time reached.                                     */
 lm_status lm_step(lm_ctx *ctx, int nsteps, lm_step_stats *stats);
 
 /* Poisson solve in RHS mode (see lm_project_args). */
@@ -288,6 +301,10 @@ lm_status lm_load_state(lm_ctx *ctx, const void *dev_buf);
  * with_adjoint = 1; otherwise LM_EUNSUPPORTED).                              */
 typedef struct {
   double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
+  double *T;   /* lm_adjoint_set only: a cotangent of the temperature,
+                  folded into that of H by the transpose of the equation of
+                  state T = qs (H - 1) (H_bar += qs T_bar, on the device);
+                  ignored by lm_adjoint_get                               */
 } lm_adjoint;
 
 /* Kinetic energy sum_cells 1/2 rho |v|^2 dV of the current state. */

@@ -112,7 +112,10 @@ class Solver:
         self.stats = None
 
     # ------------------------------------------------------------------
-    def set(self, T=None, v=None, Z=None, H=None, P=None, F=None, ib: Optional[dict] = None):
+    def set(self, T=None, v=None, Z=None, H=None, P=None, F=None, ib: Optional[dict] = None, level: int = 0):
+        """Set the state (level 0, time n), or after it the fields of time
+        n - 1 (level 1: T or H, v, optionally Z and F), from which the
+        library forms the history of the next AB2 / BDF2 step."""
         m = _Marshal(self.torch, self.device)
         f = _L.lm_fields()
         f.T = m.ptr(T)
@@ -134,7 +137,7 @@ class Solver:
             ibs.H_ib = m.ptr(ib.get("H_ib"))
             ibs.S_m = m.ptr(ib.get("Sm"))
         mem = m.mem if m.mem is not None else _L.LM_HOST
-        _check(self.lib, self.ctx, self.lib.lm_set_fields(self.ctx, 0, C.byref(f),
+        _check(self.lib, self.ctx, self.lib.lm_set_fields(self.ctx, int(level), C.byref(f),
                                                           C.byref(ibs) if ibs is not None else None, mem))
 
     def set_side(self, d: int, side: int, v=None, Z=None, H=None, F=None, wall=None):
@@ -257,10 +260,12 @@ class Solver:
     def adjoint_seed_ke(self):
         _check(self.lib, self.ctx, self.lib.lm_adjoint_seed_ke(self.ctx))
 
-    def adjoint_set(self, H=None, v=None, F=None, rho_prev=None, R_H=None, R_v=None):
+    def adjoint_set(self, H=None, v=None, F=None, rho_prev=None, R_H=None, R_v=None, T=None):
+        """Set the adjoint state; ``T``, a cotangent of the temperature, is
+        folded into that of H by the library."""
         m = _Marshal(self.torch, self.device)
         a = _L.lm_adjoint()
-        a.H, a.rho_prev, a.R_H = m.ptr(H), m.ptr(rho_prev), m.ptr(R_H)
+        a.H, a.rho_prev, a.R_H, a.T = m.ptr(H), m.ptr(rho_prev), m.ptr(R_H), m.ptr(T)
         for d in range(self.ndim):
             a.v[d] = m.ptr(v[d]) if v is not None else None
             a.F[d] = m.ptr(F[d]) if F is not None else None

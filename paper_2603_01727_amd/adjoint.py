@@ -108,8 +108,8 @@ def final_kinetic_energy(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_e
 class StepFn(torch.autograd.Function):
     """(T_n, v_n) after ``nsteps`` steps from (T0, v0), differentiable in
     T0 and v0: the backward pass seeds the adjoint state with the
-    cotangents of T_n (as H_bar = qs T_bar, the non-reacting map
-    T = qs (H - 1)) and of v_n, and walks the checkpointed trajectory back
+    cotangents of T_n (which the library folds into that of H) and of v_n,
+    and walks the checkpointed trajectory back
     (``Trajectory``). Outputs are float64 tensors on the solver's device."""
 
     @staticmethod
@@ -127,7 +127,7 @@ class StepFn(torch.autograd.Function):
         s = ctx.traj.solver
         zero = lambda g: torch.zeros(s.shape, dtype=torch.float64, device=s.device) if g is None else \
             g.to(torch.float64).contiguous()
-        seed = {"H": zero(gT) * s.params.qs, "v": [zero(g) for g in gv]}
+        seed = {"T": zero(gT), "v": [zero(g) for g in gv]}
         Tb, vb = ctx.traj.backward(seed)
         return (Tb,) + tuple(vb) + (None, None, None)
 

@@ -434,6 +434,19 @@ hipError_t launch_adj_eos(hipStream_t st, const Lay &L, const AdjPhys &P, const 
   return hipGetLastError();
 }
 
+// A cotangent of the temperature folded into that of H: T = qs (H - 1) in
+// non-reacting flow, so H_bar += qs T_bar.
+__global__ void __launch_bounds__(kBlock) k_adj_add_T(Lay L, AdjPhys P, const double *Tb, double *Hb) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  Hb[p.c] += P.qs * Tb[p.c];
+}
+
+hipError_t launch_adj_add_T(hipStream_t st, const Lay &L, const AdjPhys &P, const double *Tb, double *Hb) {
+  hipLaunchKernelGGL(k_adj_add_T, grid_for(L), dim3(kBX, kBY), 0, st, L, P, Tb, Hb);
+  return hipGetLastError();
+}
+
 // Cotangent of J = sum 1/2 rho |v|^2 dV at the current level: vb = rho v dV,
 // Hb = (d rho/d H) |v|^2/2 dV, all other cotangents zero.
 __global__ void __launch_bounds__(kBlock) k_adj_seed_ke(Lay L, AdjPhys P, double dV, const double *H,

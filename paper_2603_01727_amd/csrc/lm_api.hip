@@ -59,13 +59,15 @@ struct lm_ctx {
 
 namespace {
 
-// Text of the last failed lm_workspace_size / lm_init_grid of this thread.
-thread_local std::string g_init_err;
+// Text of the last failed call of this thread made without a context
+// (lm_workspace_size, lm_init_grid).
+thread_local char g_init_err[512];
 
-lm_status init_fail(lm_status s, const std::string &msg) {
-  g_init_err = msg;
+lm_status init_fail(lm_status s, const char *msg) {
+  snprintf(g_init_err, sizeof(g_init_err), "%s", msg);
   return s;
 }
+lm_status init_fail(lm_status s, const std::string &msg) { return init_fail(s, msg.c_str()); }
 
 lm_status fail(lm_ctx *c, lm_status s, const std::string &msg) {
   if (c) c->err = msg;
@@ -79,7 +81,8 @@ lm_status fail(lm_ctx *c, lm_status s, const std::string &msg) {
       return fail(ctx, LM_EHIP, std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-bool valid_grid(const lm_grid *g, std::string *err) {
+// Argument checks; *err receives a static message on failure.
+bool valid_grid(const lm_grid *g, const char **err) {
   if (!g || (g->ndim != 2 && g->ndim != 3)) {
     *err = "ndim must be 2 or 3";
     return false;
@@ -110,7 +113,7 @@ bool valid_grid(const lm_grid *g, std::string *err) {
   return true;
 }
 
-bool valid_params(const lm_params *p, std::string *err) {
+bool valid_params(const lm_params *p, const char **err) {
   if (!p) {
     *err = "params is NULL";
     return false;
@@ -366,8 +369,9 @@ lm_status copy_side(lm_ctx *c, const double *src, double *dst, size_t n, int mem
 extern "C" {
 
 lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t *bytes) {
-  std::string err = "bytes is NULL";
-  if (!bytes || !valid_grid(grid, &err) || !valid_params(params, &err)) return init_fail(LM_EINVAL, err);
+  const char *bad = "bytes is NULL";
+  if (!bytes || !valid_grid(grid, &bad) || !valid_params(params, &bad)) return init_fail(LM_EINVAL, bad);
+  std::string err;
   lm_ctx *c = new (std::nothrow) lm_ctx();
   if (!c) return init_fail(LM_ENOMEM, "out of host memory");
   c->grid = *grid;
@@ -386,9 +390,10 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
                        lm_ctx **out) {
   if (!out) return init_fail(LM_EINVAL, "out is NULL");
   *out = nullptr;
-  std::string err;
-  if (!valid_grid(grid, &err) || !valid_params(params, &err)) return init_fail(LM_EINVAL, err);
+  const char *bad = nullptr;
+  if (!valid_grid(grid, &bad) || !valid_params(params, &bad)) return init_fail(LM_EINVAL, bad);
   if (!ws) return init_fail(LM_EINVAL, "workspace is NULL");
+  std::string err;
   size_t need = 0;
   lm_status s = lm_workspace_size(grid, params, &need);
   if (s != LM_OK) return s;
@@ -506,14 +511,13 @@ lm_status lm_set_side(lm_ctx *c, int d, int side, const lm_side_data *data, int 
   return update_vol_out(c);
 }
 
-lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *ib, int mem) {
-  if (!c || !f) return fail(c, LM_EINVAL, "NULL argument");
-  if (level != 0) return fail(c, LM_EUNSUPPORTED, "only level 0 can be set");
+// Velocity, Z and T (or H) of a level from caller arrays; the EOS, rho and
+// the face fluxes follow in finish_level.
+static lm_status load_level(lm_ctx *c, Level &lv, const lm_fields *f, int mem) {
   if (!f->T && !f->H) return fail(c, LM_EINVAL, "need T or H");
   const int nd = c->grid.ndim;
   for (int d = 0; d < nd; ++d)
     if (!f->v[d]) return fail(c, LM_EINVAL, "need every velocity component");
-  Level &lv = cur(c);
   lm_status s;
   for (int d = 0; d < nd; ++d)
     if ((s = copy_in(c, f->v[d], lv.v[d], -1, mem)) != LM_OK) return s;
@@ -524,12 +528,70 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
       HIPCHK(c, hipMemsetAsync(lv.Z, 0, (size_t)c->lay.total * 8, c->st));
     }
   }
-  const int from_T = f->T != nullptr;
-  if (from_T) {
+  if (f->T) {
     if ((s = copy_in(c, f->T, lv.T, -1, mem)) != LM_OK) return s;
   } else {
     if ((s = copy_in(c, f->H, lv.H, -1, mem)) != LM_OK) return s;
   }
+  return LM_OK;
+}
+
+// T, H, rho = p0/T and kappa of a loaded level (flags a non-positive T in
+// dflags[0]), then its face fluxes: the given ones, or the face average of
+// rho v.
+static lm_status finish_level(lm_ctx *c, Level &lv, const lm_fields *f, int mem) {
+  const int nd = c->grid.ndim;
+  lm_status s;
+  HIPCHK(c, launch_init_state(c->st, c->lay, c->phys, c->bnd, c->sides, f->T != nullptr, lv, c->dflags));
+  if (f->F[0]) {
+    for (int d = 0; d < nd; ++d) {
+      if (!f->F[d]) return fail(c, LM_EINVAL, "give every face-flux component or none");
+      if ((s = copy_in(c, f->F[d], lv.F[d], d, mem)) != LM_OK) return s;
+    }
+  } else {
+    HIPCHK(c, launch_face_flux(c->st, c->lay, c->bnd, c->sides, lv, c->M));
+  }
+  return LM_OK;
+}
+
+// Level n-1: the fields of the previous time level, from which the level
+// n-1 density and residuals of the next step's AB2 predictor and BDF2
+// density derivative are formed (section 3.1, Eq 3.1, 3.3, 3.10, 3.11).
+static lm_status set_previous_level(lm_ctx *c, const lm_fields *f, const lm_ib *ib, int mem) {
+  if (!c->have_state) return fail(c, LM_ESTATE, "set level 0 before level 1");
+  if (ib) return fail(c, LM_EINVAL, "the immersed body is set with level 0");
+  if (c->prm.p0_closed) return fail(c, LM_EUNSUPPORTED, "level 1 needs a constant thermodynamic pressure");
+  // the level's fields go to the predicted slot; the stage kernel writes
+  // the (discarded) Euler update into the next-level slot
+  Level &pv = c->lev[c->istar];
+  lm_status s = load_level(c, pv, f, mem);
+  if (s != LM_OK) return s;
+  HIPCHK(c, hipMemsetAsync(c->dflags, 0, 64, c->st));
+  if ((s = finish_level(c, pv, f, mem)) != LM_OK) return s;
+  HIPCHK(c, hipMemcpyAsync(c->hflags, c->dflags, 16, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (c->hflags[0]) return fail(c, LM_EINVAL, "temperature must be positive everywhere");
+  HIPCHK(c, launch_ghosts(c->st, c->lay, c->bnd, c->phys, c->sides, pv.v, pv.Z, pv.H, pv.T, pv.kap));
+  // residuals of level n-1 into the history slot R^{n-1}
+  HIPCHK(c, launch_stage(c->st, 0, 1, c->lay, c->phys, pv, pv, c->R[c->rprev ^ 1], c->R[c->rprev], c->ib,
+                         c->lev[c->inxt], c->M, &c->p0d->dtp0_n));
+  std::swap(c->rho_prev, pv.rho);
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->have_prev = 1;
+  c->have_star = 0;
+  c->dt_prev = c->phys.dt;  // the step from n-1 to n: the current step
+  c->nsame = 1;
+  return LM_OK;
+}
+
+lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *ib, int mem) {
+  if (!c || !f) return fail(c, LM_EINVAL, "NULL argument");
+  if (level == 1) return set_previous_level(c, f, ib, mem);
+  if (level != 0) return fail(c, LM_EUNSUPPORTED, "level must be 0 or 1");
+  const int nd = c->grid.ndim;
+  Level &lv = cur(c);
+  lm_status s = load_level(c, lv, f, mem);
+  if (s != LM_OK) return s;
   if (f->P) {
     if ((s = copy_in(c, f->P, c->P[c->icur], -1, mem)) != LM_OK) return s;
   } else {
@@ -566,18 +628,10 @@ lm_status lm_set_fields(lm_ctx *c, int level, const lm_fields *f, const lm_ib *i
   }
   if (c->prm.p0_closed && c->ib.S_m) return fail(c, LM_EINVAL, "an enclosed system takes no mass source S_m");
   HIPCHK(c, hipMemsetAsync(c->dflags, 0, 64, c->st));
-  HIPCHK(c, launch_init_state(c->st, c->lay, c->phys, c->bnd, c->sides, from_T, lv, c->dflags));
+  if ((s = finish_level(c, lv, f, mem)) != LM_OK) return s;
   if (c->prm.p0_closed) {  // conserved mass of this state, p0 history cleared
     HIPCHK(c, launch_p0(c->st, 0, c->lay, c->phys, c->p0d, &lv, nullptr, nullptr, c->pws.partials));
     if ((s = update_vol_out(c)) != LM_OK) return s;
-  }
-  if (f->F[0]) {
-    for (int d = 0; d < nd; ++d) {
-      if (!f->F[d]) return fail(c, LM_EINVAL, "give every face-flux component or none");
-      if ((s = copy_in(c, f->F[d], lv.F[d], d, mem)) != LM_OK) return s;
-    }
-  } else {
-    HIPCHK(c, launch_face_flux(c->st, c->lay, c->bnd, c->sides, lv, c->M));
   }
   if (!(c->prm.dt > 0)) {
     HIPCHK(c, launch_cfl(c->st, c->lay, c->phys, lv, c->ib.chi, c->pws.partials, c->dscalar));
@@ -748,7 +802,15 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
     c->time += c->phys.dt;
     ++done;
     if (c->prm.dt_tol > 0.0) {
-      if ((s = adapt_dt(c, first)) != LM_OK) return s;
+      if ((s = adapt_dt(c, first)) != LM_OK) {
+        // the step that produced the estimate is committed
+        if (stats) {
+          stats->steps = done;
+          stats->dt = c->phys.dt;
+          stats->time = c->time;
+        }
+        return s;
+      }
     } else {
       c->dt_last = c->phys.dt;
     }
@@ -791,7 +853,8 @@ lm_status lm_project(lm_ctx *c, lm_project_args *a) {
   double relres = 0;
   const double rtol = a->rtol > 0 ? a->rtol : c->prm.poisson_rtol;
   c->pws.vc = a->rho != nullptr;
-  const hipError_t e = poisson_solve(c->st, c->pws, c->b, c->P[c->icur], rtol, c->prm.poisson_maxit, 0, &iters,
+  // a standalone solve: zero start in solver scratch, the state untouched
+  const hipError_t e = poisson_solve(c->st, c->pws, c->b, nullptr, rtol, c->prm.poisson_maxit, 0, &iters,
                                      &relres, &conv);
   c->pws.vc = 0;
   HIPCHK(c, e);
@@ -800,8 +863,8 @@ lm_status lm_project(lm_ctx *c, lm_project_args *a) {
   a->relres = relres;
   a->mean_b = c->pws.host_sc->mean_b;
   if (!conv) return fail(c, LM_ENOCONV, "Poisson solver did not reach rtol");
-  HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, c->P[c->icur]));
-  if (a->P) return copy_out(c, c->P[c->icur], a->P, -1, a->mem);
+  HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, c->pws.x));  // zero mean, in place
+  if (a->P) return copy_out(c, c->pws.x, a->P, -1, a->mem);
   return LM_OK;
 }
 
@@ -839,7 +902,7 @@ lm_status lm_get_dt(const lm_ctx *c, double *dt) {
   return LM_OK;
 }
 
-const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }
+const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : g_init_err; }
 
 void lm_destroy(lm_ctx *c) {
   if (!c) return;
@@ -1054,6 +1117,13 @@ extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
       lm_status s = copy_in(c, src[q], a[q], fd[q], mem);
       if (s != LM_OK) return s;
     }
+  }
+  if (in->T) {
+    // T = qs (H - 1): the cotangent of T adds qs T_bar to H_bar
+    double *Tb = c->aw[18];
+    lm_status s = copy_in(c, in->T, Tb, -1, mem);
+    if (s != LM_OK) return s;
+    HIPCHK(c, launch_adj_add_T(c->st, c->lay, adj_phys(c), Tb, a[0]));
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;

@@ -212,6 +212,8 @@ hipError_t launch_adj_seed_ke(hipStream_t st, const Lay &L, const AdjPhys &P, do
                               const double *rho, double *const v[2], double *Hb, double *vb[2]);
 hipError_t launch_adj_init(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
                            double *const v[2], double *const Fb[2], const double *Hb, double *vb[2], double *Tb);
+// H_bar += qs T_bar (transpose of the non-reacting map T = qs (H - 1)).
+hipError_t launch_adj_add_T(hipStream_t st, const Lay &L, const AdjPhys &P, const double *Tb, double *Hb);
 hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[2], double dV, double *part,
                      double *out);
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);

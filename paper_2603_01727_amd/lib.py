@@ -63,7 +63,7 @@ class lm_step_stats(C.Structure):
 
 class lm_adjoint(C.Structure):
     _fields_ = [("H", C.c_void_p), ("v", C.c_void_p * 3), ("F", C.c_void_p * 3), ("rho_prev", C.c_void_p),
-                ("R_H", C.c_void_p), ("R_v", C.c_void_p * 3)]
+                ("R_H", C.c_void_p), ("R_v", C.c_void_p * 3), ("T", C.c_void_p)]
 
 
 class lm_project_args(C.Structure):
