@@ -351,8 +351,31 @@ lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
 lm_status lm_kernel_timing(lm_ctx *ctx, int capacity);
 lm_status lm_kernel_timing_read(lm_ctx *ctx, double *avg_ms, int *count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * RHS-mode solve of lm_project (beta = 1, zero-mean P with A P = b, the
+ * same multigrid-preconditioned CG and stopping rule) in one call, with no
+ * context, no workspace and no allocation. Every solver array lives in a
+ * static device buffer of 64 MiB that the library holds on each GPU it runs
+ * on until the process ends (enough for about 512^2 or 64^3 cells in FP64).
+ * grid, params: as for lm_init_grid (params gives precision, mg_nu,
+ * poisson_rtol and poisson_maxit); stream: a hipStream_t (NULL = default
+ * stream), the call returns after it has drained. args: b (required) and P
+ * (NULL: not returned) are cell fields in C order, host or device as
+ * args->mem says; rho must be NULL; rtol 0 = params->poisson_rtol; iters,
+ * relres and mean_b are written as for lm_project. The solve starts from
+ * zero. Errors (text by lm_last_error(NULL)): LM_EINVAL for bad arguments,
+ * LM_EUNSUPPORTED for a density or a grid whose coarsest multigrid level
+ * has more than 128 cells, LM_ENOMEM when the grid needs more than the
+ * 64 MiB (checked before any device work), LM_ENOCONV, LM_EHIP. All calls on
+ * one GPU share its buffer: calls that overlap on one GPU (from several
+ * threads or streams) race and must be serialised by the caller.          */
+lm_status lm_project_static(const lm_grid *grid, const lm_params *params, void *hip_stream,
+                            lm_project_args *args);
+
 /* Text of the last error of ctx; with ctx == NULL, of the last failed
- * lm_workspace_size or lm_init_grid of the calling thread. */
+ * lm_workspace_size, lm_init_grid or lm_project_static of the calling
+ * thread. */
 const char *lm_last_error(const lm_ctx *ctx);
 
 /* Release the context (the caller still owns workspace and stream). */

@@ -14,7 +14,7 @@ import numpy as np
 
 from . import lib as _L
 
-__all__ = ["Solver", "LowMachError", "project"]
+__all__ = ["Solver", "LowMachError", "project", "project_static"]
 LowMachError = _L.LowMachError
 
 
@@ -349,3 +349,50 @@ def project(b, L, bc=None, rho=None, rtol: float = 1e-12, precision: str = "fp64
         return s.project(b, rho=rho)
     finally:
         s.close()
+
+
+def project_static(b, L, P=None, bc=None, rtol: float = 1e-12, precision: str = "fp64", maxit: int = 400,
+                   mg_nu: int = 2, stream=None):
+    """The pressure solve of ``project`` through ``lm_project_static``: no
+    context and no device allocation by the library (its arrays live in a
+    static 64 MiB device buffer per GPU; calls on one GPU must not overlap).
+    ``b`` and ``P`` (the caller's output, same shape; None: only the info)
+    are both device tensors or both host arrays. Returns the info dict."""
+    lib = _L.load()
+    shape = tuple(np.shape(b))
+    ndim = len(shape)
+    n = tuple(reversed(shape))
+    if bc is None:
+        bc = [("periodic", "periodic")] * ndim
+    g = _L.lm_grid()
+    g.ndim = ndim
+    for d in range(3):
+        g.n[d] = n[d] if d < ndim else 1
+        g.L[d] = float(L[d]) if d < ndim else 1.0
+        for q in range(2):
+            g.bc[d][q] = _L.SIDE[bc[d][q]] if d < ndim else 0
+    p = _L.lm_params(Re=1.0, Pr=0.7, sigma=0.7, qs=1.0, S=1.0, eps=0.5, tol=1e-3, Le_F=1.0, Le_O=1.0, Da_ib=1.0,
+                     p0=1.0, dt=1.0, cfl=0.2, precision=_L.PRECISION[precision], poisson_rtol=rtol,
+                     poisson_maxit=maxit, mg_nu=mg_nu)
+    a = _L.lm_project_args()
+    import torch
+    if isinstance(b, torch.Tensor) and b.device.type == "cuda":
+        if not (b.dtype == torch.float64 and b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 tensor")
+        if P is not None and not (P.device == b.device and P.dtype == torch.float64 and P.is_contiguous()
+                                  and tuple(P.shape) == shape):
+            raise ValueError("P must be a contiguous float64 tensor of b's shape on b's device")
+        a.b, a.P, a.mem = b.data_ptr(), (P.data_ptr() if P is not None else None), _L.LM_DEVICE
+        st = stream if stream is not None else torch.cuda.current_stream(b.device)
+        sp = st.cuda_stream
+    else:
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        if P is not None and not (isinstance(P, np.ndarray) and P.dtype == np.float64 and P.flags.c_contiguous
+                                  and P.shape == shape):
+            raise ValueError("P must be a C-contiguous float64 array of b's shape")
+        a.b, a.P, a.mem = b.ctypes.data, (P.ctypes.data if P is not None else None), _L.LM_HOST
+        sp = stream.cuda_stream if stream is not None else None
+    a.rtol = rtol
+    status = lib.lm_project_static(C.byref(g), C.byref(p), C.c_void_p(sp), C.byref(a))
+    _check(lib, None, status)
+    return dict(iters=a.iters, relres=a.relres, mean_b=a.mean_b)

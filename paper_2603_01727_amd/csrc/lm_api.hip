@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -60,7 +61,7 @@ struct lm_ctx {
 namespace {
 
 // Text of the last failed call of this thread made without a context
-// (lm_workspace_size, lm_init_grid).
+// (lm_workspace_size, lm_init_grid, lm_project_static).
 thread_local char g_init_err[512];
 
 lm_status init_fail(lm_status s, const char *msg) {
@@ -1316,5 +1317,130 @@ extern "C" lm_status lm_kernel_timing_read(lm_ctx *c, double *avg_ms, int *count
   }
   *count = n;
   *avg_ms = n ? tot / n : 0.0;
+  return LM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pressure solve without allocation (lm_project_static)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Every device array of the solve lives here: 64 MiB per GPU, held from the
+// first call on that GPU until the process ends. Calls on one GPU share it.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kScratchDevices];     // device address of `scratch`, per device
+SolverScalars g_scratch_sc[kScratchDevices];       // host copy of the solver scalars, per device
+
+__global__ void __launch_bounds__(kBlock) k_zero_bytes(ulonglong2 *p, size_t n16) {
+  const ulonglong2 z = make_ulonglong2(0ull, 0ull);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = z;
+}
+
+// Carves the arrays of a pressure solve (right-hand side, host staging and
+// the solver) from cv; cv.base == nullptr only sizes them.
+bool carve_solve(PoissonWS &ws, Carver &cv, const Lay &L, const Bnd &B, const double h[3], const lm_params &p,
+                 double **b, double **staging) {
+  *b = (double *)cv.take((size_t)L.total * 8);
+  *staging = (double *)cv.take((size_t)L.ncells() * 8);
+  return poisson_plan(ws, cv, L, B, h, p.precision != LM_FP64, p.precision == LM_MIXED_FLEXIBLE,
+                      p.mg_nu > 0 ? p.mg_nu : 2, 0, nullptr);
+}
+
+#define STATIC_HIPCHK(expr)                                                                        \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      snprintf(g_init_err, sizeof(g_init_err), "HIP error in %s: %s", #expr, hipGetErrorString(e_)); \
+      return LM_EHIP;                                                                              \
+    }                                                                                              \
+  } while (0)
+
+}  // namespace
+
+extern "C" lm_status lm_project_static(const lm_grid *grid, const lm_params *params, void *stream,
+                                       lm_project_args *a) {
+  if (!grid || !params || !a || !a->b) return init_fail(LM_EINVAL, "NULL argument");
+  if (a->rho) return init_fail(LM_EUNSUPPORTED, "lm_project_static solves the beta = 1 form only");
+  if (a->mem != LM_HOST && a->mem != LM_DEVICE) return init_fail(LM_EINVAL, "mem must be LM_HOST or LM_DEVICE");
+  const char *bad = nullptr;
+  if (!valid_grid(grid, &bad) || !valid_params(params, &bad)) return init_fail(LM_EINVAL, bad);
+  // layout, sides and spacings as lm_init_grid sets them up
+  Lay L = make_layout(grid->ndim, grid->n, 8);
+  Bnd B;
+  B.all_periodic = 1;
+  for (int d = 0; d < 3; ++d) {
+    for (int q = 0; q < 2; ++q) B.kind[d][q] = d < grid->ndim ? grid->bc[d][q] : LM_SIDE_PERIODIC;
+    B.periodic[d] = B.kind[d][0] == LM_SIDE_PERIODIC;
+    if (d < grid->ndim && !B.periodic[d]) B.all_periodic = 0;
+  }
+  double h[3];
+  for (int d = 0; d < 3; ++d) h[d] = d < grid->ndim ? grid->L[d] / grid->n[d] : 1.0;
+  // sizing pass: rejected before any device work when it does not fit
+  PoissonWS ws{};
+  double *b = nullptr, *staging = nullptr;
+  Carver sz{nullptr, 0};
+  if (!carve_solve(ws, sz, L, B, h, *params, &b, &staging))
+    return init_fail(LM_EUNSUPPORTED, "grid does not coarsen far enough for the multigrid solver");
+  if (ws.lev[ws.nlev - 1].lay.ncells() > kVcCoarsest)
+    return init_fail(LM_EUNSUPPORTED, "lm_project_static needs a grid that coarsens to <= 128 cells");
+  const size_t need = (sz.off + 255) & ~(size_t)255;
+  if (need > kScratchBytes) {
+    snprintf(g_init_err, sizeof(g_init_err),
+             "grid needs %zu bytes of solver scratch; lm_project_static holds %zu (64 MiB)", need, kScratchBytes);
+    return LM_ENOMEM;
+  }
+  // the device address of this GPU's copy of `scratch`, taken once per device
+  int dev = 0;
+  STATIC_HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return init_fail(LM_EUNSUPPORTED, "device index beyond 64");
+  unsigned char *base;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *ptr = nullptr;
+      STATIC_HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[dev] = (unsigned char *)ptr;
+    }
+    base = g_scratch_ptr[dev];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  ws = PoissonWS{};
+  Carver cv{(char *)base, 0};
+  carve_solve(ws, cv, L, B, h, *params, &b, &staging);
+  ws.host_sc = &g_scratch_sc[dev];
+  // the previous call's contents: ghost layers and padding start at zero
+  hipLaunchKernelGGL(k_zero_bytes, dim3(1024), dim3(kBlock), 0, st, (ulonglong2 *)base, need / 16);
+  STATIC_HIPCHK(hipGetLastError());
+  STATIC_HIPCHK(poisson_setup_device(st, ws));
+  const double *src = a->b;
+  if (a->mem == LM_HOST) {
+    STATIC_HIPCHK(hipMemcpyAsync(staging, a->b, (size_t)L.ncells() * 8, hipMemcpyHostToDevice, st));
+    src = staging;
+  }
+  STATIC_HIPCHK(launch_pack(st, L, src, b, -1));
+  STATIC_HIPCHK(launch_mean(st, L, b, ws.partials, ws.sc));
+  int iters = 0, conv = 0;
+  double relres = 0.0;
+  const double rtol = a->rtol > 0 ? a->rtol : params->poisson_rtol;
+  STATIC_HIPCHK(poisson_solve(st, ws, b, nullptr, rtol, params->poisson_maxit, 0, &iters, &relres, &conv));
+  a->iters = iters;
+  a->relres = relres;
+  a->mean_b = ws.host_sc->mean_b;
+  if (!conv) return init_fail(LM_ENOCONV, "Poisson solver did not reach rtol");
+  STATIC_HIPCHK(launch_shift(st, L, ws.x, ws.sc, ws.x));  // zero mean, in place
+  if (a->P) {
+    if (a->mem == LM_HOST) {
+      STATIC_HIPCHK(launch_unpack(st, L, ws.x, staging, -1));
+      STATIC_HIPCHK(hipMemcpyAsync(a->P, staging, (size_t)L.ncells() * 8, hipMemcpyDeviceToHost, st));
+    } else {
+      STATIC_HIPCHK(launch_unpack(st, L, ws.x, a->P, -1));
+    }
+  }
+  STATIC_HIPCHK(hipStreamSynchronize(st));
   return LM_OK;
 }

@@ -276,6 +276,10 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
                   int nu, int vc_cap, std::string *err);
 // Host-side set-up of the coarsest-level pseudo-inverse (after carving).
 hipError_t poisson_setup(hipStream_t st, PoissonWS &ws, const double h[3]);
+// The same pseudo-inverse built on the device (one block, Gauss-Jordan in
+// LDS); needs a coarsest level of <= kVcCoarsest cells
+// (hipErrorInvalidValue otherwise).
+hipError_t poisson_setup_device(hipStream_t st, PoissonWS &ws);
 // Solve A x = b for the zero-mean x (A P = sum_d delta_1 delta_1 P with
 // zero-flux non-periodic sides), warm-started from x0 (NULL = 0). b is read
 // with sc->mean_b and the outflow shift sc->outflow_c removed on the fly.

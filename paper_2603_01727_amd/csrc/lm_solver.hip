@@ -661,15 +661,16 @@ namespace lm {
 // (L + J/N)^{-1} - J/N with J the all-ones matrix: L + J/N is symmetric
 // positive definite (L is singular with the constants as null space), so
 // Gauss-Jordan elimination without pivoting inverts it in place in LDS.
+// UNIT: beta = 1 on every face (no densities read).
 constexpr int kPinvThreads = 256;
-template <int DIM, typename T>
+template <int DIM, typename T, bool UNIT = false>
 __global__ void __launch_bounds__(kPinvThreads) k_vc_pinv(CoarseArgs<T> a, T *pinv) {
   __shared__ double M[kVcCoarsest * kVcCoarsest];
   __shared__ double rk[kVcCoarsest], ck[kVcCoarsest];
   const int last = a.nlev - 1;
   const int *n = a.n[last];
   const int N = n[0] * n[1] * n[2];
-  const T *rho = a.rho_c + a.off[last];
+  const T *rho = UNIT ? nullptr : a.rho_c + a.off[last];
   const int t = threadIdx.x;
   const double jn = 1.0 / (double)N;
   for (int e = t; e < N * N; e += blockDim.x) M[e] = jn;
@@ -679,7 +680,7 @@ __global__ void __launch_bounds__(kPinvThreads) k_vc_pinv(CoarseArgs<T> a, T *pi
     c_decode<DIM, T>(n, t, i, j, k);
     const int q[3] = {i, j, k};
     const int st[3] = {1, n[0], n[0] * n[1]};
-    const double rc = (double)rho[t];
+    const double rc = UNIT ? 1.0 : (double)rho[t];
     for (int d = 0; d < DIM; ++d) {
       const bool per = a.B.periodic[d] != 0;
       const double ih2 = (double)a.ih2[last].v[d];
@@ -687,7 +688,7 @@ __global__ void __launch_bounds__(kPinvThreads) k_vc_pinv(CoarseArgs<T> a, T *pi
         const bool in = side == 0 ? q[d] > 0 : q[d] + 1 < n[d];
         if (!in && !per) continue;
         const int m = side == 0 ? (in ? t - st[d] : t + (n[d] - 1) * st[d]) : (in ? t + st[d] : t - (n[d] - 1) * st[d]);
-        const double w = ih2 * face_beta<double>(rc, (double)rho[m]);
+        const double w = UNIT ? ih2 : ih2 * face_beta<double>(rc, (double)rho[m]);
         M[t * N + t] += w;
         M[t * N + m] -= w;
       }
@@ -1492,6 +1493,25 @@ static hipError_t set_beta_dim(hipStream_t st, PoissonWS &ws) {
     hipLaunchKernelGGL((k_vc_pack<DIM, T>), grid_for(ws.lev[l].lay), bb, 0, st, ws.lev[l].lay,
                        (const T *)ws.rho[l], (T *)ws.rho_c + ca.off[l]);
   hipLaunchKernelGGL((k_vc_pinv<DIM, T>), dim3(1), dim3(kPinvThreads), 0, st, ca, (T *)ws.pinv_vc);
+  return hipGetLastError();
+}
+
+hipError_t poisson_setup_device(hipStream_t st, PoissonWS &ws) {
+  if (ws.lev[ws.nlev - 1].lay.ncells() > kVcCoarsest) return hipErrorInvalidValue;
+  const bool three = ws.lay.ndim == 3;
+  if (ws.mixed) {
+    CoarseArgs<float> ca = coarse_args<float>(ws, ws.z[0], ws.r[0]);
+    if (three)
+      hipLaunchKernelGGL((k_vc_pinv<3, float, true>), dim3(1), dim3(kPinvThreads), 0, st, ca, (float *)ws.pinv);
+    else
+      hipLaunchKernelGGL((k_vc_pinv<2, float, true>), dim3(1), dim3(kPinvThreads), 0, st, ca, (float *)ws.pinv);
+  } else {
+    CoarseArgs<double> ca = coarse_args<double>(ws, ws.z[0], ws.r[0]);
+    if (three)
+      hipLaunchKernelGGL((k_vc_pinv<3, double, true>), dim3(1), dim3(kPinvThreads), 0, st, ca, (double *)ws.pinv);
+    else
+      hipLaunchKernelGGL((k_vc_pinv<2, double, true>), dim3(1), dim3(kPinvThreads), 0, st, ca, (double *)ws.pinv);
+  }
   return hipGetLastError();
 }
 
