@@ -46,8 +46,7 @@ constexpr int kRedBlocks = 1024;   // grid of the grid-stride reduction kernels
 // for sizes that neither divides.
 constexpr int TX = 64, TY = 16;
 constexpr int TXS = 32, TYS = 8;
-constexpr int TX3 = 32, TY3 = 8;   // x-y tile of the fused 3D level kernels
-constexpr long kFused3DMinCells = 1L << 21;  // smaller 3D levels run the per-half-sweep kernels
+constexpr long kFused3DMinCells = 1L << 15;  // smaller 3D levels run the per-half-sweep kernels
 
 Lay make_layout(int ndim, const int n[3], int elem_bytes) {
   Lay L;
@@ -771,35 +770,44 @@ static void choose_tile_vc(PoissonWS &ws, int l) {
     }
 }
 
-// Depth of the z chunk of a fused 3D level kernel. Every chunk re-reads and
-// re-smooths 2H halo planes and fills a pipeline of 2 nu planes, so chunks
-// are as deep as possible while the level still has about one block per
-// block slot of the chip (256 CUs times the blocks whose LDS rings fit in
-// one CU's 160 KB): 128 planes, halved (down to 8) while there are fewer
-// blocks than that; 0 if none divides the level.
-static int tz3_of(const Lay &L, int elem_bytes, int nu) {
-  const long cols = (long)(L.n[0] / TX3) * (L.n[1] / TY3);
-  const long h = 2 * nu + 1;
-  const long ring = (4 * nu + 3) * (TX3 + 2 * h) * (TY3 + 2 * h) * elem_bytes;  // down leg's LDS
-  const long per_cu = std::max(1L, 163840L / ring);
-  const long target = 256 * per_cu;
-  int tz = 128;
-  while (tz > 8 && cols * (L.n[2] / tz) < target) tz /= 2;
-  return (L.n[2] % tz == 0) ? tz : 0;
+// Fused 3D level kernels: the owned tile edge is the 32-cell frame less
+// twice the x-y halo (down leg 2 nu; up leg 2 nu, plus one on the finest
+// level of the single-reduction CG, which also forms w = A u; rounded up to
+// even).
+static int ti3(int nu, bool down, bool extra) {
+  const int h = 2 * nu + ((!down && extra) ? 1 : 0);
+  return kF3 - 2 * ((h + 1) & ~1);
 }
-static int tz3_of(const PoissonWS &ws, const Lay &L) { return tz3_of(L, ws.mixed ? 4 : 8, ws.nu); }
+static int tiles3(const Lay &L, int ti, int d) { return (L.n[d] + ti - 1) / ti; }
 
-// Blocks of the fused 3D kernels of a level.
-static long blocks3d(const PoissonWS &ws, const Lay &L) {
-  return (long)(L.n[0] / TX3) * (L.n[1] / TY3) * (L.n[2] / tz3_of(ws, L));
+// Depth of the z chunk (a multiple of 4): the level is split into as many chunks as
+// keep about one block per block slot of the chip (256 CUs, two 512-thread
+// blocks each), but no chunk shallower than 16 planes: every chunk reads
+// 2H halo planes beyond its own.
+static int tz3_of(const Lay &L, int ti) {
+  const long tiles = (long)tiles3(L, ti, 0) * tiles3(L, ti, 1);
+  long nchunk = std::max(1L, 512L / tiles);
+  int tz = (int)((L.n[2] + nchunk - 1) / nchunk);
+  tz = std::max(16, (tz + 3) & ~3);  // chunks start on multiples of 4 (the kernels' LDS buffer order)
+  return tz;
 }
 
-// Level l runs the fused 3D kernels (fully periodic grids).
+// Blocks of one fused 3D launch on layout L with owned tile edge ti.
+static long blocks3d(const Lay &L, int ti) {
+  const int tz = tz3_of(L, ti);
+  return (long)tiles3(L, ti, 0) * tiles3(L, ti, 1) * ((L.n[2] + tz - 1) / tz);
+}
+
+// Level l runs the fused 3D kernels (fully periodic grids, even sizes).
 static bool fused3d(const PoissonWS &ws, int l) {
   const Lay &L = ws.lev[l].lay;
-  return !ws.vc && L.ndim == 3 && ws.bnd.all_periodic && ws.nu >= 1 && ws.nu <= 3 && l < ws.lc &&
-         L.ncells() >= kFused3DMinCells && L.n[0] % TX3 == 0 && L.n[1] % TY3 == 0 && tz3_of(ws, L) > 0;
+  return !ws.vc && L.ndim == 3 && ws.bnd.all_periodic && ws.nu >= 1 && ws.nu <= 2 && l < ws.lc &&
+         L.ncells() >= kFused3DMinCells && L.n[0] % 2 == 0 && L.n[1] % 2 == 0 && L.n[2] % 2 == 0 &&
+         L.n[2] >= 16;
 }
+
+// Blocks of the finest level's up kernel with w = A u (its partials).
+static long blocks3d_w(const PoissonWS &ws) { return blocks3d(ws.lev[0].lay, ti3(ws.nu, false, true)); }
 
 static bool fused_level(const PoissonWS &ws, int l) { return tile_x(ws, l) > 0; }
 
@@ -897,7 +905,7 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   long npmax = kRedBlocks;
   if (ws.tx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.tx[0]) * (fine.n[1] / ws.ty[0]) + 1);
   if (ws.vtx[0] > 0) npmax = std::max(npmax, (long)(fine.n[0] / ws.vtx[0]) * (fine.n[1] / ws.vty[0]) + 1);
-  if (fused3d(ws, 0) && blocks3d(ws, fine) > npmax) npmax = blocks3d(ws, fine);
+  if (fused3d(ws, 0) && blocks3d_w(ws) > npmax) npmax = blocks3d_w(ws);
   ws.np_max = npmax;
   ws.part_cc = (double *)cv.take((size_t)npmax * 8);
   ws.part_pq = (double *)cv.take((size_t)npmax * 8);
@@ -1008,9 +1016,7 @@ static Fused3DArgs<T> f3_args(PoissonWS &ws, int l, const void *b, int b_double)
   a.dihy = ws.lev[l].ih2[1];
   a.dihz = ws.lev[l].ih2[2];
   a.idg = (T)(1.0 / (2.0 * (ws.lev[l].ih2[0] + ws.lev[l].ih2[1] + ws.lev[l].ih2[2])));
-  a.tiles_x = L.n[0] / TX3;
-  a.tiles_y = L.n[1] / TY3;
-  a.tz = tz3_of(ws, L);
+  a.tiles_x = a.tiles_y = a.tz = 0;  // set by launch_3d for the leg
   a.b = b;
   a.b_double = b_double;
   a.xpre = nullptr;
@@ -1034,22 +1040,31 @@ static void launch_ev(K kern, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t 
 template <typename T>
 static void launch_3d(int nu, bool down, Fused3DArgs<T> &a, hipStream_t st, bool extra = false,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  const dim3 g(a.tiles_x * a.tiles_y * (a.Lf.n[2] / a.tz));
+  const int ti = ti3(nu, down, extra);
+  a.tiles_x = tiles3(a.Lf, ti, 0);
+  a.tiles_y = tiles3(a.Lf, ti, 1);
+  a.tz = tz3_of(a.Lf, ti);
+  const dim3 g((unsigned)blocks3d(a.Lf, ti));
+  const dim3 bl(kF3Threads);
+  // FP64 right-hand side in FP32 kernels only on the finest level
+  const bool bd = a.b_double && sizeof(T) == 4;
   if (down) {
-    if (nu == 1) launch_ev(&k_mg_down3d<T, 1, TX3, TY3>, g, st, e0, e1, a);
-    else if (nu == 2) launch_ev(&k_mg_down3d<T, 2, TX3, TY3>, g, st, e0, e1, a);
-    else launch_ev(&k_mg_down3d<T, 3, TX3, TY3>, g, st, e0, e1, a);
+    auto k = nu == 1 ? (bd ? &k_mg_down3d<T, 1, true> : &k_mg_down3d<T, 1, false>)
+                     : (bd ? &k_mg_down3d<T, 2, true> : &k_mg_down3d<T, 2, false>);
+    if (e0)
+      hipExtLaunchKernelGGL(k, g, bl, 0, st, e0, e1, 0, a);
+    else
+      hipLaunchKernelGGL(k, g, bl, 0, st, a);
   } else if (extra) {
-    if (nu == 1) hipLaunchKernelGGL((k_mg_up3d<T, 1, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
-    else if (nu == 2) hipLaunchKernelGGL((k_mg_up3d<T, 2, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_mg_up3d<T, 3, 1, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    auto k = nu == 1 ? (bd ? &k_mg_up3d<T, 1, 1, true> : &k_mg_up3d<T, 1, 1, false>)
+                     : (bd ? &k_mg_up3d<T, 2, 1, true> : &k_mg_up3d<T, 2, 1, false>);
+    hipLaunchKernelGGL(k, g, bl, 0, st, a);
   } else {
-    if (nu == 1) hipLaunchKernelGGL((k_mg_up3d<T, 1, 0, TX3, TY3>), g, dim3(kBlock), 0, st, a);
-    else if (nu == 2) hipLaunchKernelGGL((k_mg_up3d<T, 2, 0, TX3, TY3>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_mg_up3d<T, 3, 0, TX3, TY3>), g, dim3(kBlock), 0, st, a);
+    auto k = nu == 1 ? (bd ? &k_mg_up3d<T, 1, 0, true> : &k_mg_up3d<T, 1, 0, false>)
+                     : (bd ? &k_mg_up3d<T, 2, 0, true> : &k_mg_up3d<T, 2, 0, false>);
+    hipLaunchKernelGGL(k, g, bl, 0, st, a);
   }
 }
-
 
 // The finest 3D up kernel forms w = A u and the single-reduction CG partials.
 static bool w_in_up3d(const PoissonWS &ws) { return ws.cgcg && fused3d(ws, 0); }
@@ -1317,7 +1332,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       const bool extra = l == 0 && w_in_up3d(ws);
       a.w = ws.w;
       a.part_rz = ws.part_rz;
-      a.np = (int)blocks3d(ws, L);
+      a.np = (int)blocks3d(L, ti3(nu, false, extra));
       launch_3d<T>(nu, false, a, st, extra);
     } else {
       dim3 g = grid_for(L);
@@ -1351,7 +1366,7 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
 
 static int np_rz_of(const PoissonWS &ws) {
   if (fused_level(ws, 0)) return (ws.lay.n[0] / tile_x(ws, 0)) * (ws.lay.n[1] / tile_y(ws, 0));
-  if (w_in_up3d(ws)) return (int)blocks3d(ws, ws.lay);
+  if (w_in_up3d(ws)) return (int)blocks3d_w(ws);
   return kRedBlocks;
 }
 
