@@ -1,11 +1,19 @@
 """Benchmark: cell-updates/s of the full predictor-corrector step.
 
-Workload: the 2D doubly periodic 2*pi box at 1024^2, FP64, random-mode
-temperature (density ratio up to 4) and solenoidal velocity, Re = 500,
-Pr = 0.7, CFL 0.3, Poisson solved to relative residual 1e-10 in both stages
-(seeded synthetic input). A step is one predictor-corrector pass with two
-multigrid-preconditioned CG solves. The same workload is also timed with the
-mixed-precision preconditioner. Prints one JSON line.
+Headline workload: the 3D triply periodic 2*pi box at 256^3, FP64,
+random-mode temperature (|k| <= 6, density ratio 6) and solenoidal velocity
+(rms 0.1), Re = 400, Pr = 0.7, CFL 0.3, Poisson solved to relative residual
+1e-10 in both stages (seeded synthetic input). A step is one
+predictor-corrector pass with two multigrid-preconditioned CG solves. The
+same workload is timed with the mixed-precision preconditioner beside it.
+Its working set (about 2.7 GB) streams from HBM, so its kernels carry the
+HBM roofline. The 2D 1024^2 workload follows with an effective-bandwidth
+figure for its finest-level kernel: its working set (about 100 MB) stays in
+the 256 MB last-level cache (MALL), so that figure is not an HBM rate.
+
+Prints one JSON line. With --summarize-trace / --summarize-pmc it instead
+reads rocprofv3 output databases and prints the per-kernel summaries kept
+with the profiles (no GPU needed for those).
 """
 from __future__ import annotations
 
@@ -20,30 +28,54 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Dominant kernel: the finest-level multigrid down kernel, which also carries
-# the single-reduction CG update. Algorithmic bytes per cell (FP64): reads
-# r, w, s, u, p, x (6 x 8 B), writes p, s, x, r and the pre-smoothed
-# correction (5 x 8 B), and the coarse right-hand side (8 B per 4 cells).
-DOMINANT = "k_mg_down2d (finest level, fused CG update + 2 red-black sweeps + restriction)"
-BYTES_PER_CELL = 6 * 8 + 5 * 8 + 8 / 4
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mg_down2d_finest_c2_1024_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_01727_amd", "csrc", f)
-                  for f in ("lm_mg_kernels.h", "lm_solver.hip")]
+                  for f in ("lm_mg_kernels.h", "lm_mg3d.h", "lm_solver.hip")]
+
+# Kernel classes timed inside the step (lm_kernel_timing) and their
+# algorithmic HBM bytes per finest-level cell (FP64 build, mixed build):
+#  0 finest down: 3D reads b = r (8 B), writes the pre-smoothed correction
+#    (8 B FP64 / 4 B FP32) and the coarse right-hand side (one value per 8
+#    cells); 2D additionally carries the single-reduction CG update: reads
+#    r, w, s, u, p, x (6 x 8 B), writes p, s, x, r, correction (5 x 8 B) and
+#    the coarse right-hand side (8 B per 4 cells).
+#  1 finest 3D up: reads the pre-smoothed correction and the coarse
+#    correction (one per 8 cells), b = r (8 B), writes u = M r and w = A u
+#    (8 B each; u in FP32 for mixed).
+#  2 single-reduction CG update (3D): reads x, r, p, s, w (5 x 8 B) and u
+#    (8 B / 4 B), writes x, r, p, s (4 x 8 B). Iteration 1 has no old p, s
+#    and is left out of the timed set.
+KCLASS_3D = {
+    0: ("k_mg_down3d finest (two red-black sweeps from zero + restriction)", 8 + 8 + 1, 8 + 4 + 0.5),
+    1: ("k_mg_up3d finest (prolongation + two red-black sweeps + w = A u + CG partial sums)",
+        8 + 1 + 8 + 8 + 8, 4 + 0.5 + 8 + 4 + 8),
+    2: ("k_cgcg_update (single-reduction CG: p, s, x, r)", 10 * 8, 9 * 8 + 4),
+}
+KCLASS_2D = {
+    0: ("k_mg_down2d finest (fused CG update + two red-black sweeps + restriction)", 6 * 8 + 5 * 8 + 2,
+        None),
+}
+TRAFFIC_C4 = os.path.join(ROOT, "profiles", "c4_256_fp64_traffic.json")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=256, help="cells per side of the 3D headline box")
+    ap.add_argument("--timed-steps", type=int, default=10,
+                    help="further steps per kernel class with in-step event timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a device copy of known size (for HBM counter calibration)")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 FP64-vs-mixed comparison")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 2D 1024^2 workload")
     ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^2, slot-flame and 512^2 workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a device copy of known size (for HBM counter calibration)")
+    ap.add_argument("--summarize-trace", metavar="DB", help="summarise a rocprofv3 kernel-trace database")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="summarise two rocprofv3 --pmc databases (FETCH_SIZE, then WRITE_SIZE)")
+    ap.add_argument("--traffic-out", metavar="JSON", help="with --summarize-pmc: write the C4 traffic record")
     return ap.parse_args()
 
 
@@ -87,62 +119,120 @@ def time_solver(case, precision, steps, warmup):
     iters = (s.stats["total_poisson_iters"] - it0) / (2.0 * steps)
     sec = t1 - t0
     return dict(sec=sec, ms_per_step=1e3 * sec / steps, value=case.ncells * steps / sec,
-                poisson_iters_per_solve=iters, dt=s.dt, solver=s)
+                poisson_iters_per_solve=iters, dt=s.dt, solver=s, steps_taken=warmup + steps)
 
 
-def kernel_roofline(s, ncells, steps=20):
-    """Average duration of the dominant kernel as launched inside the step:
-    each of its launches in `steps` further steps of the same run carries a
-    start and a stop HIP event bound to the dispatch on the solver's stream
-    (lm_kernel_timing); priced at its algorithmic bytes. The same kernel
-    timed back to back in isolation (lm_bench_kernel) is reported beside it."""
+def time_class(s, which, steps):
+    """Mean event-measured duration (us) of one kernel class over its
+    full-work launches in `steps` further steps, and the launch count."""
     import ctypes as C
     ms = C.c_double()
     cnt = C.c_int()
-    if s.lib.lm_kernel_timing(s.ctx, 64 * steps) != 0:
+    if s.lib.lm_kernel_timing(s.ctx, which, 64 * steps) != 0:
         return None
     s.step(steps)
     st = s.lib.lm_kernel_timing_read(s.ctx, C.byref(ms), C.byref(cnt))
-    s.lib.lm_kernel_timing(s.ctx, 0)
+    s.lib.lm_kernel_timing(s.ctx, which, 0)
     if st != 0 or cnt.value == 0:
         return None
-    iso = C.c_double()
-    iso_us = None
-    if s.lib.lm_bench_kernel(s.ctx, 0, 200, C.byref(iso)) == 0:
-        iso_us = round(iso.value * 1e3, 3)
-    per_launch_s = ms.value * 1e-3
-    achieved = BYTES_PER_CELL * ncells / per_launch_s / 1e9
+    return ms.value * 1e3, cnt.value
+
+
+def load_traffic(path):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    return t if t.get("kernel_source_hash") == kernel_source_hash() else None
+
+
+def class_rooflines(s, ncells, classes, steps, mixed=False):
+    """Each kernel class timed inside the step (start/stop HIP events bound
+    to its dispatches on the solver's stream), priced at its algorithmic
+    bytes; the class with the largest time per step is the dominant one."""
+    rows = []
+    for which, (name, b64, bmx) in classes.items():
+        bpc = bmx if mixed else b64
+        t = time_class(s, which, steps)
+        if t is None or bpc is None:
+            continue
+        us, cnt = t
+        achieved = bpc * ncells / (us * 1e-6) / 1e9
+        rows.append(dict(kernel=name, timing_class=which, avg_us=round(us, 3), launches_timed=cnt,
+                         launches_per_step=round(cnt / steps, 2), us_per_step=round(us * cnt / steps, 1),
+                         bytes_per_cell=bpc, algorithmic_bytes_per_launch=bpc * ncells,
+                         achieved=round(achieved, 1), frac=round(achieved / HBM_PEAK_GBS, 4)))
+    return rows
+
+
+def c4_roofline(s, ncells, steps):
+    rows = class_rooflines(s, ncells, KCLASS_3D, steps)
+    if not rows:
+        return None
+    dom = max(rows, key=lambda r: r["us_per_step"])
+    t = load_traffic(TRAFFIC_C4)
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-        if t.get("kernel_source_hash") == kernel_source_hash():
-            traffic = t.get("bytes_per_launch")
-    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=DOMINANT,
-                avg_us=round(per_launch_s * 1e6, 3), launches_timed=cnt.value, timed_steps=steps,
-                isolated_avg_us=iso_us, bytes_per_cell=BYTES_PER_CELL,
-                algorithmic_bytes_per_launch=BYTES_PER_CELL * ncells)
+    if t is not None:
+        traffic = t.get("bytes_per_launch", {}).get(str(dom["timing_class"]))
+    return dict(bound="hbm", achieved=dom["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=dom["frac"],
+                traffic=traffic, kernel=dom["kernel"], avg_us=dom["avg_us"], launches_timed=dom["launches_timed"],
+                timed_steps=steps, bytes_per_cell=dom["bytes_per_cell"],
+                algorithmic_bytes_per_launch=dom["algorithmic_bytes_per_launch"],
+                dominant_by="event-timed time per step among the timed classes",
+                classes=rows)
 
 
-def bench_3d(steps=10, warmup=3):
-    """The 3D triply periodic 256^3 workload (random modes |k| <= 6,
-    density ratio 6, Re 400), FP64 against mixed precision on the same
-    device, same steps; not the headline metric."""
-    from workloads import c4_case
-    case = c4_case()
-    out = {"workload": "3D periodic 2pi box 256^3, random modes |k|<=6, density ratio 6, Re=400, Pr=0.7, "
-                       "CFL 0.3, Poisson rtol 1e-10", "steps": steps, "warmup": warmup}
-    res = {}
-    for prec in ("fp64", "mixed"):
-        r = time_solver(case, prec, steps, warmup)
-        res[prec] = r
-        out[prec] = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 3),
-                         poisson_iters_per_solve=r["poisson_iters_per_solve"])
-    out["mixed_speedup_vs_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
-    out["mixed_rel_l2_vs_fp64"] = field_differences(res["mixed"]["solver"], res["fp64"]["solver"])
-    for r in res.values():
-        r["solver"].close()
+def field_differences(s_a, s_b):
+    import numpy as np
+    fa = s_a.get(("rho", "v", "H", "T", "P"), device=False)
+    fb = s_b.get(("rho", "v", "H", "T", "P"), device=False)
+    out = {}
+    for k in ("rho", "H", "T", "P"):
+        out[k] = float(np.linalg.norm(fa[k] - fb[k]) / np.linalg.norm(fb[k]))
+    for d in range(len(fb["v"])):
+        out[f"v{d}"] = float(np.linalg.norm(fa["v"][d] - fb["v"][d]) / np.linalg.norm(fb["v"][d]))
+    return out
+
+
+def precision_block(case, ref, steps, warmup, precision):
+    """Another preconditioner precision on the same workload and step count,
+    with its per-field relative L2 difference from the FP64 state once both
+    have taken the same number of steps."""
+    r = time_solver(case, precision, steps, warmup)
+    out = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
+               poisson_iters_per_solve=r["poisson_iters_per_solve"],
+               speedup_vs_fp64=round(r["value"] / ref["value"], 3))
+    extra = ref["steps_taken"] - r["steps_taken"]
+    if extra >= 0:
+        if extra:
+            r["solver"].step(extra)
+        out["rel_l2_vs_fp64"] = field_differences(r["solver"], ref["solver"])
+        out["compared_after_steps"] = ref["steps_taken"]
+    r["solver"].close()
+    return out
+
+
+def c2_block(steps=100, warmup=5, timed=20):
+    """The 2D doubly periodic 1024^2 workload (random modes |k| <= 8,
+    density ratio 4, Re 500), FP64, mixed and mixed-flexible."""
+    from workloads import c2_case
+    case = c2_case()
+    r64 = time_solver(case, "fp64", steps, warmup)
+    out = {"workload": "2D periodic 2pi box 1024x1024, random modes |k|<=8, density ratio 4, Re=500, Pr=0.7, "
+                       "CFL 0.3, Poisson rtol 1e-10", "steps": steps, "warmup": warmup,
+           "fp64": dict(value=r64["value"], ms_per_step=round(r64["ms_per_step"], 4),
+                        poisson_iters_per_solve=r64["poisson_iters_per_solve"])}
+    rows = class_rooflines(r64["solver"], case.ncells, KCLASS_2D, timed)
+    r64["steps_taken"] += timed * len(rows)
+    if rows:
+        r = rows[0]
+        out["effective_bandwidth"] = dict(
+            kind="mall-assisted effective bandwidth (the ~100 MB working set stays in the 256 MB MALL); "
+                 "not an HBM rate", kernel=r["kernel"], avg_us=r["avg_us"], bytes_per_cell=r["bytes_per_cell"],
+            effective_GBs=r["achieved"], frac_of_hbm_peak=r["frac"], launches_timed=r["launches_timed"])
+    out["mixed"] = precision_block(case, r64, steps, warmup, "mixed")
+    out["mixed_flexible"] = precision_block(case, r64, steps, warmup, "mixed-flexible")
+    r64["solver"].close()
     return out
 
 
@@ -208,37 +298,29 @@ def bench_configs(steps=20, warmup=3):
     return out
 
 
-def field_differences(s_a, s_b):
-    import numpy as np
-    fa = s_a.get(("rho", "v", "H", "T", "P"), device=False)
-    fb = s_b.get(("rho", "v", "H", "T", "P"), device=False)
-    out = {}
-    for k in ("rho", "H", "T", "P"):
-        out[k] = float(np.linalg.norm(fa[k] - fb[k]) / np.linalg.norm(fb[k]))
-    for d in range(len(fb["v"])):
-        out[f"v{d}"] = float(np.linalg.norm(fa["v"][d] - fb["v"][d]) / np.linalg.norm(fb["v"][d]))
-    return out
+ORACLE_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O", "Da_ib",
+               "p0", "dt", "cfl")
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The FP64 oracle on the host: one warm-up step, then steps until about
-    budget_s seconds have passed (at least 2)."""
+def cpu_baseline(case):
+    """The FP64 oracle on the host cores: one step of the same workload
+    (the first, Heun-start step; set-up excluded). Its Poisson solve is the
+    exact FFT transform solve on all usable cores; the stencils are NumPy on
+    one thread."""
     from oracle import Grid, Oracle, Params
-    p = case.params
-    g = Grid(case.n[:2], case.L[:2])
-    o = Oracle(g, Params(Re=p["Re"], Pr=p["Pr"], cfl=p["cfl"]))
-    st = o.initial_state(case.T, case.v)
-    st = o.step(st)
+    from oracle.poisson import FFT_WORKERS
+    nd = case.ndim
+    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc, bnd=case.bnd)
+    o = Oracle(g, Params(**{k: case.params[k] for k in ORACLE_KEYS if k in case.params}), ib=case.ib)
+    st = o.initial_state(case.T, case.v, Z=case.Z, H=case.H)
     t0 = time.perf_counter()
-    n = 0
-    while n < 2 or time.perf_counter() - t0 < budget_s:
-        st = o.step(st)
-        n += 1
+    st = o.step(st)
     sec = time.perf_counter() - t0
-    return dict(value=case.ncells * n / sec, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"{n} steps of the {case.n[0]}x{case.n[1]} workload after one warm-up step "
-                       f"(NumPy FP64, FFT Poisson, single thread), {sec:.1f} s",
-                host_cpus=os.cpu_count(), host_cpus_usable=len(os.sched_getaffinity(0)))
+    shape = "x".join(str(x) for x in case.n[:nd])
+    return dict(value=case.ncells / sec, unit="cell-updates/s", cores=FFT_WORKERS, kind="oracle",
+                sample=f"one step (the Heun-start step) of the {shape} workload, {sec:.1f} s: FFT Poisson "
+                       f"solves on {FFT_WORKERS} threads (scipy.fft workers), NumPy stencils on one thread",
+                host_cpus=os.cpu_count(), host_cpus_usable=FFT_WORKERS)
 
 
 def copy_calibration():
@@ -252,36 +334,127 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
+# --- rocprofv3 output summaries (host only) --------------------------------
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 512 * 1024 * 1024
+
+
+def _groups(rows):
+    """rows: (name, grid, value) -> {(name, grid): [values]}"""
+    g = {}
+    for name, grid, v in rows:
+        g.setdefault((name, grid), []).append(v)
+    return g
+
+
+def _full_work(vals):
+    """Launches that did a full pass: at least half the group's 90th
+    percentile (launches queued after a solve converged return at once)."""
+    s = sorted(vals)
+    cut = 0.5 * s[int(0.9 * (len(s) - 1))]
+    return [v for v in vals if v >= cut]
+
+
+def summarize_trace(db_path):
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select name, grid_x * grid_y * grid_z, end - start, vgpr_count, lds_size, "
+                      "scratch_size from kernels").fetchall()
+    res = {}
+    for name, grid, dur, vgpr, lds, scr in rows:
+        r = res.setdefault((name.split("(")[0], grid), dict(d=[], vgpr=vgpr, lds=lds, scratch=scr))
+        r["d"].append(dur * 1e-3)
+    tot = sum(sum(r["d"]) for r in res.values())
+    print(f"kernel-trace summary of {os.path.basename(db_path)}: {len(rows)} dispatches, {tot / 1e3:.2f} ms kernel "
+          f"time. Columns: launches, mean (all), full-work launches and their mean (us; full work = at least "
+          f"half the group's 90th percentile), total ms, VGPRs, LDS bytes, scratch bytes.")
+    for (name, grid), r in sorted(res.items(), key=lambda kv: -sum(kv[1]["d"])):
+        d = r["d"]
+        fw = _full_work(d)
+        print(f"{name[:58]:58s} grid {grid:9d} n {len(d):5d} mean {sum(d) / len(d):9.2f}  full {len(fw):5d} "
+              f"mean {sum(fw) / len(fw):9.2f}  total {sum(d) / 1e3:8.3f}  vgpr {r['vgpr']:3d} lds {r['lds']:6d} "
+              f"scratch {r['scratch']}")
+
+
+def _pmc_rows(db_path, counter):
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    q = ("select kernel_name, grid_size, dispatch_id, sum(value) from counters_collection "
+         "where counter_name = ? group by dispatch_id")
+    return [(n.split("(")[0], g, v) for n, g, _, v in db.execute(q, (counter,)).fetchall()]
+
+
+def summarize_pmc(fetch_db, write_db, traffic_out=None):
+    f = _groups(_pmc_rows(fetch_db, "FETCH_SIZE"))
+    w = _groups(_pmc_rows(write_db, "WRITE_SIZE"))
+    cf = [v for (n, _), vs in f.items() if n.startswith(COPY_KERNEL) for v in vs]
+    cw = [v for (n, _), vs in w.items() if n.startswith(COPY_KERNEL) for v in vs]
+    if not cf or not cw:
+        raise SystemExit("no copy-calibration dispatch in the databases (run bench.py with --copy-calibration)")
+    kib = COPY_BYTES / 1024
+    fs, ws = kib / (sum(cf) / len(cf)), kib / (sum(cw) / len(cw))
+    print(f"HBM-side byte counters per dispatch, two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE). "
+          f"Calibration: a 512 MiB device copy ({COPY_KERNEL}) reads and writes 512 MiB; it reads "
+          f"FETCH {sum(cf) / len(cf):.1f} KiB and WRITE {sum(cw) / len(cw):.1f} KiB, so FETCH is scaled by {fs:.4f} "
+          f"and WRITE by {ws:.4f}. Columns: full-work dispatches (FETCH at least half its 90th percentile), "
+          f"scaled KiB per dispatch, MB per dispatch.")
+    out = {}
+    for key in sorted(f, key=lambda k: -sum(f[k])):
+        if key not in w:
+            continue
+        fv, wv = _full_work(f[key]), _full_work(w[key])
+        fk, wk = fs * sum(fv) / len(fv), ws * sum(wv) / len(wv)
+        tot = (fk + wk) * 1024
+        out[key] = tot
+        print(f"{key[0][:58]:58s} grid {key[1]:9d} n {len(fv):4d}/{len(wv):4d} fetch {fk:11.1f} KiB "
+              f"write {wk:11.1f} KiB total {tot / 1e6:9.2f} MB")
+    if traffic_out:
+        # timing class -> the finest-level dispatch group of that kernel
+        pick = {}
+        for (name, grid), tot in out.items():
+            for which, tag in ((0, "k_mg_down3d<double"), (1, "k_mg_up3d<double, 2, 1"),
+                               (2, "k_cgcg_update<3, double")):
+                if tag in name and (which not in pick or grid > pick[which][1]):
+                    pick[which] = (name, grid, tot)
+        rec = {"workload": "3D periodic 256^3 FP64 step", "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+               "kernels": {str(k): f"{v[0]} grid {v[1]}" for k, v in pick.items()},
+               "bytes_per_launch": {str(k): int(v[2]) for k, v in pick.items()},
+               "kernel_source_hash": kernel_source_hash()}
+        with open(traffic_out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+
+
 def main():
     a = parse()
+    if a.summarize_trace:
+        summarize_trace(a.summarize_trace)
+        return
+    if a.summarize_pmc:
+        summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.traffic_out)
+        return
     if a.gpus != 1:
-        print(json.dumps({"error": "one GPU only: --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU: --gpus must be 1 (the step has no "
+                                   "multi-GPU path)"}))
         sys.exit(2)
-    from workloads import c2_case
-    case = c2_case(n=a.n)
+    from workloads import c4_case
+    case = c4_case(n=a.n)
     if a.copy_calibration:
         copy_calibration()
     r64 = time_solver(case, "fp64", a.steps, a.warmup)
-    roof = kernel_roofline(r64["solver"], case.ncells)
+    roof = c4_roofline(r64["solver"], case.ncells, a.timed_steps)
+    if roof is not None:
+        r64["steps_taken"] += a.timed_steps * len(roof["classes"])
     mixed = None
     if not a.no_mixed:
-        rmx = time_solver(case, "mixed", a.steps, a.warmup)
-        mixed = dict(value=rmx["value"], ms_per_step=round(rmx["ms_per_step"], 4),
-                     poisson_iters_per_solve=rmx["poisson_iters_per_solve"],
-                     speedup_vs_fp64=round(rmx["value"] / r64["value"], 3))
-        if roof is not None:
-            # both runs at the same step count: per-field relative L2
-            # difference of the mixed-precision state from the FP64 one
-            rmx["solver"].step(roof["timed_steps"])
-            mixed["rel_l2_vs_fp64"] = field_differences(rmx["solver"], r64["solver"])
-            mixed["compared_after_steps"] = a.warmup + a.steps + roof["timed_steps"]
-        rfl = time_solver(case, "mixed-flexible", a.steps, a.warmup)
-        mixed["flexible_cg"] = dict(value=rfl["value"], ms_per_step=round(rfl["ms_per_step"], 4),
-                                    poisson_iters_per_solve=rfl["poisson_iters_per_solve"],
-                                    speedup_vs_fp64=round(rfl["value"] / r64["value"], 3))
-        del rfl
-    three_d = None if a.no_3d else bench_3d()
-    forms = None if a.no_vc else poisson_forms(a.n)
+        mixed = precision_block(case, r64, a.steps, a.warmup, "mixed")
+        mixed["flexible_cg"] = precision_block(case, r64, a.steps, a.warmup, "mixed-flexible")
+    cfg = {"workload": f"3D triply periodic 2pi box {a.n}^3, random modes |k|<=6, density ratio 6, Re=400, "
+                       f"Pr=0.7, CFL 0.3, Poisson rtol 1e-10", "cells": case.ncells, "dt": r64["dt"],
+           "poisson_iters_per_solve": r64["poisson_iters_per_solve"]}
+    r64["solver"].close()
+    c2 = None if a.no_c2 else c2_block()
+    forms = None if a.no_vc else poisson_forms()
     configs = None if a.no_configs else bench_configs()
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
@@ -297,12 +470,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded random-mode temperature and solenoidal velocity)",
-        "config": {"workload": f"2D periodic 2pi box {a.n}x{a.n}, random modes |k|<=8, density ratio 4, "
-                               f"Re=500, Pr=0.7, CFL 0.3, Poisson rtol 1e-10",
-                   "cells": case.ncells, "dt": r64["dt"],
-                   "poisson_iters_per_solve": r64["poisson_iters_per_solve"]},
+        "config": cfg,
         "mixed": mixed,
-        "c4_3d": three_d,
+        "c2_1024": c2,
         "poisson_forms": forms,
         "other_workloads": configs,
         "roofline": roof,

@@ -232,7 +232,13 @@ lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t
 /* Create a context on the current HIP device over a caller workspace of
  * `bytes` bytes (>= lm_workspace_size) and a caller stream (hipStream_t,
  * NULL = default stream). Errors: LM_EINVAL (bad grid: ndim, n < 4, a
- * periodic pair broken, non-positive L; bad params), LM_ENOMEM.            */
+ * periodic pair broken, non-positive L; bad params), LM_ENOMEM.
+ * The environment variable LM_STAGE_KERNEL, read here, picks the form of
+ * the explicit stage kernel: unset, the LDS halo-tile kernel in 2D and the
+ * one-thread-per-cell kernel in 3D; "lds" or "direct", that form in both
+ * (grids whose planes do not tile by 64 x 4, and 3D grids with an
+ * immersed body, always take the one-thread-per-cell kernel). The forms
+ * compute the same arithmetic.                                              */
 lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *dev_workspace,
                        size_t bytes, void *hip_stream, lm_ctx **out);
 
@@ -337,18 +343,21 @@ lm_status lm_adjoint_initial(lm_ctx *ctx, double *T0_bar, double *v0_bar[3], int
  *   6 Poisson right-hand side                  7 projection                    */
 lm_status lm_bench_kernel(lm_ctx *ctx, int which, int reps, double *avg_ms);
 
-/* In-step timing of the finest multigrid down kernel (the fused 2D or 3D
- * level kernel): with capacity > 0, the next launches of that kernel made
- * by lm_step (up to capacity of them) each carry a start and a stop HIP
- * event bound to the dispatch on the context's stream (recorded when the
- * kernel starts and ends, so the queueing gap before it is not counted);
- * capacity = 0 stops and releases the events.
+/* In-step timing of one solver kernel class, which = 0: the finest
+ * multigrid down kernel (the fused 2D or 3D level kernel); 1: the finest
+ * fused 3D up kernel; 2: the separate single-reduction CG update (grids
+ * whose finest level is not a fused 2D one). With capacity > 0, the next
+ * launches of that kernel made by lm_step (up to capacity of them) each
+ * carry a start and a stop HIP event bound to the dispatch on the context's
+ * stream (recorded when the kernel starts and ends, so the queueing gap
+ * before it is not counted); capacity = 0 stops and releases the events.
  * lm_kernel_timing_read waits for the stream, then returns the mean
  * event-measured duration (ms) and the number of the recorded launches
- * that did the full work of a CG iteration (iterations 1 .. the solve's
- * iteration count: iteration 0 has no CG update and launches queued after
- * convergence return at once); 0 when the grid has no fused finest level. */
-lm_status lm_kernel_timing(lm_ctx *ctx, int capacity);
+ * that did the full work of a CG iteration with a previous direction
+ * (iterations 2 .. the solve's iteration count: launches queued after
+ * convergence return at once);
+ * 0 when the grid has no such kernel. LM_EINVAL for another which.       */
+lm_status lm_kernel_timing(lm_ctx *ctx, int which, int capacity);
 lm_status lm_kernel_timing_read(lm_ctx *ctx, double *avg_ms, int *count);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -227,6 +227,12 @@ void setup_phys(lm_ctx *c) {
   for (int d = 0; d < g.ndim; ++d) P.volume *= g.L[d];
   P.vol_out = 0.0;
   P.suth_C = p.sutherland_C;
+  // stage kernel form: by default the LDS halo tiles in 2D and one thread
+  // per cell in 3D (the faster of the two forms measured at 1024^2 and
+  // 256^3); LM_STAGE_KERNEL=lds or =direct forces one form everywhere the
+  // grid allows it (tuning and comparison)
+  const char *sk = std::getenv("LM_STAGE_KERNEL");
+  P.stage_form = !sk ? 0 : std::strcmp(sk, "lds") == 0 ? 1 : std::strcmp(sk, "direct") == 0 ? 2 : 0;
 }
 
 // Carves every device array (or only sizes them when cv.base == nullptr).
@@ -907,7 +913,7 @@ const char *lm_last_error(const lm_ctx *c) { return c ? c->err.c_str() : g_init_
 
 void lm_destroy(lm_ctx *c) {
   if (!c) return;
-  (void)lm_kernel_timing(c, 0);
+  (void)lm_kernel_timing(c, 0, 0);
   if (c->hflags) (void)hipHostFree(c->hflags);
   if (c->hscalar) (void)hipHostFree(c->hscalar);
   if (c->pws.host_sc) (void)hipHostFree(c->pws.host_sc);
@@ -1265,8 +1271,8 @@ extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_ba
 // ---------------------------------------------------------------------------
 // In-step kernel timing
 // ---------------------------------------------------------------------------
-extern "C" lm_status lm_kernel_timing(lm_ctx *c, int capacity) {
-  if (!c || capacity < 0) return fail(c, LM_EINVAL, "bad arguments");
+extern "C" lm_status lm_kernel_timing(lm_ctx *c, int which, int capacity) {
+  if (!c || capacity < 0 || which < 0 || which > 2) return fail(c, LM_EINVAL, "bad arguments");
   PoissonWS &ws = c->pws;
   if (ws.tev) {
     (void)hipStreamSynchronize(c->st);
@@ -1277,6 +1283,7 @@ extern "C" lm_status lm_kernel_timing(lm_ctx *c, int capacity) {
     ws.tk = nullptr;
   }
   ws.tcap = ws.tcount = ws.tsolve0 = 0;
+  ws.twhich = which;
   if (capacity == 0) return LM_OK;
   ws.tev = new (std::nothrow) hipEvent_t[2 * (size_t)capacity];
   ws.tk = new (std::nothrow) int[(size_t)capacity];

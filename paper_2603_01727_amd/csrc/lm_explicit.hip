@@ -248,29 +248,70 @@ hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys 
 // Residuals at one time level and the Adams update
 // ---------------------------------------------------------------------------
 
-// tau_id on the face between cell cl and cl + s_d (Eq 2.46 on d-faces), all
-// components i at once: kappa_f [D_d v_i + D_i v_d - 2/3 delta_id div], D_d
-// the difference across the face, D_k (k != d) the mean of the two cells'
-// centred differences. Only the derivatives the face needs are formed: the
-// normal ones of every component, and along each k != d those of v_d and
-// v_k.
-template <int DIM>
-__device__ inline void face_stress(const Lay &L, const Phys &P, const Level &lv, long cl, int d, double tau[3]) {
-  const long sd = L.s[d];
-  const double kf = 0.5 * (lv.kap[cl] + lv.kap[cl + sd]);
+// ---- field access ---------------------------------------------------------
+// The residual arithmetic reads every field through an accessor, at offsets
+// (o0, o1, o2) in cells from the cell the residual is taken at, so one body
+// of arithmetic serves both the direct kernel (padded arrays in HBM) and the
+// z-marching 3D kernel (LDS planes and registers).
+struct DirectAcc {
+  static constexpr bool kPhased = false;
+  const Level &lv;
+  const IB &ib;
+  long c, s1, s2;
+  int has_ib;
+  __device__ long at(int o0, int o1, int o2) const { return c + o0 + o1 * s1 + o2 * s2; }
+  __device__ double v(int i, int o0, int o1, int o2) const { return lv.v[i][at(o0, o1, o2)]; }
+  __device__ double kap(int o0, int o1, int o2) const { return lv.kap[at(o0, o1, o2)]; }
+  // scalar field f: 0 H, 1 Z
+  __device__ double s(int f, int o0, int o1, int o2) const { return (f ? lv.Z : lv.H)[at(o0, o1, o2)]; }
+  // face flux F_d on the face of the cell at offset o (0 or -1) along d
+  __device__ double F(int d, int o) const { return lv.F[d][c + o * (d == 0 ? 1 : (d == 1 ? s1 : s2))]; }
+  __device__ double rho() const { return lv.rho[c]; }
+  __device__ double chi() const { return (has_ib && ib.chi) ? (double)ib.chi[c] : 0.0; }
+  __device__ double v_ib(int i) const { return ib.v_ib[i] ? ib.v_ib[i][c] : 0.0; }
+  __device__ double Z_ib() const { return ib.Z_ib ? ib.Z_ib[c] : 0.0; }
+  __device__ double H_ib() const { return ib.H_ib ? ib.H_ib[c] : 0.0; }
+};
+
+// Scheduling fence between the phases of a residual, for accessors that
+// ask for it (LDS-fed forms: their operands are cheap to fetch late, and
+// holding them all at once would exhaust the register file).
+template <class A>
+__device__ inline void phase_fence() {
+  if constexpr (A::kPhased) asm volatile("" ::: "memory");
+}
+
+// tau_id on the face between the cells at offsets lo e_d and (lo + 1) e_d
+// (lo = 0 or -1; Eq 2.46 on d-faces), all components i at once: kappa_f
+// [D_d v_i + D_i v_d - 2/3 delta_id div], D_d the difference across the
+// face, D_k (k != d) the mean of the two cells' centred differences. Only
+// the derivatives the face needs are formed: the normal ones of every
+// component, and along each k != d those of v_d and v_k.
+template <int DIM, class A>
+__device__ inline void face_stress(const A &a, const Phys &P, int lo, int d, double tau[3]) {
+  int o[3] = {0, 0, 0}, q[3] = {0, 0, 0};
+  o[d] = lo;
+  q[d] = lo + 1;
+  const double kf = 0.5 * (a.kap(o[0], o[1], o[2]) + a.kap(q[0], q[1], q[2]));
   double Dn[3];       // D_d v_c
   double Dkd[3];      // D_k v_d (k != d)
   double Dkk[3];      // D_k v_k (k != d)
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) Dn[c] = (lv.v[c][cl + sd] - lv.v[c][cl]) * P.ih[d];
+  for (int c = 0; c < DIM; ++c) Dn[c] = (a.v(c, q[0], q[1], q[2]) - a.v(c, o[0], o[1], o[2])) * P.ih[d];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     if (k == d) continue;
-    const long sk = L.s[k];
     const double i2h = 0.5 * P.ih[k];  // 1/(2h): centred differences
-    const double *vd = lv.v[d], *vk = lv.v[k];
-    Dkd[k] = 0.5 * ((vd[cl + sk] - vd[cl - sk]) * i2h + (vd[cl + sd + sk] - vd[cl + sd - sk]) * i2h);
-    Dkk[k] = 0.5 * ((vk[cl + sk] - vk[cl - sk]) * i2h + (vk[cl + sd + sk] - vk[cl + sd - sk]) * i2h);
+    int op[3] = {o[0], o[1], o[2]}, om[3] = {o[0], o[1], o[2]};
+    int qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
+    op[k] += 1;
+    om[k] -= 1;
+    qp[k] += 1;
+    qm[k] -= 1;
+    Dkd[k] = 0.5 * ((a.v(d, op[0], op[1], op[2]) - a.v(d, om[0], om[1], om[2])) * i2h +
+                    (a.v(d, qp[0], qp[1], qp[2]) - a.v(d, qm[0], qm[1], qm[2])) * i2h);
+    Dkk[k] = 0.5 * ((a.v(k, op[0], op[1], op[2]) - a.v(k, om[0], om[1], om[2])) * i2h +
+                    (a.v(k, qp[0], qp[1], qp[2]) - a.v(k, qm[0], qm[1], qm[2])) * i2h);
   }
   double div = 0.0;
 #pragma unroll
@@ -282,61 +323,72 @@ __device__ inline void face_stress(const Lay &L, const Phys &P, const Level &lv,
   }
 }
 
-// Scalar terms of Eq 3.26b and the centred diffusion of section 3.2.
-template <int DIM>
-__device__ inline void scalar_terms(const Lay &L, const Phys &P, const Level &lv, const double *phi, long c,
-                                    double &adv, double &dif) {
+// Scalar terms of Eq 3.26b and the centred diffusion of section 3.2 for the
+// scalar field f (0 H, 1 Z).
+template <int DIM, class A>
+__device__ inline void scalar_terms(const A &a, const Phys &P, int f, double &adv, double &dif) {
   adv = 0.0;
   dif = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const long s = L.s[d];
-    const double gp = (phi[c + s] - phi[c]) * P.ih[d];
-    const double gm = (phi[c] - phi[c - s]) * P.ih[d];
-    const double kp = 0.5 * (lv.kap[c] + lv.kap[c + s]);
-    const double km = 0.5 * (lv.kap[c - s] + lv.kap[c]);
-    adv = adv + 0.5 * (lv.F[d][c] * gp + lv.F[d][c - s] * gm);
+    int p[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+    p[d] = 1;
+    m[d] = -1;
+    const double sc = a.s(f, 0, 0, 0);
+    const double gp = (a.s(f, p[0], p[1], p[2]) - sc) * P.ih[d];
+    const double gm = (sc - a.s(f, m[0], m[1], m[2])) * P.ih[d];
+    const double kc = a.kap(0, 0, 0);
+    const double kp = 0.5 * (kc + a.kap(p[0], p[1], p[2]));
+    const double km = 0.5 * (a.kap(m[0], m[1], m[2]) + kc);
+    adv = adv + 0.5 * (a.F(d, 0) * gp + a.F(d, -1) * gm);
     dif = dif + (kp * gp - km * gm) * P.ih[d];
   }
 }
 
+// Direct form for kernels that take the scalar terms alone.
 template <int DIM>
-__device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, const IB &ib, long c, double dtp0,
-                                 double &RH, double &RZ, double Rv[3]) {
-  const double rho = lv.rho[c];
-  const double kap = lv.kap[c];
-  const double chi = (P.has_ib && ib.chi) ? (double)ib.chi[c] : 0.0;
+__device__ inline void scalar_terms(const Lay &L, const Phys &P, const Level &lv, int f, long c, double &adv,
+                                    double &dif) {
+  const IB ib{};
+  const DirectAcc a{lv, ib, c, L.s[1], L.s[2], 0};
+  scalar_terms<DIM>(a, P, f, adv, dif);
+}
+
+template <int DIM, class A>
+__device__ inline void residuals(const A &a, const Phys &P, double dtp0, double &RH, double &RZ, double Rv[3]) {
+  const double rho = a.rho();
+  const double kap = a.kap(0, 0, 0);
+  const double chi = a.chi();
   double advH, difH;
-  scalar_terms<DIM>(L, P, lv, lv.H, c, advH, difH);
+  phase_fence<A>();
+  scalar_terms<DIM>(a, P, 0, advH, difH);
+  phase_fence<A>();
   double rH = -advH + difH / P.Pe;
   RZ = 0.0;
   if (P.reacting) {
     double advZ, difZ;
-    scalar_terms<DIM>(L, P, lv, lv.Z, c, advZ, difZ);
-    const double Z = lv.Z[c];
+    scalar_terms<DIM>(a, P, 1, advZ, difZ);
+    phase_fence<A>();
+    const double Z = a.s(1, 0, 0, 0);
     const double th = theta_eps(P, Z);
     const double le = (P.Le_F - P.Le_O) * th + P.Le_O;
     const double nn = (P.N_F - P.N_O) * th + P.N_O;
     double rZ = -advZ + difZ / (le * P.Pe);
     rH = rH + nn * difZ / P.Pe;
-    if (chi != 0.0) {
-      const double zib = ib.Z_ib ? ib.Z_ib[c] : 0.0;
-      rZ = rZ - chi * kap * (Z - zib) / (le * P.Pe * P.Da);
-    }
+    if (chi != 0.0) rZ = rZ - chi * kap * (Z - a.Z_ib()) / (le * P.Pe * P.Da);
     RZ = rZ / rho;
   }
-  if (chi != 0.0) {
-    const double hib = ib.H_ib ? ib.H_ib[c] : 0.0;
-    rH = rH - chi * kap * (lv.H[c] - hib) / (P.Pe * P.Da);
-  }
+  if (chi != 0.0) rH = rH - chi * kap * (a.s(0, 0, 0, 0) - a.H_ib()) / (P.Pe * P.Da);
   if (P.closed) rH = rH + P.zeta * dtp0;  // zeta d_t p0 (Eq 3.4b), enclosed systems
   RH = rH / rho;
   double visc_all[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     double tp[3], tm[3];
-    face_stress<DIM>(L, P, lv, c, d, tp);
-    face_stress<DIM>(L, P, lv, c - L.s[d], d, tm);
+    face_stress<DIM>(a, P, 0, d, tp);
+    phase_fence<A>();
+    face_stress<DIM>(a, P, -1, d, tm);
+    phase_fence<A>();
 #pragma unroll
     for (int i = 0; i < DIM; ++i) visc_all[i] = visc_all[i] + (tp[i] - tm[i]) * P.ih[d];
   }
@@ -344,21 +396,21 @@ __device__ inline void residuals(const Lay &L, const Phys &P, const Level &lv, c
   for (int i = 0; i < DIM; ++i) {
     double conv = 0.0;
     const double visc = visc_all[i];
+    const double vc = a.v(i, 0, 0, 0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const long s = L.s[d];
-      const double *vi = lv.v[i];
-      const double flp = lv.F[d][c] * (0.5 * (vi[c] + vi[c + s]));
-      const double flm = lv.F[d][c - s] * (0.5 * (vi[c - s] + vi[c]));
+      int p[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+      p[d] = 1;
+      m[d] = -1;
+      const double flp = a.F(d, 0) * (0.5 * (vc + a.v(i, p[0], p[1], p[2])));
+      const double flm = a.F(d, -1) * (0.5 * (a.v(i, m[0], m[1], m[2]) + vc));
       conv = conv + (flp - flm) * P.ih[d];
     }
     double r = -conv + (P.Pr / P.Pe) * visc;
     if (i == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
-    if (chi != 0.0) {
-      const double vib = ib.v_ib[i] ? ib.v_ib[i][c] : 0.0;
-      r = r - chi * (P.Pr / (P.Pe * P.Da)) * kap * (lv.v[i][c] - vib);
-    }
+    if (chi != 0.0) r = r - chi * (P.Pr / (P.Pe * P.Da)) * kap * (vc - a.v_ib(i));
     Rv[i] = r;
+    phase_fence<A>();
   }
 }
 
@@ -370,21 +422,37 @@ struct StageArgs {
   const double *dtp0;  // d_t p0 of the level the residuals are taken at (enclosed systems)
 };
 
-// Predictor (corrector = 0): residuals of level n, stored for the corrector
+// Values at the cell the Adams update reads besides the residuals: level n
+// and the stored residuals (R^{n-1} in the predictor, R^n in the corrector).
+struct Centre {
+  double rho0, H0, Z0, v0[3];
+  double rH, rZ, rv[3];
+};
+
+template <int DIM, int CORR>
+__device__ inline void load_centre(const Phys &P, const StageArgs &a, long c, int first, Centre &q) {
+  q.rho0 = a.n0.rho[c];
+  q.H0 = a.n0.H[c];
+  q.Z0 = P.reacting ? a.n0.Z[c] : 0.0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) q.v0[i] = a.n0.v[i][c];
+  const Resid &r = CORR ? a.rn : a.rprev;
+  const bool need = CORR || !first;
+  q.rH = need ? r.H[c] : 0.0;
+  q.rZ = (need && P.reacting) ? r.Z[c] : 0.0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) q.rv[i] = need ? r.v[i][c] : 0.0;
+}
+
+// Predictor (corrector = 0): residuals of level n stored for the corrector
 // and the next step; AB2 (Euler on the first step) for H, Z and rho v
 // (Eq 3.1, 3.3, 3.10); T*, rho*, kappa* from the equation of state (Eq 3.6).
-// Corrector: residuals of the predicted level; AM2 with the stored level-n
-// residuals (Eq 3.12, 3.13, 3.18); T, rho, kappa at n+1 (Eq 3.15).
+// Corrector: AM2 with the stored level-n residuals (Eq 3.12, 3.13, 3.18);
+// T, rho, kappa at n+1 (Eq 3.15).
 template <int DIM, int CORR>
-__global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, int first) {
-  CellPos p;
-  if (!cell_of_thread(L, p)) return;
-  const long c = p.c;
-  double RH, RZ, Rv[3];
-  const double dtp0 = P.closed ? *a.dtp0 : 0.0;
-  residuals<DIM>(L, P, a.cur, a.ib, c, dtp0, RH, RZ, Rv);
+__device__ inline void stage_update(const Phys &P, const StageArgs &a, long c, int first, const Centre &q,
+                                    double RH, double RZ, const double Rv[3]) {
   const double dt = P.dt;
-  const double rho0 = a.n0.rho[c];
   double H, Z = 0.0;
   if (!CORR) {
     a.rn.H[c] = RH;
@@ -392,29 +460,27 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
 #pragma unroll
     for (int i = 0; i < DIM; ++i) a.rn.v[i][c] = Rv[i];
     if (first) {
-      H = a.n0.H[c] + dt * RH;
-      if (P.reacting) Z = a.n0.Z[c] + dt * RZ;
+      H = q.H0 + dt * RH;
+      if (P.reacting) Z = q.Z0 + dt * RZ;
 #pragma unroll
-      for (int i = 0; i < DIM; ++i) a.M[i][c] = rho0 * a.n0.v[i][c] + dt * Rv[i];
+      for (int i = 0; i < DIM; ++i) a.M[i][c] = q.rho0 * q.v0[i] + dt * Rv[i];
     } else if (P.var_step) {
       // AB2 for unequal steps: weights 1 + w/2 and -w/2, w = dt / dt_prev
-      H = a.n0.H[c] + dt * (P.ab0 * RH + P.ab1 * a.rprev.H[c]);
-      if (P.reacting) Z = a.n0.Z[c] + dt * (P.ab0 * RZ + P.ab1 * a.rprev.Z[c]);
+      H = q.H0 + dt * (P.ab0 * RH + P.ab1 * q.rH);
+      if (P.reacting) Z = q.Z0 + dt * (P.ab0 * RZ + P.ab1 * q.rZ);
 #pragma unroll
-      for (int i = 0; i < DIM; ++i)
-        a.M[i][c] = rho0 * a.n0.v[i][c] + dt * (P.ab0 * Rv[i] + P.ab1 * a.rprev.v[i][c]);
+      for (int i = 0; i < DIM; ++i) a.M[i][c] = q.rho0 * q.v0[i] + dt * (P.ab0 * Rv[i] + P.ab1 * q.rv[i]);
     } else {
-      H = a.n0.H[c] + dt * (1.5 * RH - 0.5 * a.rprev.H[c]);
-      if (P.reacting) Z = a.n0.Z[c] + dt * (1.5 * RZ - 0.5 * a.rprev.Z[c]);
+      H = q.H0 + dt * (1.5 * RH - 0.5 * q.rH);
+      if (P.reacting) Z = q.Z0 + dt * (1.5 * RZ - 0.5 * q.rZ);
 #pragma unroll
-      for (int i = 0; i < DIM; ++i)
-        a.M[i][c] = rho0 * a.n0.v[i][c] + dt * (1.5 * Rv[i] - 0.5 * a.rprev.v[i][c]);
+      for (int i = 0; i < DIM; ++i) a.M[i][c] = q.rho0 * q.v0[i] + dt * (1.5 * Rv[i] - 0.5 * q.rv[i]);
     }
   } else {
-    H = a.n0.H[c] + 0.5 * dt * (RH + a.rn.H[c]);
-    if (P.reacting) Z = a.n0.Z[c] + 0.5 * dt * (RZ + a.rn.Z[c]);
+    H = q.H0 + 0.5 * dt * (RH + q.rH);
+    if (P.reacting) Z = q.Z0 + 0.5 * dt * (RZ + q.rZ);
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) a.M[i][c] = rho0 * a.n0.v[i][c] + 0.5 * dt * (Rv[i] + a.rn.v[i][c]);
+    for (int i = 0; i < DIM; ++i) a.M[i][c] = q.rho0 * q.v0[i] + 0.5 * dt * (Rv[i] + q.rv[i]);
   }
   const double T = temperature(P, Z, H);
   a.out.H[c] = H;
@@ -422,6 +488,272 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
   a.out.T[c] = T;
   a.out.rho[c] = P.p0 / T;
   a.out.kap[c] = kappa_of(P, T);
+}
+
+// One thread per cell, every field read straight from the padded arrays.
+template <int DIM, int CORR>
+__global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, int first) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  const long c = p.c;
+  double RH, RZ, Rv[3];
+  const double dtp0 = P.closed ? *a.dtp0 : 0.0;
+  const DirectAcc acc{a.cur, a.ib, c, L.s[1], L.s[2], P.has_ib};
+  residuals<DIM>(acc, P, dtp0, RH, RZ, Rv);
+  Centre q;
+  load_centre<DIM, CORR>(P, a, c, first, q);
+  stage_update<DIM, CORR>(P, a, c, first, q, RH, RZ, Rv);
+}
+
+// ---- z-marching 3D stage ------------------------------------------------
+// A block owns a 64 x 4 column of cells and a run of planes; it marches up
+// the planes. The velocity components are read at edge neighbours in all
+// three planes z-1, z, z+1, so they sit in a ring of four LDS planes (three
+// read, one being filled); kappa, H, Z and the x / y face fluxes are read
+// off-centre only within the plane, so they sit in two LDS planes (read,
+// filled); their z-1 / z+1 values and the z face flux come from registers
+// of the thread's own column. The halo tiles go from HBM straight into LDS
+// (16-byte global-to-LDS loads, no registers held), one plane ahead of use
+// (two for the velocity ring), so one barrier per plane suffices and the
+// next plane streams in while this one is computed. Every field is read
+// from HBM once, plus the tile's halo.
+constexpr int kMX = 64, kMY = 4;            // cells of a block's column
+constexpr int kMW = kMX + 4;                // LDS row: x0-2 .. x0+65 (16-byte pairs from an even x)
+constexpr int kMP = kMW * (kMY + 2);        // doubles per LDS plane
+constexpr int kMPairs = kMP / 2;            // 16-byte pairs per plane (one per thread, first kMPairs threads)
+constexpr int kMarchBlocks = 2048;          // target grid (chooses the run of planes)
+static_assert(kMPairs <= kBlock, "one pair per thread");
+
+struct MarchShared {
+  double v[3][4][kMP];  // velocity components, ring of four planes (plane z in slot z & 3)
+  double s[5][2][kMP];  // kappa, H, Z, F_0, F_1: plane z in slot z & 1
+};
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Global-to-LDS copy of one 16-byte pair per lane; lane l of the wavefront
+// writes pairs 64 w + l of the plane (w = the wavefront of the block).
+__device__ inline void pair_to_lds(const double *src, double *plane) {
+  double *dst = plane + 2 * (threadIdx.x & ~63u);
+  __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)dst, 16, 0, 0);
+}
+
+// Accessor of the z-marching kernel (all offsets are compile-time after
+// unrolling: each picks one LDS plane or register).
+struct MarchAcc {
+  static constexpr bool kPhased = true;
+  const MarchShared &sm;
+  int me;                  // this cell in an LDS plane
+  int vm, v0, vp;          // ring slots of planes z-1, z, z+1
+  int sc;                  // slot of the scalar planes
+  double kz[2], sz[2][2];  // own column: kappa and H, Z at z-1, z+1
+  double F2m, F2c;         // z face fluxes below and at the cell
+  double rho_c;
+  __device__ double v(int i, int o0, int o1, int o2) const {
+    const int slot = o2 < 0 ? vm : (o2 > 0 ? vp : v0);
+    return sm.v[i][slot][me + o0 + o1 * kMW];
+  }
+  __device__ double kap(int o0, int o1, int o2) const {
+    if (o2 != 0) return kz[o2 > 0];
+    return sm.s[0][sc][me + o0 + o1 * kMW];
+  }
+  __device__ double s(int f, int o0, int o1, int o2) const {
+    if (o2 != 0) return sz[f][o2 > 0];
+    return sm.s[1 + f][sc][me + o0 + o1 * kMW];
+  }
+  __device__ double F(int d, int o) const {
+    if (d == 0) return sm.s[3][sc][me + o];
+    if (d == 1) return sm.s[4][sc][me + o * kMW];
+    return o < 0 ? F2m : F2c;
+  }
+  __device__ double rho() const { return rho_c; }
+  __device__ double chi() const { return 0.0; }
+  __device__ double v_ib(int) const { return 0.0; }
+  __device__ double Z_ib() const { return 0.0; }
+  __device__ double H_ib() const { return 0.0; }
+};
+
+// Empty asm statements that claim to change their operands: applied at the
+// top of each plane of a march, they keep the compiler from hoisting the
+// work derived from the step constants and the column address out of the
+// plane loop, where it would pin most of the register file for the whole
+// march (recomputing it costs a few instructions per plane).
+__device__ inline void refresh(Phys &P, long &cc, int &me) {
+  asm volatile("" : "+s"(P.ih[0]), "+s"(P.ih[1]), "+s"(P.ih[2]), "+s"(P.Pe), "+s"(P.Pr), "+s"(P.Da), "+s"(P.dt),
+               "+s"(P.p0));
+  asm volatile("" : "+s"(P.sigma), "+s"(P.inv_Fr2), "+s"(P.qs), "+s"(P.S), "+s"(P.k), "+s"(P.Le_F), "+s"(P.Le_O),
+               "+s"(P.N_F));
+  asm volatile("" : "+s"(P.N_O), "+s"(P.fshift), "+s"(P.zeta), "+s"(P.suth_C), "+s"(P.ab0), "+s"(P.ab1));
+  asm volatile("" : "+v"(cc), "+v"(me));
+}
+
+template <int CORR>
+__global__ void __launch_bounds__(kBlock) k_stage_march(Lay L, Phys P, StageArgs a, int first, int ntx, int nty,
+                                                        int tz) {
+  __shared__ MarchShared sm;
+  const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = (int)(b % ntx), rest = (int)(b / ntx);
+  const int by = rest % nty, ch = rest / nty;
+  const int x0 = bx * kMX, y0 = by * kMY;
+  const int z0 = ch * tz, z1 = min(z0 + tz, L.n[2]);
+  if (z0 >= z1) return;
+  const int tid = threadIdx.x;
+  const int lx = tid & (kMX - 1), ly = tid / kMX;
+  const long s2 = L.s[2];
+  // this thread's pair of the halo tile (offset from its plane)
+  const bool hp = tid < kMPairs;
+  const int pr = tid / (kMW / 2), pc = tid - pr * (kMW / 2);
+  const long gp = L.at(x0 - 2 + 2 * pc, y0 - 1 + pr, 0);
+  const int me = (ly + 1) * kMW + lx + 2;
+  const long cc = L.at(x0 + lx, y0 + ly, 0);  // own column at plane 0
+  const double *vs[3] = {a.cur.v[0], a.cur.v[1], a.cur.v[2]};
+  const double *ss[5] = {a.cur.kap, a.cur.H, a.cur.Z, a.cur.F[0], a.cur.F[1]};
+  const double dtp0 = P.closed ? *a.dtp0 : 0.0;
+
+  // prologue: velocity planes z0-1, z0, z0+1; scalar plane z0; own column
+  if (hp) {
+    for (int z = z0 - 1; z <= z0 + 1; ++z)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) pair_to_lds(vs[i] + gp + z * s2, sm.v[i][z & 3]);
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+      if (f != 2 || P.reacting) pair_to_lds(ss[f] + gp + z0 * s2, sm.s[f][z0 & 1]);
+  }
+  double kz[3], Hz[3], Zz[3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const long c = cc + (z0 + dz) * s2;
+    kz[dz + 1] = a.cur.kap[c];
+    Hz[dz + 1] = a.cur.H[c];
+    Zz[dz + 1] = P.reacting ? a.cur.Z[c] : 0.0;
+  }
+  double F2m = a.cur.F[2][cc + (z0 - 1) * s2], F2c = a.cur.F[2][cc + z0 * s2];
+  double rho_c = a.cur.rho[cc + z0 * s2];
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  for (int z = z0; z < z1; ++z) {
+    Phys Pz = P;
+    long ccz = cc;
+    int mez = me;
+    refresh(Pz, ccz, mez);
+    const bool more = z + 1 < z1;
+    // next planes: velocity tiles of z+2 and scalar tiles of z+1 into
+    // their free LDS slots; the own column's kappa, H, Z of z+2, z face
+    // flux and density of z+1
+    double kN = 0.0, HN = 0.0, ZN = 0.0, F2N = 0.0, rhoN = 0.0;
+    if (more) {
+      if (hp) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) pair_to_lds(vs[i] + gp + (z + 2) * s2, sm.v[i][(z + 2) & 3]);
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+          if (f != 2 || P.reacting) pair_to_lds(ss[f] + gp + (z + 1) * s2, sm.s[f][(z + 1) & 1]);
+      }
+      const long cn = ccz + (z + 2) * s2, c1 = ccz + (z + 1) * s2;
+      kN = a.cur.kap[cn];
+      HN = a.cur.H[cn];
+      ZN = P.reacting ? a.cur.Z[cn] : 0.0;
+      F2N = a.cur.F[2][c1];
+      rhoN = a.cur.rho[c1];
+    }
+    const long c = ccz + z * s2;
+    Centre q;
+    load_centre<3, CORR>(Pz, a, c, first, q);
+    {
+      MarchAcc acc{sm, mez, (z - 1) & 3, z & 3, (z + 1) & 3, z & 1, {kz[0], kz[2]}, {{Hz[0], Hz[2]}, {Zz[0], Zz[2]}},
+                   F2m, F2c, rho_c};
+      double RH, RZ, Rv[3];
+      residuals<3>(acc, Pz, dtp0, RH, RZ, Rv);
+      stage_update<3, CORR>(Pz, a, c, first, q, RH, RZ, Rv);
+    }
+    kz[0] = kz[1];
+    kz[1] = kz[2];
+    kz[2] = kN;
+    Hz[0] = Hz[1];
+    Hz[1] = Hz[2];
+    Hz[2] = HN;
+    Zz[0] = Zz[1];
+    Zz[1] = Zz[2];
+    Zz[2] = ZN;
+    F2m = F2c;
+    F2c = F2N;
+    rho_c = rhoN;
+    // the global-to-LDS copies of this step have landed before any
+    // wavefront reads them after the barrier
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
+// The z-marching form covers 3D grids without an immersed body whose
+// planes tile by 64 x 4 (any sides: the ghosts are filled beforehand).
+// ---- LDS-staged 2D stage ----------------------------------------------------
+// One block per 64 x 4 tile: the seven stencil fields' tiles with their
+// one-cell halo go from HBM (or the last-level cache) straight into LDS,
+// the centre-only fields are loaded meanwhile, one barrier, then the same
+// residual arithmetic reads the neighbours from LDS.
+struct Tile2DShared {
+  double t[7][kMP];  // v_0, v_1, kappa, H, Z, F_0, F_1
+};
+
+struct Tile2DAcc {
+  static constexpr bool kPhased = false;
+  const Tile2DShared &sm;
+  int me;
+  const Level &lv;
+  const IB &ib;
+  long c;
+  int has_ib;
+  __device__ double v(int i, int o0, int o1, int) const { return sm.t[i][me + o0 + o1 * kMW]; }
+  __device__ double kap(int o0, int o1, int) const { return sm.t[2][me + o0 + o1 * kMW]; }
+  __device__ double s(int f, int o0, int o1, int) const { return sm.t[3 + f][me + o0 + o1 * kMW]; }
+  __device__ double F(int d, int o) const { return d == 0 ? sm.t[5][me + o] : sm.t[6][me + o * kMW]; }
+  __device__ double rho() const { return lv.rho[c]; }
+  __device__ double chi() const { return (has_ib && ib.chi) ? (double)ib.chi[c] : 0.0; }
+  __device__ double v_ib(int i) const { return ib.v_ib[i] ? ib.v_ib[i][c] : 0.0; }
+  __device__ double Z_ib() const { return ib.Z_ib ? ib.Z_ib[c] : 0.0; }
+  __device__ double H_ib() const { return ib.H_ib ? ib.H_ib[c] : 0.0; }
+};
+
+template <int CORR>
+__global__ void __launch_bounds__(kBlock) k_stage_tile2d(Lay L, Phys P, StageArgs a, int first, int ntx) {
+  __shared__ Tile2DShared sm;
+  const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+  const int x0 = (int)(b % ntx) * kMX, y0 = (int)(b / ntx) * kMY;
+  const int tid = threadIdx.x;
+  if (tid < kMPairs) {
+    const int pr = tid / (kMW / 2), pc = tid - pr * (kMW / 2);
+    const long gp = L.at(x0 - 2 + 2 * pc, y0 - 1 + pr, 0);
+    const double *src[7] = {a.cur.v[0], a.cur.v[1], a.cur.kap, a.cur.H, a.cur.Z, a.cur.F[0], a.cur.F[1]};
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+      if (f != 4 || P.reacting) pair_to_lds(src[f] + gp, sm.t[f]);
+  }
+  const int lx = tid & (kMX - 1), ly = tid / kMX;
+  const long c = L.at(x0 + lx, y0 + ly, 0);
+  Centre q;
+  load_centre<2, CORR>(P, a, c, first, q);
+  const double dtp0 = P.closed ? *a.dtp0 : 0.0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const Tile2DAcc acc{sm, (ly + 1) * kMW + lx + 2, a.cur, a.ib, c, P.has_ib};
+  double RH, RZ, Rv[3];
+  residuals<2>(acc, P, dtp0, RH, RZ, Rv);
+  stage_update<2, CORR>(P, a, c, first, q, RH, RZ, Rv);
+}
+
+// The LDS-staged forms need planes that tile by 64 x 4 (any sides: the
+// ghosts are filled beforehand; 3D: no immersed body) and, for the 16-byte
+// tile copies, stencil fields on 16-byte boundaries (workspace arrays
+// start on 256-byte ones).
+static bool lds_stage_ok(const Lay &L, const Phys &P, const Level &cur) {
+  if (L.n[0] % kMX != 0 || L.n[1] % kMY != 0 || (L.base & 1)) return false;
+  if (L.ndim == 3 && (P.has_ib || L.n[2] < 8)) return false;
+  const double *f[7] = {cur.v[0], cur.v[1], L.ndim == 3 ? cur.v[2] : cur.v[0], cur.kap, cur.H, cur.F[0], cur.F[1]};
+  for (const double *p : f)
+    if ((uintptr_t)p & 15) return false;
+  return !P.reacting || ((uintptr_t)cur.Z & 15) == 0;
 }
 
 hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, const Phys &P,
@@ -436,6 +768,28 @@ hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, 
   a.rn = rn;
   a.ib = ib;
   for (int i = 0; i < 3; ++i) a.M[i] = M[i];
+  if (P.stage_form != 2 && L.ndim == 2 && lds_stage_ok(L, P, cur)) {
+    const int ntx = L.n[0] / kMX;
+    const dim3 g(ntx * (L.n[1] / kMY));
+    if (corrector)
+      hipLaunchKernelGGL((k_stage_tile2d<1>), g, dim3(kBlock), 0, st, L, P, a, first, ntx);
+    else
+      hipLaunchKernelGGL((k_stage_tile2d<0>), g, dim3(kBlock), 0, st, L, P, a, first, ntx);
+    return hipGetLastError();
+  }
+  if (P.stage_form == 1 && L.ndim == 3 && lds_stage_ok(L, P, cur)) {
+    const int ntx = L.n[0] / kMX, nty = L.n[1] / kMY;
+    const int tiles = ntx * nty;
+    int nch = std::max(1, (kMarchBlocks + tiles - 1) / tiles);
+    int tz = std::max(8, (L.n[2] + nch - 1) / nch);
+    nch = (L.n[2] + tz - 1) / tz;
+    const dim3 g(tiles * nch);
+    if (corrector)
+      hipLaunchKernelGGL((k_stage_march<1>), g, dim3(kBlock), 0, st, L, P, a, first, ntx, nty, tz);
+    else
+      hipLaunchKernelGGL((k_stage_march<0>), g, dim3(kBlock), 0, st, L, P, a, first, ntx, nty, tz);
+    return hipGetLastError();
+  }
   dim3 g = grid_for(L), b(kBX, kBY);
   if (L.ndim == 3) {
     if (corrector)
@@ -961,10 +1315,10 @@ __global__ void __launch_bounds__(kBlock) k_p0_heat(Lay L, Phys P, Level lv, dou
   double v = 0.0;
   if (cell_of_thread(L, p)) {
     double adv;
-    scalar_terms<DIM>(L, P, lv, lv.H, p.c, adv, v);
+    scalar_terms<DIM>(L, P, lv, 0, p.c, adv, v);
     if (P.reacting) {
       double difZ;
-      scalar_terms<DIM>(L, P, lv, lv.Z, p.c, adv, difZ);
+      scalar_terms<DIM>(L, P, lv, 1, p.c, adv, difZ);
       v += ((-1.0 / P.S - 1.0) * theta_eps(P, lv.Z[p.c]) + 1.0) * difZ;
     }
   }

@@ -51,6 +51,7 @@ struct Phys {
   double gamma;     // ratio of specific heats (p0_closed)
   double zeta;      // (gamma - 1)/(gamma qs): factor of the d_t p0 source (Eq 3.4b)
   double suth_C;    // > 0: Sutherland's law for kappa (Eq 4.12); 0: kappa = T^sigma
+  int stage_form;   // stage kernel form (host side): 0 LDS tiles in 2D, one thread per cell in 3D; 1 LDS; 2 direct
   // unequal steps (adaptive time step): AB2 weights of R^n, R^{n-1}; BDF2
   // d_t rho = (bd0 (rho^{new} - rho^n) - bd2 (rho^n - rho^{n-1})) / dt
   int var_step;
@@ -268,6 +269,7 @@ struct PoissonWS {
   hipEvent_t *tev;         // in-step timing of the finest down kernel: event pairs
   int *tk;                 // CG iteration of each timed launch; -1: not a full-work launch
   int tcap, tcount, tsolve0;
+  int twhich;              // timed kernel class (see lm_kernel_timing)
 };
 
 // Plans the hierarchy and carves (or sizes, base == nullptr) the solver

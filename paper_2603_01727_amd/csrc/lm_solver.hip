@@ -1055,14 +1055,15 @@ static void launch_3d(int nu, bool down, Fused3DArgs<T> &a, hipStream_t st, bool
       hipExtLaunchKernelGGL(k, g, bl, 0, st, e0, e1, 0, a);
     else
       hipLaunchKernelGGL(k, g, bl, 0, st, a);
-  } else if (extra) {
-    auto k = nu == 1 ? (bd ? &k_mg_up3d<T, 1, 1, true> : &k_mg_up3d<T, 1, 1, false>)
-                     : (bd ? &k_mg_up3d<T, 2, 1, true> : &k_mg_up3d<T, 2, 1, false>);
-    hipLaunchKernelGGL(k, g, bl, 0, st, a);
   } else {
-    auto k = nu == 1 ? (bd ? &k_mg_up3d<T, 1, 0, true> : &k_mg_up3d<T, 1, 0, false>)
-                     : (bd ? &k_mg_up3d<T, 2, 0, true> : &k_mg_up3d<T, 2, 0, false>);
-    hipLaunchKernelGGL(k, g, bl, 0, st, a);
+    auto k = extra ? (nu == 1 ? (bd ? &k_mg_up3d<T, 1, 1, true> : &k_mg_up3d<T, 1, 1, false>)
+                              : (bd ? &k_mg_up3d<T, 2, 1, true> : &k_mg_up3d<T, 2, 1, false>))
+                   : (nu == 1 ? (bd ? &k_mg_up3d<T, 1, 0, true> : &k_mg_up3d<T, 1, 0, false>)
+                              : (bd ? &k_mg_up3d<T, 2, 0, true> : &k_mg_up3d<T, 2, 0, false>));
+    if (e0)
+      hipExtLaunchKernelGGL(k, g, bl, 0, st, e0, e1, 0, a);
+    else
+      hipLaunchKernelGGL(k, g, bl, 0, st, a);
   }
 }
 
@@ -1257,6 +1258,17 @@ static CoarseArgs<T> coarse_args(PoissonWS &ws, void *z, const double *r) {
   return ca;
 }
 
+// In-step timing: events for this launch when it is the next timed launch
+// of the selected kernel class (0 finest down, 1 finest up, 2 CG update);
+// the caller records the iteration after launching.
+static bool timed_launch(const PoissonWS &ws, int which, hipEvent_t &e0, hipEvent_t &e1) {
+  e0 = e1 = nullptr;
+  if (ws.twhich != which || ws.tcount >= ws.tcap) return false;
+  e0 = ws.tev[2 * ws.tcount];
+  e1 = ws.tev[2 * ws.tcount + 1];
+  return true;
+}
+
 // V-cycle of iteration k on b = r_k (finest), writing z = z_k.
 template <int DIM, typename T>
 static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
@@ -1273,23 +1285,17 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
     if (fused_level(ws, l)) {
       const void *b = l == 0 ? (k >= 1 ? (const void *)rprev : (const void *)r) : ws.lev[l].b;
       Down2DArgs<T> a = down_args<T>(ws, l, k, b, xin, cg.x, cg.pnew, cg.q, ws.r[k & 1]);
-      const bool timed = l == 0 && ws.tcount < ws.tcap;
-      if (timed) {
-        launch_nu<T>(ws, l, nu, a, st, ws.tev[2 * ws.tcount], ws.tev[2 * ws.tcount + 1]);
-        ws.tk[ws.tcount++] = k;
-      } else {
-        launch_nu<T>(ws, l, nu, a, st);
-      }
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const bool timed = l == 0 && timed_launch(ws, 0, e0, e1);
+      launch_nu<T>(ws, l, nu, a, st, e0, e1);
+      if (timed) ws.tk[ws.tcount++] = k;
     } else if (fused3d(ws, l)) {
       Fused3DArgs<T> a = f3_args<T>(ws, l, l == 0 ? (const void *)r : ws.lev[l].b, l == 0);
       a.xout = xin;
-      const bool timed = l == 0 && ws.tcount < ws.tcap;
-      if (timed) {
-        launch_3d<T>(nu, true, a, st, false, ws.tev[2 * ws.tcount], ws.tev[2 * ws.tcount + 1]);
-        ws.tk[ws.tcount++] = k;
-      } else {
-        launch_3d<T>(nu, true, a, st);
-      }
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const bool timed = l == 0 && timed_launch(ws, 0, e0, e1);
+      launch_3d<T>(nu, true, a, st, false, e0, e1);
+      if (timed) ws.tk[ws.tcount++] = k;
     } else {
       dim3 g = grid_for(L);
       const T *rl = ws.vc ? (const T *)ws.rho[l] : nullptr;
@@ -1333,7 +1339,10 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
       a.w = ws.w;
       a.part_rz = ws.part_rz;
       a.np = (int)blocks3d(L, ti3(nu, false, extra));
-      launch_3d<T>(nu, false, a, st, extra);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const bool timed = l == 0 && timed_launch(ws, 1, e0, e1);
+      launch_3d<T>(nu, false, a, st, extra, e0, e1);
+      if (timed) ws.tk[ws.tcount++] = k;
     } else {
       dim3 g = grid_for(L);
       const T *rl = ws.vc ? (const T *)ws.rho[l] : nullptr;
@@ -1382,8 +1391,15 @@ static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
       a.rold = ws.r[(k - 1) & 1];
       a.rnew = ws.r[k & 1];
       a.np_rz = np_rz_of(ws);
-      hipLaunchKernelGGL((k_cgcg_update<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks,
-                         (const double *)ws.w, (const double *)ws.s[k & 1], ws.s[(k + 1) & 1]);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const bool timed = timed_launch(ws, 2, e0, e1);
+      if (timed)
+        hipExtLaunchKernelGGL((k_cgcg_update<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, e0, e1, 0, a,
+                              kRedBlocks, (const double *)ws.w, (const double *)ws.s[k & 1], ws.s[(k + 1) & 1]);
+      else
+        hipLaunchKernelGGL((k_cgcg_update<DIM, T>), dim3(kRedBlocks), dim3(kBlock), 0, st, a, kRedBlocks,
+                           (const double *)ws.w, (const double *)ws.s[k & 1], ws.s[(k + 1) & 1]);
+      if (timed) ws.tk[ws.tcount++] = k;
     }
     vcycle<DIM, T>(st, ws, k, a);
     return;
@@ -1453,10 +1469,11 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   }
   const SolverScalars &h = *ws.host_sc;
   *iters = h.iters;
-  // timed launches of this solve that did the full work: iterations 1 ..
-  // iters (iteration 0 has no CG update; later ones found the solve done)
+  // timed launches of this solve that did the full work of a CG iteration
+  // with a previous direction: iterations 2 .. iters (iteration 0 has no
+  // CG update, iteration 1 no old p and s; later ones found the solve done)
   for (int q = ws.tsolve0; q < ws.tcount; ++q)
-    if (ws.tk[q] < 1 || ws.tk[q] > h.iters) ws.tk[q] = -1;
+    if (ws.tk[q] < 2 || ws.tk[q] > h.iters) ws.tk[q] = -1;
   *relres = h.cc > 0 ? std::sqrt(h.rr / h.cc) : 0.0;
   *converged = h.done && !h.nonconv;
   // mean of the solution (the stored pressure is zero-mean)

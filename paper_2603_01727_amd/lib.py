@@ -82,7 +82,7 @@ EXPORTS = {
     "lm_get_fields": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(lm_fields), C.c_int]),
     "lm_get_dt": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lm_bench_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
-    "lm_kernel_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "lm_kernel_timing": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "lm_kernel_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "lm_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "lm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),

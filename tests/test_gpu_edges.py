@@ -106,3 +106,38 @@ def test_noncubic_fused_3d():
     errs = compare(st, s.get(device=False))
     print(errs, s.stats, flush=True)
     _check(errs)
+
+
+def _reacting_3d_case(n, seed=23):
+    """Periodic 3D flame-sheet box: smooth mixture fraction across the
+    stoichiometric value (Z in [0, 3], the sheet at Z = 1), H near its
+    uniform value, unequal Lewis numbers (the Z diffusion, its H coupling
+    and T(Z, H) all in play)."""
+    from workloads.ics import QS_C3
+    L = (2 * math.pi,) * 3
+    rng = np.random.default_rng(seed)
+    S = 1.0 / 0.055 - 1.0
+    w = fourier_temperature(n, L, rng, 2, 1.0, m=16)        # in [1, 2]
+    Z = 3.0 * (w - w.min()) / (w.max() - w.min())
+    H = 1.0 / QS_C3 + 1.0 + 0.02 * (fourier_temperature(n, L, rng, 2, 1.0, m=16) - 1.5)
+    v = solenoidal_velocity(n, L, rng, 2, 0.1, m=16)
+    params = dict(Re=150.0, Pr=0.7, Le_F=1.3, Le_O=0.9, reacting=1, S=S, qs=QS_C3, eps=0.5, tol=1e-3,
+                  p0=1.0, dt=0.02)
+    case = Case("react3d", 3, tuple(n), L, (("periodic", "periodic"),) * 3, params, None, v, Z=Z)
+    case.H = H
+    return case
+
+
+@pytest.mark.parametrize("n", [(64, 8, 16), (24, 12, 10)])
+def test_reacting_3d_matches_oracle(n):
+    """The 3D stage with the flame sheet (Z diffusion at unequal Lewis
+    numbers, its H coupling, T(Z, H))."""
+    case = _reacting_3d_case(n)
+    print("reacting 3d", n, flush=True)
+    o, st = oracle_for(case)
+    st = o.run(st, 3)
+    s = gpu_for(case)
+    s.step(3)
+    errs = compare(st, s.get(device=False))
+    print(errs, s.stats, flush=True)
+    _check(errs)
