@@ -375,6 +375,20 @@ def summarize_trace(db_path):
         print(f"{name[:58]:58s} grid {grid:9d} n {len(d):5d} mean {sum(d) / len(d):9.2f}  full {len(fw):5d} "
               f"mean {sum(fw) / len(fw):9.2f}  total {sum(d) / 1e3:8.3f}  vgpr {r['vgpr']:3d} lds {r['lds']:6d} "
               f"scratch {r['scratch']}")
+    # the single-reduction CG update by iteration: the first launch after a
+    # solve's initialisation kernel is iteration 1 (no old p, s: fewer bytes)
+    seq = db.execute("select name, end - start from kernels order by start").fetchall()
+    it, by_k = 0, {}
+    for name, dur in seq:
+        if "k_cg_init" in name:
+            it = 0
+        elif "k_cgcg_update" in name:
+            it += 1
+            by_k.setdefault(min(it, 2), []).append(dur * 1e-3)
+    for k, d in sorted(by_k.items()):
+        fw = _full_work(d)
+        print(f"k_cgcg_update iteration {'1' if k == 1 else '>= 2'}: n {len(d)}, full-work n {len(fw)} "
+              f"mean {sum(fw) / len(fw):.2f} us")
 
 
 def _pmc_rows(db_path, counter):
@@ -388,8 +402,12 @@ def _pmc_rows(db_path, counter):
 def summarize_pmc(fetch_db, write_db, traffic_out=None):
     f = _groups(_pmc_rows(fetch_db, "FETCH_SIZE"))
     w = _groups(_pmc_rows(write_db, "WRITE_SIZE"))
-    cf = [v for (n, _), vs in f.items() if n.startswith(COPY_KERNEL) for v in vs]
-    cw = [v for (n, _), vs in w.items() if n.startswith(COPY_KERNEL) for v in vs]
+    # the calibration copy: the copy-kernel dispatch group that moved the
+    # most (other copies of the run are small staging transfers)
+    def calib(groups):
+        cand = [vs for (n, _), vs in groups.items() if n.startswith(COPY_KERNEL)]
+        return max(cand, key=lambda vs: sum(vs) / len(vs)) if cand else []
+    cf, cw = calib(f), calib(w)
     if not cf or not cw:
         raise SystemExit("no copy-calibration dispatch in the databases (run bench.py with --copy-calibration)")
     kib = COPY_BYTES / 1024

@@ -32,10 +32,31 @@ __device__ inline unsigned xcd_remap(unsigned b, unsigned nb) {
   return (b % kXCD) * q + b / kXCD;
 }
 
+// 3D launches (grid z = planes) walk up the planes inside patches of a few
+// tile rows across the whole x extent: consecutive blocks cover one patch
+// plane after another, so the planes above and below that a stencil reads
+// were loaded one patch plane earlier and are still in L2; with the XCD
+// remap a patch's column of planes stays on one XCD.
+constexpr unsigned kPatchRows = 8;
 __device__ inline bool cell_of_thread(const Lay &L, CellPos &p) {
   const unsigned b = xcd_remap(linear_block(), num_blocks());
-  const unsigned bx = b % gridDim.x, byz = b / gridDim.x;
-  const unsigned by = byz % gridDim.y, bz = byz / gridDim.y;
+  unsigned bx, by, bz;
+  if (gridDim.z > 1) {
+    const unsigned tx = gridDim.x, ty = gridDim.y, nz = gridDim.z;
+    unsigned py = kPatchRows;
+    while (ty % py) py >>= 1;  // patch rows divide the tile rows
+    const unsigned pp = tx * py;  // blocks of one patch plane
+    const unsigned patch = b / (pp * nz), rem = b - patch * (pp * nz);
+    bz = rem / pp;
+    const unsigned t = rem - bz * pp;
+    by = patch * py + t / tx;
+    bx = t % tx;
+  } else {
+    bx = b % gridDim.x;
+    const unsigned byz = b / gridDim.x;
+    by = byz % gridDim.y;
+    bz = byz / gridDim.y;
+  }
   p.i = bx * kBX + threadIdx.x;
   p.j = by * kBY + threadIdx.y;
   p.k = bz;
@@ -91,11 +112,20 @@ __device__ inline double block_max(double v, double *sh) {
 // participates); valid in thread 0. Partial sums are always consumed by a
 // later kernel: no grid-wide fence is ever needed.
 __device__ inline double sum_partials(const double *part, unsigned nb, double *sh) {
-  const int t = linear_tid();
-  const int nt = blockDim.x * blockDim.y * blockDim.z;
-  double s = 0.0;
-  for (unsigned q = t; q < nb; q += nt) s += part[q];
-  return block_sum(s, sh);
+  const unsigned t = linear_tid();
+  const unsigned nt = blockDim.x * blockDim.y * blockDim.z;
+  // four independent running sums per thread (loads in flight together),
+  // combined in a fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  unsigned q = t;
+  for (; q + 3 * nt < nb; q += 4 * nt) {
+    s0 += part[q];
+    s1 += part[q + nt];
+    s2 += part[q + 2 * nt];
+    s3 += part[q + 3 * nt];
+  }
+  for (; q < nb; q += nt) s0 += part[q];
+  return block_sum((s0 + s1) + (s2 + s3), sh);
 }
 
 // ---- flame sheet: T(Z, H), section 3.5 -------------------------------------

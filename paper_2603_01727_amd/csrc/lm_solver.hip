@@ -275,9 +275,11 @@ struct CGArgs {
   const double *rho;      // density of beta = 1/rho_f; NULL: beta = 1
 };
 
-// x = x0; r_0 = c - L x0 with c = -(b - mean(b) - outflow shift); ||c||^2 partials.
+// x = x0; r_0 = c - L x0 with c = -(b - mean(b) - outflow shift); ||c||^2
+// partials, one per block (one thread per cell: the stencil of x0 reads
+// planes a patch plane apart, still in L2).
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
+__global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a, double *partials) {
   __shared__ double sh[kBlock / 64];
   SolverScalars *sc = a.sc;
   if (a.rho && sc->rho_bad) {  // invalid density: the solve ends at once
@@ -288,11 +290,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
     return;
   }
   double cc = 0.0;
-  const double mb = sc->mean_b, oc = sc->outflow_c;
-  for (int tile = blockIdx.x; tile < ntiles_of(a.L); tile += gridDim.x) {
-    int i, j, k;
-    if (!tile_cell(a.L, tile, i, j, k)) continue;
-    const long c = a.L.at(i, j, k);
+  CellPos p;
+  if (cell_of_thread(a.L, p)) {
+    const int i = p.i, j = p.j, k = p.k;
+    const long c = p.c;
+    const double mb = sc->mean_b, oc = sc->outflow_c;
     const double xv = a.x0 ? a.x0[c] : 0.0;
     a.x[c] = xv;
     double bb = a.b[c] - mb;
@@ -313,10 +315,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a) {
       Lx = dg * xv - nbs;
     }
     a.rnew[c] = cv - Lx;
-    cc += cv * cv;
+    cc = cv * cv;
   }
   const double s = block_sum(cc, sh);
-  if (linear_tid() == 0) a.part_cc[blockIdx.x] = s;
+  if (linear_tid() == 0) partials[linear_block()] = s;
+}
+
+// Folds nb per-block partials into gridDim.x partials, each the fixed-order
+// sum of a contiguous run.
+__global__ void __launch_bounds__(kBlock) k_fold_partials(const double *in, long nb, double *out) {
+  __shared__ double sh[kBlock / 64];
+  const long per = (nb + gridDim.x - 1) / gridDim.x;
+  const long q0 = (long)blockIdx.x * per, q1 = q0 + per < nb ? q0 + per : nb;
+  double s = 0.0;
+  for (long q = q0 + threadIdx.x; q < q1; q += blockDim.x) s += in[q];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // Convergence test on r_{k-1}; beta_k; p_k = z_{k-1} + beta_k p_{k-1};
@@ -513,13 +527,19 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_sum_x(Lay L, const double *x, double *part) {
   __shared__ double sh[kBlock / 64];
-  double s = 0.0;
-  for (int tile = blockIdx.x; tile < ntiles_of(L); tile += gridDim.x) {
-    int i, j, k;
-    if (!tile_cell(L, tile, i, j, k)) continue;
-    s += x[L.at(i, j, k)];
+  // four tiles' loads in flight per trip, four running sums combined in a
+  // fixed order
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  const int nt = ntiles_of(L);
+  for (int t0 = blockIdx.x; t0 < nt; t0 += 4 * gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tile = t0 + u * gridDim.x;
+      int i, j, k;
+      if (tile < nt && tile_cell(L, tile, i, j, k)) s[u] += x[L.at(i, j, k)];
+    }
   }
-  const double r = block_sum(s, sh);
+  const double r = block_sum((s[0] + s[1]) + (s[2] + s[3]), sh);
   if (linear_tid() == 0) part[blockIdx.x] = r;
 }
 
@@ -1452,7 +1472,9 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   ws.tsolve0 = ws.tcount;
   hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cg_init<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_cg_init<DIM>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, a, ws.partials);
+  hipLaunchKernelGGL(k_fold_partials, dim3(kRedBlocks), dim3(kBlock), 0, st, (const double *)ws.partials,
+                     nblocks_for(ws.lay), ws.part_cc);
   vcycle<DIM, T>(st, ws, 0, a);
   int k = 1;
   int batch = expect > 0 ? expect + 1 : 4;
