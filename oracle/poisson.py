@@ -19,6 +19,14 @@ b, dividing by the eigenvalues (the constant mode, eigenvalue 0, is
 dropped: that removes mean(b) and fixes the mean of P at 0) and
 transforming back. With a face coefficient beta the augmented matrix is
 factored by sparse LU.
+
+On a stretched grid the differences of Eq 3.21 use the local spacings and
+the operator is symmetric only after weighting each cell's row by its
+volume: K = Delta V A has face coefficients area_f / (distance between the
+two centres). The solve takes K P = Delta V (b - lam) with the constraint
+sum(Delta V P) = 0 (the discrete integral of P, Eq 3.22, vanishes), i.e. the
+augmented system [K dV; dV^T 0][P; lam] = [dV b; 0], whose lam is the
+volume-weighted mean of b.
 """
 from __future__ import annotations
 
@@ -39,13 +47,13 @@ def face_grad(g: Grid, P, d):
     """delta_1 P / delta_1 x_d on the n_d + 1 faces normal to d, with periodic
     wrap on periodic directions and zero on boundary faces otherwise."""
     ax = g.axis(d)
-    h = g.h[d]
+    dfc = g.dfc[d]                              # h on a uniform grid
     if g.periodic(d):
         Pm = np.roll(P, 1, axis=ax)             # cell f-1 for face f = 0..n-1
-        inner = (P - Pm) / h
+        inner = (P - Pm) / g.along(d, dfc[:-1])
         first = np.take(inner, [0], axis=ax)
         return np.concatenate([inner, first], axis=ax)
-    grad = np.diff(P, axis=ax) / h
+    grad = np.diff(P, axis=ax) / g.along(d, dfc[1:-1])
     shp = list(P.shape)
     shp[ax] = 1
     z = np.zeros(shp, dtype=P.dtype)
@@ -59,7 +67,7 @@ def laplacian(g: Grid, P, beta=None):
         G = face_grad(g, P, d)
         if beta is not None:
             G = G * beta[d]
-        out = out + (g.plus(G, d) - g.minus(G, d)) / g.h[d]
+        out = out + (g.plus(G, d) - g.minus(G, d)) / g.along(d, g.wid[d][1:-1])
     return out
 
 
@@ -128,7 +136,7 @@ class PoissonSolver:
     def __init__(self, g: Grid, beta=None, method=None):
         self.g = g
         self.beta = beta
-        self.transform = beta is None and method != "lu"
+        self.transform = beta is None and method != "lu" and not g.stretched
         self.fft = self.transform and g.all_periodic
         if self.transform:
             self.per_axes = [g.axis(d) for d in range(g.ndim) if g.periodic(d)]
@@ -151,10 +159,14 @@ class PoissonSolver:
         # assemble A column by column from its action on face differences
         idx = np.arange(N).reshape(g.shape)
         rows, cidx, vals = [], [], []
+        vol = g.cell_volumes() if g.stretched else None
         for d in range(g.ndim):
             ax = g.axis(d)
             h2 = g.h[d] ** 2
             n = g.n[d]
+            if g.stretched:
+                # face areas of the d-faces: cell volume over the d-width
+                area = vol / g.along(d, g.wid[d][1:-1])
             for f in range(n + 1):
                 # face f between cells f-1 and f along d
                 if f == 0 or f == n:
@@ -167,8 +179,12 @@ class PoissonSolver:
                     left = np.take(idx, f - 1, axis=ax)
                 right = np.take(idx, f % n, axis=ax)
                 w = np.ones(left.shape) / h2
+                if g.stretched:
+                    # K = dV A: area_f / (distance between the two centres)
+                    w = np.take(area, f % n, axis=ax) / g.dfc[d][f]
                 if self.beta is not None:
-                    w = np.take(self.beta[d], f, axis=ax) / h2
+                    bf = np.take(self.beta[d], f, axis=ax)
+                    w = w * bf if g.stretched else bf / h2
                 l, r, w = left.ravel(), right.ravel(), np.asarray(w).ravel()
                 # flux w (P_r - P_l) leaves cell l through its high face and
                 # enters cell r through its low face
@@ -179,7 +195,7 @@ class PoissonSolver:
         cidx = np.concatenate(cidx)
         vals = np.concatenate(vals)
         A = sp.coo_matrix((vals, (rows, cidx)), shape=(N, N)).tocsr()
-        one = sp.csr_matrix(np.ones((N, 1)))
+        one = sp.csr_matrix((vol.ravel() if g.stretched else np.ones(N)).reshape(N, 1))
         aug = sp.bmat([[A, one], [one.T, None]])
         del cols
         return aug
@@ -201,6 +217,14 @@ class PoissonSolver:
 
     def solve(self, b):
         g = self.g
+        if g.stretched:
+            vol = g.cell_volumes()
+            rhs = np.concatenate([(vol * b).ravel(), [0.0]])
+            if np.iscomplexobj(rhs):
+                x = self.lu.solve(rhs.real) + 1j * self.lu.solve(rhs.imag)
+            else:
+                x = self.lu.solve(rhs)
+            return x[: b.size].reshape(g.shape), x[b.size]
         lam = np.mean(b)
         if self.transform:
             if np.iscomplexobj(b):

@@ -17,7 +17,7 @@ from typing import Optional
 import numpy as np
 
 from .flame import FlameParams, le_eps, n_eps, n_prime_eps, temperature, enthalpy_from_T
-from .grid import Grid, fill_ghosts, field_rules
+from .grid import Grid, face_extrap_coeffs, fill_ghosts, field_rules
 from .poisson import PoissonSolver
 
 
@@ -161,7 +161,7 @@ class Oracle:
         T2 = temperature(Zs if Zs is not None else 0.0, H, fp)
         rho = self.p.p0 / T2
         # enclosed system: the mass of the initial state is conserved (Eq 2.40)
-        self.mass = np.sum(rho) * g.dV
+        self.mass = g.integral(rho)
         v = [_real_or_complex(a) for a in v]
         if F is None:
             F = self.face_average_flux([rho * a for a in v])
@@ -179,8 +179,9 @@ class Oracle:
         g, p = self.g, self.p
         kap = p.kappa(st.T)
         nu = max(p.Pr, 1.0, 1.0 / p.Le_F, 1.0 / p.Le_O) * kap / (p.Pe * st.rho)
-        rate = sum(np.abs(st.v[d]) / g.h[d] for d in range(g.ndim))
-        rate = rate + 2.0 * nu * sum(1.0 / g.h[d] ** 2 for d in range(g.ndim))
+        wid = [g.along(d, g.wid[d][1:-1]) for d in range(g.ndim)]   # h on a uniform grid
+        rate = sum(np.abs(st.v[d]) / wid[d] for d in range(g.ndim))
+        rate = rate + 2.0 * nu * sum(1.0 / wid[d] ** 2 for d in range(g.ndim))
         chi = self.ib.get("chi")
         if chi is not None:
             rate = rate + chi * nu / p.Da_ib
@@ -198,10 +199,16 @@ class Oracle:
             Mp = g.pad(M[d])
             fill_ghosts(g, Mp, [(("periodic",),) * 2 if g.periodic(e) else (("extrap",),) * 2
                                 for e in range(g.ndim)])
-            G = 0.5 * (g.S(Mp, d, None) + g.S(Mp, d, g.e(d)))
+            G = self._face_interp(Mp, d)
             self._boundary_faces(G, d, M[d], None)
             F.append(G)
         return F
+
+    def _face_interp(self, Ap, d):
+        """Eq 3.20 (n = 1) from the two cell centres to each d-face (the
+        two-point mean on a uniform grid)."""
+        g = self.g
+        return (g.along(d, g.wlo[d]) * g.S(Ap, d, None) + g.along(d, g.whi[d]) * g.S(Ap, d, g.e(d)))
 
     def _boundary_faces(self, G, d, Md, corr):
         """Overwrite boundary faces normal to d with the prescribed flux."""
@@ -225,7 +232,12 @@ class Oracle:
                 else:
                     m1, m2, m3 = (np.take(Md, 0, axis=ax), np.take(Md, 1, axis=ax),
                                   np.take(Md, 2, axis=ax))
-                G[g.face_index(d, f)] = (15.0 * m1 - 10.0 * m2 + 3.0 * m3) / 8.0 + (0.0 if corr is None else corr)
+                if g.faces[d] is None:
+                    Gf = (15.0 * m1 - 10.0 * m2 + 3.0 * m3) / 8.0
+                else:
+                    A, B, C = face_extrap_coeffs(g, d, side)
+                    Gf = A * m1 + B * m2 + C * m3
+                G[g.face_index(d, f)] = Gf + (0.0 if corr is None else corr)
 
     def padded_fields(self, st: State):
         """Ghost-filled copies of v, Z, H and T (T from Z, H at ghosts)."""
@@ -292,13 +304,15 @@ class Oracle:
         adv = 0.0
         dif = 0.0
         for d in range(g.ndim):
-            h = g.h[d]
-            grad = (g.S(phip, d, g.e(d)) - g.S(phip, d, None)) / h
-            kf = 0.5 * (g.S(kapp, d, None) + g.S(kapp, d, g.e(d)))
+            dfc = g.along(d, g.dfc[d])               # centre distance across each face
+            wid = g.along(d, g.wid[d][1:-1])         # cell width
+            grad = (g.S(phip, d, g.e(d)) - g.S(phip, d, None)) / dfc
+            kf = self._face_interp(kapp, d)
             Fg = F[d] * grad
+            # face to centre: the centroid is midway between its faces
             adv = adv + 0.5 * (g.plus(Fg, d) + g.minus(Fg, d))
             q = kf * grad
-            dif = dif + (g.plus(q, d) - g.minus(q, d)) / h
+            dif = dif + (g.plus(q, d) - g.minus(q, d)) / wid
         return adv, dif
 
     def _momentum_terms(self, vp, kapp, F):
@@ -314,39 +328,41 @@ class Oracle:
         conv = [0.0] * nd
         visc = [0.0] * nd
         for d in range(nd):
-            h = g.h[d]
-            kf = 0.5 * (g.S(kapp, d, None) + g.S(kapp, d, g.e(d)))
+            dfc = g.along(d, g.dfc[d])
+            wid = g.along(d, g.wid[d][1:-1])
+            wlo, whi = g.along(d, g.wlo[d]), g.along(d, g.whi[d])
+            kf = self._face_interp(kapp, d)
             # derivative matrix D[k][c] = D_k v_c on d-faces
             D = [[None] * nd for _ in range(nd)]
             for c in range(nd):
                 for k in range(nd):
                     if k == d:
-                        D[k][c] = (g.S(vp[c], d, g.e(d)) - g.S(vp[c], d, None)) / h
+                        D[k][c] = (g.S(vp[c], d, g.e(d)) - g.S(vp[c], d, None)) / dfc
                     else:
-                        hk = g.h[k]
+                        d2k = g.along(k, g.d2[k])    # Eq 3.21, n = 2, at the cells on either side
                         offp = g.e(k)
                         offm = g.e(k, -1)
                         offdp = tuple(a + b for a, b in zip(g.e(d), g.e(k)))
                         offdm = tuple(a + b for a, b in zip(g.e(d), g.e(k, -1)))
-                        cl = (g.S(vp[c], d, offp) - g.S(vp[c], d, offm)) / (2.0 * hk)
-                        cr = (g.S(vp[c], d, offdp) - g.S(vp[c], d, offdm)) / (2.0 * hk)
-                        D[k][c] = 0.5 * (cl + cr)
+                        cl = (g.S(vp[c], d, offp) - g.S(vp[c], d, offm)) / d2k
+                        cr = (g.S(vp[c], d, offdp) - g.S(vp[c], d, offdm)) / d2k
+                        D[k][c] = wlo * cl + whi * cr
             div = sum(D[k][k] for k in range(nd))
             for i in range(nd):
-                vf = 0.5 * (g.S(vp[i], d, None) + g.S(vp[i], d, g.e(d)))
+                vf = self._face_interp(vp[i], d)
                 fl = F[d] * vf
-                conv[i] = conv[i] + (g.plus(fl, d) - g.minus(fl, d)) / h
+                conv[i] = conv[i] + (g.plus(fl, d) - g.minus(fl, d)) / wid
                 tau = D[d][i] + D[i][d]
                 if i == d:
                     tau = tau - (2.0 / 3.0) * div
                 tau = kf * tau
-                visc[i] = visc[i] + (g.plus(tau, d) - g.minus(tau, d)) / h
+                visc[i] = visc[i] + (g.plus(tau, d) - g.minus(tau, d)) / wid
         return conv, visc
 
     def closed_p0(self, T):
         """Thermodynamic pressure of an enclosed system from the equation of
         state integrated over the domain, p0 = m / sum(dV / T) (Eq 2.40)."""
-        return self.mass / (np.sum(1.0 / T) * self.g.dV)
+        return self.mass / self.g.integral(1.0 / T)
 
     def ddt_p0(self, p_new, hist, dt_new=None, dt_old=None):
         """d_t p0 at the level whose pressure is p_new, from the levels before
@@ -383,16 +399,20 @@ class Oracle:
         if p.reacting:
             _, difZ = self._scalar_terms(Zp, kapp, st.F)
             dif = dif + n_prime_eps(st.Z, self.fp) * difZ
-        heat = float(np.sum(dif)) * g.dV
+        heat = float(g.integral(dif))
         flux = 0.0
         for d in range(g.ndim):
-            area = g.dV / g.h[d]
             for s in (0, 1):
                 if g.bc[d][s] != "inflow":
                     continue
                 vn = np.broadcast_to(np.asarray(g.bvalue(d, s, "v", d), dtype=float),
                                      tuple(g.shape[a] for a in range(g.ndim) if a != g.axis(d)))
-                flux += (1.0 if s == 1 else -1.0) * float(np.sum(vn)) * area
+                if not g.stretched:
+                    flux += (1.0 if s == 1 else -1.0) * float(np.sum(vn)) * (g.dV / g.h[d])
+                else:
+                    # face areas of the side: products of the other widths
+                    area = np.take(g.cell_volumes(), 0, axis=g.axis(d)) / g.wid[d][1]
+                    flux += (1.0 if s == 1 else -1.0) * float(np.sum(vn * area))
         return p.gamma / g.volume * (p.qs / p.Pe * heat - st.p0 * flux)
 
     def balance_ddt_p0(self, st: State):
@@ -402,7 +422,8 @@ class Oracle:
         non-reacting map T = qs (H - 1) and R_H = R_H|0 + zeta d_t p0 / rho
         (Eq 3.4), solved for d_t p0. (A first-order start, d_t p0 = 0 or a
         one-sided difference, leaves a first-order error in p0.)"""
-        p, dV = self.p, self.g.dV
+        p, g = self.p, self.g
+        dV = g.cell_volumes() if g.stretched else g.dV
         RH = self.residuals(st, 0.0)["H"]
         w = (st.p0 ** 2 / self.mass) * dV * p.qs / st.T ** 2
         A = np.sum(w * RH)
@@ -473,15 +494,15 @@ class Oracle:
             Mp = g.pad(M[d])
             fill_ghosts(g, Mp, [(("periodic",),) * 2 if g.periodic(e) else (("extrap",),) * 2
                                 for e in range(g.ndim)])
-            Gd = 0.5 * (g.S(Mp, d, None) + g.S(Mp, d, g.e(d)))
+            Gd = self._face_interp(Mp, d)
             self._boundary_faces(Gd, d, M[d], None)
             G.append(Gd)
         # outflow correction: close the global mass balance exactly
         out_sides = [(d, s) for d in range(g.ndim) for s in (0, 1)
                      if not g.periodic(d) and g.bc[d][s] == "outflow"]
         if out_sides:
-            div = sum((g.plus(G[d], d) - g.minus(G[d], d)) / g.h[d] for d in range(g.ndim))
-            total = float(np.sum((div + src) * g.dV))
+            div = sum((g.plus(G[d], d) - g.minus(G[d], d)) / g.along(d, g.wid[d][1:-1]) for d in range(g.ndim))
+            total = float(g.integral(div + src))
             area = 0.0
             for d, s in out_sides:
                 area += g.volume / g.L[d]
@@ -490,7 +511,7 @@ class Oracle:
                 f = g.n[d] if s == 1 else 0
                 sign = -1.0 if s == 1 else 1.0
                 G[d][g.face_index(d, f)] += sign * c
-        b = sum((g.plus(G[d], d) - g.minus(G[d], d)) / g.h[d] for d in range(g.ndim)) + src
+        b = sum((g.plus(G[d], d) - g.minus(G[d], d)) / g.along(d, g.wid[d][1:-1]) for d in range(g.ndim)) + src
         P, lam = self.poisson.solve(b)
         self.stats[stage + "_compat"] = lam
         Pp = g.pad(P)
@@ -498,15 +519,14 @@ class Oracle:
         F = []
         v = []
         for d in range(g.ndim):
-            h = g.h[d]
-            dP1 = (g.S(Pp, d, g.e(d)) - g.S(Pp, d, None)) / h
+            dP1 = (g.S(Pp, d, g.e(d)) - g.S(Pp, d, None)) / g.along(d, g.dfc[d])
             Fd = G[d] - dP1
             if not g.periodic(d):
                 for s in (0, 1):
                     f = 0 if s == 0 else g.n[d]
                     Fd[g.face_index(d, f)] = G[d][g.face_index(d, f)]
             F.append(Fd)
-            dP2 = (g.S(Pp, None, g.e(d)) - g.S(Pp, None, g.e(d, -1))) / (2.0 * h)
+            dP2 = (g.S(Pp, None, g.e(d)) - g.S(Pp, None, g.e(d, -1))) / g.along(d, g.d2[d])
             v.append((M[d] - dP2) / rho_new)
         return P, F, v, b
 
