@@ -58,12 +58,20 @@ enum { LM_BETA_ONE = 0, LM_BETA_INV_RHO = 1 };  /* Poisson face coefficient form
 enum { LM_HOST = 0, LM_DEVICE = 1 };  /* where caller arrays live           */
 
 /* Grid: ndim in {2,3}; n[d] interior cells and L[d] length per direction
- * (n[2] = 1, L[2] ignored in 2D); bc[d][0] / bc[d][1] the low / high side. */
+ * (n[2] = 1, L[2] ignored in 2D); bc[d][0] / bc[d][1] the low / high side.
+ * faces[d] (host, may be NULL): the n[d] + 1 face coordinates of a
+ * stretched direction, strictly increasing from 0 to L[d] (section 3.2.1:
+ * the operators of Eq 3.20-3.21 take the local spacings; each cell centre
+ * is the midpoint of its faces, ghost cells mirror the first interior cell
+ * at a wall). Copied at init, not kept. Stretched grids: 2D, no outflow
+ * side, no adjoint, the step's constant-coefficient Poisson operator only
+ * (poisson_beta LM_BETA_ONE), p0_closed 0 or 1; otherwise LM_EUNSUPPORTED. */
 typedef struct {
   int ndim;
   int n[3];
   double L[3];
   int bc[3][2];
+  const double *faces[3];
 } lm_grid;
 
 /* Dimensionless parameters (section 2.6, Eq 2.42-2.50; section 4.1):

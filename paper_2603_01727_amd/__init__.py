@@ -63,7 +63,8 @@ class Solver:
 
     Parameters follow ``lm_params`` of include/lowmach.h. ``bc`` is a list per
     direction of (low, high) side kinds: "periodic", "slip", "noslip",
-    "inflow", "outflow".
+    "inflow", "outflow". ``faces`` (optional) gives per direction None or the
+    n + 1 face coordinates of a stretched direction (``lm_grid.faces``).
     """
 
     def __init__(self, n: Sequence[int], L: Sequence[float], bc=None, *, Re: float, Pr: float = 0.7,
@@ -73,7 +74,8 @@ class Solver:
                  precision: str = "fp64", poisson_rtol: float = 1e-10, poisson_maxit: int = 200,
                  mg_nu: int = 2, with_ib: bool = False, with_adjoint: bool = False,
                  variable_coefficient: bool = False, p0_closed: bool = False, gamma: float = 1.4,
-                 sutherland_C: float = 0.0, dt_tol: float = 0.0, device: str = "cuda:0", stream=None):
+                 sutherland_C: float = 0.0, dt_tol: float = 0.0, faces=None, device: str = "cuda:0",
+                 stream=None):
         import torch
         self.torch = torch
         self.lib = _L.load()
@@ -90,6 +92,13 @@ class Solver:
             g.L[d] = float(L[d]) if d < ndim else 1.0
             for s in range(2):
                 g.bc[d][s] = _L.SIDE[bc[d][s]] if d < ndim else 0
+        self._faces = []                  # host copies alive through lm_init_grid
+        for d in range(ndim):
+            f = None if faces is None else faces[d]
+            if f is not None:
+                f = np.ascontiguousarray(f, dtype=np.float64)
+                self._faces.append(f)
+                g.faces[d] = f.ctypes.data
         p = _L.lm_params(Re=Re, Pr=Pr, sigma=sigma, inv_Fr2=inv_Fr2, reacting=int(reacting), S=S, qs=qs,
                          eps=eps, tol=tol, Le_F=Le_F, Le_O=Le_O, Da_ib=Da_ib, p0=p0, dt=dt, cfl=cfl,
                          precision=_L.PRECISION[precision],

@@ -56,6 +56,11 @@ struct lm_ctx {
   double pc_err;         // its predictor-corrector estimate
   int pc_used;           // 1 if that estimate decided the next step
   int have_star;         // the predicted level of the last step is readable
+  // stretched grid (section 3.2.1): host cell widths per direction, the
+  // packed device spacing arrays of the explicit kernels
+  int stretched;
+  std::vector<double> wid[3];
+  double *met_dev;
 };
 
 namespace {
@@ -111,7 +116,62 @@ bool valid_grid(const lm_grid *g, const char **err) {
     *err = "2D grids need n[2] == 1";
     return false;
   }
+  for (int d = 0; d < g->ndim; ++d) {
+    const double *f = g->faces[d];
+    if (!f) continue;
+    bool ok = std::fabs(f[0]) <= 1e-14 * g->L[d] && std::fabs(f[g->n[d]] - g->L[d]) <= 1e-12 * g->L[d];
+    for (int q = 0; q < g->n[d] && ok; ++q) ok = f[q + 1] > f[q];
+    if (!ok) {
+      *err = "faces[d] must hold n[d] + 1 strictly increasing values from 0 to L[d]";
+      return false;
+    }
+  }
   return true;
+}
+
+// Cell widths of every direction (stretched grids; uniform directions get
+// L/n) from the caller's face coordinates, copied.
+void setup_metric(lm_ctx *c) {
+  const lm_grid &g = c->grid;
+  c->stretched = 0;
+  for (int d = 0; d < g.ndim; ++d) c->stretched = c->stretched || g.faces[d] != nullptr;
+  for (int d = 0; d < 3; ++d) {
+    c->wid[d].clear();
+    if (!c->stretched || d >= g.ndim) continue;
+    c->wid[d].resize(g.n[d]);
+    for (int q = 0; q < g.n[d]; ++q)
+      c->wid[d][q] = g.faces[d] ? g.faces[d][q + 1] - g.faces[d][q] : g.L[d] / g.n[d];
+  }
+  for (int d = 0; d < 3; ++d) c->grid.faces[d] = nullptr;  // not kept
+  c->pws.met = c->stretched;
+}
+
+// Packed spacing arrays of the explicit kernels (the layout of met_view)
+// and the Eq 3.28 weights of the mirrored pressure ghost per side.
+std::vector<double> metric_arrays(lm_ctx *c) {
+  std::vector<double> out;
+  for (int d = 0; d < c->grid.ndim; ++d) {
+    const std::vector<double> &w = c->wid[d];
+    const int n = (int)w.size();
+    const bool per = c->bnd.periodic[d] != 0;
+    std::vector<double> wp(n + 2);
+    for (int q = 0; q < n; ++q) wp[q + 1] = w[q];
+    wp[0] = per ? w[n - 1] : w[0];        // ghosts: the wrapped cell, or the mirrored first cell
+    wp[n + 1] = per ? w[0] : w[n - 1];
+    for (int p = 0; p < n + 2; ++p) out.push_back(1.0 / wp[p]);
+    for (int f = 0; f <= n; ++f) out.push_back(1.0 / (0.5 * (wp[f] + wp[f + 1])));
+    for (int f = 0; f <= n; ++f) out.push_back(wp[f + 1] / (wp[f] + wp[f + 1]));
+    for (int f = 0; f <= n; ++f) out.push_back(wp[f] / (wp[f] + wp[f + 1]));
+    for (int i = 0; i < n; ++i) out.push_back(1.0 / (0.5 * wp[i] + wp[i + 1] + 0.5 * wp[i + 2]));
+    for (int s = 0; s < 2; ++s) {
+      const double a = s == 0 ? w[0] : w[n - 1], b = s == 0 ? w[1] : w[n - 2], e = s == 0 ? w[2] : w[n - 3];
+      const double x0 = -0.5 * a, x1 = 0.5 * a, x2 = a + 0.5 * b, x3 = a + b + 0.5 * e;
+      c->phys.gx[d][s][0] = (x2 - x0) * (x3 - x0) / ((x2 - x1) * (x3 - x1));
+      c->phys.gx[d][s][1] = (x1 - x0) * (x3 - x0) / ((x1 - x2) * (x3 - x2));
+      c->phys.gx[d][s][2] = (x1 - x0) * (x2 - x0) / ((x1 - x3) * (x2 - x3));
+    }
+  }
+  return out;
 }
 
 bool valid_params(const lm_params *p, const char **err) {
@@ -238,6 +298,20 @@ void setup_phys(lm_ctx *c) {
 // Carves every device array (or only sizes them when cv.base == nullptr).
 bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   const int nd = c->grid.ndim;
+  c->met_dev = nullptr;
+  if (c->stretched) {
+    bool outflow = false;
+    for (int d = 0; d < nd; ++d)
+      for (int s = 0; s < 2; ++s) outflow = outflow || c->grid.bc[d][s] == LM_SIDE_OUTFLOW;
+    if (nd != 2 || outflow || c->prm.with_adjoint || c->prm.poisson_beta != LM_BETA_ONE || c->prm.p0_closed == 2) {
+      if (err)
+        *err = "stretched grids: 2D, no outflow side, no adjoint, poisson_beta LM_BETA_ONE, p0_closed 0 or 1";
+      return false;
+    }
+    long m = 0;
+    for (int d = 0; d < nd; ++d) m += 5L * c->grid.n[d] + 5;
+    c->met_dev = (double *)cv.take((size_t)m * 8);
+  }
   if (c->prm.p0_closed) {
     // enclosed (1): periodic or wall sides; semi-enclosed (2, Eq 2.38):
     // inflow sides too; never an outflow side (its flux closes the mass)
@@ -315,8 +389,13 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   c->ad_cur = 0;
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = c->phys.h[d];
-  return poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision != LM_FP64, c->prm.precision == LM_MIXED_FLEXIBLE,
-                      c->prm.mg_nu > 0 ? c->prm.mg_nu : 2, c->prm.poisson_beta == LM_BETA_INV_RHO, err);
+  if (!poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision != LM_FP64, c->prm.precision == LM_MIXED_FLEXIBLE,
+                    c->prm.mg_nu > 0 ? c->prm.mg_nu : 2, c->prm.poisson_beta == LM_BETA_INV_RHO || c->stretched,
+                    err))
+    return false;
+  c->phys.met = c->met_dev;
+  c->phys.vol = c->pws.vol;
+  return true;
 }
 
 void setup_layout(lm_ctx *c) {
@@ -385,6 +464,7 @@ lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t
   c->prm = *params;
   setup_phys(c);
   setup_layout(c);
+  setup_metric(c);
   Carver cv{nullptr, 0};
   bool ok = carve(c, cv, &err);
   delete c;
@@ -412,6 +492,7 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
   c->st = (hipStream_t)stream;
   setup_phys(c);
   setup_layout(c);
+  setup_metric(c);
   char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
   Carver cv{base, 0};
   if (!carve(c, cv, &err)) {
@@ -445,6 +526,16 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
   if (e != hipSuccess) {
     lm_destroy(c);
     return init_fail(LM_EHIP, std::string("coarse-grid set-up: ") + hipGetErrorString(e));
+  }
+  if (c->stretched) {
+    const std::vector<double> m = metric_arrays(c);
+    e = hipMemcpyAsync(c->met_dev, m.data(), m.size() * 8, hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = poisson_set_metric(c->st, c->pws, c->wid[0].data(), c->wid[1].data());
+    if (e != hipSuccess) {
+      lm_destroy(c);
+      return init_fail(LM_EHIP, std::string("stretched-grid set-up: ") + hipGetErrorString(e));
+    }
   }
   *out = c;
   return LM_OK;
@@ -556,7 +647,7 @@ static lm_status finish_level(lm_ctx *c, Level &lv, const lm_fields *f, int mem)
       if ((s = copy_in(c, f->F[d], lv.F[d], d, mem)) != LM_OK) return s;
     }
   } else {
-    HIPCHK(c, launch_face_flux(c->st, c->lay, c->bnd, c->sides, lv, c->M));
+    HIPCHK(c, launch_face_flux(c->st, c->lay, c->bnd, c->sides, lv, c->M, c->phys.met));
   }
   return LM_OK;
 }
@@ -846,8 +937,8 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
 
 lm_status lm_project(lm_ctx *c, lm_project_args *a) {
   if (!c || !a || !a->b) return fail(c, LM_EINVAL, "NULL argument");
-  if (a->rho && !c->pws.vc_cap)
-    return fail(c, LM_EUNSUPPORTED, "a density needs params.poisson_beta = LM_BETA_INV_RHO");
+  if (a->rho && (!c->pws.vc_cap || c->stretched))
+    return fail(c, LM_EUNSUPPORTED, "a density needs params.poisson_beta = LM_BETA_INV_RHO (uniform grids)");
   lm_status s = copy_in(c, a->b, c->b, -1, a->mem);
   if (s != LM_OK) return s;
   const Lay &L = c->lay;
@@ -855,15 +946,15 @@ lm_status lm_project(lm_ctx *c, lm_project_args *a) {
     if ((s = copy_in(c, a->rho, c->pws.rho64, -1, a->mem)) != LM_OK) return s;
     HIPCHK(c, poisson_set_beta(c->st, c->pws));  // an invalid density ends the solve at once
   }
-  HIPCHK(c, launch_mean(c->st, L, c->b, c->pws.partials, c->pws.sc));
+  HIPCHK(c, launch_mean(c->st, L, c->b, c->pws.partials, c->pws.sc, c->phys.vol, c->phys.volume));
   int iters = 0, conv = 0;
   double relres = 0;
   const double rtol = a->rtol > 0 ? a->rtol : c->prm.poisson_rtol;
-  c->pws.vc = a->rho != nullptr;
+  c->pws.vc = c->pws.met || a->rho != nullptr;
   // a standalone solve: zero start in solver scratch, the state untouched
   const hipError_t e = poisson_solve(c->st, c->pws, c->b, nullptr, rtol, c->prm.poisson_maxit, 0, &iters,
                                      &relres, &conv);
-  c->pws.vc = 0;
+  c->pws.vc = c->pws.met;
   HIPCHK(c, e);
   if (a->rho && c->pws.host_sc->rho_bad) return fail(c, LM_EINVAL, "rho must be positive and finite");
   a->iters = iters;
@@ -1088,7 +1179,8 @@ extern "C" lm_status lm_kinetic_energy(lm_ctx *c, double *ke) {
   Level &lv = c->lev[c->icur];
   double dV = 1.0;
   for (int d = 0; d < c->grid.ndim; ++d) dV *= c->phys.h[d];
-  if (c->grid.ndim != 2) return fail(c, LM_EUNSUPPORTED, "kinetic energy implemented for 2D");
+  if (c->grid.ndim != 2 || c->stretched)
+    return fail(c, LM_EUNSUPPORTED, "kinetic energy implemented for uniform 2D grids");
   HIPCHK(c, launch_ke(c->st, c->lay, lv.rho, lv.v, dV, c->pws.partials, c->dscalar));
   HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, 8, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1185,7 +1277,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   for (double *z : {Hb_star, vb_star[0], vb_star[1], Fb_star[0], Fb_star[1], Fb_n[0], Fb_n[1]})
     HIPCHK(c, hipMemsetAsync(z, 0, ab, c->st));
   auto adjoint_solve = [&](double *rhs, double *out) -> lm_status {
-    HIPCHK(c, launch_mean(c->st, L, rhs, c->pws.partials, c->pws.sc));
+    HIPCHK(c, launch_mean(c->st, L, rhs, c->pws.partials, c->pws.sc, c->phys.vol, c->phys.volume));
     int iters = 0, conv = 0;
     double relres = 0.0;
     HIPCHK(c, poisson_solve(c->st, c->pws, rhs, nullptr, c->prm.poisson_rtol, c->prm.poisson_maxit, 0, &iters,
@@ -1373,6 +1465,8 @@ extern "C" lm_status lm_project_static(const lm_grid *grid, const lm_params *par
                                        lm_project_args *a) {
   if (!grid || !params || !a || !a->b) return init_fail(LM_EINVAL, "NULL argument");
   if (a->rho) return init_fail(LM_EUNSUPPORTED, "lm_project_static solves the beta = 1 form only");
+  if (grid->faces[0] || grid->faces[1] || grid->faces[2])
+    return init_fail(LM_EUNSUPPORTED, "lm_project_static takes uniform grids only");
   if (a->mem != LM_HOST && a->mem != LM_DEVICE) return init_fail(LM_EINVAL, "mem must be LM_HOST or LM_DEVICE");
   const char *bad = nullptr;
   if (!valid_grid(grid, &bad) || !valid_params(params, &bad)) return init_fail(LM_EINVAL, bad);
@@ -1430,7 +1524,7 @@ extern "C" lm_status lm_project_static(const lm_grid *grid, const lm_params *par
     src = staging;
   }
   STATIC_HIPCHK(launch_pack(st, L, src, b, -1));
-  STATIC_HIPCHK(launch_mean(st, L, b, ws.partials, ws.sc));
+  STATIC_HIPCHK(launch_mean(st, L, b, ws.partials, ws.sc, nullptr, 0.0));
   int iters = 0, conv = 0;
   double relres = 0.0;
   const double rtol = a->rtol > 0 ? a->rtol : params->poisson_rtol;

@@ -128,6 +128,24 @@ __device__ inline double sum_partials(const double *part, unsigned nb, double *s
   return block_sum((s0 + s1) + (s2 + s3), sh);
 }
 
+// ---- stretched grids (section 3.2.1) ---------------------------------------
+// Spacing arrays of direction d on a stretched grid, packed direction after
+// direction: inverse cell widths on the padded cells (n + 2), then per face
+// between padded cells p and p + 1 (n + 1 each) the inverse distance
+// between the two centres and the Eq 3.20 (n = 1) weights of the lower and
+// the upper centre, then per interior cell the inverse distance between its
+// two neighbours' centres (Eq 3.21, n = 2; n entries). Interior cell i is
+// padded cell i + 1; its high face is face i + 1, its low face face i.
+struct MetView {
+  const double *iwid, *idfc, *wlo, *whi, *id2;
+};
+__device__ inline MetView met_view(const double *met, const Lay &L, int d) {
+  const double *p = met;
+  for (int e = 0; e < d; ++e) p += 5 * (long)L.n[e] + 5;
+  const long n = L.n[d];
+  return {p, p + n + 2, p + 2 * n + 3, p + 3 * n + 4, p + 4 * n + 5};
+}
+
 // ---- flame sheet: T(Z, H), section 3.5 -------------------------------------
 
 __device__ inline double lncosh(double x) {

@@ -253,7 +253,18 @@ hipError_t launch_ghosts(hipStream_t st, const Lay &L, const Bnd &B, const Phys 
 // (o0, o1, o2) in cells from the cell the residual is taken at, so one body
 // of arithmetic serves both the direct kernel (padded arrays in HBM) and the
 // z-marching 3D kernel (LDS planes and registers).
+// Spacings of a uniform grid: the inverse distance across a face (lo = 0:
+// the high face, -1: the low face), the inverse cell width, the inverse
+// distance between the centres on either side along k (Eq 3.21, n = 2),
+// and the interpolation from two centres to their face (Eq 3.20, n = 1).
+#define LM_UNIFORM_SPACING                                                                   \
+  __device__ static double ihf(const Phys &P, int d, int) { return P.ih[d]; }                \
+  __device__ static double ihc(const Phys &P, int d) { return P.ih[d]; }                     \
+  __device__ static double i2h(const Phys &P, int k) { return 0.5 * P.ih[k]; }               \
+  __device__ static double interp(int, int, double a, double b) { return 0.5 * (a + b); }
+
 struct DirectAcc {
+  LM_UNIFORM_SPACING
   static constexpr bool kPhased = false;
   const Level &lv;
   const IB &ib;
@@ -271,6 +282,31 @@ struct DirectAcc {
   __device__ double v_ib(int i) const { return ib.v_ib[i] ? ib.v_ib[i][c] : 0.0; }
   __device__ double Z_ib() const { return ib.Z_ib ? ib.Z_ib[c] : 0.0; }
   __device__ double H_ib() const { return ib.H_ib ? ib.H_ib[c] : 0.0; }
+};
+
+// Stretched 2D grid: the direct accessor with the local spacings of the
+// cell at interior coordinates q.
+struct StretchedAcc {
+  static constexpr bool kPhased = false;
+  DirectAcc g;
+  MetView m[2];
+  int q[2];
+  __device__ double v(int i, int o0, int o1, int o2) const { return g.v(i, o0, o1, o2); }
+  __device__ double kap(int o0, int o1, int o2) const { return g.kap(o0, o1, o2); }
+  __device__ double s(int f, int o0, int o1, int o2) const { return g.s(f, o0, o1, o2); }
+  __device__ double F(int d, int o) const { return g.F(d, o); }
+  __device__ double rho() const { return g.rho(); }
+  __device__ double chi() const { return g.chi(); }
+  __device__ double v_ib(int i) const { return g.v_ib(i); }
+  __device__ double Z_ib() const { return g.Z_ib(); }
+  __device__ double H_ib() const { return g.H_ib(); }
+  __device__ double ihf(const Phys &, int d, int lo) const { return m[d].idfc[q[d] + 1 + lo]; }
+  __device__ double ihc(const Phys &, int d) const { return m[d].iwid[q[d] + 1]; }
+  __device__ double i2h(const Phys &, int k) const { return m[k].id2[q[k]]; }
+  __device__ double interp(int d, int lo, double x, double y) const {
+    const int f = q[d] + 1 + lo;
+    return m[d].wlo[f] * x + m[d].whi[f] * y;
+  }
 };
 
 // Scheduling fence between the phases of a residual, for accessors that
@@ -292,26 +328,27 @@ __device__ inline void face_stress(const A &a, const Phys &P, int lo, int d, dou
   int o[3] = {0, 0, 0}, q[3] = {0, 0, 0};
   o[d] = lo;
   q[d] = lo + 1;
-  const double kf = 0.5 * (a.kap(o[0], o[1], o[2]) + a.kap(q[0], q[1], q[2]));
+  const double kf = a.interp(d, lo, a.kap(o[0], o[1], o[2]), a.kap(q[0], q[1], q[2]));
   double Dn[3];       // D_d v_c
   double Dkd[3];      // D_k v_d (k != d)
   double Dkk[3];      // D_k v_k (k != d)
+  const double ihd = a.ihf(P, d, lo);
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) Dn[c] = (a.v(c, q[0], q[1], q[2]) - a.v(c, o[0], o[1], o[2])) * P.ih[d];
+  for (int c = 0; c < DIM; ++c) Dn[c] = (a.v(c, q[0], q[1], q[2]) - a.v(c, o[0], o[1], o[2])) * ihd;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     if (k == d) continue;
-    const double i2h = 0.5 * P.ih[k];  // 1/(2h): centred differences
+    const double i2h = a.i2h(P, k);  // 1/(2h): centred differences
     int op[3] = {o[0], o[1], o[2]}, om[3] = {o[0], o[1], o[2]};
     int qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
     op[k] += 1;
     om[k] -= 1;
     qp[k] += 1;
     qm[k] -= 1;
-    Dkd[k] = 0.5 * ((a.v(d, op[0], op[1], op[2]) - a.v(d, om[0], om[1], om[2])) * i2h +
-                    (a.v(d, qp[0], qp[1], qp[2]) - a.v(d, qm[0], qm[1], qm[2])) * i2h);
-    Dkk[k] = 0.5 * ((a.v(k, op[0], op[1], op[2]) - a.v(k, om[0], om[1], om[2])) * i2h +
-                    (a.v(k, qp[0], qp[1], qp[2]) - a.v(k, qm[0], qm[1], qm[2])) * i2h);
+    Dkd[k] = a.interp(d, lo, (a.v(d, op[0], op[1], op[2]) - a.v(d, om[0], om[1], om[2])) * i2h,
+                      (a.v(d, qp[0], qp[1], qp[2]) - a.v(d, qm[0], qm[1], qm[2])) * i2h);
+    Dkk[k] = a.interp(d, lo, (a.v(k, op[0], op[1], op[2]) - a.v(k, om[0], om[1], om[2])) * i2h,
+                      (a.v(k, qp[0], qp[1], qp[2]) - a.v(k, qm[0], qm[1], qm[2])) * i2h);
   }
   double div = 0.0;
 #pragma unroll
@@ -335,13 +372,14 @@ __device__ inline void scalar_terms(const A &a, const Phys &P, int f, double &ad
     p[d] = 1;
     m[d] = -1;
     const double sc = a.s(f, 0, 0, 0);
-    const double gp = (a.s(f, p[0], p[1], p[2]) - sc) * P.ih[d];
-    const double gm = (sc - a.s(f, m[0], m[1], m[2])) * P.ih[d];
+    const double gp = (a.s(f, p[0], p[1], p[2]) - sc) * a.ihf(P, d, 0);
+    const double gm = (sc - a.s(f, m[0], m[1], m[2])) * a.ihf(P, d, -1);
     const double kc = a.kap(0, 0, 0);
-    const double kp = 0.5 * (kc + a.kap(p[0], p[1], p[2]));
-    const double km = 0.5 * (a.kap(m[0], m[1], m[2]) + kc);
+    const double kp = a.interp(d, 0, kc, a.kap(p[0], p[1], p[2]));
+    const double km = a.interp(d, -1, a.kap(m[0], m[1], m[2]), kc);
+    // face to centre: the centroid lies midway between its faces
     adv = adv + 0.5 * (a.F(d, 0) * gp + a.F(d, -1) * gm);
-    dif = dif + (kp * gp - km * gm) * P.ih[d];
+    dif = dif + (kp * gp - km * gm) * a.ihc(P, d);
   }
 }
 
@@ -390,7 +428,7 @@ __device__ inline void residuals(const A &a, const Phys &P, double dtp0, double 
     face_stress<DIM>(a, P, -1, d, tm);
     phase_fence<A>();
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) visc_all[i] = visc_all[i] + (tp[i] - tm[i]) * P.ih[d];
+    for (int i = 0; i < DIM; ++i) visc_all[i] = visc_all[i] + (tp[i] - tm[i]) * a.ihc(P, d);
   }
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
@@ -402,9 +440,9 @@ __device__ inline void residuals(const A &a, const Phys &P, double dtp0, double 
       int p[3] = {0, 0, 0}, m[3] = {0, 0, 0};
       p[d] = 1;
       m[d] = -1;
-      const double flp = a.F(d, 0) * (0.5 * (vc + a.v(i, p[0], p[1], p[2])));
-      const double flm = a.F(d, -1) * (0.5 * (a.v(i, m[0], m[1], m[2]) + vc));
-      conv = conv + (flp - flm) * P.ih[d];
+      const double flp = a.F(d, 0) * a.interp(d, 0, vc, a.v(i, p[0], p[1], p[2]));
+      const double flm = a.F(d, -1) * a.interp(d, -1, a.v(i, m[0], m[1], m[2]), vc);
+      conv = conv + (flp - flm) * a.ihc(P, d);
     }
     double r = -conv + (P.Pr / P.Pe) * visc;
     if (i == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
@@ -490,8 +528,9 @@ __device__ inline void stage_update(const Phys &P, const StageArgs &a, long c, i
   a.out.kap[c] = kappa_of(P, T);
 }
 
-// One thread per cell, every field read straight from the padded arrays.
-template <int DIM, int CORR>
+// One thread per cell, every field read straight from the padded arrays
+// (MET: a stretched 2D grid, local spacings).
+template <int DIM, int CORR, bool MET = false>
 __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, int first) {
   CellPos p;
   if (!cell_of_thread(L, p)) return;
@@ -499,7 +538,12 @@ __global__ void __launch_bounds__(kBlock) k_stage(Lay L, Phys P, StageArgs a, in
   double RH, RZ, Rv[3];
   const double dtp0 = P.closed ? *a.dtp0 : 0.0;
   const DirectAcc acc{a.cur, a.ib, c, L.s[1], L.s[2], P.has_ib};
-  residuals<DIM>(acc, P, dtp0, RH, RZ, Rv);
+  if constexpr (MET) {
+    const StretchedAcc sa{acc, {met_view(P.met, L, 0), met_view(P.met, L, 1)}, {p.i, p.j}};
+    residuals<DIM>(sa, P, dtp0, RH, RZ, Rv);
+  } else {
+    residuals<DIM>(acc, P, dtp0, RH, RZ, Rv);
+  }
   Centre q;
   load_centre<DIM, CORR>(P, a, c, first, q);
   stage_update<DIM, CORR>(P, a, c, first, q, RH, RZ, Rv);
@@ -541,6 +585,7 @@ __device__ inline void pair_to_lds(const double *src, double *plane) {
 // Accessor of the z-marching kernel (all offsets are compile-time after
 // unrolling: each picks one LDS plane or register).
 struct MarchAcc {
+  LM_UNIFORM_SPACING
   static constexpr bool kPhased = true;
   const MarchShared &sm;
   int me;                  // this cell in an LDS plane
@@ -698,6 +743,7 @@ struct Tile2DShared {
 };
 
 struct Tile2DAcc {
+  LM_UNIFORM_SPACING
   static constexpr bool kPhased = false;
   const Tile2DShared &sm;
   int me;
@@ -748,7 +794,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_tile2d(Lay L, Phys P, StageArg
 // tile copies, stencil fields on 16-byte boundaries (workspace arrays
 // start on 256-byte ones).
 static bool lds_stage_ok(const Lay &L, const Phys &P, const Level &cur) {
-  if (L.n[0] % kMX != 0 || L.n[1] % kMY != 0 || (L.base & 1)) return false;
+  if (P.met || L.n[0] % kMX != 0 || L.n[1] % kMY != 0 || (L.base & 1)) return false;
   if (L.ndim == 3 && (P.has_ib || L.n[2] < 8)) return false;
   const double *f[7] = {cur.v[0], cur.v[1], L.ndim == 3 ? cur.v[2] : cur.v[0], cur.kap, cur.H, cur.F[0], cur.F[1]};
   for (const double *p : f)
@@ -791,6 +837,13 @@ hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, 
     return hipGetLastError();
   }
   dim3 g = grid_for(L), b(kBX, kBY);
+  if (P.met) {  // stretched 2D grid
+    if (corrector)
+      hipLaunchKernelGGL((k_stage<2, 1, true>), g, b, 0, st, L, P, a, first);
+    else
+      hipLaunchKernelGGL((k_stage<2, 0, true>), g, b, 0, st, L, P, a, first);
+    return hipGetLastError();
+  }
   if (L.ndim == 3) {
     if (corrector)
       hipLaunchKernelGGL((k_stage<3, 1>), g, b, 0, st, L, P, a, first);
@@ -808,6 +861,15 @@ hipError_t launch_stage(hipStream_t st, int corrector, int first, const Lay &L, 
 // ---------------------------------------------------------------------------
 // Poisson right-hand side and projection
 // ---------------------------------------------------------------------------
+
+// Eq 3.20 (n = 1) from the centres of two neighbouring cells (lower,
+// upper) along d to their face f (see met_view): the two-point mean on a
+// uniform grid (met NULL).
+__device__ inline double face_interp(const double *met, const Lay &L, int d, int f, double lo, double hi) {
+  if (!met) return 0.5 * (lo + hi);
+  const MetView m = met_view(met, L, d);
+  return m.wlo[f] * lo + m.whi[f] * hi;
+}
 
 // Prescribed normal mass flux on the boundary face of side (d, s) next to
 // cell p; outflow sides extrapolate the cell momentum quadratically to the
@@ -855,9 +917,9 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
       const double *Md = a.M[d];
       const int q = coord(p, d);
       const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
-      const double Gh = nh >= 0 ? 0.5 * (Md[c] + Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
-      const double Gl = nl >= 0 ? 0.5 * (Md[nl] + Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
-      div = div + (Gh - Gl) * P.ih[d];
+      const double Gh = nh >= 0 ? face_interp(P.met, L, d, q + 1, Md[c], Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
+      const double Gl = nl >= 0 ? face_interp(P.met, L, d, q, Md[nl], Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
+      div = div + (Gh - Gl) * (P.met ? met_view(P.met, L, d).iwid[q + 1] : P.ih[d]);
     }
     double drho;
     if (a.bdf2)
@@ -868,7 +930,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
     const double src = a.S_m ? drho - a.S_m[c] : drho;
     const double b = div + src;
     a.b[c] = b;
-    part = b;
+    part = P.met ? b * P.vol[c] : b;   // stretched: the integral of b
   }
   const double s = block_sum(part, sh);
   if (linear_tid() == 0) a.partials[linear_block()] = s;
@@ -922,7 +984,7 @@ hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P,
   else
     hipLaunchKernelGGL(k_rhs<2>, g, bl, 0, st, L, B, P, sd, a);
   hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
-                     (double)L.ncells(), a.has_outflow, a.dV, a.outflow_area, sc);
+                     P.met ? P.volume : (double)L.ncells(), a.has_outflow, a.dV, a.outflow_area, sc);
   return hipGetLastError();
 }
 
@@ -956,27 +1018,34 @@ __global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides 
     double xp, xm;
     if (nh >= 0) {
       xp = x ? x[nh] : 0.0;
-      const double G = 0.5 * (Md[c] + Md[nh]);
-      a.F[d][c] = G - (xp - xc) * P.ih[d];
+      const double G = face_interp(P.met, L, d, q + 1, Md[c], Md[nh]);
+      a.F[d][c] = G - (xp - xc) * (P.met ? met_view(P.met, L, d).idfc[q + 1] : P.ih[d]);
     } else {
       double G = boundary_flux(L, B, sd, Md, p, d, 1);
       if (B.kind[d][1] == LM_SIDE_OUTFLOW) G -= oc;
       a.F[d][c] = G;
-      xp = x ? 3.0 * xc - 3.0 * x[c - sdd] + x[c - 2 * sdd] : 0.0;
+      if (!P.met)
+        xp = x ? 3.0 * xc - 3.0 * x[c - sdd] + x[c - 2 * sdd] : 0.0;
+      else  // Eq 3.28 with the stretched positions
+        xp = x ? P.gx[d][1][0] * xc + P.gx[d][1][1] * x[c - sdd] + P.gx[d][1][2] * x[c - 2 * sdd] : 0.0;
     }
     if (nl >= 0) {
       xm = x ? x[nl] : 0.0;
       if (q == 0) {  // periodic: duplicate of the wrapped face, same arithmetic
-        const double G = 0.5 * (Md[nl] + Md[c]);
-        a.F[d][c - sdd] = G - (xc - xm) * P.ih[d];
+        const double G = face_interp(P.met, L, d, 0, Md[nl], Md[c]);
+        a.F[d][c - sdd] = G - (xc - xm) * (P.met ? met_view(P.met, L, d).idfc[0] : P.ih[d]);
       }
     } else {
       double G = boundary_flux(L, B, sd, Md, p, d, 0);
       if (B.kind[d][0] == LM_SIDE_OUTFLOW) G += oc;
       a.F[d][c - sdd] = G;
-      xm = x ? 3.0 * xc - 3.0 * x[c + sdd] + x[c + 2 * sdd] : 0.0;
+      if (!P.met)
+        xm = x ? 3.0 * xc - 3.0 * x[c + sdd] + x[c + 2 * sdd] : 0.0;
+      else
+        xm = x ? P.gx[d][0][0] * xc + P.gx[d][0][1] * x[c + sdd] + P.gx[d][0][2] * x[c + 2 * sdd] : 0.0;
     }
-    const double v = (Md[c] - (xp - xm) / (2.0 * P.h[d])) / a.rho_new[c];
+    const double v = P.met ? (Md[c] - (xp - xm) * met_view(P.met, L, d).id2[q]) / a.rho_new[c]
+                           : (Md[c] - (xp - xm) / (2.0 * P.h[d])) / a.rho_new[c];
     a.v[d][c] = v;
     bad |= !isfinite(v);
   }
@@ -1056,7 +1125,7 @@ __global__ void __launch_bounds__(kBlock) k_momentum(Lay L, Level lv, double *M0
 // Initial face flux: face average of rho v (Eq 3.20, n = 1), prescribed
 // flux on boundary faces, extrapolated flux on outflow faces.
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_face_flux(Lay L, Bnd B, Sides sd, ProjArgs a) {
+__global__ void __launch_bounds__(kBlock) k_face_flux(Lay L, Bnd B, Sides sd, ProjArgs a, const double *met) {
   CellPos p;
   if (!cell_of_thread(L, p)) return;
   const long c = p.c;
@@ -1065,13 +1134,14 @@ __global__ void __launch_bounds__(kBlock) k_face_flux(Lay L, Bnd B, Sides sd, Pr
     const double *Md = a.M[d];
     const int q = coord(p, d);
     const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
-    a.F[d][c] = nh >= 0 ? 0.5 * (Md[c] + Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
-    if (q == 0) a.F[d][c - L.s[d]] = nl >= 0 ? 0.5 * (Md[nl] + Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
+    a.F[d][c] = nh >= 0 ? face_interp(met, L, d, q + 1, Md[c], Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
+    if (q == 0)
+      a.F[d][c - L.s[d]] = nl >= 0 ? face_interp(met, L, d, 0, Md[nl], Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
   }
 }
 
 hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Sides &sd,
-                            const Level &lv, double *M[3]) {
+                            const Level &lv, double *M[3], const double *met) {
   dim3 g = grid_for(L), bl(kBX, kBY);
   hipLaunchKernelGGL(k_momentum, g, bl, 0, st, L, lv, M[0], M[1], M[2]);
   ProjArgs a{};
@@ -1080,9 +1150,9 @@ hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Si
     a.F[i] = lv.F[i];
   }
   if (L.ndim == 3)
-    hipLaunchKernelGGL(k_face_flux<3>, g, bl, 0, st, L, B, sd, a);
+    hipLaunchKernelGGL(k_face_flux<3>, g, bl, 0, st, L, B, sd, a, met);
   else
-    hipLaunchKernelGGL(k_face_flux<2>, g, bl, 0, st, L, B, sd, a);
+    hipLaunchKernelGGL(k_face_flux<2>, g, bl, 0, st, L, B, sd, a, met);
   return hipGetLastError();
 }
 
@@ -1098,8 +1168,14 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Lay L, Phys P, Level lv, const u
     const double nu = P.nu_coef * lv.kap[c] / (P.Pe * lv.rho[c]);
     double a = 0.0, q = 0.0;
     for (int d = 0; d < L.ndim; ++d) {
-      a = a + fabs(lv.v[d][c]) / P.h[d];
-      q = q + 1.0 / (P.h[d] * P.h[d]);
+      if (P.met) {  // stretched: the cell's own width
+        const double iw = met_view(P.met, L, d).iwid[coord(p, d) + 1];
+        a = a + fabs(lv.v[d][c]) * iw;
+        q = q + iw * iw;
+      } else {
+        a = a + fabs(lv.v[d][c]) / P.h[d];
+        q = q + 1.0 / (P.h[d] * P.h[d]);
+      }
     }
     rate = a + 2.0 * nu * q;
     if (chi) rate = rate + (double)chi[c] * nu / P.Da;
@@ -1243,20 +1319,22 @@ hipError_t launch_pack_u8(hipStream_t st, const Lay &L, const unsigned char *src
 namespace lm {
 
 // mean(a) over the interior into sc->mean_b (outflow shift cleared).
-__global__ void __launch_bounds__(kBlock) k_mean(Lay L, const double *a, double *partials, SolverScalars *sc) {
+__global__ void __launch_bounds__(kBlock) k_mean(Lay L, const double *a, double *partials, SolverScalars *sc,
+                                                 const double *vol) {
   __shared__ double sh[kBlock / 64];
   CellPos p;
   double v = 0.0;
-  if (cell_of_thread(L, p)) v = a[p.c];
+  if (cell_of_thread(L, p)) v = vol ? a[p.c] * vol[p.c] : a[p.c];
   const double s = block_sum(v, sh);
   if (linear_tid() == 0) partials[linear_block()] = s;
 }
 
-hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc) {
+hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc,
+                       const double *vol, double volume) {
   dim3 g = grid_for(L), bl(kBX, kBY);
-  hipLaunchKernelGGL(k_mean, g, bl, 0, st, L, a, partials, sc);
+  hipLaunchKernelGGL(k_mean, g, bl, 0, st, L, a, partials, sc, vol);
   hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
-                     (double)L.ncells(), 0, 1.0, 1.0, sc);
+                     vol ? volume : (double)L.ncells(), 0, 1.0, 1.0, sc);
   return hipGetLastError();
 }
 
@@ -1280,7 +1358,7 @@ hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const Sol
 // Per-block partial sums over the cells: 0 rho, 1 1/T, 2 R_H/T^2, 3 1/(rho T^2).
 template <int WHAT>
 __global__ void __launch_bounds__(kBlock) k_p0_sum(Lay L, const double *T, const double *rho, const double *RH,
-                                                   double *part) {
+                                                   double *part, const double *vol) {
   __shared__ double sh[kBlock / 64];
   CellPos p;
   double v = 0.0;
@@ -1290,6 +1368,7 @@ __global__ void __launch_bounds__(kBlock) k_p0_sum(Lay L, const double *T, const
     if (WHAT == 1) v = 1.0 / T[c];
     if (WHAT == 2) v = RH[c] / (T[c] * T[c]);
     if (WHAT == 3) v = 1.0 / (rho[c] * (T[c] * T[c]));
+    if (vol) v = v * vol[c];  // stretched: cell volumes enter each sum (dV = 1 below)
   }
   const double s = block_sum(v, sh);
   if (linear_tid() == 0) part[linear_block()] = s;
@@ -1428,29 +1507,30 @@ hipError_t launch_p0(hipStream_t st, int what, const Lay &L, const Phys &P, P0De
                      double *RH, double *partials) {
   const dim3 g = grid_for(L), bl(kBX, kBY);
   const int np = (int)nblocks_for(L);
-  const double dV = P.h[0] * P.h[1] * (L.ndim == 3 ? P.h[2] : 1.0);
+  const double dV = P.met ? 1.0 : P.h[0] * P.h[1] * (L.ndim == 3 ? P.h[2] : 1.0);
+  const double *vol = P.met ? P.vol : nullptr;
   auto finish = [&](int w) {
     hipLaunchKernelGGL(k_p0_finish, dim3(1), dim3(kBlock), 0, st, w, (const double *)partials, np, p0, dV, P);
   };
   switch (what) {
     case 0:
       hipLaunchKernelGGL(k_p0_sum<0>, g, bl, 0, st, L, (const double *)lv->T, (const double *)lv->rho,
-                         (const double *)nullptr, partials);
+                         (const double *)nullptr, partials, vol);
       finish(0);
       break;
     case 1:
     case 2:
       hipLaunchKernelGGL(k_p0_sum<1>, g, bl, 0, st, L, (const double *)lv->T, (const double *)nullptr,
-                         (const double *)nullptr, partials);
+                         (const double *)nullptr, partials, vol);
       finish(what);
       hipLaunchKernelGGL(k_p0_eos, g, bl, 0, st, L, (const double *)lv->T, lv->rho, (const P0Dev *)p0, what - 1);
       break;
     case 3:
       hipLaunchKernelGGL(k_p0_sum<2>, g, bl, 0, st, L, (const double *)n0->T, (const double *)nullptr,
-                         (const double *)RH, partials);
+                         (const double *)RH, partials, vol);
       finish(3);
       hipLaunchKernelGGL(k_p0_sum<3>, g, bl, 0, st, L, (const double *)n0->T, (const double *)n0->rho,
-                         (const double *)nullptr, partials);
+                         (const double *)nullptr, partials, vol);
       finish(4);
       hipLaunchKernelGGL(k_p0_startup, g, bl, 0, st, L, P, (const P0Dev *)p0, (const double *)n0->rho, RH, *lv);
       break;

@@ -52,6 +52,12 @@ struct Phys {
   double zeta;      // (gamma - 1)/(gamma qs): factor of the d_t p0 source (Eq 3.4b)
   double suth_C;    // > 0: Sutherland's law for kappa (Eq 4.12); 0: kappa = T^sigma
   int stage_form;   // stage kernel form (host side): 0 LDS tiles in 2D, one thread per cell in 3D; 1 LDS; 2 direct
+  // stretched grid (2D): packed spacing arrays per direction (device, see
+  // met_view), cell volumes on the cell layout, and the Eq 3.28 weights of
+  // the mirrored pressure ghost per side; met NULL on a uniform grid
+  const double *met = nullptr;
+  const double *vol = nullptr;
+  double gx[3][2][3] = {};
   // unequal steps (adaptive time step): AB2 weights of R^n, R^{n-1}; BDF2
   // d_t rho = (bd0 (rho^{new} - rho^n) - bd2 (rho^n - rho^{n-1})) / dt
   int var_step;
@@ -166,10 +172,11 @@ hipError_t launch_pack_u8(hipStream_t st, const Lay &L, const unsigned char *src
 hipError_t launch_init_state(hipStream_t st, const Lay &L, const Phys &P, const Bnd &B,
                              const Sides &sd, int from_T, Level &lv, int *bad_flag);
 hipError_t launch_face_flux(hipStream_t st, const Lay &L, const Bnd &B, const Sides &sd,
-                            const Level &lv, double *M[3]);
+                            const Level &lv, double *M[3], const double *met);
 hipError_t launch_cfl(hipStream_t st, const Lay &L, const Phys &P, const Level &lv,
                       const unsigned char *chi, double *partials, double *out_max);
-hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc);
+hipError_t launch_mean(hipStream_t st, const Lay &L, const double *a, double *partials, SolverScalars *sc,
+                       const double *vol, double volume);
 // Sums over cells of |v* - v^{n+1}|^2, (H* - H^{n+1})^2, (Z* - Z^{n+1})^2
 // into out[0..2] (partials: at least 3 * kErrBlocks doubles).
 constexpr int kErrBlocks = 256;
@@ -239,6 +246,10 @@ constexpr long kMaxCoarsest = 1024;   // dense pseudo-inverse limit
 constexpr int kVcCoarsest = 128;      // coarsest cells of a variable-coefficient solve (inverse built on the device)
 
 struct PoissonWS {
+  int met = 0;             // stretched 2D grid: volume-weighted operator (set before poisson_plan)
+  double *vol = nullptr;   // its cell volumes (fine layout, FP64)
+  double *met_w = nullptr; // its cell widths per level and direction (x then y, level after level)
+  double volume = 0.0;     // its domain area (the weight of the solution mean)
   Lay lay;                 // fine layout (FP64 CG vectors)
   Bnd bnd;
   int nlev, lc;            // MG levels; first level handled by the coarse kernel
@@ -294,6 +305,11 @@ hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const d
 // sc->rho_bad when a density is not positive and finite. The caller then
 // sets ws.vc for the solve.
 hipError_t poisson_set_beta(hipStream_t st, PoissonWS &ws);
+// Stretched 2D grid (ws.met, planned with vc_cap): from the finest cell
+// widths wx (n[0]) and wy (n[1]) (host arrays), every level's cell ratios
+// dx/dy, the finest cell volumes, the packed coarse-level ratios and the
+// coarsest pseudo-inverse; leaves ws.vc set for every later solve.
+hipError_t poisson_set_metric(hipStream_t st, PoissonWS &ws, const double *wx, const double *wy);
 // One launch of a solver kernel class for timing (see lm_bench_kernel);
 // the caller has cleared sc->done. Returns hipErrorInvalidValue for an
 // unknown class.

@@ -645,6 +645,7 @@ struct CoarseArgs {
   T *x0;                   // global output: correction of level l0
   const T *pinv;           // dense pseudo-inverse of the coarsest level
   const T *rho_c;          // variable coefficients: densities of levels l0.., packed at off[]
+  int met = 0;             // stretched 2D grid: rho_c holds dx/dy (face_coef)
 };
 
 template <int DIM, typename T>
@@ -745,8 +746,8 @@ struct CSet {
 // coarse levels are small and their sweeps latency bound), so the cell sets
 // hold no coefficients and stay in registers.
 template <typename T>
-__device__ inline T c_face(const T *rs, int ia, int ib, int zero_slot, T ih2) {
-  return ib == zero_slot ? T(0) : ih2 * face_beta<T>(rs[ia], rs[ib]);
+__device__ inline T c_face(const T *rs, int ia, int ib, int zero_slot, T ih2, int d, int met) {
+  return ib == zero_slot ? T(0) : ih2 * face_coef<T>(rs[ia], rs[ib], d, met);
 }
 
 template <int DIM, typename T, bool VC = false>
@@ -777,7 +778,8 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs
     if constexpr (VC) {
       T dg = T(0);
 #pragma unroll
-      for (int m = 0; m < 2 * DIM; ++m) dg += c_face<T>(rs, off + c, s.nb[q][m], zero_slot, a.ih2[l].v[m >> 1]);
+      for (int m = 0; m < 2 * DIM; ++m)
+        dg += c_face<T>(rs, off + c, s.nb[q][m], zero_slot, a.ih2[l].v[m >> 1], m >> 1, a.met);
       s.idg[q] = T(1) / dg;
     } else {
       s.idg[q] = idg_s[8 * (l - a.l0) + code];
@@ -791,7 +793,7 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs
 // whatever the coefficient.)
 template <int DIM, typename T, bool VC = false>
 __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, T> &s, const T ih2[3],
-                               bool zero_init) {
+                               bool zero_init, int met) {
   if constexpr (VC && DIM == 3) {
     // one cell at a time (fewer live registers); cells of one colour read
     // only the other colour, so each result is stored at once
@@ -803,7 +805,7 @@ __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, 
 #pragma unroll
       for (int m = 0; m < 2 * DIM; ++m) {
         const int nb = s.nb[q][m];
-        nbs += (ih2[m >> 1] * face_beta<T>(rc, rs[nb])) * xs[nb];
+        nbs += (ih2[m >> 1] * face_coef<T>(rc, rs[nb], m >> 1, met)) * xs[nb];
       }
       if (zero_init) nbs = T(0);
       xs[s.c[q]] = (bs[s.c[q]] + nbs) * s.idg[q];
@@ -830,7 +832,8 @@ __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, 
     T nbs = T(0);
     if constexpr (VC) {
 #pragma unroll
-      for (int m = 0; m < 2 * DIM; ++m) nbs += (ih2[m >> 1] * face_beta<T>(rv[q][2 * DIM], rv[q][m])) * v[q][m];
+      for (int m = 0; m < 2 * DIM; ++m)
+        nbs += (ih2[m >> 1] * face_coef<T>(rv[q][2 * DIM], rv[q][m], m >> 1, met)) * v[q][m];
     } else {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) nbs += ih2[d] * (v[q][2 * d] + v[q][2 * d + 1]);
@@ -886,8 +889,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
       c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red);
       c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black);
       for (int s = 0; s < a.nu; ++s) {
-        c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, s == 0);
-        c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false);
+        c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, s == 0, a.met);
+        c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false, a.met);
       }
     }
     const int *nf = a.n[l], *nc = a.n[l + 1];
@@ -919,8 +922,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
                 const bool lo = q[d] > 0, hi = q[d] + 1 < nf[d];
                 const int im = lo ? off + c - st[d] : (per ? off + c + (nf[d] - 1) * st[d] : zero_slot);
                 const int ip = hi ? off + c + st[d] : (per ? off + c - (nf[d] - 1) * st[d] : zero_slot);
-                const T bm = c_face<T>(rs, off + c, im, zero_slot, a.ih2[l].v[d]);
-                const T bp = c_face<T>(rs, off + c, ip, zero_slot, a.ih2[l].v[d]);
+                const T bm = c_face<T>(rs, off + c, im, zero_slot, a.ih2[l].v[d], d, a.met);
+                const T bp = c_face<T>(rs, off + c, ip, zero_slot, a.ih2[l].v[d], d, a.met);
                 nbs += bm * xs[im] + bp * xs[ip];
                 dg += bm + bp;
               }
@@ -990,8 +993,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red);
     c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black);
     for (int s = 0; s < a.nu; ++s) {
-      c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false);
-      c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, false);
+      c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false, a.met);
+      c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, false, a.met);
     }
   }
   {

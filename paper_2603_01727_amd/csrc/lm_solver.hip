@@ -222,11 +222,22 @@ __device__ inline T face_beta(T ra, T rb) {
   return T(2) / (ra + rb);
 }
 
+// Face coefficient along direction d. On a stretched 2D grid (met) the
+// volume-weighted operator dV A has, on an x-face, dy / (distance between
+// the two centres) = 2 / (dx_a/dy + dx_b/dy), i.e. face_beta of the cell
+// ratio dx/dy, and on a y-face face_beta of dy/dx: the cell array holds
+// dx/dy and y-faces take its reciprocals.
+template <typename T>
+__device__ inline T face_coef(T ra, T rb, int d, int met) {
+  if (met && d == 1) return face_beta<T>(T(1) / ra, T(1) / rb);
+  return face_beta<T>(ra, rb);
+}
+
 // Neighbour sum and diagonal of L = -A_beta at one cell, beta = 1/rho_f
 // (same neighbour rules as op_parts).
 template <int DIM, typename A, typename T, typename R>
 __device__ inline void op_parts_vc(const Lay &L, const Bnd &B, const A ih2[3], const R *rho, const T *x, int i, int j,
-                                   int k, long c, A &nbsum, A &diag) {
+                                   int k, long c, A &nbsum, A &diag, int met = 0) {
 #pragma clang fp contract(off)
   nbsum = A(0);
   diag = A(0);
@@ -238,12 +249,12 @@ __device__ inline void op_parts_vc(const Lay &L, const Bnd &B, const A ih2[3], c
     const long lo = (q[d] > 0) ? c - L.s[d] : (B.periodic[d] ? c + (long)(L.n[d] - 1) * L.s[d] : -1);
     const long hi = (q[d] + 1 < L.n[d]) ? c + L.s[d] : (B.periodic[d] ? c - (long)(L.n[d] - 1) * L.s[d] : -1);
     if (lo >= 0) {
-      const A bt = face_beta<A>(rc, (A)rho[lo]);
+      const A bt = face_coef<A>(rc, (A)rho[lo], d, met);
       s += bt * (A)x[lo];
       sb += bt;
     }
     if (hi >= 0) {
-      const A bt = face_beta<A>(rc, (A)rho[hi]);
+      const A bt = face_coef<A>(rc, (A)rho[hi], d, met);
       s += bt * (A)x[hi];
       sb += bt;
     }
@@ -273,6 +284,8 @@ struct CGArgs {
   int k;
   int flexible;
   const double *rho;      // density of beta = 1/rho_f; NULL: beta = 1
+  int met = 0;                   // stretched 2D grid: rho holds dx/dy (face_coef)
+  const double *vol = nullptr;   // stretched: cell volumes (the right-hand side is dV b)
 };
 
 // x = x0; r_0 = c - L x0 with c = -(b - mean(b) - outflow shift); ||c||^2
@@ -304,12 +317,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(CGArgs a, double *partials) 
       if (a.B.kind[d][0] == LM_SIDE_OUTFLOW && q[d] == 0) bb -= oc * a.ih[d];
       if (a.B.kind[d][1] == LM_SIDE_OUTFLOW && q[d] == a.L.n[d] - 1) bb -= oc * a.ih[d];
     }
-    const double cv = -bb;
+    const double cv = a.vol ? -(bb * a.vol[c]) : -bb;  // stretched: dV (b - mean)
     double Lx = 0.0;
     if (a.x0) {
       double nbs, dg;
       if (a.rho)
-        op_parts_vc<DIM, double, double, double>(a.L, a.B, a.ih2, a.rho, a.x0, i, j, k, c, nbs, dg);
+        op_parts_vc<DIM, double, double, double>(a.L, a.B, a.ih2, a.rho, a.x0, i, j, k, c, nbs, dg, a.met);
       else
         op_parts<DIM, double, double>(a.L, a.B, a.ih2, a.x0, i, j, k, c, nbs, dg);
       Lx = dg * xv - nbs;
@@ -377,12 +390,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_pq(CGArgs a, int np_cc) {
       const long hi = (q[d] + 1 < a.L.n[d]) ? c + a.L.s[d]
                                             : (a.B.periodic[d] ? c - (long)(a.L.n[d] - 1) * a.L.s[d] : -1);
       if (lo >= 0) {
-        const double bt = a.rho ? face_beta<double>(a.rho[c], a.rho[lo]) : 1.0;
+        const double bt = a.rho ? face_coef<double>(a.rho[c], a.rho[lo], d, a.met) : 1.0;
         s += bt * pv(lo);
         sb += bt;
       }
       if (hi >= 0) {
-        const double bt = a.rho ? face_beta<double>(a.rho[c], a.rho[hi]) : 1.0;
+        const double bt = a.rho ? face_coef<double>(a.rho[c], a.rho[hi], d, a.met) : 1.0;
         s += bt * pv(hi);
         sb += bt;
       }
@@ -503,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
     const long c = a.L.at(i, j, k);
     double nbs, dg;
     if (a.rho)
-      op_parts_vc<DIM, double, TZ, double>(a.L, a.B, a.ih2, a.rho, u, i, j, k, c, nbs, dg);
+      op_parts_vc<DIM, double, TZ, double>(a.L, a.B, a.ih2, a.rho, u, i, j, k, c, nbs, dg, a.met);
     else
       op_parts<DIM, double, TZ>(a.L, a.B, a.ih2, u, i, j, k, c, nbs, dg);
     const double uc = (double)u[c];
@@ -525,7 +538,7 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_w(CGArgs a, double *w) {
 
 // Sum of x into partials (mean of the final solution).
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_sum_x(Lay L, const double *x, double *part) {
+__global__ void __launch_bounds__(kBlock) k_sum_x(Lay L, const double *x, double *part, const double *vol) {
   __shared__ double sh[kBlock / 64];
   // four tiles' loads in flight per trip, four running sums combined in a
   // fixed order
@@ -536,7 +549,10 @@ __global__ void __launch_bounds__(kBlock) k_sum_x(Lay L, const double *x, double
     for (int u = 0; u < 4; ++u) {
       const int tile = t0 + u * gridDim.x;
       int i, j, k;
-      if (tile < nt && tile_cell(L, tile, i, j, k)) s[u] += x[L.at(i, j, k)];
+      if (tile < nt && tile_cell(L, tile, i, j, k)) {
+        const long c = L.at(i, j, k);
+        s[u] += vol ? x[c] * vol[c] : x[c];   // stretched: the integral of x
+      }
     }
   }
   const double r = block_sum((s[0] + s[1]) + (s[2] + s[3]), sh);
@@ -558,14 +574,15 @@ __global__ void __launch_bounds__(kBlock) k_fin_mean_x(const double *part, int n
 // of the pre-smoother): red cells take b/diag without reading x.
 template <int DIM, typename TX, typename TB>
 __global__ void __launch_bounds__(kBlock) k_mg_smooth(Lay L, Bnd B, Ih2<TX> ih2, TX *x, const TB *b, int color,
-                                                      int zero_init, const SolverScalars *sc, const TX *rho) {
+                                                      int zero_init, const SolverScalars *sc, const TX *rho,
+                                                      int met) {
   if (sc->done) return;
   CellPos p;
   if (!cell_of_thread(L, p)) return;
   if (((p.i + p.j + p.k) & 1) != color) return;
   TX nbs, dg;
   if (rho)
-    op_parts_vc<DIM, TX, TX, TX>(L, B, ih2.v, rho, x, p.i, p.j, p.k, p.c, nbs, dg);
+    op_parts_vc<DIM, TX, TX, TX>(L, B, ih2.v, rho, x, p.i, p.j, p.k, p.c, nbs, dg, met);
   else
     op_parts<DIM, TX, TX>(L, B, ih2.v, x, p.i, p.j, p.k, p.c, nbs, dg);
   if (zero_init && color == 0) nbs = TX(0);
@@ -575,7 +592,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_smooth(Lay L, Bnd B, Ih2<TX> ih2,
 // Coarse right-hand side: average over the 2^DIM children of b - L x.
 template <int DIM, typename TX, typename TB>
 __global__ void __launch_bounds__(kBlock) k_mg_restrict(Lay Lf, Lay Lc, Bnd B, Ih2<TX> ih2, const TX *x,
-                                                        const TB *b, TX *bc, const SolverScalars *sc, const TX *rho) {
+                                                        const TB *b, TX *bc, const SolverScalars *sc, const TX *rho,
+                                                        int met) {
   if (sc->done) return;
   CellPos p;
   if (!cell_of_thread(Lc, p)) return;
@@ -590,7 +608,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_restrict(Lay Lf, Lay Lc, Bnd B, I
         const long c = Lf.at(i, j, k);
         TX nbs, dg;
         if (rho)
-          op_parts_vc<DIM, TX, TX, TX>(Lf, B, ih2.v, rho, x, i, j, k, c, nbs, dg);
+          op_parts_vc<DIM, TX, TX, TX>(Lf, B, ih2.v, rho, x, i, j, k, c, nbs, dg, met);
         else
           op_parts<DIM, TX, TX>(Lf, B, ih2.v, x, i, j, k, c, nbs, dg);
         acc += ((TX)b[c] - (dg * x[c] - nbs));
@@ -707,7 +725,7 @@ __global__ void __launch_bounds__(kPinvThreads) k_vc_pinv(CoarseArgs<T> a, T *pi
         const bool in = side == 0 ? q[d] > 0 : q[d] + 1 < n[d];
         if (!in && !per) continue;
         const int m = side == 0 ? (in ? t - st[d] : t + (n[d] - 1) * st[d]) : (in ? t + st[d] : t - (n[d] - 1) * st[d]);
-        const double w = UNIT ? ih2 : ih2 * face_beta<double>(rc, (double)rho[m]);
+        const double w = UNIT ? ih2 : ih2 * face_coef<double>(rc, (double)rho[m], d, a.met);
         M[t * N + t] += w;
         M[t * N + m] -= w;
       }
@@ -780,7 +798,7 @@ static void choose_tile(PoissonWS &ws, int l) {
 static void choose_tile_vc(PoissonWS &ws, int l) {
   const Lay &L = ws.lev[l].lay;
   ws.vtx[l] = ws.vty[l] = 0;
-  if (!ws.vc_cap || L.ndim != 2 || ws.nu < 1 || ws.nu > 3 || l >= ws.lc) return;
+  if (!ws.vc_cap || ws.met || L.ndim != 2 || ws.nu < 1 || ws.nu > 3 || l >= ws.lc) return;
   const int cand[2][2] = {{TXS, TYS}, {16, 16}};
   for (int q = 0; q < 2; ++q)
     if (L.n[0] % cand[q][0] == 0 && L.n[1] % cand[q][1] == 0) {
@@ -859,6 +877,13 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
     }
   }
   ws.nlev = nl;
+  if (ws.met) {
+    // volume-weighted operator: unit coefficients on the finest level, a
+    // quarter per coarser level (the restriction averages the 4 children
+    // of a residual whose coarse operator sums them)
+    for (int l = 0; l < nl; ++l)
+      for (int d = 0; d < 3; ++d) ws.lev[l].ih2[d] = d < ndim ? std::ldexp(1.0, -2 * l) : 0.0;
+  }
   const long ncoarsest = ws.lev[nl - 1].lay.ncells();
   if (ncoarsest > kMaxCoarsest) {
     if (err) *err = "grid does not coarsen to <= 1024 cells (need even sizes down to the coarse grid)";
@@ -932,6 +957,14 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   ws.part_rz = (double *)cv.take((size_t)3 * npmax * 8);
   ws.partials = (double *)cv.take((size_t)(nblocks_for(fine) + kRedBlocks) * 8 + 64);
   ws.sc = (SolverScalars *)cv.take(sizeof(SolverScalars));
+  ws.vol = nullptr;
+  ws.met_w = nullptr;
+  if (ws.met) {
+    long nw = 0;
+    for (int l = 0; l < nl; ++l) nw += ws.lev[l].lay.n[0] + ws.lev[l].lay.n[1];
+    ws.vol = (double *)cv.take(fbytes);
+    ws.met_w = (double *)cv.take((size_t)nw * 8);
+  }
   return true;
 }
 
@@ -1275,6 +1308,7 @@ static CoarseArgs<T> coarse_args(PoissonWS &ws, void *z, const double *r) {
   ca.x0 = ws.lc == 0 ? (T *)z : (T *)ws.lev[ws.lc].x;
   ca.pinv = (const T *)(ws.vc ? ws.pinv_vc : ws.pinv);
   ca.rho_c = ws.vc ? (const T *)ws.rho_c : nullptr;
+  ca.met = ws.met;
   return ca;
 }
 
@@ -1323,18 +1357,18 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
         for (int color = 0; color < 2; ++color) {
           if (l == 0)
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin, r, color,
-                               s == 0 && color == 0, sc, rl);
+                               s == 0 && color == 0, sc, rl, ws.met);
           else
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, T>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin,
-                               (const T *)ws.lev[l].b, color, s == 0 && color == 0, sc, rl);
+                               (const T *)ws.lev[l].b, color, s == 0 && color == 0, sc, rl, ws.met);
         }
       }
       if (l == 0)
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(Lc), bb, 0, st, L, Lc, B, ih2_of<T>(ws, l),
-                           xin, r, (T *)ws.lev[l + 1].b, sc, rl);
+                           xin, r, (T *)ws.lev[l + 1].b, sc, rl, ws.met);
       else
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, T>), grid_for(Lc), bb, 0, st, L, Lc, B, ih2_of<T>(ws, l), xin,
-                           (const T *)ws.lev[l].b, (T *)ws.lev[l + 1].b, sc, rl);
+                           (const T *)ws.lev[l].b, (T *)ws.lev[l + 1].b, sc, rl, ws.met);
     }
   }
   if (ws.vc)
@@ -1372,10 +1406,10 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
           const int color = 1 - cc;
           if (l == 0)
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin, r, color, 0,
-                               sc, rl);
+                               sc, rl, ws.met);
           else
             hipLaunchKernelGGL((k_mg_smooth<DIM, T, T>), g, bb, 0, st, L, B, ih2_of<T>(ws, l), xin,
-                               (const T *)ws.lev[l].b, color, 0, sc, rl);
+                               (const T *)ws.lev[l].b, color, 0, sc, rl, ws.met);
         }
       }
     }
@@ -1469,6 +1503,8 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   a.k = 0;
   a.flexible = !ws.cgcg;
   a.rho = ws.vc ? ws.rho64 : nullptr;
+  a.met = ws.met;
+  a.vol = ws.met ? ws.vol : nullptr;
   ws.tsolve0 = ws.tcount;
   hipError_t e = hipMemsetAsync(&ws.sc->done, 0, 4 * sizeof(int), st);  // done, iters, zero, nonconv
   if (e != hipSuccess) return e;
@@ -1500,9 +1536,9 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
   *converged = h.done && !h.nonconv;
   // mean of the solution (the stored pressure is zero-mean)
   hipLaunchKernelGGL((k_sum_x<DIM>), dim3(kRedBlocks), dim3(kBlock), 0, st, ws.lay, (const double *)ws.x,
-                     ws.partials);
+                     ws.partials, ws.met ? (const double *)ws.vol : (const double *)nullptr);
   hipLaunchKernelGGL(k_fin_mean_x, dim3(1), dim3(kBlock), 0, st, (const double *)ws.partials, kRedBlocks,
-                     (double)ws.lay.ncells(), ws.sc);
+                     ws.met ? ws.volume : (double)ws.lay.ncells(), ws.sc);
   return hipGetLastError();
 }
 
@@ -1548,6 +1584,71 @@ static hipError_t set_beta_dim(hipStream_t st, PoissonWS &ws) {
                        (const T *)ws.rho[l], (T *)ws.rho_c + ca.off[l]);
   hipLaunchKernelGGL((k_vc_pinv<DIM, T>), dim3(1), dim3(kPinvThreads), 0, st, ca, (T *)ws.pinv_vc);
   return hipGetLastError();
+}
+
+// Stretched 2D grid: the cell ratio dx/dy of every cell of a level (the
+// cell array face_coef turns into the volume-weighted face coefficients)
+// and, on the finest level, the cell volumes.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_met_level(Lay L, const double *wx, const double *wy, T *ratio,
+                                                      double *vol) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  ratio[p.c] = (T)(wx[p.i] / wy[p.j]);
+  if (vol) vol[p.c] = wx[p.i] * wy[p.j];
+}
+
+template <typename T>
+static hipError_t set_metric_t(hipStream_t st, PoissonWS &ws) {
+  const dim3 bb(kBX, kBY);
+  long off = 0;
+  for (int l = 0; l < ws.nlev; ++l) {
+    const Lay &L = ws.lev[l].lay;
+    const double *wx = ws.met_w + off, *wy = wx + L.n[0];
+    off += L.n[0] + L.n[1];
+    if (l == 0) {
+      hipLaunchKernelGGL((k_met_level<double>), grid_for(L), bb, 0, st, L, wx, wy, ws.rho64, ws.vol);
+      if (sizeof(T) != 8)
+        hipLaunchKernelGGL((k_met_level<T>), grid_for(L), bb, 0, st, L, wx, wy, (T *)ws.rho[0], (double *)nullptr);
+    } else {
+      hipLaunchKernelGGL((k_met_level<T>), grid_for(L), bb, 0, st, L, wx, wy, (T *)ws.rho[l], (double *)nullptr);
+    }
+  }
+  ws.vc = 1;
+  CoarseArgs<T> ca = coarse_args<T>(ws, ws.z[0], ws.r[0]);
+  for (int l = ws.lc; l < ws.nlev; ++l)
+    hipLaunchKernelGGL((k_vc_pack<2, T>), grid_for(ws.lev[l].lay), bb, 0, st, ws.lev[l].lay, (const T *)ws.rho[l],
+                       (T *)ws.rho_c + ca.off[l]);
+  hipLaunchKernelGGL((k_vc_pinv<2, T>), dim3(1), dim3(kPinvThreads), 0, st, ca, (T *)ws.pinv_vc);
+  return hipGetLastError();
+}
+
+hipError_t poisson_set_metric(hipStream_t st, PoissonWS &ws, const double *wx, const double *wy) {
+  if (!ws.met || ws.lay.ndim != 2 || ws.lev[ws.nlev - 1].lay.ncells() > kVcCoarsest) return hipErrorInvalidValue;
+  // widths of every level: a coarse cell spans its two children
+  std::vector<double> all;
+  std::vector<double> cx(wx, wx + ws.lay.n[0]), cy(wy, wy + ws.lay.n[1]);
+  double V = 0.0;
+  {
+    double sx = 0.0, sy = 0.0;
+    for (double v : cx) sx += v;
+    for (double v : cy) sy += v;
+    V = sx * sy;
+  }
+  for (int l = 0; l < ws.nlev; ++l) {
+    all.insert(all.end(), cx.begin(), cx.end());
+    all.insert(all.end(), cy.begin(), cy.end());
+    std::vector<double> nx(cx.size() / 2), ny(cy.size() / 2);
+    for (size_t q = 0; q < nx.size(); ++q) nx[q] = cx[2 * q] + cx[2 * q + 1];
+    for (size_t q = 0; q < ny.size(); ++q) ny[q] = cy[2 * q] + cy[2 * q + 1];
+    cx.swap(nx);
+    cy.swap(ny);
+  }
+  ws.volume = V;
+  hipError_t e = hipMemcpyAsync(ws.met_w, all.data(), all.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  return ws.mixed ? set_metric_t<float>(st, ws) : set_metric_t<double>(st, ws);
 }
 
 hipError_t poisson_setup_device(hipStream_t st, PoissonWS &ws) {
@@ -1617,7 +1718,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
         launch_nu<T>(ws, 0, ws.nu, d, st);
       } else {
         hipLaunchKernelGGL((k_mg_smooth<DIM, T, double>), grid_for(ws.lay), dim3(kBX, kBY), 0, st, ws.lay, ws.bnd,
-                           ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc, (const T *)nullptr);
+                           ih2_of<T>(ws, 0), (T *)ws.z[0], (const double *)ws.r[0], 1, 0, ws.sc, (const T *)nullptr, 0);
       }
       break;
     }
@@ -1631,7 +1732,7 @@ static hipError_t bench_launch_dim(hipStream_t st, PoissonWS &ws, int which) {
       } else {
         hipLaunchKernelGGL((k_mg_restrict<DIM, T, double>), grid_for(ws.lev[1].lay), dim3(kBX, kBY), 0, st,
                            ws.lay, ws.lev[1].lay, ws.bnd, ih2_of<T>(ws, 0), (const T *)ws.z[0],
-                           (const double *)ws.r[0], (T *)ws.lev[1].b, ws.sc, (const T *)nullptr);
+                           (const double *)ws.r[0], (T *)ws.lev[1].b, ws.sc, (const T *)nullptr, 0);
       }
       break;
     }

@@ -24,7 +24,8 @@ LM_LEVEL_PREDICTED = 2
 
 
 class lm_grid(C.Structure):
-    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("bc", (C.c_int * 2) * 3)]
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("bc", (C.c_int * 2) * 3),
+                ("faces", C.c_void_p * 3)]
 
 
 class lm_params(C.Structure):

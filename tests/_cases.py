@@ -21,7 +21,7 @@ def _params(case: Case, over):
 
 def oracle_for(case: Case, **over):
     nd = case.ndim
-    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc, bnd=case.bnd)
+    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc, bnd=case.bnd, faces=case.faces)
     o = Oracle(g, Params(**_params(case, over)), ib=case.ib)
     st = o.initial_state(case.T, case.v, Z=case.Z, H=case.H)
     return o, st
@@ -31,7 +31,7 @@ def gpu_for(case: Case, rtol=1e-13, precision="fp64", **over):
     from paper_2603_01727_amd import Solver
     nd = case.ndim
     s = Solver(case.n[:nd], case.L[:nd], bc=case.bc, precision=precision, poisson_rtol=rtol,
-               poisson_maxit=400, with_ib=case.ib is not None, **_params(case, over))
+               poisson_maxit=400, with_ib=case.ib is not None, faces=case.faces, **_params(case, over))
     for (d, side), data in (case.bnd or {}).items():
         s.set_side(d, side, v=data.get("v"), Z=data.get("Z"), H=data.get("H"), F=data.get("F"),
                    wall=data.get("wall"))

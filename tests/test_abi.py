@@ -200,3 +200,51 @@ def test_semi_enclosed_checks_without_gpu():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EUNSUPPORTED
     p.p0_closed = 3
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+
+
+def test_stretched_grid_checks_without_gpu():
+    """lm_grid.faces: n + 1 strictly increasing values from 0 to L, else
+    LM_EINVAL; the stretched path covers 2D without outflow sides, the
+    adjoint, a density-weighted pressure or the reacting form of p0, else
+    LM_EUNSUPPORTED. A stretched grid reserves more than the uniform one
+    (the packed spacing arrays)."""
+    import numpy as np
+    from paper_2603_01727_amd import lib
+    from workloads import tanh_stretched_faces
+    L = lib.load()
+    b = C.c_size_t()
+    f = tanh_stretched_faces(64, 2.0)
+    keep = []
+
+    def size(g, p, faces):
+        for d in range(3):
+            g.faces[d] = None
+        for d, a in enumerate(faces):
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                keep.append(a)
+                g.faces[d] = a.ctypes.data
+        return L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b))
+
+    walls = [(2, 2), (2, 2), (0, 0)]
+    g, p = _grid_params((64, 64), bc=walls)
+    assert size(g, p, []) == lib.LM_OK
+    uniform = b.value
+    assert size(g, p, [f, f]) == lib.LM_OK and b.value > uniform
+    assert size(g, p, [None, f]) == lib.LM_OK
+    for bad in (f[::-1], f * 1.01, np.concatenate([[0.0, 0.02, 0.01], f[3:]]), f - 1e-3):
+        assert size(g, p, [bad, None]) == lib.LM_EINVAL
+    g, p = _grid_params((64, 64), bc=[(2, 4), (2, 2), (0, 0)])      # an outflow side
+    assert size(g, p, [f, None]) == lib.LM_EUNSUPPORTED
+    g, p = _grid_params((64, 64, 64), bc=walls)
+    assert size(g, p, [f, None, None]) == lib.LM_EUNSUPPORTED
+    g, p = _grid_params((64, 64), bc=walls)
+    p.with_adjoint = 1
+    assert size(g, p, [f, f]) == lib.LM_EUNSUPPORTED
+    p.with_adjoint, p.poisson_beta = 0, lib.LM_BETA_INV_RHO
+    assert size(g, p, [f, f]) == lib.LM_EUNSUPPORTED
+    g, p = _grid_params((64, 64))
+    p.reacting, p.p0_closed, p.gamma = 1, 2, 1.4
+    assert size(g, p, [f, f]) == lib.LM_EUNSUPPORTED
+    p.p0_closed = 0
+    assert size(g, p, [f, f]) == lib.LM_OK

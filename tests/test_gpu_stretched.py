@@ -1,0 +1,147 @@
+"""Stretched grids on the GPU (section 3.2.1, Eq 3.20-3.22; section 4.4,
+Eq 4.18): cell widths that vary along each direction, centres at the
+midpoints of their faces, face interpolation with the local weights, the
+volume-weighted pressure equation (sum dV P = 0).
+
+Parity: fields and p0 against the FP64 oracle step by step (relative L2
+<= 1e-10 per field, Poisson solved to 1e-13) on tanh-clustered cavities
+(both directions, one direction, slip walls), a smoothly stretched periodic
+box, and the bare pressure solve."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Grid, PoissonSolver
+from workloads import (Case, c1_case, heated_cavity_case, sine_stretched_faces, tanh_stretched_faces,
+                       variable_coefficient_problem)
+from _cases import oracle_for, gpu_for, compare, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+C_SUTH = 110.5 / 600.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check(errs, tol=TOL):
+    bad = {k: v for k, v in errs.items() if not (v <= tol)}
+    assert not bad, f"fields above {tol:g}: {bad} (all: {errs})"
+
+
+def _run_parity(case, steps, precision="fp64"):
+    o, st = oracle_for(case)
+    s = gpu_for(case, precision=precision)
+    assert abs(s.dt / o.dt - 1) < 1e-13, (s.dt, o.dt)
+    for k in range(steps):
+        st = o.step(st)
+        stats = s.step(1)
+        assert abs(stats["p0"] / st.p0 - 1) < 1e-12, (k, stats["p0"], st.p0)
+        errs = compare(st, s.get(device=False))
+        print(k, st.p0, errs, flush=True)
+        _check(errs)
+    return st, stats
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("m", [2.0, 5.0])
+def test_clustered_cavity_matches_oracle(m, precision):
+    """The heated cavity of section 4.4 on a 32^2 grid clustered at all four
+    walls (tanh, largest cell m times the smallest)."""
+    case = heated_cavity_case(n=32, m=m)
+    print("clustered cavity", m, precision, flush=True)
+    st, stats = _run_parity(case, 4, precision)
+    assert st.p0 > 1.0
+    assert max(abs(x) for x in stats["compat"]) < 1e-9
+
+
+def _slip_box(stretch_x, stretch_y):
+    """A 48 x 32 box of 1.5 x 1: isothermal no-slip x walls (the hot one's
+    temperature varying along y), adiabatic slip y walls, gravity along y;
+    the x and/or y faces clustered by tanh maps of ratio 3 and 4."""
+    nx, ny = 48, 32
+    y = (np.arange(ny) + 0.5) / ny
+    bc = (("noslip", "noslip"), ("slip", "slip"))
+    params = dict(Re=10.0, Pr=0.71, inv_Fr2=1.0 / (2 * 0.71 * 0.6), sutherland_C=C_SUTH,
+                  p0_closed=True, gamma=1.4, cfl=0.15)
+    bnd = {(0, 0): dict(H=2.6 + 0.1 * np.sin(2 * math.pi * y)), (0, 1): dict(H=np.full(ny, 1.4))}
+    faces = [tanh_stretched_faces(nx, 3.0, L=1.5) if stretch_x else None,
+             tanh_stretched_faces(ny, 4.0, L=1.0) if stretch_y else None]
+    return Case("slip_box", 2, (nx, ny, 1), (1.5, 1.0, 1.0), bc, params, np.ones((ny, nx)),
+                [np.zeros((ny, nx)), np.zeros((ny, nx))], bnd=bnd, faces=faces)
+
+
+@pytest.mark.parametrize("which", [(True, False), (False, True)], ids=["x", "y"])
+def test_one_stretched_direction_matches_oracle(which):
+    print("slip box stretched", which, flush=True)
+    _run_parity(_slip_box(*which), 4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_periodic_stretched_box_matches_oracle(precision):
+    """The 64^2 hot spot of the periodic 2 pi box with smooth periodic
+    stretchings (cell widths 0.5-1.5 and 0.7-1.3 times the mean)."""
+    case = c1_case(n=64)
+    L = case.L[0]
+    case.faces = [sine_stretched_faces(64, 0.5, L, shift=0.2), sine_stretched_faces(64, 0.3, L, shift=0.65)]
+    print("periodic stretched", precision, flush=True)
+    _run_parity(case, 3, precision)
+
+
+def _project_case(n, L, bc, faces, precision):
+    from paper_2603_01727_amd import Solver
+    _, b = variable_coefficient_problem(n, L, seed=41, kmax=4)
+    g = Grid(n, L, bc=bc, faces=faces)
+    Pex, lam = PoissonSolver(g).solve(b)
+    s = Solver(n, L, bc=bc, Re=100.0, dt=1e-3, precision=precision, poisson_rtol=1e-13, poisson_maxit=400,
+               faces=faces)
+    P, info = s.project(b)
+    return g, Pex, lam, P, info
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["walls", "periodic", "mixed-sides"])
+def test_stretched_pressure_solve_matches_oracle(kind, precision):
+    """The bare pressure solve sum_faces (P_nb - P) area / distance = dV (b
+    - lambda), lambda the volume-weighted mean of b, zero volume-weighted
+    mean P: element-wise against the oracle's direct solve."""
+    if kind == "walls":
+        n, L = (96, 64), (1.5, 1.0)
+        bc = (("noslip", "noslip"), ("slip", "slip"))
+        faces = [tanh_stretched_faces(96, 4.0, 1.5), tanh_stretched_faces(64, 2.0, 1.0)]
+    elif kind == "periodic":
+        n, L = (128, 96), (2 * math.pi, math.pi)
+        bc = None
+        faces = [sine_stretched_faces(128, 0.6, L[0], 0.1), sine_stretched_faces(96, 0.4, L[1], 0.3)]
+    else:
+        n, L = (80, 112), (1.0, 2.0)
+        bc = (("periodic", "periodic"), ("noslip", "inflow"))
+        faces = [None, tanh_stretched_faces(112, 8.0, 2.0)]
+    print("stretched project", kind, precision, flush=True)
+    g, Pex, lam, P, info = _project_case(n, L, bc, faces, precision)
+    err = rel_l2(P, Pex)
+    print(err, info, flush=True)
+    assert abs(info["mean_b"] - lam) < 1e-13 * max(1.0, abs(lam))
+    assert info["relres"] <= 1e-13
+    assert err <= TOL, (err, info)
+    assert abs(g.integral(P)) < 1e-13 * np.max(np.abs(P)) * np.prod(L)
+
+
+def test_stretched_call_errors():
+    """Calls the stretched path does not cover fail with LM_EUNSUPPORTED on
+    a live context (the set-up checks run without a GPU in the ABI tests)."""
+    from paper_2603_01727_amd import LowMachError, lib
+    s = gpu_for(heated_cavity_case(n=32, m=2.0))
+    with pytest.raises(LowMachError) as e:
+        s.kinetic_energy()
+    assert e.value.status == lib.LM_EUNSUPPORTED
+    _, b = variable_coefficient_problem((32, 32), (1.0, 1.0), seed=3)
+    with pytest.raises(LowMachError) as e:
+        s.project(b, rho=np.ones_like(b))
+    assert e.value.status == lib.LM_EUNSUPPORTED
+    s.step(2)                                   # the context still steps

@@ -62,3 +62,22 @@ def test_solenoidal_velocity_direct_sum(n):
     for d in range(nd):
         assert np.max(np.abs(v[d] - ref[d] * (0.1 / e))) < 1e-13
     assert abs(math.sqrt(float(np.mean(sum(x * x for x in v)))) - 0.1) < 1e-14
+
+
+def test_stretched_face_generators():
+    """The tanh faces handed to both sides equal the oracle's own Eq 4.18
+    grid (pinned there by Tables 3-4) to rounding; the sine faces span
+    [0, L], increase strictly and keep their documented width range."""
+    from oracle.grid import tanh_faces
+    from workloads import sine_stretched_faces, tanh_stretched_faces
+    for m, n in [(2.0, 32), (2.0, 64), (5.0, 32), (21.0, 64), (21.0, 216), (1.0, 16)]:
+        f = tanh_stretched_faces(n, m, L=1.5)
+        assert np.max(np.abs(f - tanh_faces(n, m, L=1.5))) < 1e-14
+        w = np.diff(f)
+        assert abs(w.max() / w.min() - m) < 1e-9 and f[0] == 0.0 and f[-1] == 1.5
+    n, amp, L = 64, 0.5, 2 * math.pi
+    f = sine_stretched_faces(n, amp, L, shift=0.2)
+    w = np.diff(f) * n / L
+    assert f[0] == 0.0 and f[-1] == L and np.all(w > 0)
+    assert 1 - amp - 1e-12 < w.min() and w.max() < 1 + amp + 1e-12
+    assert w.max() - w.min() > 1.8 * amp

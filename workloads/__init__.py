@@ -10,5 +10,5 @@ from .ics import (  # noqa: F401
     Case, cell_centres, taylor_green, hot_spot_tg, fourier_temperature,
     solenoidal_velocity, c1_case, c2_case, c3_case, c4_case, c5_case, make_case,
     fd_directions, variable_coefficient_problem, taylor_couette_case,
-    heated_cavity_case, double_tsuji_case,
+    heated_cavity_case, double_tsuji_case, tanh_stretched_faces, sine_stretched_faces,
 )

@@ -46,6 +46,7 @@ class Case:
     bnd: Optional[dict] = None
     nsteps: int = 1
     H: Optional[np.ndarray] = None
+    faces: Optional[list] = None  # per dim: None (uniform) or the n + 1 face coordinates
 
     @property
     def shape(self):
@@ -360,7 +361,47 @@ def taylor_couette_case(n=64, Re=1.0, Da=1e-2, shifted=True, half=2.5):
     return case
 
 
-def heated_cavity_case(n=64, Ra=1e2, eps=0.6, Pr=0.71, gamma=1.4, That=600.0, Chat=110.5, cfl=0.15):
+def tanh_stretched_faces(n, m, L=1.0):
+    """Face coordinates of an n-cell side of length L clustered towards both
+    ends (section 4.4, Eq 4.18): the uniform faces x = k/n mapped by
+    x~ = (1 + tanh(a (x - 1/2)) / tanh(a / 2)) / 2, with a > 0 the root of
+    max(width) / min(width) = m (the widest cell sits in the middle, the
+    narrowest at the walls). m = 1 returns the uniform faces."""
+    from scipy.optimize import brentq
+    x = np.arange(n + 1) / n
+    if m == 1.0:
+        return L * x
+
+    def mapped(a):
+        return 0.5 + 0.5 * np.tanh(a * (x - 0.5)) / math.tanh(0.5 * a)
+
+    def excess(a):
+        w = np.diff(mapped(a))
+        return w.max() / w.min() - m
+
+    hi = 1.0
+    while excess(hi) < 0.0:
+        hi *= 2.0
+    a = brentq(excess, 1e-6, hi, xtol=1e-15, rtol=4.0 * np.finfo(float).eps, maxiter=500)
+    f = L * mapped(a)
+    f[0], f[-1] = 0.0, L
+    return f
+
+
+def sine_stretched_faces(n, amp, L=1.0, shift=0.0):
+    """Face coordinates of a smooth periodic stretching of [0, L]: the
+    uniform faces x = k/n mapped by x + amp (sin(2 pi (x - shift)) +
+    sin(2 pi shift)) / (2 pi), cell widths from (1 - amp) to (1 + amp) times
+    L/n, with equal end widths (so the map suits a periodic direction)."""
+    x = np.arange(n + 1) / n
+    tp = 2.0 * math.pi
+    f = x + amp * (np.sin(tp * (x - shift)) + math.sin(tp * shift)) / tp
+    f = L * f
+    f[0], f[-1] = 0.0, L
+    return f
+
+
+def heated_cavity_case(n=64, Ra=1e2, eps=0.6, Pr=0.71, gamma=1.4, That=600.0, Chat=110.5, cfl=0.15, m=1.0):
     """Differentially heated square cavity of unit side (section 4.4): left
     wall at T_H = 1 + eps, right wall at T_C = 1 - eps (isothermal, Eq
     4.16a-b), adiabatic top and bottom (Eq 4.16c), every wall no-slip;
@@ -368,7 +409,9 @@ def heated_cavity_case(n=64, Ra=1e2, eps=0.6, Pr=0.71, gamma=1.4, That=600.0, Ch
     (Eq 4.10), so Re = Ra^{1/2}; Fr = (2 Pr eps)^{1/2} (Eq 4.11); Sutherland
     conductivity with C = Chat/That (Eq 4.12); enclosed system with gamma.
     Initial state at rest at the mean temperature, T = 1, H = 2 (Eq 4.17),
-    p0 = 1 (so the conserved mass is 1). No random draws."""
+    p0 = 1 (so the conserved mass is 1). m > 1 clusters the cells of both
+    directions towards the walls by the tanh map of Eq 4.18 (largest cell m
+    times the smallest). No random draws."""
     nn = (n, n)
     bc = (("noslip", "noslip"), ("noslip", "noslip"))
     params = dict(Re=math.sqrt(Ra), Pr=Pr, inv_Fr2=1.0 / (2.0 * Pr * eps), sutherland_C=Chat / That,
@@ -377,6 +420,9 @@ def heated_cavity_case(n=64, Ra=1e2, eps=0.6, Pr=0.71, gamma=1.4, That=600.0, Ch
     bnd = {(0, 0): side(1.0 + eps), (0, 1): side(1.0 - eps)}
     case = Case(f"heated_cavity_{n}", 2, (n, n, 1), (1.0, 1.0, 1.0), bc, params,
                 np.ones(nn), [np.zeros(nn), np.zeros(nn)], bnd=bnd)
+    if m != 1.0:
+        case.faces = [tanh_stretched_faces(n, m), tanh_stretched_faces(n, m)]
+        case.name += f"_tanh{m:g}"
     case.eps = eps
     return case
 
