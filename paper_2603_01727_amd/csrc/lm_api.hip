@@ -38,6 +38,8 @@ struct lm_ctx {
   PoissonWS pws;
   int *hflags;           // pinned
   double *hscalar;       // pinned
+  SolveLog *dlog;        // outcome of the step's two solves (one-block solver), checked after the step
+  SolveLog *hlog;        // pinned copy
   int have_state, have_prev;
   double time;
   long long total_iters;
@@ -383,6 +385,7 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   c->staging = (double *)cv.take(c->staging_bytes);
   c->dflags = (int *)cv.take(64);
   c->dscalar = (double *)cv.take(64);
+  c->dlog = (SolveLog *)cv.take(2 * sizeof(SolveLog));
   for (int s = 0; s < 2; ++s)
     for (int q = 0; q < 9; ++q) c->ad[s][q] = c->prm.with_adjoint ? (double *)cv.take(ab) : nullptr;
   for (int q = 0; q < 20; ++q) c->aw[q] = c->prm.with_adjoint ? (double *)cv.take(ab) : nullptr;
@@ -510,6 +513,7 @@ lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *ws, s
   c->last_iters[0] = c->last_iters[1] = 0;
   hipError_t e = hipHostMalloc((void **)&c->hflags, 64);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscalar, 64);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hlog, 2 * sizeof(SolveLog));
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->pws.host_sc, sizeof(SolverScalars));
   if (e != hipSuccess) {
     lm_destroy(c);
@@ -849,12 +853,17 @@ static lm_status do_stage(lm_ctx *c, int corrector, int &iters, double &relres, 
   }
   int conv = 0;
   const int expect = c->last_iters[corrector];
+  // the one-block solver leaves its outcome on the device; lm_step reads
+  // both stages' after the step (one wait per step instead of three)
+  SolveLog *log = c->pws.block_pcg ? c->dlog + corrector : nullptr;
   HIPCHK(c, poisson_solve(c->st, c->pws, c->b, x0, c->prm.poisson_rtol, c->prm.poisson_maxit, expect, &iters,
-                          &relres, &conv));
-  compat = c->pws.host_sc->mean_b;
-  c->last_iters[corrector] = iters > 0 ? iters : 1;
-  c->total_iters += iters;
-  if (!conv) return fail(c, LM_ENOCONV, "Poisson solver did not reach poisson_rtol");
+                          &relres, &conv, log));
+  if (!log) {
+    compat = c->pws.host_sc->mean_b;
+    c->last_iters[corrector] = iters > 0 ? iters : 1;
+    c->total_iters += iters;
+    if (!conv) return fail(c, LM_ENOCONV, "Poisson solver did not reach poisson_rtol");
+  }
   double *P_out = corrector ? c->P[c->inxt] : c->P[c->istar];
   HIPCHK(c, launch_project(c->st, L, c->bnd, c->phys, c->sides, c->M, c->pws.x, out.rho, c->pws.sc, out.F, out.v,
                            P_out, c->dflags + 1));
@@ -875,8 +884,21 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
     if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
     if (s == LM_OK) {
       HIPCHK(c, hipMemcpyAsync(c->hflags + 1, c->dflags + 1, 4, hipMemcpyDeviceToHost, c->st));
+      if (c->pws.block_pcg)
+        HIPCHK(c, hipMemcpyAsync(c->hlog, c->dlog, 2 * sizeof(SolveLog), hipMemcpyDeviceToHost, c->st));
       HIPCHK(c, hipStreamSynchronize(c->st));
-      if (c->hflags[1]) s = fail(c, LM_ENONFINITE, "non-finite velocity after the step");
+      if (c->pws.block_pcg) {
+        for (int q = 0; q < 2 && s == LM_OK; ++q) {
+          const SolveLog &g = c->hlog[q];
+          it[q] = g.iters;
+          rr[q] = g.cc > 0 ? std::sqrt(g.rr / g.cc) : 0.0;
+          cm[q] = g.mean_b;
+          c->last_iters[q] = g.iters > 0 ? g.iters : 1;
+          c->total_iters += g.iters;
+          if (!(g.done && !g.nonconv)) s = fail(c, LM_ENOCONV, "Poisson solver did not reach poisson_rtol");
+        }
+      }
+      if (s == LM_OK && c->hflags[1]) s = fail(c, LM_ENONFINITE, "non-finite velocity after the step");
     }
     if (s != LM_OK) {
       if (stats) {
@@ -1007,6 +1029,7 @@ void lm_destroy(lm_ctx *c) {
   (void)lm_kernel_timing(c, 0, 0);
   if (c->hflags) (void)hipHostFree(c->hflags);
   if (c->hscalar) (void)hipHostFree(c->hscalar);
+  if (c->hlog) (void)hipHostFree(c->hlog);
   if (c->pws.host_sc) (void)hipHostFree(c->pws.host_sc);
   delete c;
 }

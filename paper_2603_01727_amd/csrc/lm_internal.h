@@ -116,6 +116,13 @@ struct SolverScalars {
   int rho_bad;                     // a density given for beta = 1/rho_f is not positive and finite
 };
 
+// Outcome of one pressure solve, written on the device when the host
+// checks it later (after the step) instead of waiting for it.
+struct SolveLog {
+  double rr, cc, mean_b;
+  int iters, done, nonconv, pad;
+};
+
 // Multigrid level storage (precision chosen at run time, hence void*).
 struct MGLevel {
   Lay lay;
@@ -258,6 +265,8 @@ struct PoissonWS {
   int tx[kMaxLev], ty[kMaxLev];  // 2D tile of the fused level kernels (0: level not tiled)
   double *x, *r[2], *p[2], *q;
   int cgcg;                // single-reduction (Chronopoulos-Gear) CG in FP64 mode
+  int block_pcg;           // the whole solve in one workgroup (finest level <= kCoarseCells)
+  double *blk;             // its scratch (face coefficients, p, s)
   double tol2;             // rtol^2 of the solve in progress
   double *w, *s[2];        // its A u and s = A p vectors
   void *z[2];              // preconditioned residuals in MG precision
@@ -296,9 +305,13 @@ hipError_t poisson_setup_device(hipStream_t st, PoissonWS &ws);
 // Solve A x = b for the zero-mean x (A P = sum_d delta_1 delta_1 P with
 // zero-flux non-periodic sides), warm-started from x0 (NULL = 0). b is read
 // with sc->mean_b and the outflow shift sc->outflow_c removed on the fly.
-// The solution stays in ws.x with its mean in sc->mean_x.
+// The solution stays in ws.x with its mean in sc->mean_x. With log (only
+// when ws.block_pcg) the call returns once the solve is queued and its
+// outcome lands in *log on the device; iters, relres and converged are then
+// not written.
 hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const double *x0, double rtol,
-                         int maxit, int expect_iters, int *iters, double *relres, int *converged);
+                         int maxit, int expect_iters, int *iters, double *relres, int *converged,
+                         SolveLog *log = nullptr);
 // Prepares a variable-coefficient solve from the density in ws.rho64 (fine
 // layout): the density on every level (2^d-cell averages), the packed
 // coarse-level densities and the coarsest pseudo-inverse. Sets

@@ -752,14 +752,14 @@ __device__ inline T c_face(const T *rs, int ia, int ib, int zero_slot, T ih2, in
 
 template <int DIM, typename T, bool VC = false>
 __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs, int l, int color, int zero_slot,
-                             CSet<DIM, T> &s) {
+                             CSet<DIM, T> &s, int tid) {
   const int *n = a.n[l];
   const int N = (n[0] >> 1) * n[1] * n[2];
   const int off = a.off[l];
   const int st[3] = {1, n[0], n[0] * n[1]};
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int t = threadIdx.x + q * blockDim.x;
+    const int t = tid + q * blockDim.x;
     s.c[q] = -1;
     if (t >= N) continue;
     int i, j, k;
@@ -844,50 +844,24 @@ __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, 
   __syncthreads();
 }
 
-template <int DIM, typename T, bool VC = false>
-__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, const SolverScalars *sc) {
-  __shared__ T xs[kCoarseLds + 1];     // all coarse levels, then a zero slot
-  __shared__ T bs[kCoarseLds];
-  __shared__ T idg_s[kCoarseLev * 8];  // inverse diagonals, read with a per-cell index
-  __shared__ T rs[VC ? kCoarseLds + 1 : 1];  // densities of all coarse levels (variable coefficients)
-  if (sc->done) return;
+// The V-cycle over levels l0 .. nlev-1 out of LDS: the right-hand side of
+// level l0 is in bs at off[l0] (the coarser levels' parts are written
+// here), the correction of every level ends in xs, that of level l0 at
+// off[l0]. rs holds the levels' densities (VC), idg_s the inverse
+// diagonals by neighbour code; xs[zero_slot] = 0; tid is threadIdx.x (a
+// caller that runs the cycle in a loop passes it through an opaque copy,
+// so the per-level cell sets are recomputed, not held across iterations).
+// Ends with a barrier.
+template <int DIM, typename T, bool VC>
+__device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseArgs<T> &a, T *xs, T *bs, const T *rs,
+                                                                   const T *idg_s, int zero_slot,
+                                                                   int tid) {
   const int last = a.nlev - 1;
-  const int zero_slot = kCoarseLds;
-  if (threadIdx.x < kCoarseLev * 8) idg_s[threadIdx.x] = a.idg[threadIdx.x >> 3][threadIdx.x & 7];
-  if (threadIdx.x == 0) xs[zero_slot] = T(0);
-  if constexpr (VC) {
-    const int ntot = a.off[last] + a.n[last][0] * a.n[last][1] * a.n[last][2];
-    for (int t = threadIdx.x; t < ntot; t += blockDim.x) rs[t] = a.rho_c[t];
-    if (threadIdx.x == 0) rs[zero_slot] = T(1);
-  }
-  {
-    // all loads of the right-hand side issued before any is used
-    const int *n = a.n[a.l0];
-    const int N = n[0] * n[1] * n[2];
-    T v[kCoarseLoads];
-#pragma unroll
-    for (int q = 0; q < kCoarseLoads; ++q) {
-      const int t = threadIdx.x + q * blockDim.x;
-      v[q] = T(0);
-      if (t < N) {
-        int i, j, k;
-        c_decode<DIM, T>(n, t, i, j, k);
-        const long g = a.L0.at(i, j, k);
-        v[q] = a.b0_double ? (T)((const double *)a.b0)[g] : ((const T *)a.b0)[g];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kCoarseLoads; ++q) {
-      const int t = threadIdx.x + q * blockDim.x;
-      if (t < N) bs[a.off[a.l0] + t] = v[q];
-    }
-    __syncthreads();
-  }
   for (int l = a.l0; l < last; ++l) {
     {
       CSet<DIM, T> red, black;
-      c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red);
-      c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black);
+      c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red, tid);
+      c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black, tid);
       for (int s = 0; s < a.nu; ++s) {
         c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, s == 0, a.met);
         c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false, a.met);
@@ -898,7 +872,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     const T *x = xs + a.off[l];
     const T *b = bs + a.off[l];
 
-    for (int t = threadIdx.x; t < Nc; t += blockDim.x) {
+    for (int t = tid; t < Nc; t += blockDim.x) {
       int I, J, K;
       c_decode<DIM, T>(nc, t, I, J, K);
       T acc = T(0);
@@ -947,7 +921,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     // loads of a row group in flight together), then a wavefront sum.
     const int *n = a.n[last];
     const int N = n[0] * n[1] * n[2];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     const T *bl = bs + a.off[last];
     for (int r0 = 4 * wv; r0 < N; r0 += 4 * nw) {
       T acc[4] = {T(0), T(0), T(0), T(0)};
@@ -974,7 +948,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
       T xf[kCoarseLoads], xc[kCoarseLoads];
 #pragma unroll
       for (int q = 0; q < kCoarseLoads; ++q) {
-        const int t = threadIdx.x + q * blockDim.x;
+        const int t = tid + q * blockDim.x;
         if (t >= N) continue;
         int i, j, k;
         c_decode<DIM, T>(nf, t, i, j, k);
@@ -984,19 +958,62 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
       }
 #pragma unroll
       for (int q = 0; q < kCoarseLoads; ++q) {
-        const int t = threadIdx.x + q * blockDim.x;
+        const int t = tid + q * blockDim.x;
         if (t < N) xs[a.off[l] + t] = xf[q] + xc[q];
       }
     }
     __syncthreads();
     CSet<DIM, T> red, black;
-    c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red);
-    c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black);
+    c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red, tid);
+    c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black, tid);
     for (int s = 0; s < a.nu; ++s) {
       c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false, a.met);
       c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, false, a.met);
     }
   }
+}
+
+template <int DIM, typename T, bool VC = false>
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, const SolverScalars *sc) {
+  __shared__ T xs[kCoarseLds + 1];     // all coarse levels, then a zero slot
+  __shared__ T bs[kCoarseLds];
+  __shared__ T idg_s[kCoarseLev * 8];  // inverse diagonals, read with a per-cell index
+  __shared__ T rs[VC ? kCoarseLds + 1 : 1];  // densities of all coarse levels (variable coefficients)
+  if (sc->done) return;
+  const int last = a.nlev - 1;
+  const int zero_slot = kCoarseLds;
+  (void)last;
+  if (threadIdx.x < kCoarseLev * 8) idg_s[threadIdx.x] = a.idg[threadIdx.x >> 3][threadIdx.x & 7];
+  if (threadIdx.x == 0) xs[zero_slot] = T(0);
+  if constexpr (VC) {
+    const int ntot = a.off[last] + a.n[last][0] * a.n[last][1] * a.n[last][2];
+    for (int t = threadIdx.x; t < ntot; t += blockDim.x) rs[t] = a.rho_c[t];
+    if (threadIdx.x == 0) rs[zero_slot] = T(1);
+  }
+  {
+    // all loads of the right-hand side issued before any is used
+    const int *n = a.n[a.l0];
+    const int N = n[0] * n[1] * n[2];
+    T v[kCoarseLoads];
+#pragma unroll
+    for (int q = 0; q < kCoarseLoads; ++q) {
+      const int t = threadIdx.x + q * blockDim.x;
+      v[q] = T(0);
+      if (t < N) {
+        int i, j, k;
+        c_decode<DIM, T>(n, t, i, j, k);
+        const long g = a.L0.at(i, j, k);
+        v[q] = a.b0_double ? (T)((const double *)a.b0)[g] : ((const T *)a.b0)[g];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kCoarseLoads; ++q) {
+      const int t = threadIdx.x + q * blockDim.x;
+      if (t < N) bs[a.off[a.l0] + t] = v[q];
+    }
+    __syncthreads();
+  }
+  coarse_cycle<DIM, T, VC>(a, xs, bs, rs, idg_s, zero_slot, threadIdx.x);
   {
     const int *n = a.n[a.l0];
     const int N = n[0] * n[1] * n[2];

@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "lm_device.h"
@@ -691,6 +692,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_pack(Lay L, const T *r, T *out) {
 
 #include "lm_mg_kernels.h"
 #include "lm_mg3d.h"
+#include "lm_pcg_block.h"
 
 namespace lm {
 
@@ -909,6 +911,15 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   ws.p[1] = (double *)cv.take(fbytes);
   ws.q = (double *)cv.take(fbytes);
   ws.cgcg = !flexible;
+  // grids the one-block V-cycle covers from the finest level: the whole
+  // single-reduction solve in one workgroup (LM_BLOCK_PCG=0 turns it off)
+  {
+    const char *env = std::getenv("LM_BLOCK_PCG");
+    const bool off = env && env[0] == '0';
+    ws.block_pcg = !off && ws.cgcg && ws.lc == 0 && fine.ncells() <= (long)kCoarseLoads * kCoarseThreads;
+    // its scratch: 2 ndim + 1 coefficient vectors, p, s, w and r (compact cell order)
+    ws.blk = ws.block_pcg ? (double *)cv.take((size_t)(2 * fine.ndim + 5) * fine.ncells() * 8) : nullptr;
+  }
   ws.w = (double *)cv.take(fbytes);
   ws.s[0] = (double *)cv.take(fbytes);
   ws.s[1] = (double *)cv.take(fbytes);
@@ -1474,9 +1485,54 @@ static void iteration(hipStream_t st, PoissonWS &ws, CGArgs a, int k) {
   vcycle<DIM, T>(st, ws, k, a);
 }
 
+// The whole solve as one k_pcg_block launch (ws.block_pcg). With a log the
+// outcome is left on the device for the caller to read later; without one
+// this waits for it.
+template <int DIM, typename T>
+static hipError_t solve_block(hipStream_t st, PoissonWS &ws, const double *bvec, const double *x0, double rtol,
+                              int maxit, int *iters, double *relres, int *converged, SolveLog *log) {
+  BlockPCGArgs<T> pa;
+  pa.ca = coarse_args<T>(ws, ws.z[0], ws.r[0]);
+  pa.L = ws.lay;
+  pa.B = ws.bnd;
+  for (int d = 0; d < 3; ++d) {
+    pa.ih2[d] = ws.lev[0].ih2[d];
+    pa.ih[d] = std::sqrt(ws.lev[0].ih2[d]);
+  }
+  pa.b = bvec;
+  pa.x0 = x0;
+  pa.x = ws.x;
+  pa.rho = ws.vc ? ws.rho64 : nullptr;
+  pa.met = ws.met;
+  pa.vol = ws.met ? ws.vol : nullptr;
+  pa.mean_w = ws.met ? ws.volume : (double)ws.lay.ncells();
+  pa.tol2 = rtol * rtol;
+  pa.maxit = maxit;
+  pa.cf = ws.blk;
+  pa.sc = ws.sc;
+  pa.log = log;
+  ws.tol2 = pa.tol2;
+  if (ws.vc)
+    hipLaunchKernelGGL((k_pcg_block<DIM, T, true>), dim3(1), dim3(kCoarseThreads), 0, st, pa);
+  else
+    hipLaunchKernelGGL((k_pcg_block<DIM, T, false>), dim3(1), dim3(kCoarseThreads), 0, st, pa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || log) return e;
+  e = hipMemcpyAsync(ws.host_sc, ws.sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  const SolverScalars &h = *ws.host_sc;
+  *iters = h.iters;
+  *relres = h.cc > 0 ? std::sqrt(h.rr / h.cc) : 0.0;
+  *converged = h.done && !h.nonconv;
+  return hipSuccess;
+}
+
 template <int DIM, typename T>
 static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, const double *x0, double rtol,
-                            int maxit, int expect, int *iters, double *relres, int *converged) {
+                            int maxit, int expect, int *iters, double *relres, int *converged, SolveLog *log) {
+  if (ws.block_pcg) return solve_block<DIM, T>(st, ws, bvec, x0, rtol, maxit, iters, relres, converged, log);
+  if (log) return hipErrorInvalidValue;
   CGArgs a;
   a.L = ws.lay;
   a.B = ws.bnd;
@@ -1543,12 +1599,12 @@ static hipError_t solve_dim(hipStream_t st, PoissonWS &ws, const double *bvec, c
 }
 
 hipError_t poisson_solve(hipStream_t st, PoissonWS &ws, const double *b, const double *x0, double rtol,
-                         int maxit, int expect_iters, int *iters, double *relres, int *converged) {
+                         int maxit, int expect_iters, int *iters, double *relres, int *converged, SolveLog *log) {
   if (ws.lay.ndim == 3)
-    return ws.mixed ? solve_dim<3, float>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged)
-                    : solve_dim<3, double>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged);
-  return ws.mixed ? solve_dim<2, float>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged)
-                  : solve_dim<2, double>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged);
+    return ws.mixed ? solve_dim<3, float>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged, log)
+                    : solve_dim<3, double>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged, log);
+  return ws.mixed ? solve_dim<2, float>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged, log)
+                  : solve_dim<2, double>(st, ws, b, x0, rtol, maxit, expect_iters, iters, relres, converged, log);
 }
 
 // ---------------------------------------------------------------------------
