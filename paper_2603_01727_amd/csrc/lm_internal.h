@@ -257,6 +257,7 @@ struct PoissonWS {
   double *vol = nullptr;   // its cell volumes (fine layout, FP64)
   double *met_w = nullptr; // its cell widths per level and direction (x then y, level after level)
   double volume = 0.0;     // its domain area (the weight of the solution mean)
+  void *met_tab = nullptr; // its coarse-level spacing tables (MG precision)
   Lay lay;                 // fine layout (FP64 CG vectors)
   Bnd bnd;
   int nlev, lc;            // MG levels; first level handled by the coarse kernel

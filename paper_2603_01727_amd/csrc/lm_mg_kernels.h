@@ -646,7 +646,29 @@ struct CoarseArgs {
   const T *pinv;           // dense pseudo-inverse of the coarsest level
   const T *rho_c;          // variable coefficients: densities of levels l0.., packed at off[]
   int met = 0;             // stretched 2D grid: rho_c holds dx/dy (face_coef)
+  // stretched 2D grid: per level l >= l0 at toff[l] the cell widths wx[n0],
+  // wy[n1] and the face factors gx[n0], gy[n1] (g = 2 / (sum of the two
+  // widths across the face; the last face wraps when periodic, else 0)
+  const T *mtab = nullptr;
+  int mtab_n = 0;
+  int toff[kMaxLev];
 };
+
+// Stretched 2D grid: the four face coefficients (west, east, south, north)
+// of cell (i, j) of a level from its 1D tables: an x-face carries the
+// cell height over the distance between the two centres, dy_j 2/(dx_a +
+// dx_b), a y-face dx_i 2/(dy_a + dy_b), each times the level's scale.
+// Faces on a wall get 0 from the table.
+template <typename T>
+__device__ inline void m_faces(const T *tab, int toff, int n0, int n1, int i, int j, T ihx, T ihy, T cf[4]) {
+  const T *wx = tab + toff, *wy = wx + n0, *gx = wy + n1, *gy = gx + n0;
+  const int im = i > 0 ? i - 1 : n0 - 1, jm = j > 0 ? j - 1 : n1 - 1;
+  const T ay = ihx * wy[j], ax = ihy * wx[i];
+  cf[0] = ay * gx[im];
+  cf[1] = ay * gx[i];
+  cf[2] = ax * gy[jm];
+  cf[3] = ax * gy[j];
+}
 
 template <int DIM, typename T>
 __device__ inline void c_decode(const int n[3], int t, int &i, int &j, int &k) {
@@ -739,6 +761,7 @@ struct CSet {
   int c[2];             // LDS index of the cell, -1 when the slot is empty
   int nb[2][2 * DIM];   // LDS indices of the neighbours (-d, +d per direction)
   T idg[2];             // 1 / diagonal
+  int ij[2];            // stretched grid: i | j << 16 of the cell
 };
 
 // beta / h_d^2 of the face between LDS cells ia and ib, from the densities
@@ -750,7 +773,7 @@ __device__ inline T c_face(const T *rs, int ia, int ib, int zero_slot, T ih2, in
   return ib == zero_slot ? T(0) : ih2 * face_coef<T>(rs[ia], rs[ib], d, met);
 }
 
-template <int DIM, typename T, bool VC = false>
+template <int DIM, typename T, bool VC = false, bool MET = false>
 __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs, int l, int color, int zero_slot,
                              CSet<DIM, T> &s, int tid) {
   const int *n = a.n[l];
@@ -775,7 +798,12 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs
       code |= ((lo || per) && (hi || per)) ? (1 << d) : 0;
     }
     s.c[q] = off + c;
-    if constexpr (VC) {
+    if constexpr (MET) {
+      T cf[4];
+      m_faces<T>(rs, a.toff[l], n[0], n[1], i, j, a.ih2[l].v[0], a.ih2[l].v[1], cf);
+      s.idg[q] = T(1) / (((cf[0] + cf[1]) + cf[2]) + cf[3]);
+      s.ij[q] = i | (j << 16);
+    } else if constexpr (VC) {
       T dg = T(0);
 #pragma unroll
       for (int m = 0; m < 2 * DIM; ++m)
@@ -791,9 +819,31 @@ __device__ inline void c_set(const CoarseArgs<T> &a, const T *idg_s, const T *rs
 // diag, all LDS reads of the thread issued before the arithmetic.
 // (A missing neighbour is the zero slot: x = 0 there, so its term vanishes
 // whatever the coefficient.)
-template <int DIM, typename T, bool VC = false>
+template <int DIM, typename T, bool VC = false, bool MET = false>
 __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, T> &s, const T ih2[3],
-                               bool zero_init, int met) {
+                               bool zero_init, int met, int toff = 0, int n0 = 0, int n1 = 0) {
+  if constexpr (MET) {
+    // stretched 2D grid: coefficients from the level's 1D tables
+    T v[2][4], bv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (s.c[q] < 0) continue;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v[q][m] = xs[s.nb[q][m]];
+      bv[q] = bs[s.c[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (s.c[q] < 0) continue;
+      T cf[4];
+      m_faces<T>(rs, toff, n0, n1, s.ij[q] & 0xffff, s.ij[q] >> 16, ih2[0], ih2[1], cf);
+      T nbs = ((cf[0] * v[q][0] + cf[1] * v[q][1]) + cf[2] * v[q][2]) + cf[3] * v[q][3];
+      if (zero_init) nbs = T(0);
+      xs[s.c[q]] = (bv[q] + nbs) * s.idg[q];
+    }
+    __syncthreads();
+    return;
+  }
   if constexpr (VC && DIM == 3) {
     // one cell at a time (fewer live registers); cells of one colour read
     // only the other colour, so each result is stored at once
@@ -852,7 +902,7 @@ __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, 
 // caller that runs the cycle in a loop passes it through an opaque copy,
 // so the per-level cell sets are recomputed, not held across iterations).
 // Ends with a barrier.
-template <int DIM, typename T, bool VC>
+template <int DIM, typename T, bool VC, bool MET = false>
 __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseArgs<T> &a, T *xs, T *bs, const T *rs,
                                                                    const T *idg_s, int zero_slot,
                                                                    int tid) {
@@ -860,11 +910,11 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
   for (int l = a.l0; l < last; ++l) {
     {
       CSet<DIM, T> red, black;
-      c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red, tid);
-      c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black, tid);
+      c_set<DIM, T, VC, MET>(a, idg_s, rs, l, 0, zero_slot, red, tid);
+      c_set<DIM, T, VC, MET>(a, idg_s, rs, l, 1, zero_slot, black, tid);
       for (int s = 0; s < a.nu; ++s) {
-        c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, s == 0, a.met);
-        c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false, a.met);
+        c_sweep<DIM, T, VC, MET>(xs, bs, rs, red, a.ih2[l].v, s == 0, a.met, a.toff[l], a.n[l][0], a.n[l][1]);
+        c_sweep<DIM, T, VC, MET>(xs, bs, rs, black, a.ih2[l].v, false, a.met, a.toff[l], a.n[l][0], a.n[l][1]);
       }
     }
     const int *nf = a.n[l], *nc = a.n[l + 1];
@@ -884,7 +934,19 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
           for (int dx = 0; dx < 2; ++dx) {
             const int i = 2 * I + dx, j = 2 * J + dy, k = DIM == 3 ? 2 * K + dz : 0;
             const int c = i + nf[0] * (j + nf[1] * k);
-            if constexpr (VC) {
+            if constexpr (MET) {
+              const int off = a.off[l];
+              const bool pxp = a.B.periodic[0] != 0, pyp = a.B.periodic[1] != 0;
+              const int iw = i > 0 ? off + c - 1 : (pxp ? off + c + nf[0] - 1 : zero_slot);
+              const int ie = i + 1 < nf[0] ? off + c + 1 : (pxp ? off + c - (nf[0] - 1) : zero_slot);
+              const int is = j > 0 ? off + c - nf[0] : (pyp ? off + c + (nf[1] - 1) * nf[0] : zero_slot);
+              const int in = j + 1 < nf[1] ? off + c + nf[0] : (pyp ? off + c - (nf[1] - 1) * nf[0] : zero_slot);
+              T cf[4];
+              m_faces<T>(rs, a.toff[l], nf[0], nf[1], i, j, a.ih2[l].v[0], a.ih2[l].v[1], cf);
+              const T nbs = ((cf[0] * xs[iw] + cf[1] * xs[ie]) + cf[2] * xs[is]) + cf[3] * xs[in];
+              const T dg = ((cf[0] + cf[1]) + cf[2]) + cf[3];
+              acc += b[c] - (dg * x[c] - nbs);
+            } else if constexpr (VC) {
               // same neighbour rules and coefficients as c_set
               const int q[3] = {i, j, k};
               const int st[3] = {1, nf[0], nf[0] * nf[1]};
@@ -964,16 +1026,16 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
     }
     __syncthreads();
     CSet<DIM, T> red, black;
-    c_set<DIM, T, VC>(a, idg_s, rs, l, 0, zero_slot, red, tid);
-    c_set<DIM, T, VC>(a, idg_s, rs, l, 1, zero_slot, black, tid);
+    c_set<DIM, T, VC, MET>(a, idg_s, rs, l, 0, zero_slot, red, tid);
+    c_set<DIM, T, VC, MET>(a, idg_s, rs, l, 1, zero_slot, black, tid);
     for (int s = 0; s < a.nu; ++s) {
-      c_sweep<DIM, T, VC>(xs, bs, rs, black, a.ih2[l].v, false, a.met);
-      c_sweep<DIM, T, VC>(xs, bs, rs, red, a.ih2[l].v, false, a.met);
+      c_sweep<DIM, T, VC, MET>(xs, bs, rs, black, a.ih2[l].v, false, a.met, a.toff[l], a.n[l][0], a.n[l][1]);
+      c_sweep<DIM, T, VC, MET>(xs, bs, rs, red, a.ih2[l].v, false, a.met, a.toff[l], a.n[l][0], a.n[l][1]);
     }
   }
 }
 
-template <int DIM, typename T, bool VC = false>
+template <int DIM, typename T, bool VC = false, bool MET = false>
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, const SolverScalars *sc) {
   __shared__ T xs[kCoarseLds + 1];     // all coarse levels, then a zero slot
   __shared__ T bs[kCoarseLds];
@@ -985,7 +1047,9 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
   (void)last;
   if (threadIdx.x < kCoarseLev * 8) idg_s[threadIdx.x] = a.idg[threadIdx.x >> 3][threadIdx.x & 7];
   if (threadIdx.x == 0) xs[zero_slot] = T(0);
-  if constexpr (VC) {
+  if constexpr (MET) {
+    for (int t = threadIdx.x; t < a.mtab_n; t += blockDim.x) rs[t] = a.mtab[t];
+  } else if constexpr (VC) {
     const int ntot = a.off[last] + a.n[last][0] * a.n[last][1] * a.n[last][2];
     for (int t = threadIdx.x; t < ntot; t += blockDim.x) rs[t] = a.rho_c[t];
     if (threadIdx.x == 0) rs[zero_slot] = T(1);
@@ -1013,7 +1077,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(CoarseArgs<T> a, c
     }
     __syncthreads();
   }
-  coarse_cycle<DIM, T, VC>(a, xs, bs, rs, idg_s, zero_slot, threadIdx.x);
+  coarse_cycle<DIM, T, VC, MET>(a, xs, bs, rs, idg_s, zero_slot, threadIdx.x);
   {
     const int *n = a.n[a.l0];
     const int N = n[0] * n[1] * n[2];

@@ -46,7 +46,7 @@ __device__ inline void pb_nbrs(const int n[3], const Bnd &B, int i, int j, int k
   }
 }
 
-template <int DIM, typename T, bool VC>
+template <int DIM, typename T, bool VC, bool MET = false>
 __global__ void __launch_bounds__(kCoarseThreads) k_pcg_block(BlockPCGArgs<T> a) {
 #pragma clang fp contract(off)
   __shared__ T xs[kCoarseLds + 1];
@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(kCoarseThreads) k_pcg_block(BlockPCGArgs<T> a)
   const int last = ca.nlev - 1;
   if (tid < kCoarseLev * 8) idg_s[tid] = ca.idg[tid >> 3][tid & 7];
   if (tid == 0) xs[zero_slot] = T(0);
-  if constexpr (VC) {
+  if constexpr (MET) {
+    for (int t = tid; t < ca.mtab_n; t += blockDim.x) rs[t] = ca.mtab[t];
+  } else if constexpr (VC) {
     const int ntot = ca.off[last] + ca.n[last][0] * ca.n[last][1] * ca.n[last][2];
     for (int t = tid; t < ntot; t += blockDim.x) rs[t] = ca.rho_c[t];
     if (tid == 0) rs[zero_slot] = T(1);
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_pcg_block(BlockPCGArgs<T> a)
     int tv = tid, zs = zero_slot;
     asm volatile("" : "+v"(tv), "+s"(zs));
     __syncthreads();
-    coarse_cycle<DIM, T, VC>(ca, xs, bs, rs, idg_s, zs, tv);
+    coarse_cycle<DIM, T, VC, MET>(ca, xs, bs, rs, idg_s, zs, tv);
     gam = del = rr = 0.0;
 #pragma unroll 1
     for (int q = 0; q < NC; ++q) {

@@ -970,11 +970,18 @@ bool poisson_plan(PoissonWS &ws, Carver &cv, const Lay &fine, const Bnd &B, cons
   ws.sc = (SolverScalars *)cv.take(sizeof(SolverScalars));
   ws.vol = nullptr;
   ws.met_w = nullptr;
+  ws.met_tab = nullptr;
   if (ws.met) {
-    long nw = 0;
+    long nw = 0, nt = 0;
     for (int l = 0; l < nl; ++l) nw += ws.lev[l].lay.n[0] + ws.lev[l].lay.n[1];
+    for (int l = ws.lc; l < nl; ++l) nt += 2 * (ws.lev[l].lay.n[0] + ws.lev[l].lay.n[1]);
+    if (nt > kCoarseLds) {
+      if (err) *err = "stretched grid: the coarse levels' spacing tables exceed the one-block kernel's LDS";
+      return false;
+    }
     ws.vol = (double *)cv.take(fbytes);
     ws.met_w = (double *)cv.take((size_t)nw * 8);
+    ws.met_tab = cv.take((size_t)nt * eb);
   }
   return true;
 }
@@ -1320,6 +1327,13 @@ static CoarseArgs<T> coarse_args(PoissonWS &ws, void *z, const double *r) {
   ca.pinv = (const T *)(ws.vc ? ws.pinv_vc : ws.pinv);
   ca.rho_c = ws.vc ? (const T *)ws.rho_c : nullptr;
   ca.met = ws.met;
+  int toff = 0;
+  for (int l = 0; l < kMaxLev; ++l) {
+    ca.toff[l] = toff;
+    if (ws.met && l >= ws.lc && l < ws.nlev) toff += 2 * (ws.lev[l].lay.n[0] + ws.lev[l].lay.n[1]);
+  }
+  ca.mtab = ws.met ? (const T *)ws.met_tab : nullptr;
+  ca.mtab_n = ws.met ? toff : 0;
   return ca;
 }
 
@@ -1382,7 +1396,10 @@ static void vcycle(hipStream_t st, PoissonWS &ws, int k, const CGArgs &cg) {
                            (const T *)ws.lev[l].b, (T *)ws.lev[l + 1].b, sc, rl, ws.met);
     }
   }
-  if (ws.vc)
+  if (DIM == 2 && ws.met)
+    hipLaunchKernelGGL((k_mg_coarse<DIM, T, true, DIM == 2>), dim3(1), dim3(kCoarseThreads), 0, st,
+                       coarse_args<T>(ws, z, r), sc);
+  else if (ws.vc)
     hipLaunchKernelGGL((k_mg_coarse<DIM, T, true>), dim3(1), dim3(kCoarseThreads), 0, st, coarse_args<T>(ws, z, r), sc);
   else
     hipLaunchKernelGGL((k_mg_coarse<DIM, T>), dim3(1), dim3(kCoarseThreads), 0, st, coarse_args<T>(ws, z, r), sc);
@@ -1512,7 +1529,9 @@ static hipError_t solve_block(hipStream_t st, PoissonWS &ws, const double *bvec,
   pa.sc = ws.sc;
   pa.log = log;
   ws.tol2 = pa.tol2;
-  if (ws.vc)
+  if (DIM == 2 && ws.met)
+    hipLaunchKernelGGL((k_pcg_block<DIM, T, true, DIM == 2>), dim3(1), dim3(kCoarseThreads), 0, st, pa);
+  else if (ws.vc)
     hipLaunchKernelGGL((k_pcg_block<DIM, T, true>), dim3(1), dim3(kCoarseThreads), 0, st, pa);
   else
     hipLaunchKernelGGL((k_pcg_block<DIM, T, false>), dim3(1), dim3(kCoarseThreads), 0, st, pa);
@@ -1701,8 +1720,40 @@ hipError_t poisson_set_metric(hipStream_t st, PoissonWS &ws, const double *wx, c
     cy.swap(ny);
   }
   ws.volume = V;
+  // the coarse kernel's tables: per level l >= lc the widths and the face
+  // factors 2 / (w_a + w_b) (the last face wraps when periodic, else 0)
+  std::vector<double> tab;
+  {
+    size_t off = 0;
+    for (int l = 0; l < ws.nlev; ++l) {
+      const int n0 = ws.lev[l].lay.n[0], n1 = ws.lev[l].lay.n[1];
+      if (l >= ws.lc) {
+        const double *lx = all.data() + off, *ly = lx + n0;
+        auto faces = [&](const double *w, int n, int periodic) {
+          for (int q = 0; q < n; ++q) {
+            if (q + 1 < n)
+              tab.push_back(2.0 / (w[q] + w[q + 1]));
+            else
+              tab.push_back(periodic ? 2.0 / (w[q] + w[0]) : 0.0);
+          }
+        };
+        tab.insert(tab.end(), lx, lx + n0);
+        tab.insert(tab.end(), ly, ly + n1);
+        faces(lx, n0, ws.bnd.periodic[0]);
+        faces(ly, n1, ws.bnd.periodic[1]);
+      }
+      off += n0 + n1;
+    }
+  }
   hipError_t e = hipMemcpyAsync(ws.met_w, all.data(), all.size() * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && ws.mixed) {
+    std::vector<float> tf(tab.begin(), tab.end());
+    e = hipMemcpyAsync(ws.met_tab, tf.data(), tf.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  } else if (e == hipSuccess) {
+    e = hipMemcpyAsync(ws.met_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
   if (e != hipSuccess) return e;
   return ws.mixed ? set_metric_t<float>(st, ws) : set_metric_t<double>(st, ws);
 }

@@ -6,8 +6,12 @@ volume-weighted pressure equation (sum dV P = 0).
 Parity: fields and p0 against the FP64 oracle step by step (relative L2
 <= 1e-10 per field, Poisson solved to 1e-13) on tanh-clustered cavities
 (both directions, one direction, slip walls), a smoothly stretched periodic
-box, and the bare pressure solve."""
+box, and the bare pressure solve. Validation: the Ra = 10^2 cavity of
+Table 3 (largest cell twice the smallest) on 32^2 and 64^2 clustered grids
+marched to the paper's steady-state criterion; their second-order
+extrapolation against the limit of the table's finest rows."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -19,6 +23,7 @@ from _cases import oracle_for, gpu_for, compare, rel_l2
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "tab34_max_spacing.txt")
 C_SUTH = 110.5 / 600.0
 
 
@@ -145,3 +150,55 @@ def test_stretched_call_errors():
         s.project(b, rho=np.ones_like(b))
     assert e.value.status == lib.LM_EUNSUPPORTED
     s.step(2)                                   # the context still steps
+
+
+def _table3_rows():
+    rows = {}
+    for line in open(GOLD):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            m, n, _, p0 = line.split()
+            if float(m) == 2.0:
+                rows[int(n)] = float(p0)
+    return rows
+
+
+def _steady_p0(n, chunk):
+    """p0 of the clustered (m = 2) cavity once |d_t p0| <= 1e-6 (the
+    paper's steady-state criterion, checked over chunks of steps)."""
+    case = heated_cavity_case(n=n, m=2.0)
+    s = gpu_for(case, rtol=1e-10)
+    dt = s.dt
+    p_prev, dp = 1.0, 1.0
+    for it in range(2000):
+        st = s.step(chunk)
+        dp = (st["p0"] - p_prev) / (chunk * dt)
+        p_prev = st["p0"]
+        if it % 10 == 0:
+            print(n, "t", st["time"], "p0", st["p0"], "dp0/dt", dp, flush=True)
+        if abs(dp) <= 1e-6 and st["time"] > 2.0:
+            break
+    assert abs(dp) <= 1e-6
+    print(n, "steady p0", st["p0"], "at t", st["time"], flush=True)
+    return st["p0"]
+
+
+@pytest.mark.timeout(900)
+def test_clustered_cavity_table3():
+    """Table 3, Ra = 10^2, largest cell twice the smallest: the table's p0
+    falls at second order to a limit of 0.957364 (its two finest rows,
+    0.95740 and 0.95738, extrapolated with grid ratio 1.5; their five
+    printed digits leave about 1.3e-5 of uncertainty). The 32^2 and 64^2
+    grids here extrapolate (ratio 2) to that limit within 2e-5. Grid by
+    grid the values differ from the table's by a second-order error of
+    another constant (the 64^2 grid lies above its row by less than the
+    table's own 64^2-to-216^2 spread)."""
+    rows = _table3_rows()
+    limit = rows[216] + (rows[216] - rows[144]) / (1.5 ** 2 - 1.0)
+    p32 = _steady_p0(32, 500)
+    p64 = _steady_p0(64, 2000)
+    rich = p64 + (p64 - p32) / 3.0
+    print("p0 32", p32, "64", p64, "extrapolated", rich, "table limit", limit, "table 64", rows[64], flush=True)
+    assert p32 > p64 > rich
+    assert abs(rich - limit) <= 2e-5, (rich, limit)
+    assert abs(p64 - rows[64]) <= abs(rows[64] - rows[216]), (p64, rows[64])
