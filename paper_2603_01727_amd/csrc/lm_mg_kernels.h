@@ -824,12 +824,13 @@ __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, 
                                bool zero_init, int met, int toff = 0, int n0 = 0, int n1 = 0) {
   if constexpr (MET) {
     // stretched 2D grid: coefficients from the level's 1D tables
-    T v[2][4], bv[2];
+    T v[2][4] = {}, bv[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (s.c[q] < 0) continue;
+      if (!zero_init)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) v[q][m] = xs[s.nb[q][m]];
+        for (int m = 0; m < 4; ++m) v[q][m] = xs[s.nb[q][m]];
       bv[q] = bs[s.c[q]];
     }
 #pragma unroll
@@ -863,12 +864,13 @@ __device__ inline void c_sweep(T *xs, const T *bs, const T *rs, const CSet<DIM, 
     __syncthreads();
     return;
   }
-  T v[2][2 * DIM], bv[2], rv[2][VC ? 2 * DIM + 1 : 1];
+  T v[2][2 * DIM] = {}, bv[2], rv[2][VC ? 2 * DIM + 1 : 1];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     if (s.c[q] < 0) continue;
+    if (!zero_init)  // a sweep from zero reads no neighbours
 #pragma unroll
-    for (int m = 0; m < 2 * DIM; ++m) v[q][m] = xs[s.nb[q][m]];
+      for (int m = 0; m < 2 * DIM; ++m) v[q][m] = xs[s.nb[q][m]];
     bv[q] = bs[s.c[q]];
     if constexpr (VC) {
 #pragma unroll
@@ -922,6 +924,9 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
     const T *x = xs + a.off[l];
     const T *b = bs + a.off[l];
 
+    // After the last black half-sweep the black cells' residuals vanish
+    // (each was just solved for with its red neighbours final), so only the
+    // red children (dx + dy + dz even) are summed (nu >= 1 always).
     for (int t = tid; t < Nc; t += blockDim.x) {
       int I, J, K;
       c_decode<DIM, T>(nc, t, I, J, K);
@@ -931,7 +936,7 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
       for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
 #pragma unroll kUnroll
         for (int dy = 0; dy < 2; ++dy)
-          for (int dx = 0; dx < 2; ++dx) {
+          for (int dx = (dy + dz) & 1; dx < 2; dx += 2) {
             const int i = 2 * I + dx, j = 2 * J + dy, k = DIM == 3 ? 2 * K + dz : 0;
             const int c = i + nf[0] * (j + nf[1] * k);
             if constexpr (MET) {
@@ -978,27 +983,23 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
     __syncthreads();
   }
   {
-    // x = pinv b on the coarsest level: each wavefront takes 4 rows at a
-    // time, its lanes stride over the columns (coalesced rows of pinv, all
-    // loads of a row group in flight together), then a wavefront sum.
+    // x = pinv b on the coarsest level: 16 lanes per row, each summing a
+    // strided quarter-row share (coalesced: a wavefront reads four row
+    // segments), then a 16-lane xor-shuffle sum; rows beyond the block's
+    // 64 groups of 16 are taken in further rounds.
     const int *n = a.n[last];
     const int N = n[0] * n[1] * n[2];
-    const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     const T *bl = bs + a.off[last];
-    for (int r0 = 4 * wv; r0 < N; r0 += 4 * nw) {
-      T acc[4] = {T(0), T(0), T(0), T(0)};
-      for (int col = lane; col < N; col += 64) {
-        const T bv = bl[col];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (r0 + q < N) acc[q] += a.pinv[(long)(r0 + q) * N + col] * bv;
+    const int part = tid & 15, ngroups = blockDim.x >> 4;
+    for (int r = tid >> 4; r - (tid >> 4) < N; r += ngroups) {  // uniform trip count per wavefront
+      T acc = T(0);
+      if (r < N) {
+        const T *row = a.pinv + (long)r * N;
+        for (int col = part; col < N; col += 16) acc += row[col] * bl[col];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T v = acc[q];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (lane == 0 && r0 + q < N) xs[a.off[last] + r0 + q] = v;
-      }
+      for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+      if (part == 0 && r < N) xs[a.off[last] + r] = acc;
     }
     __syncthreads();
   }
@@ -1006,23 +1007,27 @@ __device__ __attribute__((always_inline)) inline void coarse_cycle(const CoarseA
     const int *nf = a.n[l], *nc = a.n[l + 1];
     const int N = nf[0] * nf[1] * nf[2];
     {
-      // piecewise-constant prolongation, all reads before the writes
-      T xf[kCoarseLoads], xc[kCoarseLoads];
+      // piecewise-constant prolongation to the red cells: the first
+      // post-smoothing half-sweep solves every black cell from its red
+      // neighbours, so the black cells' corrected values would be discarded
+      const int Nr = N >> 1;
+      T xf[2], xc[2];
+      int cf_[2];
 #pragma unroll
-      for (int q = 0; q < kCoarseLoads; ++q) {
+      for (int q = 0; q < 2; ++q) {
         const int t = tid + q * blockDim.x;
-        if (t >= N) continue;
+        cf_[q] = -1;
+        if (t >= Nr) continue;
         int i, j, k;
-        c_decode<DIM, T>(nf, t, i, j, k);
+        const int c = c_colour_cell<DIM, T>(a, l, 0, t, i, j, k);
         const int pc = (i >> 1) + nc[0] * ((j >> 1) + nc[1] * (DIM == 3 ? (k >> 1) : 0));
-        xf[q] = xs[a.off[l] + t];
+        cf_[q] = a.off[l] + c;
+        xf[q] = xs[cf_[q]];
         xc[q] = xs[a.off[l + 1] + pc];
       }
 #pragma unroll
-      for (int q = 0; q < kCoarseLoads; ++q) {
-        const int t = tid + q * blockDim.x;
-        if (t < N) xs[a.off[l] + t] = xf[q] + xc[q];
-      }
+      for (int q = 0; q < 2; ++q)
+        if (cf_[q] >= 0) xs[cf_[q]] = xf[q] + xc[q];
     }
     __syncthreads();
     CSet<DIM, T> red, black;
