@@ -904,7 +904,7 @@ struct RhsArgs {
 // predicted momentum on interior faces and the prescribed flux on boundary
 // faces (Eq 3.9-3.11, 3.17-3.19, 3.24, 3.33). The last block forms mean(b)
 // (periodic / closed) or the uniform outflow shift that makes sum(b) = 0.
-template <int DIM>
+template <int DIM, bool MET = false>
 __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, RhsArgs a) {
   __shared__ double sh[kBlock / 64];
   CellPos p;
@@ -917,9 +917,9 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
       const double *Md = a.M[d];
       const int q = coord(p, d);
       const long nh = nbr(L, B, c, q, d, +1), nl = nbr(L, B, c, q, d, -1);
-      const double Gh = nh >= 0 ? face_interp(P.met, L, d, q + 1, Md[c], Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
-      const double Gl = nl >= 0 ? face_interp(P.met, L, d, q, Md[nl], Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
-      div = div + (Gh - Gl) * (P.met ? met_view(P.met, L, d).iwid[q + 1] : P.ih[d]);
+      const double Gh = nh >= 0 ? face_interp(MET ? P.met : nullptr, L, d, q + 1, Md[c], Md[nh]) : boundary_flux(L, B, sd, Md, p, d, 1);
+      const double Gl = nl >= 0 ? face_interp(MET ? P.met : nullptr, L, d, q, Md[nl], Md[c]) : boundary_flux(L, B, sd, Md, p, d, 0);
+      div = div + (Gh - Gl) * (MET ? met_view(P.met, L, d).iwid[q + 1] : P.ih[d]);
     }
     double drho;
     if (a.bdf2)
@@ -930,7 +930,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Lay L, Bnd B, Phys P, Sides sd, 
     const double src = a.S_m ? drho - a.S_m[c] : drho;
     const double b = div + src;
     a.b[c] = b;
-    part = P.met ? b * P.vol[c] : b;   // stretched: the integral of b
+    part = MET ? b * P.vol[c] : b;   // stretched: the integral of b
   }
   const double s = block_sum(part, sh);
   if (linear_tid() == 0) a.partials[linear_block()] = s;
@@ -981,6 +981,8 @@ hipError_t launch_rhs(hipStream_t st, const Lay &L, const Bnd &B, const Phys &P,
   dim3 g = grid_for(L), bl(kBX, kBY);
   if (L.ndim == 3)
     hipLaunchKernelGGL(k_rhs<3>, g, bl, 0, st, L, B, P, sd, a);
+  else if (P.met)
+    hipLaunchKernelGGL((k_rhs<2, true>), g, bl, 0, st, L, B, P, sd, a);
   else
     hipLaunchKernelGGL(k_rhs<2>, g, bl, 0, st, L, B, P, sd, a);
   hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kBlock), 0, st, (const double *)partials, (int)nblocks_for(L),
@@ -1000,7 +1002,7 @@ struct ProjArgs {
 // boundary faces (Eq 3.23; outflow faces carry the uniform shift);
 // v = (M - delta_2 P)/rho_new (Eq 3.25) with P ghosts by quadratic
 // extrapolation at non-periodic sides (Eq 3.27-3.28); P stored zero-mean.
-template <int DIM>
+template <int DIM, bool MET = false>
 __global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides sd, ProjArgs a) {
   CellPos p;
   if (!cell_of_thread(L, p)) return;
@@ -1018,13 +1020,13 @@ __global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides 
     double xp, xm;
     if (nh >= 0) {
       xp = x ? x[nh] : 0.0;
-      const double G = face_interp(P.met, L, d, q + 1, Md[c], Md[nh]);
-      a.F[d][c] = G - (xp - xc) * (P.met ? met_view(P.met, L, d).idfc[q + 1] : P.ih[d]);
+      const double G = face_interp(MET ? P.met : nullptr, L, d, q + 1, Md[c], Md[nh]);
+      a.F[d][c] = G - (xp - xc) * (MET ? met_view(P.met, L, d).idfc[q + 1] : P.ih[d]);
     } else {
       double G = boundary_flux(L, B, sd, Md, p, d, 1);
       if (B.kind[d][1] == LM_SIDE_OUTFLOW) G -= oc;
       a.F[d][c] = G;
-      if (!P.met)
+      if (!MET)
         xp = x ? 3.0 * xc - 3.0 * x[c - sdd] + x[c - 2 * sdd] : 0.0;
       else  // Eq 3.28 with the stretched positions
         xp = x ? P.gx[d][1][0] * xc + P.gx[d][1][1] * x[c - sdd] + P.gx[d][1][2] * x[c - 2 * sdd] : 0.0;
@@ -1032,19 +1034,19 @@ __global__ void __launch_bounds__(kBlock) k_project(Lay L, Bnd B, Phys P, Sides 
     if (nl >= 0) {
       xm = x ? x[nl] : 0.0;
       if (q == 0) {  // periodic: duplicate of the wrapped face, same arithmetic
-        const double G = face_interp(P.met, L, d, 0, Md[nl], Md[c]);
-        a.F[d][c - sdd] = G - (xc - xm) * (P.met ? met_view(P.met, L, d).idfc[0] : P.ih[d]);
+        const double G = face_interp(MET ? P.met : nullptr, L, d, 0, Md[nl], Md[c]);
+        a.F[d][c - sdd] = G - (xc - xm) * (MET ? met_view(P.met, L, d).idfc[0] : P.ih[d]);
       }
     } else {
       double G = boundary_flux(L, B, sd, Md, p, d, 0);
       if (B.kind[d][0] == LM_SIDE_OUTFLOW) G += oc;
       a.F[d][c - sdd] = G;
-      if (!P.met)
+      if (!MET)
         xm = x ? 3.0 * xc - 3.0 * x[c + sdd] + x[c + 2 * sdd] : 0.0;
       else
         xm = x ? P.gx[d][0][0] * xc + P.gx[d][0][1] * x[c + sdd] + P.gx[d][0][2] * x[c + 2 * sdd] : 0.0;
     }
-    const double v = P.met ? (Md[c] - (xp - xm) * met_view(P.met, L, d).id2[q]) / a.rho_new[c]
+    const double v = MET ? (Md[c] - (xp - xm) * met_view(P.met, L, d).id2[q]) / a.rho_new[c]
                            : (Md[c] - (xp - xm) / (2.0 * P.h[d])) / a.rho_new[c];
     a.v[d][c] = v;
     bad |= !isfinite(v);
@@ -1071,6 +1073,8 @@ hipError_t launch_project(hipStream_t st, const Lay &L, const Bnd &B, const Phys
   dim3 g = grid_for(L), bl(kBX, kBY);
   if (L.ndim == 3)
     hipLaunchKernelGGL(k_project<3>, g, bl, 0, st, L, B, P, sd, a);
+  else if (P.met)
+    hipLaunchKernelGGL((k_project<2, true>), g, bl, 0, st, L, B, P, sd, a);
   else
     hipLaunchKernelGGL(k_project<2>, g, bl, 0, st, L, B, P, sd, a);
   return hipGetLastError();

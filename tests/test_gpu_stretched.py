@@ -98,6 +98,45 @@ def test_periodic_stretched_box_matches_oracle(precision):
     _run_parity(case, 3, precision)
 
 
+def _reacting_stretched_case(n=(48, 40), seed=29):
+    """Periodic 2D flame-sheet box on smoothly stretched faces: mixture
+    fraction across the stoichiometric value (Z in [0, 3], the sheet at Z =
+    1), H near its uniform value, unequal Lewis numbers."""
+    from workloads import fourier_temperature, solenoidal_velocity
+    from workloads.ics import QS_C3
+    L = (2 * math.pi, 2 * math.pi)
+    rng = np.random.default_rng(seed)
+    S = 1.0 / 0.055 - 1.0
+    w = fourier_temperature(n, L, rng, 3, 1.0, m=8)
+    Z = 3.0 * (w - w.min()) / (w.max() - w.min())
+    H = 1.0 / QS_C3 + 1.0 + 0.02 * (fourier_temperature(n, L, rng, 3, 1.0, m=8) - 1.5)
+    v = solenoidal_velocity(n, L, rng, 3, 0.1, m=8)
+    params = dict(Re=150.0, Pr=0.7, Le_F=1.3, Le_O=0.9, reacting=1, S=S, qs=QS_C3, eps=0.5, tol=1e-3,
+                  p0=1.0, dt=0.02)
+    faces = [sine_stretched_faces(n[0], 0.5, L[0], 0.15), sine_stretched_faces(n[1], 0.4, L[1], 0.6)]
+    return Case("react2d_stretched", 2, tuple(n) + (1,), L + (1.0,), (("periodic", "periodic"),) * 2, params,
+                None, v, Z=Z, H=H, faces=faces)
+
+
+def test_reacting_stretched_matches_oracle():
+    """The flame sheet (Z diffusion at unequal Lewis numbers, its H
+    coupling, T(Z, H)) on a stretched periodic grid."""
+    print("reacting stretched", flush=True)
+    _run_parity(_reacting_stretched_case(), 4)
+
+
+def test_immersed_cylinders_stretched_matches_oracle():
+    """Penalised Taylor-Couette cylinders (section 4.3) on a stretched
+    periodic grid: the mask, targets and penalisation per cell with the
+    local spacings everywhere else."""
+    from workloads import taylor_couette_case
+    case = taylor_couette_case(n=48)
+    Lx = case.L[0]
+    case.faces = [sine_stretched_faces(48, 0.4, Lx, 0.25), sine_stretched_faces(48, 0.3, Lx, 0.7)]
+    print("immersed cylinders stretched", flush=True)
+    _run_parity(case, 3)
+
+
 def _project_case(n, L, bc, faces, precision):
     from paper_2603_01727_amd import Solver
     _, b = variable_coefficient_problem(n, L, seed=41, kmax=4)
