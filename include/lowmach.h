@@ -246,7 +246,10 @@ lm_status lm_workspace_size(const lm_grid *grid, const lm_params *params, size_t
  * one-thread-per-cell kernel in 3D; "lds" or "direct", that form in both
  * (grids whose planes do not tile by 64 x 4, and 3D grids with an
  * immersed body, always take the one-thread-per-cell kernel). The forms
- * compute the same arithmetic.                                              */
+ * compute the same arithmetic. LM_BLOCK_PCG=0, also read here, keeps
+ * grids of at most 4096 cells on the multi-kernel pressure solve (by
+ * default their whole solve runs in one workgroup and lm_step checks its
+ * outcome after the step); the equations and the tolerance are the same.   */
 lm_status lm_init_grid(const lm_grid *grid, const lm_params *params, void *dev_workspace,
                        size_t bytes, void *hip_stream, lm_ctx **out);
 
