@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-c2", action="store_true", help="skip the 2D 1024^2 workload")
     ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^2, slot-flame and 512^2 workloads")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 512^2 200-step gradient")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for HBM counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB", help="summarise a rocprofv3 kernel-trace database")
@@ -298,6 +299,56 @@ def bench_configs(steps=20, warmup=3):
     return out
 
 
+def adjoint_block(every=20):
+    """The adjoint workload: 512^2 periodic random modes, its full length
+    (200 steps), checkpoints every 20 steps: the gradient of the final
+    kinetic energy with respect to T0 (the checkpointed forward run, then
+    the reverse sweep, which replays each segment forward to tape its states
+    and runs the adjoint steps back through it), against the same steps
+    forward only. Fixed time step (the CFL step of the initial state), the
+    Poisson solves of both sweeps to 1e-10."""
+    import torch
+    from paper_2603_01727_amd import Solver
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    from workloads import c5_case
+    case = c5_case()
+    nsteps = case.nsteps
+    kw = dict(bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], poisson_rtol=1e-10, poisson_maxit=400)
+    probe = Solver(case.n[:2], case.L[:2], cfl=case.params["cfl"], **kw)
+    probe.set(T=case.T, v=case.v)
+    dt = probe.dt
+    probe.close()
+    s = Solver(case.n[:2], case.L[:2], dt=dt, with_adjoint=True, **kw)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(x, dtype=torch.float64, device="cuda") for x in case.v]
+    J = final_kinetic_energy(s, T0, v0, 4, 2)      # warm-up of both sweeps
+    J.backward()
+    T0.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = final_kinetic_energy(s, T0, v0, nsteps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.set(T=case.T, v=case.v)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    s.step(nsteps)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    s.close()
+    fwd = t4 - t3
+    return dict(workload=f"2D periodic 2pi box 512^2, random modes |k|<=8, density ratio 4, Re=300, Pr=0.7, "
+                         f"{nsteps} steps of dt={dt:.6g}, gradient of the final kinetic energy w.r.t. T0",
+                checkpoint_every=every, gradient_s=round(t2 - t0, 4),
+                forward_with_checkpoints_s=round(t1 - t0, 4), reverse_sweep_s=round(t2 - t1, 4),
+                forward_only_s=round(fwd, 4), gradient_over_forward=round((t2 - t0) / fwd, 3),
+                reverse_ms_per_step=round((t2 - t1) / nsteps * 1e3, 4),
+                J=float(J.item()), grad_norm=float(T0.grad.norm().item()))
+
+
 ORACLE_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O", "Da_ib",
                "p0", "dt", "cfl")
 
@@ -479,6 +530,7 @@ def main():
     c2 = None if a.no_c2 else c2_block()
     forms = None if a.no_vc else poisson_forms()
     configs = None if a.no_configs else bench_configs()
+    adj = None if a.no_adjoint else adjoint_block()
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
         "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",
@@ -498,6 +550,7 @@ def main():
         "c2_1024": c2,
         "poisson_forms": forms,
         "other_workloads": configs,
+        "adjoint_c5": adj,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
