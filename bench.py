@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^2, slot-flame and 512^2 workloads")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 512^2 200-step gradient")
+    ap.add_argument("--small", choices=("c1", "c2"), help="only the 64^2 (c1) or 1024^2 (c2) FP64 steps "
+                    "(for kernel traces of the small-grid paths)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for HBM counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB", help="summarise a rocprofv3 kernel-trace database")
@@ -445,6 +447,18 @@ def summarize_trace(db_path):
         fw = _full_work(d)
         print(f"k_cgcg_update iteration {'1' if k == 1 else '>= 2'}: n {len(d)}, full-work n {len(fw)} "
               f"mean {sum(fw) / len(fw):.2f} us")
+    # time between consecutive dispatches (end of one to start of the next)
+    # inside the runs of work, i.e. leaving out pauses of 1 ms and more
+    # (set-up, host work between workloads)
+    tl = db.execute("select start, end from kernels order by start").fetchall()
+    gaps = [(tl[i + 1][0] - tl[i][1]) * 1e-3 for i in range(len(tl) - 1)]
+    gaps = [g for g in gaps if g < 1000.0]
+    if gaps:
+        gs = sorted(gaps)
+        busy = sum((e - b) * 1e-3 for b, e in tl)
+        print(f"dispatch gaps inside runs of work: n {len(gs)}, median {gs[len(gs) // 2]:.2f} us, mean "
+              f"{sum(gs) / len(gs):.2f} us, total {sum(gs) / 1e3:.3f} ms against {busy / 1e3:.3f} ms of kernel time "
+              f"(under the profiler, which lengthens both)")
 
 
 def _pmc_rows(db_path, counter):
@@ -506,6 +520,15 @@ def main():
         return
     if a.summarize_pmc:
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.traffic_out)
+        return
+    if a.small:
+        from workloads import c1_case, c2_case
+        case = c1_case() if a.small == "c1" else c2_case()
+        r = time_solver(case, "fp64", a.steps, a.warmup)
+        r["solver"].close()
+        print(json.dumps({"workload": case.name, "steps": a.steps, "warmup": a.warmup,
+                          "ms_per_step": round(r["ms_per_step"], 4),
+                          "poisson_iters_per_solve": r["poisson_iters_per_solve"]}))
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU: --gpus must be 1 (the step has no "
