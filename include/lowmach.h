@@ -313,9 +313,10 @@ lm_status lm_load_state(lm_ctx *ctx, const void *dev_buf);
 
 /* ---- adjoint of the step (reverse mode, hand-written) ---------------------
  * The adjoint state is the cotangent of the context's state: fields H, v,
- * F (faces) and the history rho^{n-1}, R_H^{n-1}, R_v^{n-1}. Supported for
- * 2D periodic, non-reacting grids without immersed body in FP64 (params
- * with_adjoint = 1; otherwise LM_EUNSUPPORTED).                              */
+ * F (faces) and the history rho^{n-1}, R_H^{n-1}, R_v^{n-1}, with ndim
+ * entries in each per-direction array (the rest are ignored). Supported for
+ * 2D and 3D periodic, non-reacting grids without immersed body on uniform
+ * spacing in FP64 (params with_adjoint = 1; otherwise LM_EUNSUPPORTED).     */
 typedef struct {
   double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
   double *T;   /* lm_adjoint_set only: a cotangent of the temperature,
@@ -324,7 +325,8 @@ typedef struct {
                   ignored by lm_adjoint_get                               */
 } lm_adjoint;
 
-/* Kinetic energy sum_cells 1/2 rho |v|^2 dV of the current state. */
+/* Kinetic energy sum_cells 1/2 rho |v|^2 dV of the current state (uniform
+ * grids; LM_EUNSUPPORTED on stretched ones). */
 lm_status lm_kinetic_energy(lm_ctx *ctx, double *ke);
 /* Adjoint state := d(kinetic energy)/d(state) at the current state. */
 lm_status lm_adjoint_seed_ke(lm_ctx *ctx);

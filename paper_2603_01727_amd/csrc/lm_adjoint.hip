@@ -1,5 +1,5 @@
-// Adjoint (reverse mode) of one predictor-corrector step for the 2D
-// periodic, non-reacting configuration without immersed boundary. The step
+// Adjoint (reverse mode) of one predictor-corrector step for the periodic,
+// non-reacting configuration without immersed boundary, in 2D and 3D. The step
 // is recomputed forward from the stored state (not committed); the sweep
 // back applies, in reverse order, the transposes of
 //   projection   F = avg(M) - delta_1 P,  v = (M - delta_2 P)/rho   (Eq 3.23, 3.25)
@@ -9,9 +9,10 @@
 //   Adams steps  AB2 predictor / AM2 corrector                          (Eq 3.1-3.18)
 //   residuals    R_H, R_v of Eq 3.4, 3.8, 3.26 with tau of Eq 2.46.
 // The residual transpose is a gather: for every input cell m the residuals
-// of the 3 x 3 cells whose stencils reach m are re-evaluated with dual
-// numbers seeded at m (derivatives with respect to H, v1, v2, F1, F2 at m)
-// and contracted with the residual cotangents. No atomics; deterministic.
+// of the 3^DIM cells whose stencils reach m are re-evaluated with dual
+// numbers seeded at m (derivatives with respect to H, the DIM velocity
+// components and the DIM face fluxes at m) and contracted with the residual
+// cotangents. No atomics; deterministic.
 #include "lm_device.h"
 
 namespace lm {
@@ -123,109 +124,150 @@ __device__ inline Dual<N> dpow(const Dual<N> &x, double p) {
 // ---------------------------------------------------------------------------
 // Residuals of one cell, written over a loader of dual-valued fields
 // ---------------------------------------------------------------------------
-using D5 = Dual<5>;
+// Dual numbers carrying derivatives with respect to H, v (DIM) and F (DIM).
+template <int DIM>
+using DD = Dual<1 + 2 * DIM>;
 
-// Periodic 2D loader of the level fields; values at cell (mi, mj) carry unit
-// seeds: H -> 0, v1 -> 1, v2 -> 2, F1 -> 3, F2 -> 4.
+struct Ix {
+  int i, j, k;
+};
+// x shifted by s cells along direction d
+__device__ inline Ix off(Ix x, int d, int s) {
+  if (d == 0)
+    x.i += s;
+  else if (d == 1)
+    x.j += s;
+  else
+    x.k += s;
+  return x;
+}
+__device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+__device__ inline Ix wrap(const Lay &L, Ix x) { return Ix{wrap(x.i, L.n[0]), wrap(x.j, L.n[1]), wrap(x.k, L.n[2])}; }
+__device__ inline long pw(const Lay &L, Ix x) {
+  x = wrap(L, x);
+  return L.at(x.i, x.j, x.k);
+}
+
+// Periodic loader of the level fields; values at cell m carry unit seeds:
+// H -> 0, v_c -> 1 + c, F_d -> 1 + DIM + d.
+template <int DIM>
 struct Loader {
   Lay L;
-  const double *H, *v[2], *F[2];
-  int mi, mj;
-  __device__ int wx(int i) const { return i < 0 ? i + L.n[0] : (i >= L.n[0] ? i - L.n[0] : i); }
-  __device__ int wy(int j) const { return j < 0 ? j + L.n[1] : (j >= L.n[1] ? j - L.n[1] : j); }
-  __device__ D5 load(const double *a, int i, int j, int seed) const {
-    i = wx(i);
-    j = wy(j);
-    D5 r(a[L.at(i, j, 0)]);
-    if (i == mi && j == mj) r.d[seed] = 1.0;
+  const double *H, *v[3], *F[3];
+  Ix m;
+  __device__ DD<DIM> load(const double *a, Ix x, int seed) const {
+    x = wrap(L, x);
+    DD<DIM> r(a[L.at(x.i, x.j, x.k)]);
+    if (x.i == m.i && x.j == m.j && x.k == m.k) r.d[seed] = 1.0;
     return r;
   }
-  __device__ D5 hh(int i, int j) const { return load(H, i, j, 0); }
-  __device__ D5 vv(int c, int i, int j) const { return load(v[c], i, j, 1 + c); }
-  __device__ D5 ff(int d, int i, int j) const { return load(F[d], i, j, 3 + d); }
+  __device__ DD<DIM> hh(Ix x) const { return load(H, x, 0); }
+  __device__ DD<DIM> vv(int c, Ix x) const { return load(v[c], x, 1 + c); }
+  __device__ DD<DIM> ff(int d, Ix x) const { return load(F[d], x, 1 + DIM + d); }
 };
 
-__device__ inline D5 temp_of(const AdjPhys &P, const D5 &H) { return P.qs * (H - 1.0); }
+template <int N>
+__device__ inline Dual<N> temp_of(const AdjPhys &P, const Dual<N> &H) {
+  return P.qs * (H - 1.0);
+}
 
 // kappa(T) with its derivative: T^sigma (Eq 2.50), or Sutherland's law
 // T^{3/2} (1 + C)/(T + C) (Eq 4.12), d kappa/dT = kappa (3/(2T) - 1/(T + C)).
-__device__ inline D5 kappa_dual(const AdjPhys &P, const D5 &T) {
+template <int N>
+__device__ inline Dual<N> kappa_dual(const AdjPhys &P, const Dual<N> &T) {
   if (P.suth_C > 0.0) {
     const double C = P.suth_C, t = T.v;
-    D5 r;
+    Dual<N> r;
     r.v = t * sqrt(t) * (1.0 + C) / (t + C);
     const double dv = r.v * (1.5 / t - 1.0 / (t + C));
 #pragma unroll
-    for (int q = 0; q < 5; ++q) r.d[q] = dv * T.d[q];
+    for (int q = 0; q < N; ++q) r.d[q] = dv * T.d[q];
     return r;
   }
   return dpow(T, P.sigma);
 }
 
-__device__ inline D5 kap_at(const AdjPhys &P, const Loader &ld, int i, int j) {
-  return kappa_dual(P, temp_of(P, ld.hh(i, j)));
+template <int DIM>
+__device__ inline DD<DIM> kap_at(const AdjPhys &P, const Loader<DIM> &ld, Ix x) {
+  return kappa_dual(P, temp_of(P, ld.hh(x)));
 }
 
-// tau_id on the face between (i, j) and its +d neighbour (Eq 2.46 on d-faces).
-__device__ inline D5 tau_face_d(const AdjPhys &P, const Loader &ld, int i, int j, int d, int comp) {
-  const int di = d == 0 ? 1 : 0, dj = d == 1 ? 1 : 0;
-  const D5 kf = 0.5 * (kap_at(P, ld, i, j) + kap_at(P, ld, i + di, j + dj));
-  D5 D[2][2];
+// tau_{d c} for every component c on the face between cell x and its +d
+// neighbour (Eq 2.46 on d-faces): normal derivatives across the face,
+// tangential ones as the mean of the centred differences of the two cells.
+template <int DIM>
+__device__ inline void tau_face(const AdjPhys &P, const Loader<DIM> &ld, Ix x, int d, DD<DIM> tau[DIM]) {
+  const Ix y = off(x, d, 1);
+  const DD<DIM> kf = 0.5 * (kap_at(P, ld, x) + kap_at(P, ld, y));
+  DD<DIM> D[DIM][DIM];  // D[k][c] = d v_c / d x_k on the face
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
+  for (int c = 0; c < DIM; ++c) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < DIM; ++k) {
       if (k == d) {
-        D[k][c] = (ld.vv(c, i + di, j + dj) - ld.vv(c, i, j)) * (1.0 / P.h[d]);
+        D[k][c] = (ld.vv(c, y) - ld.vv(c, x)) * (1.0 / P.h[d]);
       } else {
-        const int ki = k == 0 ? 1 : 0, kj = k == 1 ? 1 : 0;
         const double h2 = 2.0 * P.h[k];
-        const D5 a = (ld.vv(c, i + ki, j + kj) - ld.vv(c, i - ki, j - kj)) / h2;
-        const D5 b = (ld.vv(c, i + di + ki, j + dj + kj) - ld.vv(c, i + di - ki, j + dj - kj)) / h2;
+        const DD<DIM> a = (ld.vv(c, off(x, k, 1)) - ld.vv(c, off(x, k, -1))) / h2;
+        const DD<DIM> b = (ld.vv(c, off(y, k, 1)) - ld.vv(c, off(y, k, -1))) / h2;
         D[k][c] = 0.5 * (a + b);
       }
     }
   }
-  D5 t = D[d][comp] + D[comp][d];
-  if (comp == d) t = t - (2.0 / 3.0) * (D[0][0] + D[1][1]);
-  return kf * t;
+  DD<DIM> div = D[0][0];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) div = div + D[k][k];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    DD<DIM> t = D[d][c] + D[c][d];
+    if (c == d) t = t - (2.0 / 3.0) * div;
+    tau[c] = kf * t;
+  }
 }
 
-// R_H, R_v1, R_v2 at cell (i, j): the arithmetic of the forward residual
-// (Eq 3.4a, 3.8a with the flux forms of Eq 3.26), non-reacting, no body.
-__device__ inline void resid_cell(const AdjPhys &P, const Loader &ld, int i, int j, D5 &RH, D5 Rv[2]) {
-  const D5 Hc = ld.hh(i, j);
-  const D5 Tc = temp_of(P, Hc);
-  const D5 rho = D5(P.p0) / Tc;
-  const D5 kc = kappa_dual(P, Tc);
-  D5 adv(0.0), dif(0.0);
+// R_H and R_v at cell x: the arithmetic of the forward residual (Eq 3.4a,
+// 3.8a with the flux forms of Eq 3.26), non-reacting, no body.
+template <int DIM>
+__device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM> &ld, Ix x, DD<DIM> &RH, DD<DIM> Rv[DIM]) {
+  const DD<DIM> Hc = ld.hh(x);
+  const DD<DIM> Tc = temp_of(P, Hc);
+  const DD<DIM> rho = DD<DIM>(P.p0) / Tc;
+  const DD<DIM> kc = kappa_dual(P, Tc);
+  DD<DIM> adv(0.0), dif(0.0);
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const int di = d == 0 ? 1 : 0, dj = d == 1 ? 1 : 0;
-    const D5 Hp = ld.hh(i + di, j + dj), Hm = ld.hh(i - di, j - dj);
-    const D5 gp = (Hp - Hc) / P.h[d];
-    const D5 gm = (Hc - Hm) / P.h[d];
-    const D5 kp = 0.5 * (kc + kap_at(P, ld, i + di, j + dj));
-    const D5 km = 0.5 * (kap_at(P, ld, i - di, j - dj) + kc);
-    adv = adv + 0.5 * (ld.ff(d, i, j) * gp + ld.ff(d, i - di, j - dj) * gm);
+  for (int d = 0; d < DIM; ++d) {
+    const Ix xp = off(x, d, 1), xm = off(x, d, -1);
+    const DD<DIM> gp = (ld.hh(xp) - Hc) / P.h[d];
+    const DD<DIM> gm = (Hc - ld.hh(xm)) / P.h[d];
+    const DD<DIM> kp = 0.5 * (kc + kap_at(P, ld, xp));
+    const DD<DIM> km = 0.5 * (kap_at(P, ld, xm) + kc);
+    adv = adv + 0.5 * (ld.ff(d, x) * gp + ld.ff(d, xm) * gm);
     dif = dif + (kp * gp - km * gm) / P.h[d];
   }
   RH = (-adv + dif / P.Pe) / rho;
+  DD<DIM> visc[DIM];
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    D5 conv(0.0), visc(0.0);
+  for (int c = 0; c < DIM; ++c) visc[c] = DD<DIM>(0.0);
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int di = d == 0 ? 1 : 0, dj = d == 1 ? 1 : 0;
-      const D5 vc = ld.vv(c, i, j);
-      const D5 flp = ld.ff(d, i, j) * (0.5 * (vc + ld.vv(c, i + di, j + dj)));
-      const D5 flm = ld.ff(d, i - di, j - dj) * (0.5 * (ld.vv(c, i - di, j - dj) + vc));
+  for (int d = 0; d < DIM; ++d) {
+    DD<DIM> tp[DIM], tm[DIM];
+    tau_face<DIM>(P, ld, x, d, tp);
+    tau_face<DIM>(P, ld, off(x, d, -1), d, tm);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) visc[c] = visc[c] + (tp[c] - tm[c]) / P.h[d];
+  }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const DD<DIM> vc = ld.vv(c, x);
+    DD<DIM> conv(0.0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const Ix xp = off(x, d, 1), xm = off(x, d, -1);
+      const DD<DIM> flp = ld.ff(d, x) * (0.5 * (vc + ld.vv(c, xp)));
+      const DD<DIM> flm = ld.ff(d, xm) * (0.5 * (ld.vv(c, xm) + vc));
       conv = conv + (flp - flm) / P.h[d];
-      const D5 tp = tau_face_d(P, ld, i, j, d, c);
-      const D5 tm = tau_face_d(P, ld, i - di, j - dj, d, c);
-      visc = visc + (tp - tm) / P.h[d];
     }
-    D5 r = -conv + (P.Pr / P.Pe) * visc;
+    DD<DIM> r = -conv + (P.Pr / P.Pe) * visc[c];
     if (c == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
     Rv[c] = r;
   }
@@ -237,52 +279,67 @@ __device__ inline void resid_cell(const AdjPhys &P, const Loader &ld, int i, int
 struct AdjResidArgs {
   Lay L;
   AdjPhys P;
-  const double *H, *v[2], *F[2];        // level at which the residuals are taken
-  const double *RbH, *Rbv[2];           // residual cotangents
-  double *Hb, *vb[2], *Fb[2];           // accumulated adjoints
+  const double *H, *v[3], *F[3];        // level at which the residuals are taken
+  const double *RbH, *Rbv[3];           // residual cotangents
+  double *Hb, *vb[3], *Fb[3];           // accumulated adjoints
 };
 
-// (Hb, vb, Fb) += (dR/d(H, v, F))^T (RbH, Rbv) by gather over the 3 x 3
+// (Hb, vb, Fb) += (dR/d(H, v, F))^T (RbH, Rbv) by gather over the 3^DIM
 // cells whose residual stencils reach the cell.
+template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
+  constexpr int N = 1 + 2 * DIM;
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
-  Loader ld;
+  Loader<DIM> ld;
   ld.L = a.L;
   ld.H = a.H;
-  ld.v[0] = a.v[0];
-  ld.v[1] = a.v[1];
-  ld.F[0] = a.F[0];
-  ld.F[1] = a.F[1];
-  ld.mi = p.i;
-  ld.mj = p.j;
-  double acc[5] = {0, 0, 0, 0, 0};
-  for (int dj = -1; dj <= 1; ++dj)
-    for (int di = -1; di <= 1; ++di) {
-      const int ci = ld.wx(p.i + di), cj = ld.wy(p.j + dj);
-      D5 RH, Rv[2];
-      resid_cell(a.P, ld, ci, cj, RH, Rv);
-      const long c = a.L.at(ci, cj, 0);
-      const double rh = a.RbH[c], r0 = a.Rbv[0][c], r1 = a.Rbv[1][c];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) acc[q] += rh * RH.d[q] + r0 * Rv[0].d[q] + r1 * Rv[1].d[q];
-    }
+  for (int d = 0; d < 3; ++d) {
+    ld.v[d] = a.v[d];
+    ld.F[d] = a.F[d];
+  }
+  ld.m = Ix{p.i, p.j, p.k};
+  double acc[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) acc[q] = 0.0;
+  const int kr = DIM == 3 ? 1 : 0;
+  for (int dk = -kr; dk <= kr; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const Ix x = wrap(a.L, Ix{p.i + di, p.j + dj, p.k + dk});
+        DD<DIM> RH, Rv[DIM];
+        resid_cell<DIM>(a.P, ld, x, RH, Rv);
+        const long c = a.L.at(x.i, x.j, x.k);
+        const double rh = a.RbH[c];
+        double r[DIM];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) r[e] = a.Rbv[e][c];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          double s = rh * RH.d[q];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e) s += r[e] * Rv[e].d[q];
+          acc[q] += s;
+        }
+      }
   const long m = p.c;
   a.Hb[m] += acc[0];
-  a.vb[0][m] += acc[1];
-  a.vb[1][m] += acc[2];
-  a.Fb[0][m] += acc[3];
-  a.Fb[1][m] += acc[4];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    a.vb[d][m] += acc[1 + d];
+    a.Fb[d][m] += acc[1 + DIM + d];
+  }
 }
 
-hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[2],
-                            double *const F[2], const double *RbH, double *const Rbv[2], double *Hb, double *vb[2],
-                            double *Fb[2]) {
-  AdjResidArgs a;
+hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[3],
+                            double *const F[3], const double *RbH, double *const Rbv[3], double *Hb, double *vb[3],
+                            double *Fb[3]) {
+  AdjResidArgs a{};
   a.L = L;
   a.P = P;
   a.H = H;
-  for (int d = 0; d < 2; ++d) {
+  for (int d = 0; d < L.ndim; ++d) {
     a.v[d] = v[d];
     a.F[d] = F[d];
     a.Rbv[d] = Rbv[d];
@@ -291,45 +348,64 @@ hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, cons
   }
   a.RbH = RbH;
   a.Hb = Hb;
-  hipLaunchKernelGGL(k_adj_resid, grid_for(L), dim3(kBX, kBY), 0, st, a);
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_adj_resid<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adj_resid<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
   return hipGetLastError();
 }
 
-__device__ inline long pw(const Lay &L, int i, int j) {
-  i = i < 0 ? i + L.n[0] : (i >= L.n[0] ? i - L.n[0] : i);
-  j = j < 0 ? j + L.n[1] : (j >= L.n[1] ? j - L.n[1] : j);
-  return L.at(i, j, 0);
-}
+struct AdjProjArgs {
+  Lay L;
+  AdjPhys P;
+  const double *Fb[3], *vb[3], *v[3], *rho;
+  double *Mb[3], *rhob, *Pb;
+};
 
 // Transpose of the projection: from (Fb, vb) at the projected level to the
 // momentum cotangent Mb, the density cotangent rhob and the pressure
 // cotangent Pb (= -delta_1^T Fb + delta_2 (vb/rho)).
-__global__ void __launch_bounds__(kBlock) k_adj_proj(Lay L, AdjPhys P, const double *Fb0, const double *Fb1,
-                                                     const double *vb0, const double *vb1, const double *v0,
-                                                     const double *v1, const double *rho, double *Mb0, double *Mb1,
-                                                     double *rhob, double *Pb) {
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_adj_proj(AdjProjArgs a) {
   CellPos p;
-  if (!cell_of_thread(L, p)) return;
-  const int i = p.i, j = p.j;
+  if (!cell_of_thread(a.L, p)) return;
+  const Ix x{p.i, p.j, p.k};
   const long c = p.c;
-  const double *Fb[2] = {Fb0, Fb1};
-  const double *vb[2] = {vb0, vb1};
-  const double *vv[2] = {v0, v1};
-  double *Mb[2] = {Mb0, Mb1};
-  const double r = rho[c];
+  const double r = a.rho[c];
   double rb = 0.0, pb = 0.0;
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const long cm = d == 0 ? pw(L, i - 1, j) : pw(L, i, j - 1);
-    const long cp = d == 0 ? pw(L, i + 1, j) : pw(L, i, j + 1);
-    const double w = vb[d][c] / r;
-    rb -= vb[d][c] * vv[d][c] / r;
-    Mb[d][c] = 0.5 * (Fb[d][c] + Fb[d][cm]) + w;
-    const double wp = vb[d][cp] / rho[cp], wm = vb[d][cm] / rho[cm];
-    pb += (Fb[d][c] - Fb[d][cm]) / P.h[d] + (wp - wm) / (2.0 * P.h[d]);
+  for (int d = 0; d < DIM; ++d) {
+    const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
+    const double w = a.vb[d][c] / r;
+    rb -= a.vb[d][c] * a.v[d][c] / r;
+    a.Mb[d][c] = 0.5 * (a.Fb[d][c] + a.Fb[d][cm]) + w;
+    const double wp = a.vb[d][cp] / a.rho[cp], wm = a.vb[d][cm] / a.rho[cm];
+    pb += (a.Fb[d][c] - a.Fb[d][cm]) / a.P.h[d] + (wp - wm) / (2.0 * a.P.h[d]);
   }
-  rhob[c] = rb;
-  Pb[c] = pb;
+  a.rhob[c] = rb;
+  a.Pb[c] = pb;
+}
+
+hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[3],
+                           double *const vb[3], double *const v[3], const double *rho, double *Mb[3], double *rhob,
+                           double *Pb) {
+  AdjProjArgs a{};
+  a.L = L;
+  a.P = P;
+  for (int d = 0; d < L.ndim; ++d) {
+    a.Fb[d] = Fb[d];
+    a.vb[d] = vb[d];
+    a.v[d] = v[d];
+    a.Mb[d] = Mb[d];
+  }
+  a.rho = rho;
+  a.rhob = rhob;
+  a.Pb = Pb;
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_adj_proj<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adj_proj<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+  return hipGetLastError();
 }
 
 // Transposes of the right-hand side, the EOS and the Adams update of one
@@ -340,10 +416,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_proj(Lay L, AdjPhys P, const dou
 // rhoprevb_out); for the predictor Hb_star from the corrector residual
 // transpose; outputs the level-n accumulators, the residual cotangents and
 // the cotangents of the level n-1 history.
+template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
-  const int i = p.i, j = p.j;
+  const Ix x{p.i, p.j, p.k};
   const long c = p.c;
   const double dt = a.P.dt;
   double c1, c2, c3;
@@ -357,11 +434,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
     c3 = 1.0 / (2.0 * dt);
   }
   const double bb = a.bb[c];
-  double Mb[2];
+  double Mb[DIM];
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const long cm = d == 0 ? pw(a.L, i - 1, j) : pw(a.L, i, j - 1);
-    const long cp = d == 0 ? pw(a.L, i + 1, j) : pw(a.L, i, j + 1);
+  for (int d = 0; d < DIM; ++d) {
+    const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
     Mb[d] = a.Mb[d][c] - (a.bb[cp] - a.bb[cm]) / (2.0 * a.P.h[d]);
   }
   const double rnew = a.rho_new[c];
@@ -378,7 +454,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
     a.RbH_n[c] = 0.5 * dt * Hb + a.RbH_out[c];
     rhob_n += a.rhoprevb_out[c];
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
+    for (int d = 0; d < DIM; ++d) {
       a.Rbv_star[d][c] = 0.5 * dt * Mb[d];
       a.Rbv_n[d][c] = 0.5 * dt * Mb[d] + a.Rbv_out[d][c];
       rhob_n += Mb[d] * a.v_n[d][c];
@@ -393,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
     a.RbH_n[c] += dt * ca * Hb;
     a.RbH_prev_in[c] = -dt * cb * Hb;
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
+    for (int d = 0; d < DIM; ++d) {
       rhob_n += Mb[d] * a.v_n[d][c];
       a.vb_n[d][c] += rho_n * Mb[d];
       a.Rbv_n[d][c] += dt * ca * Mb[d];
@@ -404,17 +480,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
   }
 }
 
-hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[2],
-                           double *const vb[2], double *const v[2], const double *rho, double *Mb[2], double *rhob,
-                           double *Pb) {
-  hipLaunchKernelGGL(k_adj_proj, grid_for(L), dim3(kBX, kBY), 0, st, L, P, (const double *)Fb[0],
-                     (const double *)Fb[1], (const double *)vb[0], (const double *)vb[1], (const double *)v[0],
-                     (const double *)v[1], rho, Mb[0], Mb[1], rhob, Pb);
-  return hipGetLastError();
-}
-
 hipError_t launch_adj_tail(hipStream_t st, const AdjTailArgs &a) {
-  hipLaunchKernelGGL(k_adj_tail, grid_for(a.L), dim3(kBX, kBY), 0, st, a);
+  if (a.L.ndim == 3)
+    hipLaunchKernelGGL(k_adj_tail<3>, grid_for(a.L), dim3(kBX, kBY), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adj_tail<2>, grid_for(a.L), dim3(kBX, kBY), 0, st, a);
   return hipGetLastError();
 }
 
@@ -447,65 +517,108 @@ hipError_t launch_adj_add_T(hipStream_t st, const Lay &L, const AdjPhys &P, cons
   return hipGetLastError();
 }
 
+struct AdjCellArgs {
+  Lay L;
+  AdjPhys P;
+  double dV;
+  const double *H, *rho, *v[3], *Fb[3], *Hb_in;
+  double *Hb, *vb[3], *Tb;
+};
+
 // Cotangent of J = sum 1/2 rho |v|^2 dV at the current level: vb = rho v dV,
 // Hb = (d rho/d H) |v|^2/2 dV, all other cotangents zero.
-__global__ void __launch_bounds__(kBlock) k_adj_seed_ke(Lay L, AdjPhys P, double dV, const double *H,
-                                                        const double *rho, const double *v0, const double *v1,
-                                                        double *Hb, double *vb0, double *vb1) {
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_adj_seed_ke(AdjCellArgs a) {
   CellPos p;
-  if (!cell_of_thread(L, p)) return;
+  if (!cell_of_thread(a.L, p)) return;
   const long c = p.c;
-  const double r = rho[c];
-  const double T = P.qs * (H[c] - 1.0);
-  const double e = 0.5 * (v0[c] * v0[c] + v1[c] * v1[c]);
-  vb0[c] = r * v0[c] * dV;
-  vb1[c] = r * v1[c] * dV;
-  Hb[c] = -r * P.qs / T * e * dV;
+  const double r = a.rho[c];
+  const double T = a.P.qs * (a.H[c] - 1.0);
+  double e = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double u = a.v[d][c];
+    e += u * u;
+    a.vb[d][c] = r * u * a.dV;
+  }
+  a.Hb[c] = -r * a.P.qs / T * (0.5 * e) * a.dV;
 }
 
 hipError_t launch_adj_seed_ke(hipStream_t st, const Lay &L, const AdjPhys &P, double dV, const double *H,
-                              const double *rho, double *const v[2], double *Hb, double *vb[2]) {
-  hipLaunchKernelGGL(k_adj_seed_ke, grid_for(L), dim3(kBX, kBY), 0, st, L, P, dV, H, rho, (const double *)v[0],
-                     (const double *)v[1], Hb, vb[0], vb[1]);
+                              const double *rho, double *const v[3], double *Hb, double *vb[3]) {
+  AdjCellArgs a{};
+  a.L = L;
+  a.P = P;
+  a.dV = dV;
+  a.H = H;
+  a.rho = rho;
+  for (int d = 0; d < L.ndim; ++d) {
+    a.v[d] = v[d];
+    a.vb[d] = vb[d];
+  }
+  a.Hb = Hb;
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_adj_seed_ke<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adj_seed_ke<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
   return hipGetLastError();
 }
 
 // Adjoint of the initial state built from (T0, v0): F0 = avg(rho0 v0),
 // rho0 = p0/T(H0), H0 = T0/qs + 1. Outputs Tb (cotangent of T0) and adds
 // rho0 avg^T(Fb) to vb.
-__global__ void __launch_bounds__(kBlock) k_adj_init(Lay L, AdjPhys P, const double *H, const double *rho,
-                                                     const double *v0, const double *v1, const double *Fb0,
-                                                     const double *Fb1, const double *Hb, double *vb0, double *vb1,
-                                                     double *Tb) {
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_adj_init(AdjCellArgs a) {
   CellPos p;
-  if (!cell_of_thread(L, p)) return;
-  const int i = p.i, j = p.j;
+  if (!cell_of_thread(a.L, p)) return;
+  const Ix x{p.i, p.j, p.k};
   const long c = p.c;
-  const double r = rho[c];
-  const double mb0 = 0.5 * (Fb0[c] + Fb0[pw(L, i - 1, j)]);
-  const double mb1 = 0.5 * (Fb1[c] + Fb1[pw(L, i, j - 1)]);
-  const double rhob = mb0 * v0[c] + mb1 * v1[c];
-  vb0[c] += r * mb0;
-  vb1[c] += r * mb1;
-  const double T = P.qs * (H[c] - 1.0);
-  const double hb = Hb[c] - r * P.qs / T * rhob;
-  Tb[c] = hb / P.qs;
+  const double r = a.rho[c];
+  double rhob = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double mb = 0.5 * (a.Fb[d][c] + a.Fb[d][pw(a.L, off(x, d, -1))]);
+    rhob += mb * a.v[d][c];
+    a.vb[d][c] += r * mb;
+  }
+  const double T = a.P.qs * (a.H[c] - 1.0);
+  const double hb = a.Hb_in[c] - r * a.P.qs / T * rhob;
+  a.Tb[c] = hb / a.P.qs;
 }
 
 hipError_t launch_adj_init(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
-                           double *const v[2], double *const Fb[2], const double *Hb, double *vb[2], double *Tb) {
-  hipLaunchKernelGGL(k_adj_init, grid_for(L), dim3(kBX, kBY), 0, st, L, P, H, rho, (const double *)v[0],
-                     (const double *)v[1], (const double *)Fb[0], (const double *)Fb[1], Hb, vb[0], vb[1], Tb);
+                           double *const v[3], double *const Fb[3], const double *Hb, double *vb[3], double *Tb) {
+  AdjCellArgs a{};
+  a.L = L;
+  a.P = P;
+  a.H = H;
+  a.rho = rho;
+  for (int d = 0; d < L.ndim; ++d) {
+    a.v[d] = v[d];
+    a.Fb[d] = Fb[d];
+    a.vb[d] = vb[d];
+  }
+  a.Hb_in = Hb;
+  a.Tb = Tb;
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_adj_init<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adj_init<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
   return hipGetLastError();
 }
 
 // sum over cells of 1/2 rho |v|^2 into per-block partials.
-__global__ void __launch_bounds__(kBlock) k_ke(Lay L, const double *rho, const double *v0, const double *v1,
-                                               double *part) {
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_ke(AdjCellArgs a, double *part) {
   __shared__ double sh[kBlock / 64];
   CellPos p;
   double e = 0.0;
-  if (cell_of_thread(L, p)) e = 0.5 * rho[p.c] * (v0[p.c] * v0[p.c] + v1[p.c] * v1[p.c]);
+  if (cell_of_thread(a.L, p)) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) s += a.v[d][p.c] * a.v[d][p.c];
+    e = 0.5 * a.rho[p.c] * s;
+  }
   const double s = block_sum(e, sh);
   if (linear_tid() == 0) part[linear_block()] = s;
 }
@@ -516,10 +629,16 @@ __global__ void __launch_bounds__(kBlock) k_ke_finish(const double *part, int np
   if (threadIdx.x == 0) *out = s * dV;
 }
 
-hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[2], double dV, double *part,
+hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[3], double dV, double *part,
                      double *out) {
-  hipLaunchKernelGGL(k_ke, grid_for(L), dim3(kBX, kBY), 0, st, L, rho, (const double *)v[0], (const double *)v[1],
-                     part);
+  AdjCellArgs a{};
+  a.L = L;
+  a.rho = rho;
+  for (int d = 0; d < L.ndim; ++d) a.v[d] = v[d];
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_ke<3>, grid_for(L), dim3(kBX, kBY), 0, st, a, part);
+  else
+    hipLaunchKernelGGL(k_ke<2>, grid_for(L), dim3(kBX, kBY), 0, st, a, part);
   hipLaunchKernelGGL(k_ke_finish, dim3(1), dim3(kBlock), 0, st, (const double *)part, (int)nblocks_for(L), dV, out);
   return hipGetLastError();
 }

@@ -12,6 +12,19 @@
 
 using namespace lm;
 
+// Cotangent of the context's state (per-direction entries beyond ndim are
+// unused and null).
+struct AdjState {
+  double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
+};
+// Work arrays of one reverse step.
+struct AdjWork {
+  double *Mb[3], *rhob_new, *Pb, *bb;
+  double *Hb_star, *vb_star[3], *Fb_star[3];
+  double *RbH_star, *Rbv_star[3], *RbH_n, *Rbv_n[3], *rhob_n;
+  double *Tb_set, *Tb_init;
+};
+
 struct lm_ctx {
   lm_grid grid;
   lm_params prm;
@@ -45,11 +58,11 @@ struct lm_ctx {
   long long total_iters;
   int last_iters[2];
   std::string err;
-  // adjoint: two sets of the adjoint state (H, v0, v1, F0, F1, rho_prev,
-  // RH_prev, Rv0_prev, Rv1_prev) and work arrays
-  double *ad[2][9];
+  // adjoint: two sets of the adjoint state (input and output of a reverse
+  // step) and work arrays
+  AdjState ad[2];
   int ad_cur;
-  double *aw[20];
+  AdjWork aw;
   P0Dev *p0d;            // enclosed-system thermodynamic pressure (device)
   // adaptive time step
   double dt_prev;        // size of the step that made level n (0 before the first)
@@ -386,10 +399,28 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
   c->dflags = (int *)cv.take(64);
   c->dscalar = (double *)cv.take(64);
   c->dlog = (SolveLog *)cv.take(2 * sizeof(SolveLog));
-  for (int s = 0; s < 2; ++s)
-    for (int q = 0; q < 9; ++q) c->ad[s][q] = c->prm.with_adjoint ? (double *)cv.take(ab) : nullptr;
-  for (int q = 0; q < 20; ++q) c->aw[q] = c->prm.with_adjoint ? (double *)cv.take(ab) : nullptr;
-  c->ad_cur = 0;
+  {
+    const bool adj = c->prm.with_adjoint;
+    auto take = [&](bool on) { return adj && on ? (double *)cv.take(ab) : nullptr; };
+    for (int s = 0; s < 2; ++s) {
+      AdjState &a = c->ad[s];
+      a.H = take(true);
+      a.rho_prev = take(true);
+      a.R_H = take(true);
+      for (int d = 0; d < 3; ++d) {
+        a.v[d] = take(d < nd);
+        a.F[d] = take(d < nd);
+        a.R_v[d] = take(d < nd);
+      }
+    }
+    AdjWork &w = c->aw;
+    for (double **q : {&w.rhob_new, &w.Pb, &w.bb, &w.Hb_star, &w.RbH_star, &w.RbH_n, &w.rhob_n, &w.Tb_set,
+                       &w.Tb_init})
+      *q = take(true);
+    for (int d = 0; d < 3; ++d)
+      for (double **q : {&w.Mb[d], &w.vb_star[d], &w.Fb_star[d], &w.Rbv_star[d], &w.Rbv_n[d]}) *q = take(d < nd);
+    c->ad_cur = 0;
+  }
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = c->phys.h[d];
   if (!poisson_plan(c->pws, cv, L, c->bnd, h, c->prm.precision != LM_FP64, c->prm.precision == LM_MIXED_FLEXIBLE,
@@ -870,6 +901,26 @@ static lm_status do_stage(lm_ctx *c, int corrector, int &iters, double &relres, 
   return LM_OK;
 }
 
+// Reads back the outcome of both stage solves when the one-workgroup solver
+// deferred it to the device log (stage solves then skip their own host
+// check), synchronising the stream; otherwise only synchronises.
+static lm_status read_solve_logs(lm_ctx *c, int it[2], double rr[2], double cm[2]) {
+  if (c->pws.block_pcg)
+    HIPCHK(c, hipMemcpyAsync(c->hlog, c->dlog, 2 * sizeof(SolveLog), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (!c->pws.block_pcg) return LM_OK;
+  for (int q = 0; q < 2; ++q) {
+    const SolveLog &g = c->hlog[q];
+    it[q] = g.iters;
+    rr[q] = g.cc > 0 ? std::sqrt(g.rr / g.cc) : 0.0;
+    cm[q] = g.mean_b;
+    c->last_iters[q] = g.iters > 0 ? g.iters : 1;
+    c->total_iters += g.iters;
+    if (!(g.done && !g.nonconv)) return fail(c, LM_ENOCONV, "Poisson solver did not reach poisson_rtol");
+  }
+  return LM_OK;
+}
+
 lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
   if (!c) return LM_EINVAL;
   if (!c->have_state) return fail(c, LM_ESTATE, "lm_set_fields must come first");
@@ -884,20 +935,7 @@ lm_status lm_step(lm_ctx *c, int nsteps, lm_step_stats *stats) {
     if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
     if (s == LM_OK) {
       HIPCHK(c, hipMemcpyAsync(c->hflags + 1, c->dflags + 1, 4, hipMemcpyDeviceToHost, c->st));
-      if (c->pws.block_pcg)
-        HIPCHK(c, hipMemcpyAsync(c->hlog, c->dlog, 2 * sizeof(SolveLog), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(c, hipStreamSynchronize(c->st));
-      if (c->pws.block_pcg) {
-        for (int q = 0; q < 2 && s == LM_OK; ++q) {
-          const SolveLog &g = c->hlog[q];
-          it[q] = g.iters;
-          rr[q] = g.cc > 0 ? std::sqrt(g.rr / g.cc) : 0.0;
-          cm[q] = g.mean_b;
-          c->last_iters[q] = g.iters > 0 ? g.iters : 1;
-          c->total_iters += g.iters;
-          if (!(g.done && !g.nonconv)) s = fail(c, LM_ENOCONV, "Poisson solver did not reach poisson_rtol");
-        }
-      }
+      s = read_solve_logs(c, it, rr, cm);
       if (s == LM_OK && c->hflags[1]) s = fail(c, LM_ENONFINITE, "non-finite velocity after the step");
     }
     if (s != LM_OK) {
@@ -1121,14 +1159,28 @@ int state_arrays(lm_ctx *c, double **out) {
   return k;
 }
 
-bool adjoint_ok(lm_ctx *c) {
-  return c->prm.with_adjoint && c->grid.ndim == 2 && c->bnd.all_periodic;
+bool adjoint_ok(lm_ctx *c) { return c->prm.with_adjoint && c->bnd.all_periodic; }
+
+// The arrays of an adjoint state with the face direction of each (-1 for
+// cell arrays), in the order H, v, F, rho_prev, R_H, R_v; returns the count.
+int adj_arrays(const AdjState &a, int nd, double *arr[12], int fd[12]) {
+  int k = 0;
+  auto put = [&](double *x, int f) {
+    arr[k] = x;
+    fd[k++] = f;
+  };
+  put(a.H, -1);
+  for (int d = 0; d < nd; ++d) put(a.v[d], -1);
+  for (int d = 0; d < nd; ++d) put(a.F[d], d);
+  put(a.rho_prev, -1);
+  put(a.R_H, -1);
+  for (int d = 0; d < nd; ++d) put(a.R_v[d], -1);
+  return k;
 }
 
 AdjPhys adj_phys(const lm_ctx *c) {
   AdjPhys P;
-  P.h[0] = c->phys.h[0];
-  P.h[1] = c->phys.h[1];
+  for (int d = 0; d < 3; ++d) P.h[d] = c->phys.h[d];
   P.Pe = c->phys.Pe;
   P.Pr = c->phys.Pr;
   P.sigma = c->phys.sigma;
@@ -1202,8 +1254,7 @@ extern "C" lm_status lm_kinetic_energy(lm_ctx *c, double *ke) {
   Level &lv = c->lev[c->icur];
   double dV = 1.0;
   for (int d = 0; d < c->grid.ndim; ++d) dV *= c->phys.h[d];
-  if (c->grid.ndim != 2 || c->stretched)
-    return fail(c, LM_EUNSUPPORTED, "kinetic energy implemented for uniform 2D grids");
+  if (c->stretched) return fail(c, LM_EUNSUPPORTED, "kinetic energy implemented for uniform grids");
   HIPCHK(c, launch_ke(c->st, c->lay, lv.rho, lv.v, dV, c->pws.partials, c->dscalar));
   HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, 8, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1211,41 +1262,59 @@ extern "C" lm_status lm_kinetic_energy(lm_ctx *c, double *ke) {
   return LM_OK;
 }
 
+static const char *kAdjUnsupported = "adjoint needs with_adjoint and a periodic grid";
+
 extern "C" lm_status lm_adjoint_seed_ke(lm_ctx *c) {
   if (!c) return LM_EINVAL;
-  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
-  double **a = c->ad[c->ad_cur];
+  const int nd = c->grid.ndim;
+  AdjState &a = c->ad[c->ad_cur];
+  double *arr[12];
+  int fd[12];
+  const int k = adj_arrays(a, nd, arr, fd);
   const size_t ab = (size_t)c->lay.total * 8;
-  for (int q = 0; q < 9; ++q) HIPCHK(c, hipMemsetAsync(a[q], 0, ab, c->st));
+  for (int q = 0; q < k; ++q) HIPCHK(c, hipMemsetAsync(arr[q], 0, ab, c->st));
   Level &lv = c->lev[c->icur];
-  double *vb[2] = {a[1], a[2]};
-  const double dV = c->phys.h[0] * c->phys.h[1];
-  HIPCHK(c, launch_adj_seed_ke(c->st, c->lay, adj_phys(c), dV, lv.H, lv.rho, lv.v, a[0], vb));
+  double dV = 1.0;
+  for (int d = 0; d < nd; ++d) dV *= c->phys.h[d];
+  HIPCHK(c, launch_adj_seed_ke(c->st, c->lay, adj_phys(c), dV, lv.H, lv.rho, lv.v, a.H, a.v));
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;
 }
 
 extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
   if (!c || !in) return LM_EINVAL;
-  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
-  double **a = c->ad[c->ad_cur];
-  const double *src[9] = {in->H, in->v[0], in->v[1], in->F[0], in->F[1], in->rho_prev, in->R_H, in->R_v[0],
-                          in->R_v[1]};
-  const int fd[9] = {-1, -1, -1, 0, 1, -1, -1, -1, -1};
-  for (int q = 0; q < 9; ++q) {
-    HIPCHK(c, hipMemsetAsync(a[q], 0, (size_t)c->lay.total * 8, c->st));
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
+  const int nd = c->grid.ndim;
+  AdjState &a = c->ad[c->ad_cur];
+  double *arr[12], *src[12];
+  int fd[12];
+  const int k = adj_arrays(a, nd, arr, fd);
+  AdjState view{};
+  view.H = in->H;
+  view.rho_prev = in->rho_prev;
+  view.R_H = in->R_H;
+  for (int d = 0; d < nd; ++d) {
+    view.v[d] = in->v[d];
+    view.F[d] = in->F[d];
+    view.R_v[d] = in->R_v[d];
+  }
+  int fd2[12];
+  adj_arrays(view, nd, src, fd2);
+  for (int q = 0; q < k; ++q) {
+    HIPCHK(c, hipMemsetAsync(arr[q], 0, (size_t)c->lay.total * 8, c->st));
     if (src[q]) {
-      lm_status s = copy_in(c, src[q], a[q], fd[q], mem);
+      lm_status s = copy_in(c, src[q], arr[q], fd[q], mem);
       if (s != LM_OK) return s;
     }
   }
   if (in->T) {
     // T = qs (H - 1): the cotangent of T adds qs T_bar to H_bar
-    double *Tb = c->aw[18];
+    double *Tb = c->aw.Tb_set;
     lm_status s = copy_in(c, in->T, Tb, -1, mem);
     if (s != LM_OK) return s;
-    HIPCHK(c, launch_adj_add_T(c->st, c->lay, adj_phys(c), Tb, a[0]));
+    HIPCHK(c, launch_adj_add_T(c->st, c->lay, adj_phys(c), Tb, a.H));
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;
@@ -1253,14 +1322,24 @@ extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
 
 extern "C" lm_status lm_adjoint_get(lm_ctx *c, lm_adjoint *out, int mem) {
   if (!c || !out) return LM_EINVAL;
-  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
-  double **a = c->ad[c->ad_cur];
-  double *dst[9] = {out->H, out->v[0], out->v[1], out->F[0], out->F[1], out->rho_prev, out->R_H, out->R_v[0],
-                    out->R_v[1]};
-  const int fd[9] = {-1, -1, -1, 0, 1, -1, -1, -1, -1};
-  for (int q = 0; q < 9; ++q) {
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
+  const int nd = c->grid.ndim;
+  double *arr[12], *dst[12];
+  int fd[12], fd2[12];
+  const int k = adj_arrays(c->ad[c->ad_cur], nd, arr, fd);
+  AdjState view{};
+  view.H = out->H;
+  view.rho_prev = out->rho_prev;
+  view.R_H = out->R_H;
+  for (int d = 0; d < nd; ++d) {
+    view.v[d] = out->v[d];
+    view.F[d] = out->F[d];
+    view.R_v[d] = out->R_v[d];
+  }
+  adj_arrays(view, nd, dst, fd2);
+  for (int q = 0; q < k; ++q) {
     if (!dst[q]) continue;
-    lm_status s = copy_out(c, a[q], dst[q], fd[q], mem);
+    lm_status s = copy_out(c, arr[q], dst[q], fd[q], mem);
     if (s != LM_OK) return s;
   }
   if (mem == LM_DEVICE) HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1269,9 +1348,10 @@ extern "C" lm_status lm_adjoint_get(lm_ctx *c, lm_adjoint *out, int mem) {
 
 extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   if (!c) return LM_EINVAL;
-  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
   const Lay &L = c->lay;
+  const int nd = c->grid.ndim;
   const size_t ab = (size_t)L.total * 8;
   // forward recompute of the step (state at n untouched: outputs go to the
   // predicted and next levels)
@@ -1279,26 +1359,18 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   double rr[2], cm[2];
   lm_status s = do_stage(c, 0, it[0], rr[0], cm[0]);
   if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
+  if (s == LM_OK) s = read_solve_logs(c, it, rr, cm);
   if (s != LM_OK) return s;
   const int first = !c->have_prev;
   const AdjPhys P = adj_phys(c);
   Level &N = c->lev[c->icur], &S = c->lev[c->istar], &X = c->lev[c->inxt];
-  double **ain = c->ad[c->ad_cur];        // cotangent of the step's outputs
-  double **aout = c->ad[c->ad_cur ^ 1];   // cotangent of the step's inputs
-  double **w = c->aw;
-  double *Mb[2] = {w[0], w[1]};
-  double *rhob_new = w[2], *Pb = w[3], *bb = w[4];
-  double *Hb_star = w[5], *vb_star[2] = {w[6], w[7]}, *Fb_star[2] = {w[8], w[9]};
-  double *RbH_star = w[10], *Rbv_star[2] = {w[11], w[12]};
-  double *RbH_n = w[13], *Rbv_n[2] = {w[14], w[15]};
-  double *rhob_n = w[16];
-  double *Fb_n[2] = {aout[3], aout[4]};
-  double *vb_n[2] = {aout[1], aout[2]};
-  double *Fb_in[2] = {ain[3], ain[4]};
-  double *vb_in[2] = {ain[1], ain[2]};
+  AdjState &ain = c->ad[c->ad_cur];        // cotangent of the step's outputs
+  AdjState &aout = c->ad[c->ad_cur ^ 1];   // cotangent of the step's inputs
+  AdjWork &w = c->aw;
   // zero what is accumulated into
-  for (double *z : {Hb_star, vb_star[0], vb_star[1], Fb_star[0], Fb_star[1], Fb_n[0], Fb_n[1]})
-    HIPCHK(c, hipMemsetAsync(z, 0, ab, c->st));
+  HIPCHK(c, hipMemsetAsync(w.Hb_star, 0, ab, c->st));
+  for (int d = 0; d < nd; ++d)
+    for (double *z : {w.vb_star[d], w.Fb_star[d], aout.F[d]}) HIPCHK(c, hipMemsetAsync(z, 0, ab, c->st));
   auto adjoint_solve = [&](double *rhs, double *out) -> lm_status {
     HIPCHK(c, launch_mean(c->st, L, rhs, c->pws.partials, c->pws.sc, c->phys.vol, c->phys.volume));
     int iters = 0, conv = 0;
@@ -1310,55 +1382,51 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
     return LM_OK;
   };
   // corrector: projection, Poisson, right-hand side, EOS and AM2 transposes
-  HIPCHK(c, launch_adj_proj(c->st, L, P, Fb_in, vb_in, X.v, X.rho, Mb, rhob_new, Pb));
-  if ((s = adjoint_solve(Pb, bb)) != LM_OK) return s;
+  HIPCHK(c, launch_adj_proj(c->st, L, P, ain.F, ain.v, X.v, X.rho, w.Mb, w.rhob_new, w.Pb));
+  if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
   AdjTailArgs t{};
   t.L = L;
   t.P = P;
   t.first = first;
   t.corrector = 1;
-  t.bb = bb;
-  t.Mb[0] = Mb[0];
-  t.Mb[1] = Mb[1];
-  t.rhob_new = rhob_new;
+  t.bb = w.bb;
+  t.rhob_new = w.rhob_new;
   t.H_new = X.H;
   t.rho_new = X.rho;
-  t.v_n[0] = N.v[0];
-  t.v_n[1] = N.v[1];
   t.rho_n = N.rho;
-  t.Hb_out = ain[0];
-  t.RbH_out = ain[6];
-  t.Rbv_out[0] = ain[7];
-  t.Rbv_out[1] = ain[8];
-  t.rhoprevb_out = ain[5];
-  t.Hb_star = Hb_star;
-  t.Hb_n = aout[0];
-  t.vb_n[0] = vb_n[0];
-  t.vb_n[1] = vb_n[1];
-  t.rhob_n = rhob_n;
-  t.RbH_star = RbH_star;
-  t.Rbv_star[0] = Rbv_star[0];
-  t.Rbv_star[1] = Rbv_star[1];
-  t.RbH_n = RbH_n;
-  t.Rbv_n[0] = Rbv_n[0];
-  t.Rbv_n[1] = Rbv_n[1];
-  t.rhoprevb_in = aout[5];
-  t.RbH_prev_in = aout[6];
-  t.Rbv_prev_in[0] = aout[7];
-  t.Rbv_prev_in[1] = aout[8];
+  t.Hb_out = ain.H;
+  t.RbH_out = ain.R_H;
+  t.rhoprevb_out = ain.rho_prev;
+  t.Hb_star = w.Hb_star;
+  t.Hb_n = aout.H;
+  t.rhob_n = w.rhob_n;
+  t.RbH_star = w.RbH_star;
+  t.RbH_n = w.RbH_n;
+  t.rhoprevb_in = aout.rho_prev;
+  t.RbH_prev_in = aout.R_H;
+  for (int d = 0; d < nd; ++d) {
+    t.Mb[d] = w.Mb[d];
+    t.v_n[d] = N.v[d];
+    t.Rbv_out[d] = ain.R_v[d];
+    t.vb_n[d] = aout.v[d];
+    t.Rbv_star[d] = w.Rbv_star[d];
+    t.Rbv_n[d] = w.Rbv_n[d];
+    t.Rbv_prev_in[d] = aout.R_v[d];
+  }
   HIPCHK(c, launch_adj_tail(c->st, t));
   // residuals at the predicted level
-  HIPCHK(c, launch_adj_resid(c->st, L, P, S.H, S.v, S.F, RbH_star, Rbv_star, Hb_star, vb_star, Fb_star));
+  HIPCHK(c, launch_adj_resid(c->st, L, P, S.H, S.v, S.F, w.RbH_star, w.Rbv_star, w.Hb_star, w.vb_star,
+                             w.Fb_star));
   // predictor: projection, Poisson, right-hand side, EOS and AB2 transposes
-  HIPCHK(c, launch_adj_proj(c->st, L, P, Fb_star, vb_star, S.v, S.rho, Mb, rhob_new, Pb));
-  if ((s = adjoint_solve(Pb, bb)) != LM_OK) return s;
+  HIPCHK(c, launch_adj_proj(c->st, L, P, w.Fb_star, w.vb_star, S.v, S.rho, w.Mb, w.rhob_new, w.Pb));
+  if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
   t.corrector = 0;
   t.H_new = S.H;
   t.rho_new = S.rho;
   HIPCHK(c, launch_adj_tail(c->st, t));
   // residuals at level n, then the EOS of level n
-  HIPCHK(c, launch_adj_resid(c->st, L, P, N.H, N.v, N.F, RbH_n, Rbv_n, aout[0], vb_n, Fb_n));
-  HIPCHK(c, launch_adj_eos(c->st, L, P, N.H, N.rho, rhob_n, aout[0]));
+  HIPCHK(c, launch_adj_resid(c->st, L, P, N.H, N.v, N.F, w.RbH_n, w.Rbv_n, aout.H, aout.v, aout.F));
+  HIPCHK(c, launch_adj_eos(c->st, L, P, N.H, N.rho, w.rhob_n, aout.H));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->ad_cur ^= 1;
   return LM_OK;
@@ -1366,18 +1434,16 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
 
 extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_bar[3], int mem) {
   if (!c || !T0_bar) return LM_EINVAL;
-  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, "adjoint needs with_adjoint and a 2D periodic grid");
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
   Level &N = c->lev[c->icur];
-  double **a = c->ad[c->ad_cur];
-  double *Fb[2] = {a[3], a[4]};
-  double *vb[2] = {a[1], a[2]};
-  double *Tb = c->aw[17];
-  HIPCHK(c, launch_adj_init(c->st, c->lay, adj_phys(c), N.H, N.rho, N.v, Fb, a[0], vb, Tb));
+  AdjState &a = c->ad[c->ad_cur];
+  double *Tb = c->aw.Tb_init;
+  HIPCHK(c, launch_adj_init(c->st, c->lay, adj_phys(c), N.H, N.rho, N.v, a.F, a.H, a.v, Tb));
   lm_status s = copy_out(c, Tb, T0_bar, -1, mem);
   if (s != LM_OK) return s;
   if (v0_bar) {
-    for (int d = 0; d < 2; ++d)
-      if (v0_bar[d] && (s = copy_out(c, vb[d], v0_bar[d], -1, mem)) != LM_OK) return s;
+    for (int d = 0; d < c->grid.ndim; ++d)
+      if (v0_bar[d] && (s = copy_out(c, a.v[d], v0_bar[d], -1, mem)) != LM_OK) return s;
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;

@@ -192,44 +192,45 @@ hipError_t launch_scale_copy(hipStream_t st, long n, double a, const double *x, 
 hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level &star, const Level &nw,
                          double *partials, double *out);
 
-// ---- adjoint (lm_adjoint.hip): 2D periodic, non-reacting, no body --------
+// ---- adjoint (lm_adjoint.hip): periodic 2D/3D, non-reacting, no body ----
 struct AdjPhys {
-  double h[2];
+  double h[3];
   double Pe, Pr, sigma, inv_Fr2, p0, qs, dt;
   double suth_C;  // > 0: Sutherland's law for kappa (Eq 4.12)
 };
+// Per-direction arrays hold ndim entries.
 struct AdjTailArgs {
   Lay L;
   AdjPhys P;
   int first, corrector;
   const double *bb;
-  double *Mb[2];
+  double *Mb[3];
   double *rhob_new;
   const double *H_new, *rho_new;
-  const double *v_n[2], *rho_n;
-  const double *Hb_out, *RbH_out, *Rbv_out[2], *rhoprevb_out;
+  const double *v_n[3], *rho_n;
+  const double *Hb_out, *RbH_out, *Rbv_out[3], *rhoprevb_out;
   double *Hb_star;
-  double *Hb_n, *vb_n[2], *rhob_n;
-  double *RbH_star, *Rbv_star[2];
-  double *RbH_n, *Rbv_n[2];
-  double *rhoprevb_in, *RbH_prev_in, *Rbv_prev_in[2];
+  double *Hb_n, *vb_n[3], *rhob_n;
+  double *RbH_star, *Rbv_star[3];
+  double *RbH_n, *Rbv_n[3];
+  double *rhoprevb_in, *RbH_prev_in, *Rbv_prev_in[3];
 };
-hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[2],
-                            double *const F[2], const double *RbH, double *const Rbv[2], double *Hb, double *vb[2],
-                            double *Fb[2]);
-hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[2],
-                           double *const vb[2], double *const v[2], const double *rho, double *Mb[2], double *rhob,
+hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[3],
+                            double *const F[3], const double *RbH, double *const Rbv[3], double *Hb, double *vb[3],
+                            double *Fb[3]);
+hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[3],
+                           double *const vb[3], double *const v[3], const double *rho, double *Mb[3], double *rhob,
                            double *Pb);
 hipError_t launch_adj_tail(hipStream_t st, const AdjTailArgs &a);
 hipError_t launch_adj_eos(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
                           const double *rhob, double *Hb);
 hipError_t launch_adj_seed_ke(hipStream_t st, const Lay &L, const AdjPhys &P, double dV, const double *H,
-                              const double *rho, double *const v[2], double *Hb, double *vb[2]);
+                              const double *rho, double *const v[3], double *Hb, double *vb[3]);
 hipError_t launch_adj_init(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
-                           double *const v[2], double *const Fb[2], const double *Hb, double *vb[2], double *Tb);
+                           double *const v[3], double *const Fb[3], const double *Hb, double *vb[3], double *Tb);
 // H_bar += qs T_bar (transpose of the non-reacting map T = qs (H - 1)).
 hipError_t launch_adj_add_T(hipStream_t st, const Lay &L, const AdjPhys &P, const double *Tb, double *Hb);
-hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[2], double dV, double *part,
+hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[3], double dV, double *part,
                      double *out);
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);
 

@@ -3,7 +3,8 @@
 * save/load of the state reproduces a run bit for bit;
 * dot-product test of one adjoint step against the oracle's complex-step
   tangent of the same step: <ybar, J dx> = <J^T ybar, dx> for random
-  cotangents ybar of every output and random directions dx of every input;
+  cotangents ybar of every output and random directions dx of every input,
+  in 2D and 3D (also with buoyancy and Sutherland's conductivity);
 * gradient of the final kinetic energy with respect to T0 (autograd
   Function, checkpointed) against the oracle's complex-step derivative and
   against central finite differences of the GPU forward (h = 1e-6, 16
@@ -33,16 +34,19 @@ def _gpu():
 
 
 def _dt(case):
-    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    nd = case.ndim
+    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc)
     o = Oracle(g, Params(Re=case.params["Re"], Pr=case.params["Pr"], cfl=case.params["cfl"]))
     o.initial_state(case.T, case.v)
     return o.dt
 
 
-def _solver(case, dt, with_adjoint=True, rtol=RTOL, sutherland_C=0.0):
+def _solver(case, dt, with_adjoint=True, rtol=RTOL, sutherland_C=0.0, inv_Fr2=0.0):
     from paper_2603_01727_amd import Solver
-    return Solver(case.n[:2], case.L[:2], bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], dt=dt,
-                  poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint, sutherland_C=sutherland_C)
+    nd = case.ndim
+    return Solver(case.n[:nd], case.L[:nd], bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], dt=dt,
+                  poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint, sutherland_C=sutherland_C,
+                  inv_Fr2=inv_Fr2)
 
 
 def test_state_restart_is_bit_exact():
@@ -89,13 +93,60 @@ def _dot(a, b):
     return out
 
 
-@pytest.mark.parametrize("shape,history,suth", [((72, 80), False, 0.0), ((72, 80), True, 0.0), ((64, 64), True, 0.0),
-                                                ((64, 64), True, 110.5 / 600.0)],
-                         ids=["72x80", "72x80-hist", "64-hist", "64-hist-sutherland"])
-def test_adjoint_step_dot_product_against_oracle_tangent(shape, history, suth):
+def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     """One step back on the GPU against the complex-step tangent of the same
-    step in the oracle, per input component (also with Sutherland's
-    conductivity, Eq 4.12)."""
+    step in the oracle, per input component."""
+    nd = case.ndim
+    dt = 0.5 * _dt(case)
+    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth, inv_Fr2=inv_Fr2)
+    o = Oracle(g, p)
+    st = o.initial_state(case.T, case.v)
+    nhist = 1 if history else 0
+    st = tg.with_eos(o, o.run(st, nhist))
+    s = _solver(case, dt, sutherland_C=suth, inv_Fr2=inv_Fr2)
+    s.set(T=case.T, v=case.v)
+    if nhist:
+        s.step(nhist)
+    rng = np.random.default_rng(seed)
+    # cotangents of the step's outputs (face 0 of a periodic face array is a
+    # duplicate of face n and carries none)
+    ybar = {"H": rng.normal(size=g.shape), "v": [rng.normal(size=g.shape) for _ in range(nd)],
+            "rho_prev": rng.normal(size=g.shape), "R_H": rng.normal(size=g.shape),
+            "R_v": [rng.normal(size=g.shape) for _ in range(nd)]}
+    ybar["F"] = [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(nd)]
+    for d in range(nd):
+        idx = [slice(None)] * nd
+        idx[g.axis(d)] = 0
+        ybar["F"][d][tuple(idx)] = 0.0
+    s.adjoint_set(**ybar)
+    t0 = time.time()
+    s.step_adjoint()
+    xbar = s.adjoint_get(device=False)
+    print("step_adjoint", time.time() - t0, flush=True)
+    comps = ["H", "v", "F"] + (["rho_prev", "R_H", "R_v"] if history else [])
+    for k in comps:
+        if k == "F":
+            dx = {k: [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(nd)]}
+        elif k in ("v", "R_v"):
+            dx = {k: [rng.normal(size=g.shape) for _ in range(nd)]}
+        else:
+            dx = {k: rng.normal(size=g.shape)}
+        ydot = tg.step_tangent(o, st, dx)
+        lhs = _dot(ybar, ydot)
+        rhs = _dot(xbar, dx)
+        print(k, lhs, rhs, abs(lhs - rhs) / abs(lhs), flush=True)
+        assert abs(lhs - rhs) <= 1e-9 * abs(lhs), (k, lhs, rhs)
+
+
+@pytest.mark.parametrize("shape,history,suth,fr", [((72, 80), False, 0.0, 0.0), ((72, 80), True, 0.0, 0.0),
+                                                   ((64, 64), True, 0.0, 0.0),
+                                                   ((64, 64), True, 110.5 / 600.0, 0.0),
+                                                   ((64, 64), True, 0.0, 0.5)],
+                         ids=["72x80", "72x80-hist", "64-hist", "64-hist-sutherland", "64-hist-buoyancy"])
+def test_adjoint_step_dot_product_against_oracle_tangent(shape, history, suth, fr):
+    """2D: also with Sutherland's conductivity (Eq 4.12) and with buoyancy
+    (1/Fr^2 = 0.5, Eq 2.43)."""
     ny, nx = shape
     case = c5_case(n=nx)
     if ny != nx:
@@ -105,48 +156,33 @@ def test_adjoint_step_dot_product_against_oracle_tangent(shape, history, suth):
         case.T = fourier_temperature((nx, ny), L, rng, 8, 3.0)
         case.v = solenoidal_velocity((nx, ny), L, rng, 8, 0.1)
         case.n = (nx, ny, 1)
-    print("adjoint dot", shape, history, flush=True)
-    dt = 0.5 * _dt(case)
-    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
-    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth)
-    o = Oracle(g, p)
-    st = o.initial_state(case.T, case.v)
-    nhist = 1 if history else 0
-    st = tg.with_eos(o, o.run(st, nhist))
-    s = _solver(case, dt, sutherland_C=suth)
-    s.set(T=case.T, v=case.v)
-    if nhist:
-        s.step(nhist)
-    rng = np.random.default_rng(100 + nx + ny)
-    # cotangents of the step's outputs (face 0 of a periodic face array is a
-    # duplicate of face n and carries none)
-    ybar = {"H": rng.normal(size=g.shape), "v": [rng.normal(size=g.shape) for _ in range(2)],
-            "rho_prev": rng.normal(size=g.shape), "R_H": rng.normal(size=g.shape),
-            "R_v": [rng.normal(size=g.shape) for _ in range(2)]}
-    ybar["F"] = [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(2)]
-    for d in range(2):
-        idx = [slice(None)] * 2
-        idx[g.axis(d)] = 0
-        ybar["F"][d][tuple(idx)] = 0.0
-    s.adjoint_set(**ybar)
-    t0 = time.time()
-    s.step_adjoint()
-    xbar = s.adjoint_get(device=False)
-    print("step_adjoint", time.time() - t0, flush=True)
-    comps = [("H",), ("v",), ("F",)] + ([("rho_prev",), ("R_H",), ("R_v",)] if history else [])
-    for keys in comps:
-        k = keys[0]
-        if k == "F":
-            dx = {k: [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(2)]}
-        elif k in ("v", "R_v"):
-            dx = {k: [rng.normal(size=g.shape) for _ in range(2)]}
-        else:
-            dx = {k: rng.normal(size=g.shape)}
-        ydot = tg.step_tangent(o, st, dx)
-        lhs = _dot(ybar, ydot)
-        rhs = _dot(xbar, dx)
-        print(k, lhs, rhs, abs(lhs - rhs) / abs(lhs), flush=True)
-        assert abs(lhs - rhs) <= 1e-9 * abs(lhs), (k, lhs, rhs)
+    print("adjoint dot", shape, history, suth, fr, flush=True)
+    _dot_product_check(case, history, suth, fr, seed=100 + nx + ny)
+
+
+def _case3d(n, seed=8, amp=3.0):
+    """Periodic 2*pi box in 3D with n = (nx, ny, nz): T = 1 + amp fhat
+    (24 modes, |k| <= 3), solenoidal velocity rms 0.1, Re = 300."""
+    from workloads.ics import Case, fourier_temperature, solenoidal_velocity
+    L = (2 * math.pi,) * 3
+    rng = np.random.default_rng(seed)
+    T = fourier_temperature(n, L, rng, 3, amp, m=24)
+    v = solenoidal_velocity(n, L, rng, 3, 0.1, m=24)
+    return Case("adjoint_3d", 3, tuple(n), L, (("periodic", "periodic"),) * 3,
+                dict(Re=300.0, Pr=0.7, cfl=0.3), T, v, nsteps=1)
+
+
+@pytest.mark.parametrize("n,history,suth,fr", [((12, 10, 8), False, 0.0, 0.0), ((12, 10, 8), True, 0.0, 0.5),
+                                               ((20, 18, 16), True, 110.5 / 600.0, 0.0),
+                                               ((24, 16, 20), True, 0.0, 0.5)],
+                         ids=["12x10x8", "12x10x8-hist-buoyancy", "20x18x16-hist-sutherland",
+                              "24x16x20-hist-buoyancy"])
+def test_adjoint_step_dot_product_3d(n, history, suth, fr):
+    """3D: the 3^3-cell residual gather, the three-component projection and
+    Adams transposes; 960 cells take the one-workgroup pressure solve,
+    the larger grids the multi-kernel one."""
+    print("adjoint dot 3d", n, history, suth, fr, flush=True)
+    _dot_product_check(_case3d(n), history, suth, fr, seed=200 + sum(n))
 
 
 def _ke_setup(n, nsteps):
@@ -320,3 +356,52 @@ def test_step_fn_gradients():
             ad += float(torch.sum(v0[1].grad.cpu() * torch.tensor(d)))
         print(which, cs, ad, abs(ad - cs) / abs(cs), flush=True)
         assert abs(ad - cs) <= 1e-9 * abs(cs)
+
+
+def test_ke_gradient_3d_against_oracle_complex_step():
+    """3D, 16^3, 6 steps with checkpoints every 2: the final kinetic energy
+    and its T0-gradient along seeded directions against the oracle's
+    complex-step derivative; then StepFn's v0-gradient of a random linear
+    functional of (T_n, v_n) along a direction in the third velocity
+    component."""
+    import torch
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy, step_fn
+    nsteps, k = 6, 2
+    case = _case3d((16, 16, 16), seed=9)
+    dt = _dt(case)
+    print("ke gradient 3d vs oracle", case.n, nsteps, flush=True)
+    s = _solver(case, dt)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in case.v]
+    J = final_kinetic_energy(s, T0, v0, nsteps, k)
+    J.backward()
+    grad = T0.grad.cpu().numpy()
+    g = Grid(case.n, case.L, bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt)
+    Jo = tg.final_kinetic_energy(g, p, case.T, case.v, nsteps)
+    print("J", J.item(), Jo, flush=True)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    for d in fd_directions(case.T.shape, k=3):
+        cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps)
+        ad = float(np.sum(grad * d))
+        print(cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
+    # StepFn in 3D: a linear functional of (T_n, v_n), direction in v0[2]
+    rng = np.random.default_rng(78)
+    wT = rng.normal(size=case.T.shape)
+    wv = [rng.normal(size=case.T.shape) for _ in range(3)]
+    T1 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v1 = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in case.v]
+    Tn, vn = step_fn(s, T1, v1, nsteps, k)
+    Lf = (torch.tensor(wT, device="cuda") * Tn).sum() + sum((torch.tensor(w, device="cuda") * v).sum()
+                                                              for w, v in zip(wv, vn))
+    Lf.backward()
+    o = Oracle(g, p)
+    d = rng.normal(size=case.T.shape)
+    hstep = 1e-20
+    st = o.initial_state(case.T, [case.v[0], case.v[1], case.v[2] + 1j * hstep * d])
+    st = o.run(st, nsteps)
+    cs = (np.sum(wT * st.T.imag) + sum(np.sum(w * a.imag) for w, a in zip(wv, st.v))) / hstep
+    ad = float(torch.sum(v1[2].grad.cpu() * torch.tensor(d)))
+    print("v0[2]", cs, ad, abs(ad - cs) / abs(cs), flush=True)
+    assert abs(ad - cs) <= 1e-9 * abs(cs)
