@@ -315,8 +315,10 @@ lm_status lm_load_state(lm_ctx *ctx, const void *dev_buf);
  * The adjoint state is the cotangent of the context's state: fields H, v,
  * F (faces) and the history rho^{n-1}, R_H^{n-1}, R_v^{n-1}, with ndim
  * entries in each per-direction array (the rest are ignored). Supported for
- * 2D and 3D periodic, non-reacting grids without immersed body on uniform
- * spacing in FP64 (params with_adjoint = 1; otherwise LM_EUNSUPPORTED).     */
+ * 2D and 3D periodic, non-reacting grids on uniform spacing in FP64, with or
+ * without an immersed body (the body arrays are constants of the step:
+ * they carry no cotangent) (params with_adjoint = 1; otherwise
+ * LM_EUNSUPPORTED).                                                         */
 typedef struct {
   double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
   double *T;   /* lm_adjoint_set only: a cotangent of the temperature,

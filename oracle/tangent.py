@@ -27,18 +27,19 @@ def kinetic_energy(g: Grid, st: State):
     return 0.5 * sum(np.sum(st.rho * a * a) for a in st.v) * g.dV
 
 
-def final_kinetic_energy(g: Grid, p: Params, T0, v0, nsteps: int):
-    """J after nsteps steps from (T0, v0)."""
+def final_kinetic_energy(g: Grid, p: Params, T0, v0, nsteps: int, ib=None):
+    """J after nsteps steps from (T0, v0); ``ib``: the immersed-body arrays
+    (constants of the run)."""
     if not p.dt > 0:
         raise ValueError("complex-step derivatives need a fixed dt")
-    o = Oracle(g, p)
+    o = Oracle(g, p, ib=ib)
     st = o.run(o.initial_state(T0, v0), nsteps)
     return kinetic_energy(g, st)
 
 
-def ke_directional(g: Grid, p: Params, T0, v0, dT, nsteps: int, h: float = H_CS) -> float:
+def ke_directional(g: Grid, p: Params, T0, v0, dT, nsteps: int, h: float = H_CS, ib=None) -> float:
     """dJ/dT0 . dT by one complex-step run."""
-    J = final_kinetic_energy(g, p, np.asarray(T0) + 1j * h * np.asarray(dT), v0, nsteps)
+    J = final_kinetic_energy(g, p, np.asarray(T0) + 1j * h * np.asarray(dT), v0, nsteps, ib=ib)
     return float(J.imag / h)
 
 

@@ -20,11 +20,23 @@ import math
 import torch
 
 
+def _on_device(x, device, mask: bool):
+    """A body array (or list of arrays) as a tensor on the solver's device,
+    so that it travels with device-resident initial fields in one call."""
+    if x is None:
+        return None
+    if isinstance(x, (list, tuple)):
+        return [_on_device(y, device, mask) for y in x]
+    return torch.as_tensor(x, dtype=torch.uint8 if mask else torch.float64, device=device)
+
+
 class Trajectory:
     """Checkpointed forward run of a ``Solver`` built with ``with_adjoint``
-    and a fixed ``dt`` (the gradient is taken at fixed dt)."""
+    and a fixed ``dt`` (the gradient is taken at fixed dt). ``ib``: the
+    immersed-body arrays handed to ``Solver.set`` with the initial state
+    (constants of the run)."""
 
-    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20):
+    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20, ib=None):
         if nsteps < 0 or checkpoint_every < 1:
             raise ValueError("nsteps >= 0 and checkpoint_every >= 1 required")
         if not solver.params.with_adjoint:
@@ -34,13 +46,14 @@ class Trajectory:
         self.solver = solver
         self.nsteps = int(nsteps)
         self.k = int(checkpoint_every)
+        self.ib = None if ib is None else {k: _on_device(x, solver.device, k == "chi") for k, x in ib.items()}
         self.ckpt = {}
         self.tape = []
         self.final = None
 
     def forward(self, T0, v0) -> float:
         s = self.solver
-        s.set(T=T0, v=v0)
+        s.set(T=T0, v=v0, ib=self.ib)
         self.ckpt = {0: s.save_state()}
         done = 0
         while done < self.nsteps:
@@ -88,8 +101,8 @@ class FinalKineticEnergy(torch.autograd.Function):
     with respect to T0 (v0 is held fixed)."""
 
     @staticmethod
-    def forward(ctx, T0, v0, solver, nsteps, checkpoint_every):
-        traj = Trajectory(solver, nsteps, checkpoint_every)
+    def forward(ctx, T0, v0, solver, nsteps, checkpoint_every, ib):
+        traj = Trajectory(solver, nsteps, checkpoint_every, ib)
         J = traj.forward(T0.detach(), [x.detach() for x in v0])
         ctx.traj = traj
         return torch.tensor(J, dtype=torch.float64, device=T0.device)
@@ -97,12 +110,14 @@ class FinalKineticEnergy(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         Tb, _ = ctx.traj.backward()
-        return Tb * gJ.to(Tb.device), None, None, None, None
+        return Tb * gJ.to(Tb.device), None, None, None, None, None
 
 
-def final_kinetic_energy(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_every: int = 20) -> torch.Tensor:
-    """Differentiable J(T0); ``T0`` is a float64 tensor on the solver's device."""
-    return FinalKineticEnergy.apply(T0, list(v0), solver, nsteps, checkpoint_every)
+def final_kinetic_energy(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_every: int = 20,
+                         ib=None) -> torch.Tensor:
+    """Differentiable J(T0); ``T0`` is a float64 tensor on the solver's
+    device; ``ib``: immersed-body arrays as for ``Solver.set``."""
+    return FinalKineticEnergy.apply(T0, list(v0), solver, nsteps, checkpoint_every, ib)
 
 
 class StepFn(torch.autograd.Function):

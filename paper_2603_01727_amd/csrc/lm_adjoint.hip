@@ -1,5 +1,7 @@
 // Adjoint (reverse mode) of one predictor-corrector step for the periodic,
-// non-reacting configuration without immersed boundary, in 2D and 3D. The step
+// non-reacting configuration, in 2D and 3D, with or without an immersed body
+// (volume penalisation, Eq 3.30-3.32; the mass source S_m does not depend on
+// the state and has no cotangent). The step
 // is recomputed forward from the stored state (not committed); the sweep
 // back applies, in reverse order, the transposes of
 //   projection   F = avg(M) - delta_1 P,  v = (M - delta_2 P)/rho   (Eq 3.23, 3.25)
@@ -7,7 +9,8 @@
 //   right side   b = delta_2 . M + BDF(rho)                            (Eq 3.9-3.11)
 //   EOS          rho = p0 / (Q/(S+1) (H - 1))                           (Eq 2.49, 3.42)
 //   Adams steps  AB2 predictor / AM2 corrector                          (Eq 3.1-3.18)
-//   residuals    R_H, R_v of Eq 3.4, 3.8, 3.26 with tau of Eq 2.46.
+//   residuals    R_H, R_v of Eq 3.4, 3.8, 3.26 with tau of Eq 2.46 and the
+//                penalisation terms of Eq 3.30-3.32.
 // The residual transpose is a gather: for every input cell m the residuals
 // of the 3^DIM cells whose stencils reach m are re-evaluated with dual
 // numbers seeded at m (derivatives with respect to H, the DIM velocity
@@ -149,12 +152,18 @@ __device__ inline long pw(const Lay &L, Ix x) {
 }
 
 // Periodic loader of the level fields; values at cell m carry unit seeds:
-// H -> 0, v_c -> 1 + c, F_d -> 1 + DIM + d.
+// H -> 0, v_c -> 1 + c, F_d -> 1 + DIM + d. The body mask and targets are
+// constants (null: no body, or a zero target).
 template <int DIM>
 struct Loader {
   Lay L;
   const double *H, *v[3], *F[3];
+  const unsigned char *chi;
+  const double *H_ib, *v_ib[3];
   Ix m;
+  __device__ double chi_at(Ix x) const { return chi ? (double)chi[L.at(x.i, x.j, x.k)] : 0.0; }
+  __device__ double hib(Ix x) const { return H_ib ? H_ib[L.at(x.i, x.j, x.k)] : 0.0; }
+  __device__ double vib(int c, Ix x) const { return v_ib[c] ? v_ib[c][L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ DD<DIM> load(const double *a, Ix x, int seed) const {
     x = wrap(L, x);
     DD<DIM> r(a[L.at(x.i, x.j, x.k)]);
@@ -225,8 +234,9 @@ __device__ inline void tau_face(const AdjPhys &P, const Loader<DIM> &ld, Ix x, i
   }
 }
 
-// R_H and R_v at cell x: the arithmetic of the forward residual (Eq 3.4a,
-// 3.8a with the flux forms of Eq 3.26), non-reacting, no body.
+// R_H and R_v at cell x (wrapped into the grid): the arithmetic of the
+// forward residual (Eq 3.4a, 3.8a with the flux forms of Eq 3.26), with the
+// penalisation of the body mask chi (Eq 3.30-3.32), non-reacting.
 template <int DIM>
 __device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM> &ld, Ix x, DD<DIM> &RH, DD<DIM> Rv[DIM]) {
   const DD<DIM> Hc = ld.hh(x);
@@ -244,7 +254,10 @@ __device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM> &ld, Ix x,
     adv = adv + 0.5 * (ld.ff(d, x) * gp + ld.ff(d, xm) * gm);
     dif = dif + (kp * gp - km * gm) / P.h[d];
   }
-  RH = (-adv + dif / P.Pe) / rho;
+  const double chi = ld.chi_at(x);
+  DD<DIM> rH = -adv + dif / P.Pe;
+  if (chi != 0.0) rH = rH - chi * (kc * (Hc - ld.hib(x))) / (P.Pe * P.Da);
+  RH = rH / rho;
   DD<DIM> visc[DIM];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) visc[c] = DD<DIM>(0.0);
@@ -269,6 +282,7 @@ __device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM> &ld, Ix x,
     }
     DD<DIM> r = -conv + (P.Pr / P.Pe) * visc[c];
     if (c == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
+    if (chi != 0.0) r = r - chi * (P.Pr / (P.Pe * P.Da)) * (kc * (vc - ld.vib(c, x)));
     Rv[c] = r;
   }
 }
@@ -282,6 +296,8 @@ struct AdjResidArgs {
   const double *H, *v[3], *F[3];        // level at which the residuals are taken
   const double *RbH, *Rbv[3];           // residual cotangents
   double *Hb, *vb[3], *Fb[3];           // accumulated adjoints
+  const unsigned char *chi;             // body mask (null: no body)
+  const double *H_ib, *v_ib[3];         // body targets (null: 0)
 };
 
 // (Hb, vb, Fb) += (dR/d(H, v, F))^T (RbH, Rbv) by gather over the 3^DIM
@@ -299,6 +315,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
     ld.v[d] = a.v[d];
     ld.F[d] = a.F[d];
   }
+  ld.chi = a.chi;
+  ld.H_ib = a.H_ib;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ld.v_ib[d] = a.v_ib[d];
   ld.m = Ix{p.i, p.j, p.k};
   double acc[N];
 #pragma unroll
@@ -334,8 +354,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
 
 hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[3],
                             double *const F[3], const double *RbH, double *const Rbv[3], double *Hb, double *vb[3],
-                            double *Fb[3]) {
+                            double *Fb[3], const IB *ib) {
   AdjResidArgs a{};
+  if (ib && ib->chi) {
+    a.chi = ib->chi;
+    a.H_ib = ib->H_ib;
+    for (int d = 0; d < L.ndim; ++d) a.v_ib[d] = ib->v_ib[d];
+  }
   a.L = L;
   a.P = P;
   a.H = H;

@@ -254,8 +254,8 @@ bool valid_params(const lm_params *p, const char **err) {
     *err = "the adjoint needs a constant thermodynamic pressure";
     return false;
   }
-  if (p->with_adjoint && (p->reacting || p->with_ib || p->precision != LM_FP64)) {
-    *err = "the adjoint supports non-reacting FP64 runs without immersed body";
+  if (p->with_adjoint && (p->reacting || p->precision != LM_FP64)) {
+    *err = "the adjoint supports non-reacting FP64 runs";
     return false;
   }
   return true;
@@ -1189,6 +1189,7 @@ AdjPhys adj_phys(const lm_ctx *c) {
   P.qs = c->phys.qs;
   P.dt = c->phys.dt;
   P.suth_C = c->phys.suth_C;
+  P.Da = c->phys.Da;
   return P;
 }
 
@@ -1415,8 +1416,9 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   }
   HIPCHK(c, launch_adj_tail(c->st, t));
   // residuals at the predicted level
+  const IB *ib = c->phys.has_ib ? &c->ib : nullptr;
   HIPCHK(c, launch_adj_resid(c->st, L, P, S.H, S.v, S.F, w.RbH_star, w.Rbv_star, w.Hb_star, w.vb_star,
-                             w.Fb_star));
+                             w.Fb_star, ib));
   // predictor: projection, Poisson, right-hand side, EOS and AB2 transposes
   HIPCHK(c, launch_adj_proj(c->st, L, P, w.Fb_star, w.vb_star, S.v, S.rho, w.Mb, w.rhob_new, w.Pb));
   if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
@@ -1425,7 +1427,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   t.rho_new = S.rho;
   HIPCHK(c, launch_adj_tail(c->st, t));
   // residuals at level n, then the EOS of level n
-  HIPCHK(c, launch_adj_resid(c->st, L, P, N.H, N.v, N.F, w.RbH_n, w.Rbv_n, aout.H, aout.v, aout.F));
+  HIPCHK(c, launch_adj_resid(c->st, L, P, N.H, N.v, N.F, w.RbH_n, w.Rbv_n, aout.H, aout.v, aout.F, ib));
   HIPCHK(c, launch_adj_eos(c->st, L, P, N.H, N.rho, w.rhob_n, aout.H));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->ad_cur ^= 1;

@@ -192,11 +192,12 @@ hipError_t launch_scale_copy(hipStream_t st, long n, double a, const double *x, 
 hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level &star, const Level &nw,
                          double *partials, double *out);
 
-// ---- adjoint (lm_adjoint.hip): periodic 2D/3D, non-reacting, no body ----
+// ---- adjoint (lm_adjoint.hip): periodic 2D/3D, non-reacting -------------
 struct AdjPhys {
   double h[3];
   double Pe, Pr, sigma, inv_Fr2, p0, qs, dt;
   double suth_C;  // > 0: Sutherland's law for kappa (Eq 4.12)
+  double Da;      // Darcy number of the body penalisation (Eq 3.30)
 };
 // Per-direction arrays hold ndim entries.
 struct AdjTailArgs {
@@ -217,7 +218,7 @@ struct AdjTailArgs {
 };
 hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[3],
                             double *const F[3], const double *RbH, double *const Rbv[3], double *Hb, double *vb[3],
-                            double *Fb[3]);
+                            double *Fb[3], const IB *ib);
 hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[3],
                            double *const vb[3], double *const v[3], const double *rho, double *Mb[3], double *rhob,
                            double *Pb);

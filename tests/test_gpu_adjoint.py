@@ -46,7 +46,7 @@ def _solver(case, dt, with_adjoint=True, rtol=RTOL, sutherland_C=0.0, inv_Fr2=0.
     nd = case.ndim
     return Solver(case.n[:nd], case.L[:nd], bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], dt=dt,
                   poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint, sutherland_C=sutherland_C,
-                  inv_Fr2=inv_Fr2)
+                  inv_Fr2=inv_Fr2, with_ib=case.ib is not None, Da_ib=case.params.get("Da_ib", 1.0))
 
 
 def test_state_restart_is_bit_exact():
@@ -99,13 +99,14 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     nd = case.ndim
     dt = 0.5 * _dt(case)
     g = Grid(case.n[:nd], case.L[:nd], bc=case.bc)
-    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth, inv_Fr2=inv_Fr2)
-    o = Oracle(g, p)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth, inv_Fr2=inv_Fr2,
+               Da_ib=case.params.get("Da_ib", 1.0))
+    o = Oracle(g, p, ib=case.ib)
     st = o.initial_state(case.T, case.v)
     nhist = 1 if history else 0
     st = tg.with_eos(o, o.run(st, nhist))
     s = _solver(case, dt, sutherland_C=suth, inv_Fr2=inv_Fr2)
-    s.set(T=case.T, v=case.v)
+    s.set(T=case.T, v=case.v, ib=case.ib)
     if nhist:
         s.step(nhist)
     rng = np.random.default_rng(seed)
@@ -183,6 +184,67 @@ def test_adjoint_step_dot_product_3d(n, history, suth, fr):
     the larger grids the multi-kernel one."""
     print("adjoint dot 3d", n, history, suth, fr, flush=True)
     _dot_product_check(_case3d(n), history, suth, fr, seed=200 + sum(n))
+
+
+def _with_body(case, seed, Da=0.05, source=False):
+    """The case with a penalised body (Eq 3.30-3.32): a ball of radius 1.2
+    at the box centre turning rigidly about z with unit angular speed
+    (v_ib = (-y, x, 0) about the centre, zero beyond the ball), H_ib = 2.5;
+    with ``source`` also a seeded mass source S_m ~ 0.1 N(0, 1)."""
+    nd = case.ndim
+    from workloads.ics import cell_centres
+    xs = cell_centres(case.n[:nd], case.L[:nd])
+    xs = [x - 0.5 * Lq for x, Lq in zip(xs, case.L[:nd])]
+    X = np.broadcast_arrays(*xs)
+    r2 = sum(x * x for x in X)
+    chi = (r2 < 1.2 ** 2).astype(np.uint8)
+    vib = [np.where(chi == 1, -X[1], 0.0), np.where(chi == 1, X[0], 0.0)] + ([np.zeros(chi.shape)] if nd == 3 else [])
+    ib = dict(chi=chi, v_ib=vib, H_ib=np.full(chi.shape, 2.5))
+    if source:
+        ib["Sm"] = 0.1 * np.random.default_rng(seed).normal(size=chi.shape)
+    case.ib = ib
+    case.params = dict(case.params, Da_ib=Da)
+    return case
+
+
+@pytest.mark.parametrize("dim,history,source", [(2, True, False), (2, False, True), (3, True, True)],
+                         ids=["2d-64-hist", "2d-64-source", "3d-16x14x12-hist-source"])
+def test_adjoint_step_dot_product_immersed_body(dim, history, source):
+    """With a penalised body: the body terms of R_H and R_v enter the
+    residual gather (mask and targets are constants); S_m has no
+    cotangent."""
+    case = c5_case(n=64) if dim == 2 else _case3d((16, 14, 12), seed=11)
+    case = _with_body(case, seed=31, source=source)
+    print("adjoint dot body", dim, history, source, flush=True)
+    _dot_product_check(case, history, seed=300 + dim)
+
+
+def test_ke_gradient_immersed_body_against_oracle_complex_step():
+    """2D 64^2 with the turning body, 6 steps, checkpoints every 2: J and its
+    T0-gradient along 3 seeded directions against the oracle's complex
+    step."""
+    import torch
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    nsteps, k = 6, 2
+    case = _with_body(c5_case(n=64), seed=32, source=True)
+    dt = _dt(case)
+    print("ke gradient with body", nsteps, flush=True)
+    s = _solver(case, dt)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in case.v]
+    J = final_kinetic_energy(s, T0, v0, nsteps, k, ib=case.ib)
+    J.backward()
+    grad = T0.grad.cpu().numpy()
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, Da_ib=case.params["Da_ib"])
+    Jo = tg.final_kinetic_energy(g, p, case.T, case.v, nsteps, ib=case.ib)
+    print("J", J.item(), Jo, flush=True)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    for d in fd_directions(case.T.shape, k=3):
+        cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps, ib=case.ib)
+        ad = float(np.sum(grad * d))
+        print(cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
 
 
 def _ke_setup(n, nsteps):
