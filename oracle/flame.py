@@ -52,8 +52,11 @@ def n_prime_eps(Z, fp: FlameParams):
 
 
 def _lncosh(x):
-    """ln cosh x written as |x| + log1p(exp(-2|x|)) - ln 2 (no overflow)."""
-    ax = np.abs(x)
+    """ln cosh x written as |x| + log1p(exp(-2|x|)) - ln 2 (no overflow).
+    |x| is formed as x times the sign of its real part: the same number for
+    real x, and analytic in x near the real axis (away from 0, where ln cosh
+    is even and smooth), so a complex-step derivative passes through."""
+    ax = x * np.where(np.real(x) < 0.0, -1.0, 1.0)
     return ax + np.log1p(np.exp(-2.0 * ax)) - math.log(2.0)
 
 

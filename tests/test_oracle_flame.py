@@ -94,3 +94,22 @@ def test_lewis_and_n_coefficients_limits():
     assert abs(n_eps(np.float64(-5.0), p) - (1.11 - 1) / 1.11) < 1e-12
     pe = fp()
     assert np.all(n_eps(np.linspace(0, 5, 9), pe) == 0.0)
+
+
+def test_lncosh_sign_form_is_abs_form_and_complex_differentiable():
+    """ln cosh takes |x| as x sign(Re x): on real input the same bits as
+    the |x| form; under a complex step the derivative of F_eps is the
+    regularised dF/dZ = -(1/S + 1) theta_eps(Z - 1) + 1 (Eq 3.39), which a
+    wrong sign choice (the derivative of ln cosh is tanh, odd) would flip on
+    one side of the flame."""
+    from oracle.flame import _lncosh
+    x = np.concatenate([np.linspace(-40.0, 40.0, 801), [0.0, -0.0, 1e-300, -1e-300, 700.0, -700.0]])
+    ax = np.abs(x)
+    ref = ax + np.log1p(np.exp(-2.0 * ax)) - math.log(2.0)
+    assert np.array_equal(_lncosh(x), ref)
+    p = fp(S=2.0)
+    Z = np.array([0.05, 0.5, 0.9, 0.99, 1.01, 1.1, 1.5, 2.9])
+    h = 1e-30
+    d = f_eps(Z + 1j * h, p).imag / h
+    closed = -(1.0 / p.S + 1.0) * theta_eps(Z - 1.0, p) + 1.0
+    assert np.max(np.abs(d - closed)) < 1e-13
