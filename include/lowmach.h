@@ -314,17 +314,20 @@ lm_status lm_load_state(lm_ctx *ctx, const void *dev_buf);
 /* ---- adjoint of the step (reverse mode, hand-written) ---------------------
  * The adjoint state is the cotangent of the context's state: fields H, v,
  * F (faces) and the history rho^{n-1}, R_H^{n-1}, R_v^{n-1}, with ndim
- * entries in each per-direction array (the rest are ignored). Supported for
- * 2D and 3D periodic, non-reacting grids on uniform spacing in FP64, with or
- * without an immersed body (the body arrays are constants of the step:
- * they carry no cotangent) (params with_adjoint = 1; otherwise
- * LM_EUNSUPPORTED).                                                         */
+ * entries in each per-direction array (the rest are ignored), and in
+ * reacting flow also Z and R_Z^{n-1}. Supported for 2D and 3D periodic
+ * grids on uniform spacing in FP64, reacting or not, with or without an
+ * immersed body (the body arrays are constants of the step: they carry no
+ * cotangent) (params with_adjoint = 1; otherwise LM_EUNSUPPORTED).         */
 typedef struct {
   double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
   double *T;   /* lm_adjoint_set only: a cotangent of the temperature,
-                  folded into that of H by the transpose of the equation of
-                  state T = qs (H - 1) (H_bar += qs T_bar, on the device);
-                  ignored by lm_adjoint_get                               */
+                  folded into those of H and Z by the transpose of
+                  T = qs (F~(Z) + H) (Eq 3.42; qs (H - 1) without reaction):
+                  H_bar += qs T_bar, Z_bar += qs F~'(Z) T_bar at the
+                  current state, on the device; ignored by lm_adjoint_get */
+  double *Z, *R_Z; /* reacting flow only (else NULL): the cotangents of Z
+                      and of R_Z^{n-1}                                    */
 } lm_adjoint;
 
 /* Kinetic energy sum_cells 1/2 rho |v|^2 dV of the current state (uniform
@@ -341,10 +344,13 @@ lm_status lm_adjoint_get(lm_ctx *ctx, lm_adjoint *a, int mem);
  * left at n). Each stage needs one adjoint Poisson solve with the same
  * symmetric operator; errors as lm_step.                                    */
 lm_status lm_step_adjoint(lm_ctx *ctx);
-/* With the forward state freshly set from (T0, v0) by lm_set_fields and the
- * adjoint state holding its cotangent: cotangents of T0 and v0 (through
- * H0 = T0/qs + 1, rho0 = p0/T(H0), F0 = face average of rho0 v0). */
-lm_status lm_adjoint_initial(lm_ctx *ctx, double *T0_bar, double *v0_bar[3], int mem);
+/* With the forward state freshly set from (T0, v0) (and Z0 in reacting
+ * flow) by lm_set_fields and the adjoint state holding its cotangent:
+ * cotangents of T0, v0 and Z0 (through H0 = T0/qs - F~(Z0), or T0/qs + 1
+ * without reaction, rho0 = p0/T0, F0 = face average of rho0 v0). v0_bar
+ * entries and Z0_bar may be NULL; Z0_bar must be NULL without reaction
+ * (LM_EINVAL).                                                             */
+lm_status lm_adjoint_initial(lm_ctx *ctx, double *T0_bar, double *v0_bar[3], double *Z0_bar, int mem);
 
 /* Kernel timing hook: launches one kernel class `reps` times back to back on
  * the context's stream between two HIP events and returns the mean duration

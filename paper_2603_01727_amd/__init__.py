@@ -260,7 +260,7 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.lm_load_state(self.ctx, C.c_void_p(buf.data_ptr())))
 
     # ------------------------------------------------------------------
-    # adjoint (periodic 2D or 3D, non-reacting, FP64; needs with_adjoint=True)
+    # adjoint (periodic 2D or 3D, FP64; needs with_adjoint=True)
     def kinetic_energy(self) -> float:
         v = C.c_double()
         _check(self.lib, self.ctx, self.lib.lm_kinetic_energy(self.ctx, C.byref(v)))
@@ -269,12 +269,13 @@ class Solver:
     def adjoint_seed_ke(self):
         _check(self.lib, self.ctx, self.lib.lm_adjoint_seed_ke(self.ctx))
 
-    def adjoint_set(self, H=None, v=None, F=None, rho_prev=None, R_H=None, R_v=None, T=None):
+    def adjoint_set(self, H=None, v=None, F=None, rho_prev=None, R_H=None, R_v=None, T=None, Z=None, R_Z=None):
         """Set the adjoint state; ``T``, a cotangent of the temperature, is
-        folded into that of H by the library."""
+        folded into those of H (and Z in reacting flow) by the library."""
         m = _Marshal(self.torch, self.device)
         a = _L.lm_adjoint()
         a.H, a.rho_prev, a.R_H, a.T = m.ptr(H), m.ptr(rho_prev), m.ptr(R_H), m.ptr(T)
+        a.Z, a.R_Z = m.ptr(Z), m.ptr(R_Z)
         for d in range(self.ndim):
             a.v[d] = m.ptr(v[d]) if v is not None else None
             a.F[d] = m.ptr(F[d]) if F is not None else None
@@ -285,7 +286,7 @@ class Solver:
     def adjoint_get(self, device: bool = True) -> dict:
         """Current adjoint state: H, v, F (faces as in ``get``; the low face
         of cell 0 of a periodic direction is the duplicate of face n and
-        reads 0), rho_prev, R_H, R_v."""
+        reads 0), rho_prev, R_H, R_v, and Z, R_Z in reacting flow."""
         t = self.torch
         keep = []
 
@@ -296,7 +297,8 @@ class Solver:
 
         a = _L.lm_adjoint()
         out = {}
-        for name in ("H", "rho_prev", "R_H"):
+        names = ("H", "rho_prev", "R_H") + (("Z", "R_Z") if self.params.reacting else ())
+        for name in names:
             x, p = alloc(self.shape)
             setattr(a, name, p)
             out[name] = x
@@ -319,17 +321,21 @@ class Solver:
 
     def adjoint_initial(self, device: bool = True):
         """Cotangents (T0_bar, [v0_bar...]) of the initial fields given to
-        ``set(T=..., v=...)``; the forward state must be that initial state."""
+        ``set(T=..., v=...)``, and Z0_bar as a third entry in reacting flow
+        (``set(T=..., v=..., Z=...)``); the forward state must be that
+        initial state."""
         t = self.torch
         mk = (lambda: t.empty(self.shape, dtype=t.float64, device=self.device)) if device else \
             (lambda: np.empty(self.shape))
         Tb = mk()
         vb = [mk() for _ in range(self.ndim)]
+        Zb = mk() if self.params.reacting else None
         ptr = (lambda x: x.data_ptr()) if device else (lambda x: x.ctypes.data)
         arr = (C.c_void_p * 3)(*([ptr(x) for x in vb] + [None] * (3 - self.ndim)))
         _check(self.lib, self.ctx, self.lib.lm_adjoint_initial(self.ctx, C.c_void_p(ptr(Tb)), arr,
+                                                               C.c_void_p(ptr(Zb)) if Zb is not None else None,
                                                                _L.LM_DEVICE if device else _L.LM_HOST))
-        return Tb, vb
+        return (Tb, vb) if Zb is None else (Tb, vb, Zb)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -51,9 +51,10 @@ class Trajectory:
         self.tape = []
         self.final = None
 
-    def forward(self, T0, v0) -> float:
+    def forward(self, T0, v0, Z0=None) -> float:
+        """Runs from (T0, v0), and the mixture fraction Z0 in reacting flow."""
         s = self.solver
-        s.set(T=T0, v=v0, ib=self.ib)
+        s.set(T=T0, v=v0, Z=Z0, ib=self.ib)
         self.ckpt = {0: s.save_state()}
         done = 0
         while done < self.nsteps:
@@ -66,7 +67,8 @@ class Trajectory:
         return s.kinetic_energy()
 
     def backward(self, seed=None):
-        """Returns (T0_bar, [v0_bar...]) as device tensors. ``seed``: the
+        """Returns (T0_bar, [v0_bar...]) as device tensors, and Z0_bar as a
+        third entry in reacting flow. ``seed``: the
         cotangents of the final state as keyword arguments of
         ``Solver.adjoint_set`` (None: the gradient of the final kinetic
         energy)."""
@@ -101,23 +103,24 @@ class FinalKineticEnergy(torch.autograd.Function):
     with respect to T0 (v0 is held fixed)."""
 
     @staticmethod
-    def forward(ctx, T0, v0, solver, nsteps, checkpoint_every, ib):
+    def forward(ctx, T0, v0, solver, nsteps, checkpoint_every, ib, Z0):
         traj = Trajectory(solver, nsteps, checkpoint_every, ib)
-        J = traj.forward(T0.detach(), [x.detach() for x in v0])
+        J = traj.forward(T0.detach(), [x.detach() for x in v0], Z0)
         ctx.traj = traj
         return torch.tensor(J, dtype=torch.float64, device=T0.device)
 
     @staticmethod
     def backward(ctx, gJ):
-        Tb, _ = ctx.traj.backward()
-        return Tb * gJ.to(Tb.device), None, None, None, None, None
+        Tb = ctx.traj.backward()[0]
+        return Tb * gJ.to(Tb.device), None, None, None, None, None, None
 
 
 def final_kinetic_energy(solver, T0: torch.Tensor, v0, nsteps: int, checkpoint_every: int = 20,
-                         ib=None) -> torch.Tensor:
+                         ib=None, Z0=None) -> torch.Tensor:
     """Differentiable J(T0); ``T0`` is a float64 tensor on the solver's
-    device; ``ib``: immersed-body arrays as for ``Solver.set``."""
-    return FinalKineticEnergy.apply(T0, list(v0), solver, nsteps, checkpoint_every, ib)
+    device; ``ib``: immersed-body arrays as for ``Solver.set``; ``Z0``: the
+    initial mixture fraction of a reacting run (held fixed)."""
+    return FinalKineticEnergy.apply(T0, list(v0), solver, nsteps, checkpoint_every, ib, Z0)
 
 
 class StepFn(torch.autograd.Function):
@@ -143,7 +146,7 @@ class StepFn(torch.autograd.Function):
         zero = lambda g: torch.zeros(s.shape, dtype=torch.float64, device=s.device) if g is None else \
             g.to(torch.float64).contiguous()
         seed = {"T": zero(gT), "v": [zero(g) for g in gv]}
-        Tb, vb = ctx.traj.backward(seed)
+        Tb, vb = ctx.traj.backward(seed)[:2]
         return (Tb,) + tuple(vb) + (None, None, None)
 
 

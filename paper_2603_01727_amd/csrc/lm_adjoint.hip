@@ -127,9 +127,10 @@ __device__ inline Dual<N> dpow(const Dual<N> &x, double p) {
 // ---------------------------------------------------------------------------
 // Residuals of one cell, written over a loader of dual-valued fields
 // ---------------------------------------------------------------------------
-// Dual numbers carrying derivatives with respect to H, v (DIM) and F (DIM).
-template <int DIM>
-using DD = Dual<1 + 2 * DIM>;
+// Dual numbers carrying derivatives with respect to H, Z (reacting flow
+// only, R = 1), v (DIM) and F (DIM).
+template <int DIM, int R>
+using DD = Dual<1 + R + 2 * DIM>;
 
 struct Ix {
   int i, j, k;
@@ -152,32 +153,67 @@ __device__ inline long pw(const Lay &L, Ix x) {
 }
 
 // Periodic loader of the level fields; values at cell m carry unit seeds:
-// H -> 0, v_c -> 1 + c, F_d -> 1 + DIM + d. The body mask and targets are
-// constants (null: no body, or a zero target).
-template <int DIM>
+// H -> 0, Z -> 1 (R = 1), v_c -> 1 + R + c, F_d -> 1 + R + DIM + d. The
+// body mask and targets are constants (null: no body, or a zero target).
+template <int DIM, int R>
 struct Loader {
   Lay L;
-  const double *H, *v[3], *F[3];
+  const double *H, *Z, *v[3], *F[3];
   const unsigned char *chi;
-  const double *H_ib, *v_ib[3];
+  const double *H_ib, *Z_ib, *v_ib[3];
   Ix m;
   __device__ double chi_at(Ix x) const { return chi ? (double)chi[L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ double hib(Ix x) const { return H_ib ? H_ib[L.at(x.i, x.j, x.k)] : 0.0; }
+  __device__ double zib(Ix x) const { return Z_ib ? Z_ib[L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ double vib(int c, Ix x) const { return v_ib[c] ? v_ib[c][L.at(x.i, x.j, x.k)] : 0.0; }
-  __device__ DD<DIM> load(const double *a, Ix x, int seed) const {
+  __device__ DD<DIM, R> load(const double *a, Ix x, int seed) const {
     x = wrap(L, x);
-    DD<DIM> r(a[L.at(x.i, x.j, x.k)]);
+    DD<DIM, R> r(a[L.at(x.i, x.j, x.k)]);
     if (x.i == m.i && x.j == m.j && x.k == m.k) r.d[seed] = 1.0;
     return r;
   }
-  __device__ DD<DIM> hh(Ix x) const { return load(H, x, 0); }
-  __device__ DD<DIM> vv(int c, Ix x) const { return load(v[c], x, 1 + c); }
-  __device__ DD<DIM> ff(int d, Ix x) const { return load(F[d], x, 1 + DIM + d); }
+  __device__ DD<DIM, R> hh(Ix x) const { return load(H, x, 0); }
+  __device__ DD<DIM, R> zz(Ix x) const { return load(Z, x, 1); }  // R = 1 only
+  __device__ DD<DIM, R> vv(int c, Ix x) const { return load(v[c], x, 1 + R + c); }
+  __device__ DD<DIM, R> ff(int d, Ix x) const { return load(F[d], x, 1 + R + DIM + d); }
 };
 
+// Flame map (section 3.5): F~(Z) = F_eps(Z) + fshift with
+// F_eps = [-(S+1) ln cosh(k (Z-1))/k + (S-1)(Z-1)]/(2S) (Eq 3.41), so
+// dF~/dZ = [-(S+1) tanh(k (Z-1)) + S - 1]/(2S).
+__device__ inline double ftilde_of(const AdjPhys &P, double Z) {
+  const double S = P.S, k = P.k;
+  return (-(S + 1.0) * lncosh(k * (Z - 1.0)) / k + (S - 1.0) * (Z - 1.0)) / (2.0 * S) + P.fshift;
+}
+__device__ inline double dftilde_of(const AdjPhys &P, double Z) {
+  return (-(P.S + 1.0) * tanh(P.k * (Z - 1.0)) + (P.S - 1.0)) / (2.0 * P.S);
+}
 template <int N>
-__device__ inline Dual<N> temp_of(const AdjPhys &P, const Dual<N> &H) {
-  return P.qs * (H - 1.0);
+__device__ inline Dual<N> ftilde_dual(const AdjPhys &P, const Dual<N> &Z) {
+  Dual<N> r;
+  r.v = ftilde_of(P, Z.v);
+  const double dv = dftilde_of(P, Z.v);
+#pragma unroll
+  for (int q = 0; q < N; ++q) r.d[q] = dv * Z.d[q];
+  return r;
+}
+// theta_eps(Z) = (1 + tanh(k (Z - 1)))/2 (Eq 3.34)
+template <int N>
+__device__ inline Dual<N> theta_dual(const AdjPhys &P, const Dual<N> &Z) {
+  const double t = tanh(P.k * (Z.v - 1.0));
+  Dual<N> r;
+  r.v = 0.5 * (1.0 + t);
+  const double dv = 0.5 * P.k * (1.0 - t * t);
+#pragma unroll
+  for (int q = 0; q < N; ++q) r.d[q] = dv * Z.d[q];
+  return r;
+}
+
+// T(Z, H) of Eq 3.42; without reaction T = qs (H - 1).
+template <int DIM, int R>
+__device__ inline DD<DIM, R> temp_at(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x) {
+  if (R) return P.qs * (ftilde_dual(P, ld.zz(x)) + ld.hh(x));
+  return P.qs * (ld.hh(x) - 1.0);
 }
 
 // kappa(T) with its derivative: T^sigma (Eq 2.50), or Sutherland's law
@@ -196,19 +232,19 @@ __device__ inline Dual<N> kappa_dual(const AdjPhys &P, const Dual<N> &T) {
   return dpow(T, P.sigma);
 }
 
-template <int DIM>
-__device__ inline DD<DIM> kap_at(const AdjPhys &P, const Loader<DIM> &ld, Ix x) {
-  return kappa_dual(P, temp_of(P, ld.hh(x)));
+template <int DIM, int R>
+__device__ inline DD<DIM, R> kap_at(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x) {
+  return kappa_dual(P, temp_at(P, ld, x));
 }
 
 // tau_{d c} for every component c on the face between cell x and its +d
 // neighbour (Eq 2.46 on d-faces): normal derivatives across the face,
 // tangential ones as the mean of the centred differences of the two cells.
-template <int DIM>
-__device__ inline void tau_face(const AdjPhys &P, const Loader<DIM> &ld, Ix x, int d, DD<DIM> tau[DIM]) {
+template <int DIM, int R>
+__device__ inline void tau_face(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x, int d, DD<DIM, R> tau[DIM]) {
   const Ix y = off(x, d, 1);
-  const DD<DIM> kf = 0.5 * (kap_at(P, ld, x) + kap_at(P, ld, y));
-  DD<DIM> D[DIM][DIM];  // D[k][c] = d v_c / d x_k on the face
+  const DD<DIM, R> kf = 0.5 * (kap_at(P, ld, x) + kap_at(P, ld, y));
+  DD<DIM, R> D[DIM][DIM];  // D[k][c] = d v_c / d x_k on the face
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
 #pragma unroll
@@ -217,108 +253,153 @@ __device__ inline void tau_face(const AdjPhys &P, const Loader<DIM> &ld, Ix x, i
         D[k][c] = (ld.vv(c, y) - ld.vv(c, x)) * (1.0 / P.h[d]);
       } else {
         const double h2 = 2.0 * P.h[k];
-        const DD<DIM> a = (ld.vv(c, off(x, k, 1)) - ld.vv(c, off(x, k, -1))) / h2;
-        const DD<DIM> b = (ld.vv(c, off(y, k, 1)) - ld.vv(c, off(y, k, -1))) / h2;
+        const DD<DIM, R> a = (ld.vv(c, off(x, k, 1)) - ld.vv(c, off(x, k, -1))) / h2;
+        const DD<DIM, R> b = (ld.vv(c, off(y, k, 1)) - ld.vv(c, off(y, k, -1))) / h2;
         D[k][c] = 0.5 * (a + b);
       }
     }
   }
-  DD<DIM> div = D[0][0];
+  DD<DIM, R> div = D[0][0];
 #pragma unroll
   for (int k = 1; k < DIM; ++k) div = div + D[k][k];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    DD<DIM> t = D[d][c] + D[c][d];
+    DD<DIM, R> t = D[d][c] + D[c][d];
     if (c == d) t = t - (2.0 / 3.0) * div;
     tau[c] = kf * t;
   }
 }
 
-// R_H and R_v at cell x (wrapped into the grid): the arithmetic of the
-// forward residual (Eq 3.4a, 3.8a with the flux forms of Eq 3.26), with the
-// penalisation of the body mask chi (Eq 3.30-3.32), non-reacting.
-template <int DIM>
-__device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM> &ld, Ix x, DD<DIM> &RH, DD<DIM> Rv[DIM]) {
-  const DD<DIM> Hc = ld.hh(x);
-  const DD<DIM> Tc = temp_of(P, Hc);
-  const DD<DIM> rho = DD<DIM>(P.p0) / Tc;
-  const DD<DIM> kc = kappa_dual(P, Tc);
-  DD<DIM> adv(0.0), dif(0.0);
+// Advection (face fluxes times the one-sided differences, averaged to the
+// centre) and centred diffusion of a scalar at cell x (Eq 3.26b, section
+// 3.2): field 0 H, 1 Z.
+template <int DIM, int R>
+__device__ inline void scalar_dual(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x, int f, const DD<DIM, R> &kc,
+                                   DD<DIM, R> &adv, DD<DIM, R> &dif) {
+  auto val = [&](Ix y) { return f == 0 ? ld.hh(y) : ld.zz(y); };
+  const DD<DIM, R> sc = val(x);
+  adv = DD<DIM, R>(0.0);
+  dif = DD<DIM, R>(0.0);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const Ix xp = off(x, d, 1), xm = off(x, d, -1);
-    const DD<DIM> gp = (ld.hh(xp) - Hc) / P.h[d];
-    const DD<DIM> gm = (Hc - ld.hh(xm)) / P.h[d];
-    const DD<DIM> kp = 0.5 * (kc + kap_at(P, ld, xp));
-    const DD<DIM> km = 0.5 * (kap_at(P, ld, xm) + kc);
+    const DD<DIM, R> gp = (val(xp) - sc) / P.h[d];
+    const DD<DIM, R> gm = (sc - val(xm)) / P.h[d];
+    const DD<DIM, R> kp = 0.5 * (kc + kap_at(P, ld, xp));
+    const DD<DIM, R> km = 0.5 * (kap_at(P, ld, xm) + kc);
     adv = adv + 0.5 * (ld.ff(d, x) * gp + ld.ff(d, xm) * gm);
     dif = dif + (kp * gp - km * gm) / P.h[d];
   }
+}
+
+// R_H, R_Z (R = 1) and R_v at cell x (wrapped into the grid): the
+// arithmetic of the forward residual (Eq 3.2a, 3.4a, 3.8a with the flux
+// forms of Eq 3.26, the Lewis-number factors of Eq 3.35), with the
+// penalisation of the body mask chi (Eq 3.30-3.32).
+template <int DIM, int R>
+__device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x, DD<DIM, R> &RH,
+                                  DD<DIM, R> &RZ, DD<DIM, R> Rv[DIM]) {
+  const DD<DIM, R> Hc = ld.hh(x);
+  const DD<DIM, R> Tc = temp_at(P, ld, x);
+  const DD<DIM, R> rho = DD<DIM, R>(P.p0) / Tc;
+  const DD<DIM, R> kc = kappa_dual(P, Tc);
   const double chi = ld.chi_at(x);
-  DD<DIM> rH = -adv + dif / P.Pe;
+  DD<DIM, R> adv, dif;
+  scalar_dual(P, ld, x, 0, kc, adv, dif);
+  DD<DIM, R> rH = -adv + dif / P.Pe;
+  if (R) {
+    DD<DIM, R> advZ, difZ;
+    scalar_dual(P, ld, x, 1, kc, advZ, difZ);
+    const DD<DIM, R> Zc = ld.zz(x);
+    const DD<DIM, R> th = theta_dual(P, Zc);
+    const DD<DIM, R> le = (P.Le_F - P.Le_O) * th + P.Le_O;
+    const DD<DIM, R> nn = (P.N_F - P.N_O) * th + P.N_O;
+    DD<DIM, R> rZ = -advZ + difZ / (le * P.Pe);
+    rH = rH + nn * difZ / P.Pe;
+    if (chi != 0.0) rZ = rZ - chi * (kc * (Zc - ld.zib(x))) / (le * (P.Pe * P.Da));
+    RZ = rZ / rho;
+  }
   if (chi != 0.0) rH = rH - chi * (kc * (Hc - ld.hib(x))) / (P.Pe * P.Da);
   RH = rH / rho;
-  DD<DIM> visc[DIM];
+  DD<DIM, R> visc[DIM];
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) visc[c] = DD<DIM>(0.0);
+  for (int c = 0; c < DIM; ++c) visc[c] = DD<DIM, R>(0.0);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    DD<DIM> tp[DIM], tm[DIM];
-    tau_face<DIM>(P, ld, x, d, tp);
-    tau_face<DIM>(P, ld, off(x, d, -1), d, tm);
+    DD<DIM, R> tp[DIM], tm[DIM];
+    tau_face<DIM, R>(P, ld, x, d, tp);
+    tau_face<DIM, R>(P, ld, off(x, d, -1), d, tm);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) visc[c] = visc[c] + (tp[c] - tm[c]) / P.h[d];
   }
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    const DD<DIM> vc = ld.vv(c, x);
-    DD<DIM> conv(0.0);
+    const DD<DIM, R> vc = ld.vv(c, x);
+    DD<DIM, R> conv(0.0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const Ix xp = off(x, d, 1), xm = off(x, d, -1);
-      const DD<DIM> flp = ld.ff(d, x) * (0.5 * (vc + ld.vv(c, xp)));
-      const DD<DIM> flm = ld.ff(d, xm) * (0.5 * (ld.vv(c, xm) + vc));
+      const DD<DIM, R> flp = ld.ff(d, x) * (0.5 * (vc + ld.vv(c, xp)));
+      const DD<DIM, R> flm = ld.ff(d, xm) * (0.5 * (ld.vv(c, xm) + vc));
       conv = conv + (flp - flm) / P.h[d];
     }
-    DD<DIM> r = -conv + (P.Pr / P.Pe) * visc[c];
+    DD<DIM, R> r = -conv + (P.Pr / P.Pe) * visc[c];
     if (c == 1 && P.inv_Fr2 != 0.0) r = r + P.inv_Fr2 * (1.0 - rho);
     if (chi != 0.0) r = r - chi * (P.Pr / (P.Pe * P.Da)) * (kc * (vc - ld.vib(c, x)));
     Rv[c] = r;
   }
 }
 
+// Density of the equation of state rho = p0/T(Z, H) and its derivatives
+// d rho/dH = -rho qs/T and d rho/dZ = -rho qs F~'(Z)/T.
+struct EosD {
+  double dH, dZ;
+};
+__device__ inline EosD eos_d(const AdjPhys &P, double rho, double H, double Z) {
+  const double T = P.reacting ? P.qs * (ftilde_of(P, Z) + H) : P.qs * (H - 1.0);
+  const double g = -rho * P.qs / T;
+  return EosD{g, P.reacting ? g * dftilde_of(P, Z) : 0.0};
+}
+
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-struct AdjResidArgs {
-  Lay L;
-  AdjPhys P;
-  const double *H, *v[3], *F[3];        // level at which the residuals are taken
-  const double *RbH, *Rbv[3];           // residual cotangents
-  double *Hb, *vb[3], *Fb[3];           // accumulated adjoints
-  const unsigned char *chi;             // body mask (null: no body)
-  const double *H_ib, *v_ib[3];         // body targets (null: 0)
-};
+// Launch one of the <DIM, R> instances of a kernel.
+#define LM_ADJ_LAUNCH(K, L, R, ...)                                                          \
+  do {                                                                                       \
+    if ((L).ndim == 3) {                                                                     \
+      if (R)                                                                                 \
+        hipLaunchKernelGGL((K<3, 1>), grid_for(L), dim3(kBX, kBY), 0, st, __VA_ARGS__);     \
+      else                                                                                   \
+        hipLaunchKernelGGL((K<3, 0>), grid_for(L), dim3(kBX, kBY), 0, st, __VA_ARGS__);     \
+    } else {                                                                                 \
+      if (R)                                                                                 \
+        hipLaunchKernelGGL((K<2, 1>), grid_for(L), dim3(kBX, kBY), 0, st, __VA_ARGS__);     \
+      else                                                                                   \
+        hipLaunchKernelGGL((K<2, 0>), grid_for(L), dim3(kBX, kBY), 0, st, __VA_ARGS__);     \
+    }                                                                                        \
+  } while (0)
 
-// (Hb, vb, Fb) += (dR/d(H, v, F))^T (RbH, Rbv) by gather over the 3^DIM
-// cells whose residual stencils reach the cell.
-template <int DIM>
+// (Hb, Zb, vb, Fb) += (dR/d(H, Z, v, F))^T (RbH, RbZ, Rbv) by gather over
+// the 3^DIM cells whose residual stencils reach the cell.
+template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
-  constexpr int N = 1 + 2 * DIM;
+  constexpr int N = 1 + R + 2 * DIM;
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
-  Loader<DIM> ld;
+  Loader<DIM, R> ld;
   ld.L = a.L;
   ld.H = a.H;
+  ld.Z = a.Z;
+  ld.chi = a.chi;
+  ld.H_ib = a.H_ib;
+  ld.Z_ib = a.Z_ib;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     ld.v[d] = a.v[d];
     ld.F[d] = a.F[d];
+    ld.v_ib[d] = a.v_ib[d];
   }
-  ld.chi = a.chi;
-  ld.H_ib = a.H_ib;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) ld.v_ib[d] = a.v_ib[d];
   ld.m = Ix{p.i, p.j, p.k};
   double acc[N];
 #pragma unroll
@@ -328,16 +409,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
     for (int dj = -1; dj <= 1; ++dj)
       for (int di = -1; di <= 1; ++di) {
         const Ix x = wrap(a.L, Ix{p.i + di, p.j + dj, p.k + dk});
-        DD<DIM> RH, Rv[DIM];
-        resid_cell<DIM>(a.P, ld, x, RH, Rv);
+        DD<DIM, R> RH, RZ, Rv[DIM];
+        resid_cell<DIM, R>(a.P, ld, x, RH, RZ, Rv);
         const long c = a.L.at(x.i, x.j, x.k);
-        const double rh = a.RbH[c];
+        const double rh = a.RbH[c], rz = R ? a.RbZ[c] : 0.0;
         double r[DIM];
 #pragma unroll
         for (int e = 0; e < DIM; ++e) r[e] = a.Rbv[e][c];
 #pragma unroll
         for (int q = 0; q < N; ++q) {
           double s = rh * RH.d[q];
+          if (R) s += rz * RZ.d[q];
 #pragma unroll
           for (int e = 0; e < DIM; ++e) s += r[e] * Rv[e].d[q];
           acc[q] += s;
@@ -345,52 +427,23 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
       }
   const long m = p.c;
   a.Hb[m] += acc[0];
+  if (R) a.Zb[m] += acc[1];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    a.vb[d][m] += acc[1 + d];
-    a.Fb[d][m] += acc[1 + DIM + d];
+    a.vb[d][m] += acc[1 + R + d];
+    a.Fb[d][m] += acc[1 + R + DIM + d];
   }
 }
 
-hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[3],
-                            double *const F[3], const double *RbH, double *const Rbv[3], double *Hb, double *vb[3],
-                            double *Fb[3], const IB *ib) {
-  AdjResidArgs a{};
-  if (ib && ib->chi) {
-    a.chi = ib->chi;
-    a.H_ib = ib->H_ib;
-    for (int d = 0; d < L.ndim; ++d) a.v_ib[d] = ib->v_ib[d];
-  }
-  a.L = L;
-  a.P = P;
-  a.H = H;
-  for (int d = 0; d < L.ndim; ++d) {
-    a.v[d] = v[d];
-    a.F[d] = F[d];
-    a.Rbv[d] = Rbv[d];
-    a.vb[d] = vb[d];
-    a.Fb[d] = Fb[d];
-  }
-  a.RbH = RbH;
-  a.Hb = Hb;
-  if (L.ndim == 3)
-    hipLaunchKernelGGL(k_adj_resid<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adj_resid<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+hipError_t launch_adj_resid(hipStream_t st, const AdjResidArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_resid, a.L, a.P.reacting, a);
   return hipGetLastError();
 }
-
-struct AdjProjArgs {
-  Lay L;
-  AdjPhys P;
-  const double *Fb[3], *vb[3], *v[3], *rho;
-  double *Mb[3], *rhob, *Pb;
-};
 
 // Transpose of the projection: from (Fb, vb) at the projected level to the
 // momentum cotangent Mb, the density cotangent rhob and the pressure
 // cotangent Pb (= -delta_1^T Fb + delta_2 (vb/rho)).
-template <int DIM>
+template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_adj_proj(AdjProjArgs a) {
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
@@ -411,25 +464,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_proj(AdjProjArgs a) {
   a.Pb[c] = pb;
 }
 
-hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[3],
-                           double *const vb[3], double *const v[3], const double *rho, double *Mb[3], double *rhob,
-                           double *Pb) {
-  AdjProjArgs a{};
-  a.L = L;
-  a.P = P;
-  for (int d = 0; d < L.ndim; ++d) {
-    a.Fb[d] = Fb[d];
-    a.vb[d] = vb[d];
-    a.v[d] = v[d];
-    a.Mb[d] = Mb[d];
-  }
-  a.rho = rho;
-  a.rhob = rhob;
-  a.Pb = Pb;
-  if (L.ndim == 3)
-    hipLaunchKernelGGL(k_adj_proj<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adj_proj<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+hipError_t launch_adj_proj(hipStream_t st, const AdjProjArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_proj, a.L, 0, a);
   return hipGetLastError();
 }
 
@@ -437,11 +473,12 @@ hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, doubl
 // stage (corrector or predictor). AdjTailArgs: bb the zero-mean Poisson
 // right-hand-side cotangent; Mb the momentum cotangent from the projection
 // transpose; rhob_new the cotangent of the stage's new density; for the
-// corrector the cotangents of the step's outputs (Hb_out, RbH_out, Rbv_out,
-// rhoprevb_out); for the predictor Hb_star from the corrector residual
-// transpose; outputs the level-n accumulators, the residual cotangents and
-// the cotangents of the level n-1 history.
-template <int DIM>
+// corrector the cotangents of the step's outputs (Hb_out, Zb_out, RbH_out,
+// RbZ_out, Rbv_out, rhoprevb_out); for the predictor Hb_star, Zb_star from
+// the corrector residual transpose; outputs the level-n accumulators, the
+// residual cotangents and the cotangents of the level n-1 history. H and Z
+// follow the same Adams updates (Eq 3.1, 3.3, 3.12, 3.14).
+template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
@@ -465,18 +502,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
     const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
     Mb[d] = a.Mb[d][c] - (a.bb[cp] - a.bb[cm]) / (2.0 * a.P.h[d]);
   }
-  const double rnew = a.rho_new[c];
-  const double Tnew = a.P.qs * (a.H_new[c] - 1.0);
-  const double drho = -rnew * a.P.qs / Tnew;      // d rho / d H
+  const EosD e = eos_d(a.P, a.rho_new[c], a.H_new[c], R ? a.Z_new[c] : 0.0);
   const double rhob_new = a.rhob_new[c] + c1 * bb;
   const double rho_n = a.rho_n[c];
   double rhob_n = c2 * bb;
   double prevb = c3 * bb;
   if (a.corrector) {
-    const double Hb = a.Hb_out[c] + drho * rhob_new;   // cotangent of H^{n+1}
+    const double Hb = a.Hb_out[c] + e.dH * rhob_new;   // cotangent of H^{n+1}
     a.Hb_n[c] = Hb;
     a.RbH_star[c] = 0.5 * dt * Hb;
     a.RbH_n[c] = 0.5 * dt * Hb + a.RbH_out[c];
+    if (R) {
+      const double Zb = a.Zb_out[c] + e.dZ * rhob_new;  // cotangent of Z^{n+1}
+      a.Zb_n[c] = Zb;
+      a.RbZ_star[c] = 0.5 * dt * Zb;
+      a.RbZ_n[c] = 0.5 * dt * Zb + a.RbZ_out[c];
+    }
     rhob_n += a.rhoprevb_out[c];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -489,10 +530,16 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
     a.rhoprevb_in[c] = prevb;
   } else {
     const double ca = a.first ? 1.0 : 1.5, cb = a.first ? 0.0 : 0.5;
-    const double Hb = a.Hb_star[c] + drho * rhob_new;  // cotangent of H*
+    const double Hb = a.Hb_star[c] + e.dH * rhob_new;  // cotangent of H*
     a.Hb_n[c] += Hb;
     a.RbH_n[c] += dt * ca * Hb;
     a.RbH_prev_in[c] = -dt * cb * Hb;
+    if (R) {
+      const double Zb = a.Zb_star[c] + e.dZ * rhob_new;  // cotangent of Z*
+      a.Zb_n[c] += Zb;
+      a.RbZ_n[c] += dt * ca * Zb;
+      a.RbZ_prev_in[c] = -dt * cb * Zb;
+    }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       rhob_n += Mb[d] * a.v_n[d][c];
@@ -506,59 +553,52 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
 }
 
 hipError_t launch_adj_tail(hipStream_t st, const AdjTailArgs &a) {
-  if (a.L.ndim == 3)
-    hipLaunchKernelGGL(k_adj_tail<3>, grid_for(a.L), dim3(kBX, kBY), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adj_tail<2>, grid_for(a.L), dim3(kBX, kBY), 0, st, a);
+  LM_ADJ_LAUNCH(k_adj_tail, a.L, a.P.reacting, a);
   return hipGetLastError();
 }
 
-// Hb += (d rho/d H) rhob at level n; the step's input cotangent is complete.
-__global__ void __launch_bounds__(kBlock) k_adj_eos(Lay L, AdjPhys P, const double *H, const double *rho,
-                                                    const double *rhob, double *Hb) {
+// (Hb, Zb) += (d rho/d(H, Z)) rhob at level n; the step's input cotangent
+// is complete.
+template <int DIM, int R>
+__global__ void __launch_bounds__(kBlock) k_adj_eos(AdjCellArgs a) {
   CellPos p;
-  if (!cell_of_thread(L, p)) return;
+  if (!cell_of_thread(a.L, p)) return;
   const long c = p.c;
-  const double T = P.qs * (H[c] - 1.0);
-  Hb[c] += -rho[c] * P.qs / T * rhob[c];
+  const EosD e = eos_d(a.P, a.rho[c], a.H[c], R ? a.Z[c] : 0.0);
+  a.Hb[c] += e.dH * a.rhob[c];
+  if (R) a.Zb[c] += e.dZ * a.rhob[c];
 }
 
-hipError_t launch_adj_eos(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
-                          const double *rhob, double *Hb) {
-  hipLaunchKernelGGL(k_adj_eos, grid_for(L), dim3(kBX, kBY), 0, st, L, P, H, rho, rhob, Hb);
+hipError_t launch_adj_eos(hipStream_t st, const AdjCellArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_eos, a.L, a.P.reacting, a);
   return hipGetLastError();
 }
 
-// A cotangent of the temperature folded into that of H: T = qs (H - 1) in
-// non-reacting flow, so H_bar += qs T_bar.
-__global__ void __launch_bounds__(kBlock) k_adj_add_T(Lay L, AdjPhys P, const double *Tb, double *Hb) {
+// A cotangent of the temperature folded into those of H and Z:
+// T = qs (F~(Z) + H) (T = qs (H - 1) without reaction), so H_bar += qs T_bar
+// and Z_bar += qs F~'(Z) T_bar.
+template <int DIM, int R>
+__global__ void __launch_bounds__(kBlock) k_adj_add_T(AdjCellArgs a) {
   CellPos p;
-  if (!cell_of_thread(L, p)) return;
-  Hb[p.c] += P.qs * Tb[p.c];
+  if (!cell_of_thread(a.L, p)) return;
+  const long c = p.c;
+  a.Hb[c] += a.P.qs * a.Tb[c];
+  if (R) a.Zb[c] += a.P.qs * dftilde_of(a.P, a.Z[c]) * a.Tb[c];
 }
 
-hipError_t launch_adj_add_T(hipStream_t st, const Lay &L, const AdjPhys &P, const double *Tb, double *Hb) {
-  hipLaunchKernelGGL(k_adj_add_T, grid_for(L), dim3(kBX, kBY), 0, st, L, P, Tb, Hb);
+hipError_t launch_adj_add_T(hipStream_t st, const AdjCellArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_add_T, a.L, a.P.reacting, a);
   return hipGetLastError();
 }
-
-struct AdjCellArgs {
-  Lay L;
-  AdjPhys P;
-  double dV;
-  const double *H, *rho, *v[3], *Fb[3], *Hb_in;
-  double *Hb, *vb[3], *Tb;
-};
 
 // Cotangent of J = sum 1/2 rho |v|^2 dV at the current level: vb = rho v dV,
-// Hb = (d rho/d H) |v|^2/2 dV, all other cotangents zero.
-template <int DIM>
+// (Hb, Zb) = (d rho/d(H, Z)) |v|^2/2 dV, all other cotangents zero.
+template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_adj_seed_ke(AdjCellArgs a) {
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
   const long c = p.c;
   const double r = a.rho[c];
-  const double T = a.P.qs * (a.H[c] - 1.0);
   double e = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -566,33 +606,23 @@ __global__ void __launch_bounds__(kBlock) k_adj_seed_ke(AdjCellArgs a) {
     e += u * u;
     a.vb[d][c] = r * u * a.dV;
   }
-  a.Hb[c] = -r * a.P.qs / T * (0.5 * e) * a.dV;
+  const EosD g = eos_d(a.P, r, a.H[c], R ? a.Z[c] : 0.0);
+  a.Hb[c] = g.dH * (0.5 * e) * a.dV;
+  if (R) a.Zb[c] = g.dZ * (0.5 * e) * a.dV;
 }
 
-hipError_t launch_adj_seed_ke(hipStream_t st, const Lay &L, const AdjPhys &P, double dV, const double *H,
-                              const double *rho, double *const v[3], double *Hb, double *vb[3]) {
-  AdjCellArgs a{};
-  a.L = L;
-  a.P = P;
-  a.dV = dV;
-  a.H = H;
-  a.rho = rho;
-  for (int d = 0; d < L.ndim; ++d) {
-    a.v[d] = v[d];
-    a.vb[d] = vb[d];
-  }
-  a.Hb = Hb;
-  if (L.ndim == 3)
-    hipLaunchKernelGGL(k_adj_seed_ke<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adj_seed_ke<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+hipError_t launch_adj_seed_ke(hipStream_t st, const AdjCellArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_seed_ke, a.L, a.P.reacting, a);
   return hipGetLastError();
 }
 
-// Adjoint of the initial state built from (T0, v0): F0 = avg(rho0 v0),
-// rho0 = p0/T(H0), H0 = T0/qs + 1. Outputs Tb (cotangent of T0) and adds
-// rho0 avg^T(Fb) to vb.
-template <int DIM>
+// Adjoint of the initial state built from (T0, Z0, v0): H0 = T0/qs - F~(Z0)
+// (T0/qs + 1 without reaction), rho0 = p0/T0, F0 = avg(rho0 v0). Outputs
+// Tb (cotangent of T0), Zb0 (of Z0, reacting flow) and adds
+// rho0 avg^T(Fb) to vb. rho0 depends on T0 alone, so the density cotangent
+// from F0 enters T0 only; the state cotangents of H and Z map through the
+// enthalpy map.
+template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_adj_init(AdjCellArgs a) {
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
@@ -606,35 +636,19 @@ __global__ void __launch_bounds__(kBlock) k_adj_init(AdjCellArgs a) {
     rhob += mb * a.v[d][c];
     a.vb[d][c] += r * mb;
   }
-  const double T = a.P.qs * (a.H[c] - 1.0);
-  const double hb = a.Hb_in[c] - r * a.P.qs / T * rhob;
-  a.Tb[c] = hb / a.P.qs;
+  const double hb = a.Hb_in[c];
+  a.Tb_out[c] = hb / a.P.qs - r * r / a.P.p0 * rhob;  // d rho0/d T0 = -rho0/T0 = -rho0^2/p0
+  if (R) a.Zb0[c] = a.Zb_in[c] - dftilde_of(a.P, a.Z[c]) * hb;
 }
 
-hipError_t launch_adj_init(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
-                           double *const v[3], double *const Fb[3], const double *Hb, double *vb[3], double *Tb) {
-  AdjCellArgs a{};
-  a.L = L;
-  a.P = P;
-  a.H = H;
-  a.rho = rho;
-  for (int d = 0; d < L.ndim; ++d) {
-    a.v[d] = v[d];
-    a.Fb[d] = Fb[d];
-    a.vb[d] = vb[d];
-  }
-  a.Hb_in = Hb;
-  a.Tb = Tb;
-  if (L.ndim == 3)
-    hipLaunchKernelGGL(k_adj_init<3>, grid_for(L), dim3(kBX, kBY), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adj_init<2>, grid_for(L), dim3(kBX, kBY), 0, st, a);
+hipError_t launch_adj_init(hipStream_t st, const AdjCellArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_init, a.L, a.P.reacting, a);
   return hipGetLastError();
 }
 
 // sum over cells of 1/2 rho |v|^2 into per-block partials.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_ke(AdjCellArgs a, double *part) {
+template <int DIM, int R>
+__global__ void __launch_bounds__(kBlock) k_ke(AdjCellArgs a) {
   __shared__ double sh[kBlock / 64];
   CellPos p;
   double e = 0.0;
@@ -645,7 +659,7 @@ __global__ void __launch_bounds__(kBlock) k_ke(AdjCellArgs a, double *part) {
     e = 0.5 * a.rho[p.c] * s;
   }
   const double s = block_sum(e, sh);
-  if (linear_tid() == 0) part[linear_block()] = s;
+  if (linear_tid() == 0) a.part[linear_block()] = s;
 }
 
 __global__ void __launch_bounds__(kBlock) k_ke_finish(const double *part, int np, double dV, double *out) {
@@ -659,11 +673,9 @@ hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *co
   AdjCellArgs a{};
   a.L = L;
   a.rho = rho;
+  a.part = part;
   for (int d = 0; d < L.ndim; ++d) a.v[d] = v[d];
-  if (L.ndim == 3)
-    hipLaunchKernelGGL(k_ke<3>, grid_for(L), dim3(kBX, kBY), 0, st, a, part);
-  else
-    hipLaunchKernelGGL(k_ke<2>, grid_for(L), dim3(kBX, kBY), 0, st, a, part);
+  LM_ADJ_LAUNCH(k_ke, L, 0, a);
   hipLaunchKernelGGL(k_ke_finish, dim3(1), dim3(kBlock), 0, st, (const double *)part, (int)nblocks_for(L), dV, out);
   return hipGetLastError();
 }

@@ -15,14 +15,14 @@ using namespace lm;
 // Cotangent of the context's state (per-direction entries beyond ndim are
 // unused and null).
 struct AdjState {
-  double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
+  double *H, *Z, *v[3], *F[3], *rho_prev, *R_H, *R_Z, *R_v[3];
 };
 // Work arrays of one reverse step.
 struct AdjWork {
   double *Mb[3], *rhob_new, *Pb, *bb;
-  double *Hb_star, *vb_star[3], *Fb_star[3];
-  double *RbH_star, *Rbv_star[3], *RbH_n, *Rbv_n[3], *rhob_n;
-  double *Tb_set, *Tb_init;
+  double *Hb_star, *Zb_star, *vb_star[3], *Fb_star[3];
+  double *RbH_star, *RbZ_star, *Rbv_star[3], *RbH_n, *RbZ_n, *Rbv_n[3], *rhob_n;
+  double *Tb_set, *Tb_init, *Zb_init;
 };
 
 struct lm_ctx {
@@ -254,8 +254,8 @@ bool valid_params(const lm_params *p, const char **err) {
     *err = "the adjoint needs a constant thermodynamic pressure";
     return false;
   }
-  if (p->with_adjoint && (p->reacting || p->precision != LM_FP64)) {
-    *err = "the adjoint supports non-reacting FP64 runs";
+  if (p->with_adjoint && p->precision != LM_FP64) {
+    *err = "the adjoint supports FP64 runs";
     return false;
   }
   return true;
@@ -405,8 +405,10 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
     for (int s = 0; s < 2; ++s) {
       AdjState &a = c->ad[s];
       a.H = take(true);
+      a.Z = take(c->prm.reacting);
       a.rho_prev = take(true);
       a.R_H = take(true);
+      a.R_Z = take(c->prm.reacting);
       for (int d = 0; d < 3; ++d) {
         a.v[d] = take(d < nd);
         a.F[d] = take(d < nd);
@@ -417,6 +419,7 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
     for (double **q : {&w.rhob_new, &w.Pb, &w.bb, &w.Hb_star, &w.RbH_star, &w.RbH_n, &w.rhob_n, &w.Tb_set,
                        &w.Tb_init})
       *q = take(true);
+    for (double **q : {&w.Zb_star, &w.RbZ_star, &w.RbZ_n, &w.Zb_init}) *q = take(c->prm.reacting);
     for (int d = 0; d < 3; ++d)
       for (double **q : {&w.Mb[d], &w.vb_star[d], &w.Fb_star[d], &w.Rbv_star[d], &w.Rbv_n[d]}) *q = take(d < nd);
     c->ad_cur = 0;
@@ -1162,20 +1165,39 @@ int state_arrays(lm_ctx *c, double **out) {
 bool adjoint_ok(lm_ctx *c) { return c->prm.with_adjoint && c->bnd.all_periodic; }
 
 // The arrays of an adjoint state with the face direction of each (-1 for
-// cell arrays), in the order H, v, F, rho_prev, R_H, R_v; returns the count.
-int adj_arrays(const AdjState &a, int nd, double *arr[12], int fd[12]) {
+// cell arrays), in the order H, Z, v, F, rho_prev, R_H, R_Z, R_v (Z and R_Z
+// in reacting flow only); returns the count.
+int adj_arrays(const AdjState &a, int nd, bool react, double *arr[14], int fd[14]) {
   int k = 0;
   auto put = [&](double *x, int f) {
     arr[k] = x;
     fd[k++] = f;
   };
   put(a.H, -1);
+  if (react) put(a.Z, -1);
   for (int d = 0; d < nd; ++d) put(a.v[d], -1);
   for (int d = 0; d < nd; ++d) put(a.F[d], d);
   put(a.rho_prev, -1);
   put(a.R_H, -1);
+  if (react) put(a.R_Z, -1);
   for (int d = 0; d < nd; ++d) put(a.R_v[d], -1);
   return k;
+}
+
+// The caller's lm_adjoint as an adjoint state view.
+AdjState adj_view(const lm_adjoint *in, int nd) {
+  AdjState v{};
+  v.H = in->H;
+  v.Z = in->Z;
+  v.rho_prev = in->rho_prev;
+  v.R_H = in->R_H;
+  v.R_Z = in->R_Z;
+  for (int d = 0; d < nd; ++d) {
+    v.v[d] = in->v[d];
+    v.F[d] = in->F[d];
+    v.R_v[d] = in->R_v[d];
+  }
+  return v;
 }
 
 AdjPhys adj_phys(const lm_ctx *c) {
@@ -1190,6 +1212,14 @@ AdjPhys adj_phys(const lm_ctx *c) {
   P.dt = c->phys.dt;
   P.suth_C = c->phys.suth_C;
   P.Da = c->phys.Da;
+  P.reacting = c->phys.reacting;
+  P.S = c->phys.S;
+  P.k = c->phys.k;
+  P.Le_F = c->phys.Le_F;
+  P.Le_O = c->phys.Le_O;
+  P.N_F = c->phys.N_F;
+  P.N_O = c->phys.N_O;
+  P.fshift = c->phys.fshift;
   return P;
 }
 
@@ -1271,15 +1301,27 @@ extern "C" lm_status lm_adjoint_seed_ke(lm_ctx *c) {
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
   const int nd = c->grid.ndim;
   AdjState &a = c->ad[c->ad_cur];
-  double *arr[12];
-  int fd[12];
-  const int k = adj_arrays(a, nd, arr, fd);
+  double *arr[14];
+  int fd[14];
+  const int k = adj_arrays(a, nd, c->prm.reacting, arr, fd);
   const size_t ab = (size_t)c->lay.total * 8;
   for (int q = 0; q < k; ++q) HIPCHK(c, hipMemsetAsync(arr[q], 0, ab, c->st));
   Level &lv = c->lev[c->icur];
-  double dV = 1.0;
-  for (int d = 0; d < nd; ++d) dV *= c->phys.h[d];
-  HIPCHK(c, launch_adj_seed_ke(c->st, c->lay, adj_phys(c), dV, lv.H, lv.rho, lv.v, a.H, a.v));
+  AdjCellArgs g{};
+  g.L = c->lay;
+  g.P = adj_phys(c);
+  g.dV = 1.0;
+  for (int d = 0; d < nd; ++d) g.dV *= c->phys.h[d];
+  g.H = lv.H;
+  g.Z = lv.Z;
+  g.rho = lv.rho;
+  g.Hb = a.H;
+  g.Zb = a.Z;
+  for (int d = 0; d < nd; ++d) {
+    g.v[d] = lv.v[d];
+    g.vb[d] = a.v[d];
+  }
+  HIPCHK(c, launch_adj_seed_ke(c->st, g));
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;
 }
@@ -1288,21 +1330,13 @@ extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
   if (!c || !in) return LM_EINVAL;
   if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
   const int nd = c->grid.ndim;
+  const bool react = c->prm.reacting;
+  if (!react && (in->Z || in->R_Z)) return fail(c, LM_EINVAL, "Z cotangents need reacting flow");
   AdjState &a = c->ad[c->ad_cur];
-  double *arr[12], *src[12];
-  int fd[12];
-  const int k = adj_arrays(a, nd, arr, fd);
-  AdjState view{};
-  view.H = in->H;
-  view.rho_prev = in->rho_prev;
-  view.R_H = in->R_H;
-  for (int d = 0; d < nd; ++d) {
-    view.v[d] = in->v[d];
-    view.F[d] = in->F[d];
-    view.R_v[d] = in->R_v[d];
-  }
-  int fd2[12];
-  adj_arrays(view, nd, src, fd2);
+  double *arr[14], *src[14];
+  int fd[14], fd2[14];
+  const int k = adj_arrays(a, nd, react, arr, fd);
+  adj_arrays(adj_view(in, nd), nd, react, src, fd2);
   for (int q = 0; q < k; ++q) {
     HIPCHK(c, hipMemsetAsync(arr[q], 0, (size_t)c->lay.total * 8, c->st));
     if (src[q]) {
@@ -1311,11 +1345,20 @@ extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
     }
   }
   if (in->T) {
-    // T = qs (H - 1): the cotangent of T adds qs T_bar to H_bar
+    // T = qs (F~(Z) + H) (qs (H - 1) without reaction) at the current level:
+    // the cotangent of T adds qs T_bar to H_bar and qs F~'(Z) T_bar to Z_bar
+    if (react && !c->have_state) return fail(c, LM_ESTATE, "a T cotangent in reacting flow needs the state");
     double *Tb = c->aw.Tb_set;
     lm_status s = copy_in(c, in->T, Tb, -1, mem);
     if (s != LM_OK) return s;
-    HIPCHK(c, launch_adj_add_T(c->st, c->lay, adj_phys(c), Tb, a.H));
+    AdjCellArgs g{};
+    g.L = c->lay;
+    g.P = adj_phys(c);
+    g.Z = c->lev[c->icur].Z;
+    g.Tb = Tb;
+    g.Hb = a.H;
+    g.Zb = a.Z;
+    HIPCHK(c, launch_adj_add_T(c->st, g));
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LM_OK;
@@ -1325,19 +1368,11 @@ extern "C" lm_status lm_adjoint_get(lm_ctx *c, lm_adjoint *out, int mem) {
   if (!c || !out) return LM_EINVAL;
   if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
   const int nd = c->grid.ndim;
-  double *arr[12], *dst[12];
-  int fd[12], fd2[12];
-  const int k = adj_arrays(c->ad[c->ad_cur], nd, arr, fd);
-  AdjState view{};
-  view.H = out->H;
-  view.rho_prev = out->rho_prev;
-  view.R_H = out->R_H;
-  for (int d = 0; d < nd; ++d) {
-    view.v[d] = out->v[d];
-    view.F[d] = out->F[d];
-    view.R_v[d] = out->R_v[d];
-  }
-  adj_arrays(view, nd, dst, fd2);
+  const bool react = c->prm.reacting;
+  double *arr[14], *dst[14];
+  int fd[14], fd2[14];
+  const int k = adj_arrays(c->ad[c->ad_cur], nd, react, arr, fd);
+  adj_arrays(adj_view(out, nd), nd, react, dst, fd2);
   for (int q = 0; q < k; ++q) {
     if (!dst[q]) continue;
     lm_status s = copy_out(c, arr[q], dst[q], fd[q], mem);
@@ -1353,6 +1388,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
   const Lay &L = c->lay;
   const int nd = c->grid.ndim;
+  const bool react = c->prm.reacting;
   const size_t ab = (size_t)L.total * 8;
   // forward recompute of the step (state at n untouched: outputs go to the
   // predicted and next levels)
@@ -1370,6 +1406,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   AdjWork &w = c->aw;
   // zero what is accumulated into
   HIPCHK(c, hipMemsetAsync(w.Hb_star, 0, ab, c->st));
+  if (react) HIPCHK(c, hipMemsetAsync(w.Zb_star, 0, ab, c->st));
   for (int d = 0; d < nd; ++d)
     for (double *z : {w.vb_star[d], w.Fb_star[d], aout.F[d]}) HIPCHK(c, hipMemsetAsync(z, 0, ab, c->st));
   auto adjoint_solve = [&](double *rhs, double *out) -> lm_status {
@@ -1382,8 +1419,50 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
     HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, out));
     return LM_OK;
   };
+  auto proj = [&](double *const Fb[3], double *const vb[3], const Level &lv) -> hipError_t {
+    AdjProjArgs a{};
+    a.L = L;
+    a.P = P;
+    for (int d = 0; d < nd; ++d) {
+      a.Fb[d] = Fb[d];
+      a.vb[d] = vb[d];
+      a.v[d] = lv.v[d];
+      a.Mb[d] = w.Mb[d];
+    }
+    a.rho = lv.rho;
+    a.rhob = w.rhob_new;
+    a.Pb = w.Pb;
+    return launch_adj_proj(c->st, a);
+  };
+  const IB *ib = c->phys.has_ib ? &c->ib : nullptr;
+  auto resid = [&](const Level &lv, const double *RbH, const double *RbZ, double *const Rbv[3], double *Hb,
+                   double *Zb, double *const vb[3], double *const Fb[3]) -> hipError_t {
+    AdjResidArgs a{};
+    a.L = L;
+    a.P = P;
+    a.H = lv.H;
+    a.Z = lv.Z;
+    a.RbH = RbH;
+    a.RbZ = RbZ;
+    a.Hb = Hb;
+    a.Zb = Zb;
+    for (int d = 0; d < nd; ++d) {
+      a.v[d] = lv.v[d];
+      a.F[d] = lv.F[d];
+      a.Rbv[d] = Rbv[d];
+      a.vb[d] = vb[d];
+      a.Fb[d] = Fb[d];
+    }
+    if (ib && ib->chi) {
+      a.chi = ib->chi;
+      a.H_ib = ib->H_ib;
+      a.Z_ib = ib->Z_ib;
+      for (int d = 0; d < nd; ++d) a.v_ib[d] = ib->v_ib[d];
+    }
+    return launch_adj_resid(c->st, a);
+  };
   // corrector: projection, Poisson, right-hand side, EOS and AM2 transposes
-  HIPCHK(c, launch_adj_proj(c->st, L, P, ain.F, ain.v, X.v, X.rho, w.Mb, w.rhob_new, w.Pb));
+  HIPCHK(c, proj(ain.F, ain.v, X));
   if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
   AdjTailArgs t{};
   t.L = L;
@@ -1393,18 +1472,26 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   t.bb = w.bb;
   t.rhob_new = w.rhob_new;
   t.H_new = X.H;
+  t.Z_new = X.Z;
   t.rho_new = X.rho;
   t.rho_n = N.rho;
   t.Hb_out = ain.H;
+  t.Zb_out = ain.Z;
   t.RbH_out = ain.R_H;
+  t.RbZ_out = ain.R_Z;
   t.rhoprevb_out = ain.rho_prev;
   t.Hb_star = w.Hb_star;
+  t.Zb_star = w.Zb_star;
   t.Hb_n = aout.H;
+  t.Zb_n = aout.Z;
   t.rhob_n = w.rhob_n;
   t.RbH_star = w.RbH_star;
+  t.RbZ_star = w.RbZ_star;
   t.RbH_n = w.RbH_n;
+  t.RbZ_n = w.RbZ_n;
   t.rhoprevb_in = aout.rho_prev;
   t.RbH_prev_in = aout.R_H;
+  t.RbZ_prev_in = aout.R_Z;
   for (int d = 0; d < nd; ++d) {
     t.Mb[d] = w.Mb[d];
     t.v_n[d] = N.v[d];
@@ -1416,35 +1503,61 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   }
   HIPCHK(c, launch_adj_tail(c->st, t));
   // residuals at the predicted level
-  const IB *ib = c->phys.has_ib ? &c->ib : nullptr;
-  HIPCHK(c, launch_adj_resid(c->st, L, P, S.H, S.v, S.F, w.RbH_star, w.Rbv_star, w.Hb_star, w.vb_star,
-                             w.Fb_star, ib));
+  HIPCHK(c, resid(S, w.RbH_star, w.RbZ_star, w.Rbv_star, w.Hb_star, w.Zb_star, w.vb_star, w.Fb_star));
   // predictor: projection, Poisson, right-hand side, EOS and AB2 transposes
-  HIPCHK(c, launch_adj_proj(c->st, L, P, w.Fb_star, w.vb_star, S.v, S.rho, w.Mb, w.rhob_new, w.Pb));
+  HIPCHK(c, proj(w.Fb_star, w.vb_star, S));
   if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
   t.corrector = 0;
   t.H_new = S.H;
+  t.Z_new = S.Z;
   t.rho_new = S.rho;
   HIPCHK(c, launch_adj_tail(c->st, t));
   // residuals at level n, then the EOS of level n
-  HIPCHK(c, launch_adj_resid(c->st, L, P, N.H, N.v, N.F, w.RbH_n, w.Rbv_n, aout.H, aout.v, aout.F, ib));
-  HIPCHK(c, launch_adj_eos(c->st, L, P, N.H, N.rho, w.rhob_n, aout.H));
+  HIPCHK(c, resid(N, w.RbH_n, w.RbZ_n, w.Rbv_n, aout.H, aout.Z, aout.v, aout.F));
+  AdjCellArgs e{};
+  e.L = L;
+  e.P = P;
+  e.H = N.H;
+  e.Z = N.Z;
+  e.rho = N.rho;
+  e.rhob = w.rhob_n;
+  e.Hb = aout.H;
+  e.Zb = aout.Z;
+  HIPCHK(c, launch_adj_eos(c->st, e));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->ad_cur ^= 1;
   return LM_OK;
 }
 
-extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_bar[3], int mem) {
+extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_bar[3], double *Z0_bar, int mem) {
   if (!c || !T0_bar) return LM_EINVAL;
   if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
+  if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
+  if (Z0_bar && !c->prm.reacting) return fail(c, LM_EINVAL, "Z0_bar needs reacting flow");
+  const int nd = c->grid.ndim;
   Level &N = c->lev[c->icur];
   AdjState &a = c->ad[c->ad_cur];
-  double *Tb = c->aw.Tb_init;
-  HIPCHK(c, launch_adj_init(c->st, c->lay, adj_phys(c), N.H, N.rho, N.v, a.F, a.H, a.v, Tb));
-  lm_status s = copy_out(c, Tb, T0_bar, -1, mem);
+  AdjCellArgs g{};
+  g.L = c->lay;
+  g.P = adj_phys(c);
+  g.H = N.H;
+  g.Z = N.Z;
+  g.rho = N.rho;
+  g.Hb_in = a.H;
+  g.Zb_in = a.Z;
+  g.Tb_out = c->aw.Tb_init;
+  g.Zb0 = c->aw.Zb_init;
+  for (int d = 0; d < nd; ++d) {
+    g.v[d] = N.v[d];
+    g.Fb[d] = a.F[d];
+    g.vb[d] = a.v[d];
+  }
+  HIPCHK(c, launch_adj_init(c->st, g));
+  lm_status s = copy_out(c, g.Tb_out, T0_bar, -1, mem);
   if (s != LM_OK) return s;
+  if (Z0_bar && (s = copy_out(c, g.Zb0, Z0_bar, -1, mem)) != LM_OK) return s;
   if (v0_bar) {
-    for (int d = 0; d < c->grid.ndim; ++d)
+    for (int d = 0; d < nd; ++d)
       if (v0_bar[d] && (s = copy_out(c, a.v[d], v0_bar[d], -1, mem)) != LM_OK) return s;
   }
   HIPCHK(c, hipStreamSynchronize(c->st));

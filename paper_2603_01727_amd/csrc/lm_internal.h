@@ -192,14 +192,42 @@ hipError_t launch_scale_copy(hipStream_t st, long n, double a, const double *x, 
 hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level &star, const Level &nw,
                          double *partials, double *out);
 
-// ---- adjoint (lm_adjoint.hip): periodic 2D/3D, non-reacting -------------
+// ---- adjoint (lm_adjoint.hip): periodic 2D/3D ------------------------------
 struct AdjPhys {
   double h[3];
   double Pe, Pr, sigma, inv_Fr2, p0, qs, dt;
   double suth_C;  // > 0: Sutherland's law for kappa (Eq 4.12)
   double Da;      // Darcy number of the body penalisation (Eq 3.30)
+  int reacting;   // flame map and Z transport (section 3.5)
+  double S, k, Le_F, Le_O, N_F, N_O, fshift;
 };
-// Per-direction arrays hold ndim entries.
+// Per-direction arrays hold ndim entries; Z entries are used in reacting
+// flow only.
+struct AdjResidArgs {
+  Lay L;
+  AdjPhys P;
+  const double *H, *Z, *v[3], *F[3];    // level at which the residuals are taken
+  const double *RbH, *RbZ, *Rbv[3];     // residual cotangents
+  double *Hb, *Zb, *vb[3], *Fb[3];      // accumulated adjoints
+  const unsigned char *chi;             // body mask (null: no body)
+  const double *H_ib, *Z_ib, *v_ib[3];  // body targets (null: 0)
+};
+struct AdjProjArgs {
+  Lay L;
+  AdjPhys P;
+  const double *Fb[3], *vb[3], *v[3], *rho;
+  double *Mb[3], *rhob, *Pb;
+};
+// Cell-wise transposes (EOS, temperature, kinetic-energy seed, initial
+// state) and the kinetic-energy sum.
+struct AdjCellArgs {
+  Lay L;
+  AdjPhys P;
+  double dV;
+  const double *H, *Z, *rho, *v[3], *Fb[3], *Hb_in, *Zb_in, *rhob, *Tb;
+  double *Hb, *Zb, *vb[3], *Zb0, *part;
+  double *Tb_out;
+};
 struct AdjTailArgs {
   Lay L;
   AdjPhys P;
@@ -207,30 +235,26 @@ struct AdjTailArgs {
   const double *bb;
   double *Mb[3];
   double *rhob_new;
-  const double *H_new, *rho_new;
+  const double *H_new, *Z_new, *rho_new;
   const double *v_n[3], *rho_n;
-  const double *Hb_out, *RbH_out, *Rbv_out[3], *rhoprevb_out;
-  double *Hb_star;
-  double *Hb_n, *vb_n[3], *rhob_n;
-  double *RbH_star, *Rbv_star[3];
-  double *RbH_n, *Rbv_n[3];
-  double *rhoprevb_in, *RbH_prev_in, *Rbv_prev_in[3];
+  const double *Hb_out, *Zb_out, *RbH_out, *RbZ_out, *Rbv_out[3], *rhoprevb_out;
+  double *Hb_star, *Zb_star;
+  double *Hb_n, *Zb_n, *vb_n[3], *rhob_n;
+  double *RbH_star, *RbZ_star, *Rbv_star[3];
+  double *RbH_n, *RbZ_n, *Rbv_n[3];
+  double *rhoprevb_in, *RbH_prev_in, *RbZ_prev_in, *Rbv_prev_in[3];
 };
-hipError_t launch_adj_resid(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, double *const v[3],
-                            double *const F[3], const double *RbH, double *const Rbv[3], double *Hb, double *vb[3],
-                            double *Fb[3], const IB *ib);
-hipError_t launch_adj_proj(hipStream_t st, const Lay &L, const AdjPhys &P, double *const Fb[3],
-                           double *const vb[3], double *const v[3], const double *rho, double *Mb[3], double *rhob,
-                           double *Pb);
+hipError_t launch_adj_resid(hipStream_t st, const AdjResidArgs &a);
+hipError_t launch_adj_proj(hipStream_t st, const AdjProjArgs &a);
 hipError_t launch_adj_tail(hipStream_t st, const AdjTailArgs &a);
-hipError_t launch_adj_eos(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
-                          const double *rhob, double *Hb);
-hipError_t launch_adj_seed_ke(hipStream_t st, const Lay &L, const AdjPhys &P, double dV, const double *H,
-                              const double *rho, double *const v[3], double *Hb, double *vb[3]);
-hipError_t launch_adj_init(hipStream_t st, const Lay &L, const AdjPhys &P, const double *H, const double *rho,
-                           double *const v[3], double *const Fb[3], const double *Hb, double *vb[3], double *Tb);
-// H_bar += qs T_bar (transpose of the non-reacting map T = qs (H - 1)).
-hipError_t launch_adj_add_T(hipStream_t st, const Lay &L, const AdjPhys &P, const double *Tb, double *Hb);
+// (Hb, Zb) += d rho/d(H, Z) rhob (H, Z, rho, rhob -> Hb, Zb)
+hipError_t launch_adj_eos(hipStream_t st, const AdjCellArgs &a);
+// (Hb, Zb) += transpose of T(Z, H) applied to Tb (H, Z, Tb -> Hb, Zb)
+hipError_t launch_adj_add_T(hipStream_t st, const AdjCellArgs &a);
+// kinetic-energy cotangent (dV, H, Z, rho, v -> Hb, Zb, vb)
+hipError_t launch_adj_seed_ke(hipStream_t st, const AdjCellArgs &a);
+// initial-state transpose (H, Z, rho, v, Fb, Hb_in, Zb_in -> Tb_out, Zb0, vb += )
+hipError_t launch_adj_init(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[3], double dV, double *part,
                      double *out);
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);

@@ -64,7 +64,8 @@ class lm_step_stats(C.Structure):
 
 class lm_adjoint(C.Structure):
     _fields_ = [("H", C.c_void_p), ("v", C.c_void_p * 3), ("F", C.c_void_p * 3), ("rho_prev", C.c_void_p),
-                ("R_H", C.c_void_p), ("R_v", C.c_void_p * 3), ("T", C.c_void_p)]
+                ("R_H", C.c_void_p), ("R_v", C.c_void_p * 3), ("T", C.c_void_p), ("Z", C.c_void_p),
+                ("R_Z", C.c_void_p)]
 
 
 class lm_project_args(C.Structure):
@@ -93,7 +94,7 @@ EXPORTS = {
     "lm_adjoint_set": (C.c_int, [C.c_void_p, C.POINTER(lm_adjoint), C.c_int]),
     "lm_adjoint_get": (C.c_int, [C.c_void_p, C.POINTER(lm_adjoint), C.c_int]),
     "lm_step_adjoint": (C.c_int, [C.c_void_p]),
-    "lm_adjoint_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int]),
+    "lm_adjoint_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_int]),
     "lm_project_static": (C.c_int, [C.POINTER(lm_grid), C.POINTER(lm_params), C.c_void_p,
                                     C.POINTER(lm_project_args)]),
     "lm_last_error": (C.c_char_p, [C.c_void_p]),

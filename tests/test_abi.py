@@ -91,8 +91,11 @@ def test_degenerate_grids_and_params_rejected():
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
     g, p = _grid_params((64, 64))
     p.with_adjoint = 1
-    p.reacting = 1
+    p.precision = lib.LM_MIXED          # the adjoint is FP64 only
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_EINVAL
+    g, p = _grid_params((64, 64))
+    p.with_adjoint, p.reacting = 1, 1   # reacting flow has an adjoint
+    assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
     g, p = _grid_params((4, 4))       # smallest grid: one level, solved by the dense pseudo-inverse
     assert L.lm_workspace_size(C.byref(g), C.byref(p), C.byref(b)) == lib.LM_OK
 

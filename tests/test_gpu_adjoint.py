@@ -41,12 +41,19 @@ def _dt(case):
     return o.dt
 
 
+def _flame(case):
+    """The reacting-flow parameters of a case (empty without reaction)."""
+    keys = ("reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O")
+    return {k: case.params[k] for k in keys if k in case.params}
+
+
 def _solver(case, dt, with_adjoint=True, rtol=RTOL, sutherland_C=0.0, inv_Fr2=0.0):
     from paper_2603_01727_amd import Solver
     nd = case.ndim
     return Solver(case.n[:nd], case.L[:nd], bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], dt=dt,
                   poisson_rtol=rtol, poisson_maxit=400, with_adjoint=with_adjoint, sutherland_C=sutherland_C,
-                  inv_Fr2=inv_Fr2, with_ib=case.ib is not None, Da_ib=case.params.get("Da_ib", 1.0))
+                  inv_Fr2=inv_Fr2, with_ib=case.ib is not None, Da_ib=case.params.get("Da_ib", 1.0),
+                  **_flame(case))
 
 
 def test_state_restart_is_bit_exact():
@@ -100,13 +107,14 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     dt = 0.5 * _dt(case)
     g = Grid(case.n[:nd], case.L[:nd], bc=case.bc)
     p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth, inv_Fr2=inv_Fr2,
-               Da_ib=case.params.get("Da_ib", 1.0))
+               Da_ib=case.params.get("Da_ib", 1.0), **_flame(case))
+    react = p.reacting
     o = Oracle(g, p, ib=case.ib)
-    st = o.initial_state(case.T, case.v)
+    st = o.initial_state(case.T, case.v, Z=case.Z)
     nhist = 1 if history else 0
     st = tg.with_eos(o, o.run(st, nhist))
     s = _solver(case, dt, sutherland_C=suth, inv_Fr2=inv_Fr2)
-    s.set(T=case.T, v=case.v, ib=case.ib)
+    s.set(T=case.T, v=case.v, Z=case.Z, ib=case.ib)
     if nhist:
         s.step(nhist)
     rng = np.random.default_rng(seed)
@@ -116,6 +124,9 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
             "rho_prev": rng.normal(size=g.shape), "R_H": rng.normal(size=g.shape),
             "R_v": [rng.normal(size=g.shape) for _ in range(nd)]}
     ybar["F"] = [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(nd)]
+    if react:
+        ybar["Z"] = rng.normal(size=g.shape)
+        ybar["R_Z"] = rng.normal(size=g.shape)
     for d in range(nd):
         idx = [slice(None)] * nd
         idx[g.axis(d)] = 0
@@ -126,11 +137,15 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     xbar = s.adjoint_get(device=False)
     print("step_adjoint", time.time() - t0, flush=True)
     comps = ["H", "v", "F"] + (["rho_prev", "R_H", "R_v"] if history else [])
+    if react:
+        comps += ["Z"] + (["R_Z"] if history else [])
     for k in comps:
         if k == "F":
             dx = {k: [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(nd)]}
         elif k in ("v", "R_v"):
             dx = {k: [rng.normal(size=g.shape) for _ in range(nd)]}
+        elif k == "Z":
+            dx = {k: 0.1 * rng.normal(size=g.shape)}
         else:
             dx = {k: rng.normal(size=g.shape)}
         ydot = tg.step_tangent(o, st, dx)
@@ -189,8 +204,8 @@ def test_adjoint_step_dot_product_3d(n, history, suth, fr):
 def _with_body(case, seed, Da=0.05, source=False):
     """The case with a penalised body (Eq 3.30-3.32): a ball of radius 1.2
     at the box centre turning rigidly about z with unit angular speed
-    (v_ib = (-y, x, 0) about the centre, zero beyond the ball), H_ib = 2.5;
-    with ``source`` also a seeded mass source S_m ~ 0.1 N(0, 1)."""
+    (v_ib = (-y, x, 0) about the centre, zero beyond the ball), H_ib = 2.5
+    (and Z_ib = 0.5 in reacting flow); with ``source`` also a seeded mass source S_m ~ 0.1 N(0, 1)."""
     nd = case.ndim
     from workloads.ics import cell_centres
     xs = cell_centres(case.n[:nd], case.L[:nd])
@@ -200,6 +215,8 @@ def _with_body(case, seed, Da=0.05, source=False):
     chi = (r2 < 1.2 ** 2).astype(np.uint8)
     vib = [np.where(chi == 1, -X[1], 0.0), np.where(chi == 1, X[0], 0.0)] + ([np.zeros(chi.shape)] if nd == 3 else [])
     ib = dict(chi=chi, v_ib=vib, H_ib=np.full(chi.shape, 2.5))
+    if case.Z is not None:
+        ib["Z_ib"] = np.full(chi.shape, 0.5)
     if source:
         ib["Sm"] = 0.1 * np.random.default_rng(seed).normal(size=chi.shape)
     case.ib = ib
@@ -244,6 +261,61 @@ def test_ke_gradient_immersed_body_against_oracle_complex_step():
         cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps, ib=case.ib)
         ad = float(np.sum(grad * d))
         print(cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
+
+
+@pytest.mark.parametrize("n,history,body", [((64, 64), False, False), ((64, 64), True, False),
+                                             ((72, 56), True, True), ((12, 10, 8), True, False),
+                                             ((16, 14, 12), True, True)],
+                         ids=["2d-64", "2d-64-hist", "2d-72x56-hist-body", "3d-12x10x8-hist",
+                              "3d-16x14x12-hist-body"])
+def test_adjoint_step_dot_product_reacting(n, history, body):
+    """Reacting mixture (Z spans the flame level Z = 1, Le_F = 0.8,
+    Le_O = 1.2): the dual gather carries Z (the flame map T(Z, H) of
+    Eq 3.42, theta_eps and the Lewis factors of Eq 3.34-3.35, the Z
+    transport and its body term), the tail the Z Adams updates and
+    d rho/dZ; per input component including Z and R_Z."""
+    from workloads.ics import reacting_periodic_case
+    case = reacting_periodic_case(n, seed=13)
+    if body:
+        case = _with_body(case, seed=33, source=True)
+    print("adjoint dot reacting", n, history, body, flush=True)
+    _dot_product_check(case, history, seed=400 + sum(n))
+
+
+def test_ke_gradient_reacting_against_oracle_complex_step():
+    """Reacting 2D 64^2, 6 steps, checkpoints every 2: J, its T0-gradient
+    (Z0 fixed) and the Z0-gradient from the initial-state transpose
+    (H0 = T0/qs - F~(Z0)) along seeded directions against the oracle's
+    complex step."""
+    import torch
+    from paper_2603_01727_amd.adjoint import Trajectory
+    from workloads.ics import reacting_periodic_case
+    nsteps, k = 6, 2
+    case = reacting_periodic_case((64, 64), seed=14)
+    dt = _dt(case)
+    print("ke gradient reacting", nsteps, flush=True)
+    s = _solver(case, dt)
+    traj = Trajectory(s, nsteps, k)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    J = traj.forward(dev(case.T), [dev(a) for a in case.v], dev(case.Z))
+    Tb, vb, Zb = traj.backward()
+    Tb, Zb = Tb.cpu().numpy(), Zb.cpu().numpy()
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, **_flame(case))
+    Jo = tg.final_kinetic_energy(g, p, case.T, case.v, nsteps, Z0=case.Z)
+    print("J", J, Jo, flush=True)
+    assert abs(J - Jo) <= 1e-12 * abs(Jo)
+    zero = np.zeros(case.T.shape)
+    for q, d in enumerate(fd_directions(case.T.shape, k=4)):
+        if q % 2 == 0:
+            cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps, Z0=case.Z)
+            ad = float(np.sum(Tb * d))
+        else:
+            d = 0.1 * d
+            cs = tg.ke_directional(g, p, case.T, case.v, zero, nsteps, Z0=case.Z, dZ=d)
+            ad = float(np.sum(Zb * d))
+        print("T0" if q % 2 == 0 else "Z0", cs, ad, abs(ad - cs) / abs(cs), flush=True)
         assert abs(ad - cs) <= 1e-9 * abs(cs)
 
 

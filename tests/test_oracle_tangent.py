@@ -115,3 +115,49 @@ def test_kinetic_energy_of_uniform_flow():
     st = o.initial_state(np.full(g.shape, 2.0), [np.full(g.shape, 0.3), np.full(g.shape, -0.4)])
     J = tg.kinetic_energy(g, st)
     assert abs(J - 0.5 * 0.5 * 0.25 * (2 * math.pi) ** 2) < 1e-13
+
+
+@pytest.mark.parametrize("with_history", [False, True])
+def test_reacting_step_tangent_matches_central_differences(with_history):
+    """Reacting periodic mixture (Z spans the flame level, Le_F != Le_O):
+    the complex-step tangent of one step, along directions in every input
+    including Z and R_Z, against central differences of the real step."""
+    from workloads.ics import reacting_periodic_case
+    c = reacting_periodic_case((20, 16), seed=7)
+    g = Grid(c.n[:2], c.L[:2], bc=c.bc)
+    pr = dict(c.params)
+    pr.pop("cfl")
+    o = Oracle(g, Params(dt=0.02, **pr))
+    st = o.initial_state(c.T, c.v, Z=c.Z)
+    if with_history:
+        st = o.step(st)
+    st = tg.with_eos(o, st)
+    rng = np.random.default_rng(12)
+    dx = _direction(g, rng, with_history)
+    dx["Z"] = 0.1 * rng.normal(size=g.shape)
+    if with_history:
+        dx["R_Z"] = rng.normal(size=g.shape)
+    t = tg.step_tangent(o, st, dx)
+    h = 1e-6
+
+    def real_step(sign):
+        s = st.copy()
+        s.H = s.H + sign * h * dx["H"]
+        s.Z = s.Z + sign * h * dx["Z"]
+        s.v = [a + sign * h * dx["v"][d] for d, a in enumerate(s.v)]
+        s.F = [a + sign * h * dx["F"][d] for d, a in enumerate(s.F)]
+        if with_history:
+            s.rho_prev = s.rho_prev + sign * h * dx["rho_prev"]
+            s.R_prev = dict(s.R_prev)
+            s.R_prev["H"] = s.R_prev["H"] + sign * h * dx["R_H"]
+            s.R_prev["Z"] = s.R_prev["Z"] + sign * h * dx["R_Z"]
+            s.R_prev["v"] = [a + sign * h * dx["R_v"][d] for d, a in enumerate(s.R_prev["v"])]
+        tg.with_eos(o, s)
+        out = o.step(s)
+        return dict(H=out.H, Z=out.Z, v=out.v, F=out.F, rho_prev=out.rho_prev, R_H=out.R_prev["H"],
+                    R_Z=out.R_prev["Z"], R_v=out.R_prev["v"])
+
+    flat = lambda y: np.concatenate([_flat(y), np.ravel(y["Z"]), np.ravel(y["R_Z"])])
+    fd = (flat(real_step(1.0)) - flat(real_step(-1.0))) / (2 * h)
+    cs = flat(t)
+    assert np.linalg.norm(fd - cs) <= 1e-7 * np.linalg.norm(cs)

@@ -81,3 +81,16 @@ def test_stretched_face_generators():
     assert f[0] == 0.0 and f[-1] == L and np.all(w > 0)
     assert 1 - amp - 1e-12 < w.min() and w.max() < 1 + amp + 1e-12
     assert w.max() - w.min() > 1.8 * amp
+
+
+def test_reacting_periodic_case_ranges():
+    """T in [1, 3], Z in [0.2, 1.8] (both ends reached), seeded."""
+    from workloads.ics import reacting_periodic_case
+    c = reacting_periodic_case((24, 20), seed=3)
+    assert c.T.shape == c.Z.shape == (20, 24) and c.ndim == 2 and c.n == (24, 20, 1)
+    assert abs(c.T.min() - 1.0) < 1e-12 and abs(c.T.max() - 3.0) < 1e-12
+    assert abs(c.Z.min() - 0.2) < 1e-12 and abs(c.Z.max() - 1.8) < 1e-12
+    d = reacting_periodic_case((24, 20), seed=3)
+    assert np.array_equal(c.Z, d.Z) and np.array_equal(c.v[0], d.v[0])
+    e = reacting_periodic_case((8, 6, 4), seed=3)
+    assert e.T.shape == (4, 6, 8) and len(e.v) == 3 and e.params["reacting"]

@@ -11,4 +11,5 @@ from .ics import (  # noqa: F401
     solenoidal_velocity, c1_case, c2_case, c3_case, c4_case, c5_case, make_case,
     fd_directions, variable_coefficient_problem, taylor_couette_case,
     heated_cavity_case, double_tsuji_case, tanh_stretched_faces, sine_stretched_faces,
+    reacting_periodic_case,
 )

@@ -249,6 +249,24 @@ def c5_case(n=512, seed=5):
                 nsteps=200)
 
 
+def reacting_periodic_case(n=(64, 64), seed=6, S=2.0, Le_F=0.8, Le_O=1.2):
+    """Periodic 2*pi box in 2D or 3D (n = (nx, ny[, nz])) with a reacting
+    mixture: T = 1 + 2 fhat and Z = 0.2 + 1.6 fhat' (independent Fourier
+    fields, 24 modes, |k| <= 3; Z spans the flame level Z = 1), solenoidal
+    velocity rms 0.1, S = 2, qs = 1, eps = 0.5, tol = 1e-3, Lewis numbers
+    Le_F = 0.8, Le_O = 1.2, Re = 200, Pr = 0.7. Draws: T, then Z, then v."""
+    nd = len(n)
+    L = (2 * math.pi,) * nd
+    rng = np.random.default_rng(seed)
+    T = fourier_temperature(n, L, rng, 3, 2.0, m=24)
+    Z = fourier_temperature(n, L, rng, 3, 1.6, m=24) - 0.8
+    v = solenoidal_velocity(n, L, rng, 3, 0.1, m=24)
+    params = dict(Re=200.0, Pr=0.7, cfl=0.3, reacting=True, S=S, qs=1.0, eps=0.5, tol=1e-3, Le_F=Le_F,
+                  Le_O=Le_O)
+    return Case(f"reacting_periodic_{'x'.join(map(str, n))}", nd, tuple(n) + (1,) * (3 - nd),
+                L + (1.0,) * (3 - nd), (("periodic", "periodic"),) * nd, params, T, v, Z=Z, nsteps=1)
+
+
 def c3_case(nx=768, ny=1536, seed=3, W=32, wall=4, wall_h=64, inj=4,
             Umax=1.0, coflow=0.1, noise=0.01):
     """Planar slot-jet diffusion flame in a channel (nx x ny cells, dx = 1/W).
