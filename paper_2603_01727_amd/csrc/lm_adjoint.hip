@@ -17,6 +17,7 @@
 // components and the DIM face fluxes at m) and contracted with the residual
 // cotangents. No atomics; deterministic.
 #include "lm_device.h"
+#include "lm_sides.h"
 
 namespace lm {
 
@@ -152,12 +153,20 @@ __device__ inline long pw(const Lay &L, Ix x) {
   return L.at(x.i, x.j, x.k);
 }
 
-// Periodic loader of the level fields; values at cell m carry unit seeds:
-// H -> 0, Z -> 1 (R = 1), v_c -> 1 + R + c, F_d -> 1 + R + DIM + d. The
-// body mask and targets are constants (null: no body, or a zero target).
-template <int DIM, int R>
+// Loader of the level fields at cell positions, interior or ghost; values
+// at cell m carry unit seeds: H -> 0, Z -> 1 (R = 1), v_c -> 1 + R + c,
+// F_d -> 1 + R + DIM + d. W = 0: every direction periodic (positions wrap);
+// W = 1: slip / no-slip wall sides as well, whose ghost values follow the
+// forward ghost rules (mirror, or 2 x side value - mirror; corner ghosts by
+// the rules of the highest out-of-range direction first), so that a ghost
+// carries the seed of the interior cell it mirrors with weight -1 or +1.
+// The body mask and targets are constants (null: no body, or a zero
+// target).
+template <int DIM, int R, int W>
 struct Loader {
   Lay L;
+  Bnd B;
+  Sides sd;
   const double *H, *Z, *v[3], *F[3];
   const unsigned char *chi;
   const double *H_ib, *Z_ib, *v_ib[3];
@@ -166,16 +175,51 @@ struct Loader {
   __device__ double hib(Ix x) const { return H_ib ? H_ib[L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ double zib(Ix x) const { return Z_ib ? Z_ib[L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ double vib(int c, Ix x) const { return v_ib[c] ? v_ib[c][L.at(x.i, x.j, x.k)] : 0.0; }
-  __device__ DD<DIM, R> load(const double *a, Ix x, int seed) const {
-    x = wrap(L, x);
-    DD<DIM, R> r(a[L.at(x.i, x.j, x.k)]);
-    if (x.i == m.i && x.j == m.j && x.k == m.k) r.d[seed] = 1.0;
+  // field a with rule set f (0..2 velocity components, 3 Z, 4 H)
+  __device__ DD<DIM, R> load(const double *a, int f, Ix x, int seed) const {
+    if (!W) {
+      x = wrap(L, x);
+      DD<DIM, R> r(a[L.at(x.i, x.j, x.k)]);
+      if (x.i == m.i && x.j == m.j && x.k == m.k) r.d[seed] = 1.0;
+      return r;
+    }
+    int pos[3] = {x.i, x.j, x.k};
+    double w = 1.0, cst = 0.0;
+#pragma unroll
+    for (int d = DIM - 1; d >= 0; --d) {
+      const int n = L.n[d], q = pos[d];
+      if (q >= 0 && q < n) continue;
+      const int s = q < 0 ? 0 : 1;
+      if (B.periodic[d]) {
+        pos[d] = s == 0 ? n - 1 : 0;
+        continue;
+      }
+      if (ghost_rule(B, sd, L, d, s, f, pos[0], pos[1], pos[2]) == R_DIR) {
+        cst += 2.0 * w * side_value(sd, L, d, s, f, pos[0], pos[1], pos[2]);
+        w = -w;
+      }
+      pos[d] = s == 0 ? 0 : n - 1;
+    }
+    DD<DIM, R> r(cst + w * a[L.at(pos[0], pos[1], pos[2])]);
+    if (pos[0] == m.i && pos[1] == m.j && pos[2] == m.k) r.d[seed] = w;
     return r;
   }
-  __device__ DD<DIM, R> hh(Ix x) const { return load(H, x, 0); }
-  __device__ DD<DIM, R> zz(Ix x) const { return load(Z, x, 1); }  // R = 1 only
-  __device__ DD<DIM, R> vv(int c, Ix x) const { return load(v[c], x, 1 + R + c); }
-  __device__ DD<DIM, R> ff(int d, Ix x) const { return load(F[d], x, 1 + R + DIM + d); }
+  __device__ DD<DIM, R> hh(Ix x) const { return load(H, 4, x, 0); }
+  __device__ DD<DIM, R> zz(Ix x) const { return load(Z, 3, x, 1); }  // R = 1 only
+  __device__ DD<DIM, R> vv(int c, Ix x) const { return load(v[c], c, x, 1 + R + c); }
+  // flux on the +d face of x (x interior, or one cell below the low side
+  // along d: that side's face, a constant on a wall)
+  __device__ DD<DIM, R> ff(int d, Ix x) const {
+    if (!W) return load(F[d], 0, x, 1 + R + DIM + d);
+    int pos[3] = {x.i, x.j, x.k};
+    if (pos[d] < 0 && B.periodic[d]) pos[d] += L.n[d];
+    DD<DIM, R> r(F[d][L.at(pos[0], pos[1], pos[2])]);
+    if (pos[0] == m.i && pos[1] == m.j && pos[2] == m.k) r.d[1 + R + DIM + d] = 1.0;
+    return r;
+  }
+  __device__ bool inside(Ix x) const {
+    return x.i >= 0 && x.i < L.n[0] && x.j >= 0 && x.j < L.n[1] && (DIM == 2 || (x.k >= 0 && x.k < L.n[2]));
+  }
 };
 
 // Flame map (section 3.5): F~(Z) = F_eps(Z) + fshift with
@@ -210,8 +254,8 @@ __device__ inline Dual<N> theta_dual(const AdjPhys &P, const Dual<N> &Z) {
 }
 
 // T(Z, H) of Eq 3.42; without reaction T = qs (H - 1).
-template <int DIM, int R>
-__device__ inline DD<DIM, R> temp_at(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x) {
+template <int DIM, int R, int W>
+__device__ inline DD<DIM, R> temp_at(const AdjPhys &P, const Loader<DIM, R, W> &ld, Ix x) {
   if (R) return P.qs * (ftilde_dual(P, ld.zz(x)) + ld.hh(x));
   return P.qs * (ld.hh(x) - 1.0);
 }
@@ -232,16 +276,33 @@ __device__ inline Dual<N> kappa_dual(const AdjPhys &P, const Dual<N> &T) {
   return dpow(T, P.sigma);
 }
 
-template <int DIM, int R>
-__device__ inline DD<DIM, R> kap_at(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x) {
-  return kappa_dual(P, temp_at(P, ld, x));
+// Conductivity at a cell position. Ghosts (W = 1) follow the forward ghost
+// fill: at an isothermal wall 2 kappa(T_w) - kappa(T) of the interior cell
+// the ghost position clamps to; elsewhere kappa of the ghost temperature,
+// with the ghost Z clamped to [0, S+1].
+template <int DIM, int R, int W>
+__device__ inline DD<DIM, R> kap_at(const AdjPhys &P, const Loader<DIM, R, W> &ld, Ix x) {
+  if (!W || ld.inside(x)) return kappa_dual(P, temp_at(P, ld, x));
+  int dw, sw;
+  if (isothermal_ghost<DIM>(ld.L, ld.B, ld.sd, x.i, x.j, x.k, dw, sw)) {
+    const double Hw = side_value(ld.sd, ld.L, dw, sw, 4, x.i, x.j, x.k);
+    const double Tw = P.reacting ? P.qs * (ftilde_of(P, 0.0) + Hw) : P.qs * (Hw - 1.0);
+    const Ix src{min(max(x.i, 0), ld.L.n[0] - 1), min(max(x.j, 0), ld.L.n[1] - 1),
+                 DIM == 3 ? min(max(x.k, 0), ld.L.n[2] - 1) : x.k};
+    return 2.0 * kappa_dual(P, DD<DIM, R>(Tw)).v - kappa_dual(P, temp_at(P, ld, src));
+  }
+  const DD<DIM, R> H = ld.hh(x);
+  if (!R) return kappa_dual(P, P.qs * (H - 1.0));
+  DD<DIM, R> Z = ld.zz(x);
+  if (Z.v < 0.0 || Z.v > P.S + 1.0) Z = DD<DIM, R>(fmin(fmax(Z.v, 0.0), P.S + 1.0));
+  return kappa_dual(P, P.qs * (ftilde_dual(P, Z) + H));
 }
 
 // tau_{d c} for every component c on the face between cell x and its +d
 // neighbour (Eq 2.46 on d-faces): normal derivatives across the face,
 // tangential ones as the mean of the centred differences of the two cells.
-template <int DIM, int R>
-__device__ inline void tau_face(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x, int d, DD<DIM, R> tau[DIM]) {
+template <int DIM, int R, int W>
+__device__ inline void tau_face(const AdjPhys &P, const Loader<DIM, R, W> &ld, Ix x, int d, DD<DIM, R> tau[DIM]) {
   const Ix y = off(x, d, 1);
   const DD<DIM, R> kf = 0.5 * (kap_at(P, ld, x) + kap_at(P, ld, y));
   DD<DIM, R> D[DIM][DIM];  // D[k][c] = d v_c / d x_k on the face
@@ -273,8 +334,8 @@ __device__ inline void tau_face(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x
 // Advection (face fluxes times the one-sided differences, averaged to the
 // centre) and centred diffusion of a scalar at cell x (Eq 3.26b, section
 // 3.2): field 0 H, 1 Z.
-template <int DIM, int R>
-__device__ inline void scalar_dual(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x, int f, const DD<DIM, R> &kc,
+template <int DIM, int R, int W>
+__device__ inline void scalar_dual(const AdjPhys &P, const Loader<DIM, R, W> &ld, Ix x, int f, const DD<DIM, R> &kc,
                                    DD<DIM, R> &adv, DD<DIM, R> &dif) {
   auto val = [&](Ix y) { return f == 0 ? ld.hh(y) : ld.zz(y); };
   const DD<DIM, R> sc = val(x);
@@ -296,8 +357,8 @@ __device__ inline void scalar_dual(const AdjPhys &P, const Loader<DIM, R> &ld, I
 // arithmetic of the forward residual (Eq 3.2a, 3.4a, 3.8a with the flux
 // forms of Eq 3.26, the Lewis-number factors of Eq 3.35), with the
 // penalisation of the body mask chi (Eq 3.30-3.32).
-template <int DIM, int R>
-__device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM, R> &ld, Ix x, DD<DIM, R> &RH,
+template <int DIM, int R, int W>
+__device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM, R, W> &ld, Ix x, DD<DIM, R> &RH,
                                   DD<DIM, R> &RZ, DD<DIM, R> Rv[DIM]) {
   const DD<DIM, R> Hc = ld.hh(x);
   const DD<DIM, R> Tc = temp_at(P, ld, x);
@@ -327,8 +388,8 @@ __device__ inline void resid_cell(const AdjPhys &P, const Loader<DIM, R> &ld, Ix
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     DD<DIM, R> tp[DIM], tm[DIM];
-    tau_face<DIM, R>(P, ld, x, d, tp);
-    tau_face<DIM, R>(P, ld, off(x, d, -1), d, tm);
+    tau_face<DIM, R, W>(P, ld, x, d, tp);
+    tau_face<DIM, R, W>(P, ld, off(x, d, -1), d, tm);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) visc[c] = visc[c] + (tp[c] - tm[c]) / P.h[d];
   }
@@ -381,14 +442,18 @@ __device__ inline EosD eos_d(const AdjPhys &P, double rho, double H, double Z) {
   } while (0)
 
 // (Hb, Zb, vb, Fb) += (dR/d(H, Z, v, F))^T (RbH, RbZ, Rbv) by gather over
-// the 3^DIM cells whose residual stencils reach the cell.
-template <int DIM, int R>
+// the 3^DIM cells whose residual stencils reach the cell (with walls, the
+// interior ones: a ghost mirrors a cell within one cell of the reader).
+// The flux of a wall face is a constant of the step: its cotangent stays 0.
+template <int DIM, int R, int W>
 __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   constexpr int N = 1 + R + 2 * DIM;
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
-  Loader<DIM, R> ld;
+  Loader<DIM, R, W> ld;
   ld.L = a.L;
+  ld.B = a.B;
+  ld.sd = a.sd;
   ld.H = a.H;
   ld.Z = a.Z;
   ld.chi = a.chi;
@@ -408,9 +473,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   for (int dk = -kr; dk <= kr; ++dk)
     for (int dj = -1; dj <= 1; ++dj)
       for (int di = -1; di <= 1; ++di) {
-        const Ix x = wrap(a.L, Ix{p.i + di, p.j + dj, p.k + dk});
+        Ix x{p.i + di, p.j + dj, p.k + dk};
+        if (W && !ld.inside(x)) {
+          const int q[3] = {x.i, x.j, x.k};
+          bool wall = false;
+          for (int d = 0; d < DIM; ++d)
+            if ((q[d] < 0 || q[d] >= a.L.n[d]) && !a.B.periodic[d]) wall = true;
+          if (wall) continue;  // a ghost has no residual
+        }
+        x = wrap(a.L, x);
         DD<DIM, R> RH, RZ, Rv[DIM];
-        resid_cell<DIM, R>(a.P, ld, x, RH, RZ, Rv);
+        resid_cell<DIM, R, W>(a.P, ld, x, RH, RZ, Rv);
         const long c = a.L.at(x.i, x.j, x.k);
         const double rh = a.RbH[c], rz = R ? a.RbZ[c] : 0.0;
         double r[DIM];
@@ -428,21 +501,47 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   const long m = p.c;
   a.Hb[m] += acc[0];
   if (R) a.Zb[m] += acc[1];
+  const int pm[3] = {p.i, p.j, p.k};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     a.vb[d][m] += acc[1 + R + d];
-    a.Fb[d][m] += acc[1 + R + DIM + d];
+    if (!W || a.B.periodic[d] || pm[d] + 1 < a.L.n[d]) a.Fb[d][m] += acc[1 + R + DIM + d];
   }
 }
 
 hipError_t launch_adj_resid(hipStream_t st, const AdjResidArgs &a) {
-  LM_ADJ_LAUNCH(k_adj_resid, a.L, a.P.reacting, a);
+  const dim3 g = grid_for(a.L), bl(kBX, kBY);
+  const int sel = (a.L.ndim == 3 ? 4 : 0) + (a.P.reacting ? 2 : 0) + (a.B.all_periodic ? 0 : 1);
+  switch (sel) {
+    case 0: hipLaunchKernelGGL((k_adj_resid<2, 0, 0>), g, bl, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_adj_resid<2, 0, 1>), g, bl, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_adj_resid<2, 1, 0>), g, bl, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_adj_resid<2, 1, 1>), g, bl, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_adj_resid<3, 0, 0>), g, bl, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_adj_resid<3, 0, 1>), g, bl, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_adj_resid<3, 1, 0>), g, bl, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_adj_resid<3, 1, 1>), g, bl, 0, st, a); break;
+  }
   return hipGetLastError();
+}
+
+// Coefficient of x_q in (xm - xp) at cell qq of a direction with two wall
+// sides (n >= 3): xp, xm are the neighbours of qq, or at the sides the
+// ghost 3 x_0 - 3 x_1 + x_2 (mirrored at the high side) of the quadratic
+// extrapolation the projection uses (Eq 3.27-3.28).
+__device__ inline double xcoef(int qq, int q, int n) {
+  const double cm = qq > 0 ? (double)(q == qq - 1)
+                           : 3.0 * (q == qq) - 3.0 * (q == qq + 1) + (double)(q == qq + 2);
+  const double cp = qq + 1 < n ? (double)(q == qq + 1)
+                               : 3.0 * (q == qq) - 3.0 * (q == qq - 1) + (double)(q == qq - 2);
+  return cm - cp;
 }
 
 // Transpose of the projection: from (Fb, vb) at the projected level to the
 // momentum cotangent Mb, the density cotangent rhob and the pressure
-// cotangent Pb (= -delta_1^T Fb + delta_2 (vb/rho)).
+// cotangent Pb (= -delta_1^T Fb + delta_2^T (vb/rho)). Wall faces carry a
+// constant flux (no cotangent); near a wall delta_2 reads the extrapolated
+// ghost of P.
 template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_adj_proj(AdjProjArgs a) {
   CellPos p;
@@ -453,12 +552,26 @@ __global__ void __launch_bounds__(kBlock) k_adj_proj(AdjProjArgs a) {
   double rb = 0.0, pb = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
+    const double ih = 1.0 / a.P.h[d];
     const double w = a.vb[d][c] / r;
     rb -= a.vb[d][c] * a.v[d][c] / r;
-    a.Mb[d][c] = 0.5 * (a.Fb[d][c] + a.Fb[d][cm]) + w;
-    const double wp = a.vb[d][cp] / a.rho[cp], wm = a.vb[d][cm] / a.rho[cm];
-    pb += (a.Fb[d][c] - a.Fb[d][cm]) / a.P.h[d] + (wp - wm) / (2.0 * a.P.h[d]);
+    if (a.B.periodic[d]) {
+      const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
+      a.Mb[d][c] = 0.5 * (a.Fb[d][c] + a.Fb[d][cm]) + w;
+      const double wp = a.vb[d][cp] / a.rho[cp], wm = a.vb[d][cm] / a.rho[cm];
+      pb += (a.Fb[d][c] - a.Fb[d][cm]) / a.P.h[d] + (wp - wm) / (2.0 * a.P.h[d]);
+    } else {
+      const int n = a.L.n[d], q = coord(p, d);
+      const long sdd = a.L.s[d];
+      const double fh = q + 1 < n ? a.Fb[d][c] : 0.0, fl = q > 0 ? a.Fb[d][c - sdd] : 0.0;
+      a.Mb[d][c] = 0.5 * (fh + fl) + w;
+      double s2 = 0.0;
+      for (int qq = max(q - 2, 0); qq <= min(q + 2, n - 1); ++qq) {
+        const long cq = c + (long)(qq - q) * sdd;
+        s2 += a.vb[d][cq] / a.rho[cq] * xcoef(qq, q, n);
+      }
+      pb += (fh - fl) * ih + s2 * (0.5 * ih);
+    }
   }
   a.rhob[c] = rb;
   a.Pb[c] = pb;
@@ -499,8 +612,19 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
   double Mb[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
-    Mb[d] = a.Mb[d][c] - (a.bb[cp] - a.bb[cm]) / (2.0 * a.P.h[d]);
+    if (a.B.periodic[d]) {
+      const long cm = pw(a.L, off(x, d, -1)), cp = pw(a.L, off(x, d, 1));
+      Mb[d] = a.Mb[d][c] - (a.bb[cp] - a.bb[cm]) / (2.0 * a.P.h[d]);
+    } else {
+      // a wall face carries no momentum: b's face averages exist on interior
+      // faces only, so d b_c/d M_c = (hi - lo)/(2h) with hi, lo = 1 for an
+      // interior face
+      const int n = a.L.n[d], q = coord(p, d);
+      const long sdd = a.L.s[d];
+      const double hi = q + 1 < n ? 1.0 : 0.0, lo = q > 0 ? 1.0 : 0.0;
+      const double bp = q + 1 < n ? a.bb[c + sdd] : 0.0, bm = q > 0 ? a.bb[c - sdd] : 0.0;
+      Mb[d] = a.Mb[d][c] - (bp - bm) / (2.0 * a.P.h[d]) + bb * (hi - lo) / (2.0 * a.P.h[d]);
+    }
   }
   const EosD e = eos_d(a.P, a.rho_new[c], a.H_new[c], R ? a.Z_new[c] : 0.0);
   const double rhob_new = a.rhob_new[c] + c1 * bb;
@@ -617,7 +741,8 @@ hipError_t launch_adj_seed_ke(hipStream_t st, const AdjCellArgs &a) {
 }
 
 // Adjoint of the initial state built from (T0, Z0, v0): H0 = T0/qs - F~(Z0)
-// (T0/qs + 1 without reaction), rho0 = p0/T0, F0 = avg(rho0 v0). Outputs
+// (T0/qs + 1 without reaction), rho0 = p0/T0, F0 = avg(rho0 v0) on interior
+// faces (wall faces carry the constant wall flux). Outputs
 // Tb (cotangent of T0), Zb0 (of Z0, reacting flow) and adds
 // rho0 avg^T(Fb) to vb. rho0 depends on T0 alone, so the density cotangent
 // from F0 enters T0 only; the state cotangents of H and Z map through the
@@ -632,7 +757,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_init(AdjCellArgs a) {
   double rhob = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const double mb = 0.5 * (a.Fb[d][c] + a.Fb[d][pw(a.L, off(x, d, -1))]);
+    const int q = coord(p, d);
+    const bool per = a.B.periodic[d];
+    const double fh = (per || q + 1 < a.L.n[d]) ? a.Fb[d][c] : 0.0;  // wall faces: constant flux
+    const double fl = (per || q > 0) ? a.Fb[d][pw(a.L, off(x, d, -1))] : 0.0;
+    const double mb = 0.5 * (fh + fl);
     rhob += mb * a.v[d][c];
     a.vb[d][c] += r * mb;
   }

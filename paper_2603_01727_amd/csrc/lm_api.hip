@@ -1162,7 +1162,17 @@ int state_arrays(lm_ctx *c, double **out) {
   return k;
 }
 
-bool adjoint_ok(lm_ctx *c) { return c->prm.with_adjoint && c->bnd.all_periodic; }
+// The adjoint covers periodic and slip / no-slip wall sides on uniform
+// spacing (inflow and outflow sides are not transposed).
+bool adjoint_ok(lm_ctx *c) {
+  if (!c->prm.with_adjoint || c->stretched) return false;
+  for (int d = 0; d < c->grid.ndim; ++d)
+    for (int s = 0; s < 2; ++s) {
+      const int k = c->grid.bc[d][s];
+      if (k != LM_SIDE_PERIODIC && k != LM_SIDE_SLIP && k != LM_SIDE_NOSLIP) return false;
+    }
+  return true;
+}
 
 // The arrays of an adjoint state with the face direction of each (-1 for
 // cell arrays), in the order H, Z, v, F, rho_prev, R_H, R_Z, R_v (Z and R_Z
@@ -1293,7 +1303,7 @@ extern "C" lm_status lm_kinetic_energy(lm_ctx *c, double *ke) {
   return LM_OK;
 }
 
-static const char *kAdjUnsupported = "adjoint needs with_adjoint and a periodic grid";
+static const char *kAdjUnsupported = "adjoint needs with_adjoint and periodic or wall sides";
 
 extern "C" lm_status lm_adjoint_seed_ke(lm_ctx *c) {
   if (!c) return LM_EINVAL;
@@ -1423,6 +1433,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
     AdjProjArgs a{};
     a.L = L;
     a.P = P;
+    a.B = c->bnd;
     for (int d = 0; d < nd; ++d) {
       a.Fb[d] = Fb[d];
       a.vb[d] = vb[d];
@@ -1440,6 +1451,8 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
     AdjResidArgs a{};
     a.L = L;
     a.P = P;
+    a.B = c->bnd;
+    a.sd = c->sides;
     a.H = lv.H;
     a.Z = lv.Z;
     a.RbH = RbH;
@@ -1467,6 +1480,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   AdjTailArgs t{};
   t.L = L;
   t.P = P;
+  t.B = c->bnd;
   t.first = first;
   t.corrector = 1;
   t.bb = w.bb;
@@ -1540,6 +1554,7 @@ extern "C" lm_status lm_adjoint_initial(lm_ctx *c, double *T0_bar, double *v0_ba
   AdjCellArgs g{};
   g.L = c->lay;
   g.P = adj_phys(c);
+  g.B = c->bnd;
   g.H = N.H;
   g.Z = N.Z;
   g.rho = N.rho;

@@ -192,7 +192,7 @@ hipError_t launch_scale_copy(hipStream_t st, long n, double a, const double *x, 
 hipError_t launch_pc_err(hipStream_t st, const Lay &L, int reacting, const Level &star, const Level &nw,
                          double *partials, double *out);
 
-// ---- adjoint (lm_adjoint.hip): periodic 2D/3D ------------------------------
+// ---- adjoint (lm_adjoint.hip): 2D/3D, periodic or wall sides ----------------
 struct AdjPhys {
   double h[3];
   double Pe, Pr, sigma, inv_Fr2, p0, qs, dt;
@@ -206,6 +206,8 @@ struct AdjPhys {
 struct AdjResidArgs {
   Lay L;
   AdjPhys P;
+  Bnd B;                                // periodic or slip / no-slip wall sides
+  Sides sd;                             // wall values (H of isothermal walls, v)
   const double *H, *Z, *v[3], *F[3];    // level at which the residuals are taken
   const double *RbH, *RbZ, *Rbv[3];     // residual cotangents
   double *Hb, *Zb, *vb[3], *Fb[3];      // accumulated adjoints
@@ -215,6 +217,7 @@ struct AdjResidArgs {
 struct AdjProjArgs {
   Lay L;
   AdjPhys P;
+  Bnd B;
   const double *Fb[3], *vb[3], *v[3], *rho;
   double *Mb[3], *rhob, *Pb;
 };
@@ -223,6 +226,7 @@ struct AdjProjArgs {
 struct AdjCellArgs {
   Lay L;
   AdjPhys P;
+  Bnd B;
   double dV;
   const double *H, *Z, *rho, *v[3], *Fb[3], *Hb_in, *Zb_in, *rhob, *Tb;
   double *Hb, *Zb, *vb[3], *Zb0, *part;
@@ -231,6 +235,7 @@ struct AdjCellArgs {
 struct AdjTailArgs {
   Lay L;
   AdjPhys P;
+  Bnd B;
   int first, corrector;
   const double *bb;
   double *Mb[3];

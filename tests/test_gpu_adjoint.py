@@ -100,12 +100,30 @@ def _dot(a, b):
     return out
 
 
+def _clear_fixed_faces(g, case, F, direction=False):
+    """Face arrays restricted to their free entries. Face 0 of a periodic
+    direction duplicates face n: a cotangent carries nothing there (the
+    library holds the pair's cotangent at face n), and a direction of the
+    state (``direction``) moves both alike, as every state the step makes
+    has them equal. Wall faces carry a constant flux: zero in both."""
+    for d in range(case.ndim):
+        lo = [slice(None)] * case.ndim
+        hi = [slice(None)] * case.ndim
+        lo[g.axis(d)] = 0
+        hi[g.axis(d)] = -1
+        if case.bc[d][0] == "periodic":
+            F[d][tuple(lo)] = F[d][tuple(hi)] if direction else 0.0
+        else:
+            F[d][tuple(lo)] = 0.0
+            F[d][tuple(hi)] = 0.0
+
+
 def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     """One step back on the GPU against the complex-step tangent of the same
     step in the oracle, per input component."""
     nd = case.ndim
     dt = 0.5 * _dt(case)
-    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc)
+    g = Grid(case.n[:nd], case.L[:nd], bc=case.bc, bnd=case.bnd)
     p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, sutherland_C=suth, inv_Fr2=inv_Fr2,
                Da_ib=case.params.get("Da_ib", 1.0), **_flame(case))
     react = p.reacting
@@ -114,12 +132,14 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     nhist = 1 if history else 0
     st = tg.with_eos(o, o.run(st, nhist))
     s = _solver(case, dt, sutherland_C=suth, inv_Fr2=inv_Fr2)
+    for (d, side), data in (case.bnd or {}).items():
+        s.set_side(d, side, v=data.get("v"), H=data.get("H"))
     s.set(T=case.T, v=case.v, Z=case.Z, ib=case.ib)
     if nhist:
         s.step(nhist)
     rng = np.random.default_rng(seed)
     # cotangents of the step's outputs (face 0 of a periodic face array is a
-    # duplicate of face n and carries none)
+    # duplicate of face n and carries none; wall faces carry a constant flux)
     ybar = {"H": rng.normal(size=g.shape), "v": [rng.normal(size=g.shape) for _ in range(nd)],
             "rho_prev": rng.normal(size=g.shape), "R_H": rng.normal(size=g.shape),
             "R_v": [rng.normal(size=g.shape) for _ in range(nd)]}
@@ -127,10 +147,7 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     if react:
         ybar["Z"] = rng.normal(size=g.shape)
         ybar["R_Z"] = rng.normal(size=g.shape)
-    for d in range(nd):
-        idx = [slice(None)] * nd
-        idx[g.axis(d)] = 0
-        ybar["F"][d][tuple(idx)] = 0.0
+    _clear_fixed_faces(g, case, ybar["F"])
     s.adjoint_set(**ybar)
     t0 = time.time()
     s.step_adjoint()
@@ -142,6 +159,7 @@ def _dot_product_check(case, history, suth=0.0, inv_Fr2=0.0, seed=100):
     for k in comps:
         if k == "F":
             dx = {k: [_faces(rng.normal(size=g.shape), g.axis(d)) for d in range(nd)]}
+            _clear_fixed_faces(g, case, dx[k], direction=True)
         elif k in ("v", "R_v"):
             dx = {k: [rng.normal(size=g.shape) for _ in range(nd)]}
         elif k == "Z":
@@ -316,6 +334,84 @@ def test_ke_gradient_reacting_against_oracle_complex_step():
             cs = tg.ke_directional(g, p, case.T, case.v, zero, nsteps, Z0=case.Z, dZ=d)
             ad = float(np.sum(Zb * d))
         print("T0" if q % 2 == 0 else "Z0", cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
+
+
+def _walls_case(kind, seed=21):
+    """Boxes with wall sides (section 3.6, Eq 3.43), random T in [1, 3] and
+    velocity rms 0.1 (the fields need not meet the wall conditions: the
+    step's ghosts and wall fluxes impose them):
+    'channel'  2D 64 x 48, periodic in x, slip walls in y;
+    'cavity'   2D 48 x 40 unit box, no-slip walls, the x walls isothermal
+               (T = 1.4 and 0.6: H = T + 1), adiabatic y walls;
+    'duct3d'   3D 16 x 14 x 12, periodic in x, slip walls in y, no-slip in z;
+    'box3d'    3D 12 x 10 x 8, no-slip walls on every side."""
+    from workloads.ics import Case, fourier_temperature, solenoidal_velocity
+    shapes = {"channel": ((64, 48), (2 * math.pi, 1.5 * math.pi), ("periodic", "slip")),
+              "cavity": ((48, 40), (1.0, 1.0), ("noslip", "noslip")),
+              "duct3d": ((16, 14, 12), (2 * math.pi,) * 3, ("periodic", "slip", "noslip")),
+              "box3d": ((12, 10, 8), (2 * math.pi,) * 3, ("noslip", "noslip", "noslip"))}
+    n, L, kinds = shapes[kind]
+    rng = np.random.default_rng(seed)
+    T = fourier_temperature(n, L, rng, 3, 2.0, m=24)
+    v = solenoidal_velocity(n, L, rng, 3, 0.1, m=24)
+    bc = tuple((k, k) for k in kinds)
+    bnd = None
+    if kind == "cavity":
+        bnd = {(0, 0): dict(H=np.full(n[1], 2.4)), (0, 1): dict(H=np.full(n[1], 1.6))}
+    return Case(f"walls_{kind}", len(n), tuple(n) + (1,) * (3 - len(n)), L + (1.0,) * (3 - len(n)), bc,
+                dict(Re=200.0, Pr=0.7, cfl=0.3), T, v, bnd=bnd, nsteps=1)
+
+
+@pytest.mark.parametrize("kind,history,fr,react", [("channel", False, 0.0, False), ("channel", True, 0.5, False),
+                                                   ("cavity", True, 0.5, False), ("channel", True, 0.0, True),
+                                                   ("duct3d", True, 0.5, False), ("box3d", True, 0.0, True)],
+                         ids=["channel", "channel-hist-buoyancy", "cavity-hist-buoyancy", "channel-hist-reacting",
+                              "duct3d-hist-buoyancy", "box3d-hist-reacting"])
+def test_adjoint_step_dot_product_walls(kind, history, fr, react):
+    """Slip and no-slip walls, isothermal or adiabatic: the residual gather
+    reads ghosts by the forward's rules (mirrors of interior cells, the
+    wall conductivity 2 kappa(T_w) - kappa(T) at isothermal walls), wall
+    faces carry a constant flux, the projection transpose takes the
+    extrapolated pressure ghost and the right-hand side the one-sided face
+    sums at walls."""
+    case = _walls_case(kind)
+    if react:
+        from workloads.ics import reacting_periodic_case
+        r = reacting_periodic_case(case.n[:case.ndim], seed=22)
+        case.Z = r.Z
+        case.params = dict(r.params, Re=case.params["Re"], cfl=case.params["cfl"])
+    print("adjoint dot walls", kind, history, fr, react, flush=True)
+    _dot_product_check(case, history, inv_Fr2=fr, seed=500 + len(kind))
+
+
+def test_ke_gradient_cavity_against_oracle_complex_step():
+    """The isothermal cavity (48 x 40, no-slip walls, buoyancy 1/Fr^2 = 0.5),
+    6 steps with checkpoints every 2: J and its T0-gradient along 3 seeded
+    directions against the oracle's complex step."""
+    import torch
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    nsteps, k = 6, 2
+    case = _walls_case("cavity", seed=23)
+    dt = _dt(case)
+    print("ke gradient cavity", nsteps, flush=True)
+    s = _solver(case, dt, inv_Fr2=0.5)
+    for (d, side), data in case.bnd.items():
+        s.set_side(d, side, H=data.get("H"))
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in case.v]
+    J = final_kinetic_energy(s, T0, v0, nsteps, k)
+    J.backward()
+    grad = T0.grad.cpu().numpy()
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc, bnd=case.bnd)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt, inv_Fr2=0.5)
+    Jo = tg.final_kinetic_energy(g, p, case.T, case.v, nsteps)
+    print("J", J.item(), Jo, flush=True)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    for d in fd_directions(case.T.shape, k=3):
+        cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps)
+        ad = float(np.sum(grad * d))
+        print(cs, ad, abs(ad - cs) / abs(cs), flush=True)
         assert abs(ad - cs) <= 1e-9 * abs(cs)
 
 
