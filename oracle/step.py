@@ -502,7 +502,7 @@ class Oracle:
                      if not g.periodic(d) and g.bc[d][s] == "outflow"]
         if out_sides:
             div = sum((g.plus(G[d], d) - g.minus(G[d], d)) / g.along(d, g.wid[d][1:-1]) for d in range(g.ndim))
-            total = float(g.integral(div + src))
+            total = g.integral(div + src)  # (complex under a complex-step tangent)
             area = 0.0
             for d, s in out_sides:
                 area += g.volume / g.L[d]

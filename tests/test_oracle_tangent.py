@@ -161,3 +161,42 @@ def test_reacting_step_tangent_matches_central_differences(with_history):
     fd = (flat(real_step(1.0)) - flat(real_step(-1.0))) / (2 * h)
     cs = flat(t)
     assert np.linalg.norm(fd - cs) <= 1e-7 * np.linalg.norm(cs)
+
+
+def test_open_channel_step_tangent_matches_central_differences():
+    """Inflow / outflow channel (section 3.6; the outflow closure of section
+    3.3 sums the right-hand side over the domain): the complex-step tangent
+    of one step along H, v and F against central differences of the real
+    step, so the closure keeps the imaginary part of that sum."""
+    from workloads.ics import fourier_temperature, solenoidal_velocity
+    n, L = (24, 32), (2 * math.pi, 2.5 * math.pi)
+    rng = np.random.default_rng(17)
+    T = fourier_temperature(n, L, rng, 3, 2.0, m=16)
+    v = solenoidal_velocity(n, L, rng, 3, 0.1, m=16)
+    v[1] = v[1] + 0.5
+    bnd = {(1, 0): dict(v=[np.zeros(n[0]), np.full(n[0], 0.5)], H=np.full(n[0], 2.5),
+                        F=np.full(n[0], 0.5 / 1.5))}
+    g = Grid(n, L, bc=(("periodic", "periodic"), ("inflow", "outflow")), bnd=bnd)
+    o = Oracle(g, Params(Re=200.0, Pr=0.7, dt=0.02))
+    st = tg.with_eos(o, o.step(o.initial_state(T, v)))
+    dx = _direction(g, np.random.default_rng(18), True)
+    t = tg.step_tangent(o, st, dx)
+    h = 1e-6
+
+    def real_step(sign):
+        s = st.copy()
+        s.H = s.H + sign * h * dx["H"]
+        s.v = [a + sign * h * dx["v"][d] for d, a in enumerate(s.v)]
+        s.F = [a + sign * h * dx["F"][d] for d, a in enumerate(s.F)]
+        s.rho_prev = s.rho_prev + sign * h * dx["rho_prev"]
+        s.R_prev = dict(s.R_prev)
+        s.R_prev["H"] = s.R_prev["H"] + sign * h * dx["R_H"]
+        s.R_prev["v"] = [a + sign * h * dx["R_v"][d] for d, a in enumerate(s.R_prev["v"])]
+        tg.with_eos(o, s)
+        out = o.step(s)
+        return dict(H=out.H, v=out.v, F=out.F, rho_prev=out.rho_prev, R_H=out.R_prev["H"],
+                    R_v=out.R_prev["v"])
+
+    fd = (_flat(real_step(1.0)) - _flat(real_step(-1.0))) / (2 * h)
+    cs = _flat(t)
+    assert np.linalg.norm(fd - cs) <= 1e-7 * np.linalg.norm(cs)
