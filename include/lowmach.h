@@ -317,12 +317,14 @@ lm_status lm_load_state(lm_ctx *ctx, const void *dev_buf);
  * entries in each per-direction array (the rest are ignored), and in
  * reacting flow also Z and R_Z^{n-1}. Supported for 2D and 3D grids on
  * uniform spacing whose sides are periodic, slip or no-slip walls
- * (isothermal or adiabatic), in FP64, reacting or not, with or without an
- * immersed body (the body arrays and wall values are constants of the
- * step: they carry no cotangent) (params with_adjoint = 1; otherwise, and
- * for inflow / outflow sides, LM_EUNSUPPORTED). Face cotangents: a wall
- * face carries a constant flux and its cotangent is 0; face 0 of a
- * periodic direction duplicates face n, whose cotangent holds the pair's. */
+ * (isothermal or adiabatic) or inflow, with an outflow side on the high
+ * end of at most one direction, in FP64, reacting or not, with or without
+ * an immersed body (the body arrays, wall and inflow values are constants
+ * of the step: they carry no cotangent) (params with_adjoint = 1;
+ * otherwise LM_EUNSUPPORTED). Face cotangents: a wall or inflow face
+ * carries a constant flux and its cotangent is 0; an outflow face flux is
+ * a state variable; face 0 of a periodic direction duplicates face n,
+ * whose cotangent holds the pair's.                                        */
 typedef struct {
   double *H, *v[3], *F[3], *rho_prev, *R_H, *R_v[3];
   double *T;   /* lm_adjoint_set only: a cotangent of the temperature,

@@ -175,7 +175,10 @@ struct Loader {
   __device__ double hib(Ix x) const { return H_ib ? H_ib[L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ double zib(Ix x) const { return Z_ib ? Z_ib[L.at(x.i, x.j, x.k)] : 0.0; }
   __device__ double vib(int c, Ix x) const { return v_ib[c] ? v_ib[c][L.at(x.i, x.j, x.k)] : 0.0; }
-  // field a with rule set f (0..2 velocity components, 3 Z, 4 H)
+  // field a with rule set f (0..2 velocity components, 3 Z, 4 H). An
+  // outflow side's ghost is the quadratic extrapolation 3 u_0 - 3 u_1 + u_2
+  // of the three cells inside; with at most one outflow direction (checked
+  // at set-up) a ghost spans at most three cells.
   __device__ DD<DIM, R> load(const double *a, int f, Ix x, int seed) const {
     if (!W) {
       x = wrap(L, x);
@@ -183,25 +186,52 @@ struct Loader {
       if (x.i == m.i && x.j == m.j && x.k == m.k) r.d[seed] = 1.0;
       return r;
     }
-    int pos[3] = {x.i, x.j, x.k};
-    double w = 1.0, cst = 0.0;
+    int pos[3][3] = {{x.i, x.j, x.k}, {0, 0, 0}, {0, 0, 0}};
+    double w[3] = {1.0, 0.0, 0.0};
+    int nt = 1;
+    double cst = 0.0;
 #pragma unroll
     for (int d = DIM - 1; d >= 0; --d) {
-      const int n = L.n[d], q = pos[d];
-      if (q >= 0 && q < n) continue;
-      const int s = q < 0 ? 0 : 1;
-      if (B.periodic[d]) {
-        pos[d] = s == 0 ? n - 1 : 0;
-        continue;
+      const int n = L.n[d];
+      const int cur = nt;
+      for (int t = 0; t < cur; ++t) {
+        const int q = pos[t][d];
+        if (q >= 0 && q < n) continue;
+        const int s = q < 0 ? 0 : 1;
+        if (B.periodic[d]) {
+          pos[t][d] = s == 0 ? n - 1 : 0;
+          continue;
+        }
+        const int i1 = s == 0 ? 0 : n - 1, step = s == 0 ? 1 : -1;
+        const int rule = ghost_rule(B, sd, L, d, s, f, pos[t][0], pos[t][1], pos[t][2]);
+        if (rule == R_DIR) {
+          cst += 2.0 * w[t] * side_value(sd, L, d, s, f, pos[t][0], pos[t][1], pos[t][2]);
+          w[t] = -w[t];
+          pos[t][d] = i1;
+        } else if (rule == R_NEU || nt != 1) {
+          pos[t][d] = i1;
+        } else {  // extrapolated (outflow)
+          const double wt = w[t];
+          for (int e = 0; e < 3; ++e) {
+            pos[e][0] = pos[t][0];
+            pos[e][1] = pos[t][1];
+            pos[e][2] = pos[t][2];
+            pos[e][d] = i1 + e * step;
+          }
+          w[0] = 3.0 * wt;
+          w[1] = -3.0 * wt;
+          w[2] = wt;
+          nt = 3;
+        }
       }
-      if (ghost_rule(B, sd, L, d, s, f, pos[0], pos[1], pos[2]) == R_DIR) {
-        cst += 2.0 * w * side_value(sd, L, d, s, f, pos[0], pos[1], pos[2]);
-        w = -w;
-      }
-      pos[d] = s == 0 ? 0 : n - 1;
     }
-    DD<DIM, R> r(cst + w * a[L.at(pos[0], pos[1], pos[2])]);
-    if (pos[0] == m.i && pos[1] == m.j && pos[2] == m.k) r.d[seed] = w;
+    double val = cst, der = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      val += w[t] * a[L.at(pos[t][0], pos[t][1], pos[t][2])];
+      if (pos[t][0] == m.i && pos[t][1] == m.j && pos[t][2] == m.k) der += w[t];
+    }
+    DD<DIM, R> r(val);
+    r.d[seed] = der;
     return r;
   }
   __device__ DD<DIM, R> hh(Ix x) const { return load(H, 4, x, 0); }
@@ -442,9 +472,11 @@ __device__ inline EosD eos_d(const AdjPhys &P, double rho, double H, double Z) {
   } while (0)
 
 // (Hb, Zb, vb, Fb) += (dR/d(H, Z, v, F))^T (RbH, RbZ, Rbv) by gather over
-// the 3^DIM cells whose residual stencils reach the cell (with walls, the
-// interior ones: a ghost mirrors a cell within one cell of the reader).
-// The flux of a wall face is a constant of the step: its cotangent stays 0.
+// the 3^DIM cells whose residual stencils reach the cell (with wall or
+// inflow sides, the interior ones: a ghost mirrors a cell within one cell
+// of the reader; towards a high outflow side two cells further, as its
+// extrapolated ghost reads three cells in). The flux of a wall or inflow
+// face is a constant of the step: its cotangent stays 0.
 template <int DIM, int R, int W>
 __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   constexpr int N = 1 + R + 2 * DIM;
@@ -470,9 +502,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
 #pragma unroll
   for (int q = 0; q < N; ++q) acc[q] = 0.0;
   const int kr = DIM == 3 ? 1 : 0;
-  for (int dk = -kr; dk <= kr; ++dk)
-    for (int dj = -1; dj <= 1; ++dj)
-      for (int di = -1; di <= 1; ++di) {
+  // an outflow ghost reads the third cell inside: readers of cell m reach
+  // two cells towards a high outflow side
+  const int pm[3] = {p.i, p.j, p.k};
+  int hi[3] = {1, 1, kr};
+  if (W)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      if (a.B.kind[d][1] == LM_SIDE_OUTFLOW && pm[d] == a.L.n[d] - 3) hi[d] = 2;
+  for (int dk = -kr; dk <= hi[2]; ++dk)
+    for (int dj = -1; dj <= hi[1]; ++dj)
+      for (int di = -1; di <= hi[0]; ++di) {
         Ix x{p.i + di, p.j + dj, p.k + dk};
         if (W && !ld.inside(x)) {
           const int q[3] = {x.i, x.j, x.k};
@@ -501,11 +541,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   const long m = p.c;
   a.Hb[m] += acc[0];
   if (R) a.Zb[m] += acc[1];
-  const int pm[3] = {p.i, p.j, p.k};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     a.vb[d][m] += acc[1 + R + d];
-    if (!W || a.B.periodic[d] || pm[d] + 1 < a.L.n[d]) a.Fb[d][m] += acc[1 + R + DIM + d];
+    // the high face of the last cell: a state flux on an outflow side, a
+    // constant on a wall or inflow side
+    if (!W || a.B.periodic[d] || pm[d] + 1 < a.L.n[d] || a.B.kind[d][1] == LM_SIDE_OUTFLOW)
+      a.Fb[d][m] += acc[1 + R + DIM + d];
   }
 }
 
@@ -537,6 +579,18 @@ __device__ inline double xcoef(int qq, int q, int n) {
   return cm - cp;
 }
 
+// Outflow face flux on the high side of direction d: the quadratic
+// extrapolation (15 M_{n-1} - 10 M_{n-2} + 3 M_{n-3})/8 of the cell
+// momentum (less the uniform closure shift); the cotangent it passes to
+// the momentum of cell q (zero away from the side) from the face
+// cotangent Fb of its column.
+__constant__ double kOutW[3] = {15.0 / 8.0, -10.0 / 8.0, 3.0 / 8.0};
+__device__ inline double outflow_face_mb(const Lay &L, const Bnd &B, const double *Fb, long c, int d, int q) {
+  const int n = L.n[d], j = n - 1 - q;
+  if (B.kind[d][1] != LM_SIDE_OUTFLOW || j > 2) return 0.0;
+  return kOutW[j] * Fb[c + (long)j * L.s[d]];
+}
+
 // Transpose of the projection: from (Fb, vb) at the projected level to the
 // momentum cotangent Mb, the density cotangent rhob and the pressure
 // cotangent Pb (= -delta_1^T Fb + delta_2^T (vb/rho)). Wall faces carry a
@@ -564,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_proj(AdjProjArgs a) {
       const int n = a.L.n[d], q = coord(p, d);
       const long sdd = a.L.s[d];
       const double fh = q + 1 < n ? a.Fb[d][c] : 0.0, fl = q > 0 ? a.Fb[d][c - sdd] : 0.0;
-      a.Mb[d][c] = 0.5 * (fh + fl) + w;
+      a.Mb[d][c] = 0.5 * (fh + fl) + w + outflow_face_mb(a.L, a.B, a.Fb[d], c, d, q);
       double s2 = 0.0;
       for (int qq = max(q - 2, 0); qq <= min(q + 2, n - 1); ++qq) {
         const long cq = c + (long)(qq - q) * sdd;
@@ -624,6 +678,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_tail(AdjTailArgs a) {
       const double hi = q + 1 < n ? 1.0 : 0.0, lo = q > 0 ? 1.0 : 0.0;
       const double bp = q + 1 < n ? a.bb[c + sdd] : 0.0, bm = q > 0 ? a.bb[c - sdd] : 0.0;
       Mb[d] = a.Mb[d][c] - (bp - bm) / (2.0 * a.P.h[d]) + bb * (hi - lo) / (2.0 * a.P.h[d]);
+      // the last cell's high face on an outflow side is the extrapolated
+      // momentum (unshifted in b)
+      Mb[d] += outflow_face_mb(a.L, a.B, a.bb, c, d, q) / a.P.h[d];
     }
   }
   const EosD e = eos_d(a.P, a.rho_new[c], a.H_new[c], R ? a.Z_new[c] : 0.0);
@@ -761,7 +818,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_init(AdjCellArgs a) {
     const bool per = a.B.periodic[d];
     const double fh = (per || q + 1 < a.L.n[d]) ? a.Fb[d][c] : 0.0;  // wall faces: constant flux
     const double fl = (per || q > 0) ? a.Fb[d][pw(a.L, off(x, d, -1))] : 0.0;
-    const double mb = 0.5 * (fh + fl);
+    const double mb = 0.5 * (fh + fl) + (per ? 0.0 : outflow_face_mb(a.L, a.B, a.Fb[d], c, d, q));
     rhob += mb * a.v[d][c];
     a.vb[d][c] += r * mb;
   }
@@ -772,6 +829,49 @@ __global__ void __launch_bounds__(kBlock) k_adj_init(AdjCellArgs a) {
 
 hipError_t launch_adj_init(hipStream_t st, const AdjCellArgs &a) {
   LM_ADJ_LAUNCH(k_adj_init, a.L, a.P.reacting, a);
+  return hipGetLastError();
+}
+
+// Outflow closure (one high outflow side, direction d): the forward shifts
+// the Poisson right-hand side of the cells next to the side by oc/h and the
+// outflow face fluxes by -oc, oc = sum(b) dV / area. Given the adjoint
+// solve's output y (the cotangent of the shifted right-hand side) and the
+// outflow face cotangents Fb, one block forms
+//   s = (-sum_side y/h - sum_side Fb) dV / area
+// and the second kernel adds it to every cell: b_bar = y + s.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_adj_outflow_sum(Lay L, AdjPhys P, int d, const double *y,
+                                                            const double *Fb, double *out) {
+  __shared__ double sh[kBlock / 64];
+  const int n = L.n[d];
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;  // the two other directions
+  const long m0 = L.n[a0], m1 = DIM == 3 ? L.n[a1] : 1;
+  double acc = 0.0;
+  for (long t = threadIdx.x; t < m0 * m1; t += blockDim.x) {
+    int q[3] = {0, 0, 0};
+    q[d] = n - 1;
+    q[a0] = (int)(t % m0);
+    if (DIM == 3) q[a1] = (int)(t / m0);
+    const long c = L.at(q[0], q[1], q[2]);
+    acc += y[c] / P.h[d] + Fb[c];
+  }
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = -tot * P.h[d] / (double)(m0 * m1);  // dV/area = h_d / (faces on the side)
+}
+
+__global__ void __launch_bounds__(kBlock) k_adj_add_scalar(Lay L, double *y, const double *s) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  y[p.c] += *s;
+}
+
+hipError_t launch_adj_outflow(hipStream_t st, const Lay &L, const AdjPhys &P, int d, double *y, const double *Fb,
+                              double *scratch) {
+  if (L.ndim == 3)
+    hipLaunchKernelGGL(k_adj_outflow_sum<3>, dim3(1), dim3(kBlock), 0, st, L, P, d, (const double *)y, Fb, scratch);
+  else
+    hipLaunchKernelGGL(k_adj_outflow_sum<2>, dim3(1), dim3(kBlock), 0, st, L, P, d, (const double *)y, Fb, scratch);
+  hipLaunchKernelGGL(k_adj_add_scalar, grid_for(L), dim3(kBX, kBY), 0, st, L, y, (const double *)scratch);
   return hipGetLastError();
 }
 

@@ -1162,16 +1162,27 @@ int state_arrays(lm_ctx *c, double **out) {
   return k;
 }
 
-// The adjoint covers periodic and slip / no-slip wall sides on uniform
-// spacing (inflow and outflow sides are not transposed).
+// Direction of the outflow side (-1: none).
+int outflow_dir(const lm_ctx *c) {
+  for (int d = 0; d < c->grid.ndim; ++d)
+    for (int s = 0; s < 2; ++s)
+      if (c->grid.bc[d][s] == LM_SIDE_OUTFLOW) return d;
+  return -1;
+}
+
+// The adjoint covers periodic, slip / no-slip wall and inflow sides, and an
+// outflow side on the high end of at most one direction (at least 3 cells
+// long), on uniform spacing.
 bool adjoint_ok(lm_ctx *c) {
   if (!c->prm.with_adjoint || c->stretched) return false;
+  int nout = 0;
   for (int d = 0; d < c->grid.ndim; ++d)
-    for (int s = 0; s < 2; ++s) {
-      const int k = c->grid.bc[d][s];
-      if (k != LM_SIDE_PERIODIC && k != LM_SIDE_SLIP && k != LM_SIDE_NOSLIP) return false;
-    }
-  return true;
+    for (int s = 0; s < 2; ++s)
+      if (c->grid.bc[d][s] == LM_SIDE_OUTFLOW) {
+        if (s == 0 || c->grid.n[d] < 3) return false;
+        ++nout;
+      }
+  return nout <= 1;
 }
 
 // The arrays of an adjoint state with the face direction of each (-1 for
@@ -1303,7 +1314,8 @@ extern "C" lm_status lm_kinetic_energy(lm_ctx *c, double *ke) {
   return LM_OK;
 }
 
-static const char *kAdjUnsupported = "adjoint needs with_adjoint and periodic or wall sides";
+static const char *kAdjUnsupported =
+    "adjoint needs with_adjoint, uniform spacing and at most one outflow side, on a high end";
 
 extern "C" lm_status lm_adjoint_seed_ke(lm_ctx *c) {
   if (!c) return LM_EINVAL;
@@ -1474,9 +1486,18 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
     }
     return launch_adj_resid(c->st, a);
   };
+  // outflow closure: the cotangent of the stage's right-hand side b from
+  // that of the shifted one (y, the adjoint solve's output) and of the
+  // outflow face fluxes
+  const int dout = outflow_dir(c);
+  auto closure = [&](double *const Fb[3]) -> hipError_t {
+    if (dout < 0) return hipSuccess;
+    return launch_adj_outflow(c->st, L, P, dout, w.bb, Fb[dout], c->dscalar + 1);
+  };
   // corrector: projection, Poisson, right-hand side, EOS and AM2 transposes
   HIPCHK(c, proj(ain.F, ain.v, X));
   if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
+  HIPCHK(c, closure(ain.F));
   AdjTailArgs t{};
   t.L = L;
   t.P = P;
@@ -1521,6 +1542,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   // predictor: projection, Poisson, right-hand side, EOS and AB2 transposes
   HIPCHK(c, proj(w.Fb_star, w.vb_star, S));
   if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
+  HIPCHK(c, closure(w.Fb_star));
   t.corrector = 0;
   t.H_new = S.H;
   t.Z_new = S.Z;

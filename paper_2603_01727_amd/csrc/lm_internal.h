@@ -262,6 +262,10 @@ hipError_t launch_adj_seed_ke(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_adj_init(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[3], double dV, double *part,
                      double *out);
+// Transpose of the outflow closure of a high outflow side in direction d:
+// y += (-sum_side y/h - sum_side Fb) dV/area (scratch: one double).
+hipError_t launch_adj_outflow(hipStream_t st, const Lay &L, const AdjPhys &P, int d, double *y, const double *Fb,
+                              double *scratch);
 hipError_t launch_shift(hipStream_t st, const Lay &L, const double *x, const SolverScalars *sc, double *out);
 
 // ---- Poisson (lm_solver.hip) -----------------------------------------------
