@@ -439,6 +439,37 @@ def test_adjoint_step_dot_product_open(kind, history):
     _dot_product_check(case, history, seed=600 + len(kind))
 
 
+def test_ke_gradient_open_channel_against_oracle_complex_step():
+    """The open channel (inflow / outflow), 6 steps with checkpoints every 2:
+    J and its T0-gradient along 3 seeded directions against the oracle's
+    complex step (the initial-state transpose takes the extrapolated
+    outflow face flux; the closure enters every step)."""
+    import torch
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    nsteps, k = 6, 2
+    case = _open_case("channel", seed=42)
+    dt = _dt(case)
+    print("ke gradient open channel", nsteps, flush=True)
+    s = _solver(case, dt)
+    for (d, side), data in case.bnd.items():
+        s.set_side(d, side, v=data.get("v"), H=data.get("H"), F=data.get("F"))
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in case.v]
+    J = final_kinetic_energy(s, T0, v0, nsteps, k)
+    J.backward()
+    grad = T0.grad.cpu().numpy()
+    g = Grid(case.n[:2], case.L[:2], bc=case.bc, bnd=case.bnd)
+    p = Params(Re=case.params["Re"], Pr=case.params["Pr"], dt=dt)
+    Jo = tg.final_kinetic_energy(g, p, case.T, case.v, nsteps)
+    print("J", J.item(), Jo, flush=True)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    for d in fd_directions(case.T.shape, k=3):
+        cs = tg.ke_directional(g, p, case.T, case.v, d, nsteps)
+        ad = float(np.sum(grad * d))
+        print(cs, ad, abs(ad - cs) / abs(cs), flush=True)
+        assert abs(ad - cs) <= 1e-9 * abs(cs)
+
+
 def test_ke_gradient_cavity_against_oracle_complex_step():
     """The isothermal cavity (48 x 40, no-slip walls, buoyancy 1/Fr^2 = 0.5),
     6 steps with checkpoints every 2: J and its T0-gradient along 3 seeded
