@@ -71,8 +71,9 @@ def parse():
     ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^2, slot-flame and 512^2 workloads")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 512^2 200-step gradient")
-    ap.add_argument("--small", choices=("c1", "c2"), help="only the 64^2 (c1) or 1024^2 (c2) FP64 steps "
-                    "(for kernel traces of the small-grid paths)")
+    ap.add_argument("--small", choices=("c1", "c2", "adjoint"),
+                    help="only the 64^2 (c1) or 1024^2 (c2) FP64 steps, or only the 512^2 200-step gradient "
+                    "(adjoint), for kernel traces of those paths")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for HBM counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB", help="summarise a rocprofv3 kernel-trace database")
@@ -520,6 +521,9 @@ def main():
         return
     if a.summarize_pmc:
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.traffic_out)
+        return
+    if a.small == "adjoint":
+        print(json.dumps({"adjoint_c5": adjoint_block()}))
         return
     if a.small:
         from workloads import c1_case, c2_case

@@ -23,6 +23,10 @@ struct AdjWork {
   double *Hb_star, *Zb_star, *vb_star[3], *Fb_star[3];
   double *RbH_star, *RbZ_star, *Rbv_star[3], *RbH_n, *RbZ_n, *Rbv_n[3], *rhob_n;
   double *Tb_set, *Tb_init, *Zb_init;
+  // the last adjoint Poisson solution of each stage (0 corrector, 1
+  // predictor): the initial guess of the same stage's solve one step back
+  double *xa[2];
+  int xa_valid[2], xa_iters[2];
 };
 
 struct lm_ctx {
@@ -420,6 +424,10 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
                        &w.Tb_init})
       *q = take(true);
     for (double **q : {&w.Zb_star, &w.RbZ_star, &w.RbZ_n, &w.Zb_init}) *q = take(c->prm.reacting);
+    for (int q = 0; q < 2; ++q) {
+      w.xa[q] = take(true);
+      w.xa_valid[q] = w.xa_iters[q] = 0;
+    }
     for (int d = 0; d < 3; ++d)
       for (double **q : {&w.Mb[d], &w.vb_star[d], &w.Fb_star[d], &w.Rbv_star[d], &w.Rbv_n[d]}) *q = take(d < nd);
     c->ad_cur = 0;
@@ -1328,6 +1336,7 @@ extern "C" lm_status lm_adjoint_seed_ke(lm_ctx *c) {
   const int k = adj_arrays(a, nd, c->prm.reacting, arr, fd);
   const size_t ab = (size_t)c->lay.total * 8;
   for (int q = 0; q < k; ++q) HIPCHK(c, hipMemsetAsync(arr[q], 0, ab, c->st));
+  c->aw.xa_valid[0] = c->aw.xa_valid[1] = 0;  // a new reverse sweep: no warm start
   Level &lv = c->lev[c->icur];
   AdjCellArgs g{};
   g.L = c->lay;
@@ -1355,6 +1364,7 @@ extern "C" lm_status lm_adjoint_set(lm_ctx *c, const lm_adjoint *in, int mem) {
   const bool react = c->prm.reacting;
   if (!react && (in->Z || in->R_Z)) return fail(c, LM_EINVAL, "Z cotangents need reacting flow");
   AdjState &a = c->ad[c->ad_cur];
+  c->aw.xa_valid[0] = c->aw.xa_valid[1] = 0;  // a new reverse sweep: no warm start
   double *arr[14], *src[14];
   int fd[14], fd2[14];
   const int k = adj_arrays(a, nd, react, arr, fd);
@@ -1431,14 +1441,21 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   if (react) HIPCHK(c, hipMemsetAsync(w.Zb_star, 0, ab, c->st));
   for (int d = 0; d < nd; ++d)
     for (double *z : {w.vb_star[d], w.Fb_star[d], aout.F[d]}) HIPCHK(c, hipMemsetAsync(z, 0, ab, c->st));
-  auto adjoint_solve = [&](double *rhs, double *out) -> lm_status {
+  // the stage's adjoint solve starts from its solution one step later in
+  // time (the previous call's), which the pressure cotangents of
+  // consecutive steps leave close; the tolerance is the same
+  auto adjoint_solve = [&](double *rhs, double *out, int stage) -> lm_status {
     HIPCHK(c, launch_mean(c->st, L, rhs, c->pws.partials, c->pws.sc, c->phys.vol, c->phys.volume));
     int iters = 0, conv = 0;
     double relres = 0.0;
-    HIPCHK(c, poisson_solve(c->st, c->pws, rhs, nullptr, c->prm.poisson_rtol, c->prm.poisson_maxit, 0, &iters,
-                            &relres, &conv));
+    const double *x0 = w.xa_valid[stage] ? w.xa[stage] : nullptr;
+    HIPCHK(c, poisson_solve(c->st, c->pws, rhs, x0, c->prm.poisson_rtol, c->prm.poisson_maxit, w.xa_iters[stage],
+                            &iters, &relres, &conv));
     if (!conv) return fail(c, LM_ENOCONV, "adjoint Poisson solve did not converge");
     HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, out));
+    HIPCHK(c, hipMemcpyAsync(w.xa[stage], out, ab, hipMemcpyDeviceToDevice, c->st));
+    w.xa_valid[stage] = 1;
+    w.xa_iters[stage] = iters;
     return LM_OK;
   };
   auto proj = [&](double *const Fb[3], double *const vb[3], const Level &lv) -> hipError_t {
@@ -1496,7 +1513,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   };
   // corrector: projection, Poisson, right-hand side, EOS and AM2 transposes
   HIPCHK(c, proj(ain.F, ain.v, X));
-  if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
+  if ((s = adjoint_solve(w.Pb, w.bb, 0)) != LM_OK) return s;
   HIPCHK(c, closure(ain.F));
   AdjTailArgs t{};
   t.L = L;
@@ -1541,7 +1558,7 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   HIPCHK(c, resid(S, w.RbH_star, w.RbZ_star, w.Rbv_star, w.Hb_star, w.Zb_star, w.vb_star, w.Fb_star));
   // predictor: projection, Poisson, right-hand side, EOS and AB2 transposes
   HIPCHK(c, proj(w.Fb_star, w.vb_star, S));
-  if ((s = adjoint_solve(w.Pb, w.bb)) != LM_OK) return s;
+  if ((s = adjoint_solve(w.Pb, w.bb, 1)) != LM_OK) return s;
   HIPCHK(c, closure(w.Fb_star));
   t.corrector = 0;
   t.H_new = S.H;
