@@ -97,7 +97,8 @@ typedef struct {
  *  with_ib       1 = reserve immersed-boundary arrays (needed by lm_set_fields
  *                with a non-NULL lm_ib)
  *  with_adjoint  1 = reserve the adjoint arrays (lm_step_adjoint and its
- *                helpers; 2D periodic, non-reacting, no body, FP64 only)
+ *                helpers; FP64, constant p0, fixed dt; the grids and sides
+ *                listed at lm_adjoint)
  *  poisson_beta  LM_BETA_ONE (0): the step's operator only; LM_BETA_INV_RHO:
  *                also reserve the arrays of the variable-coefficient form
  *                beta = 1/rho_f for lm_project with a density (needs a grid
@@ -348,7 +349,10 @@ lm_status lm_adjoint_get(lm_ctx *ctx, lm_adjoint *a, int mem);
  * holding the cotangent of the state at n+1, replace it by the cotangent of
  * the state at n (the step is recomputed internally; the forward state is
  * left at n). Each stage needs one adjoint Poisson solve with the same
- * symmetric operator; errors as lm_step.                                    */
+ * symmetric operator, started from that stage's solution of the previous
+ * lm_step_adjoint call since the last lm_adjoint_set / lm_adjoint_seed_ke
+ * (a reverse sweep steps back in time; the tolerance is poisson_rtol as
+ * ever); errors as lm_step.                                                */
 lm_status lm_step_adjoint(lm_ctx *ctx);
 /* With the forward state freshly set from (T0, v0) (and Z0 in reacting
  * flow) by lm_set_fields and the adjoint state holding its cotangent:
