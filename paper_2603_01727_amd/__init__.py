@@ -260,7 +260,7 @@ class Solver:
         _check(self.lib, self.ctx, self.lib.lm_load_state(self.ctx, C.c_void_p(buf.data_ptr())))
 
     # ------------------------------------------------------------------
-    # adjoint (periodic 2D or 3D, FP64; needs with_adjoint=True)
+    # adjoint (2D or 3D; periodic, wall, inflow and high-side outflow sides; FP64; needs with_adjoint=True)
     def kinetic_energy(self) -> float:
         v = C.c_double()
         _check(self.lib, self.ctx, self.lib.lm_kinetic_energy(self.ctx, C.byref(v)))
