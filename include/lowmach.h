@@ -354,6 +354,18 @@ lm_status lm_adjoint_get(lm_ctx *ctx, lm_adjoint *a, int mem);
  * (a reverse sweep steps back in time; the tolerance is poisson_rtol as
  * ever); errors as lm_step.                                                */
 lm_status lm_step_adjoint(lm_ctx *ctx);
+/* The reverse step without the recompute, for callers that replay steps
+ * anyway (a checkpointed reverse sweep): right after lm_step took one step
+ * from a state, lm_save_step_levels copies that step's predicted level (rho,
+ * H, Z in reacting flow, v, F) and its new level (rho, H, Z, v) into a
+ * caller device buffer of lm_step_levels_size bytes (LM_ESTATE when no step
+ * was taken since the state was set or loaded); with the state restored to
+ * the one the step was taken from, lm_step_adjoint_levels does what
+ * lm_step_adjoint does, reading those levels instead of recomputing them
+ * (the same results bit for bit). The buffer is read, not kept.            */
+lm_status lm_step_levels_size(const lm_ctx *ctx, size_t *bytes);
+lm_status lm_save_step_levels(lm_ctx *ctx, void *dev_buf);
+lm_status lm_step_adjoint_levels(lm_ctx *ctx, const void *dev_buf);
 /* With the forward state freshly set from (T0, v0) (and Z0 in reacting
  * flow) by lm_set_fields and the adjoint state holding its cotangent:
  * cotangents of T0, v0 and Z0 (through H0 = T0/qs - F~(Z0), or T0/qs + 1

@@ -316,8 +316,26 @@ class Solver:
                                                            _L.LM_DEVICE if device else _L.LM_HOST))
         return out
 
-    def step_adjoint(self):
-        _check(self.lib, self.ctx, self.lib.lm_step_adjoint(self.ctx))
+    def step_adjoint(self, levels=None):
+        """One step back; ``levels``: the buffer ``save_step_levels`` filled
+        right after stepping from the current state (no recompute)."""
+        if levels is None:
+            _check(self.lib, self.ctx, self.lib.lm_step_adjoint(self.ctx))
+        else:
+            _check(self.lib, self.ctx, self.lib.lm_step_adjoint_levels(self.ctx, C.c_void_p(levels.data_ptr())))
+
+    def step_levels_size(self) -> int:
+        n = C.c_size_t()
+        _check(self.lib, self.ctx, self.lib.lm_step_levels_size(self.ctx, C.byref(n)))
+        return n.value
+
+    def save_step_levels(self, buf=None):
+        """The last step's predicted and new levels into a device uint8
+        tensor of ``step_levels_size()`` bytes (allocated when not given)."""
+        if buf is None:
+            buf = self.torch.empty(self.step_levels_size(), dtype=self.torch.uint8, device=self.device)
+        _check(self.lib, self.ctx, self.lib.lm_save_step_levels(self.ctx, C.c_void_p(buf.data_ptr())))
+        return buf
 
     def adjoint_initial(self, device: bool = True):
         """Cotangents (T0_bar, [v0_bar...]) of the initial fields given to

@@ -7,11 +7,13 @@ J(T0) = sum_cells 1/2 rho |v|^2 dV after ``nsteps`` predictor-corrector
 steps from (T0, v0) with a fixed time step. The forward pass stores a full
 state checkpoint every ``checkpoint_every`` steps. The backward pass walks
 the segments from last to first: it restores the segment's checkpoint,
-replays the segment forward while storing each step's state (the segment
-tape), then runs ``lm_step_adjoint`` from the last step of the segment back
-to its first. Peak storage is (nsteps / k + k) states. Every step of the
-forward and reverse sweeps runs in the HIP library; this module only
-sequences the calls.
+replays the segment forward while storing each step's state and the
+step's predicted and new levels (the segment tape), then steps back from
+the last step of the segment to its first with ``lm_step_adjoint_levels``,
+which reads the taped levels instead of recomputing the step (one forward
+step per step of the reverse sweep). Peak storage is (nsteps / k + k)
+states and k step levels. Every step of the forward and reverse sweeps
+runs in the HIP library; this module only sequences the calls.
 """
 from __future__ import annotations
 
@@ -36,7 +38,7 @@ class Trajectory:
     immersed-body arrays handed to ``Solver.set`` with the initial state
     (constants of the run)."""
 
-    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20, ib=None):
+    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20, ib=None, tape_levels: bool = True):
         if nsteps < 0 or checkpoint_every < 1:
             raise ValueError("nsteps >= 0 and checkpoint_every >= 1 required")
         if not solver.params.with_adjoint:
@@ -47,8 +49,10 @@ class Trajectory:
         self.nsteps = int(nsteps)
         self.k = int(checkpoint_every)
         self.ib = None if ib is None else {k: _on_device(x, solver.device, k == "chi") for k, x in ib.items()}
+        self.tape_levels = bool(tape_levels)   # False: lm_step_adjoint recomputes each step
         self.ckpt = {}
         self.tape = []
+        self.levels = []
         self.final = None
 
     def forward(self, T0, v0, Z0=None) -> float:
@@ -86,13 +90,24 @@ class Trajectory:
             while len(self.tape) < b - a:
                 self.tape.append(torch.empty(size, dtype=torch.uint8, device=s.device))
             s.load_state(self.ckpt[a])
-            s.save_state(self.tape[0])
-            for n in range(a + 1, b):
-                s.step(1)
-                s.save_state(self.tape[n - a])
-            for n in reversed(range(a, b)):
-                s.load_state(self.tape[n - a])
-                s.step_adjoint()
+            if self.tape_levels:
+                while len(self.levels) < b - a:
+                    self.levels.append(torch.empty(s.step_levels_size(), dtype=torch.uint8, device=s.device))
+                for n in range(a, b):
+                    s.save_state(self.tape[n - a])
+                    s.step(1)
+                    s.save_step_levels(self.levels[n - a])
+                for n in reversed(range(a, b)):
+                    s.load_state(self.tape[n - a])
+                    s.step_adjoint(self.levels[n - a])
+            else:
+                s.save_state(self.tape[0])
+                for n in range(a + 1, b):
+                    s.step(1)
+                    s.save_state(self.tape[n - a])
+                for n in reversed(range(a, b)):
+                    s.load_state(self.tape[n - a])
+                    s.step_adjoint()
         if self.nsteps == 0:
             s.load_state(self.ckpt[0])
         return s.adjoint_initial()

@@ -1414,7 +1414,56 @@ extern "C" lm_status lm_adjoint_get(lm_ctx *c, lm_adjoint *out, int mem) {
   return LM_OK;
 }
 
-extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
+// The arrays of a step's levels that its reverse step reads: the predicted
+// level (rho, H, Z in reacting flow, v, F) and the new level (rho, H, Z, v).
+static int step_level_arrays(const lm_ctx *c, const Level &S, const Level &X, double **out) {
+  const int nd = c->grid.ndim;
+  const bool react = c->prm.reacting;
+  int k = 0;
+  out[k++] = S.rho;
+  out[k++] = S.H;
+  if (react) out[k++] = S.Z;
+  for (int d = 0; d < nd; ++d) out[k++] = S.v[d];
+  for (int d = 0; d < nd; ++d) out[k++] = S.F[d];
+  out[k++] = X.rho;
+  out[k++] = X.H;
+  if (react) out[k++] = X.Z;
+  for (int d = 0; d < nd; ++d) out[k++] = X.v[d];
+  return k;
+}
+
+extern "C" lm_status lm_step_levels_size(const lm_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return LM_EINVAL;
+  double *arr[16];
+  const Level &l = c->lev[0];
+  *bytes = (size_t)step_level_arrays(c, l, l, arr) * c->lay.total * 8;
+  return LM_OK;
+}
+
+extern "C" lm_status lm_save_step_levels(lm_ctx *c, void *buf) {
+  if (!c || !buf) return fail(c, LM_EINVAL, "NULL argument");
+  if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
+  if (!c->have_star) return fail(c, LM_ESTATE, "no step taken since the state was set or loaded");
+  double *arr[16];
+  // after a committed step the new level is the current one
+  const int k = step_level_arrays(c, c->lev[c->istar], c->lev[c->icur], arr);
+  const size_t ab = (size_t)c->lay.total * 8;
+  for (int q = 0; q < k; ++q)
+    HIPCHK(c, hipMemcpyAsync((char *)buf + q * ab, arr[q], ab, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return LM_OK;
+}
+
+static lm_status step_adjoint(lm_ctx *c, const void *levels);
+
+extern "C" lm_status lm_step_adjoint(lm_ctx *c) { return step_adjoint(c, nullptr); }
+
+extern "C" lm_status lm_step_adjoint_levels(lm_ctx *c, const void *levels) {
+  if (!levels) return fail(c, LM_EINVAL, "NULL argument");
+  return step_adjoint(c, levels);
+}
+
+static lm_status step_adjoint(lm_ctx *c, const void *levels) {
   if (!c) return LM_EINVAL;
   if (!adjoint_ok(c)) return fail(c, LM_EUNSUPPORTED, kAdjUnsupported);
   if (!c->have_state) return fail(c, LM_ESTATE, "no state set");
@@ -1422,14 +1471,24 @@ extern "C" lm_status lm_step_adjoint(lm_ctx *c) {
   const int nd = c->grid.ndim;
   const bool react = c->prm.reacting;
   const size_t ab = (size_t)L.total * 8;
-  // forward recompute of the step (state at n untouched: outputs go to the
-  // predicted and next levels)
-  int it[2];
-  double rr[2], cm[2];
-  lm_status s = do_stage(c, 0, it[0], rr[0], cm[0]);
-  if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
-  if (s == LM_OK) s = read_solve_logs(c, it, rr, cm);
-  if (s != LM_OK) return s;
+  lm_status s = LM_OK;
+  if (levels) {
+    // the step's predicted and new levels as saved right after it was
+    // taken from this state
+    double *arr[16];
+    const int k = step_level_arrays(c, c->lev[c->istar], c->lev[c->inxt], arr);
+    for (int q = 0; q < k; ++q)
+      HIPCHK(c, hipMemcpyAsync(arr[q], (const char *)levels + q * ab, ab, hipMemcpyDeviceToDevice, c->st));
+  } else {
+    // forward recompute of the step (state at n untouched: outputs go to the
+    // predicted and next levels)
+    int it[2];
+    double rr[2], cm[2];
+    s = do_stage(c, 0, it[0], rr[0], cm[0]);
+    if (s == LM_OK) s = do_stage(c, 1, it[1], rr[1], cm[1]);
+    if (s == LM_OK) s = read_solve_logs(c, it, rr, cm);
+    if (s != LM_OK) return s;
+  }
   const int first = !c->have_prev;
   const AdjPhys P = adj_phys(c);
   Level &N = c->lev[c->icur], &S = c->lev[c->istar], &X = c->lev[c->inxt];

@@ -94,6 +94,9 @@ EXPORTS = {
     "lm_adjoint_set": (C.c_int, [C.c_void_p, C.POINTER(lm_adjoint), C.c_int]),
     "lm_adjoint_get": (C.c_int, [C.c_void_p, C.POINTER(lm_adjoint), C.c_int]),
     "lm_step_adjoint": (C.c_int, [C.c_void_p]),
+    "lm_step_levels_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "lm_save_step_levels": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lm_step_adjoint_levels": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lm_adjoint_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_int]),
     "lm_project_static": (C.c_int, [C.POINTER(lm_grid), C.POINTER(lm_params), C.c_void_p,
                                     C.POINTER(lm_project_args)]),

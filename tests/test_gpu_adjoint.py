@@ -720,3 +720,43 @@ def test_ke_gradient_3d_against_oracle_complex_step():
     ad = float(torch.sum(v1[2].grad.cpu() * torch.tensor(d)))
     print("v0[2]", cs, ad, abs(ad - cs) / abs(cs), flush=True)
     assert abs(ad - cs) <= 1e-9 * abs(cs)
+
+
+@pytest.mark.parametrize("kind", ["periodic-2d", "walls-3d-reacting"])
+def test_taped_levels_reverse_sweep_is_bit_exact(kind):
+    """The reverse sweep that tapes each replayed step's predicted and new
+    levels (lm_save_step_levels / lm_step_adjoint_levels) gives the same
+    gradient, bit for bit, as the one that recomputes every step inside
+    lm_step_adjoint; a save with no step since the state was set is an
+    error."""
+    import torch
+    from paper_2603_01727_amd import LowMachError, lib
+    from paper_2603_01727_amd.adjoint import Trajectory
+    if kind == "periodic-2d":
+        case, nsteps, k = c5_case(n=64), 7, 3
+    else:
+        from workloads.ics import reacting_periodic_case
+        case, nsteps, k = _walls_case("box3d"), 5, 2
+        r = reacting_periodic_case(case.n[:3], seed=22)
+        case.Z = r.Z
+        case.params = dict(r.params, Re=case.params["Re"], cfl=case.params["cfl"])
+    dt = _dt(case)
+    print("taped levels", kind, flush=True)
+    s = _solver(case, dt)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    out = []
+    for tape in (True, False):
+        traj = Trajectory(s, nsteps, k, tape_levels=tape)
+        traj.forward(dev(case.T), [dev(a) for a in case.v], None if case.Z is None else dev(case.Z))
+        out.append([x.cpu().numpy() if not isinstance(x, list) else [y.cpu().numpy() for y in x]
+                    for x in traj.backward()])
+    a, b = out
+    assert np.array_equal(a[0], b[0]), "T0 gradient"
+    for x, y in zip(a[1], b[1]):
+        assert np.array_equal(x, y), "v0 gradient"
+    if len(a) > 2:
+        assert np.array_equal(a[2], b[2]), "Z0 gradient"
+    s.set(T=case.T, v=case.v, Z=case.Z)
+    with pytest.raises(LowMachError) as e:
+        s.save_step_levels()
+    assert e.value.status == lib.LM_ESTATE
