@@ -168,6 +168,7 @@ struct Loader {
   Bnd B;
   Sides sd;
   const double *H, *Z, *v[3], *F[3];
+  const double *kap, *dkap;  // the level's kappa(T) and d kappa/dT at the cells
   const unsigned char *chi;
   const double *H_ib, *Z_ib, *v_ib[3];
   Ix m;
@@ -312,7 +313,19 @@ __device__ inline Dual<N> kappa_dual(const AdjPhys &P, const Dual<N> &T) {
 // with the ghost Z clamped to [0, S+1].
 template <int DIM, int R, int W>
 __device__ inline DD<DIM, R> kap_at(const AdjPhys &P, const Loader<DIM, R, W> &ld, Ix x) {
-  if (!W || ld.inside(x)) return kappa_dual(P, temp_at(P, ld, x));
+  if (!W || ld.inside(x)) {
+    // kappa of a cell from the level's precomputed kappa and d kappa/dT:
+    // T = qs (F~(Z) + H) carries the seeds (dT/dH = qs, dT/dZ = qs F~'(Z))
+    if (!W) x = wrap(ld.L, x);
+    const long c = ld.L.at(x.i, x.j, x.k);
+    DD<DIM, R> r(ld.kap[c]);
+    if (x.i == ld.m.i && x.j == ld.m.j && x.k == ld.m.k) {
+      const double g = ld.dkap[c] * P.qs;
+      r.d[0] = g;
+      if (R) r.d[1] = g * dftilde_of(P, ld.Z[c]);
+    }
+    return r;
+  }
   int dw, sw;
   if (isothermal_ghost<DIM>(ld.L, ld.B, ld.sd, x.i, x.j, x.k, dw, sw)) {
     const double Hw = side_value(ld.sd, ld.L, dw, sw, 4, x.i, x.j, x.k);
@@ -471,6 +484,27 @@ __device__ inline EosD eos_d(const AdjPhys &P, double rho, double H, double Z) {
     }                                                                                        \
   } while (0)
 
+// kappa(T) and d kappa/dT of every cell of a level, T = T(Z, H): one
+// evaluation per cell, which the residual gather reads (it meets each cell
+// in up to 13 stencil positions of each of its 3^DIM residuals).
+template <int DIM, int R>
+__global__ void __launch_bounds__(kBlock) k_adj_kappa(AdjCellArgs a) {
+  CellPos p;
+  if (!cell_of_thread(a.L, p)) return;
+  const long c = p.c;
+  const double T = R ? a.P.qs * (ftilde_of(a.P, a.Z[c]) + a.H[c]) : a.P.qs * (a.H[c] - 1.0);
+  Dual<1> t(T);
+  t.d[0] = 1.0;
+  const Dual<1> k = kappa_dual(a.P, t);
+  a.Hb[c] = k.v;     // kappa
+  a.Zb0[c] = k.d[0]; // d kappa/dT
+}
+
+hipError_t launch_adj_kappa(hipStream_t st, const AdjCellArgs &a) {
+  LM_ADJ_LAUNCH(k_adj_kappa, a.L, a.P.reacting, a);
+  return hipGetLastError();
+}
+
 // (Hb, Zb, vb, Fb) += (dR/d(H, Z, v, F))^T (RbH, RbZ, Rbv) by gather over
 // the 3^DIM cells whose residual stencils reach the cell (with wall or
 // inflow sides, the interior ones: a ghost mirrors a cell within one cell
@@ -488,6 +522,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   ld.sd = a.sd;
   ld.H = a.H;
   ld.Z = a.Z;
+  ld.kap = a.kap;
+  ld.dkap = a.dkap;
   ld.chi = a.chi;
   ld.H_ib = a.H_ib;
   ld.Z_ib = a.Z_ib;

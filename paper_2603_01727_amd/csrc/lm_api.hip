@@ -27,6 +27,7 @@ struct AdjWork {
   // predictor): the initial guess of the same stage's solve one step back
   double *xa[2];
   int xa_valid[2], xa_iters[2];
+  double *kap, *dkap;  // kappa and d kappa/dT of the level a residual gather reads
 };
 
 struct lm_ctx {
@@ -428,6 +429,8 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
       w.xa[q] = take(true);
       w.xa_valid[q] = w.xa_iters[q] = 0;
     }
+    w.kap = take(true);
+    w.dkap = take(true);
     for (int d = 0; d < 3; ++d)
       for (double **q : {&w.Mb[d], &w.vb_star[d], &w.Fb_star[d], &w.Rbv_star[d], &w.Rbv_n[d]}) *q = take(d < nd);
     c->ad_cur = 0;
@@ -1560,6 +1563,17 @@ static lm_status step_adjoint(lm_ctx *c, const void *levels) {
       a.Z_ib = ib->Z_ib;
       for (int d = 0; d < nd; ++d) a.v_ib[d] = ib->v_ib[d];
     }
+    AdjCellArgs kk{};
+    kk.L = L;
+    kk.P = P;
+    kk.H = lv.H;
+    kk.Z = lv.Z;
+    kk.Hb = w.kap;
+    kk.Zb0 = w.dkap;
+    hipError_t e = launch_adj_kappa(c->st, kk);
+    if (e != hipSuccess) return e;
+    a.kap = w.kap;
+    a.dkap = w.dkap;
     return launch_adj_resid(c->st, a);
   };
   // outflow closure: the cotangent of the stage's right-hand side b from

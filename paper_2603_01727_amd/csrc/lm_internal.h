@@ -213,6 +213,7 @@ struct AdjResidArgs {
   double *Hb, *Zb, *vb[3], *Fb[3];      // accumulated adjoints
   const unsigned char *chi;             // body mask (null: no body)
   const double *H_ib, *Z_ib, *v_ib[3];  // body targets (null: 0)
+  const double *kap, *dkap;             // the level's kappa and d kappa/dT (launch_adj_kappa)
 };
 struct AdjProjArgs {
   Lay L;
@@ -260,6 +261,9 @@ hipError_t launch_adj_add_T(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_adj_seed_ke(hipStream_t st, const AdjCellArgs &a);
 // initial-state transpose (H, Z, rho, v, Fb, Hb_in, Zb_in -> Tb_out, Zb0, vb += )
 hipError_t launch_adj_init(hipStream_t st, const AdjCellArgs &a);
+// kappa(T(Z, H)) and d kappa/dT of a level's cells (H, Z -> Hb: kappa,
+// Zb0: d kappa/dT)
+hipError_t launch_adj_kappa(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[3], double dV, double *part,
                      double *out);
 // Transpose of the outflow closure of a high outflow side in direction d:
