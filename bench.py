@@ -70,10 +70,10 @@ def parse():
     ap.add_argument("--no-c2", action="store_true", help="skip the 2D 1024^2 workload")
     ap.add_argument("--no-vc", action="store_true", help="skip the beta = 1 vs beta = 1/rho solve comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^2, slot-flame and 512^2 workloads")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the 512^2 200-step gradient")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 512^2 200-step and 128^3 gradients")
     ap.add_argument("--small", choices=("c1", "c2", "adjoint"),
                     help="only the 64^2 (c1) or 1024^2 (c2) FP64 steps, or only the 512^2 200-step gradient "
-                    "(adjoint), for kernel traces of those paths")
+                    "and the 128^3 40-step gradients (adjoint), for kernel traces of those paths")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of known size (for HBM counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB", help="summarise a rocprofv3 kernel-trace database")
@@ -352,6 +352,48 @@ def adjoint_block(every=20):
                 J=float(J.item()), grad_norm=float(T0.grad.norm().item()))
 
 
+def adjoint3d_block(n=128, nsteps=40, every=10):
+    """The adjoint in 3D: the headline's triply periodic random-mode box at
+    n^3 (same seeded fields as the 256^3 workload's generator at this size),
+    nsteps steps of the initial state's CFL step, checkpoints every
+    ``every``: the gradient of the final kinetic energy with respect to T0
+    against the same steps forward only."""
+    import torch
+    from paper_2603_01727_amd import Solver
+    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    from workloads import c4_case
+    case = c4_case(n=n)
+    kw = dict(bc=case.bc, Re=case.params["Re"], Pr=case.params["Pr"], poisson_rtol=1e-10, poisson_maxit=400)
+    probe = Solver(case.n, case.L, cfl=case.params["cfl"], **kw)
+    probe.set(T=case.T, v=case.v)
+    dt = probe.dt
+    probe.close()
+    s = Solver(case.n, case.L, dt=dt, with_adjoint=True, **kw)
+    T0 = torch.tensor(case.T, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = [torch.tensor(x, dtype=torch.float64, device="cuda") for x in case.v]
+    J = final_kinetic_energy(s, T0, v0, 2, 1)      # warm-up of both sweeps
+    J.backward()
+    T0.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = final_kinetic_energy(s, T0, v0, nsteps, every)
+    J.backward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.set(T=case.T, v=case.v)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.step(nsteps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    s.close()
+    return dict(workload=f"3D triply periodic 2pi box {n}^3, random modes |k|<=6, density ratio 6, Re=400, "
+                         f"Pr=0.7, {nsteps} steps of dt={dt:.6g}, gradient of the final kinetic energy w.r.t. T0",
+                checkpoint_every=every, gradient_s=round(t1 - t0, 4), forward_only_s=round(t3 - t2, 4),
+                gradient_over_forward=round((t1 - t0) / (t3 - t2), 3), J=float(J.item()),
+                grad_norm=float(T0.grad.norm().item()))
+
+
 ORACLE_KEYS = ("Re", "Pr", "sigma", "inv_Fr2", "reacting", "S", "qs", "eps", "tol", "Le_F", "Le_O", "Da_ib",
                "p0", "dt", "cfl")
 
@@ -523,7 +565,7 @@ def main():
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.traffic_out)
         return
     if a.small == "adjoint":
-        print(json.dumps({"adjoint_c5": adjoint_block()}))
+        print(json.dumps({"adjoint_c5": adjoint_block(), "adjoint_3d_128": adjoint3d_block()}))
         return
     if a.small:
         from workloads import c1_case, c2_case
@@ -558,6 +600,7 @@ def main():
     forms = None if a.no_vc else poisson_forms()
     configs = None if a.no_configs else bench_configs()
     adj = None if a.no_adjoint else adjoint_block()
+    adj3 = None if a.no_adjoint else adjoint3d_block()
     cpu = None if a.no_cpu else cpu_baseline(case)
     out = {
         "metric": "cell-updates/s per full time step (Poisson to 1e-10), FP64 vs mixed; HBM GB/s",
@@ -578,6 +621,7 @@ def main():
         "poisson_forms": forms,
         "other_workloads": configs,
         "adjoint_c5": adj,
+        "adjoint_3d_128": adj3,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
