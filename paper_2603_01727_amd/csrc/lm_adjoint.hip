@@ -16,6 +16,8 @@
 // numbers seeded at m (derivatives with respect to H, the DIM velocity
 // components and the DIM face fluxes at m) and contracted with the residual
 // cotangents. No atomics; deterministic.
+#include <type_traits>
+
 #include "lm_device.h"
 #include "lm_sides.h"
 
@@ -133,6 +135,15 @@ __device__ inline Dual<N> dpow(const Dual<N> &x, double p) {
 template <int DIM, int R>
 using DD = Dual<1 + R + 2 * DIM>;
 
+// f(integral_constant<int, I>) for I = B .. E-1, unrolled at compile time.
+template <int B, int E, typename F>
+__device__ __attribute__((always_inline)) inline void adj_static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>());
+    adj_static_for<B + 1, E>(f);
+  }
+}
+
 struct Ix {
   int i, j, k;
 };
@@ -172,19 +183,28 @@ struct Loader {
   const unsigned char *chi;
   const double *H_ib, *Z_ib, *v_ib[3];
   Ix m;
-  __device__ double chi_at(Ix x) const { return chi ? (double)chi[L.at(x.i, x.j, x.k)] : 0.0; }
-  __device__ double hib(Ix x) const { return H_ib ? H_ib[L.at(x.i, x.j, x.k)] : 0.0; }
-  __device__ double zib(Ix x) const { return Z_ib ? Z_ib[L.at(x.i, x.j, x.k)] : 0.0; }
-  __device__ double vib(int c, Ix x) const { return v_ib[c] ? v_ib[c][L.at(x.i, x.j, x.k)] : 0.0; }
+  // cell constants at x (x wrapped into a periodic grid first)
+  __device__ long cidx(Ix x) const {
+    if (!W) x = wrap(L, x);
+    return L.at(x.i, x.j, x.k);
+  }
+  __device__ double chi_at(Ix x) const { return chi ? (double)chi[cidx(x)] : 0.0; }
+  __device__ double hib(Ix x) const { return H_ib ? H_ib[cidx(x)] : 0.0; }
+  __device__ double zib(Ix x) const { return Z_ib ? Z_ib[cidx(x)] : 0.0; }
+  __device__ double vib(int c, Ix x) const { return v_ib[c] ? v_ib[c][cidx(x)] : 0.0; }
   // field a with rule set f (0..2 velocity components, 3 Z, 4 H). An
   // outflow side's ghost is the quadratic extrapolation 3 u_0 - 3 u_1 + u_2
   // of the three cells inside; with at most one outflow direction (checked
   // at set-up) a ghost spans at most three cells.
   __device__ DD<DIM, R> load(const double *a, int f, Ix x, int seed) const {
     if (!W) {
+      // periodic: the seed test on unwrapped coordinates (exact when every
+      // direction has at least 3 cells, as readers lie within 2 of m), which
+      // an unrolled gather resolves at compile time
+      const bool seeded = x.i == m.i && x.j == m.j && x.k == m.k;
       x = wrap(L, x);
       DD<DIM, R> r(a[L.at(x.i, x.j, x.k)]);
-      if (x.i == m.i && x.j == m.j && x.k == m.k) r.d[seed] = 1.0;
+      if (seeded) r.d[seed] = 1.0;
       return r;
     }
     int pos[3][3] = {{x.i, x.j, x.k}, {0, 0, 0}, {0, 0, 0}};
@@ -316,10 +336,11 @@ __device__ inline DD<DIM, R> kap_at(const AdjPhys &P, const Loader<DIM, R, W> &l
   if (!W || ld.inside(x)) {
     // kappa of a cell from the level's precomputed kappa and d kappa/dT:
     // T = qs (F~(Z) + H) carries the seeds (dT/dH = qs, dT/dZ = qs F~'(Z))
+    const bool seeded = x.i == ld.m.i && x.j == ld.m.j && x.k == ld.m.k;
     if (!W) x = wrap(ld.L, x);
     const long c = ld.L.at(x.i, x.j, x.k);
     DD<DIM, R> r(ld.kap[c]);
-    if (x.i == ld.m.i && x.j == ld.m.j && x.k == ld.m.k) {
+    if (seeded) {
       const double g = ld.dkap[c] * P.qs;
       r.d[0] = g;
       if (R) r.d[1] = g * dftilde_of(P, ld.Z[c]);
@@ -546,34 +567,49 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
       if (a.B.kind[d][1] == LM_SIDE_OUTFLOW && pm[d] == a.L.n[d] - 3) hi[d] = 2;
-  for (int dk = -kr; dk <= hi[2]; ++dk)
-    for (int dj = -1; dj <= hi[1]; ++dj)
-      for (int di = -1; di <= hi[0]; ++di) {
-        Ix x{p.i + di, p.j + dj, p.k + dk};
-        if (W && !ld.inside(x)) {
-          const int q[3] = {x.i, x.j, x.k};
-          bool wall = false;
-          for (int d = 0; d < DIM; ++d)
-            if ((q[d] < 0 || q[d] >= a.L.n[d]) && !a.B.periodic[d]) wall = true;
-          if (wall) continue;  // a ghost has no residual
+  // the residual of cell x (unwrapped in a periodic grid) contracted with
+  // its cotangents into acc
+  auto gather = [&](Ix x) __attribute__((always_inline)) {
+    DD<DIM, R> RH, RZ, Rv[DIM];
+    resid_cell<DIM, R, W>(a.P, ld, x, RH, RZ, Rv);
+    const long c = ld.cidx(x);
+    const double rh = a.RbH[c], rz = R ? a.RbZ[c] : 0.0;
+    double r[DIM];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) r[e] = a.Rbv[e][c];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      double s = rh * RH.d[q];
+      if (R) s += rz * RZ.d[q];
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) s += r[e] * Rv[e].d[q];
+      acc[q] += s;
+    }
+  };
+  if constexpr (!W) {
+    // periodic: the 3^DIM offsets unrolled, so that every seed test (which
+    // stencil position is cell m) is a constant and the derivative
+    // arithmetic of the positions that are not m folds away
+    adj_static_for<0, (DIM == 3 ? 27 : 9)>([&](auto T) __attribute__((always_inline)) {
+      constexpr int t = decltype(T)::value;
+      constexpr int di = t % 3 - 1, dj = (t / 3) % 3 - 1, dk = DIM == 3 ? t / 9 - 1 : 0;
+      gather(Ix{p.i + di, p.j + dj, p.k + dk});
+    });
+  } else {
+    for (int dk = -kr; dk <= hi[2]; ++dk)
+      for (int dj = -1; dj <= hi[1]; ++dj)
+        for (int di = -1; di <= hi[0]; ++di) {
+          Ix x{p.i + di, p.j + dj, p.k + dk};
+          if (!ld.inside(x)) {
+            const int q[3] = {x.i, x.j, x.k};
+            bool wall = false;
+            for (int d = 0; d < DIM; ++d)
+              if ((q[d] < 0 || q[d] >= a.L.n[d]) && !a.B.periodic[d]) wall = true;
+            if (wall) continue;  // a ghost has no residual
+          }
+          gather(wrap(a.L, x));
         }
-        x = wrap(a.L, x);
-        DD<DIM, R> RH, RZ, Rv[DIM];
-        resid_cell<DIM, R, W>(a.P, ld, x, RH, RZ, Rv);
-        const long c = a.L.at(x.i, x.j, x.k);
-        const double rh = a.RbH[c], rz = R ? a.RbZ[c] : 0.0;
-        double r[DIM];
-#pragma unroll
-        for (int e = 0; e < DIM; ++e) r[e] = a.Rbv[e][c];
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-          double s = rh * RH.d[q];
-          if (R) s += rz * RZ.d[q];
-#pragma unroll
-          for (int e = 0; e < DIM; ++e) s += r[e] * Rv[e].d[q];
-          acc[q] += s;
-        }
-      }
+  }
   const long m = p.c;
   a.Hb[m] += acc[0];
   if (R) a.Zb[m] += acc[1];

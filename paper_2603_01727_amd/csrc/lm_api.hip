@@ -1182,10 +1182,14 @@ int outflow_dir(const lm_ctx *c) {
 }
 
 // The adjoint covers periodic, slip / no-slip wall and inflow sides, and an
-// outflow side on the high end of at most one direction (at least 3 cells
-// long), on uniform spacing.
+// outflow side on the high end of at most one direction, on uniform spacing
+// with at least 3 cells per direction.
 bool adjoint_ok(lm_ctx *c) {
   if (!c->prm.with_adjoint || c->stretched) return false;
+  // the residual gather tells a periodic stencil position from the cell it
+  // wraps to by its unwrapped offset: 3 cells per direction at least
+  for (int d = 0; d < c->grid.ndim; ++d)
+    if (c->grid.n[d] < 3) return false;
   int nout = 0;
   for (int d = 0; d < c->grid.ndim; ++d)
     for (int s = 0; s < 2; ++s)
