@@ -350,9 +350,9 @@ lm_status lm_adjoint_get(lm_ctx *ctx, lm_adjoint *a, int mem);
  * the state at n (the step is recomputed internally; the forward state is
  * left at n). Each stage needs one adjoint Poisson solve with the same
  * symmetric operator, started from that stage's solution of the previous
- * lm_step_adjoint call since the last lm_adjoint_set / lm_adjoint_seed_ke
- * (a reverse sweep steps back in time; the tolerance is poisson_rtol as
- * ever); errors as lm_step.                                                */
+ * lm_step_adjoint call since the last lm_adjoint_set / lm_adjoint_seed_ke,
+ * or the linear extrapolation of its last two (a reverse sweep steps back
+ * in time; the tolerance is poisson_rtol as ever); errors as lm_step.      */
 lm_status lm_step_adjoint(lm_ctx *ctx);
 /* The reverse step without the recompute, for callers that replay steps
  * anyway (a checkpointed reverse sweep): right after lm_step took one step

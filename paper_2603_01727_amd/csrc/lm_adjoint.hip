@@ -947,6 +947,19 @@ hipError_t launch_adj_outflow(hipStream_t st, const Lay &L, const AdjPhys &P, in
   return hipGetLastError();
 }
 
+// out = 2 x1 - x2 on the cells: the linear extrapolation of a stage's last
+// two adjoint Poisson solutions, the next solve's initial guess.
+__global__ void __launch_bounds__(kBlock) k_adj_extrap(Lay L, const double *x1, const double *x2, double *out) {
+  CellPos p;
+  if (!cell_of_thread(L, p)) return;
+  out[p.c] = 2.0 * x1[p.c] - x2[p.c];
+}
+
+hipError_t launch_adj_extrap(hipStream_t st, const Lay &L, const double *x1, const double *x2, double *out) {
+  hipLaunchKernelGGL(k_adj_extrap, grid_for(L), dim3(kBX, kBY), 0, st, L, x1, x2, out);
+  return hipGetLastError();
+}
+
 // sum over cells of 1/2 rho |v|^2 into per-block partials.
 template <int DIM, int R>
 __global__ void __launch_bounds__(kBlock) k_ke(AdjCellArgs a) {

@@ -25,7 +25,7 @@ struct AdjWork {
   double *Tb_set, *Tb_init, *Zb_init;
   // the last adjoint Poisson solution of each stage (0 corrector, 1
   // predictor): the initial guess of the same stage's solve one step back
-  double *xa[2];
+  double *xa[2], *xa_old[2], *xa_guess;
   int xa_valid[2], xa_iters[2];
   double *kap, *dkap;  // kappa and d kappa/dT of the level a residual gather reads
 };
@@ -427,8 +427,10 @@ bool carve(lm_ctx *c, Carver &cv, std::string *err) {
     for (double **q : {&w.Zb_star, &w.RbZ_star, &w.RbZ_n, &w.Zb_init}) *q = take(c->prm.reacting);
     for (int q = 0; q < 2; ++q) {
       w.xa[q] = take(true);
+      w.xa_old[q] = take(true);
       w.xa_valid[q] = w.xa_iters[q] = 0;
     }
+    w.xa_guess = take(true);
     w.kap = take(true);
     w.dkap = take(true);
     for (int d = 0; d < 3; ++d)
@@ -1515,12 +1517,17 @@ static lm_status step_adjoint(lm_ctx *c, const void *levels) {
     int iters = 0, conv = 0;
     double relres = 0.0;
     const double *x0 = w.xa_valid[stage] ? w.xa[stage] : nullptr;
+    if (w.xa_valid[stage] >= 2) {
+      HIPCHK(c, launch_adj_extrap(c->st, L, w.xa[stage], w.xa_old[stage], w.xa_guess));
+      x0 = w.xa_guess;
+    }
     HIPCHK(c, poisson_solve(c->st, c->pws, rhs, x0, c->prm.poisson_rtol, c->prm.poisson_maxit, w.xa_iters[stage],
                             &iters, &relres, &conv));
     if (!conv) return fail(c, LM_ENOCONV, "adjoint Poisson solve did not converge");
     HIPCHK(c, launch_shift(c->st, L, c->pws.x, c->pws.sc, out));
+    std::swap(w.xa[stage], w.xa_old[stage]);
     HIPCHK(c, hipMemcpyAsync(w.xa[stage], out, ab, hipMemcpyDeviceToDevice, c->st));
-    w.xa_valid[stage] = 1;
+    w.xa_valid[stage] = w.xa_valid[stage] + 1 > 2 ? 2 : w.xa_valid[stage] + 1;
     w.xa_iters[stage] = iters;
     return LM_OK;
   };

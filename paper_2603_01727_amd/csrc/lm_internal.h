@@ -266,6 +266,8 @@ hipError_t launch_adj_init(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_adj_kappa(hipStream_t st, const AdjCellArgs &a);
 hipError_t launch_ke(hipStream_t st, const Lay &L, const double *rho, double *const v[3], double dV, double *part,
                      double *out);
+// out = 2 x1 - x2 on the cells (extrapolated initial guess).
+hipError_t launch_adj_extrap(hipStream_t st, const Lay &L, const double *x1, const double *x2, double *out);
 // Transpose of the outflow closure of a high outflow side in direction d:
 // y += (-sum_side y/h - sum_side Fb) dV/area (scratch: one double).
 hipError_t launch_adj_outflow(hipStream_t st, const Lay &L, const AdjPhys &P, int d, double *y, const double *Fb,
