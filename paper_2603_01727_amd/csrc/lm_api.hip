@@ -1189,7 +1189,8 @@ int outflow_dir(const lm_ctx *c) {
 bool adjoint_ok(lm_ctx *c) {
   if (!c->prm.with_adjoint || c->stretched) return false;
   // the residual gather tells a periodic stencil position from the cell it
-  // wraps to by its unwrapped offset: 3 cells per direction at least
+  // wraps to by its unwrapped offset: 3 cells per direction at least (the
+  // set-up already asks for 4)
   for (int d = 0; d < c->grid.ndim; ++d)
     if (c->grid.n[d] < 3) return false;
   int nout = 0;

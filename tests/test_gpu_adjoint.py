@@ -760,3 +760,4 @@ def test_taped_levels_reverse_sweep_is_bit_exact(kind):
     with pytest.raises(LowMachError) as e:
         s.save_step_levels()
     assert e.value.status == lib.LM_ESTATE
+
