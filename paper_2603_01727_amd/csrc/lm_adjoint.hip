@@ -537,6 +537,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   constexpr int N = 1 + R + 2 * DIM;
   CellPos p;
   if (!cell_of_thread(a.L, p)) return;
+  if (a.box_mode) {
+    const bool in = p.i >= a.box_lo[0] && p.i <= a.box_hi[0] && p.j >= a.box_lo[1] && p.j <= a.box_hi[1] &&
+                    p.k >= a.box_lo[2] && p.k <= a.box_hi[2];
+    if (in != (a.box_mode == 1)) return;
+  }
   Loader<DIM, R, W> ld;
   ld.L = a.L;
   ld.B = a.B;
@@ -623,9 +628,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_resid(AdjResidArgs a) {
   }
 }
 
-hipError_t launch_adj_resid(hipStream_t st, const AdjResidArgs &a) {
+static void launch_resid_sel(hipStream_t st, const AdjResidArgs &a, int W) {
   const dim3 g = grid_for(a.L), bl(kBX, kBY);
-  const int sel = (a.L.ndim == 3 ? 4 : 0) + (a.P.reacting ? 2 : 0) + (a.B.all_periodic ? 0 : 1);
+  const int sel = (a.L.ndim == 3 ? 4 : 0) + (a.P.reacting ? 2 : 0) + W;
   switch (sel) {
     case 0: hipLaunchKernelGGL((k_adj_resid<2, 0, 0>), g, bl, 0, st, a); break;
     case 1: hipLaunchKernelGGL((k_adj_resid<2, 0, 1>), g, bl, 0, st, a); break;
@@ -636,6 +641,37 @@ hipError_t launch_adj_resid(hipStream_t st, const AdjResidArgs &a) {
     case 6: hipLaunchKernelGGL((k_adj_resid<3, 1, 0>), g, bl, 0, st, a); break;
     default: hipLaunchKernelGGL((k_adj_resid<3, 1, 1>), g, bl, 0, st, a); break;
   }
+}
+
+// With wall, inflow or outflow sides: the cells whose readers' stencils
+// stay inside the grid (at least 2 cells from every non-periodic side, 3
+// from a high outflow side, whose gather reaches further) take the
+// periodic kernel, exact there (no ghost is read and no position wraps
+// across such a side); the band along those sides the kernel with the
+// ghost rules.
+hipError_t launch_adj_resid(hipStream_t st, const AdjResidArgs &a0) {
+  AdjResidArgs a = a0;
+  a.box_mode = 0;
+  if (a.B.all_periodic) {
+    launch_resid_sel(st, a, 0);
+    return hipGetLastError();
+  }
+  bool empty = false;
+  for (int d = 0; d < 3; ++d) {
+    a.box_lo[d] = 0;
+    a.box_hi[d] = a.L.n[d] - 1;
+    if (d < a.L.ndim && !a.B.periodic[d]) {
+      a.box_lo[d] = 2;
+      a.box_hi[d] = a.L.n[d] - (a.B.kind[d][1] == LM_SIDE_OUTFLOW ? 4 : 3);
+      empty = empty || a.box_hi[d] < a.box_lo[d];
+    }
+  }
+  if (!empty) {
+    a.box_mode = 1;
+    launch_resid_sel(st, a, 0);
+    a.box_mode = 2;
+  }
+  launch_resid_sel(st, a, 1);
   return hipGetLastError();
 }
 

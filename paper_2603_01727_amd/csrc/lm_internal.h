@@ -214,6 +214,8 @@ struct AdjResidArgs {
   const unsigned char *chi;             // body mask (null: no body)
   const double *H_ib, *Z_ib, *v_ib[3];  // body targets (null: 0)
   const double *kap, *dkap;             // the level's kappa and d kappa/dT (launch_adj_kappa)
+  int box_mode;                         // 0 every cell; 1 only cells in the box; 2 only cells outside it
+  int box_lo[3], box_hi[3];             // inclusive cell ranges per direction
 };
 struct AdjProjArgs {
   Lay L;
