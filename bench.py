@@ -312,7 +312,7 @@ def adjoint_block(every=20):
     Poisson solves of both sweeps to 1e-10."""
     import torch
     from paper_2603_01727_amd import Solver
-    from paper_2603_01727_amd.adjoint import final_kinetic_energy
+    from paper_2603_01727_amd.adjoint import Trajectory, final_kinetic_energy
     from workloads import c5_case
     case = c5_case()
     nsteps = case.nsteps
@@ -341,6 +341,21 @@ def adjoint_block(every=20):
     s.step(nsteps)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
+    # the same gradient with every step taped in the forward pass (no
+    # replay: 200 states and step levels, about 11 GB of HBM)
+    traj = Trajectory(s, nsteps, every, tape_all=True)
+    traj.forward(T0.detach(), v0)
+    traj.backward()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    traj.forward(T0.detach(), v0)
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    g_all = traj.backward()[0]
+    torch.cuda.synchronize()
+    t7 = time.perf_counter()
+    same = bool(torch.equal(g_all, T0.grad))
+    del traj
     s.close()
     fwd = t4 - t3
     return dict(workload=f"2D periodic 2pi box 512^2, random modes |k|<=8, density ratio 4, Re=300, Pr=0.7, "
@@ -349,7 +364,10 @@ def adjoint_block(every=20):
                 forward_with_checkpoints_s=round(t1 - t0, 4), reverse_sweep_s=round(t2 - t1, 4),
                 forward_only_s=round(fwd, 4), gradient_over_forward=round((t2 - t0) / fwd, 3),
                 reverse_ms_per_step=round((t2 - t1) / nsteps * 1e3, 4),
-                J=float(J.item()), grad_norm=float(T0.grad.norm().item()))
+                J=float(J.item()), grad_norm=float(T0.grad.norm().item()),
+                tape_all=dict(gradient_s=round(t7 - t5, 4), forward_with_tape_s=round(t6 - t5, 4),
+                              reverse_sweep_s=round(t7 - t6, 4), gradient_over_forward=round((t7 - t5) / fwd, 3),
+                              same_gradient_bits=same))
 
 
 def adjoint3d_block(n=128, nsteps=40, every=10):

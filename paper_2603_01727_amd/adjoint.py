@@ -38,7 +38,8 @@ class Trajectory:
     immersed-body arrays handed to ``Solver.set`` with the initial state
     (constants of the run)."""
 
-    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20, ib=None, tape_levels: bool = True):
+    def __init__(self, solver, nsteps: int, checkpoint_every: int = 20, ib=None, tape_levels: bool = True,
+                 tape_all: bool = False):
         if nsteps < 0 or checkpoint_every < 1:
             raise ValueError("nsteps >= 0 and checkpoint_every >= 1 required")
         if not solver.params.with_adjoint:
@@ -50,6 +51,10 @@ class Trajectory:
         self.k = int(checkpoint_every)
         self.ib = None if ib is None else {k: _on_device(x, solver.device, k == "chi") for k, x in ib.items()}
         self.tape_levels = bool(tape_levels)   # False: lm_step_adjoint recomputes each step
+        # True: the forward pass itself tapes every step's state and levels
+        # (nsteps of each in device memory), so the reverse sweep replays
+        # nothing; checkpoint_every is then unused
+        self.tape_all = bool(tape_all)
         self.ckpt = {}
         self.tape = []
         self.levels = []
@@ -59,6 +64,18 @@ class Trajectory:
         """Runs from (T0, v0), and the mixture fraction Z0 in reacting flow."""
         s = self.solver
         s.set(T=T0, v=v0, Z=Z0, ib=self.ib)
+        if self.tape_all:
+            size, lsize = s.state_size(), s.step_levels_size()
+            while len(self.tape) < self.nsteps:
+                self.tape.append(torch.empty(size, dtype=torch.uint8, device=s.device))
+                self.levels.append(torch.empty(lsize, dtype=torch.uint8, device=s.device))
+            self.ckpt = {0: s.save_state()}
+            for n in range(self.nsteps):
+                s.save_state(self.tape[n])
+                s.step(1)
+                s.save_step_levels(self.levels[n])
+            self.final = s.save_state()
+            return s.kinetic_energy()
         self.ckpt = {0: s.save_state()}
         done = 0
         while done < self.nsteps:
@@ -82,6 +99,13 @@ class Trajectory:
             s.adjoint_seed_ke()
         else:
             s.adjoint_set(**seed)
+        if self.tape_all:
+            for n in reversed(range(self.nsteps)):
+                s.load_state(self.tape[n])
+                s.step_adjoint(self.levels[n])
+            if self.nsteps == 0:
+                s.load_state(self.ckpt[0])
+            return s.adjoint_initial()
         size = s.state_size()
         nseg = math.ceil(self.nsteps / self.k)
         for q in reversed(range(nseg)):

@@ -727,8 +727,8 @@ def test_taped_levels_reverse_sweep_is_bit_exact(kind):
     """The reverse sweep that tapes each replayed step's predicted and new
     levels (lm_save_step_levels / lm_step_adjoint_levels) gives the same
     gradient, bit for bit, as the one that recomputes every step inside
-    lm_step_adjoint; a save with no step since the state was set is an
-    error."""
+    lm_step_adjoint, and as the one whose forward pass tapes every step (no
+    replay); a save with no step since the state was set is an error."""
     import torch
     from paper_2603_01727_amd import LowMachError, lib
     from paper_2603_01727_amd.adjoint import Trajectory
@@ -745,17 +745,18 @@ def test_taped_levels_reverse_sweep_is_bit_exact(kind):
     s = _solver(case, dt)
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     out = []
-    for tape in (True, False):
-        traj = Trajectory(s, nsteps, k, tape_levels=tape)
+    for tape, every in ((True, False), (False, False), (True, True)):
+        traj = Trajectory(s, nsteps, k, tape_levels=tape, tape_all=every)
         traj.forward(dev(case.T), [dev(a) for a in case.v], None if case.Z is None else dev(case.Z))
         out.append([x.cpu().numpy() if not isinstance(x, list) else [y.cpu().numpy() for y in x]
                     for x in traj.backward()])
-    a, b = out
-    assert np.array_equal(a[0], b[0]), "T0 gradient"
-    for x, y in zip(a[1], b[1]):
-        assert np.array_equal(x, y), "v0 gradient"
-    if len(a) > 2:
-        assert np.array_equal(a[2], b[2]), "Z0 gradient"
+    a = out[0]
+    for b in out[1:]:
+        assert np.array_equal(a[0], b[0]), "T0 gradient"
+        for x, y in zip(a[1], b[1]):
+            assert np.array_equal(x, y), "v0 gradient"
+        if len(a) > 2:
+            assert np.array_equal(a[2], b[2]), "Z0 gradient"
     s.set(T=case.T, v=case.v, Z=case.Z)
     with pytest.raises(LowMachError) as e:
         s.save_step_levels()
